@@ -1,0 +1,567 @@
+/*
+ * CPU FP64 ORACLE for the PCG/FCG + matching-aggregation AMG solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * reference that the GPU library is checked against.  It shares no code,
+ * header, table or helper with the library; only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it.  The product path
+ * never calls it.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, no
+ * fast-math: every floating-point operation below is one IEEE-754 binary64
+ * operation in the order written).
+ *
+ * What it computes (paper: "Alya towards Exascale: Algorithmic Scalability
+ * using PSCToolkit", arXiv 2210.16660):
+ *   - the AMG hierarchy of Sec. 3.1: Galerkin coarse matrices
+ *     A_{l+1} = P_l^T A_l P_l, edge weights of eq. (weights), an
+ *     approximate maximum-product matching (eq. approximatematch), aggregates
+ *     made of matched pairs and singletons, and the tentative prolongator of
+ *     eq. (prolongator) (piecewise constant, w in its range);
+ *   - the V-cycle of eq. (multiplicative_composition) with nu = 1 and the
+ *     l1-Jacobi smoother M_l = diag(sum_j |a_ij|), and a direct (dense
+ *     Cholesky) coarsest solve B_L = A_L^{-1};
+ *   - preconditioned CG, or flexible CG with truncation 1 (Sec. 5 uses FCG),
+ *     stopped when ||r||_2 <= tol * ||b||_2.
+ *
+ * Readings where the paper is silent (each is the definition used below):
+ *   R1 smoother: l1-Jacobi, D_ii = sum_j |a_ij| summed in ascending column
+ *      order, one undamped pre- and one post-sweep, zero initial guess.
+ *   R2 w_0 = 1 (the "arbitrary vector w" of the weights).
+ *   R3 eligible edges: c_ij > 1 as computed (only those raise the product).
+ *   R4 weight evaluation order: num = ((2*a)*w_lo)*w_hi,
+ *      den = (a_lolo*w_lo)*w_lo + (a_hihi*w_hi)*w_hi, c = 1 - num/den.
+ *   R5 matching: greedy over eligible edges sorted by (c descending, lo
+ *      ascending, hi ascending); an edge is taken iff both ends are free.
+ *      Under this strict total order the result is unique and is a
+ *      half-approximation of the maximum product (the bound the paper quotes
+ *      for its matching library).
+ *   R6 coarse numbering: aggregates numbered by ascending smallest member.
+ *   R7 prolongator: pair (lo, hi): nu = sqrt(w_lo*w_lo + w_hi*w_hi),
+ *      p = w/nu, w_c = nu;  singleton s: p = w_s/|w_s|, w_c = |w_s|.
+ *   R8 Galerkin rounding: A_{l+1}[I,J] = sum of a_ij*(p_i*p_j) over stored
+ *      (i,j) with agg(i)=I, agg(j)=J, added left to right in ascending order
+ *      of (min(i,j), max(i,j), i); every structural entry kept (even 0.0).
+ *   R9 levels: coarsen while n_l > max_coarse (200); a level whose matching
+ *      has no pair is the coarsest (error STALLED if it exceeds max_dense);
+ *      at most max_levels levels.  Levels are 0..L; smoothing on 0..L-1.
+ *   R10 Krylov: PCG, or FCG(1) with beta = -(z.q_old)/delta_old and
+ *      alpha = (p.r)/delta; dot products summed in index order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_E_INVALID (-1)
+#define OR_E_NOT_SPD (-2)
+#define OR_E_NUMERIC (-3)
+#define OR_E_OOM (-4)
+#define OR_E_STALLED (-6)
+
+#define OR_MAX_LEVELS 64
+
+typedef struct {
+    int n;
+    long nnz;
+    int *rp;
+    int *ci;
+    double *v;
+} or_csr;
+
+typedef struct {
+    int nlev;                       /* levels 0 .. nlev-1; coarsest L = nlev-1 */
+    or_csr A[OR_MAX_LEVELS];
+    double *w[OR_MAX_LEVELS];       /* near-null vector of level l */
+    double *dinv[OR_MAX_LEVELS];    /* 1 / l1 diagonal */
+    int *agg[OR_MAX_LEVELS];        /* level l -> level l+1 aggregate index (l < L) */
+    double *p[OR_MAX_LEVELS];       /* the single nonzero of row i of P_l (l < L) */
+    int n_pairs[OR_MAX_LEVELS];
+    double *chol;                   /* lower Cholesky factor of A_L, row-major n_L x n_L */
+} or_hier;
+
+/* ------------------------------------------------------------------ utils */
+
+static void csr_free(or_csr *a) {
+    free(a->rp); free(a->ci); free(a->v);
+    memset(a, 0, sizeof(*a));
+}
+
+void oracle_free(or_hier *h) {
+    if (!h) return;
+    for (int l = 0; l < OR_MAX_LEVELS; ++l) {
+        csr_free(&h->A[l]);
+        free(h->w[l]); free(h->dinv[l]); free(h->agg[l]); free(h->p[l]);
+    }
+    free(h->chol);
+    free(h);
+}
+
+/* y = A x, each row summed in ascending column order */
+static void csr_mv(const or_csr *a, const double *x, double *y) {
+    for (int i = 0; i < a->n; ++i) {
+        double s = 0.0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) s += a->v[k] * x[a->ci[k]];
+        y[i] = s;
+    }
+}
+
+static double dot(int n, const double *x, const double *y) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+static double diag_entry(const or_csr *a, int i) {
+    for (int k = a->rp[i]; k < a->rp[i + 1]; ++k)
+        if (a->ci[k] == i) return a->v[k];
+    return 0.0;
+}
+
+/* ----------------------------------------------- matching (Sec. 3.1, R3-R5) */
+
+typedef struct { double c; int lo, hi; } or_edge;
+
+static int edge_order(const void *pa, const void *pb) {
+    const or_edge *a = (const or_edge *)pa, *b = (const or_edge *)pb;
+    if (a->c > b->c) return -1;          /* weight descending */
+    if (a->c < b->c) return 1;
+    if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+    if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+    return 0;
+}
+
+/* weight c_ij of eq. (weights), evaluated as in R4 */
+static double edge_weight(double a_lohi, double a_lolo, double a_hihi, double w_lo, double w_hi) {
+    double num = ((2.0 * a_lohi) * w_lo) * w_hi;
+    double den = (a_lolo * w_lo) * w_lo + (a_hihi * w_hi) * w_hi;
+    return 1.0 - num / den;
+}
+
+/* mate[i] = partner or -1.  Returns number of pairs, or -1 on OOM. */
+static long greedy_matching(const or_csr *a, const double *w, int match_all, int *mate) {
+    int n = a->n;
+    double *diag = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!diag) return -1;
+    for (int i = 0; i < n; ++i) diag[i] = diag_entry(a, i);
+    long ne = 0;
+    for (int i = 0; i < n; ++i)
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k)
+            if (a->ci[k] > i) ++ne;
+    or_edge *e = (or_edge *)malloc(sizeof(or_edge) * (size_t)(ne > 0 ? ne : 1));
+    if (!e) { free(diag); return -1; }
+    long m = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            int j = a->ci[k];
+            if (j <= i) continue;               /* lo = i, hi = j, a_{lo,hi} stored in row lo */
+            double c = edge_weight(a->v[k], diag[i], diag[j], w[i], w[j]);
+            if (match_all || c > 1.0) { e[m].c = c; e[m].lo = i; e[m].hi = j; ++m; }
+        }
+    }
+    qsort(e, (size_t)m, sizeof(or_edge), edge_order);
+    for (int i = 0; i < n; ++i) mate[i] = -1;
+    long pairs = 0;
+    for (long t = 0; t < m; ++t) {
+        if (mate[e[t].lo] < 0 && mate[e[t].hi] < 0) {
+            mate[e[t].lo] = e[t].hi;
+            mate[e[t].hi] = e[t].lo;
+            ++pairs;
+        }
+    }
+    free(e); free(diag);
+    return pairs;
+}
+
+/* ------------------------------------ aggregates and prolongator (R6, R7) */
+
+/* returns n_c; fills agg, p (level l) and wc (level l+1) */
+static int build_aggregates(int n, const int *mate, const double *w, int *agg, double *p, double *wc) {
+    int nc = 0;
+    for (int i = 0; i < n; ++i) {
+        int m = mate[i];
+        if (m < 0) {                              /* singleton: W = diag(w_s/|w_s|) */
+            agg[i] = nc;
+            p[i] = w[i] / fabs(w[i]);
+            wc[nc] = fabs(w[i]);
+            ++nc;
+        } else if (m > i) {                       /* pair (i, m), i smallest member */
+            double nu = sqrt(w[i] * w[i] + w[m] * w[m]);
+            agg[i] = nc; agg[m] = nc;
+            p[i] = w[i] / nu;
+            p[m] = w[m] / nu;
+            wc[nc] = nu;
+            ++nc;
+        }                                          /* m < i: already assigned */
+    }
+    return nc;
+}
+
+/* ------------------------------------------------------- Galerkin (R8) */
+
+typedef struct {
+    int I, J;           /* coarse position */
+    int k1, k2, k3;     /* min(i,j), max(i,j), i */
+    double t;           /* a_ij * (p_i * p_j) */
+} or_term;
+
+static int term_order(const void *pa, const void *pb) {
+    const or_term *a = (const or_term *)pa, *b = (const or_term *)pb;
+    if (a->I != b->I) return a->I < b->I ? -1 : 1;
+    if (a->J != b->J) return a->J < b->J ? -1 : 1;
+    if (a->k1 != b->k1) return a->k1 < b->k1 ? -1 : 1;
+    if (a->k2 != b->k2) return a->k2 < b->k2 ? -1 : 1;
+    if (a->k3 != b->k3) return a->k3 < b->k3 ? -1 : 1;
+    return 0;
+}
+
+static int galerkin(const or_csr *a, const int *agg, const double *p, int nc, or_csr *out) {
+    long nnz = a->nnz;
+    or_term *t = (or_term *)malloc(sizeof(or_term) * (size_t)nnz);
+    if (!t) return OR_E_OOM;
+    long m = 0;
+    for (int i = 0; i < a->n; ++i) {
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            int j = a->ci[k];
+            t[m].I = agg[i]; t[m].J = agg[j];
+            t[m].k1 = i < j ? i : j;
+            t[m].k2 = i < j ? j : i;
+            t[m].k3 = i;
+            t[m].t = a->v[k] * (p[i] * p[j]);
+            ++m;
+        }
+    }
+    qsort(t, (size_t)m, sizeof(or_term), term_order);
+    /* count distinct (I, J) */
+    long cnt = 0;
+    for (long s = 0; s < m; ++s)
+        if (s == 0 || t[s].I != t[s - 1].I || t[s].J != t[s - 1].J) ++cnt;
+    out->n = nc;
+    out->nnz = cnt;
+    out->rp = (int *)calloc((size_t)nc + 1, sizeof(int));
+    out->ci = (int *)malloc(sizeof(int) * (size_t)(cnt > 0 ? cnt : 1));
+    out->v = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+    if (!out->rp || !out->ci || !out->v) { free(t); return OR_E_OOM; }
+    long q = -1;
+    for (long s = 0; s < m; ++s) {
+        if (s == 0 || t[s].I != t[s - 1].I || t[s].J != t[s - 1].J) {
+            ++q;
+            out->ci[q] = t[s].J;
+            out->v[q] = t[s].t;                  /* the first term starts the sum */
+            out->rp[t[s].I + 1]++;
+        } else {
+            out->v[q] = out->v[q] + t[s].t;
+        }
+    }
+    for (int I = 0; I < nc; ++I) out->rp[I + 1] += out->rp[I];
+    free(t);
+    return OR_OK;
+}
+
+/* ------------------------------------------------- l1 diagonal (R1) */
+
+static int l1_inverse(const or_csr *a, double *dinv) {
+    for (int i = 0; i < a->n; ++i) {
+        double d = 0.0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) d += fabs(a->v[k]);
+        if (!(d > 0.0)) return OR_E_NUMERIC;
+        dinv[i] = 1.0 / d;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------ dense Cholesky (coarsest, R9) */
+
+static int dense_cholesky(const or_csr *a, double **out) {
+    int n = a->n;
+    double *L = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    if (!L) return OR_E_OOM;
+    for (int i = 0; i < n; ++i)
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) L[(size_t)i * n + a->ci[k]] = a->v[k];
+    /* left-looking column algorithm on the lower triangle */
+    for (int j = 0; j < n; ++j) {
+        double s = L[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 0.0)) { free(L); return OR_E_NOT_SPD; }
+        double d = sqrt(s);
+        L[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = L[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / d;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) L[(size_t)i * n + j] = 0.0;
+    *out = L;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------ setup */
+
+static int validate(int n, const int *rp, const int *ci, const double *v) {
+    if (n <= 0 || !rp || !ci || !v) return OR_E_INVALID;
+    if (rp[0] != 0) return OR_E_INVALID;
+    for (int i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return OR_E_INVALID;
+        int has_diag = 0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= n) return OR_E_INVALID;
+            if (k > rp[i] && ci[k] <= ci[k - 1]) return OR_E_INVALID;
+            if (ci[k] == i) { has_diag = 1; if (!(v[k] > 0.0)) return OR_E_INVALID; }
+        }
+        if (!has_diag) return OR_E_INVALID;
+    }
+    return OR_OK;
+}
+
+int oracle_setup(int n, const int *rp, const int *ci, const double *v,
+                 int max_coarse, int max_levels, int max_dense, int match_all,
+                 or_hier **out) {
+    *out = NULL;
+    int st = validate(n, rp, ci, v);
+    if (st) return st;
+    if (max_levels < 1 || max_levels > OR_MAX_LEVELS) return OR_E_INVALID;
+    or_hier *h = (or_hier *)calloc(1, sizeof(or_hier));
+    if (!h) return OR_E_OOM;
+    or_csr *A0 = &h->A[0];
+    long nnz = rp[n];
+    A0->n = n; A0->nnz = nnz;
+    A0->rp = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    A0->ci = (int *)malloc(sizeof(int) * (size_t)nnz);
+    A0->v = (double *)malloc(sizeof(double) * (size_t)nnz);
+    h->w[0] = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!A0->rp || !A0->ci || !A0->v || !h->w[0]) { oracle_free(h); return OR_E_OOM; }
+    memcpy(A0->rp, rp, sizeof(int) * ((size_t)n + 1));
+    memcpy(A0->ci, ci, sizeof(int) * (size_t)nnz);
+    memcpy(A0->v, v, sizeof(double) * (size_t)nnz);
+    for (int i = 0; i < n; ++i) h->w[0][i] = 1.0;         /* R2 */
+
+    int l = 0;
+    for (;;) {
+        or_csr *A = &h->A[l];
+        h->dinv[l] = (double *)malloc(sizeof(double) * (size_t)A->n);
+        if (!h->dinv[l]) { oracle_free(h); return OR_E_OOM; }
+        st = l1_inverse(A, h->dinv[l]);
+        if (st) { oracle_free(h); return st; }
+        if (A->n <= max_coarse || l + 1 >= max_levels) break;
+        int *mate = (int *)malloc(sizeof(int) * (size_t)A->n);
+        if (!mate) { oracle_free(h); return OR_E_OOM; }
+        long pairs = greedy_matching(A, h->w[l], match_all, mate);
+        if (pairs < 0) { free(mate); oracle_free(h); return OR_E_OOM; }
+        if (pairs == 0) { free(mate); break; }               /* stall: this level is coarsest */
+        h->n_pairs[l] = (int)pairs;
+        h->agg[l] = (int *)malloc(sizeof(int) * (size_t)A->n);
+        h->p[l] = (double *)malloc(sizeof(double) * (size_t)A->n);
+        h->w[l + 1] = (double *)malloc(sizeof(double) * (size_t)A->n);
+        if (!h->agg[l] || !h->p[l] || !h->w[l + 1]) { free(mate); oracle_free(h); return OR_E_OOM; }
+        int nc = build_aggregates(A->n, mate, h->w[l], h->agg[l], h->p[l], h->w[l + 1]);
+        free(mate);
+        st = galerkin(A, h->agg[l], h->p[l], nc, &h->A[l + 1]);
+        if (st) { oracle_free(h); return st; }
+        ++l;
+    }
+    h->nlev = l + 1;
+    if (h->A[l].n > max_dense) { oracle_free(h); return OR_E_STALLED; }
+    st = dense_cholesky(&h->A[l], &h->chol);
+    if (st) { oracle_free(h); return st; }
+    *out = h;
+    return OR_OK;
+}
+
+/* Copy of a hierarchy with A_l, dinv_l, p_l and the Cholesky factor rounded to
+ * binary32 (stored as binary64).  Aggregates are those of the FP64 build. */
+int oracle_round_f32(const or_hier *h, or_hier **out) {
+    *out = NULL;
+    or_hier *g = (or_hier *)calloc(1, sizeof(or_hier));
+    if (!g) return OR_E_OOM;
+    g->nlev = h->nlev;
+    for (int l = 0; l < h->nlev; ++l) {
+        const or_csr *a = &h->A[l];
+        or_csr *b = &g->A[l];
+        b->n = a->n; b->nnz = a->nnz;
+        b->rp = (int *)malloc(sizeof(int) * ((size_t)a->n + 1));
+        b->ci = (int *)malloc(sizeof(int) * (size_t)a->nnz);
+        b->v = (double *)malloc(sizeof(double) * (size_t)a->nnz);
+        g->dinv[l] = (double *)malloc(sizeof(double) * (size_t)a->n);
+        g->w[l] = (double *)malloc(sizeof(double) * (size_t)a->n);
+        if (!b->rp || !b->ci || !b->v || !g->dinv[l] || !g->w[l]) { oracle_free(g); return OR_E_OOM; }
+        memcpy(b->rp, a->rp, sizeof(int) * ((size_t)a->n + 1));
+        memcpy(b->ci, a->ci, sizeof(int) * (size_t)a->nnz);
+        for (long k = 0; k < a->nnz; ++k) b->v[k] = (double)(float)a->v[k];
+        for (int i = 0; i < a->n; ++i) {
+            g->dinv[l][i] = (double)(float)h->dinv[l][i];
+            g->w[l][i] = h->w[l][i];
+        }
+        if (l + 1 < h->nlev) {
+            g->agg[l] = (int *)malloc(sizeof(int) * (size_t)a->n);
+            g->p[l] = (double *)malloc(sizeof(double) * (size_t)a->n);
+            if (!g->agg[l] || !g->p[l]) { oracle_free(g); return OR_E_OOM; }
+            memcpy(g->agg[l], h->agg[l], sizeof(int) * (size_t)a->n);
+            for (int i = 0; i < a->n; ++i) g->p[l][i] = (double)(float)h->p[l][i];
+            g->n_pairs[l] = h->n_pairs[l];
+        }
+    }
+    int nL = h->A[h->nlev - 1].n;
+    g->chol = (double *)malloc(sizeof(double) * (size_t)nL * (size_t)nL);
+    if (!g->chol) { oracle_free(g); return OR_E_OOM; }
+    for (size_t k = 0; k < (size_t)nL * (size_t)nL; ++k) g->chol[k] = (double)(float)h->chol[k];
+    *out = g;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------- accessors */
+
+int oracle_nlevels(const or_hier *h) { return h->nlev; }
+int oracle_level_n(const or_hier *h, int l) { return h->A[l].n; }
+long oracle_level_nnz(const or_hier *h, int l) { return h->A[l].nnz; }
+int oracle_level_pairs(const or_hier *h, int l) { return h->n_pairs[l]; }
+
+void oracle_get_level(const or_hier *h, int l, int *rp, int *ci, double *v) {
+    const or_csr *a = &h->A[l];
+    memcpy(rp, a->rp, sizeof(int) * ((size_t)a->n + 1));
+    memcpy(ci, a->ci, sizeof(int) * (size_t)a->nnz);
+    memcpy(v, a->v, sizeof(double) * (size_t)a->nnz);
+}
+void oracle_get_agg(const or_hier *h, int l, int *agg) { memcpy(agg, h->agg[l], sizeof(int) * (size_t)h->A[l].n); }
+void oracle_get_p(const or_hier *h, int l, double *p) { memcpy(p, h->p[l], sizeof(double) * (size_t)h->A[l].n); }
+void oracle_get_w(const or_hier *h, int l, double *w) { memcpy(w, h->w[l], sizeof(double) * (size_t)h->A[l].n); }
+void oracle_get_dinv(const or_hier *h, int l, double *d) { memcpy(d, h->dinv[l], sizeof(double) * (size_t)h->A[l].n); }
+void oracle_get_chol(const or_hier *h, double *L) {
+    int n = h->A[h->nlev - 1].n;
+    memcpy(L, h->chol, sizeof(double) * (size_t)n * (size_t)n);
+}
+
+/* ------------------------------------------------ operators (Sec. 3.1) */
+
+void oracle_spmv(const or_hier *h, int l, const double *x, double *y) { csr_mv(&h->A[l], x, y); }
+
+/* r_c = P_l^T t: members of each aggregate added in ascending fine index */
+void oracle_restrict(const or_hier *h, int l, const double *t, double *rc) {
+    int nc = h->A[l + 1].n;
+    for (int I = 0; I < nc; ++I) rc[I] = 0.0;
+    for (int i = 0; i < h->A[l].n; ++i) rc[h->agg[l][i]] += h->p[l][i] * t[i];
+}
+
+/* z += P_l e */
+void oracle_prolong_add(const or_hier *h, int l, const double *e, double *z) {
+    for (int i = 0; i < h->A[l].n; ++i) z[i] += h->p[l][i] * e[h->agg[l][i]];
+}
+
+/* z = A_L^{-1} r by forward then backward substitution with the dense factor */
+void oracle_coarse_solve(const or_hier *h, const double *r, double *z) {
+    int n = h->A[h->nlev - 1].n;
+    const double *L = h->chol;
+    for (int i = 0; i < n; ++i) {
+        double s = r[i];
+        for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * z[k];
+        z[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];
+        z[i] = s / L[(size_t)i * n + i];
+    }
+}
+
+/* z = V(l, r): eq. (multiplicative_composition) with nu = 1, M = diag(l1) */
+void oracle_vcycle(const or_hier *h, int l, const double *r, double *z) {
+    int L = h->nlev - 1;
+    if (l == L) { oracle_coarse_solve(h, r, z); return; }
+    int n = h->A[l].n, nc = h->A[l + 1].n;
+    const double *dinv = h->dinv[l];
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rc = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *e = (double *)malloc(sizeof(double) * (size_t)nc);
+    for (int i = 0; i < n; ++i) z[i] = dinv[i] * r[i];          /* pre-smooth from zero */
+    csr_mv(&h->A[l], z, t);
+    for (int i = 0; i < n; ++i) t[i] = r[i] - t[i];             /* residual */
+    oracle_restrict(h, l, t, rc);                               /* restriction */
+    oracle_vcycle(h, l + 1, rc, e);                             /* coarse correction */
+    oracle_prolong_add(h, l, e, z);                             /* prolongation */
+    csr_mv(&h->A[l], z, t);
+    for (int i = 0; i < n; ++i) z[i] += dinv[i] * (r[i] - t[i]); /* post-smooth */
+    free(t); free(rc); free(e);
+}
+
+/* ---------------------------------------------------- Krylov (Sec. 5, R10) */
+
+/*
+ * krylov: 0 = PCG, 1 = FCG(1).  use_x0: x holds the initial guess on entry.
+ * fixed_iters > 0: run exactly that many iterations and ignore tol.
+ * true_res: at convergence recompute b - A x; if it exceeds tol*||b||, restart
+ * the recurrence from it (at most 10 restarts).
+ * Outputs: x, *iters, *relres (recurrence residual / ||b||).
+ */
+int oracle_solve(const or_hier *h, const double *b, double *x, double tol, int maxit,
+                 int krylov, int use_x0, int fixed_iters, int true_res,
+                 int *iters, double *relres) {
+    int n = h->A[0].n;
+    const or_csr *A = &h->A[0];
+    *iters = 0; *relres = 0.0;
+    double nb = sqrt(dot(n, b, b));
+    if (!use_x0) for (int i = 0; i < n; ++i) x[i] = 0.0;
+    if (nb == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        return OR_OK;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r || !z || !p || !q) { free(r); free(z); free(p); free(q); return OR_E_OOM; }
+    int status = OR_NOT_CONVERGED;
+    int it = 0, restarts = 0;
+    double rn = 0.0;
+restart:
+    csr_mv(A, x, q);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    rn = sqrt(dot(n, r, r));
+    if (fixed_iters <= 0 && rn <= tol * nb) { status = OR_OK; goto done; }
+    {
+        double rho_old = 0.0, delta_old = 0.0;
+        for (int k = 0; ; ++k) {
+            if (fixed_iters > 0 ? it >= fixed_iters : it >= maxit) { status = fixed_iters > 0 ? OR_OK : OR_NOT_CONVERGED; break; }
+            oracle_vcycle(h, 0, r, z);
+            double alpha_num;
+            if (krylov == 0) {
+                double rho = dot(n, r, z);
+                if (k == 0) for (int i = 0; i < n; ++i) p[i] = z[i];
+                else { double beta = rho / rho_old; for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i]; }
+                rho_old = rho;
+                alpha_num = rho;
+            } else {
+                if (k == 0) for (int i = 0; i < n; ++i) p[i] = z[i];
+                else {
+                    double beta = -dot(n, z, q) / delta_old;      /* q holds q_old here */
+                    for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+                }
+                alpha_num = 0.0;                                  /* set after q */
+            }
+            csr_mv(A, p, q);
+            double delta = dot(n, p, q);
+            if (!(delta > 0.0)) { status = OR_E_NOT_SPD; goto done; }
+            if (krylov != 0) alpha_num = dot(n, p, r);
+            double alpha = alpha_num / delta;
+            for (int i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+            delta_old = delta;
+            ++it;
+            rn = sqrt(dot(n, r, r));
+            if (!(rn == rn)) { status = OR_E_NUMERIC; goto done; }
+            if (fixed_iters <= 0 && rn <= tol * nb) { status = OR_OK; break; }
+        }
+    }
+    if (status == OR_OK && true_res && fixed_iters <= 0) {
+        csr_mv(A, x, q);
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) { double d = b[i] - q[i]; tr += d * d; }
+        if (sqrt(tr) > tol * nb && restarts < 10 && it < maxit) { ++restarts; status = OR_NOT_CONVERGED; goto restart; }
+    }
+done:
+    *iters = it;
+    *relres = rn / nb;
+    free(r); free(z); free(p); free(q);
+    return status;
+}

@@ -1,0 +1,55 @@
+"""The oracle's pins must reject plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (a dropped term,
+a wrong sign or index, a transposed operand, a flipped tie-break), compiles
+it on the CPU and runs the pin suite against it in a subprocess: every mutant
+must make at least one pin fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    "post_smooth_sign": ("z[i] += dinv[i] * (r[i] - t[i]);", "z[i] += dinv[i] * (t[i] - r[i]);"),
+    "residual_sign": ("t[i] = r[i] - t[i];", "t[i] = r[i] + t[i];"),
+    "prolong_drops_p": ("z[i] += h->p[l][i] * e[h->agg[l][i]];", "z[i] += e[h->agg[l][i]];"),
+    "restrict_drops_p": ("rc[h->agg[l][i]] += h->p[l][i] * t[i];", "rc[h->agg[l][i]] += t[i];"),
+    "weight_wrong_index": ("double num = ((2.0 * a_lohi) * w_lo) * w_hi;",
+                           "double num = ((2.0 * a_lohi) * w_lo) * w_lo;"),
+    "eligibility_all": ("if (match_all || c > 1.0)", "if (match_all || c > 0.0)"),
+    "galerkin_transposed_p": ("t[m].t = a->v[k] * (p[i] * p[j]);", "t[m].t = a->v[k] * (p[i] * p[i]);"),
+    "tie_break_flipped": ("if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;",
+                          "if (a->lo != b->lo) return a->lo < b->lo ? 1 : -1;"),
+    "fcg_beta_sign": ("double beta = -dot(n, z, q) / delta_old;", "double beta = dot(n, z, q) / delta_old;"),
+    "pcg_direction_sign": ("double beta = rho / rho_old; for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];",
+                           "double beta = rho / rho_old; for (int i = 0; i < n; ++i) p[i] = z[i] - beta * p[i];"),
+    "cholesky_drops_term": ("for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];",
+                            "for (int k = 1; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];"),
+    "l1_not_absolute": ("for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) d += fabs(a->v[k]);",
+                        "for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) d += a->v[k];"),
+    "pair_norm_wrong": ("double nu = sqrt(w[i] * w[i] + w[m] * w[m]);", "double nu = sqrt(w[i] * w[i] + w[i] * w[m]);"),
+    "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
+                             "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    mut = tmp_path / "oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", str(mut), "-o", str(so), "-lm"],
+                   check=True)
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

@@ -1,0 +1,436 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, library routines (numpy / scipy / networkx), brute force on tiny
+inputs, invariants the paper states, and the V-cycle error-propagation
+formula (Sec. 3.1, eq. multiplicative_composition).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from workloads import CSR, lap7, varcoef7, q1_stretched, q1_rhs, uniform_rhs
+
+ULP = np.finfo(np.float64).eps
+
+
+def csr_from_scipy(M) -> CSR:
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    return CSR(M.shape[0], M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def prolongator(H, l):
+    n, nc = H.n(l), H.n(l + 1)
+    return sp.csr_matrix((H.p(l), (np.arange(n), H.agg(l))), shape=(n, nc))
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def test_lap7_eigenpairs_through_oracle_spmv():
+    # A u = lambda u for u = sin(p pi x) sin(q pi y) sin(r pi z) at the nodes,
+    # lambda = (4/h^2)(sin^2(p pi h/2) + sin^2(q pi h/2) + sin^2(r pi h/2)).
+    n = 32
+    h = 1.0 / (n + 1)
+    H = oracle.Hierarchy(lap7(n))
+    x = (np.arange(n) + 1) * h
+    for (p, q, r) in [(1, 1, 1), (32, 32, 32), (3, 7, 20), (1, 32, 5)]:
+        u = (np.sin(p * np.pi * x)[None, None, :] * np.sin(q * np.pi * x)[None, :, None]
+             * np.sin(r * np.pi * x)[:, None, None]).reshape(-1)     # idx = i + n j + n^2 k
+        lam = 4.0 / h ** 2 * (np.sin(p * np.pi * h / 2) ** 2 + np.sin(q * np.pi * h / 2) ** 2
+                              + np.sin(r * np.pi * h / 2) ** 2)
+        Au = H.spmv(0, u)
+        assert np.linalg.norm(Au - lam * u) <= 1e-12 * lam * np.linalg.norm(u)
+    lmin = 12.0 / h ** 2 * np.sin(np.pi * h / 2) ** 2
+    lmax = 12.0 / h ** 2 * np.sin(32 * np.pi * h / 2) ** 2
+    assert lmax / lmin == pytest.approx(1.0 / np.tan(np.pi / 66) ** 2, rel=1e-12)
+
+
+def test_l1_diagonal_closed_form():
+    # D_ii = sum_j |a_ij|: 12/h^2 interior, 11/h^2 next to one face, 10 next to an
+    # edge, 9 next to a corner (7-point stencil with Dirichlet boundary).
+    n = 8
+    H = oracle.Hierarchy(lap7(n), max_coarse=10 ** 9)
+    inv_h2 = float((n + 1) ** 2)
+    d = 1.0 / H.dinv(0)
+    i = np.arange(n)
+    I, J, K = np.meshgrid(i, i, i, indexing="ij")
+    bnd = (I == 0).astype(int) + (I == n - 1) + (J == 0) + (J == n - 1) + (K == 0) + (K == n - 1)
+    expect = ((12 - bnd) * inv_h2).transpose(2, 1, 0).reshape(-1)
+    assert np.array_equal(H.dinv(0), 1.0 / expect)
+    assert np.allclose(d, expect, rtol=4 * ULP)
+
+
+def _stencil7(nx, ny, nz, diag, cx, cy, cz):
+    """Dense-free 7-point operator on an nx*ny*nz grid (x fastest)."""
+    N = nx * ny * nz
+    idx = np.arange(N).reshape(nz, ny, nx)
+    rows, cols, vals = [np.arange(N)], [np.arange(N)], [np.full(N, diag)]
+    for (a, b, c) in [(idx[:, :, :-1], idx[:, :, 1:], cx), (idx[:, :-1, :], idx[:, 1:, :], cy),
+                      (idx[:-1, :, :], idx[1:, :, :], cz)]:
+        rows += [a.ravel(), b.ravel()]
+        cols += [b.ravel(), a.ravel()]
+        vals += [np.full(a.size, c), np.full(a.size, c)]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def test_lap7_32_first_levels_closed_form():
+    # Hand derivation for the 32^3 Laplacian with w = 1:
+    #  level 0: every weight equals 7/6, so the (lo, hi) tie-break pairs (i, i+1) along x;
+    #  A_1 = h^-2 [5; x -1/2, y -1, z -1] on 16x32x32, weights 1.1 (x) and 1.2 (y, z) -> y pairs;
+    #  A_2 = h^-2 [4; x -1/2, y -1/2, z -1] on 16x16x32, weights 1.125, 1.125, 1.25 -> z pairs;
+    #  A_3 = h^-2 [3; -1/2 x 6] on 16^3 (half the 16^3 Laplacian).  No singletons.
+    n = 32
+    inv_h2 = 33.0 ** 2
+    H = oracle.Hierarchy(lap7(n))
+    assert [H.n(l) for l in range(4)] == [32768, 16384, 8192, 4096]
+    assert [H.pairs(l) for l in range(3)] == [16384, 8192, 4096]
+    i = np.arange(32768)
+    assert np.array_equal(H.agg(0), i // 2)
+    # level 1 grid 16 x 32 x 32: y pairs (j = 2m, 2m+1)
+    i1 = np.arange(16384)
+    x1, y1, z1 = i1 % 16, (i1 // 16) % 32, i1 // 512
+    assert np.array_equal(H.agg(1), x1 + 16 * (y1 // 2) + 256 * z1)
+    i2 = np.arange(8192)
+    x2, y2, z2 = i2 % 16, (i2 // 16) % 16, i2 // 256
+    assert np.array_equal(H.agg(2), x2 + 16 * y2 + 256 * (z2 // 2))
+    expected = {1: (16, 32, 32, 5.0, -0.5, -1.0, -1.0), 2: (16, 16, 32, 4.0, -0.5, -0.5, -1.0),
+                3: (16, 16, 16, 3.0, -0.5, -0.5, -0.5)}
+    for l, (nx, ny, nz, d, cx, cy, cz) in expected.items():
+        E = _stencil7(nx, ny, nz, d * inv_h2, cx * inv_h2, cy * inv_h2, cz * inv_h2)
+        A = H.level_scipy(l)
+        assert np.array_equal(A.indptr, E.indptr) and np.array_equal(A.indices, E.indices)
+        assert np.allclose(A.data, E.data, rtol=8 * ULP, atol=0)
+    # all the way down: 9 levels, coarsest 128 unknowns (pairs every level)
+    assert H.nlevels == 9 and H.n(8) == 128
+
+
+def test_1d_galerkin_halves_the_operator():
+    # tridiag(-1, 2, -1) of even size: all weights 3/2 tie, pairs (2k, 2k+1),
+    # p = 1/sqrt(2) and A_1 = 1/2 tridiag(-1, 2, -1).
+    n = 64
+    T = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    H = oracle.Hierarchy(csr_from_scipy(T), max_coarse=32)
+    assert H.nlevels == 2
+    assert np.array_equal(H.agg(0), np.arange(n) // 2)
+    A1 = H.level_scipy(1).toarray()
+    E = 0.5 * sp.diags([-np.ones(31), 2 * np.ones(32), -np.ones(31)], [-1, 0, 1]).toarray()
+    assert np.allclose(A1, E, rtol=4 * ULP, atol=4 * ULP)
+    assert np.allclose(H.p(0), 1 / math.sqrt(2), rtol=ULP)
+
+
+# --------------------------------------------------------------------------- matching
+
+def test_1d_odd_size_tie_break():
+    # tridiag(-1, 2, -1) of size 9: every weight ties at 3/2, so the order (lo, hi)
+    # ascending decides: pairs (0,1), (2,3), (4,5), (6,7) and the singleton 8.
+    n = 9
+    T = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    H = oracle.Hierarchy(csr_from_scipy(T), max_coarse=1, max_levels=2)
+    assert np.array_equal(H.agg(0), [0, 0, 1, 1, 2, 2, 3, 3, 4])
+    assert H.p(0)[8] == 1.0 and H.w(1)[4] == 1.0
+
+
+def _random_spd(n, density, seed, discrete=False):
+    rng = np.random.default_rng(seed)
+    if discrete:   # few distinct values: many exact weight ties
+        rvs = lambda k: rng.choice([-1.0, -0.5, -0.25, 0.25], k)
+    else:
+        rvs = lambda k: rng.uniform(-1, 0.3, k)
+    M = sp.random(n, n, density=density, random_state=rng, data_rvs=rvs)
+    M = sp.triu(M, 1)
+    M = M + M.T
+    d = np.asarray(abs(M).sum(axis=1)).ravel() + (0.5 if discrete else rng.uniform(0.1, 1.0, n))
+    M = M + sp.diags(d)
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    return M
+
+
+def _edge_weight(a, aii, ajj, wi, wj):
+    return 1.0 - 2.0 * a * wi * wj / (aii * wi * wi + ajj * wj * wj)
+
+
+def _weights_eq(a, aii, ajj, wi, wj):
+    """eq. (weights) evaluated in the oracle's stated operation order (R4), so that
+    ties compare exactly; numpy float64 arithmetic, one rounding per operation."""
+    num = ((2.0 * a) * wi) * wj
+    den = (aii * wi) * wi + (ajj * wj) * wj
+    return 1.0 - num / den
+
+
+def _check_matching_level(H, l, check_half_approx=True):
+    """Greedy characterisation + half-approximation for level l of H."""
+    import networkx as nx
+    A = H.level_scipy(l)
+    agg = H.agg(l)
+    w = H.w(l)
+    D = A.diagonal()
+    Au = sp.triu(A, 1).tocoo()
+    edges = {}
+    for i, j, a in zip(Au.row, Au.col, Au.data):
+        c = _weights_eq(a, D[i], D[j], w[i], w[j])
+        if c > 1.0:
+            edges[(int(i), int(j))] = c
+    order = np.argsort(agg, kind="stable")
+    sa = agg[order]
+    M = set()
+    starts = np.flatnonzero(np.r_[True, sa[1:] != sa[:-1]])
+    sizes = np.diff(np.r_[starts, len(sa)])
+    assert sizes.min() >= 1 and sizes.max() <= 2
+    for s0, sz in zip(starts, sizes):
+        if sz == 2:
+            M.add((int(order[s0]), int(order[s0 + 1])))
+    assert all(e in edges for e in M), "matched an ineligible edge"
+    key = lambda e: (-edges[e], e[0], e[1])   # weight descending, then lo, then hi
+    at = {}
+    for e in M:
+        at[e[0]] = e
+        at[e[1]] = e
+    for e in edges:
+        if e in M:
+            continue
+        dom = [f for f in (at.get(e[0]), at.get(e[1])) if f is not None and key(f) < key(e)]
+        assert dom, f"level {l}: edge {e} not dominated, so the matching is not the greedy one"
+    if check_half_approx:
+        G = nx.Graph()
+        for (i, j), c in edges.items():
+            G.add_edge(i, j, weight=math.log(c))
+        opt = nx.max_weight_matching(G)
+        wopt = sum(math.log(edges[(min(a, b), max(a, b))]) for a, b in opt)
+        wg = sum(math.log(edges[e]) for e in M)
+        assert wg >= 0.5 * wopt - 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("discrete", [False, True])
+def test_matching_greedy_characterisation_and_half_approx(seed, discrete):
+    # The greedy matching under a strict total order is the unique matching M in
+    # which every eligible edge outside M touches a heavier edge of M; its weight
+    # is at least half the optimum (the bound the paper quotes for its matching).
+    # Weight of an edge = log c (maximum product), eligible iff c > 1.
+    A = _random_spd(60, 0.12, seed, discrete=discrete)
+    H = oracle.Hierarchy(csr_from_scipy(A), max_coarse=1, max_levels=2)
+    _check_matching_level(H, 0)
+
+
+@pytest.mark.parametrize("case", ["varcoef_12", "q1_7"])
+def test_matching_characterisation_on_every_level(case):
+    # coarse levels carry a non-uniform w (singletons keep |w_s|, pairs get the norm)
+    A = {"varcoef_12": lambda: varcoef7(12, seed=4), "q1_7": lambda: q1_stretched(7, 1.05)}[case]()
+    H = oracle.Hierarchy(A, max_coarse=10)
+    assert any(len(np.unique(H.w(l))) > 2 for l in range(1, H.nlevels))
+    for l in range(H.nlevels - 1):
+        _check_matching_level(H, l, check_half_approx=H.n(l) <= 400)
+
+
+# --------------------------------------------------------------------------- invariants
+
+CASES = {
+    "lap7_10": lambda: lap7(10),
+    "varcoef_9": lambda: varcoef7(9, seed=5),
+    "q1_6": lambda: q1_stretched(6, 1.05),
+    "q1_8_uniform": lambda: q1_stretched(8, 1.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_aggregation_invariants(case):
+    A = CASES[case]()
+    H = oracle.Hierarchy(A, max_coarse=20)
+    assert H.nlevels >= 2
+    for l in range(H.nlevels - 1):
+        n, nc = H.n(l), H.n(l + 1)
+        agg = H.agg(l)
+        counts = np.bincount(agg, minlength=nc)
+        # a partition of {0..n-1} into aggregates of size 1 or 2; n_c = n_M + n_S >= n/2
+        assert agg.min() == 0 and agg.max() == nc - 1
+        assert counts.min() >= 1 and counts.max() <= 2
+        assert H.pairs(l) == int((counts == 2).sum()) and nc == n - H.pairs(l)
+        assert 2 * nc >= n
+        # coarse numbering by smallest member ascending
+        first = np.full(nc, n)
+        np.minimum.at(first, agg, np.arange(n))
+        assert np.all(np.diff(first) > 0)
+        P = prolongator(H, l)
+        # orthonormal columns and w in range(P): P^T P = I, P w_c = w
+        PtP = (P.T @ P).toarray()
+        assert np.allclose(PtP, np.eye(nc), rtol=0, atol=2 * ULP)
+        assert np.allclose(P @ H.w(l + 1), H.w(l), rtol=2 * ULP, atol=0)
+        # Galerkin product (Sec. 3.1) against scipy's triple product
+        Al = H.level_scipy(l)
+        Ac = H.level_scipy(l + 1)
+        G = (P.T @ Al @ P).tocsr()
+        assert np.allclose(Ac.toarray(), G.toarray(), rtol=1e-14, atol=1e-14 * abs(Al).max())
+        # bitwise symmetric, SPD
+        Ad = Ac.toarray()
+        assert np.array_equal(Ad.view(np.uint64), Ad.T.view(np.uint64))
+        np.linalg.cholesky(Ad)
+        # A_c w_c = P^T A w
+        lhs = Ac @ H.w(l + 1)
+        rhs = P.T @ (Al @ H.w(l))
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12 * np.abs(Al).max() * np.abs(H.w(l)).max())
+        # pairs are eligible edges (c > 1)
+        D = Al.diagonal()
+        w = H.w(l)
+        for I in np.nonzero(counts == 2)[0][:200]:
+            i, j = np.nonzero(agg == I)[0]
+            assert _edge_weight(Al[i, j], D[i], D[j], w[i], w[j]) > 1.0
+    # coarsest factor against numpy's Cholesky
+    L = H.chol()
+    AL = H.level_scipy(H.nlevels - 1).toarray()
+    assert np.allclose(L, np.linalg.cholesky(AL), rtol=1e-12, atol=1e-12 * np.sqrt(abs(AL).max()))
+
+
+def test_l1_diagonal_definition_general():
+    A = varcoef7(7, seed=3)
+    H = oracle.Hierarchy(A, max_coarse=10)
+    for l in range(H.nlevels):
+        M = H.level_scipy(l)
+        d = np.asarray(abs(M).sum(axis=1)).ravel()
+        assert np.allclose(1.0 / H.dinv(l), d, rtol=8 * ULP)
+
+
+# --------------------------------------------------------------------------- V-cycle
+
+def _dense_B(H, l):
+    """B_l from eq. (multiplicative_composition) with nu = 1, M_l = diag(l1):
+    I - B_l A_l = (I - D^-1 A)(I - P B_{l+1} P^T A)(I - D^-1 A), B_L = A_L^-1."""
+    A = H.level_scipy(l).toarray()
+    if l == H.nlevels - 1:
+        return np.linalg.inv(A)
+    n = A.shape[0]
+    P = prolongator(H, l).toarray()
+    S = np.eye(n) - np.diag(H.dinv(l)) @ A
+    C = np.eye(n) - P @ _dense_B(H, l + 1) @ P.T @ A
+    E = S @ C @ S
+    return (np.eye(n) - E) @ np.linalg.inv(A)
+
+
+@pytest.mark.parametrize("case", ["lap7_6", "q1_4", "varcoef_6"])
+def test_vcycle_matches_multiplicative_composition(case):
+    A = {"lap7_6": lambda: lap7(6), "q1_4": lambda: q1_stretched(4, 1.05),
+         "varcoef_6": lambda: varcoef7(6, seed=8)}[case]()
+    H = oracle.Hierarchy(A, max_coarse=12)
+    assert H.nlevels >= 3
+    n = H.n(0)
+    Bcols = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    Bf = _dense_B(H, 0)
+    assert np.allclose(Bcols, Bf, rtol=1e-10, atol=1e-10 * abs(Bf).max())
+    # symmetric positive definite preconditioner
+    assert np.allclose(Bcols, Bcols.T, rtol=1e-12, atol=1e-12 * abs(Bcols).max())
+    assert np.linalg.eigvalsh(0.5 * (Bcols + Bcols.T)).min() > 0
+
+
+def test_single_level_is_exact_inverse():
+    A = lap7(5)
+    H = oracle.Hierarchy(A, max_coarse=10 ** 6)
+    assert H.nlevels == 1
+    b = uniform_rhs(A.n, 4)
+    x, it, rr, st = H.solve(b, 1e-10, krylov="cg")
+    assert st == 0 and it == 1
+    xs = np.linalg.solve(A.to_scipy().toarray(), b)
+    assert np.linalg.norm(x - xs) <= 1e-13 * np.linalg.norm(xs)
+    z = H.coarse_solve(b)
+    import scipy.linalg as sl
+    assert np.allclose(z, sl.cho_solve(sl.cho_factor(A.to_scipy().toarray(), lower=True), b), rtol=1e-13)
+
+
+# --------------------------------------------------------------------------- Krylov
+
+@pytest.mark.parametrize("krylov", ["cg", "fcg"])
+def test_krylov_matches_dense_solve(krylov):
+    for A in (lap7(8), q1_stretched(5, 1.05), varcoef7(8, seed=2)):
+        H = oracle.Hierarchy(A, max_coarse=30)
+        b = uniform_rhs(A.n, 9)
+        Ad = A.to_scipy().toarray()
+        xs = np.linalg.solve(Ad, b)
+        x, it, rr, st = H.solve(b, 1e-13, krylov=krylov)
+        assert st == 0 and rr <= 1e-13
+        assert np.linalg.norm(x - xs) <= 1e-11 * np.linalg.norm(xs)
+        # recurrence residual matches the true one
+        assert np.linalg.norm(b - Ad @ x) <= 2e-13 * np.linalg.norm(b)
+
+
+def test_manufactured_solution():
+    # b = A u for u = sin(pi x) sin(2 pi y) sin(3 pi z) + x(1-x)y(1-y)z(1-z):
+    # ||x - u|| / ||u|| <= kappa * tol.
+    n = 24
+    A = lap7(n)
+    h = 1.0 / (n + 1)
+    t = (np.arange(n) + 1) * h
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    u = (np.sin(np.pi * X) * np.sin(2 * np.pi * Y) * np.sin(3 * np.pi * Z)
+         + X * (1 - X) * Y * (1 - Y) * Z * (1 - Z)).reshape(-1)
+    b = A.to_scipy() @ u
+    H = oracle.Hierarchy(A)
+    tol = 1e-8
+    kappa = 1.0 / np.tan(np.pi * h / 2) ** 2
+    for krylov in ("cg", "fcg"):
+        x, it, rr, st = H.solve(b, tol, krylov=krylov)
+        assert st == 0
+        assert np.linalg.norm(x - u) <= kappa * tol * np.linalg.norm(u)
+
+
+def test_pcg_and_fcg_agree_for_symmetric_preconditioner():
+    A = lap7(16)
+    b = uniform_rhs(A.n, 1)
+    H = oracle.Hierarchy(A)
+    x1, i1, r1, s1 = H.solve(b, 1e-8, krylov="cg")
+    x2, i2, r2, s2 = H.solve(b, 1e-8, krylov="fcg")
+    assert s1 == s2 == 0 and abs(i1 - i2) <= 1
+    assert np.linalg.norm(x1 - x2) <= 1e-7 * np.linalg.norm(x1)
+
+
+def test_fixed_iterations_and_warm_start():
+    A = lap7(10)
+    b = uniform_rhs(A.n, 3)
+    H = oracle.Hierarchy(A)
+    x5, it, rr5, st = H.solve(b, 0.0, fixed_iters=5)
+    assert it == 5 and st == 0
+    x_all, it_all, _, _ = H.solve(b, 1e-9)
+    # warm start from a converged solution returns immediately
+    x_w, it_w, _, st_w = H.solve(b, 1e-9, x0=x_all)
+    assert it_w == 0 and st_w == 0 and np.array_equal(x_w, x_all)
+    # zero right-hand side
+    xz, itz, _, stz = H.solve(np.zeros(A.n), 1e-6)
+    assert itz == 0 and stz == 0 and not xz.any()
+
+
+def test_diag_level_count_doubling_claim_of_plain_cg():
+    # Without multigrid the iteration count of diagonally preconditioned CG roughly
+    # doubles per halving of h; the V-cycle keeps it nearly flat.  (Qualitative,
+    # as in the paper's motivation; only the multigrid side runs through the oracle.)
+    its = []
+    for n in (8, 16, 32):
+        A = lap7(n)
+        H = oracle.Hierarchy(A)
+        _, it, _, st = H.solve(uniform_rhs(A.n, 1), 1e-6, krylov="cg")
+        assert st == 0
+        its.append(it)
+    assert its[-1] <= 2 * its[0] + 4
+
+
+# --------------------------------------------------------------------------- failures
+
+def test_invalid_inputs_rejected():
+    A = lap7(3)
+    bad = CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.col[5] = A.n + 3
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(bad)
+    assert e.value.code == oracle.E_INVALID
+    neg = CSR(A.n, A.row_ptr.copy(), A.col.copy(), -A.val.copy())
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(neg)
+    assert e.value.code == oracle.E_INVALID
+
+
+def test_indefinite_matrix_reports_not_spd():
+    M = sp.csr_matrix(np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 1.0]]))
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(csr_from_scipy(M))
+    assert e.value.code == oracle.E_NOT_SPD
