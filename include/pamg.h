@@ -1,0 +1,175 @@
+/*
+ * pamg — PCG/FCG with an aggregation-based AMG V-cycle on one MI355X (gfx950).
+ *
+ * C ABI.  All entry points return a pamg_status; on a negative status the
+ * outputs are untouched and pamg_last_error() describes the failure.  No C++
+ * exception crosses this boundary.  Pointers named *_dev are device pointers
+ * (hipMalloc'd or from a framework allocator) on the current HIP device;
+ * every other pointer is host memory.  `stream` is a hipStream_t (NULL = the
+ * default stream); work is enqueued on it and the call returns after the
+ * result it reports is known on the host.
+ *
+ * The method (arXiv 2210.16660, Sec. 3.1 and Sec. 5):
+ *   solve A x = b with A symmetric positive definite, by preconditioned CG or
+ *   flexible CG, where the preconditioner B is the V-cycle of
+ *   eq. (multiplicative_composition) with nu = 1 pre-/post-sweep of the
+ *   l1-Jacobi smoother, tentative piecewise-constant prolongators of
+ *   eq. (prolongator) built from a maximum-product matching of the weights
+ *   of eq. (weights), Galerkin coarse matrices A_{l+1} = P_l^T A_l P_l, and a
+ *   dense direct solve on the coarsest level.  Stopping test: ||r||_2 no
+ *   larger than tol * ||b||_2 (Sec. 5).
+ */
+#ifndef PAMG_H
+#define PAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PAMG_OK = 0,
+    PAMG_NOT_CONVERGED = 1,   /* warning: outputs valid, maxit reached */
+    PAMG_E_INVALID = -1,      /* bad argument or malformed CSR */
+    PAMG_E_NOT_SPD = -2,      /* non-positive Cholesky pivot or p.Ap <= 0 */
+    PAMG_E_NUMERIC = -3,      /* NaN/Inf met in the iteration */
+    PAMG_E_OOM = -4,          /* host or device allocation failed */
+    PAMG_E_DEVICE = -5,       /* HIP runtime error */
+    PAMG_E_STALLED = -6,      /* coarsening found no pair and the level is too large for the dense solve */
+    PAMG_E_BUSY = -7          /* server admission refused (budget / capacity) */
+} pamg_status;
+
+enum { PAMG_PREC_F64 = 0, PAMG_PREC_F32 = 1 };   /* storage/arithmetic of the V-cycle */
+enum { PAMG_KRYLOV_CG = 0, PAMG_KRYLOV_FCG = 1 };
+
+typedef struct pamg_hierarchy pamg_hierarchy;
+
+/* A in CSR, host memory, 0-based, full symmetric storage, columns strictly
+ * ascending in every row, a positive diagonal entry present in every row.
+ * (Sec. 4: the application hands the matrix over in CSR.) */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;   /* n+1 */
+    const int32_t *col_idx;   /* nnz */
+    const double *val;        /* nnz */
+} pamg_csr;
+
+typedef struct {
+    int32_t max_coarse;       /* coarsen while n_l > max_coarse (default 200, Sec. 3.1 coarsest size) */
+    int32_t max_levels;       /* default 50 */
+    int32_t max_dense;        /* largest coarsest level accepted for the dense solve (default 4096) */
+    int32_t match_all_edges;  /* 0: only edges with weight > 1 may be matched (default) */
+    int32_t build_f32;        /* 1: also keep an FP32 copy of the hierarchy (mixed-precision V-cycle) */
+    int32_t num_threads;      /* host threads for setup (0 = hardware concurrency) */
+    int32_t check_symmetry;   /* 1: reject A unless bitwise symmetric */
+    int32_t host_only;        /* 1: build the hierarchy on the host only (no device upload; info,
+                                 aggregates and level queries work, solves return PAMG_E_INVALID) */
+    int32_t reserved[8];
+} pamg_params;
+
+typedef struct {
+    double tol;               /* relative residual target (default 1e-6) */
+    int32_t maxit;            /* default 1000 */
+    int32_t use_x0;           /* 1: x_dev holds the initial guess on entry (warm start, Sec. 5) */
+    int32_t krylov;           /* PAMG_KRYLOV_CG or PAMG_KRYLOV_FCG (default FCG) */
+    int32_t precision;        /* PAMG_PREC_F64 or PAMG_PREC_F32 (needs build_f32) */
+    int32_t check_every;      /* iterations enqueued between host convergence checks (default 4) */
+    int32_t fixed_iters;      /* > 0: run exactly this many iterations, ignore tol */
+    int32_t use_graph;        /* 1: replay the check_every-iteration block as a HIP graph (default 1) */
+    int32_t true_residual;    /* 1: recompute ||b - A x|| at the end; with FP32 restart if above tol */
+    int32_t reserved[8];
+} pamg_solve_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t iterations;
+    int32_t restarts;
+    double relres;            /* recurrence residual / ||b|| */
+    double relres_true;       /* ||b - A x|| / ||b|| (if requested, else -1) */
+    double solve_ms;          /* wall time of the call (host clock, stream synchronised) */
+} pamg_solve_info;
+
+#define PAMG_MAX_LEVELS 64
+typedef struct {
+    int32_t levels;
+    int32_t n[PAMG_MAX_LEVELS];
+    int64_t nnz[PAMG_MAX_LEVELS];
+    int32_t pairs[PAMG_MAX_LEVELS];
+    double setup_ms;          /* host setup + upload */
+    double operator_complexity;
+    uint64_t device_bytes;
+    uint64_t vcycle_bytes_f64;   /* algorithmic HBM bytes of one FP64 V-cycle */
+    uint64_t vcycle_bytes_f32;   /* same for the FP32 V-cycle (0 if not built) */
+    uint64_t spmv_bytes;         /* algorithmic bytes of one level-0 FP64 SpMV */
+} pamg_hier_info;
+
+/* Fill defaults. */
+int pamg_params_default(pamg_params *p);
+int pamg_solve_opts_default(pamg_solve_opts *o);
+
+/* Build the hierarchy from A (copied; the caller may free A on return), then
+ * upload it to the current device.  Deterministic: aggregates and coarse
+ * matrices are bitwise reproducible (Sec. 3.1 construction, readings listed
+ * in the design notes).  Errors: INVALID (bad CSR), NOT_SPD (coarsest
+ * factorisation), STALLED, OOM, DEVICE. */
+int pamg_setup(const pamg_csr *A, const pamg_params *params, void *stream, pamg_hierarchy **out);
+
+int pamg_hierarchy_destroy(pamg_hierarchy *h);
+int pamg_hierarchy_info(const pamg_hierarchy *h, pamg_hier_info *out);
+
+/* Level-l aggregate index of every level-l unknown (canonical numbering:
+ * level-0 unknowns in the caller's order, coarse unknowns numbered by their
+ * smallest member).  agg_host has n_l entries; l < levels-1. */
+int pamg_hierarchy_aggregates(const pamg_hierarchy *h, int32_t level, int32_t *agg_host);
+
+/* Level-l Galerkin matrix in canonical numbering (host buffers of n_l+1 and
+ * nnz_l entries). */
+int pamg_hierarchy_level_csr(const pamg_hierarchy *h, int32_t level, int32_t *row_ptr,
+                             int32_t *col_idx, double *val);
+
+/* Solve A x = b.  b_dev, x_dev: n doubles in the caller's numbering.  On
+ * return x_dev holds the last iterate (also for NOT_CONVERGED). */
+int pamg_solve(pamg_hierarchy *h, const double *b_dev, double *x_dev, const pamg_solve_opts *opts,
+               void *stream, pamg_solve_info *info);
+
+/* Single operators of the V-cycle, for parity checks.  Vectors are FP64 in
+ * canonical level numbering.
+ *   PAMG_OP_SPMV     out = A_l in0
+ *   PAMG_OP_DOWN     out = P_l^T (in0 - A_l D_l^-1 in0)        (pre-smooth, residual, restriction; n_{l+1})
+ *   PAMG_OP_UP       out = in1 + D_l^-1 (in0 - A_l in1)         (post-smooth of in1 given r = in0)
+ *   PAMG_OP_PROLONG  out = D_l^-1 in0 + P_l in1                 (in1 has n_{l+1} entries)
+ *   PAMG_OP_COARSE   out = A_L^-1 in0                           (level = L)
+ *   PAMG_OP_VCYCLE   out = B in0                                (level 0)
+ */
+enum { PAMG_OP_SPMV = 0, PAMG_OP_DOWN = 1, PAMG_OP_UP = 2, PAMG_OP_PROLONG = 3, PAMG_OP_COARSE = 4,
+       PAMG_OP_VCYCLE = 5 };
+int pamg_debug_apply(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision, const double *in0_dev,
+                     const double *in1_dev, double *out_dev, void *stream);
+
+/* Time `reps` back-to-back V-cycles (level 0 input r_dev, canonical order) and
+ * `reps` level-0 SpMVs on `stream`, measured with HIP events; milliseconds per
+ * operation.  Used by the benchmark. */
+int pamg_time_kernels(pamg_hierarchy *h, int32_t precision, const double *r_dev, int32_t reps, void *stream,
+                      double *vcycle_ms, double *spmv_ms);
+
+/* Time `reps` back-to-back launches of one kernel of the solve on `stream`
+ * with HIP events (milliseconds per launch), on the data currently held in
+ * the hierarchy's buffers.  op: PAMG_OP_DOWN or PAMG_OP_UP (V-cycle kernels of
+ * level `level`), PAMG_OP_SPMV (level-`level` SpMV), PAMG_OP_KRYLOV (level-0
+ * FCG kernel: p = z + beta p, q = A p, p.q, p.r).  *bytes receives the
+ * algorithmic HBM bytes of one launch (matrix, owned vector entries and
+ * outputs counted once; gathered entries are not recounted). */
+enum { PAMG_OP_KRYLOV = 6 };
+int pamg_time_op(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision, int32_t reps, void *stream,
+                 double *ms_per_launch, uint64_t *bytes);
+
+/* Thread-local description of the last failure on this thread. */
+const char *pamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMG_H */

@@ -1,0 +1,227 @@
+"""Python binding of libpamg (include/pamg.h): argument marshalling only.
+
+Every step of setup and solve runs in the C++/HIP library; this module only
+converts arguments.  Device vectors are passed as torch tensors (their data
+pointers) or raw integers, and the stream defaults to torch's current stream.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpamg.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_NOT_SPD, E_NUMERIC, E_OOM, E_DEVICE, E_STALLED, E_BUSY = -1, -2, -3, -4, -5, -6, -7
+PREC_F64, PREC_F32 = 0, 1
+KRYLOV_CG, KRYLOV_FCG = 0, 1
+OP_SPMV, OP_DOWN, OP_UP, OP_PROLONG, OP_COARSE, OP_VCYCLE, OP_KRYLOV = 0, 1, 2, 3, 4, 5, 6
+MAX_LEVELS = 64
+
+
+class pamg_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.POINTER(C.c_int32)),
+                ("col_idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
+
+
+class pamg_params(C.Structure):
+    _fields_ = [("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("max_dense", C.c_int32),
+                ("match_all_edges", C.c_int32), ("build_f32", C.c_int32), ("num_threads", C.c_int32),
+                ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class pamg_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("use_x0", C.c_int32), ("krylov", C.c_int32),
+                ("precision", C.c_int32), ("check_every", C.c_int32), ("fixed_iters", C.c_int32),
+                ("use_graph", C.c_int32), ("true_residual", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class pamg_solve_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("relres", C.c_double), ("relres_true", C.c_double), ("solve_ms", C.c_double)]
+
+
+class pamg_hier_info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("n", C.c_int32 * MAX_LEVELS), ("nnz", C.c_int64 * MAX_LEVELS),
+                ("pairs", C.c_int32 * MAX_LEVELS), ("setup_ms", C.c_double), ("operator_complexity", C.c_double),
+                ("device_bytes", C.c_uint64), ("vcycle_bytes_f64", C.c_uint64), ("vcycle_bytes_f32", C.c_uint64),
+                ("spmv_bytes", C.c_uint64)]
+
+
+# every entry point declared in include/pamg.h: name -> (restype, argtypes)
+_VP = C.c_void_p
+SIGNATURES = {
+    "pamg_params_default": (C.c_int, [C.POINTER(pamg_params)]),
+    "pamg_solve_opts_default": (C.c_int, [C.POINTER(pamg_solve_opts)]),
+    "pamg_setup": (C.c_int, [C.POINTER(pamg_csr), C.POINTER(pamg_params), _VP, C.POINTER(_VP)]),
+    "pamg_hierarchy_destroy": (C.c_int, [_VP]),
+    "pamg_hierarchy_info": (C.c_int, [_VP, C.POINTER(pamg_hier_info)]),
+    "pamg_hierarchy_aggregates": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
+    "pamg_hierarchy_level_csr": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_double)]),
+    "pamg_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pamg_solve_opts), _VP, C.POINTER(pamg_solve_info)]),
+    "pamg_debug_apply": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP]),
+    "pamg_time_kernels": (C.c_int, [_VP, C.c_int32, _VP, C.c_int32, _VP, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
+    "pamg_time_op": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.POINTER(C.c_double),
+                               C.POINTER(C.c_uint64)]),
+    "pamg_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class PamgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pamg error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libpamg.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python paper_2210_16660_amd/build.py`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str, allow=(OK,)):
+    if rc not in allow:
+        raise PamgError(rc, f"{what}: {lib().pamg_last_error().decode()}")
+    return rc
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor (or an int)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def params(**kw) -> pamg_params:
+    p = pamg_params()
+    _check(lib().pamg_params_default(C.byref(p)), "pamg_params_default")
+    for k, v in kw.items():
+        setattr(p, k, int(v))
+    return p
+
+
+def solve_opts(**kw) -> pamg_solve_opts:
+    o = pamg_solve_opts()
+    _check(lib().pamg_solve_opts_default(C.byref(o)), "pamg_solve_opts_default")
+    for k, v in kw.items():
+        if k == "krylov" and isinstance(v, str):
+            v = {"cg": KRYLOV_CG, "pcg": KRYLOV_CG, "fcg": KRYLOV_FCG}[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"f64": PREC_F64, "fp64": PREC_F64, "f32": PREC_F32, "fp32": PREC_F32}[v]
+        setattr(o, k, v if k == "tol" else int(v))
+    return o
+
+
+class Hierarchy:
+    """An AMG hierarchy built by pamg_setup (owned by the library)."""
+
+    def __init__(self, A, stream=None, **kw):
+        rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.col, dtype=np.int32)
+        v = np.ascontiguousarray(A.val, dtype=np.float64)
+        csr = pamg_csr(int(A.n), int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                       ci.ctypes.data_as(C.POINTER(C.c_int32)), v.ctypes.data_as(C.POINTER(C.c_double)))
+        self.params = params(**kw)
+        h = C.c_void_p()
+        s = None if self.params.host_only else _stream(stream)
+        _check(lib().pamg_setup(C.byref(csr), C.byref(self.params), s, C.byref(h)), "pamg_setup")
+        self._h = h
+        self.n = int(A.n)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.pamg_hierarchy_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self) -> pamg_hier_info:
+        i = pamg_hier_info()
+        _check(lib().pamg_hierarchy_info(self._h, C.byref(i)), "pamg_hierarchy_info")
+        return i
+
+    @property
+    def levels(self) -> int:
+        return self.info().levels
+
+    def level_sizes(self):
+        i = self.info()
+        return [i.n[l] for l in range(i.levels)], [i.nnz[l] for l in range(i.levels)]
+
+    def aggregates(self, level: int) -> np.ndarray:
+        n = self.info().n[level]
+        a = np.empty(n, np.int32)
+        _check(lib().pamg_hierarchy_aggregates(self._h, level, a.ctypes.data_as(C.POINTER(C.c_int32))),
+               "pamg_hierarchy_aggregates")
+        return a
+
+    def level_csr(self, level: int):
+        i = self.info()
+        n, nnz = i.n[level], i.nnz[level]
+        rp = np.empty(n + 1, np.int32)
+        ci = np.empty(nnz, np.int32)
+        v = np.empty(nnz, np.float64)
+        _check(lib().pamg_hierarchy_level_csr(self._h, level, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              v.ctypes.data_as(C.POINTER(C.c_double))), "pamg_hierarchy_level_csr")
+        return rp, ci, v
+
+    def solve(self, b, x, stream=None, **kw) -> pamg_solve_info:
+        """Solve A x = b for device tensors b, x (float64, n).  x is the initial
+        guess when use_x0=1.  Returns the info struct; raises on errors."""
+        o = solve_opts(**kw)
+        info = pamg_solve_info()
+        _check(lib().pamg_solve(self._h, _ptr(b), _ptr(x), C.byref(o), _stream(stream), C.byref(info)),
+               "pamg_solve", allow=(OK, NOT_CONVERGED))
+        return info
+
+    def debug_apply(self, op: int, level: int, in0, out, in1=None, precision: int = PREC_F64, stream=None):
+        _check(lib().pamg_debug_apply(self._h, op, level, precision, _ptr(in0), _ptr(in1), _ptr(out),
+                                      _stream(stream)), "pamg_debug_apply")
+
+    def time_kernels(self, r, reps: int = 20, precision: int = PREC_F64, stream=None):
+        vms, sms = C.c_double(), C.c_double()
+        _check(lib().pamg_time_kernels(self._h, precision, _ptr(r), reps, _stream(stream), C.byref(vms),
+                                       C.byref(sms)), "pamg_time_kernels")
+        return vms.value, sms.value
+
+
+    def time_op(self, op: int, level: int = 0, reps: int = 20, precision: int = PREC_F64, stream=None):
+        """(ms per launch, algorithmic bytes per launch) of one solve kernel."""
+        ms, nb = C.c_double(), C.c_uint64()
+        _check(lib().pamg_time_op(self._h, op, level, precision, reps, _stream(stream), C.byref(ms), C.byref(nb)),
+               "pamg_time_op")
+        return ms.value, nb.value
+
+
+def setup(A, **kw) -> Hierarchy:
+    return Hierarchy(A, **kw)

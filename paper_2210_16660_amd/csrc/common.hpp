@@ -1,0 +1,105 @@
+// Internal declarations shared by the host setup and the device driver.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pamg.h"
+
+namespace pamg {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+// Host CSR in canonical numbering.
+struct HostCSR {
+    int32_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// One level of the canonical hierarchy built on the host.
+struct HostLevel {
+    HostCSR A;
+    std::vector<double> w;      // near-null vector
+    std::vector<double> dinv;   // 1 / sum_j |a_ij|
+    std::vector<int32_t> agg;   // aggregate of each unknown (levels < L)
+    std::vector<double> p;      // prolongator entry of each unknown (levels < L)
+    int32_t pairs = 0;
+};
+
+struct HostHierarchy {
+    std::vector<HostLevel> lev;         // 0..L
+    std::vector<double> coarse_inv;    // A_L^{-1}, n_L x n_L (symmetric, row-major)
+    std::vector<double> coarse_chol;   // lower factor of A_L, row-major
+};
+
+// Device-ready layout of one level in hierarchical (aggregate-contiguous) order.
+struct LayoutLevel {
+    std::vector<int32_t> perm;      // canonical -> hierarchical index
+    std::vector<int32_t> iperm;     // hierarchical -> canonical
+    std::vector<int32_t> rp, ci;    // permuted CSR, columns ascending
+    std::vector<double> v;
+    std::vector<double> dinv, p;    // permuted
+    std::vector<int32_t> aggptr;    // n_{l+1}+1: members of coarse row I are rows [aggptr[I], aggptr[I+1])
+    std::vector<int32_t> down_tiles;  // coarse-row boundaries of the restriction tiles (l < L)
+    std::vector<int32_t> up_tiles;    // row boundaries of the row tiles
+};
+
+constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
+constexpr int kItems = 8;            // matrix entries per thread per tile
+constexpr int kTileNnz = kBlock * kItems;
+constexpr int kTileRows = kBlock;    // at most one row (or aggregate) per thread in a tile
+
+// setup.cpp
+void validate_csr(const pamg_csr& A, bool check_symmetry);
+HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
+std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
+
+// parallel helpers
+int num_threads();
+void set_num_threads(int t);
+
+template <class F>
+void parallel_for(int64_t n, F&& f, int64_t grain = 4096) {
+    int nt = num_threads();
+    if (nt <= 1 || n < 2 * grain) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    int64_t chunks = (n + grain - 1) / grain;
+    if (chunks < nt) nt = (int)chunks;
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t) {
+        th.emplace_back([&, t]() {
+            int64_t b = n * t / nt, e = n * (t + 1) / nt;
+            for (int64_t i = b; i < e; ++i) f(i);
+        });
+    }
+    for (auto& x : th) x.join();
+}
+
+// Run f(t, begin, end) over nt contiguous ranges.
+template <class F>
+void parallel_ranges(int64_t n, F&& f) {
+    int nt = num_threads();
+    if (n < 8192) nt = 1;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        if (nt == 1) { f(0, b, e); return; }
+        th.emplace_back([&f, t, b, e]() { f(t, b, e); });
+    }
+    for (auto& x : th) x.join();
+}
+
+}  // namespace pamg

@@ -1,0 +1,867 @@
+// Device side of the library: hierarchy upload, V-cycle and Krylov launch
+// schedule, HIP-graph replay of iteration blocks, and the C-ABI entry points
+// that touch the GPU.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
+
+#include "kernels.hpp"
+
+#define HIP_CHECK(call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            throw ::pamg::Error(e_ == hipErrorOutOfMemory ? PAMG_E_OOM : PAMG_E_DEVICE,              \
+                                std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+namespace pamg {
+
+template <typename T>
+struct DevVals {
+    bool built = false;
+    std::vector<T*> v, dinv, p;   // per level (p for l < L)
+    std::vector<T*> r, zp;        // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
+    T* ainv = nullptr;            // dense A_L^{-1}
+    T* dbg_in = nullptr;          // scratch in this precision (max n)
+    T* dbg_in2 = nullptr;
+};
+
+struct DevLevelIdx {
+    int n = 0, nc = 0;
+    long long nnz = 0;
+    int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *down_tiles = nullptr, *up_tiles = nullptr;
+    int *perm = nullptr, *iperm = nullptr;
+    int n_down = 0, n_up = 0;
+};
+
+}  // namespace pamg
+
+struct pamg_hierarchy {
+    int device = 0;
+    int L = 0;
+    bool host_only = false;
+    std::vector<pamg::DevLevelIdx> idx;
+    pamg::DevVals<double> f64;
+    pamg::DevVals<float> f32;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *b = nullptr;
+    double *dbg0 = nullptr, *dbg1 = nullptr, *dbg2 = nullptr;
+    double *partial = nullptr, *partial_b = nullptr;
+    int* zero_flag = nullptr;
+    pamg::SolveState* st = nullptr;
+    pamg::SolveState* st_host = nullptr;   // pinned
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int graph_k[2][2] = {{0, 0}, {0, 0}};
+    std::vector<void*> allocs;
+    pamg::HostHierarchy host;
+    pamg_hier_info info{};
+    std::mutex mu;
+};
+
+namespace pamg {
+
+template <typename T>
+static T* dalloc(pamg_hierarchy* h, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
+    h->allocs.push_back(p);
+    h->info.device_bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+}
+
+template <typename T, typename S>
+static T* upload(pamg_hierarchy* h, const std::vector<S>& src, hipStream_t s) {
+    T* d = dalloc<T>(h, src.size());
+    if (src.empty()) return d;
+    if constexpr (std::is_same<T, S>::value) {
+        HIP_CHECK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    } else {
+        std::vector<T> tmp(src.begin(), src.end());
+        HIP_CHECK(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    return d;
+}
+
+static inline int vec_grid(long long n) {
+    long long g = (n + kBlock - 1) / kBlock;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return g < 1 ? 1 : (int)g;
+}
+
+template <typename T>
+static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<LayoutLevel>& lay, hipStream_t s) {
+    const int nl = (int)lay.size();
+    V.v.resize(nl); V.dinv.resize(nl); V.p.assign(nl, nullptr); V.r.assign(nl, nullptr); V.zp.assign(nl, nullptr);
+    size_t maxn = 0;
+    for (int l = 0; l < nl; ++l) {
+        V.v[l] = upload<T>(h, lay[l].v, s);
+        V.dinv[l] = upload<T>(h, lay[l].dinv, s);
+        if (l + 1 < nl) {
+            V.p[l] = upload<T>(h, lay[l].p, s);
+            V.zp[l] = dalloc<T>(h, lay[l].dinv.size());
+        }
+        if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size());
+        maxn = std::max(maxn, lay[l].dinv.size());
+    }
+    V.ainv = upload<T>(h, h->host.coarse_inv, s);
+    V.dbg_in = dalloc<T>(h, maxn);
+    V.dbg_in2 = dalloc<T>(h, maxn);
+    V.built = true;
+}
+
+static uint64_t vcycle_bytes(const pamg_hierarchy* h, int s) {
+    // sum over l < L of 2 M_l + (10 n_l + 2 n_{l+1}) s, plus the coarse solve
+    uint64_t B = 0;
+    for (int l = 0; l < h->L; ++l) {
+        const uint64_t n = h->idx[l].n, nc = h->idx[l + 1].n, nnz = h->idx[l].nnz;
+        const uint64_t M = nnz * (4 + s) + 4 * (n + 1);
+        B += 2 * M + (10 * n + 2 * nc) * s;
+    }
+    const uint64_t nL = h->idx[h->L].n;
+    B += (nL * nL + 2 * nL) * s;
+    return B;
+}
+
+void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bool build_f32, hipStream_t s) {
+    const int nl = (int)lay.size();
+    h->L = nl - 1;
+    h->idx.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+        DevLevelIdx& I = h->idx[l];
+        const LayoutLevel& Ly = lay[l];
+        I.n = (int)Ly.dinv.size();
+        I.nnz = (long long)Ly.ci.size();
+        I.nc = (l + 1 < nl) ? (int)lay[l + 1].dinv.size() : 0;
+        I.rp = upload<int>(h, Ly.rp, s);
+        I.ci = upload<int>(h, Ly.ci, s);
+        I.perm = upload<int>(h, Ly.perm, s);
+        I.iperm = upload<int>(h, Ly.iperm, s);
+        I.up_tiles = upload<int>(h, Ly.up_tiles, s);
+        I.n_up = (int)Ly.up_tiles.size() - 1;
+        if (l + 1 < nl) {
+            I.aggptr = upload<int>(h, Ly.aggptr, s);
+            I.down_tiles = upload<int>(h, Ly.down_tiles, s);
+            I.n_down = (int)Ly.down_tiles.size() - 1;
+        }
+    }
+    upload_values<double>(h, h->f64, lay, s);
+    if (build_f32) upload_values<float>(h, h->f32, lay, s);
+    const int n0 = h->idx[0].n;
+    int maxn = 0;
+    for (auto& I : h->idx) maxn = std::max(maxn, I.n);
+    h->x = dalloc<double>(h, n0);
+    h->r = dalloc<double>(h, n0);
+    h->z = dalloc<double>(h, n0);
+    h->p[0] = dalloc<double>(h, n0);
+    h->p[1] = dalloc<double>(h, n0);
+    h->q = dalloc<double>(h, n0);
+    h->b = dalloc<double>(h, n0);
+    h->dbg0 = dalloc<double>(h, maxn);
+    h->dbg1 = dalloc<double>(h, maxn);
+    h->dbg2 = dalloc<double>(h, maxn);
+    h->partial = dalloc<double>(h, 2 * kMaxGrid);
+    h->partial_b = dalloc<double>(h, 2 * kMaxGrid);
+    h->zero_flag = dalloc<int>(h, 1);
+    h->st = dalloc<SolveState>(h, 1);
+    HIP_CHECK(hipMemsetAsync(h->zero_flag, 0, sizeof(int), s));
+    HIP_CHECK(hipMemsetAsync(h->st, 0, sizeof(SolveState), s));
+    for (double* v : {h->x, h->r, h->z, h->p[0], h->p[1], h->q, h->b})
+        HIP_CHECK(hipMemsetAsync(v, 0, sizeof(double) * n0, s));
+    HIP_CHECK(hipHostMalloc((void**)&h->st_host, sizeof(SolveState), hipHostMallocDefault));
+    HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_CHECK(hipStreamSynchronize(s));
+    h->info.levels = nl;
+    double tot = 0;
+    for (int l = 0; l < nl && l < PAMG_MAX_LEVELS; ++l) {
+        h->info.n[l] = h->idx[l].n;
+        h->info.nnz[l] = h->idx[l].nnz;
+        h->info.pairs[l] = h->host.lev[l].pairs;
+        tot += (double)h->idx[l].nnz;
+    }
+    h->info.operator_complexity = tot / (double)h->idx[0].nnz;
+    h->info.vcycle_bytes_f64 = vcycle_bytes(h, 8);
+    h->info.vcycle_bytes_f32 = build_f32 ? vcycle_bytes(h, 4) : 0;
+    h->info.spmv_bytes = (uint64_t)h->idx[0].nnz * 12 + 4 * ((uint64_t)n0 + 1) + 2 * 8 * (uint64_t)n0;
+}
+
+void destroy_hierarchy(pamg_hierarchy* h) {
+    if (h->host_only) {
+        delete h;
+        return;
+    }
+    (void)hipDeviceSynchronize();
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            if (h->graph[a][b]) (void)hipGraphExecDestroy(h->graph[a][b]);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->st_host) (void)hipHostFree(h->st_host);
+    delete h;
+}
+
+// ---------------------------------------------------------------- schedule
+
+#define LAUNCH(kernel, grid, shmem, stream, ...)                           \
+    do {                                                                   \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), shmem, stream, __VA_ARGS__); \
+    } while (0)
+
+// z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
+// up-sweep also writes partial[g] of z . dv.  Returns the number of partials.
+template <typename T>
+static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
+                          const int* done, hipStream_t s) {
+    const int L = h->L;
+    for (int l = 0; l < L; ++l) {
+        const DevLevelIdx& I = h->idx[l];
+        const int g = tile_grid(I.n_down);
+        if (l == 0)
+            LAUNCH((k_down<T, double>), g, 0, s, I.rp, I.ci, V.v[0], r0, V.dinv[0], V.p[0], I.aggptr,
+                   I.down_tiles, I.n_down, V.r[1], done);
+        else
+            LAUNCH((k_down<T, T>), g, 0, s, I.rp, I.ci, V.v[l], (const T*)V.r[l], V.dinv[l], V.p[l], I.aggptr,
+                   I.down_tiles, I.n_down, V.r[l + 1], done);
+    }
+    const int nL = h->idx[L].n;
+    const size_t lds = (size_t)nL * sizeof(T);
+    if (L == 0) {
+        LAUNCH((k_coarse<T, double, double, true>), 1, lds, s, nL, (const T*)V.ainv, r0, (const int*)nullptr,
+               (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, z_out, dv, h->partial,
+               done);
+        return 1;
+    }
+    const DevLevelIdx& F = h->idx[L - 1];
+    if (L - 1 == 0)
+        LAUNCH((k_coarse<T, T, double, false>), 1, lds, s, nL, (const T*)V.ainv, (const T*)V.r[L],
+               (const int*)F.aggptr, r0, (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], V.zp[L - 1], z_out, dv,
+               h->partial, done);
+    else
+        LAUNCH((k_coarse<T, T, T, false>), 1, lds, s, nL, (const T*)V.ainv, (const T*)V.r[L], (const int*)F.aggptr,
+               (const T*)V.r[L - 1], (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], V.zp[L - 1], z_out, dv,
+               h->partial, done);
+    for (int l = L - 1; l >= 0; --l) {
+        const DevLevelIdx& I = h->idx[l];
+        const int g = tile_grid(I.n_up);
+        if (l == 0) {
+            LAUNCH((k_up<T, double, double, true>), g, 0, s, I.rp, I.ci, (const T*)V.v[0], (const T*)V.zp[0], r0,
+                   (const T*)V.dinv[0], I.up_tiles, I.n_up, (const int*)nullptr, (const double*)nullptr,
+                   (const T*)nullptr, (const T*)nullptr, (T*)nullptr, z_out, dv, h->partial, done);
+            return g;
+        }
+        const DevLevelIdx& Fi = h->idx[l - 1];
+        if (l - 1 == 0)
+            LAUNCH((k_up<T, T, double, false>), g, 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.zp[l],
+                   (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up, (const int*)Fi.aggptr, r0,
+                   (const T*)V.dinv[l - 1], (const T*)V.p[l - 1], V.zp[l - 1], (double*)nullptr,
+                   (const double*)nullptr, (double*)nullptr, done);
+        else
+            LAUNCH((k_up<T, T, T, false>), g, 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.zp[l],
+                   (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up, (const int*)Fi.aggptr,
+                   (const T*)V.r[l - 1], (const T*)V.dinv[l - 1], (const T*)V.p[l - 1], V.zp[l - 1],
+                   (double*)nullptr, (const double*)nullptr, (double*)nullptr, done);
+    }
+    return 0;  // unreachable
+}
+
+template <typename T>
+static void enqueue_iteration(pamg_hierarchy* h, DevVals<T>& V, int krylov, int parity, hipStream_t s) {
+    const int* done = &h->st->done;
+    const double* dv = (krylov == PAMG_KRYLOV_CG) ? h->r : h->q;
+    const int cnt = enqueue_vcycle<T>(h, V, h->r, h->z, dv, done, s);
+    LAUNCH(k_fin_beta, 1, 0, s, h->st, (const double*)h->partial, cnt);
+    const DevLevelIdx& I = h->idx[0];
+    const int g = tile_grid(I.n_up);
+    LAUNCH(k_krylov_pq, g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->z,
+           (const double*)h->p[parity], h->p[1 - parity], h->q, (const double*)h->r, I.up_tiles, I.n_up,
+           (const SolveState*)h->st, h->partial, done);
+    LAUNCH(k_fin_alpha, 1, 0, s, h->st, (const double*)h->partial, g);
+    const int gv = vec_grid(I.n);
+    LAUNCH(k_krylov_update, gv, 0, s, I.n, h->x, h->r, (const double*)h->p[1 - parity], (const double*)h->q,
+           (const SolveState*)h->st, h->partial, done);
+    LAUNCH(k_fin_norm, 1, 0, s, h->st, (const double*)h->partial, gv);
+}
+
+template <typename T>
+static void enqueue_block(pamg_hierarchy* h, DevVals<T>& V, int krylov, int k, hipStream_t s) {
+    for (int j = 0; j < k; ++j) enqueue_iteration<T>(h, V, krylov, j & 1, s);
+}
+
+template <typename T>
+static hipGraphExec_t get_graph(pamg_hierarchy* h, DevVals<T>& V, int prec, int krylov, int k) {
+    hipGraphExec_t& ex = h->graph[prec][krylov];
+    if (ex && h->graph_k[prec][krylov] == k) return ex;
+    if (ex) {
+        HIP_CHECK(hipGraphExecDestroy(ex));
+        ex = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_block<T>(h, V, krylov, k, h->cap_stream);
+    HIP_CHECK(hipStreamEndCapture(h->cap_stream, &g));
+    HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    HIP_CHECK(hipGraphDestroy(g));
+    h->graph_k[prec][krylov] = k;
+    return ex;
+}
+
+static void read_state(pamg_hierarchy* h, hipStream_t s) {
+    HIP_CHECK(hipMemcpyAsync(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+// ||b - A x|| / ||b|| for the hierarchical-order x, b; uses dbg0 as scratch.
+static double true_relres(pamg_hierarchy* h, hipStream_t s) {
+    const DevLevelIdx& I = h->idx[0];
+    const int g = tile_grid(I.n_up);
+    LAUNCH((k_spmv<double, double, double>), g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->x,
+           (const double*)h->b, h->dbg0, I.up_tiles, I.n_up, h->partial_b);
+    std::vector<double> part(g);
+    HIP_CHECK(hipMemcpyAsync(part.data(), h->partial_b, sizeof(double) * g, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    double rr = 0.0;
+    for (double v : part) rr += v;
+    return std::sqrt(rr) / h->st_host->bnorm;
+}
+
+template <typename T>
+static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double* b_user, double* x_user,
+                       const pamg_solve_opts& o, hipStream_t s, pamg_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const DevLevelIdx& I0 = h->idx[0];
+    const int n = I0.n;
+    const int gv = vec_grid(n);
+    const int krylov = o.krylov == PAMG_KRYLOV_CG ? PAMG_KRYLOV_CG : PAMG_KRYLOV_FCG;
+    SolveState init{};
+    init.tol = o.tol;
+    init.maxit = o.maxit;
+    init.fixed_iters = o.fixed_iters;
+    init.krylov = krylov;
+    // wait for any earlier use of the pinned staging buffer
+    HIP_CHECK(hipStreamSynchronize(s));
+    *h->st_host = init;
+    HIP_CHECK(hipMemcpyAsync(h->st, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
+    LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, b_user, h->b);
+    LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, (double*)nullptr, h->partial_b);
+    if (o.use_x0) {
+        LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, (const double*)x_user, h->x);
+        const int g = tile_grid(I0.n_up);
+        LAUNCH((k_spmv<double, double, double>), g, 0, s, I0.rp, I0.ci, (const double*)h->f64.v[0],
+               (const double*)h->x, (const double*)h->b, h->r, I0.up_tiles, I0.n_up, h->partial);
+        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial, g);
+    } else {
+        LAUNCH(k_fill, gv, 0, s, (long long)n, h->x, 0.0);
+        LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, h->r, h->partial);
+        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial, gv);
+    }
+    int k = o.check_every > 0 ? o.check_every : 4;
+    if (k & 1) ++k;
+    hipGraphExec_t ex = o.use_graph ? get_graph<T>(h, V, prec, krylov, k) : nullptr;
+    int restarts = 0;
+    double relres_true = -1.0;
+    read_state(h, s);
+    for (;;) {
+        while (!h->st_host->done) {
+            if (ex)
+                HIP_CHECK(hipGraphLaunch(ex, s));
+            else
+                enqueue_block<T>(h, V, krylov, k, s);
+            read_state(h, s);
+        }
+        if (h->st_host->done == 2) {   // zero right-hand side
+            LAUNCH(k_fill, gv, 0, s, (long long)n, h->x, 0.0);
+            break;
+        }
+        const bool want_true = o.true_residual || prec == PAMG_PREC_F32;
+        if (!want_true || h->st_host->status != PAMG_OK || o.fixed_iters > 0) break;
+        relres_true = true_relres(h, s);
+        if (relres_true <= o.tol || prec != PAMG_PREC_F32 || restarts >= 10 || h->st_host->iter >= o.maxit) break;
+        // FP32 preconditioner: restart the recurrence from the true residual
+        ++restarts;
+        const int g = tile_grid(I0.n_up);
+        LAUNCH((k_spmv<double, double, double>), g, 0, s, I0.rp, I0.ci, (const double*)h->f64.v[0],
+               (const double*)h->x, (const double*)h->b, h->r, I0.up_tiles, I0.n_up, h->partial);
+        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, 0, (const double*)h->partial, g);
+        read_state(h, s);
+        relres_true = -1.0;
+    }
+    LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.perm, (const double*)h->x, x_user);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->status = h->st_host->status;
+        info->iterations = h->st_host->iter;
+        info->restarts = restarts;
+        info->relres = h->st_host->bnorm > 0 ? h->st_host->rnorm / h->st_host->bnorm : 0.0;
+        info->relres_true = relres_true;
+        info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+}
+
+static void require_device(const pamg_hierarchy* h);
+
+int solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts& o, hipStream_t s,
+          pamg_solve_info* info) {
+    require_device(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    HIP_CHECK(hipSetDevice(h->device));
+    pamg_solve_info tmp{};
+    if (!info) info = &tmp;
+    if (o.precision == PAMG_PREC_F32) {
+        if (!h->f32.built) throw Error(PAMG_E_INVALID, "FP32 hierarchy not built (set params.build_f32)");
+        solve_impl<float>(h, h->f32, 1, b, x, o, s, info);
+    } else {
+        solve_impl<double>(h, h->f64, 0, b, x, o, s, info);
+    }
+    return info->status;
+}
+
+// ---------------------------------------------------------------- debug ops
+
+template <typename T>
+static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const double* in0, const double* in1,
+                       double* out, hipStream_t s) {
+    const int* nodone = h->zero_flag;
+    const DevLevelIdx& I = h->idx[l];
+    const int gv = vec_grid(I.n);
+    switch (op) {
+        case PAMG_OP_SPMV: {
+            LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in0, V.dbg_in);
+            LAUNCH((k_spmv<T, T, double>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
+                   (const double*)nullptr, h->dbg1, I.up_tiles, I.n_up, (double*)nullptr);
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
+            break;
+        }
+        case PAMG_OP_DOWN: {
+            if (l >= h->L) throw Error(PAMG_E_INVALID, "DOWN needs level < L");
+            const DevLevelIdx& C = h->idx[l + 1];
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+            LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in0, V.dbg_in);
+            if (l == 0)
+                LAUNCH((k_down<T, double>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[0],
+                       (const double*)h->dbg0, (const T*)V.dinv[0], (const T*)V.p[0], (const int*)I.aggptr,
+                       (const int*)I.down_tiles, I.n_down, V.dbg_in2, nodone);
+            else
+                LAUNCH((k_down<T, T>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
+                       (const T*)V.dinv[l], (const T*)V.p[l], (const int*)I.aggptr, (const int*)I.down_tiles,
+                       I.n_down, V.dbg_in2, nodone);
+            LAUNCH((k_gather<T, double>), vec_grid(C.n), 0, s, C.n, (const int*)C.perm, (const T*)V.dbg_in2, out);
+            break;
+        }
+        case PAMG_OP_UP: {
+            // out = in1 + D^-1 (in0 - A in1): the post-smoothing step
+            if (l >= h->L) throw Error(PAMG_E_INVALID, "UP needs level < L");
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+            LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in1, V.dbg_in);
+            LAUNCH((k_up<T, double, double, true>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
+                   (const T*)V.dbg_in, (const double*)h->dbg0, (const T*)V.dinv[l], I.up_tiles, I.n_up,
+                   (const int*)nullptr, (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                   h->dbg1, (const double*)h->dbg0, h->partial, nodone);
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
+            break;
+        }
+        case PAMG_OP_PROLONG: {
+            // out = D^-1 in0 + P in1, via the coarse-row kernel of level l+1's
+            // up-sweep: run k_coarse-style prolongation through k_prolong
+            if (l >= h->L) throw Error(PAMG_E_INVALID, "PROLONG needs level < L");
+            const DevLevelIdx& C = h->idx[l + 1];
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+            LAUNCH((k_gather<double, T>), vec_grid(C.n), 0, s, C.n, (const int*)C.iperm, in1, V.dbg_in);
+            LAUNCH((k_prolong<T>), vec_grid(C.n), 0, s, C.n, (const T*)V.dbg_in, (const int*)I.aggptr,
+                   (const double*)h->dbg0, (const T*)V.dinv[l], (const T*)V.p[l], V.dbg_in2);
+            LAUNCH((k_gather<T, double>), gv, 0, s, I.n, (const int*)I.perm, (const T*)V.dbg_in2, out);
+            break;
+        }
+        case PAMG_OP_COARSE: {
+            if (l != h->L) throw Error(PAMG_E_INVALID, "COARSE needs level == L");
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+            LAUNCH((k_coarse<T, double, double, true>), 1, (size_t)I.n * sizeof(T), s, I.n, (const T*)V.ainv,
+                   (const double*)h->dbg0, (const int*)nullptr, (const double*)nullptr, (const T*)nullptr,
+                   (const T*)nullptr, (T*)nullptr, h->dbg1, (const double*)h->dbg0, h->partial, nodone);
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
+            break;
+        }
+        case PAMG_OP_VCYCLE: {
+            if (l != 0) throw Error(PAMG_E_INVALID, "VCYCLE is applied at level 0");
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+            enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, nodone, s);
+            LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
+            break;
+        }
+        default:
+            throw Error(PAMG_E_INVALID, "unknown operator");
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+int debug_apply(pamg_hierarchy* h, int op, int level, int prec, const double* in0, const double* in1, double* out,
+                hipStream_t s) {
+    require_device(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    HIP_CHECK(hipSetDevice(h->device));
+    if (level < 0 || level > h->L) throw Error(PAMG_E_INVALID, "level out of range");
+    if (prec == PAMG_PREC_F32) {
+        if (!h->f32.built) throw Error(PAMG_E_INVALID, "FP32 hierarchy not built");
+        debug_impl<float>(h, h->f32, op, level, in0, in1, out, s);
+    } else {
+        debug_impl<double>(h, h->f64, op, level, in0, in1, out, s);
+    }
+    return PAMG_OK;
+}
+
+template <typename T>
+static void time_impl(pamg_hierarchy* h, DevVals<T>& V, const double* r, int reps, hipStream_t s, double* vms,
+                      double* sms) {
+    const DevLevelIdx& I = h->idx[0];
+    const int gv = vec_grid(I.n);
+    LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, r, h->dbg0);
+    hipEvent_t e0, e1, e2;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventCreate(&e2));
+    for (int w = 0; w < 2; ++w) enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, h->zero_flag, s);
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, h->zero_flag, s);
+    HIP_CHECK(hipEventRecord(e1, s));
+    const int g = tile_grid(I.n_up);
+    for (int i = 0; i < reps; ++i)
+        LAUNCH((k_spmv<double, double, double>), g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0],
+               (const double*)h->dbg1, (const double*)nullptr, h->dbg2, I.up_tiles, I.n_up, (double*)nullptr);
+    HIP_CHECK(hipEventRecord(e2, s));
+    HIP_CHECK(hipEventSynchronize(e2));
+    float a = 0, b = 0;
+    HIP_CHECK(hipEventElapsedTime(&a, e0, e1));
+    HIP_CHECK(hipEventElapsedTime(&b, e1, e2));
+    *vms = a / reps;
+    *sms = b / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+}
+
+int time_kernels(pamg_hierarchy* h, int prec, const double* r, int reps, hipStream_t s, double* vms, double* sms) {
+    require_device(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    HIP_CHECK(hipSetDevice(h->device));
+    if (reps < 1) throw Error(PAMG_E_INVALID, "reps must be >= 1");
+    if (prec == PAMG_PREC_F32) {
+        if (!h->f32.built) throw Error(PAMG_E_INVALID, "FP32 hierarchy not built");
+        time_impl<float>(h, h->f32, r, reps, s, vms, sms);
+    } else {
+        time_impl<double>(h, h->f64, r, reps, s, vms, sms);
+    }
+    return PAMG_OK;
+}
+
+static void require_device(const pamg_hierarchy* h);
+
+template <typename T>
+static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int reps, hipStream_t s, double* ms,
+                         uint64_t* bytes) {
+    const DevLevelIdx& I = h->idx[l];
+    const int* nodone = h->zero_flag;
+    const uint64_t n = I.n, nnz = I.nnz, sz = sizeof(T);
+    const uint64_t M = nnz * (4 + sz) + 4 * (n + 1);
+    std::function<void()> launch;
+    if (op == PAMG_OP_DOWN) {
+        if (l >= h->L) throw Error(PAMG_E_INVALID, "DOWN needs level < L");
+        const uint64_t nc = h->idx[l + 1].n;
+        // matrix, own r/dinv/p (r in FP64 at level 0), aggptr, coarse output
+        *bytes = M + n * (l == 0 ? 8 : sz) + 2 * n * sz + 4 * (nc + 1) + nc * sz;
+        if (l == 0)
+            launch = [=]() {
+                LAUNCH((k_down<T, double>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[0],
+                       (const double*)h->r, (const T*)V.dinv[0], (const T*)V.p[0], (const int*)I.aggptr,
+                       (const int*)I.down_tiles, I.n_down, V.r[1], nodone);
+            };
+        else
+            launch = [=]() {
+                LAUNCH((k_down<T, T>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.r[l],
+                       (const T*)V.dinv[l], (const T*)V.p[l], (const int*)I.aggptr, (const int*)I.down_tiles,
+                       I.n_down, V.r[l + 1], nodone);
+            };
+    } else if (op == PAMG_OP_UP) {
+        if (l >= h->L) throw Error(PAMG_E_INVALID, "UP needs level < L");
+        if (l == 0) {
+            // matrix, own zp/dinv (T), r and dv (FP64), z out (FP64)
+            *bytes = M + 2 * n * sz + 3 * n * 8;
+            launch = [=]() {
+                LAUNCH((k_up<T, double, double, true>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[0],
+                       (const T*)V.zp[0], (const double*)h->r, (const T*)V.dinv[0], I.up_tiles, I.n_up,
+                       (const int*)nullptr, (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       h->z, (const double*)h->q, h->partial, nodone);
+            };
+        } else {
+            const DevLevelIdx& F = h->idx[l - 1];
+            const uint64_t nf = F.n;
+            // matrix, own zp/r/dinv, fine aggptr, fine r/dinv/p reads and zp write
+            *bytes = M + 3 * n * sz + 4 * (n + 1) + nf * ((l - 1 == 0 ? 8 : sz) + 3 * sz);
+            if (l - 1 == 0)
+                launch = [=]() {
+                    LAUNCH((k_up<T, T, double, false>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
+                           (const T*)V.zp[l], (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up,
+                           (const int*)F.aggptr, (const double*)h->r, (const T*)V.dinv[0], (const T*)V.p[0], V.zp[0],
+                           (double*)nullptr, (const double*)nullptr, (double*)nullptr, nodone);
+                };
+            else
+                launch = [=]() {
+                    LAUNCH((k_up<T, T, T, false>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
+                           (const T*)V.zp[l], (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up,
+                           (const int*)F.aggptr, (const T*)V.r[l - 1], (const T*)V.dinv[l - 1], (const T*)V.p[l - 1],
+                           V.zp[l - 1], (double*)nullptr, (const double*)nullptr, (double*)nullptr, nodone);
+                };
+        }
+    } else if (op == PAMG_OP_SPMV) {
+        *bytes = M + n * sz + n * 8;
+        launch = [=]() {
+            LAUNCH((k_spmv<T, T, double>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
+                   (const double*)nullptr, h->dbg1, I.up_tiles, I.n_up, (double*)nullptr);
+        };
+    } else if (op == PAMG_OP_KRYLOV) {
+        if (l != 0) throw Error(PAMG_E_INVALID, "KRYLOV runs on level 0");
+        const uint64_t M8 = nnz * 12 + 4 * (n + 1);
+        // matrix (FP64), z, p_old, r reads; p_new, q writes
+        *bytes = M8 + 5 * n * 8;
+        launch = [=]() {
+            LAUNCH(k_krylov_pq, tile_grid(I.n_up), 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->z,
+                   (const double*)h->p[0], h->p[1], h->q, (const double*)h->r, I.up_tiles, I.n_up,
+                   (const SolveState*)h->st, h->partial, nodone);
+        };
+    } else {
+        throw Error(PAMG_E_INVALID, "op must be DOWN, UP, SPMV or KRYLOV");
+    }
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    for (int w = 0; w < 3; ++w) launch();
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    HIP_CHECK(hipGetLastError());
+    float a = 0;
+    HIP_CHECK(hipEventElapsedTime(&a, e0, e1));
+    *ms = a / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+int time_op(pamg_hierarchy* h, int op, int level, int prec, int reps, hipStream_t s, double* ms, uint64_t* bytes) {
+    require_device(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    HIP_CHECK(hipSetDevice(h->device));
+    if (reps < 1) throw Error(PAMG_E_INVALID, "reps must be >= 1");
+    if (level < 0 || level > h->L) throw Error(PAMG_E_INVALID, "level out of range");
+    if (prec == PAMG_PREC_F32) {
+        if (!h->f32.built) throw Error(PAMG_E_INVALID, "FP32 hierarchy not built");
+        if (op == PAMG_OP_KRYLOV) throw Error(PAMG_E_INVALID, "KRYLOV is FP64 only");
+        time_op_impl<float>(h, h->f32, op, level, reps, s, ms, bytes);
+    } else {
+        time_op_impl<double>(h, h->f64, op, level, reps, s, ms, bytes);
+    }
+    return PAMG_OK;
+}
+
+pamg_hierarchy* new_hierarchy(bool host_only) {
+    pamg_hierarchy* h = new pamg_hierarchy();
+    h->host_only = host_only;
+    if (!host_only) {
+        try {
+            HIP_CHECK(hipGetDevice(&h->device));
+        } catch (...) {
+            delete h;
+            throw;
+        }
+    }
+    return h;
+}
+
+static void require_device(const pamg_hierarchy* h) {
+    if (h->host_only) throw Error(PAMG_E_INVALID, "hierarchy was built with host_only=1");
+}
+
+}  // namespace pamg
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const pamg::Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return PAMG_E_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return PAMG_E_DEVICE;
+    }
+}
+}  // namespace
+
+namespace pamg {
+void set_last_error(const std::string& m) { g_last_error = m; }
+}
+
+extern "C" {
+
+const char* pamg_last_error(void) { return g_last_error.c_str(); }
+
+int pamg_params_default(pamg_params* p) {
+    if (!p) return PAMG_E_INVALID;
+    std::memset(p, 0, sizeof(*p));
+    p->max_coarse = 200;
+    p->max_levels = 50;
+    p->max_dense = 4096;
+    p->match_all_edges = 0;
+    p->build_f32 = 0;
+    p->num_threads = 0;
+    p->check_symmetry = 0;
+    return PAMG_OK;
+}
+
+int pamg_solve_opts_default(pamg_solve_opts* o) {
+    if (!o) return PAMG_E_INVALID;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6;
+    o->maxit = 1000;
+    o->krylov = PAMG_KRYLOV_FCG;
+    o->precision = PAMG_PREC_F64;
+    o->check_every = 4;
+    o->use_graph = 1;
+    return PAMG_OK;
+}
+
+int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out) {
+    return guarded([&]() -> int {
+        if (!A || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        *out = nullptr;
+        pamg_params prm;
+        if (params) prm = *params; else pamg_params_default(&prm);
+        if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
+            prm.max_dense > 4096)
+            throw pamg::Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, 1 <= max_dense <= 4096)");
+        pamg::set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
+        auto t0 = std::chrono::steady_clock::now();
+        pamg::validate_csr(*A, prm.check_symmetry != 0);
+        pamg::HostHierarchy H = pamg::build_hierarchy(*A, prm);
+        std::vector<pamg::LayoutLevel> lay = pamg::build_layout(H);
+        pamg_hierarchy* h = pamg::new_hierarchy(prm.host_only != 0);
+        try {
+            h->host = std::move(H);
+            if (prm.host_only) {
+                const int nl = (int)h->host.lev.size();
+                h->L = nl - 1;
+                h->info.levels = nl;
+                double tot = 0;
+                for (int l = 0; l < nl; ++l) {
+                    h->info.n[l] = h->host.lev[l].A.n;
+                    h->info.nnz[l] = h->host.lev[l].A.nnz();
+                    h->info.pairs[l] = h->host.lev[l].pairs;
+                    tot += (double)h->info.nnz[l];
+                }
+                h->info.operator_complexity = tot / (double)h->info.nnz[0];
+            } else {
+                pamg::upload_hierarchy(h, lay, prm.build_f32 != 0, (hipStream_t)stream);
+            }
+        } catch (...) {
+            pamg::destroy_hierarchy(h);
+            throw;
+        }
+        auto t1 = std::chrono::steady_clock::now();
+        h->info.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        *out = h;
+        return PAMG_OK;
+    });
+}
+
+int pamg_hierarchy_destroy(pamg_hierarchy* h) {
+    return guarded([&]() -> int {
+        if (h) pamg::destroy_hierarchy(h);
+        return PAMG_OK;
+    });
+}
+
+int pamg_hierarchy_info(const pamg_hierarchy* h, pamg_hier_info* out) {
+    if (!h || !out) { g_last_error = "null argument"; return PAMG_E_INVALID; }
+    *out = h->info;
+    return PAMG_OK;
+}
+
+int pamg_hierarchy_aggregates(const pamg_hierarchy* h, int32_t level, int32_t* agg) {
+    return guarded([&]() -> int {
+        if (!h || !agg) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        if (level < 0 || level >= h->L) throw pamg::Error(PAMG_E_INVALID, "level must be in [0, levels-2]");
+        const auto& a = h->host.lev[level].agg;
+        std::memcpy(agg, a.data(), a.size() * sizeof(int32_t));
+        return PAMG_OK;
+    });
+}
+
+int pamg_hierarchy_level_csr(const pamg_hierarchy* h, int32_t level, int32_t* rp, int32_t* ci, double* v) {
+    return guarded([&]() -> int {
+        if (!h || !rp || !ci || !v) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        if (level < 0 || level > h->L) throw pamg::Error(PAMG_E_INVALID, "level out of range");
+        const auto& A = h->host.lev[level].A;
+        std::memcpy(rp, A.rp.data(), A.rp.size() * sizeof(int32_t));
+        std::memcpy(ci, A.ci.data(), A.ci.size() * sizeof(int32_t));
+        std::memcpy(v, A.v.data(), A.v.size() * sizeof(double));
+        return PAMG_OK;
+    });
+}
+
+int pamg_solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts* opts, void* stream,
+               pamg_solve_info* info) {
+    return guarded([&]() -> int {
+        if (!h || !b || !x) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        pamg_solve_opts o;
+        if (opts) o = *opts; else pamg_solve_opts_default(&o);
+        if (!(o.tol >= 0.0) || o.maxit < 1 || o.fixed_iters < 0)
+            throw pamg::Error(PAMG_E_INVALID, "bad solve options (need tol >= 0, maxit >= 1)");
+        return pamg::solve(h, b, x, o, (hipStream_t)stream, info);
+    });
+}
+
+int pamg_debug_apply(pamg_hierarchy* h, int32_t op, int32_t level, int32_t precision, const double* in0,
+                     const double* in1, double* out, void* stream) {
+    return guarded([&]() -> int {
+        if (!h || !in0 || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        if ((op == PAMG_OP_UP || op == PAMG_OP_PROLONG) && !in1) throw pamg::Error(PAMG_E_INVALID, "in1 required");
+        return pamg::debug_apply(h, op, level, precision, in0, in1, out, (hipStream_t)stream);
+    });
+}
+
+int pamg_time_kernels(pamg_hierarchy* h, int32_t precision, const double* r, int32_t reps, void* stream,
+                      double* vms, double* sms) {
+    return guarded([&]() -> int {
+        if (!h || !r || !vms || !sms) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        return pamg::time_kernels(h, precision, r, reps, (hipStream_t)stream, vms, sms);
+    });
+}
+
+int pamg_time_op(pamg_hierarchy* h, int32_t op, int32_t level, int32_t precision, int32_t reps, void* stream,
+                 double* ms, uint64_t* bytes) {
+    return guarded([&]() -> int {
+        if (!h || !ms || !bytes) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        return pamg::time_op(h, op, level, precision, reps, (hipStream_t)stream, ms, bytes);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,495 @@
+// Host construction of the AMG hierarchy (arXiv 2210.16660, Sec. 3.1).
+//
+// Compiled with -ffp-contract=off: every floating-point expression below is
+// evaluated one IEEE binary64 operation at a time, in the written order, so
+// that weights, prolongator entries and Galerkin sums are bitwise
+// reproducible.  The definitions followed (canonical numbering):
+//   * l1 diagonal d_i = sum_j |a_ij| (ascending columns); dinv = 1/d.
+//   * edge weight of eq. (weights) for a stored upper entry (lo, hi):
+//       num = ((2 a_lohi) w_lo) w_hi, den = (a_lolo w_lo) w_lo + (a_hihi w_hi) w_hi,
+//       c = 1 - num/den;  an edge may be matched iff c > 1.
+//   * matching: the greedy matching under the strict order (c desc, lo asc,
+//     hi asc), which is what eq. (approximatematch) approximates within 1/2.
+//     Computed here with the parallel Suitor algorithm (Manne & Halappanavar,
+//     IPDPS 2014), which yields exactly the greedy matching for a strict
+//     total order on the edges.
+//   * aggregates: matched pairs and singletons, numbered by smallest member.
+//   * tentative prolongator of eq. (prolongator): pair: nu = sqrt(w_lo^2 + w_hi^2),
+//     p = w/nu, w_c = nu; singleton: p = w/|w|, w_c = |w|.
+//   * Galerkin A_{l+1} = P^T A P: entry (I, J) is the sum of a_ij (p_i p_j)
+//     over stored (i, j) with agg(i) = I, agg(j) = J, added left to right in
+//     ascending (min(i,j), max(i,j), i); structural zeros are kept.
+//   * coarsen while n_l > max_coarse; a level without pairs is the coarsest.
+//   * coarsest: dense Cholesky A_L = L L^T and the explicit inverse
+//     A_L^{-1} = L^{-T} L^{-1} used by the device coarse solve.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.hpp"
+
+namespace pamg {
+
+static thread_local int g_threads = 0;
+
+int num_threads() {
+    if (g_threads > 0) return g_threads;
+    unsigned h = std::thread::hardware_concurrency();
+    return h == 0 ? 1 : (int)std::min(h, 64u);
+}
+void set_num_threads(int t) { g_threads = t; }
+
+void validate_csr(const pamg_csr& A, bool check_symmetry) {
+    if (A.n <= 0) throw Error(PAMG_E_INVALID, "n must be positive");
+    if (!A.row_ptr || !A.col_idx || !A.val) throw Error(PAMG_E_INVALID, "null CSR pointer");
+    if (A.nnz < A.n || A.nnz >= (int64_t(1) << 31)) throw Error(PAMG_E_INVALID, "nnz out of range (need n <= nnz < 2^31)");
+    if (A.row_ptr[0] != 0 || A.row_ptr[A.n] != A.nnz) throw Error(PAMG_E_INVALID, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
+    std::atomic<int> bad{0};
+    std::atomic<int32_t> bad_row{-1};
+    parallel_for(A.n, [&](int64_t i) {
+        int32_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+        int err = 0;
+        if (e < b) err = 1;
+        bool diag = false;
+        for (int32_t k = b; k < e && !err; ++k) {
+            int32_t c = A.col_idx[k];
+            if (c < 0 || c >= A.n) err = 2;
+            else if (k > b && c <= A.col_idx[k - 1]) err = 3;
+            else if (c == i) {
+                diag = true;
+                if (!(A.val[k] > 0.0)) err = 4;
+            }
+            if (!std::isfinite(A.val[k])) err = 6;
+        }
+        if (!err && !diag) err = 5;
+        if (err) { bad.store(err); bad_row.store((int32_t)i); }
+    });
+    static const char* msg[] = {"", "row_ptr not monotone", "column index out of range",
+                                "columns not strictly ascending", "non-positive diagonal",
+                                "missing diagonal entry", "non-finite value"};
+    if (bad.load()) throw Error(PAMG_E_INVALID, std::string(msg[bad.load()]) + " in row " + std::to_string(bad_row.load()));
+    if (check_symmetry) {
+        std::atomic<int> asym{0};
+        parallel_for(A.n, [&](int64_t i) {
+            for (int32_t k = A.row_ptr[i]; k < A.row_ptr[i + 1]; ++k) {
+                int32_t j = A.col_idx[k];
+                const int32_t* b = A.col_idx + A.row_ptr[j];
+                const int32_t* e = A.col_idx + A.row_ptr[j + 1];
+                const int32_t* f = std::lower_bound(b, e, (int32_t)i);
+                if (f == e || *f != i || std::memcmp(&A.val[f - A.col_idx], &A.val[k], 8) != 0) asym.store(1);
+            }
+        });
+        if (asym.load()) throw Error(PAMG_E_INVALID, "matrix is not bitwise symmetric");
+    }
+}
+
+// ---------------------------------------------------------------- weights
+
+static inline double edge_weight(double a_lohi, double a_lolo, double a_hihi, double w_lo, double w_hi) {
+    double num = ((2.0 * a_lohi) * w_lo) * w_hi;
+    double den = (a_lolo * w_lo) * w_lo + (a_hihi * w_hi) * w_hi;
+    return 1.0 - num / den;
+}
+
+// strict total order on edges: true if (c1, lo1, hi1) is heavier than (c2, lo2, hi2)
+static inline bool heavier(double c1, int32_t lo1, int32_t hi1, double c2, int32_t lo2, int32_t hi2) {
+    if (c1 != c2) return c1 > c2;
+    if (lo1 != lo2) return lo1 < lo2;
+    return hi1 < hi2;
+}
+
+struct Adj {
+    std::vector<int64_t> ptr;    // n+1
+    std::vector<int32_t> nbr;
+    std::vector<double> c;
+};
+
+// Eligible edges of the graph of A with their weights, both directions,
+// each vertex's list sorted heaviest first.
+static Adj eligible_adjacency(const HostCSR& A, const std::vector<double>& diag, const std::vector<double>& w,
+                              bool match_all) {
+    const int32_t n = A.n;
+    Adj g;
+    std::vector<int32_t> deg(n, 0);
+    // upper entries: eligible flag per stored entry
+    std::vector<double> cval(A.nnz());
+    std::vector<uint8_t> elig(A.nnz(), 0);
+    parallel_for(n, [&](int64_t i) {
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            int32_t j = A.ci[k];
+            if (j <= i) continue;
+            double c = edge_weight(A.v[k], diag[i], diag[j], w[i], w[j]);
+            cval[k] = c;
+            elig[k] = (match_all || c > 1.0) ? 1 : 0;
+        }
+    });
+    // degree count (both endpoints); sequential over rows to keep it simple and exact
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (elig[k]) { ++deg[i]; ++deg[A.ci[k]]; }
+    g.ptr.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) g.ptr[i + 1] = g.ptr[i] + deg[i];
+    g.nbr.resize(g.ptr[n]);
+    g.c.resize(g.ptr[n]);
+    std::vector<int64_t> pos(g.ptr.begin(), g.ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (elig[k]) {
+                int32_t j = A.ci[k];
+                g.nbr[pos[i]] = j; g.c[pos[i]++] = cval[k];
+                g.nbr[pos[j]] = i; g.c[pos[j]++] = cval[k];
+            }
+    parallel_for(n, [&](int64_t i) {
+        int64_t b = g.ptr[i], e = g.ptr[i + 1];
+        if (e - b < 2) return;
+        std::vector<std::pair<double, int32_t>> t;
+        t.reserve(e - b);
+        for (int64_t k = b; k < e; ++k) t.emplace_back(g.c[k], g.nbr[k]);
+        int32_t u = (int32_t)i;
+        std::sort(t.begin(), t.end(), [u](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+            return heavier(x.first, std::min(u, x.second), std::max(u, x.second),
+                           y.first, std::min(u, y.second), std::max(u, y.second));
+        });
+        for (int64_t k = b; k < e; ++k) { g.c[k] = t[k - b].first; g.nbr[k] = t[k - b].second; }
+    }, 1024);
+    return g;
+}
+
+// Parallel Suitor matching.  mate[i] = partner or -1; returns number of pairs.
+static int64_t suitor_matching(const Adj& g, int32_t n, std::vector<int32_t>& mate) {
+    std::vector<int32_t> suitor(n, -1);
+    std::vector<double> ws(n, 0.0);                 // weight of the suitor's edge (valid if suitor >= 0)
+    std::unique_ptr<std::atomic<uint8_t>[]> lock(new std::atomic<uint8_t>[n]);
+    for (int32_t i = 0; i < n; ++i) lock[i].store(0, std::memory_order_relaxed);
+    std::vector<int64_t> next(g.ptr.begin(), g.ptr.end() - 1);   // scan position per vertex
+
+    auto propose = [&](int32_t u0) {
+        int32_t cur = u0;
+        while (cur >= 0) {
+            int32_t displaced = -1;
+            bool placed = false;
+            for (int64_t k = next[cur]; k < g.ptr[cur + 1]; ++k) {
+                int32_t v = g.nbr[k];
+                double c = g.c[k];
+                int32_t lo = std::min(cur, v), hi = std::max(cur, v);
+                while (lock[v].exchange(1, std::memory_order_acquire)) { }
+                int32_t s = suitor[v];
+                bool beats = (s < 0) || heavier(c, lo, hi, ws[v], std::min(s, v), std::max(s, v));
+                if (beats) {
+                    displaced = s;
+                    suitor[v] = cur;
+                    ws[v] = c;
+                    // publish the scan position before cur can be displaced by another thread
+                    next[cur] = k + 1;
+                }
+                lock[v].store(0, std::memory_order_release);
+                if (beats) { placed = true; break; }
+            }
+            if (!placed) next[cur] = g.ptr[cur + 1];
+            cur = placed ? displaced : -1;
+        }
+    };
+    parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+        for (int64_t u = b; u < e; ++u) propose((int32_t)u);
+    });
+    int64_t pairs = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t s = suitor[i];
+        mate[i] = (s >= 0 && suitor[s] == i) ? s : -1;
+        if (mate[i] > i) ++pairs;
+    }
+    return pairs;
+}
+
+// ---------------------------------------------------------------- Galerkin
+
+struct Term {
+    int32_t J, k1, k2, k3;
+    double t;
+};
+
+static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,
+                     const std::vector<int32_t>& mem_ptr, const std::vector<int32_t>& mem, HostCSR& Ac) {
+    const int32_t nc = (int32_t)mem_ptr.size() - 1;
+    auto row_terms = [&](int32_t I, std::vector<Term>& t) {
+        t.clear();
+        for (int32_t q = mem_ptr[I]; q < mem_ptr[I + 1]; ++q) {
+            int32_t i = mem[q];
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                int32_t j = A.ci[k];
+                Term x;
+                x.J = agg[j];
+                x.k1 = std::min(i, j);
+                x.k2 = std::max(i, j);
+                x.k3 = i;
+                x.t = A.v[k] * (p[i] * p[j]);
+                t.push_back(x);
+            }
+        }
+        std::sort(t.begin(), t.end(), [](const Term& a, const Term& b) {
+            if (a.J != b.J) return a.J < b.J;
+            if (a.k1 != b.k1) return a.k1 < b.k1;
+            if (a.k2 != b.k2) return a.k2 < b.k2;
+            return a.k3 < b.k3;
+        });
+    };
+    std::vector<int32_t> cnt(nc, 0);
+    parallel_ranges(nc, [&](int, int64_t b, int64_t e) {
+        std::vector<Term> t;
+        for (int64_t I = b; I < e; ++I) {
+            row_terms((int32_t)I, t);
+            int32_t d = 0;
+            for (size_t s = 0; s < t.size(); ++s)
+                if (s == 0 || t[s].J != t[s - 1].J) ++d;
+            cnt[I] = d;
+        }
+    });
+    Ac.n = nc;
+    Ac.rp.assign(nc + 1, 0);
+    for (int32_t I = 0; I < nc; ++I) {
+        int64_t nx = (int64_t)Ac.rp[I] + cnt[I];
+        if (nx >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "coarse matrix exceeds 2^31 entries");
+        Ac.rp[I + 1] = (int32_t)nx;
+    }
+    Ac.ci.resize(Ac.rp[nc]);
+    Ac.v.resize(Ac.rp[nc]);
+    parallel_ranges(nc, [&](int, int64_t b, int64_t e) {
+        std::vector<Term> t;
+        for (int64_t I = b; I < e; ++I) {
+            row_terms((int32_t)I, t);
+            int32_t q = Ac.rp[I] - 1;
+            for (size_t s = 0; s < t.size(); ++s) {
+                if (s == 0 || t[s].J != t[s - 1].J) {
+                    ++q;
+                    Ac.ci[q] = t[s].J;
+                    Ac.v[q] = t[s].t;
+                } else {
+                    Ac.v[q] = Ac.v[q] + t[s].t;
+                }
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------- coarsest
+
+static void dense_factor_and_inverse(const HostCSR& A, std::vector<double>& L, std::vector<double>& Ainv) {
+    const int32_t n = A.n;
+    L.assign((size_t)n * n, 0.0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) L[(size_t)i * n + A.ci[k]] = A.v[k];
+    // right-looking Cholesky on the lower triangle
+    for (int32_t j = 0; j < n; ++j) {
+        double d = L[(size_t)j * n + j];
+        if (!(d > 0.0)) throw Error(PAMG_E_NOT_SPD, "coarsest matrix is not positive definite (pivot " +
+                                                   std::to_string(j) + ")");
+        d = std::sqrt(d);
+        L[(size_t)j * n + j] = d;
+        for (int32_t i = j + 1; i < n; ++i) L[(size_t)i * n + j] /= d;
+        for (int32_t k = j + 1; k < n; ++k) {
+            double lkj = L[(size_t)k * n + j];
+            for (int32_t i = k; i < n; ++i) L[(size_t)i * n + k] -= L[(size_t)i * n + j] * lkj;
+        }
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) L[(size_t)i * n + j] = 0.0;
+    // X = L^{-1} by forward substitution on the identity
+    std::vector<double> X((size_t)n * n, 0.0);
+    for (int32_t c = 0; c < n; ++c) {
+        for (int32_t i = c; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int32_t k = c; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + c];
+            X[(size_t)i * n + c] = s / L[(size_t)i * n + i];
+        }
+    }
+    // A^{-1} = X^T X (symmetric by construction)
+    Ainv.assign((size_t)n * n, 0.0);
+    parallel_for(n, [&](int64_t i) {
+        for (int32_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            int32_t k0 = std::max((int32_t)i, j);
+            for (int32_t k = k0; k < n; ++k) s += X[(size_t)k * n + i] * X[(size_t)k * n + j];
+            Ainv[(size_t)i * n + j] = s;
+        }
+    }, 16);
+}
+
+// ---------------------------------------------------------------- driver
+
+HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
+    HostHierarchy H;
+    H.lev.emplace_back();
+    {
+        HostLevel& L0 = H.lev[0];
+        L0.A.n = Ain.n;
+        L0.A.rp.assign(Ain.row_ptr, Ain.row_ptr + Ain.n + 1);
+        L0.A.ci.assign(Ain.col_idx, Ain.col_idx + Ain.nnz);
+        L0.A.v.assign(Ain.val, Ain.val + Ain.nnz);
+        L0.w.assign(Ain.n, 1.0);
+    }
+    for (int l = 0;; ++l) {
+        HostLevel& cur = H.lev[l];
+        const HostCSR& A = cur.A;
+        const int32_t n = A.n;
+        std::vector<double> diag(n, 0.0);
+        cur.dinv.resize(n);
+        parallel_for(n, [&](int64_t i) {
+            double d = 0.0;
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                d += std::fabs(A.v[k]);
+                if (A.ci[k] == i) diag[i] = A.v[k];
+            }
+            cur.dinv[i] = 1.0 / d;
+        });
+        if (n <= prm.max_coarse || l + 1 >= prm.max_levels) break;
+        Adj g = eligible_adjacency(A, diag, cur.w, prm.match_all_edges != 0);
+        std::vector<int32_t> mate(n, -1);
+        int64_t pairs = suitor_matching(g, n, mate);
+        if (pairs == 0) break;
+        cur.pairs = (int32_t)pairs;
+        // aggregates numbered by smallest member
+        cur.agg.assign(n, -1);
+        cur.p.assign(n, 0.0);
+        int32_t nc = 0;
+        for (int32_t i = 0; i < n; ++i)
+            if (mate[i] < 0 || mate[i] > i) ++nc;
+        std::vector<double> wc(nc);
+        std::vector<int32_t> mem_ptr(nc + 1), mem(n);
+        int32_t I = 0, q = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t m = mate[i];
+            if (m >= 0 && m < i) continue;
+            mem_ptr[I] = q;
+            if (m < 0) {
+                cur.agg[i] = I;
+                cur.p[i] = cur.w[i] / std::fabs(cur.w[i]);
+                wc[I] = std::fabs(cur.w[i]);
+                mem[q++] = i;
+            } else {
+                double nu = std::sqrt(cur.w[i] * cur.w[i] + cur.w[m] * cur.w[m]);
+                cur.agg[i] = I; cur.agg[m] = I;
+                cur.p[i] = cur.w[i] / nu;
+                cur.p[m] = cur.w[m] / nu;
+                wc[I] = nu;
+                mem[q++] = i; mem[q++] = m;
+            }
+            ++I;
+        }
+        mem_ptr[nc] = q;
+        HostLevel next;
+        galerkin(A, cur.agg, cur.p, mem_ptr, mem, next.A);
+        next.w = std::move(wc);
+        H.lev.push_back(std::move(next));
+    }
+    const HostCSR& AL = H.lev.back().A;
+    if (AL.n > prm.max_dense)
+        throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
+                                        " unknowns, above the dense-solve limit");
+    dense_factor_and_inverse(AL, H.coarse_chol, H.coarse_inv);
+    return H;
+}
+
+// ---------------------------------------------------------------- layout
+
+// Hierarchical numbering: the coarsest level keeps its numbering; on every
+// finer level the members of each aggregate are placed next to each other,
+// in the order of their aggregate's (already permuted) coarse index, members
+// ascending.  Restriction and prolongation then touch contiguous rows.
+std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
+    const int nl = (int)H.lev.size();
+    std::vector<LayoutLevel> out(nl);
+    {
+        LayoutLevel& c = out[nl - 1];
+        int32_t n = H.lev[nl - 1].A.n;
+        c.perm.resize(n);
+        c.iperm.resize(n);
+        std::iota(c.perm.begin(), c.perm.end(), 0);
+        std::iota(c.iperm.begin(), c.iperm.end(), 0);
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const HostLevel& hl = H.lev[l];
+        const int32_t n = hl.A.n, nc = H.lev[l + 1].A.n;
+        // canonical members of each canonical aggregate, ascending
+        std::vector<int32_t> first(nc, -1), second(nc, -1);
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t I = hl.agg[i];
+            if (first[I] < 0) first[I] = i; else second[I] = i;
+        }
+        LayoutLevel& L = out[l];
+        L.iperm.resize(n);
+        L.perm.resize(n);
+        L.aggptr.resize(nc + 1);
+        const std::vector<int32_t>& cip = out[l + 1].iperm;
+        int32_t q = 0;
+        for (int32_t Ip = 0; Ip < nc; ++Ip) {
+            int32_t I = cip[Ip];
+            L.aggptr[Ip] = q;
+            L.iperm[q++] = first[I];
+            if (second[I] >= 0) L.iperm[q++] = second[I];
+        }
+        L.aggptr[nc] = q;
+        for (int32_t ip = 0; ip < n; ++ip) L.perm[L.iperm[ip]] = ip;
+    }
+    for (int l = 0; l < nl; ++l) {
+        const HostLevel& hl = H.lev[l];
+        LayoutLevel& L = out[l];
+        const int32_t n = hl.A.n;
+        L.rp.resize(n + 1);
+        L.rp[0] = 0;
+        for (int32_t ip = 0; ip < n; ++ip) {
+            int32_t i = L.iperm[ip];
+            L.rp[ip + 1] = L.rp[ip] + (hl.A.rp[i + 1] - hl.A.rp[i]);
+        }
+        L.ci.resize(hl.A.nnz());
+        L.v.resize(hl.A.nnz());
+        L.dinv.resize(n);
+        if (l + 1 < nl) L.p.resize(n);
+        parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+            std::vector<std::pair<int32_t, double>> row;
+            for (int64_t ip = b; ip < e; ++ip) {
+                int32_t i = L.iperm[ip];
+                row.clear();
+                for (int32_t k = hl.A.rp[i]; k < hl.A.rp[i + 1]; ++k) row.emplace_back(L.perm[hl.A.ci[k]], hl.A.v[k]);
+                std::sort(row.begin(), row.end(),
+                          [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b2) { return a.first < b2.first; });
+                int32_t o = L.rp[ip];
+                for (size_t s = 0; s < row.size(); ++s) { L.ci[o + s] = row[s].first; L.v[o + s] = row[s].second; }
+                L.dinv[ip] = hl.dinv[i];
+                if (l + 1 < nl) L.p[ip] = hl.p[i];
+            }
+        });
+        // row tiles: <= kTileRows rows and <= kTileNnz entries, or a single long row
+        L.up_tiles.clear();
+        L.up_tiles.push_back(0);
+        {
+            int32_t start = 0;
+            while (start < n) {
+                int32_t end = start + 1;
+                while (end < n && end - start < kTileRows && L.rp[end + 1] - L.rp[start] <= kTileNnz) ++end;
+                L.up_tiles.push_back(end);
+                start = end;
+            }
+        }
+        // restriction tiles over coarse rows: the fine rows of <= kTileRows
+        // aggregates holding <= kTileNnz entries, or a single aggregate
+        if (l + 1 < nl) {
+            const int32_t nc = H.lev[l + 1].A.n;
+            L.down_tiles.clear();
+            L.down_tiles.push_back(0);
+            int32_t start = 0;
+            while (start < nc) {
+                int32_t end = start + 1;
+                while (end < nc && end - start < kTileRows &&
+                       L.rp[L.aggptr[end + 1]] - L.rp[L.aggptr[start]] <= kTileNnz)
+                    ++end;
+                L.down_tiles.push_back(end);
+                start = end;
+            }
+        }
+    }
+    return out;
+}
+
+}  // namespace pamg

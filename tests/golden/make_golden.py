@@ -1,0 +1,56 @@
+"""Write the stored expected values of the full-size parity test.
+
+Calls only the CPU oracle (and the seeded input generators): the 128^3
+stretched-mesh Q1 system with its divergence right-hand side (seed 2),
+solved by FCG + the V-cycle to 1e-6; stores the iteration count, the
+recurrence residual and sampled entries of the solution, of the 5-iteration
+iterate and of one V-cycle application z = B b.
+
+    python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from workloads import SplitMix64, q1_rhs, q1_stretched  # noqa: E402
+
+
+def main():
+    N, ratio, seed = 128, 1.05, 2
+    A = q1_stretched(N, ratio)
+    b = q1_rhs(N, ratio, seed)
+    O = oracle.Hierarchy(A)
+    idx = np.unique(SplitMix64(99).integers(600, 0, A.n - 1))[:512]
+    x, it, rr, st = O.solve(b, 1e-6, krylov="fcg")
+    assert st == 0
+    x5, _, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=5)
+    z = O.vcycle(b)
+    out = {
+        "source": "oracle/oracle.c via tests/golden/make_golden.py",
+        "workload": {"q1_elements": N, "ratio": ratio, "rhs_seed": seed, "n": A.n, "nnz": A.nnz},
+        "levels": O.nlevels,
+        "level_n": [O.n(l) for l in range(O.nlevels)],
+        "fcg_tol": 1e-6,
+        "fcg_iterations": it,
+        "fcg_relres": rr,
+        "x_norm": float(np.linalg.norm(x)),
+        "x5_norm": float(np.linalg.norm(x5)),
+        "z_norm": float(np.linalg.norm(z)),
+        "sample_index": idx.tolist(),
+        "x_sample": [float(v) for v in x[idx]],
+        "x5_sample": [float(v) for v in x5[idx]],
+        "z_sample": [float(v) for v in z[idx]],
+    }
+    with open(os.path.join(HERE, "q1_128_fcg.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"levels {O.nlevels}, iterations {it}, relres {rr:.3e}")
+
+
+if __name__ == "__main__":
+    main()
