@@ -74,12 +74,25 @@ def lib():
         L.oracle_solve.argtypes = [vp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, ip, dp]
         L.oracle_solve.restype = C.c_int
+        L.oracle_csr_mv.argtypes = [C.c_int, ip, ip, dp, dp, dp]
         _lib = L
     return _lib
 
 
 def _p(a, t):
     return a.ctypes.data_as(C.POINTER(t))
+
+
+def csr_mv(A, x):
+    """y = A x with the oracle's plain row loop (no hierarchy needed)."""
+    rp = np.ascontiguousarray(A.row_ptr, np.int32)
+    ci = np.ascontiguousarray(A.col, np.int32)
+    v = np.ascontiguousarray(A.val, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.empty(A.n)
+    lib().oracle_csr_mv(int(A.n), _p(rp, C.c_int), _p(ci, C.c_int), _p(v, C.c_double), _p(x, C.c_double),
+                        _p(y, C.c_double))
+    return y
 
 
 class OracleError(RuntimeError):

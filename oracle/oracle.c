@@ -565,3 +565,12 @@ done:
     free(r); free(z); free(p); free(q);
     return status;
 }
+
+/* y = A x for a caller-held CSR (no hierarchy): the plain definition, rows
+ * summed in ascending column order. */
+void oracle_csr_mv(int n, const int *rp, const int *ci, const double *v, const double *x, double *y) {
+    or_csr a;
+    a.n = n; a.nnz = rp[n];
+    a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    csr_mv(&a, x, y);
+}

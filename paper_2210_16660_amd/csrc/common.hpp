@@ -48,16 +48,18 @@ struct LayoutLevel {
     std::vector<int32_t> iperm;     // hierarchical -> canonical
     std::vector<int32_t> rp, ci;    // permuted CSR, columns ascending
     std::vector<double> v;
+    std::vector<double> vd;         // column-scaled values a_ij / d_j (restriction pass, l < L)
     std::vector<double> dinv, p;    // permuted
     std::vector<int32_t> aggptr;    // n_{l+1}+1: members of coarse row I are rows [aggptr[I], aggptr[I+1])
-    std::vector<int32_t> down_tiles;  // coarse-row boundaries of the restriction tiles (l < L)
-    std::vector<int32_t> up_tiles;    // row boundaries of the row tiles
+    int items = 8;                  // tile capacity of this level: items * kBlock entries
+    std::vector<int32_t> down_tiles;  // 4 ints per restriction tile: k0, k1, c0, c1 (l < L)
+    std::vector<int32_t> up_tiles;    // 4 ints per row tile: k0, k1, r0, r1
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
-constexpr int kItems = 8;            // matrix entries per thread per tile
-constexpr int kTileNnz = kBlock * kItems;
+constexpr int kMaxItems = 8;         // matrix entries per thread per tile (largest tiles)
 constexpr int kTileRows = kBlock;    // at most one row (or aggregate) per thread in a tile
+constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep >= this many
 
 // setup.cpp
 void validate_csr(const pamg_csr& A, bool check_symmetry);

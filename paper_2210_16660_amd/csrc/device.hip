@@ -1,6 +1,5 @@
 // Device side of the library: hierarchy upload, V-cycle and Krylov launch
-// schedule, HIP-graph replay of iteration blocks, and the C-ABI entry points
-// that touch the GPU.
+// schedule, HIP-graph replay of iteration blocks, and the C-ABI entry points.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -9,6 +8,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -25,18 +25,18 @@ namespace pamg {
 template <typename T>
 struct DevVals {
     bool built = false;
-    std::vector<T*> v, dinv, p;   // per level (p for l < L)
-    std::vector<T*> r, zp;        // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
-    T* ainv = nullptr;            // dense A_L^{-1}
-    T* dbg_in = nullptr;          // scratch in this precision (max n)
+    std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
+    std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
+    T* ainv = nullptr;                // dense A_L^{-1}
+    T* dbg_in = nullptr;              // scratch in this precision (max n)
     T* dbg_in2 = nullptr;
 };
 
 struct DevLevelIdx {
-    int n = 0, nc = 0;
+    int n = 0, nc = 0, items = 8;
     long long nnz = 0;
-    int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *down_tiles = nullptr, *up_tiles = nullptr;
-    int *perm = nullptr, *iperm = nullptr;
+    int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *perm = nullptr, *iperm = nullptr;
+    const int4 *down_tiles = nullptr, *up_tiles = nullptr;
     int n_down = 0, n_up = 0;
 };
 
@@ -100,12 +100,14 @@ static inline int vec_grid(long long n) {
 template <typename T>
 static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<LayoutLevel>& lay, hipStream_t s) {
     const int nl = (int)lay.size();
-    V.v.resize(nl); V.dinv.resize(nl); V.p.assign(nl, nullptr); V.r.assign(nl, nullptr); V.zp.assign(nl, nullptr);
+    V.v.resize(nl); V.dinv.resize(nl);
+    V.vd.assign(nl, nullptr); V.p.assign(nl, nullptr); V.r.assign(nl, nullptr); V.zp.assign(nl, nullptr);
     size_t maxn = 0;
     for (int l = 0; l < nl; ++l) {
         V.v[l] = upload<T>(h, lay[l].v, s);
         V.dinv[l] = upload<T>(h, lay[l].dinv, s);
         if (l + 1 < nl) {
+            V.vd[l] = upload<T>(h, lay[l].vd, s);
             V.p[l] = upload<T>(h, lay[l].p, s);
             V.zp[l] = dalloc<T>(h, lay[l].dinv.size());
         }
@@ -141,16 +143,17 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
         I.n = (int)Ly.dinv.size();
         I.nnz = (long long)Ly.ci.size();
         I.nc = (l + 1 < nl) ? (int)lay[l + 1].dinv.size() : 0;
+        I.items = Ly.items;
         I.rp = upload<int>(h, Ly.rp, s);
         I.ci = upload<int>(h, Ly.ci, s);
         I.perm = upload<int>(h, Ly.perm, s);
         I.iperm = upload<int>(h, Ly.iperm, s);
-        I.up_tiles = upload<int>(h, Ly.up_tiles, s);
-        I.n_up = (int)Ly.up_tiles.size() - 1;
+        I.up_tiles = reinterpret_cast<const int4*>(upload<int>(h, Ly.up_tiles, s));
+        I.n_up = (int)Ly.up_tiles.size() / 4;
         if (l + 1 < nl) {
             I.aggptr = upload<int>(h, Ly.aggptr, s);
-            I.down_tiles = upload<int>(h, Ly.down_tiles, s);
-            I.n_down = (int)Ly.down_tiles.size() - 1;
+            I.down_tiles = reinterpret_cast<const int4*>(upload<int>(h, Ly.down_tiles, s));
+            I.n_down = (int)Ly.down_tiles.size() / 4;
         }
     }
     upload_values<double>(h, h->f64, lay, s);
@@ -174,8 +177,8 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     h->st = dalloc<SolveState>(h, 1);
     HIP_CHECK(hipMemsetAsync(h->zero_flag, 0, sizeof(int), s));
     HIP_CHECK(hipMemsetAsync(h->st, 0, sizeof(SolveState), s));
-    for (double* v : {h->x, h->r, h->z, h->p[0], h->p[1], h->q, h->b})
-        HIP_CHECK(hipMemsetAsync(v, 0, sizeof(double) * n0, s));
+    for (double* v : {h->x, h->r, h->z, h->p[0], h->p[1], h->q, h->b, h->dbg0, h->dbg1, h->dbg2})
+        HIP_CHECK(hipMemsetAsync(v, 0, sizeof(double) * (v == h->dbg0 || v == h->dbg1 || v == h->dbg2 ? maxn : n0), s));
     HIP_CHECK(hipHostMalloc((void**)&h->st_host, sizeof(SolveState), hipHostMallocDefault));
     HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -208,68 +211,117 @@ void destroy_hierarchy(pamg_hierarchy* h) {
     delete h;
 }
 
-// ---------------------------------------------------------------- schedule
+// ---------------------------------------------------------------- launchers
 
-#define LAUNCH(kernel, grid, shmem, stream, ...)                           \
-    do {                                                                   \
+#define LAUNCH(kernel, grid, shmem, stream, ...)                                           \
+    do {                                                                                   \
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), shmem, stream, __VA_ARGS__); \
     } while (0)
 
+// Call f with std::integral_constant<int, items> for the level's tile capacity.
+template <typename F>
+static void with_items(int items, F&& f) {
+    switch (items) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        default: f(std::integral_constant<int, 8>{}); break;
+    }
+}
+
+template <typename T, typename RT>
+static void launch_down(const DevLevelIdx& I, const T* vd, const RT* r, const T* p, T* rc, const int* done,
+                        hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_down<IT, T, RT>), tile_grid(I.n_down), 0, s, (const int*)I.rp, (const int*)I.ci, vd, r, p,
+               (const int*)I.aggptr, I.down_tiles, I.n_down, rc, done);
+    });
+}
+
+template <typename T, typename RT, typename RTF, bool OUT>
+static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r, const T* dinv, const int* aggptr_f,
+                      const RTF* r_f, const T* dinv_f, const T* p_f, T* zp_f, double* z_out, const double* dv,
+                      double* partial, const int* done, hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_up<IT, T, RT, RTF, OUT>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, zp, r,
+               dinv, I.up_tiles, I.n_up, aggptr_f, r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+    });
+}
+
+template <typename T, typename XT>
+static void launch_spmv(const DevLevelIdx& I, const T* v, const XT* x, const double* b, double* y, double* partial,
+                        hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, x, b, y,
+               I.up_tiles, I.n_up, partial);
+    });
+}
+
+static void launch_krylov(const DevLevelIdx& I, const double* v, const double* z, const double* p_old, double* p_new,
+                          double* q, const double* r, const SolveState* st, double* partial, const int* done,
+                          hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, z, p_old, p_new,
+               q, r, I.up_tiles, I.n_up, st, partial, done);
+    });
+}
+
+template <typename T, typename RT, typename RTF, bool OUT>
+static void launch_coarse(int nL, const T* ainv, const RT* r, const int* aggptr_f, const RTF* r_f, const T* dinv_f,
+                          const T* p_f, T* zp_f, double* z_out, const double* dv, double* partial, const int* done,
+                          hipStream_t s) {
+    const int G = coarse_groups(nL);
+    const size_t lds = (size_t)(1 + G) * nL * sizeof(T);
+    hipLaunchKernelGGL((k_coarse<T, RT, RTF, OUT>), dim3(1), dim3(kCoarseThreads), lds, s, nL, G, ainv, r, aggptr_f,
+                       r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+}
+
+// ---------------------------------------------------------------- schedule
+
 // z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
-// up-sweep also writes partial[g] of z . dv.  Returns the number of partials.
+// up-sweep also writes the partials of z . dv.  Returns the number of partials.
 template <typename T>
 static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
                           const int* done, hipStream_t s) {
     const int L = h->L;
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
-        const int g = tile_grid(I.n_down);
         if (l == 0)
-            LAUNCH((k_down<T, double>), g, 0, s, I.rp, I.ci, V.v[0], r0, V.dinv[0], V.p[0], I.aggptr,
-                   I.down_tiles, I.n_down, V.r[1], done);
+            launch_down<T, double>(I, V.vd[0], r0, V.p[0], V.r[1], done, s);
         else
-            LAUNCH((k_down<T, T>), g, 0, s, I.rp, I.ci, V.v[l], (const T*)V.r[l], V.dinv[l], V.p[l], I.aggptr,
-                   I.down_tiles, I.n_down, V.r[l + 1], done);
+            launch_down<T, T>(I, V.vd[l], V.r[l], V.p[l], V.r[l + 1], done, s);
     }
     const int nL = h->idx[L].n;
-    const size_t lds = (size_t)nL * sizeof(T);
     if (L == 0) {
-        LAUNCH((k_coarse<T, double, double, true>), 1, lds, s, nL, (const T*)V.ainv, r0, (const int*)nullptr,
-               (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, z_out, dv, h->partial,
-               done);
+        launch_coarse<T, double, double, true>(nL, V.ainv, r0, nullptr, (const double*)nullptr, nullptr, nullptr,
+                                               nullptr, z_out, dv, h->partial, done, s);
         return 1;
     }
     const DevLevelIdx& F = h->idx[L - 1];
     if (L - 1 == 0)
-        LAUNCH((k_coarse<T, T, double, false>), 1, lds, s, nL, (const T*)V.ainv, (const T*)V.r[L],
-               (const int*)F.aggptr, r0, (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], V.zp[L - 1], z_out, dv,
-               h->partial, done);
+        launch_coarse<T, T, double, false>(nL, V.ainv, V.r[L], F.aggptr, r0, V.dinv[0], V.p[0], V.zp[0], nullptr,
+                                           nullptr, nullptr, done, s);
     else
-        LAUNCH((k_coarse<T, T, T, false>), 1, lds, s, nL, (const T*)V.ainv, (const T*)V.r[L], (const int*)F.aggptr,
-               (const T*)V.r[L - 1], (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], V.zp[L - 1], z_out, dv,
-               h->partial, done);
-    for (int l = L - 1; l >= 0; --l) {
+        launch_coarse<T, T, T, false>(nL, V.ainv, V.r[L], F.aggptr, V.r[L - 1], V.dinv[L - 1], V.p[L - 1],
+                                      V.zp[L - 1], nullptr, nullptr, nullptr, done, s);
+    for (int l = L - 1; l >= 1; --l) {
         const DevLevelIdx& I = h->idx[l];
-        const int g = tile_grid(I.n_up);
-        if (l == 0) {
-            LAUNCH((k_up<T, double, double, true>), g, 0, s, I.rp, I.ci, (const T*)V.v[0], (const T*)V.zp[0], r0,
-                   (const T*)V.dinv[0], I.up_tiles, I.n_up, (const int*)nullptr, (const double*)nullptr,
-                   (const T*)nullptr, (const T*)nullptr, (T*)nullptr, z_out, dv, h->partial, done);
-            return g;
-        }
         const DevLevelIdx& Fi = h->idx[l - 1];
         if (l - 1 == 0)
-            LAUNCH((k_up<T, T, double, false>), g, 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.zp[l],
-                   (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up, (const int*)Fi.aggptr, r0,
-                   (const T*)V.dinv[l - 1], (const T*)V.p[l - 1], V.zp[l - 1], (double*)nullptr,
-                   (const double*)nullptr, (double*)nullptr, done);
+            launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], Fi.aggptr, r0, V.dinv[0], V.p[0],
+                                           V.zp[0], nullptr, nullptr, nullptr, done, s);
         else
-            LAUNCH((k_up<T, T, T, false>), g, 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.zp[l],
-                   (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up, (const int*)Fi.aggptr,
-                   (const T*)V.r[l - 1], (const T*)V.dinv[l - 1], (const T*)V.p[l - 1], V.zp[l - 1],
-                   (double*)nullptr, (const double*)nullptr, (double*)nullptr, done);
+            launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], Fi.aggptr, V.r[l - 1], V.dinv[l - 1],
+                                      V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr, done, s);
     }
-    return 0;  // unreachable
+    const DevLevelIdx& I0 = h->idx[0];
+    launch_up<T, double, double, true>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const double*)nullptr, nullptr,
+                                       nullptr, nullptr, z_out, dv, h->partial, done, s);
+    return tile_grid(I0.n_up);
 }
 
 template <typename T>
@@ -279,11 +331,8 @@ static void enqueue_iteration(pamg_hierarchy* h, DevVals<T>& V, int krylov, int 
     const int cnt = enqueue_vcycle<T>(h, V, h->r, h->z, dv, done, s);
     LAUNCH(k_fin_beta, 1, 0, s, h->st, (const double*)h->partial, cnt);
     const DevLevelIdx& I = h->idx[0];
-    const int g = tile_grid(I.n_up);
-    LAUNCH(k_krylov_pq, g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->z,
-           (const double*)h->p[parity], h->p[1 - parity], h->q, (const double*)h->r, I.up_tiles, I.n_up,
-           (const SolveState*)h->st, h->partial, done);
-    LAUNCH(k_fin_alpha, 1, 0, s, h->st, (const double*)h->partial, g);
+    launch_krylov(I, h->f64.v[0], h->z, h->p[parity], h->p[1 - parity], h->q, h->r, h->st, h->partial, done, s);
+    LAUNCH(k_fin_alpha, 1, 0, s, h->st, (const double*)h->partial, tile_grid(I.n_up));
     const int gv = vec_grid(I.n);
     LAUNCH(k_krylov_update, gv, 0, s, I.n, h->x, h->r, (const double*)h->p[1 - parity], (const double*)h->q,
            (const SolveState*)h->st, h->partial, done);
@@ -322,8 +371,7 @@ static void read_state(pamg_hierarchy* h, hipStream_t s) {
 static double true_relres(pamg_hierarchy* h, hipStream_t s) {
     const DevLevelIdx& I = h->idx[0];
     const int g = tile_grid(I.n_up);
-    LAUNCH((k_spmv<double, double, double>), g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->x,
-           (const double*)h->b, h->dbg0, I.up_tiles, I.n_up, h->partial_b);
+    launch_spmv<double, double>(I, h->f64.v[0], h->x, h->b, h->dbg0, h->partial_b, s);
     std::vector<double> part(g);
     HIP_CHECK(hipMemcpyAsync(part.data(), h->partial_b, sizeof(double) * g, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -353,10 +401,9 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
     LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, (double*)nullptr, h->partial_b);
     if (o.use_x0) {
         LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, (const double*)x_user, h->x);
-        const int g = tile_grid(I0.n_up);
-        LAUNCH((k_spmv<double, double, double>), g, 0, s, I0.rp, I0.ci, (const double*)h->f64.v[0],
-               (const double*)h->x, (const double*)h->b, h->r, I0.up_tiles, I0.n_up, h->partial);
-        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial, g);
+        launch_spmv<double, double>(I0, h->f64.v[0], h->x, h->b, h->r, h->partial, s);
+        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial,
+               tile_grid(I0.n_up));
     } else {
         LAUNCH(k_fill, gv, 0, s, (long long)n, h->x, 0.0);
         LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, h->r, h->partial);
@@ -386,10 +433,9 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
         if (relres_true <= o.tol || prec != PAMG_PREC_F32 || restarts >= 10 || h->st_host->iter >= o.maxit) break;
         // FP32 preconditioner: restart the recurrence from the true residual
         ++restarts;
-        const int g = tile_grid(I0.n_up);
-        LAUNCH((k_spmv<double, double, double>), g, 0, s, I0.rp, I0.ci, (const double*)h->f64.v[0],
-               (const double*)h->x, (const double*)h->b, h->r, I0.up_tiles, I0.n_up, h->partial);
-        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, 0, (const double*)h->partial, g);
+        launch_spmv<double, double>(I0, h->f64.v[0], h->x, h->b, h->r, h->partial, s);
+        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, 0, (const double*)h->partial,
+               tile_grid(I0.n_up));
         read_state(h, s);
         relres_true = -1.0;
     }
@@ -407,7 +453,9 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
     }
 }
 
-static void require_device(const pamg_hierarchy* h);
+static void require_device(const pamg_hierarchy* h) {
+    if (h->host_only) throw Error(PAMG_E_INVALID, "hierarchy was built with host_only=1");
+}
 
 int solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts& o, hipStream_t s,
           pamg_solve_info* info) {
@@ -436,8 +484,7 @@ static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const do
     switch (op) {
         case PAMG_OP_SPMV: {
             LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in0, V.dbg_in);
-            LAUNCH((k_spmv<T, T, double>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
-                   (const double*)nullptr, h->dbg1, I.up_tiles, I.n_up, (double*)nullptr);
+            launch_spmv<T, T>(I, V.v[l], V.dbg_in, nullptr, h->dbg1, nullptr, s);
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
             break;
         }
@@ -447,13 +494,9 @@ static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const do
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
             LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in0, V.dbg_in);
             if (l == 0)
-                LAUNCH((k_down<T, double>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[0],
-                       (const double*)h->dbg0, (const T*)V.dinv[0], (const T*)V.p[0], (const int*)I.aggptr,
-                       (const int*)I.down_tiles, I.n_down, V.dbg_in2, nodone);
+                launch_down<T, double>(I, V.vd[0], h->dbg0, V.p[0], V.dbg_in2, nodone, s);
             else
-                LAUNCH((k_down<T, T>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
-                       (const T*)V.dinv[l], (const T*)V.p[l], (const int*)I.aggptr, (const int*)I.down_tiles,
-                       I.n_down, V.dbg_in2, nodone);
+                launch_down<T, T>(I, V.vd[l], V.dbg_in, V.p[l], V.dbg_in2, nodone, s);
             LAUNCH((k_gather<T, double>), vec_grid(C.n), 0, s, C.n, (const int*)C.perm, (const T*)V.dbg_in2, out);
             break;
         }
@@ -462,16 +505,14 @@ static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const do
             if (l >= h->L) throw Error(PAMG_E_INVALID, "UP needs level < L");
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
             LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in1, V.dbg_in);
-            LAUNCH((k_up<T, double, double, true>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
-                   (const T*)V.dbg_in, (const double*)h->dbg0, (const T*)V.dinv[l], I.up_tiles, I.n_up,
-                   (const int*)nullptr, (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
-                   h->dbg1, (const double*)h->dbg0, h->partial, nodone);
+            launch_up<T, double, double, true>(I, V.v[l], V.dbg_in, h->dbg0, V.dinv[l], nullptr,
+                                               (const double*)nullptr, nullptr, nullptr, nullptr, h->dbg1, h->dbg0,
+                                               h->partial, nodone, s);
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
             break;
         }
         case PAMG_OP_PROLONG: {
-            // out = D^-1 in0 + P in1, via the coarse-row kernel of level l+1's
-            // up-sweep: run k_coarse-style prolongation through k_prolong
+            // out = D^-1 in0 + P in1
             if (l >= h->L) throw Error(PAMG_E_INVALID, "PROLONG needs level < L");
             const DevLevelIdx& C = h->idx[l + 1];
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
@@ -484,9 +525,8 @@ static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const do
         case PAMG_OP_COARSE: {
             if (l != h->L) throw Error(PAMG_E_INVALID, "COARSE needs level == L");
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
-            LAUNCH((k_coarse<T, double, double, true>), 1, (size_t)I.n * sizeof(T), s, I.n, (const T*)V.ainv,
-                   (const double*)h->dbg0, (const int*)nullptr, (const double*)nullptr, (const T*)nullptr,
-                   (const T*)nullptr, (T*)nullptr, h->dbg1, (const double*)h->dbg0, h->partial, nodone);
+            launch_coarse<T, double, double, true>(I.n, V.ainv, h->dbg0, nullptr, (const double*)nullptr, nullptr,
+                                                   nullptr, nullptr, h->dbg1, h->dbg0, h->partial, nodone, s);
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
             break;
         }
@@ -519,34 +559,34 @@ int debug_apply(pamg_hierarchy* h, int op, int level, int prec, const double* in
     return PAMG_OK;
 }
 
+// ---------------------------------------------------------------- timing
+
+template <typename F>
+static double time_launches(F&& launch, int reps, hipStream_t s) {
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    for (int w = 0; w < 2; ++w) launch();
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    HIP_CHECK(hipGetLastError());
+    float a = 0;
+    HIP_CHECK(hipEventElapsedTime(&a, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)a / reps;
+}
+
 template <typename T>
 static void time_impl(pamg_hierarchy* h, DevVals<T>& V, const double* r, int reps, hipStream_t s, double* vms,
                       double* sms) {
     const DevLevelIdx& I = h->idx[0];
-    const int gv = vec_grid(I.n);
-    LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, r, h->dbg0);
-    hipEvent_t e0, e1, e2;
-    HIP_CHECK(hipEventCreate(&e0));
-    HIP_CHECK(hipEventCreate(&e1));
-    HIP_CHECK(hipEventCreate(&e2));
-    for (int w = 0; w < 2; ++w) enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, h->zero_flag, s);
-    HIP_CHECK(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, h->zero_flag, s);
-    HIP_CHECK(hipEventRecord(e1, s));
-    const int g = tile_grid(I.n_up);
-    for (int i = 0; i < reps; ++i)
-        LAUNCH((k_spmv<double, double, double>), g, 0, s, I.rp, I.ci, (const double*)h->f64.v[0],
-               (const double*)h->dbg1, (const double*)nullptr, h->dbg2, I.up_tiles, I.n_up, (double*)nullptr);
-    HIP_CHECK(hipEventRecord(e2, s));
-    HIP_CHECK(hipEventSynchronize(e2));
-    float a = 0, b = 0;
-    HIP_CHECK(hipEventElapsedTime(&a, e0, e1));
-    HIP_CHECK(hipEventElapsedTime(&b, e1, e2));
-    *vms = a / reps;
-    *sms = b / reps;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
+    LAUNCH((k_gather<double, double>), vec_grid(I.n), 0, s, I.n, (const int*)I.iperm, r, h->dbg0);
+    *vms = time_launches([&]() { enqueue_vcycle<T>(h, V, h->dbg0, h->dbg1, h->dbg0, h->zero_flag, s); }, reps, s);
+    *sms = time_launches([&]() { launch_spmv<double, double>(I, h->f64.v[0], h->dbg1, nullptr, h->dbg2, nullptr, s); },
+                         reps, s);
 }
 
 int time_kernels(pamg_hierarchy* h, int prec, const double* r, int reps, hipStream_t s, double* vms, double* sms) {
@@ -563,8 +603,6 @@ int time_kernels(pamg_hierarchy* h, int prec, const double* r, int reps, hipStre
     return PAMG_OK;
 }
 
-static void require_device(const pamg_hierarchy* h);
-
 template <typename T>
 static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int reps, hipStream_t s, double* ms,
                          uint64_t* bytes) {
@@ -576,30 +614,21 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
     if (op == PAMG_OP_DOWN) {
         if (l >= h->L) throw Error(PAMG_E_INVALID, "DOWN needs level < L");
         const uint64_t nc = h->idx[l + 1].n;
-        // matrix, own r/dinv/p (r in FP64 at level 0), aggptr, coarse output
-        *bytes = M + n * (l == 0 ? 8 : sz) + 2 * n * sz + 4 * (nc + 1) + nc * sz;
+        // scaled matrix, own r/p (r in FP64 at level 0), aggptr, coarse output
+        *bytes = M + n * (l == 0 ? 8 : sz) + n * sz + 4 * (nc + 1) + nc * sz;
         if (l == 0)
-            launch = [=]() {
-                LAUNCH((k_down<T, double>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[0],
-                       (const double*)h->r, (const T*)V.dinv[0], (const T*)V.p[0], (const int*)I.aggptr,
-                       (const int*)I.down_tiles, I.n_down, V.r[1], nodone);
-            };
+            launch = [=]() { launch_down<T, double>(I, V.vd[0], h->r, V.p[0], V.r[1], nodone, s); };
         else
-            launch = [=]() {
-                LAUNCH((k_down<T, T>), tile_grid(I.n_down), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.r[l],
-                       (const T*)V.dinv[l], (const T*)V.p[l], (const int*)I.aggptr, (const int*)I.down_tiles,
-                       I.n_down, V.r[l + 1], nodone);
-            };
+            launch = [=]() { launch_down<T, T>(I, V.vd[l], V.r[l], V.p[l], V.r[l + 1], nodone, s); };
     } else if (op == PAMG_OP_UP) {
         if (l >= h->L) throw Error(PAMG_E_INVALID, "UP needs level < L");
         if (l == 0) {
             // matrix, own zp/dinv (T), r and dv (FP64), z out (FP64)
             *bytes = M + 2 * n * sz + 3 * n * 8;
             launch = [=]() {
-                LAUNCH((k_up<T, double, double, true>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[0],
-                       (const T*)V.zp[0], (const double*)h->r, (const T*)V.dinv[0], I.up_tiles, I.n_up,
-                       (const int*)nullptr, (const double*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
-                       h->z, (const double*)h->q, h->partial, nodone);
+                launch_up<T, double, double, true>(I, V.v[0], V.zp[0], h->r, V.dinv[0], nullptr,
+                                                   (const double*)nullptr, nullptr, nullptr, nullptr, h->z, h->q,
+                                                   h->partial, nodone, s);
             };
         } else {
             const DevLevelIdx& F = h->idx[l - 1];
@@ -608,52 +637,31 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
             *bytes = M + 3 * n * sz + 4 * (n + 1) + nf * ((l - 1 == 0 ? 8 : sz) + 3 * sz);
             if (l - 1 == 0)
                 launch = [=]() {
-                    LAUNCH((k_up<T, T, double, false>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
-                           (const T*)V.zp[l], (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up,
-                           (const int*)F.aggptr, (const double*)h->r, (const T*)V.dinv[0], (const T*)V.p[0], V.zp[0],
-                           (double*)nullptr, (const double*)nullptr, (double*)nullptr, nodone);
+                    launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], F.aggptr, h->r, V.dinv[0],
+                                                   V.p[0], V.zp[0], nullptr, nullptr, nullptr, nodone, s);
                 };
             else
                 launch = [=]() {
-                    LAUNCH((k_up<T, T, T, false>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l],
-                           (const T*)V.zp[l], (const T*)V.r[l], (const T*)V.dinv[l], I.up_tiles, I.n_up,
-                           (const int*)F.aggptr, (const T*)V.r[l - 1], (const T*)V.dinv[l - 1], (const T*)V.p[l - 1],
-                           V.zp[l - 1], (double*)nullptr, (const double*)nullptr, (double*)nullptr, nodone);
+                    launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], F.aggptr, V.r[l - 1],
+                                              V.dinv[l - 1], V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr,
+                                              nodone, s);
                 };
         }
     } else if (op == PAMG_OP_SPMV) {
         *bytes = M + n * sz + n * 8;
-        launch = [=]() {
-            LAUNCH((k_spmv<T, T, double>), tile_grid(I.n_up), 0, s, I.rp, I.ci, (const T*)V.v[l], (const T*)V.dbg_in,
-                   (const double*)nullptr, h->dbg1, I.up_tiles, I.n_up, (double*)nullptr);
-        };
+        launch = [=]() { launch_spmv<T, T>(I, V.v[l], V.dbg_in, nullptr, h->dbg1, nullptr, s); };
     } else if (op == PAMG_OP_KRYLOV) {
         if (l != 0) throw Error(PAMG_E_INVALID, "KRYLOV runs on level 0");
         const uint64_t M8 = nnz * 12 + 4 * (n + 1);
         // matrix (FP64), z, p_old, r reads; p_new, q writes
         *bytes = M8 + 5 * n * 8;
         launch = [=]() {
-            LAUNCH(k_krylov_pq, tile_grid(I.n_up), 0, s, I.rp, I.ci, (const double*)h->f64.v[0], (const double*)h->z,
-                   (const double*)h->p[0], h->p[1], h->q, (const double*)h->r, I.up_tiles, I.n_up,
-                   (const SolveState*)h->st, h->partial, nodone);
+            launch_krylov(I, h->f64.v[0], h->z, h->p[0], h->p[1], h->q, h->r, h->st, h->partial, nodone, s);
         };
     } else {
         throw Error(PAMG_E_INVALID, "op must be DOWN, UP, SPMV or KRYLOV");
     }
-    hipEvent_t e0, e1;
-    HIP_CHECK(hipEventCreate(&e0));
-    HIP_CHECK(hipEventCreate(&e1));
-    for (int w = 0; w < 3; ++w) launch();
-    HIP_CHECK(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) launch();
-    HIP_CHECK(hipEventRecord(e1, s));
-    HIP_CHECK(hipEventSynchronize(e1));
-    HIP_CHECK(hipGetLastError());
-    float a = 0;
-    HIP_CHECK(hipEventElapsedTime(&a, e0, e1));
-    *ms = a / reps;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    *ms = time_launches(launch, reps, s);
 }
 
 int time_op(pamg_hierarchy* h, int op, int level, int prec, int reps, hipStream_t s, double* ms, uint64_t* bytes) {
@@ -684,10 +692,6 @@ pamg_hierarchy* new_hierarchy(bool host_only) {
         }
     }
     return h;
-}
-
-static void require_device(const pamg_hierarchy* h) {
-    if (h->host_only) throw Error(PAMG_E_INVALID, "hierarchy was built with host_only=1");
 }
 
 }  // namespace pamg

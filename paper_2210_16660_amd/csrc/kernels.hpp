@@ -4,7 +4,7 @@
 // each aggregate are adjacent rows (the tentative prolongator of
 // eq. (prolongator) then maps the contiguous rows aggptr[I]..aggptr[I+1]-1
 // to coarse row I).  Tiles are row ranges (or aggregate ranges) whose
-// entries fit kTileNnz; one workgroup streams a tile's col/val arrays once,
+// entries fit one tile; one workgroup streams a tile's col/val arrays once,
 // fully coalesced, into LDS as products a_ij * x_j, then finishes each row
 // from LDS.  A fixed grid walks the tiles: the tiles are split into eight
 // contiguous chunks, one per XCD (workgroups are dispatched round-robin over
@@ -72,58 +72,99 @@ __device__ __forceinline__ TileWalk tile_walk(int ntiles) {
 
 inline int tile_grid(int ntiles) { return ntiles < kMaxGrid ? (ntiles > 0 ? ntiles : 1) : kMaxGrid; }
 
+// Tile descriptors (precomputed on the host, one 16-byte load per tile):
+//   row tile          {k0, k1, r0, r1}: entries [k0, k1) of rows [r0, r1)
+//   restriction tile  {k0, k1, c0, c1}: entries [k0, k1) of the fine rows that
+//                     are the members of coarse rows [c0, c1)
+// A tile holds at most ITEMS*kBlock entries (ITEMS chosen per level so that
+// small levels still spread over all CUs), except a single row / aggregate
+// longer than that, which takes the block-reduction path.
+//
+// Phase 1 of every tile kernel issues all of a thread's col/val loads at once
+// (indices clamped into the tile, so there is no branch between the loads),
+// then the gathers, then writes the products to LDS; the per-row data each
+// thread needs in phase 2 is loaded in the same batch.
+
+template <int ITEMS>
+__device__ __forceinline__ void tile_slots(int k0, int k1, int (&kk)[ITEMS]) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int k = k0 + it * kBlock + (int)threadIdx.x;
+        kk[it] = k < k1 ? k : k1 - 1;
+    }
+}
+
+template <int ITEMS, typename T>
+__device__ __forceinline__ void tile_store(int k0, int k1, const T (&a)[ITEMS], const T (&x)[ITEMS], T* s_prod) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int k = k0 + it * kBlock + (int)threadIdx.x;
+        if (k < k1) s_prod[k - k0] = a[it] * x[it];
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Down-sweep at level l (pre-smooth from zero, residual, restriction):
-//   z = D^-1 r;  t = r - A z;  rc[I] = sum_{i in G_I} p_i t_i
-// Tiles are ranges of coarse rows.  z is never stored: z_j = dinv_j r_j is
-// formed at the gather.
-template <typename T, typename RT>
+//   z = D^-1 r;  t = r - A z = r - (A D^-1) r;  rc[I] = sum_{i in G_I} p_i t_i
+// `ad` holds the column-scaled values a_ij / d_j, so one gather of r suffices.
+template <int ITEMS, typename T, typename RT>
 __global__ __launch_bounds__(kBlock) void k_down(
-    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const RT* __restrict__ r, const T* __restrict__ dinv, const T* __restrict__ p,
-    const int* __restrict__ aggptr, const int* __restrict__ tiles, int ntiles,
-    T* __restrict__ rc, const int* __restrict__ done) {
+    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ ad,
+    const RT* __restrict__ r, const T* __restrict__ p, const int* __restrict__ aggptr,
+    const int4* __restrict__ tiles, int ntiles, T* __restrict__ rc, const int* __restrict__ done) {
     if (*done) return;
-    __shared__ T s_prod[kTileNnz];
+    __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int c0 = tiles[t], c1 = tiles[t + 1];
-        const int f0 = aggptr[c0], f1 = aggptr[c1];
-        const int k0 = rp[f0], k1 = rp[f1];
-        if (k1 - k0 <= kTileNnz) {
+        const int4 d = tiles[t];
+        const int k0 = d.x, k1 = d.y, c0 = d.z, c1 = d.w;
+        if (k1 - k0 <= ITEMS * kBlock) {
+            int kk[ITEMS], c[ITEMS];
+            T a[ITEMS], x[ITEMS];
+            tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                const int k = k0 + it * kBlock + tid;
-                if (k < k1) {
-                    const int c = ci[k];
-                    s_prod[k - k0] = av[k] * (dinv[c] * (T)r[c]);
-                }
-            }
-            __syncthreads();
+            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) a[it] = ad[kk[it]];
             const int I = c0 + tid;
-            if (I < c1) {
-                T acc = 0;
-                const int m1 = aggptr[I + 1];
-                for (int m = aggptr[I]; m < m1; ++m) {
-                    T s = 0;
-                    const int e = rp[m + 1] - k0;
-                    for (int k = rp[m] - k0; k < e; ++k) s += s_prod[k];
-                    acc += p[m] * ((T)r[m] - s);
+            const bool own = I < c1;
+            const int Ic = own ? I : c1 - 1;
+            const int m0 = aggptr[Ic], m1 = aggptr[Ic + 1];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) x[it] = (T)r[c[it]];
+            const int e0 = rp[m0], e1 = rp[m0 + 1], e2 = rp[m1];
+            const T r0 = (T)r[m0], p0 = p[m0];
+            const bool two = m1 - m0 >= 2;
+            const T r1 = two ? (T)r[m0 + 1] : T(0), p1 = two ? p[m0 + 1] : T(0);
+            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            __syncthreads();
+            if (own) {
+                T s = 0;
+                for (int k = e0 - k0; k < e1 - k0; ++k) s += s_prod[k];
+                T acc = p0 * (r0 - s);
+                if (two) {
+                    const int e1b = (m1 - m0 == 2) ? e2 : rp[m0 + 2];
+                    s = 0;
+                    for (int k = e1 - k0; k < e1b - k0; ++k) s += s_prod[k];
+                    acc += p1 * (r1 - s);
+                    for (int m = m0 + 2; m < m1; ++m) {      // aggregates larger than pairs
+                        s = 0;
+                        for (int k = rp[m] - k0; k < rp[m + 1] - k0; ++k) s += s_prod[k];
+                        acc += p[m] * ((T)r[m] - s);
+                    }
                 }
                 rc[I] = acc;
             }
             __syncthreads();
         } else {
             // one aggregate whose rows exceed a tile
+            const int f0 = aggptr[c0], f1 = aggptr[c1];
             T acc = 0;
             for (int m = f0; m < f1; ++m) {
                 T s = 0;
-                for (int k = rp[m] + tid; k < rp[m + 1]; k += kBlock) {
-                    const int c = ci[k];
-                    s += av[k] * (dinv[c] * (T)r[c]);
-                }
+                for (int k = rp[m] + tid; k < rp[m + 1]; k += kBlock) s += ad[k] * (T)r[ci[k]];
                 s = block_sum(s, s_red);
                 if (tid == 0) acc += p[m] * ((T)r[m] - s);
             }
@@ -138,44 +179,64 @@ __global__ __launch_bounds__(kBlock) void k_down(
 //   l > 0: prolongate into level l-1:  zp_f[m] = dinv_f[m] r_f[m] + p_f[m] z_I
 //          for the members m of coarse row I (= this level's row);
 //   l = 0: write z (FP64) and accumulate the partial of z . dv.
-template <typename T, typename RT, typename RTF, bool TO_OUT>
+template <int ITEMS, typename T, typename RT, typename RTF, bool TO_OUT>
 __global__ __launch_bounds__(kBlock) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
-    const int* __restrict__ tiles, int ntiles,
+    const int4* __restrict__ tiles, int ntiles,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
     const T* __restrict__ p_f, T* __restrict__ zp_f,
     double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
     const int* __restrict__ done) {
     if (*done) return;
-    __shared__ T s_prod[kTileNnz];
+    __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double dot = 0.0;
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int i0 = tiles[t], i1 = tiles[t + 1];
-        const int k0 = rp[i0], k1 = rp[i1];
-        if (k1 - k0 <= kTileNnz) {
+        const int4 d = tiles[t];
+        const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
+        if (k1 - k0 <= ITEMS * kBlock) {
+            int kk[ITEMS], c[ITEMS];
+            T a[ITEMS], x[ITEMS];
+            tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                const int k = k0 + it * kBlock + tid;
-                if (k < k1) s_prod[k - k0] = av[k] * zp[ci[k]];
-            }
-            __syncthreads();
+            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
             const int i = i0 + tid;
-            if (i < i1) {
+            const bool own = i < i1;
+            const int ic = own ? i : i1 - 1;
+            const int rb = rp[ic], re = rp[ic + 1];
+            const T zpi = zp[ic], di = dinv[ic];
+            const T ri = (T)r[ic];
+            int a0 = 0, a1 = 0;
+            if constexpr (!TO_OUT) { a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1]; }
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) x[it] = zp[c[it]];
+            double dvi = 0.0;
+            T rf0 = 0, df0 = 0, pf0 = 0, rf1 = 0, df1 = 0, pf1 = 0;
+            if constexpr (TO_OUT) {
+                dvi = dv[ic];
+            } else {
+                rf0 = (T)r_f[a0]; df0 = dinv_f[a0]; pf0 = p_f[a0];
+                if (a1 - a0 >= 2) { rf1 = (T)r_f[a0 + 1]; df1 = dinv_f[a0 + 1]; pf1 = p_f[a0 + 1]; }
+            }
+            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            __syncthreads();
+            if (own) {
                 T s = 0;
-                const int e = rp[i + 1] - k0;
-                for (int k = rp[i] - k0; k < e; ++k) s += s_prod[k];
-                const T z = zp[i] + dinv[i] * ((T)r[i] - s);
+                for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
+                const T z = zpi + di * (ri - s);
                 if constexpr (TO_OUT) {
                     z_out[i] = (double)z;
-                    dot += (double)z * dv[i];
+                    dot += (double)z * dvi;
                 } else {
-                    const int m1 = aggptr_f[i + 1];
-                    for (int m = aggptr_f[i]; m < m1; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
+                    zp_f[a0] = df0 * rf0 + pf0 * z;
+                    if (a1 - a0 >= 2) zp_f[a0 + 1] = df1 * rf1 + pf1 * z;
+                    for (int m = a0 + 2; m < a1; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
                 }
             }
             __syncthreads();
@@ -202,12 +263,17 @@ __global__ __launch_bounds__(kBlock) void k_up(
 }
 
 // ----------------------------------------------------------------------------
-// Coarsest level: z = A_L^-1 r (dense symmetric inverse, one workgroup; r is
-// staged in LDS, nL <= 4096), then prolongate into level L-1 as in k_up, or
-// (single-level hierarchy) write z.
+// Coarsest level: z = A_L^-1 r with the dense symmetric inverse, one
+// workgroup of 1024 threads: the columns j are split into G groups whose
+// partial sums meet in LDS (fixed order), then each row I prolongates into
+// level L-1 as in k_up, or (single-level hierarchy) writes z.
+// Dynamic LDS: (1 + G) * nL values, G = 16 (nL <= 256), 4 (nL <= 1024), else 1.
+constexpr int kCoarseThreads = 1024;
+inline int coarse_groups(int nL) { return nL <= 256 ? 16 : (nL <= 1024 ? 4 : 1); }
+
 template <typename T, typename RT, typename RTF, bool TO_OUT>
-__global__ __launch_bounds__(kBlock) void k_coarse(
-    int nL, const T* __restrict__ ainv, const RT* __restrict__ r,
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(
+    int nL, int G, const T* __restrict__ ainv, const RT* __restrict__ r,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
     const T* __restrict__ p_f, T* __restrict__ zp_f,
     double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
@@ -215,14 +281,24 @@ __global__ __launch_bounds__(kBlock) void k_coarse(
     if (*done) return;
     extern __shared__ __align__(16) unsigned char s_raw[];
     T* s_r = reinterpret_cast<T*>(s_raw);
-    __shared__ double s_redd[kBlock / 64];
+    T* s_part = s_r + nL;
+    __shared__ double s_redd[kCoarseThreads / 64];
     const int tid = threadIdx.x;
-    for (int i = tid; i < nL; i += kBlock) s_r[i] = (T)r[i];
+    for (int i = tid; i < nL; i += kCoarseThreads) s_r[i] = (T)r[i];
+    __syncthreads();
+    const int per = kCoarseThreads / G;          // threads per column group
+    const int g = tid / per, lt = tid % per;
+    const int j0 = (int)((long long)nL * g / G), j1 = (int)((long long)nL * (g + 1) / G);
+    for (int I = lt; I < nL; I += per) {
+        T s = 0;
+        for (int j = j0; j < j1; ++j) s += ainv[(size_t)j * nL + I] * s_r[j];
+        s_part[(size_t)g * nL + I] = s;
+    }
     __syncthreads();
     double dot = 0.0;
-    for (int I = tid; I < nL; I += kBlock) {
+    for (int I = tid; I < nL; I += kCoarseThreads) {
         T z = 0;
-        for (int j = 0; j < nL; ++j) z += ainv[(size_t)j * nL + I] * s_r[j];
+        for (int q = 0; q < G; ++q) z += s_part[(size_t)q * nL + I];
         if constexpr (TO_OUT) {
             z_out[I] = (double)z;
             dot += (double)z * dv[I];
@@ -231,8 +307,14 @@ __global__ __launch_bounds__(kBlock) void k_coarse(
         }
     }
     if constexpr (TO_OUT) {
-        dot = block_sum(dot, s_redd);
-        if (tid == 0) partial[0] = dot;
+        dot = wave_sum(dot);
+        if ((tid & 63) == 0) s_redd[tid >> 6] = dot;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int q = 0; q < kCoarseThreads / 64; ++q) t += s_redd[q];
+            partial[0] = t;
+        }
     }
 }
 
@@ -253,43 +335,51 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __restrict_
 // ----------------------------------------------------------------------------
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
 // y . y.
-template <typename T, typename XT, typename YT>
+template <int ITEMS, typename T, typename XT, typename YT>
 __global__ __launch_bounds__(kBlock) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const XT* __restrict__ x, const double* __restrict__ b, YT* __restrict__ y,
-    const int* __restrict__ tiles, int ntiles, double* __restrict__ partial) {
-    __shared__ T s_prod[kTileNnz];
+    const XT* __restrict__ xv, const double* __restrict__ b, YT* __restrict__ y,
+    const int4* __restrict__ tiles, int ntiles, double* __restrict__ partial) {
+    __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double nrm = 0.0;
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int i0 = tiles[t], i1 = tiles[t + 1];
-        const int k0 = rp[i0], k1 = rp[i1];
-        if (k1 - k0 <= kTileNnz) {
+        const int4 d = tiles[t];
+        const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
+        if (k1 - k0 <= ITEMS * kBlock) {
+            int kk[ITEMS], c[ITEMS];
+            T a[ITEMS], x[ITEMS];
+            tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                const int k = k0 + it * kBlock + tid;
-                if (k < k1) s_prod[k - k0] = av[k] * (T)x[ci[k]];
-            }
-            __syncthreads();
+            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
             const int i = i0 + tid;
-            if (i < i1) {
+            const bool own = i < i1;
+            const int ic = own ? i : i1 - 1;
+            const int rb = rp[ic], re = rp[ic + 1];
+            const double bi = b ? b[ic] : 0.0;
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) x[it] = (T)xv[c[it]];
+            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            __syncthreads();
+            if (own) {
                 T s = 0;
-                const int e = rp[i + 1] - k0;
-                for (int k = rp[i] - k0; k < e; ++k) s += s_prod[k];
-                double v = b ? b[i] - (double)s : (double)s;
+                for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
+                const double v = b ? bi - (double)s : (double)s;
                 y[i] = (YT)v;
                 nrm += v * v;
             }
             __syncthreads();
         } else {
             T s = 0;
-            for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (T)x[ci[k]];
+            for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (T)xv[ci[k]];
             s = block_sum(s, s_red);
             if (tid == 0) {
-                double v = b ? b[i0] - (double)s : (double)s;
+                const double v = b ? b[i0] - (double)s : (double)s;
                 y[i0] = (YT)v;
                 nrm += v * v;
             }
@@ -306,14 +396,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
 // Krylov step, part 1: p = z + beta p_old (p = z on the first iteration),
 // q = A p, partials of p.q and p.r.  p_j is formed at the gather from z and
 // p_old (ping-pong buffers), with the same expression as for the owned rows.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
     const double* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
     double* __restrict__ q, const double* __restrict__ r,
-    const int* __restrict__ tiles, int ntiles, const SolveState* __restrict__ st,
+    const int4* __restrict__ tiles, int ntiles, const SolveState* __restrict__ st,
     double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
-    __shared__ double s_prod[kTileNnz];
+    __shared__ double s_prod[ITEMS * kBlock];
     __shared__ double s_red[kBlock / 64];
     const int tid = threadIdx.x;
     const bool first = st->first != 0;
@@ -321,29 +412,43 @@ __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const TileWalk w = tile_walk(ntiles);
     double pq = 0.0, pr = 0.0;
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int i0 = tiles[t], i1 = tiles[t + 1];
-        const int k0 = rp[i0], k1 = rp[i1];
-        if (k1 - k0 <= kTileNnz) {
+        const int4 d = tiles[t];
+        const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
+        if (k1 - k0 <= ITEMS * kBlock) {
+            int kk[ITEMS], c[ITEMS];
+            double a[ITEMS], x[ITEMS];
+            tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < kItems; ++it) {
-                const int k = k0 + it * kBlock + tid;
-                if (k < k1) {
-                    const int c = ci[k];
-                    const double pj = first ? z[c] : z[c] + beta * p_old[c];
-                    s_prod[k - k0] = av[k] * pj;
-                }
-            }
-            __syncthreads();
+            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
             const int i = i0 + tid;
-            if (i < i1) {
+            const bool own = i < i1;
+            const int ic = own ? i : i1 - 1;
+            const int rb = rp[ic], re = rp[ic + 1];
+            const double zi = z[ic], poi = p_old[ic], ri = r[ic];
+            if (first) {
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) x[it] = z[c[it]];
+            } else {
+                double zc[ITEMS], pc[ITEMS];
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) zc[it] = z[c[it]];
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) pc[it] = p_old[c[it]];
+#pragma unroll
+                for (int it = 0; it < ITEMS; ++it) x[it] = zc[it] + beta * pc[it];
+            }
+            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            __syncthreads();
+            if (own) {
                 double s = 0.0;
-                const int e = rp[i + 1] - k0;
-                for (int k = rp[i] - k0; k < e; ++k) s += s_prod[k];
-                const double pi = first ? z[i] : z[i] + beta * p_old[i];
+                for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
+                const double pi = first ? zi : zi + beta * poi;
                 p_new[i] = pi;
                 q[i] = s;
                 pq += pi * s;
-                pr += pi * r[i];
+                pr += pi * ri;
             }
             __syncthreads();
         } else {

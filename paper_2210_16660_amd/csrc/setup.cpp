@@ -460,33 +460,45 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
                 if (l + 1 < nl) L.p[ip] = hl.p[i];
             }
         });
-        // row tiles: <= kTileRows rows and <= kTileNnz entries, or a single long row
+        // tile capacity: the largest power of two <= kMaxItems with at least
+        // kTargetTiles tiles' worth of entries (small levels get small tiles)
+        {
+            const int64_t nnz = L.rp[n];
+            int items = kMaxItems;
+            while (items > 1 && (int64_t)items * kBlock * kTargetTiles > nnz) items /= 2;
+            L.items = items;
+        }
+        const int32_t cap = L.items * kBlock;
+        // row tiles: <= kTileRows rows and <= cap entries, or a single long row
         L.up_tiles.clear();
-        L.up_tiles.push_back(0);
         {
             int32_t start = 0;
             while (start < n) {
                 int32_t end = start + 1;
-                while (end < n && end - start < kTileRows && L.rp[end + 1] - L.rp[start] <= kTileNnz) ++end;
-                L.up_tiles.push_back(end);
+                while (end < n && end - start < kTileRows && L.rp[end + 1] - L.rp[start] <= cap) ++end;
+                L.up_tiles.insert(L.up_tiles.end(), {L.rp[start], L.rp[end], start, end});
                 start = end;
             }
         }
         // restriction tiles over coarse rows: the fine rows of <= kTileRows
-        // aggregates holding <= kTileNnz entries, or a single aggregate
+        // aggregates holding <= cap entries, or a single aggregate
         if (l + 1 < nl) {
             const int32_t nc = H.lev[l + 1].A.n;
             L.down_tiles.clear();
-            L.down_tiles.push_back(0);
             int32_t start = 0;
             while (start < nc) {
                 int32_t end = start + 1;
                 while (end < nc && end - start < kTileRows &&
-                       L.rp[L.aggptr[end + 1]] - L.rp[L.aggptr[start]] <= kTileNnz)
+                       L.rp[L.aggptr[end + 1]] - L.rp[L.aggptr[start]] <= cap)
                     ++end;
-                L.down_tiles.push_back(end);
+                L.down_tiles.insert(L.down_tiles.end(), {L.rp[L.aggptr[start]], L.rp[L.aggptr[end]], start, end});
                 start = end;
             }
+            // column-scaled values for the restriction pass: a_ij / d_j
+            L.vd.resize(L.v.size());
+            parallel_for(n, [&](int64_t ip) {
+                for (int32_t k = L.rp[ip]; k < L.rp[ip + 1]; ++k) L.vd[k] = L.v[k] * L.dinv[L.ci[k]];
+            });
         }
     }
     return out;

@@ -6,7 +6,7 @@ solved by FCG + the V-cycle to 1e-6; stores the iteration count, the
 recurrence residual and sampled entries of the solution, of the 5-iteration
 iterate and of one V-cycle application z = B b.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [N]     (N = 128 by default; 256 for the large case)
 """
 import json
 import os
@@ -22,7 +22,8 @@ from workloads import SplitMix64, q1_rhs, q1_stretched  # noqa: E402
 
 
 def main():
-    N, ratio, seed = 128, 1.05, 2
+    N = int(sys.argv[1]) if len(sys.argv) > 1 else 128
+    ratio, seed = 1.05, {128: 2, 256: 3}.get(N, 2)
     A = q1_stretched(N, ratio)
     b = q1_rhs(N, ratio, seed)
     O = oracle.Hierarchy(A)
@@ -31,6 +32,7 @@ def main():
     assert st == 0
     x5, _, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=5)
     z = O.vcycle(b)
+    del O
     out = {
         "source": "oracle/oracle.c via tests/golden/make_golden.py",
         "workload": {"q1_elements": N, "ratio": ratio, "rhs_seed": seed, "n": A.n, "nnz": A.nnz},
@@ -47,7 +49,7 @@ def main():
         "x5_sample": [float(v) for v in x5[idx]],
         "z_sample": [float(v) for v in z[idx]],
     }
-    with open(os.path.join(HERE, "q1_128_fcg.json"), "w") as f:
+    with open(os.path.join(HERE, f"q1_{N}_fcg.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(f"levels {O.nlevels}, iterations {it}, relres {rr:.3e}")
 
