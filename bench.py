@@ -8,10 +8,18 @@ hierarchy setup is timed separately.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 128]
                     [--precision f64|f32] [--no-cpu-baseline]
+    python bench.py --mode kernels [--reps R]   (level-0 kernels and a plain
+                    copy only, for hardware-counter runs under rocprofv3)
+
+The roofline "traffic" figure comes from profiles/traffic_q1_128.json (HBM
+bytes per launch from FETCH_SIZE/WRITE_SIZE counter runs, calibrated on a
+plain copy); it is reported only while the kernel source it was measured on
+is unchanged (SHA-256 of csrc/kernels.hpp), else null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +29,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNELS_SRC = os.path.join(ROOT, "paper_2210_16660_amd", "csrc", "kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_q1_128.json")
+
+
+def kernels_hash() -> str:
+    return hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+
+
+def traffic_for(kernel: str):
+    """Counter-measured HBM bytes per launch of `kernel`, if measured on this source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hpp_sha256") != kernels_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("traffic_bytes")
+
+
+def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
+    """Plain device-to-device copy (torch), GB/s counting read + write."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
 def main() -> int:
@@ -34,6 +78,8 @@ def main() -> int:
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels"])
+    ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -70,6 +116,20 @@ def main() -> int:
     b_d = torch.from_numpy(b).to(dev)
     x_d = torch.zeros(A.n, dtype=torch.float64, device=dev)
     opts = dict(tol=args.tol, krylov="fcg", precision=prec)
+
+    if args.mode == "kernels":
+        # one warm solve fills every work vector with real data, then each
+        # level-0 kernel and a plain copy are launched back to back
+        H.solve(b_d, x_d, **opts)
+        out = {}
+        for name, op in (("vcycle_down_l0", pamg.OP_DOWN), ("vcycle_up_l0", pamg.OP_UP),
+                         ("krylov_spmv_l0", pamg.OP_KRYLOV)):
+            ms, nb = H.time_op(op, 0, reps=args.reps, precision=pamg.PREC_F64 if op == pamg.OP_KRYLOV else prec)
+            out[name] = {"ms": ms, "bytes": nb, "GBps": nb / (ms * 1e-3) / 1e9}
+        gbs, cms = copy_bandwidth(torch, reps=args.reps)
+        out["copy_2GiB"] = {"ms": cms, "bytes": 2 * (1 << 31), "GBps": gbs}
+        print(json.dumps(out), flush=True)
+        return 0
 
     for _ in range(args.warmup):
         x_d.zero_()
@@ -111,6 +171,8 @@ def main() -> int:
         kern[name] = {"ms": ms, "bytes": nb, "GBps": nb / (ms * 1e-3) / 1e9}
     dom = max(kern, key=lambda k: kern[k]["ms"])
     dk = kern[dom]
+    copy_gbs, _ = copy_bandwidth(torch)
+    traffic = traffic_for(dom)
     log(f"V-cycle {v_ms:.3f} ms ({v_gbs:.0f} GB/s), SpMV {s_ms:.3f} ms ({s_gbs:.0f} GB/s); "
         + ", ".join(f"{k} {v['ms']:.4f} ms {v['GBps']:.0f} GB/s" for k, v in kern.items()))
 
@@ -145,6 +207,7 @@ def main() -> int:
         "spmv_pct_peak": round(100 * s_gbs / HBM_PEAK_GBS, 2),
         "kernels": {k: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GBps": round(v["GBps"], 1)}
                     for k, v in kern.items()},
+        "copy_GBps": round(copy_gbs, 1),
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
@@ -152,7 +215,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
         },
     }
 

@@ -85,6 +85,11 @@ inline int tile_grid(int ntiles) { return ntiles < kMaxGrid ? (ntiles > 0 ? ntil
 // then the gathers, then writes the products to LDS; the per-row data each
 // thread needs in phase 2 is loaded in the same batch.
 
+// Streamed matrix arrays are read exactly once per pass: non-temporal loads
+// keep them from evicting the gathered vectors from L2.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+
 template <int ITEMS>
 __device__ __forceinline__ void tile_slots(int k0, int k1, int (&kk)[ITEMS]) {
 #pragma unroll
@@ -125,9 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_down(
             T a[ITEMS], x[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) a[it] = ad[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&ad[kk[it]]);
             const int I = c0 + tid;
             const bool own = I < c1;
             const int Ic = own ? I : c1 - 1;
@@ -203,9 +208,9 @@ __global__ __launch_bounds__(kBlock) void k_up(
             T a[ITEMS], x[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
@@ -354,9 +359,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
             T a[ITEMS], x[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
@@ -419,9 +424,9 @@ __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             double a[ITEMS], x[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ci[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
 #pragma unroll
-            for (int it = 0; it < ITEMS; ++it) a[it] = av[kk[it]];
+            for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
