@@ -10,6 +10,13 @@ hierarchy setup is timed separately.  Prints one JSON line.
                     [--precision f64|f32] [--no-cpu-baseline]
     python bench.py --mode kernels [--reps R]   (level-0 kernels and a plain
                     copy only, for hardware-counter runs under rocprofv3)
+    python bench.py --mode batch [--steps K]    (16 right-hand sides from
+                    consecutive time steps: one batched solve vs 16 single
+                    solves, FP64 and FP32 V-cycles; prints its own JSON line)
+    python bench.py --mode serve [--requests R] (serving stream: variable-
+                    coefficient 7-point operators from a pool of 64, Poisson
+                    arrivals at 0.7 x the closed-loop capacity; p50/p99
+                    latency and solves/s; prints its own JSON line)
 
 The roofline "traffic" figure comes from profiles/traffic_q1_128.json (HBM
 bytes per launch from FETCH_SIZE/WRITE_SIZE counter runs, calibrated on a
@@ -78,7 +85,10 @@ def main() -> int:
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
 
@@ -93,16 +103,20 @@ def main() -> int:
     import torch
 
     import paper_2210_16660_amd as pamg
-    from workloads import q1_rhs, q1_stretched
+    from workloads import q1_rhs, q1_rhs_sequence, q1_stretched
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.mode == "serve":
+        return bench_serve(args, torch, np, pamg, log)
     t0 = time.perf_counter()
     A = q1_stretched(args.n, args.ratio)
     b = q1_rhs(args.n, args.ratio, 2)
     log(f"generated Q1 {args.n}^3: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
     prec = pamg.PREC_F32 if args.precision == "f32" else pamg.PREC_F64
+    if args.mode == "batch":
+        return bench_batch(args, A, torch, np, pamg, log)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
@@ -239,6 +253,163 @@ def main() -> int:
         log(f"oracle {per_iter_ms:.1f} ms/iteration")
     print(json.dumps(result), flush=True)
     return 0
+
+
+def bench_batch(args, A, torch, np, pamg, log) -> int:
+    """16 right-hand sides (a base divergence field plus successive 5%
+    perturbations, seed 4) solved as one batch versus one at a time."""
+    from workloads import q1_rhs_sequence
+    t0 = time.perf_counter()
+    Bm = q1_rhs_sequence(args.n, args.ratio, 4, 16).T.copy()        # (16, n)
+    log(f"16 right-hand sides in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    H = pamg.Hierarchy(A, build_f32=1)
+    B = torch.from_numpy(Bm).to(dev)
+    X = torch.zeros_like(B)
+    S = A.to_scipy()
+
+    def run_batch(prec):
+        X.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = H.solve_batch(B, X, tol=args.tol, precision=prec)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, infos
+
+    def run_single(prec):
+        x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for j in range(16):
+            x.zero_()
+            its.append(H.solve(B[j], x, tol=args.tol, precision=prec).iterations)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, its
+
+    res = {}
+    for name, prec in (("f64", pamg.PREC_F64), ("f32", pamg.PREC_F32)):
+        run_batch(prec)                      # first call builds the engine and runs the autotuner
+        run_single(prec)
+        tb = min(run_batch(prec)[0] for _ in range(max(1, args.steps // 4)))
+        _, infos = run_batch(prec)
+        Xh = X.cpu().numpy()
+        rel = max(float(np.linalg.norm(Bm[j] - S @ Xh[j]) / np.linalg.norm(Bm[j])) for j in range(16))
+        ts, its = min((run_single(prec) for _ in range(max(1, args.steps // 8))), key=lambda r: r[0])
+        res[name] = {"batch_ms": round(1e3 * tb, 3), "single16_ms": round(1e3 * ts, 3),
+                     "batch_solves_per_s": round(16 / tb, 2), "single_solves_per_s": round(16 / ts, 2),
+                     "batch_iterations": [i.iterations for i in infos], "single_iterations": its,
+                     "max_true_relres": rel}
+        log(f"{name}: batch {1e3 * tb:.1f} ms, 16 singles {1e3 * ts:.1f} ms, max true relres {rel:.2e}")
+    cfg = H.batch_config(pamg.PREC_F32)
+    out = {
+        "metric": "16-RHS batched FCG+AMG solve time to 1e-6 (solves/s)",
+        "value": res["f32"]["batch_solves_per_s"],
+        "unit": "solves/s",
+        "higher_is_better": True,
+        "config": {"workload": f"Q1 {args.n}^3 stretched, 16 RHS: base divergence field (seed 4) + 15 "
+                               f"successive 5% perturbations; batched FCG, FP32 V-cycle / FP64 outer",
+                   "n": A.n, "nnz": A.nnz},
+        "f64": res["f64"], "f32": res["f32"],
+        "speedup_batch_f32_vs_16_single_f64": round(res["f64"]["single16_ms"] / res["f32"]["batch_ms"], 3),
+        "speedup_batch_f32_vs_16_single_f32": round(res["f32"]["single16_ms"] / res["f32"]["batch_ms"], 3),
+        "speedup_batch_f64_vs_16_single_f64": round(res["f64"]["single16_ms"] / res["f64"]["batch_ms"], 3),
+        "autotuned_f32": cfg,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args, torch, np, pamg, log) -> int:
+    """Serving stream: a pool of variable-coefficient 7-point operators
+    -div(k grad p) on n^3 grids, n = floor(24 (161/24)^u) capped at 160
+    (log-uniform), k = exp(N(0,1)) per cell; each request picks an operator
+    uniformly and carries a U[-1,1] right-hand side; Poisson arrivals."""
+    import threading
+    from workloads import SplitMix64, varcoef7
+    rng = SplitMix64(5)
+    sizes = [min(160, int(np.floor(24 * (161 / 24) ** u))) for u in rng.uniform01(args.pool)]
+    t0 = time.perf_counter()
+    ops = [varcoef7(n, seed=5000 + k) for k, n in enumerate(sizes)]
+    picks = rng.integers(args.requests, 0, args.pool - 1)
+    log(f"{args.pool} operators (n^3, n in [{min(sizes)}, {max(sizes)}], {sum(A.n for A in ops)} dofs) "
+        f"in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    # right-hand sides, generated up front and kept on the device
+    t0 = time.perf_counter()
+    rhs = [torch.from_numpy(SplitMix64(50000 + t).uniform(ops[int(picks[t])].n)).to(dev) for t in range(args.requests)]
+    torch.cuda.synchronize()
+    log(f"{args.requests} right-hand sides in {time.perf_counter() - t0:.1f}s")
+    budget = int(args.budget_gib * (1 << 30))
+
+    def run(count, arrivals):
+        S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32)
+        xs = [torch.zeros(ops[int(picks[t])].n, dtype=torch.float64, device=dev) for t in range(count)]
+        torch.cuda.synchronize()
+        comps = []
+        stop = threading.Event()
+
+        def poller():
+            while not stop.is_set() or len(comps) < count:
+                comps.extend(S.poll())
+                if len(comps) >= count:
+                    break
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t_start = time.perf_counter()
+        for t in range(count):
+            if arrivals is not None:
+                wait = t_start + arrivals[t] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            k = int(picks[t])
+            S.submit(k, ops[k], rhs[t], xs[t], tol=1e-6, tag=t)
+        stop.set()
+        th.join()
+        wall = time.perf_counter() - t_start
+        st = S.stats()
+        S.close()
+        return comps, wall, st
+
+    # closed loop: everything queued at once -> capacity
+    ncl = min(args.requests, 500)
+    comps, wall, st = run(ncl, None)
+    capacity = ncl / wall
+    log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s "
+        f"({st.setups} setups, {st.evictions} evictions)")
+    lam = 0.7 * capacity
+    arrivals = np.cumsum(SplitMix64(55).exponential(args.requests, lam))
+    comps, wall, st = run(args.requests, arrivals)
+    lat = np.array([c.latency_ms for c in comps])
+    ok = sum(1 for c in comps if c.status == pamg.OK)
+    its = np.array([c.iterations for c in comps])
+    worst = max(c.relres_true for c in comps)
+    out = {
+        "metric": "serving: p50/p99 latency and solves/s at 1e-6",
+        "value": round(len(comps) / wall, 2),
+        "unit": "solves/s",
+        "higher_is_better": True,
+        "config": {"workload": f"{args.requests} requests, Poisson arrivals at lambda = 0.7 x closed-loop capacity; "
+                               f"variable-coefficient 7-point operators (pool of {args.pool}, n^3 with n log-uniform "
+                               f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "
+                               f"FP32 V-cycle / FP64 FCG, accepted on the true residual",
+                   "hbm_budget_gib": args.budget_gib, "block_iters": 4},
+        "lambda_per_s": round(lam, 2),
+        "closed_loop_capacity_per_s": round(capacity, 2),
+        "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
+        "mean_latency_ms": round(float(lat.mean()), 3),
+        "completed_ok": ok,
+        "iterations_median": int(np.median(its)),
+        "max_true_relres": worst,
+        "setups": st.setups, "evictions": st.evictions, "rejected": st.rejected,
+        "aggregate_GBps": round(st.algorithmic_bytes / wall / 1e9, 1),
+        "wall_s": round(wall, 2),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok == len(comps) else 1
 
 
 if __name__ == "__main__":

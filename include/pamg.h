@@ -135,6 +135,30 @@ int pamg_hierarchy_level_csr(const pamg_hierarchy *h, int32_t level, int32_t *ro
 int pamg_solve(pamg_hierarchy *h, const double *b_dev, double *x_dev, const pamg_solve_opts *opts,
                void *stream, pamg_solve_info *info);
 
+/* Solve A X = B for 1 <= nrhs <= 16 right-hand sides at once (successive time
+ * steps, or independent requests on one operator; Sec. 2: one matrix, many
+ * solves).  Column j of B is at B_dev + j*ldb, of X at X_dev + j*ldx (device,
+ * caller numbering, ldb, ldx >= n).  Each column runs its own FCG (or PCG)
+ * recurrence with its own step lengths and stopping test; every pass over a
+ * level's matrix serves all columns.  x0 = 0 (use_x0 must be 0).  A column's
+ * result does not depend on the other columns.  infos: nrhs entries.  The
+ * return value is the worst column status. */
+int pamg_solve_batch(pamg_hierarchy *h, int32_t nrhs, const double *B_dev, int64_t ldb, double *X_dev,
+                     int64_t ldx, const pamg_solve_opts *opts, void *stream, pamg_solve_info *infos);
+
+/* Batched operators for parity checks: op = PAMG_OP_COARSE (16 vectors of
+ * the coarsest level, A_L^-1 applied on the matrix cores in FP64) or
+ * PAMG_OP_VCYCLE (16 level-0 vectors through the batched V-cycle).  in_dev,
+ * out_dev: 16 FP64 vectors, vector c at ptr + c*n_level, canonical numbering. */
+int pamg_debug_apply_batch(pamg_hierarchy *h, int32_t op, int32_t precision, const double *in_dev, double *out_dev,
+                           void *stream);
+
+/* Kernel variants the multi-RHS autotuner chose for each level (timed on the
+ * real hierarchy the first time a batch of this precision runs): cfg[4l+0..3]
+ * = down-sweep unroll, down-sweep columns per lane, up-sweep unroll, up-sweep
+ * columns per lane, for l = 0 .. levels-2 (cfg holds 4*(levels-1) entries). */
+int pamg_batch_config(pamg_hierarchy *h, int32_t precision, int32_t *cfg);
+
 /* Single operators of the V-cycle, for parity checks.  Vectors are FP64 in
  * canonical level numbering.
  *   PAMG_OP_SPMV     out = A_l in0
@@ -165,6 +189,74 @@ int pamg_time_kernels(pamg_hierarchy *h, int32_t precision, const double *r_dev,
 enum { PAMG_OP_KRYLOV = 6 };
 int pamg_time_op(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision, int32_t reps, void *stream,
                  double *ms_per_launch, uint64_t *bytes);
+
+/* ---------------------------------------------------------------- serving
+ *
+ * A request loop on one GPU for many pressure solves (the paper's setting:
+ * one operator, many solves, Sec. 2; hierarchy reuse, Sec. 4).  A scheduler
+ * thread owns all GPU work.  An operator (identified by a caller-chosen key)
+ * gets its hierarchy built the first time a request names it, if its device
+ * bytes fit the HBM budget next to the operators already cached (idle ones
+ * are evicted least-recently-used first); otherwise the request waits.  Every
+ * cached operator batches up to 16 requests as independent columns; waiting
+ * requests join between iteration blocks and finished ones retire at once.
+ * Blocks of all operators are launched before any is waited on, so their
+ * work overlaps.  A request's result does not depend on what it was batched
+ * with.  Calls that overlap on one server from several threads are safe. */
+typedef struct pamg_server pamg_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;   /* device bytes for cached hierarchies + work vectors (default 64 GiB) */
+    int32_t block_iters;         /* iterations per block between join/retire points (default 4, made even) */
+    int32_t precision;           /* V-cycle precision, default PAMG_PREC_F32 (FP64 recurrences; a
+                                    column is accepted on its true FP64 residual) */
+    int32_t reserved[8];
+} pamg_server_opts;
+
+typedef struct {
+    uint64_t op_key;             /* operator identity chosen by the caller */
+    const pamg_csr *A;           /* host CSR; read only if op_key is not cached (else may be NULL);
+                                    must stay valid until the request completes */
+    const double *b_dev;         /* device right-hand side (caller numbering); valid until completion */
+    double *x_dev;               /* device result (caller numbering); written before completion */
+    double tol;                  /* relative residual target */
+    int32_t maxit;               /* <= 0: 1000 */
+    int32_t reserved;
+    uint64_t tag;                /* returned in the completion */
+} pamg_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;              /* pamg_status; PAMG_E_BUSY: the operator alone exceeds the budget */
+    int32_t iterations;
+    double relres;               /* recurrence residual / ||b|| */
+    double relres_true;          /* true residual / ||b|| (FP32 V-cycle), else -1 */
+    double queue_ms;             /* submit -> column assigned */
+    double latency_ms;           /* submit -> result written */
+} pamg_completion;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;
+    uint64_t bytes_in_use, hbm_budget_bytes;
+    int32_t cached_operators, active_columns, pending, pad;
+    uint64_t setups, evictions, blocks;
+    double busy_ms;              /* scheduler time spent in ticks */
+    uint64_t algorithmic_bytes;  /* HBM bytes the executed iterations had to move */
+} pamg_server_stats;
+
+int pamg_server_opts_default(pamg_server_opts *o);
+/* The bytes admission charges for an uncached operator before its hierarchy
+ * exists: an upper estimate of hierarchy + 16-column engine for A (host CSR)
+ * at the given V-cycle precision.  Once built, the exact figure is used. */
+int pamg_server_estimate_bytes(const pamg_csr *A, int32_t precision, uint64_t *out);
+int pamg_server_create(const pamg_server_opts *opts, pamg_server **out);
+/* Queue a request (copied).  Errors: INVALID (null pointers, bad tol). */
+int pamg_server_submit(pamg_server *s, const pamg_request *req);
+/* Move up to `max` completions into out (non-blocking); *n_out = count. */
+int pamg_server_poll(pamg_server *s, pamg_completion *out, int32_t max, int32_t *n_out);
+int pamg_server_stats_get(pamg_server *s, pamg_server_stats *out);
+/* Finish every queued and running request, then free all server resources. */
+int pamg_server_destroy(pamg_server *s);
 
 /* Thread-local description of the last failure on this thread. */
 const char *pamg_last_error(void);

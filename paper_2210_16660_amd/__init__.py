@@ -52,6 +52,29 @@ class pamg_hier_info(C.Structure):
                 ("spmv_bytes", C.c_uint64)]
 
 
+class pamg_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("block_iters", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32 * 8)]
+
+
+class pamg_request(C.Structure):
+    _fields_ = [("op_key", C.c_uint64), ("A", C.POINTER(pamg_csr)), ("b_dev", C.c_void_p), ("x_dev", C.c_void_p),
+                ("tol", C.c_double), ("maxit", C.c_int32), ("reserved", C.c_int32), ("tag", C.c_uint64)]
+
+
+class pamg_completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("iterations", C.c_int32), ("relres", C.c_double),
+                ("relres_true", C.c_double), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class pamg_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("bytes_in_use", C.c_uint64), ("hbm_budget_bytes", C.c_uint64), ("cached_operators", C.c_int32),
+                ("active_columns", C.c_int32), ("pending", C.c_int32), ("pad", C.c_int32), ("setups", C.c_uint64),
+                ("evictions", C.c_uint64), ("blocks", C.c_uint64), ("busy_ms", C.c_double),
+                ("algorithmic_bytes", C.c_uint64)]
+
+
 # every entry point declared in include/pamg.h: name -> (restype, argtypes)
 _VP = C.c_void_p
 SIGNATURES = {
@@ -64,11 +87,22 @@ SIGNATURES = {
     "pamg_hierarchy_level_csr": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                            C.POINTER(C.c_double)]),
     "pamg_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pamg_solve_opts), _VP, C.POINTER(pamg_solve_info)]),
+    "pamg_solve_batch": (C.c_int, [_VP, C.c_int32, _VP, C.c_int64, _VP, C.c_int64, C.POINTER(pamg_solve_opts), _VP,
+                                   C.POINTER(pamg_solve_info)]),
+    "pamg_batch_config": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
+    "pamg_debug_apply_batch": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP]),
     "pamg_debug_apply": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP]),
     "pamg_time_kernels": (C.c_int, [_VP, C.c_int32, _VP, C.c_int32, _VP, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
     "pamg_time_op": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _VP, C.POINTER(C.c_double),
                                C.POINTER(C.c_uint64)]),
+    "pamg_server_opts_default": (C.c_int, [C.POINTER(pamg_server_opts)]),
+    "pamg_server_estimate_bytes": (C.c_int, [C.POINTER(pamg_csr), C.c_int32, C.POINTER(C.c_uint64)]),
+    "pamg_server_create": (C.c_int, [C.POINTER(pamg_server_opts), C.POINTER(_VP)]),
+    "pamg_server_submit": (C.c_int, [_VP, C.POINTER(pamg_request)]),
+    "pamg_server_poll": (C.c_int, [_VP, C.POINTER(pamg_completion), C.c_int32, C.POINTER(C.c_int32)]),
+    "pamg_server_stats_get": (C.c_int, [_VP, C.POINTER(pamg_server_stats)]),
+    "pamg_server_destroy": (C.c_int, [_VP]),
     "pamg_last_error": (C.c_char_p, []),
 }
 
@@ -204,6 +238,30 @@ class Hierarchy:
                "pamg_solve", allow=(OK, NOT_CONVERGED))
         return info
 
+    def solve_batch(self, B, X, stream=None, **kw):
+        """Solve A X = B for a (nrhs, n) float64 device tensor B (row j = right-hand
+        side j, i.e. column-major n x nrhs with ld = n); X has the same shape.
+        Returns the list of per-column info structs."""
+        nrhs = int(B.shape[0])
+        ld = int(B.shape[1])
+        o = solve_opts(**kw)
+        infos = (pamg_solve_info * nrhs)()
+        _check(lib().pamg_solve_batch(self._h, nrhs, _ptr(B), ld, _ptr(X), int(X.shape[1]), C.byref(o),
+                                      _stream(stream), infos), "pamg_solve_batch", allow=(OK, NOT_CONVERGED))
+        return list(infos)
+
+    def debug_apply_batch(self, op: int, in16, out16, precision: int = PREC_F64, stream=None):
+        """Batched COARSE or VCYCLE on a (16, n_level) device tensor."""
+        _check(lib().pamg_debug_apply_batch(self._h, op, precision, _ptr(in16), _ptr(out16), _stream(stream)),
+               "pamg_debug_apply_batch")
+
+    def batch_config(self, precision: int = PREC_F64):
+        """Autotuned (down unroll, down cols/lane, up unroll, up cols/lane) per level."""
+        L = self.levels - 1
+        cfg = (C.c_int32 * (4 * max(L, 1)))()
+        _check(lib().pamg_batch_config(self._h, precision, cfg), "pamg_batch_config")
+        return [tuple(cfg[4 * l:4 * l + 4]) for l in range(L)]
+
     def debug_apply(self, op: int, level: int, in0, out, in1=None, precision: int = PREC_F64, stream=None):
         _check(lib().pamg_debug_apply(self._h, op, level, precision, _ptr(in0), _ptr(in1), _ptr(out),
                                       _stream(stream)), "pamg_debug_apply")
@@ -225,3 +283,75 @@ class Hierarchy:
 
 def setup(A, **kw) -> Hierarchy:
     return Hierarchy(A, **kw)
+
+
+class _HostCSR:
+    """A CSR kept alive (and its pamg_csr view) while a server may read it."""
+
+    def __init__(self, A):
+        self.rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+        self.ci = np.ascontiguousarray(A.col, dtype=np.int32)
+        self.v = np.ascontiguousarray(A.val, dtype=np.float64)
+        self.csr = pamg_csr(int(A.n), int(self.rp[-1]), self.rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                            self.ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                            self.v.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def server_estimate_bytes(A, precision: int = PREC_F32) -> int:
+    """Admission charge of an uncached operator (host CSR A)."""
+    hc = _HostCSR(A)
+    out = C.c_uint64()
+    _check(lib().pamg_server_estimate_bytes(C.byref(hc.csr), int(precision), C.byref(out)),
+           "pamg_server_estimate_bytes")
+    return out.value
+
+
+class Server:
+    """Continuous-batching solve server (pamg_server_*).  Keeps the operator
+    CSRs and the device vectors of outstanding requests alive until their
+    completions are polled."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32):
+        o = pamg_server_opts()
+        _check(lib().pamg_server_opts_default(C.byref(o)), "pamg_server_opts_default")
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.block_iters = int(block_iters)
+        o.precision = int(precision)
+        h = C.c_void_p()
+        _check(lib().pamg_server_create(C.byref(o), C.byref(h)), "pamg_server_create")
+        self._h = h
+        self._ops = {}
+        self._live = {}
+
+    def submit(self, op_key: int, A, b, x, tol: float = 1e-6, tag: int = 0, maxit: int = 1000):
+        """Queue a solve of A x = b (device tensors b, x).  A (a CSR) is needed the
+        first time op_key is used; later requests may pass None."""
+        if A is not None and op_key not in self._ops:
+            self._ops[op_key] = _HostCSR(A)
+        hc = self._ops.get(op_key)
+        req = pamg_request(int(op_key), C.pointer(hc.csr) if hc is not None else None, _ptr(b), _ptr(x), float(tol),
+                           int(maxit), 0, int(tag))
+        self._live[int(tag)] = (b, x)
+        _check(lib().pamg_server_submit(self._h, C.byref(req)), "pamg_server_submit")
+
+    def poll(self, max_n: int = 256):
+        out = (pamg_completion * max_n)()
+        n = C.c_int32()
+        _check(lib().pamg_server_poll(self._h, out, max_n, C.byref(n)), "pamg_server_poll")
+        res = [out[i] for i in range(n.value)]
+        for c in res:
+            self._live.pop(int(c.tag), None)
+        return res
+
+    def stats(self) -> pamg_server_stats:
+        s = pamg_server_stats()
+        _check(lib().pamg_server_stats_get(self._h, C.byref(s)), "pamg_server_stats_get")
+        return s
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.pamg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -33,12 +33,18 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     setup_o = os.path.join(BUILD, "setup.o")
     device_o = os.path.join(BUILD, "device.o")
+    batch_o = os.path.join(BUILD, "batch.o")
+    serve_o = os.path.join(BUILD, "serve.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-pthread",
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "device.hip"), "-o", device_o])
+    _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
+          "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "batch.hip"), "-o", batch_o])
+    _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
+          "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "serve.hip"), "-o", serve_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", device_o, setup_o, "-o", tmp, "-pthread"])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", device_o, batch_o, serve_o, setup_o, "-o", tmp, "-pthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -10,71 +10,9 @@
 #include <mutex>
 #include <type_traits>
 
-#include "kernels.hpp"
-
-#define HIP_CHECK(call)                                                                              \
-    do {                                                                                             \
-        hipError_t e_ = (call);                                                                      \
-        if (e_ != hipSuccess)                                                                        \
-            throw ::pamg::Error(e_ == hipErrorOutOfMemory ? PAMG_E_OOM : PAMG_E_DEVICE,              \
-                                std::string(#call) + ": " + hipGetErrorString(e_));                  \
-    } while (0)
+#include "hier.hpp"
 
 namespace pamg {
-
-template <typename T>
-struct DevVals {
-    bool built = false;
-    std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
-    std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
-    T* ainv = nullptr;                // dense A_L^{-1}
-    T* dbg_in = nullptr;              // scratch in this precision (max n)
-    T* dbg_in2 = nullptr;
-};
-
-struct DevLevelIdx {
-    int n = 0, nc = 0, items = 8;
-    long long nnz = 0;
-    int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *perm = nullptr, *iperm = nullptr;
-    const int4 *down_tiles = nullptr, *up_tiles = nullptr;
-    int n_down = 0, n_up = 0;
-};
-
-}  // namespace pamg
-
-struct pamg_hierarchy {
-    int device = 0;
-    int L = 0;
-    bool host_only = false;
-    std::vector<pamg::DevLevelIdx> idx;
-    pamg::DevVals<double> f64;
-    pamg::DevVals<float> f32;
-    double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *b = nullptr;
-    double *dbg0 = nullptr, *dbg1 = nullptr, *dbg2 = nullptr;
-    double *partial = nullptr, *partial_b = nullptr;
-    int* zero_flag = nullptr;
-    pamg::SolveState* st = nullptr;
-    pamg::SolveState* st_host = nullptr;   // pinned
-    hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    int graph_k[2][2] = {{0, 0}, {0, 0}};
-    std::vector<void*> allocs;
-    pamg::HostHierarchy host;
-    pamg_hier_info info{};
-    std::mutex mu;
-};
-
-namespace pamg {
-
-template <typename T>
-static T* dalloc(pamg_hierarchy* h, size_t count) {
-    void* p = nullptr;
-    if (count == 0) count = 1;
-    HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
-    h->allocs.push_back(p);
-    h->info.device_bytes += count * sizeof(T);
-    return static_cast<T*>(p);
-}
 
 template <typename T, typename S>
 static T* upload(pamg_hierarchy* h, const std::vector<S>& src, hipStream_t s) {
@@ -89,12 +27,6 @@ static T* upload(pamg_hierarchy* h, const std::vector<S>& src, hipStream_t s) {
         HIP_CHECK(hipStreamSynchronize(s));
     }
     return d;
-}
-
-static inline int vec_grid(long long n) {
-    long long g = (n + kBlock - 1) / kBlock;
-    if (g > kMaxGrid) g = kMaxGrid;
-    return g < 1 ? 1 : (int)g;
 }
 
 template <typename T>
@@ -202,6 +134,8 @@ void destroy_hierarchy(pamg_hierarchy* h) {
         return;
     }
     (void)hipDeviceSynchronize();
+    h->batch[0].reset();
+    h->batch[1].reset();
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             if (h->graph[a][b]) (void)hipGraphExecDestroy(h->graph[a][b]);
@@ -453,7 +387,7 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
     }
 }
 
-static void require_device(const pamg_hierarchy* h) {
+void require_device(const pamg_hierarchy* h) {
     if (h->host_only) throw Error(PAMG_E_INVALID, "hierarchy was built with host_only=1");
 }
 
@@ -702,22 +636,6 @@ pamg_hierarchy* new_hierarchy(bool host_only) {
 
 namespace {
 thread_local std::string g_last_error;
-
-template <class F>
-int guarded(F&& f) {
-    try {
-        return f();
-    } catch (const pamg::Error& e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return PAMG_E_OOM;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return PAMG_E_DEVICE;
-    }
-}
 }  // namespace
 
 namespace pamg {
@@ -754,7 +672,7 @@ int pamg_solve_opts_default(pamg_solve_opts* o) {
 }
 
 int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!A || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
         *out = nullptr;
         pamg_params prm;
@@ -797,7 +715,7 @@ int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_
 }
 
 int pamg_hierarchy_destroy(pamg_hierarchy* h) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (h) pamg::destroy_hierarchy(h);
         return PAMG_OK;
     });
@@ -810,7 +728,7 @@ int pamg_hierarchy_info(const pamg_hierarchy* h, pamg_hier_info* out) {
 }
 
 int pamg_hierarchy_aggregates(const pamg_hierarchy* h, int32_t level, int32_t* agg) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !agg) throw pamg::Error(PAMG_E_INVALID, "null argument");
         if (level < 0 || level >= h->L) throw pamg::Error(PAMG_E_INVALID, "level must be in [0, levels-2]");
         const auto& a = h->host.lev[level].agg;
@@ -820,7 +738,7 @@ int pamg_hierarchy_aggregates(const pamg_hierarchy* h, int32_t level, int32_t* a
 }
 
 int pamg_hierarchy_level_csr(const pamg_hierarchy* h, int32_t level, int32_t* rp, int32_t* ci, double* v) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !rp || !ci || !v) throw pamg::Error(PAMG_E_INVALID, "null argument");
         if (level < 0 || level > h->L) throw pamg::Error(PAMG_E_INVALID, "level out of range");
         const auto& A = h->host.lev[level].A;
@@ -833,7 +751,7 @@ int pamg_hierarchy_level_csr(const pamg_hierarchy* h, int32_t level, int32_t* rp
 
 int pamg_solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts* opts, void* stream,
                pamg_solve_info* info) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !b || !x) throw pamg::Error(PAMG_E_INVALID, "null argument");
         pamg_solve_opts o;
         if (opts) o = *opts; else pamg_solve_opts_default(&o);
@@ -845,7 +763,7 @@ int pamg_solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_o
 
 int pamg_debug_apply(pamg_hierarchy* h, int32_t op, int32_t level, int32_t precision, const double* in0,
                      const double* in1, double* out, void* stream) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !in0 || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
         if ((op == PAMG_OP_UP || op == PAMG_OP_PROLONG) && !in1) throw pamg::Error(PAMG_E_INVALID, "in1 required");
         return pamg::debug_apply(h, op, level, precision, in0, in1, out, (hipStream_t)stream);
@@ -854,7 +772,7 @@ int pamg_debug_apply(pamg_hierarchy* h, int32_t op, int32_t level, int32_t preci
 
 int pamg_time_kernels(pamg_hierarchy* h, int32_t precision, const double* r, int32_t reps, void* stream,
                       double* vms, double* sms) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !r || !vms || !sms) throw pamg::Error(PAMG_E_INVALID, "null argument");
         return pamg::time_kernels(h, precision, r, reps, (hipStream_t)stream, vms, sms);
     });
@@ -862,7 +780,7 @@ int pamg_time_kernels(pamg_hierarchy* h, int32_t precision, const double* r, int
 
 int pamg_time_op(pamg_hierarchy* h, int32_t op, int32_t level, int32_t precision, int32_t reps, void* stream,
                  double* ms, uint64_t* bytes) {
-    return guarded([&]() -> int {
+    return pamg::guarded([&]() -> int {
         if (!h || !ms || !bytes) throw pamg::Error(PAMG_E_INVALID, "null argument");
         return pamg::time_op(h, op, level, precision, reps, (hipStream_t)stream, ms, bytes);
     });

@@ -1,0 +1,110 @@
+// Internal device-side structures shared by the single- and multi-RHS drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+#define HIP_CHECK(call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            throw ::pamg::Error(e_ == hipErrorOutOfMemory ? PAMG_E_OOM : PAMG_E_DEVICE,              \
+                                std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+namespace pamg {
+
+template <typename T>
+struct DevVals {
+    bool built = false;
+    std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
+    std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
+    T* ainv = nullptr;                // dense A_L^{-1}
+    T* dbg_in = nullptr;              // scratch in this precision (max n)
+    T* dbg_in2 = nullptr;
+};
+
+struct BatchEngine;
+void destroy_batch(BatchEngine* b);
+struct BatchDeleter {
+    void operator()(BatchEngine* b) const { destroy_batch(b); }
+};
+
+struct DevLevelIdx {
+    int n = 0, nc = 0, items = 8;
+    long long nnz = 0;
+    int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *perm = nullptr, *iperm = nullptr;
+    const int4 *down_tiles = nullptr, *up_tiles = nullptr;
+    int n_down = 0, n_up = 0;
+};
+
+}  // namespace pamg
+
+struct pamg_hierarchy {
+    int device = 0;
+    int L = 0;
+    bool host_only = false;
+    std::vector<pamg::DevLevelIdx> idx;
+    pamg::DevVals<double> f64;
+    pamg::DevVals<float> f32;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *b = nullptr;
+    double *dbg0 = nullptr, *dbg1 = nullptr, *dbg2 = nullptr;
+    double *partial = nullptr, *partial_b = nullptr;
+    int* zero_flag = nullptr;
+    pamg::SolveState* st = nullptr;
+    pamg::SolveState* st_host = nullptr;   // pinned
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int graph_k[2][2] = {{0, 0}, {0, 0}};
+    std::vector<void*> allocs;
+    pamg::HostHierarchy host;
+    pamg_hier_info info{};
+    std::mutex mu;
+    std::unique_ptr<pamg::BatchEngine, pamg::BatchDeleter> batch[2];   // multi-RHS workspaces (FP64 / FP32 V-cycle)
+};
+
+namespace pamg {
+
+template <typename T>
+inline T* dalloc(pamg_hierarchy* h, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
+    h->allocs.push_back(p);
+    h->info.device_bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+}
+
+inline int vec_grid(long long n) {
+    long long g = (n + kBlock - 1) / kBlock;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return g < 1 ? 1 : (int)g;
+}
+void require_device(const pamg_hierarchy* h);
+}  // namespace pamg
+
+namespace pamg {
+// Run an entry point body: C++ exceptions become status codes plus the
+// thread-local message.
+template <class F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return PAMG_E_OOM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return PAMG_E_DEVICE;
+    }
+}
+}  // namespace pamg

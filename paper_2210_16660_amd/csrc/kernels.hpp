@@ -51,6 +51,15 @@ __device__ __forceinline__ T block_sum(T v, T* s_red) {
     return t;
 }
 
+// zp = d r + p z (pre-smoothed value plus prolongated correction) with an
+// explicit fused multiply-add: the product d r is rounded, p z is fused.
+// Spelled out so that every kernel variant rounds it identically.
+template <typename T>
+__device__ __forceinline__ T prolong_value(T d, T r, T p, T z) {
+    const T dr = d * r;
+    return fma(p, z, dr);
+}
+
 // Tiles handled by this workgroup: first, first+stride, ... < end.
 struct TileWalk {
     int first, stride, end;
@@ -113,7 +122,7 @@ __device__ __forceinline__ void tile_store(int k0, int k1, const T (&a)[ITEMS], 
 //   z = D^-1 r;  t = r - A z = r - (A D^-1) r;  rc[I] = sum_{i in G_I} p_i t_i
 // `ad` holds the column-scaled values a_ij / d_j, so one gather of r suffices.
 template <int ITEMS, typename T, typename RT>
-__global__ __launch_bounds__(kBlock) void k_down(
+static __global__ __launch_bounds__(kBlock) void k_down(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ ad,
     const RT* __restrict__ r, const T* __restrict__ p, const int* __restrict__ aggptr,
     const int4* __restrict__ tiles, int ntiles, T* __restrict__ rc, const int* __restrict__ done) {
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_down(
 //          for the members m of coarse row I (= this level's row);
 //   l = 0: write z (FP64) and accumulate the partial of z . dv.
 template <int ITEMS, typename T, typename RT, typename RTF, bool TO_OUT>
-__global__ __launch_bounds__(kBlock) void k_up(
+static __global__ __launch_bounds__(kBlock) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
     const int4* __restrict__ tiles, int ntiles,
@@ -239,9 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_up(
                     z_out[i] = (double)z;
                     dot += (double)z * dvi;
                 } else {
-                    zp_f[a0] = df0 * rf0 + pf0 * z;
-                    if (a1 - a0 >= 2) zp_f[a0 + 1] = df1 * rf1 + pf1 * z;
-                    for (int m = a0 + 2; m < a1; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
+                    zp_f[a0] = prolong_value(df0, rf0, pf0, z);
+                    if (a1 - a0 >= 2) zp_f[a0 + 1] = prolong_value(df1, rf1, pf1, z);
+                    for (int m = a0 + 2; m < a1; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
                 }
             }
             __syncthreads();
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_up(
                     z_out[i0] = (double)z;
                     dot += (double)z * dv[i0];
                 } else {
-                    for (int m = aggptr_f[i0]; m < aggptr_f[i0 + 1]; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
+                    for (int m = aggptr_f[i0]; m < aggptr_f[i0 + 1]; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
                 }
             }
             __syncthreads();
@@ -277,7 +286,7 @@ constexpr int kCoarseThreads = 1024;
 inline int coarse_groups(int nL) { return nL <= 256 ? 16 : (nL <= 1024 ? 4 : 1); }
 
 template <typename T, typename RT, typename RTF, bool TO_OUT>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse(
+static __global__ __launch_bounds__(kCoarseThreads) void k_coarse(
     int nL, int G, const T* __restrict__ ainv, const RT* __restrict__ r,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
     const T* __restrict__ p_f, T* __restrict__ zp_f,
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(
             z_out[I] = (double)z;
             dot += (double)z * dv[I];
         } else {
-            for (int m = aggptr_f[I]; m < aggptr_f[I + 1]; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
+            for (int m = aggptr_f[I]; m < aggptr_f[I + 1]; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
         }
     }
     if constexpr (TO_OUT) {
@@ -327,13 +336,13 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(
 // Prolongation alone (parity checks): zp_f[m] = dinv_f[m] r_f[m] + p_f[m] e[I]
 // for the members m of every coarse row I.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __restrict__ e, const int* __restrict__ aggptr,
+static __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __restrict__ e, const int* __restrict__ aggptr,
                                                     const double* __restrict__ r_f, const T* __restrict__ dinv_f,
                                                     const T* __restrict__ p_f, T* __restrict__ zp_f) {
     const int stride = gridDim.x * kBlock;
     for (int I = blockIdx.x * kBlock + threadIdx.x; I < nc; I += stride) {
         const T z = e[I];
-        for (int m = aggptr[I]; m < aggptr[I + 1]; ++m) zp_f[m] = dinv_f[m] * (T)r_f[m] + p_f[m] * z;
+        for (int m = aggptr[I]; m < aggptr[I + 1]; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
     }
 }
 
@@ -341,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __restrict_
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
 // y . y.
 template <int ITEMS, typename T, typename XT, typename YT>
-__global__ __launch_bounds__(kBlock) void k_spmv(
+static __global__ __launch_bounds__(kBlock) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const XT* __restrict__ xv, const double* __restrict__ b, YT* __restrict__ y,
     const int4* __restrict__ tiles, int ntiles, double* __restrict__ partial) {
@@ -402,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
 // q = A p, partials of p.q and p.r.  p_j is formed at the gather from z and
 // p_old (ping-pong buffers), with the same expression as for the owned rows.
 template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_krylov_pq(
+static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
     const double* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
     double* __restrict__ q, const double* __restrict__ r,
@@ -484,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_krylov_pq(
 }
 
 // Krylov step, part 2: x += alpha p, r -= alpha q, partial of r.r.
-__global__ __launch_bounds__(kBlock) void k_krylov_update(
+static __global__ __launch_bounds__(kBlock) void k_krylov_update(
     int n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, const SolveState* __restrict__ st, double* __restrict__ partial,
     const int* __restrict__ done) {
@@ -512,7 +521,7 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 }
 
 // beta (and rho for PCG) from the partials of z.dv written by the level-0 up-sweep.
-__global__ __launch_bounds__(kBlock) void k_fin_beta(SolveState* __restrict__ st, const double* __restrict__ partial,
+static __global__ __launch_bounds__(kBlock) void k_fin_beta(SolveState* __restrict__ st, const double* __restrict__ partial,
                                                      int count) {
     if (st->done) return;
     __shared__ double s_red[kBlock / 64];
@@ -528,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(SolveState* __restrict__ st
 }
 
 // delta = p.q, gamma = p.r, alpha.
-__global__ __launch_bounds__(kBlock) void k_fin_alpha(SolveState* __restrict__ st, const double* __restrict__ partial,
+static __global__ __launch_bounds__(kBlock) void k_fin_alpha(SolveState* __restrict__ st, const double* __restrict__ partial,
                                                       int count) {
     if (st->done) return;
     __shared__ double s_red[kBlock / 64];
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(SolveState* __restrict__ s
 }
 
 // ||r||, iteration count and the stopping test ||r|| <= tol ||b||.
-__global__ __launch_bounds__(kBlock) void k_fin_norm(SolveState* __restrict__ st, const double* __restrict__ partial,
+static __global__ __launch_bounds__(kBlock) void k_fin_norm(SolveState* __restrict__ st, const double* __restrict__ partial,
                                                      int count) {
     if (st->done) return;
     __shared__ double s_red[kBlock / 64];
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_norm(SolveState* __restrict__ st
 
 // Start of a solve (or restart): ||b||, ||r|| from partials (b.b in bb_part,
 // r.r in rr_part); sets the stopping state.  bb_count == 0: keep st->bnorm.
-__global__ __launch_bounds__(kBlock) void k_fin_init(SolveState* __restrict__ st, const double* __restrict__ bb_part,
+static __global__ __launch_bounds__(kBlock) void k_fin_init(SolveState* __restrict__ st, const double* __restrict__ bb_part,
                                                      int bb_count, const double* __restrict__ rr_part, int rr_count) {
     __shared__ double s_red[kBlock / 64];
     double bb = 0.0;
@@ -613,20 +622,20 @@ __global__ __launch_bounds__(kBlock) void k_fin_init(SolveState* __restrict__ st
 // ----------------------------------------------------------------------------
 // vector helpers
 template <typename S, typename D>
-__global__ __launch_bounds__(kBlock) void k_gather(int n, const int* __restrict__ idx, const S* __restrict__ src,
+static __global__ __launch_bounds__(kBlock) void k_gather(int n, const int* __restrict__ idx, const S* __restrict__ src,
                                                    D* __restrict__ dst) {
     const int stride = gridDim.x * kBlock;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = (D)src[idx[i]];
 }
 
 template <typename S, typename D>
-__global__ __launch_bounds__(kBlock) void k_convert(long long n, const S* __restrict__ src, D* __restrict__ dst) {
+static __global__ __launch_bounds__(kBlock) void k_convert(long long n, const S* __restrict__ src, D* __restrict__ dst) {
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = (D)src[i];
 }
 
 // b.b partials, and optionally r = b (x0 = 0) with r.r partials equal to b.b
-__global__ __launch_bounds__(kBlock) void k_norm2(int n, const double* __restrict__ b, double* __restrict__ copy_to,
+static __global__ __launch_bounds__(kBlock) void k_norm2(int n, const double* __restrict__ b, double* __restrict__ copy_to,
                                                   double* __restrict__ partial) {
     __shared__ double s_red[kBlock / 64];
     double s = 0.0;
@@ -640,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_norm2(int n, const double* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill(long long n, double* __restrict__ x, double v) {
+static __global__ __launch_bounds__(kBlock) void k_fill(long long n, double* __restrict__ x, double v) {
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] = v;
 }

@@ -1,0 +1,457 @@
+// Serving loop: continuous batching of pressure solves on one GPU.
+//
+// Requests name an operator (a caller-chosen key plus its CSR, read only the
+// first time the key is seen) and carry a device right-hand side, a device
+// output vector and a tolerance.  A scheduler thread owns all GPU work:
+//   * admission: an operator's hierarchy (and its 16-column batch engine) is
+//     built on first use if its bytes fit the HBM budget, evicting idle cached
+//     operators in least-recently-used order; otherwise the request waits;
+//   * batching: every cached operator is a group with its own stream and 16
+//     columns; a waiting request takes a free column between iteration blocks
+//     and its recurrence starts there (columns are independent, so a result
+//     is the same whatever else is in the group);
+//   * overlap: each tick launches one iteration block for every group with
+//     running columns before waiting on any, so the groups' work overlaps;
+//   * retirement: a column whose stopping test holds (or hit maxit) is copied
+//     out and freed at once; with the FP32 V-cycle its true residual is
+//     checked first and the recurrence restarted from it if needed.
+// The problem setting is the paper's: the same pressure operator is solved
+// many times (Sec. 2), and hierarchies are reused (Sec. 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "batch.hpp"
+
+extern "C" int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out);
+extern "C" int pamg_hierarchy_destroy(pamg_hierarchy* h);
+extern "C" const char* pamg_last_error(void);
+
+namespace pamg {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServeRequest {
+    pamg_request r;
+    Clock::time_point t_submit, t_admit;
+    int restarts = 0;
+};
+
+struct ServeGroup {
+    uint64_t key = 0;
+    pamg_hierarchy* h = nullptr;
+    BatchEngine* E = nullptr;
+    hipStream_t stream = nullptr;
+    ServeRequest* col[kW] = {};
+    int active = 0;
+    uint64_t last_used = 0;
+    uint64_t bytes = 0;
+    uint64_t iter_bytes = 0;     // algorithmic bytes of one batched iteration
+    bool launched = false;
+};
+
+}  // namespace pamg
+
+struct pamg_server {
+    pamg_server_opts opts{};
+    int device = 0;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    std::deque<pamg::ServeRequest*> incoming;        // guarded by mu
+    std::vector<pamg_completion> done;               // guarded by mu
+    pamg_server_stats stats{};                       // guarded by mu (copied out)
+    // scheduler-owned
+    std::deque<pamg::ServeRequest*> pending;
+    std::map<uint64_t, pamg::ServeGroup*> groups;
+    uint64_t tick = 0;
+    std::string fatal;
+};
+
+namespace pamg {
+
+static double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// Upper estimate of the device bytes of an operator's hierarchy plus its
+// batch engine, before it is built (replaced by the exact figure after).
+// Hierarchy: per level index arrays, values and the restriction values (plus
+// their FP32 copies), vectors; coarse levels add at most 1.3x the finest
+// (pairwise coarsening), fixed buffers ~0.2 MB.  Engine: eight n x 16 FP64
+// vectors at level 0, two n_l x 16 vectors per level, 1.1 MB of partials.
+uint64_t estimate_bytes(const pamg_csr& A, int prec) {
+    const double cx = 2.3;
+    const double n = (double)A.n, nnz = (double)A.nnz;
+    const double s = prec == PAMG_PREC_F32 ? 4.0 : 8.0;
+    double hier = cx * (nnz * (4 + 8 + 8) + n * 80) + 96.0 * n + (1 << 18);
+    if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32);
+    const double engine = n * kW * 8 * 8 + 2.0 * cx * n * kW * s + 1.2 * (1 << 20);
+    return (uint64_t)(hier + engine);
+}
+
+static uint64_t batch_iteration_bytes(const pamg_hierarchy* h, int prec) {
+    const uint64_t s = prec == PAMG_PREC_F32 ? 4 : 8;
+    uint64_t B = 0;
+    for (int l = 0; l < h->L; ++l) {
+        const uint64_t n = h->idx[l].n, nc = h->idx[l + 1].n, nnz = h->idx[l].nnz;
+        B += 2 * (nnz * (4 + s) + 4 * (n + 1)) + (10 * n + 2 * nc) * kW * s;
+    }
+    const uint64_t n0 = h->idx[0].n, nnz0 = h->idx[0].nnz;
+    B += nnz0 * 12 + 4 * (n0 + 1) + 12 * n0 * kW * 8;
+    return B;
+}
+
+static void complete(pamg_server* S, ServeRequest* q, int status, int iters, double relres, double relres_true) {
+    pamg_completion c{};
+    c.tag = q->r.tag;
+    c.status = status;
+    c.iterations = iters;
+    c.relres = relres;
+    c.relres_true = relres_true;
+    const auto now = Clock::now();
+    c.queue_ms = ms_between(q->t_submit, q->t_admit.time_since_epoch().count() ? q->t_admit : now);
+    c.latency_ms = ms_between(q->t_submit, now);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->done.push_back(c);
+        S->stats.completed += 1;
+        if (status == PAMG_E_BUSY) S->stats.rejected += 1;
+    }
+    delete q;
+}
+
+static void evict(pamg_server* S, ServeGroup* g) {
+    HIP_CHECK(hipStreamSynchronize(g->stream));
+    pamg_hierarchy_destroy(g->h);
+    (void)hipStreamDestroy(g->stream);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.bytes_in_use -= g->bytes;
+        S->stats.evictions += 1;
+        S->stats.cached_operators -= 1;
+    }
+    S->groups.erase(g->key);
+    delete g;
+}
+
+// Find or build the group of a request's operator; nullptr if it has to wait.
+static ServeGroup* admit_operator(pamg_server* S, ServeRequest* q, bool* reject) {
+    *reject = false;
+    auto it = S->groups.find(q->r.op_key);
+    if (it != S->groups.end()) return it->second;
+    if (!q->r.A) throw Error(PAMG_E_INVALID, "request for an uncached operator carries no matrix");
+    const int prec = S->opts.precision;
+    const uint64_t est = estimate_bytes(*q->r.A, prec);
+    const uint64_t budget = S->opts.hbm_budget_bytes;
+    if (est > budget) {
+        *reject = true;
+        return nullptr;
+    }
+    auto in_use = [&]() {
+        std::lock_guard<std::mutex> lk(S->mu);
+        return S->stats.bytes_in_use;
+    };
+    while (in_use() + est > budget) {
+        ServeGroup* lru = nullptr;
+        for (auto& kv : S->groups)
+            if (kv.second->active == 0 && (!lru || kv.second->last_used < lru->last_used)) lru = kv.second;
+        if (!lru) return nullptr;                      // everything busy: wait
+        evict(S, lru);
+    }
+    std::unique_ptr<ServeGroup> g(new ServeGroup());
+    g->key = q->r.op_key;
+    HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    pamg_params prm;
+    pamg_params_default(&prm);
+    prm.build_f32 = prec == PAMG_PREC_F32 ? 1 : 0;
+    const int rc = pamg_setup(q->r.A, &prm, g->stream, &g->h);
+    if (rc != PAMG_OK) {
+        (void)hipStreamDestroy(g->stream);
+        throw Error(rc, std::string("operator setup failed: ") + pamg_last_error());
+    }
+    g->E = get_engine(g->h, prec, g->stream);
+    g->bytes = g->h->info.device_bytes + batch_bytes(g->E);
+    g->iter_bytes = batch_iteration_bytes(g->h, prec);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.bytes_in_use += g->bytes;
+        S->stats.setups += 1;
+        S->stats.cached_operators += 1;
+    }
+    ServeGroup* raw = g.release();
+    S->groups[raw->key] = raw;
+    return raw;
+}
+
+// Copy out and free the finished columns of a group (state host copy current).
+static void retire(pamg_server* S, ServeGroup* g) {
+    BatchState& st = batch_state_host(g->E);
+    int finished = 0;
+    for (int c = 0; c < kW; ++c)
+        if (g->col[c] && st.col[c].active && st.col[c].done) finished |= 1 << c;
+    if (!finished) return;
+    double rel[kW];
+    for (double& v : rel) v = -1.0;
+    if (S->opts.precision == PAMG_PREC_F32) {
+        // the FP32 V-cycle: accept a column on its true FP64 residual only
+        batch_true_residual(g->E, 0, rel, g->stream);
+        int restart = 0;
+        for (int c = 0; c < kW; ++c) {
+            if (!((finished >> c) & 1)) continue;
+            const BatchCol& C = st.col[c];
+            ServeRequest* q = g->col[c];
+            if (C.status == PAMG_OK && C.done == 1 && rel[c] > C.tol && q->restarts < 10 && C.iter < C.maxit) {
+                restart |= 1 << c;
+                q->restarts += 1;
+            }
+        }
+        if (restart) {
+            double tmp[kW];
+            batch_true_residual(g->E, restart, tmp, g->stream);
+            finished &= ~restart;
+        }
+    }
+    if (!finished) return;
+    double* dst[kW] = {};
+    for (int c = 0; c < kW; ++c)
+        if ((finished >> c) & 1) dst[c] = g->col[c]->r.x_dev;
+    batch_store(g->E, dst, g->stream);
+    for (int c = 0; c < kW; ++c) {
+        if (!((finished >> c) & 1)) continue;
+        const BatchCol& C = st.col[c];
+        complete(S, g->col[c], C.status, C.iter, C.bnorm > 0 ? C.rnorm / C.bnorm : 0.0, rel[c]);
+        g->col[c] = nullptr;
+        g->active -= 1;
+    }
+    batch_retire(g->E, finished);
+    batch_write_state(g->E, g->stream);
+}
+
+static void scheduler_tick(pamg_server* S) {
+    ++S->tick;
+    // 1. admission and column assignment
+    std::map<ServeGroup*, int> loads;
+    for (auto it = S->pending.begin(); it != S->pending.end();) {
+        ServeRequest* q = *it;
+        bool reject = false;
+        ServeGroup* g = nullptr;
+        try {
+            g = admit_operator(S, q, &reject);
+        } catch (const Error& e) {
+            it = S->pending.erase(it);
+            complete(S, q, e.code, 0, 0.0, -1.0);
+            continue;
+        }
+        if (reject) {
+            it = S->pending.erase(it);
+            complete(S, q, PAMG_E_BUSY, 0, 0.0, -1.0);
+            continue;
+        }
+        if (!g || g->active >= kW) {
+            ++it;
+            continue;
+        }
+        int c = 0;
+        while (g->col[c]) ++c;
+        g->col[c] = q;
+        g->active += 1;
+        loads[g] |= 1 << c;
+        q->t_admit = Clock::now();
+        it = S->pending.erase(it);
+    }
+    for (auto& kv : loads) {
+        ServeGroup* g = kv.first;
+        const double* src[kW] = {};
+        double tol[kW];
+        int maxit[kW], fixed[kW];
+        for (int c = 0; c < kW; ++c) {
+            tol[c] = 1e-6;
+            maxit[c] = 1000;
+            fixed[c] = 0;
+            if ((kv.second >> c) & 1) {
+                src[c] = g->col[c]->r.b_dev;
+                tol[c] = g->col[c]->r.tol;
+                maxit[c] = g->col[c]->r.maxit > 0 ? g->col[c]->r.maxit : 1000;
+            }
+        }
+        batch_read_state(g->E, g->stream);
+        batch_load(g->E, src, tol, maxit, fixed, PAMG_KRYLOV_FCG, g->stream);
+        retire(S, g);                    // zero right-hand sides finish at once
+    }
+    // 2. one iteration block for every group with running columns, all
+    //    launched before any is waited on
+    const int k = S->opts.block_iters;
+    uint64_t blocks = 0;
+    for (auto& kv : S->groups) {
+        ServeGroup* g = kv.second;
+        g->launched = false;
+        if (g->active == 0 || batch_state_host(g->E).all_done) continue;
+        batch_run_block(g->E, PAMG_KRYLOV_FCG, k, true, g->stream);
+        g->launched = true;
+        g->last_used = S->tick;
+        ++blocks;
+    }
+    // 3. collect: read each group's state, retire finished columns
+    uint64_t moved = 0;
+    for (auto it = S->groups.begin(); it != S->groups.end();) {
+        ServeGroup* g = (it++)->second;
+        if (!g->launched) continue;
+        int before[kW];
+        for (int c = 0; c < kW; ++c) before[c] = batch_state_host(g->E).col[c].iter;
+        batch_read_state(g->E, g->stream);
+        int ran = 0;
+        for (int c = 0; c < kW; ++c) ran = std::max(ran, batch_state_host(g->E).col[c].iter - before[c]);
+        moved += (uint64_t)ran * g->iter_bytes;
+        retire(S, g);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.blocks += blocks;
+    S->stats.algorithmic_bytes += moved;
+    int active = 0;
+    for (auto& kv : S->groups) active += kv.second->active;
+    S->stats.active_columns = active;
+    S->stats.pending = (int32_t)S->pending.size();
+}
+
+static void scheduler_main(pamg_server* S) {
+    try {
+        HIP_CHECK(hipSetDevice(S->device));
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                bool idle = S->pending.empty();
+                if (idle)
+                    for (auto& kv : S->groups)
+                        if (kv.second->active) idle = false;
+                if (idle && S->incoming.empty() && !S->stop)
+                    S->cv.wait_for(lk, std::chrono::milliseconds(2));
+                if (S->stop && S->incoming.empty() && idle) return;
+                while (!S->incoming.empty()) {
+                    S->pending.push_back(S->incoming.front());
+                    S->incoming.pop_front();
+                }
+            }
+            auto t0 = Clock::now();
+            scheduler_tick(S);
+            const double dt = ms_between(t0, Clock::now());
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.busy_ms += dt;
+        }
+    } catch (const std::exception& e) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->fatal = e.what();
+    }
+}
+
+}  // namespace pamg
+
+extern "C" {
+
+int pamg_server_opts_default(pamg_server_opts* o) {
+    if (!o) return PAMG_E_INVALID;
+    std::memset(o, 0, sizeof(*o));
+    o->hbm_budget_bytes = 64ull << 30;
+    o->block_iters = 4;
+    o->precision = PAMG_PREC_F32;
+    return PAMG_OK;
+}
+
+int pamg_server_estimate_bytes(const pamg_csr* A, int32_t precision, uint64_t* out) {
+    return pamg::guarded([&]() -> int {
+        if (!A || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        *out = pamg::estimate_bytes(*A, precision == PAMG_PREC_F32 ? PAMG_PREC_F32 : PAMG_PREC_F64);
+        return PAMG_OK;
+    });
+}
+
+int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
+    return pamg::guarded([&]() -> int {
+        if (!out) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        *out = nullptr;
+        std::unique_ptr<pamg_server> S(new pamg_server());
+        if (opts) S->opts = *opts; else pamg_server_opts_default(&S->opts);
+        if (S->opts.block_iters < 2) S->opts.block_iters = 2;
+        if (S->opts.block_iters & 1) S->opts.block_iters += 1;
+        if (S->opts.precision != PAMG_PREC_F32) S->opts.precision = PAMG_PREC_F64;
+        if (S->opts.hbm_budget_bytes == 0) throw pamg::Error(PAMG_E_INVALID, "zero HBM budget");
+        HIP_CHECK(hipGetDevice(&S->device));
+        S->stats.hbm_budget_bytes = S->opts.hbm_budget_bytes;
+        pamg_server* raw = S.release();
+        raw->th = std::thread(pamg::scheduler_main, raw);
+        *out = raw;
+        return PAMG_OK;
+    });
+}
+
+int pamg_server_submit(pamg_server* S, const pamg_request* req) {
+    return pamg::guarded([&]() -> int {
+        if (!S || !req || !req->b_dev || !req->x_dev) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        if (!(req->tol >= 0.0)) throw pamg::Error(PAMG_E_INVALID, "bad tolerance");
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->fatal.empty()) throw pamg::Error(PAMG_E_DEVICE, "server stopped: " + S->fatal);
+        if (S->stop) throw pamg::Error(PAMG_E_INVALID, "server is shutting down");
+        pamg::ServeRequest* q = new pamg::ServeRequest();
+        q->r = *req;
+        q->t_submit = pamg::Clock::now();
+        S->incoming.push_back(q);
+        S->stats.submitted += 1;
+        S->cv.notify_one();
+        return PAMG_OK;
+    });
+}
+
+int pamg_server_poll(pamg_server* S, pamg_completion* out, int32_t max, int32_t* n_out) {
+    return pamg::guarded([&]() -> int {
+        if (!S || !n_out || (max > 0 && !out)) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(S->mu);
+        const int32_t n = (int32_t)std::min<size_t>(S->done.size(), (size_t)std::max(0, max));
+        for (int32_t i = 0; i < n; ++i) out[i] = S->done[i];
+        S->done.erase(S->done.begin(), S->done.begin() + n);
+        *n_out = n;
+        if (!S->fatal.empty()) throw pamg::Error(PAMG_E_DEVICE, "server stopped: " + S->fatal);
+        return PAMG_OK;
+    });
+}
+
+int pamg_server_stats_get(pamg_server* S, pamg_server_stats* out) {
+    return pamg::guarded([&]() -> int {
+        if (!S || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        std::lock_guard<std::mutex> lk(S->mu);
+        *out = S->stats;
+        return PAMG_OK;
+    });
+}
+
+int pamg_server_destroy(pamg_server* S) {
+    return pamg::guarded([&]() -> int {
+        if (!S) return PAMG_OK;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+            S->cv.notify_all();
+        }
+        if (S->th.joinable()) S->th.join();
+        // outstanding requests (only after a fatal error) are dropped
+        for (auto* q : S->pending) delete q;
+        for (auto* q : S->incoming) delete q;
+        for (auto& kv : S->groups) {
+            (void)hipStreamSynchronize(kv.second->stream);
+            pamg_hierarchy_destroy(kv.second->h);
+            (void)hipStreamDestroy(kv.second->stream);
+            for (auto* q : kv.second->col) delete q;
+            delete kv.second;
+        }
+        delete S;
+        return PAMG_OK;
+    });
+}
+
+}  // extern "C"

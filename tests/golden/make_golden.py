@@ -32,12 +32,13 @@ def main():
     assert st == 0
     x5, _, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=5)
     z = O.vcycle(b)
+    nlev, level_n = O.nlevels, [O.n(l) for l in range(O.nlevels)]
     del O
     out = {
         "source": "oracle/oracle.c via tests/golden/make_golden.py",
         "workload": {"q1_elements": N, "ratio": ratio, "rhs_seed": seed, "n": A.n, "nnz": A.nnz},
-        "levels": O.nlevels,
-        "level_n": [O.n(l) for l in range(O.nlevels)],
+        "levels": nlev,
+        "level_n": level_n,
         "fcg_tol": 1e-6,
         "fcg_iterations": it,
         "fcg_relres": rr,
@@ -51,7 +52,7 @@ def main():
     }
     with open(os.path.join(HERE, f"q1_{N}_fcg.json"), "w") as f:
         json.dump(out, f, indent=1)
-    print(f"levels {O.nlevels}, iterations {it}, relres {rr:.3e}")
+    print(f"levels {nlev}, iterations {it}, relres {rr:.3e}")
 
 
 if __name__ == "__main__":

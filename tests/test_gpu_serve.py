@@ -1,0 +1,139 @@
+"""Serving loop (continuous batching) through the C ABI.
+
+* every served result meets its tolerance on the true FP64 residual and
+  agrees with the oracle's FP64 solution;
+* a request's result is bitwise the same alone and in a mix of requests on
+  several operators (columns are independent and the hierarchy is
+  deterministic), also against a one-column batched solve;
+* a tiny HBM budget forces queueing and LRU eviction, and every request
+  still completes correctly; an operator larger than the budget is refused;
+* a zero right-hand side completes with x = 0.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2210_16660_amd as pamg
+from workloads import SplitMix64, varcoef7
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).to("cuda:0")
+
+
+def wait_all(S, n, timeout=120.0):
+    got = []
+    t0 = time.time()
+    while len(got) < n:
+        got += S.poll()
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(got)} of {n} completions after {timeout}s")
+        time.sleep(0.002)
+    return {int(c.tag): c for c in got}
+
+
+OPS = {k: (n, 40 + k) for k, n in enumerate([10, 14, 17, 12])}
+
+
+@pytest.fixture(scope="module")
+def ops():
+    return {k: varcoef7(n, seed=s) for k, (n, s) in OPS.items()}
+
+
+def make_requests(ops, count, seed=7):
+    rng = SplitMix64(seed)
+    keys = rng.integers(count, 0, len(ops) - 1)
+    reqs = []
+    for t in range(count):
+        k = int(keys[t])
+        b = SplitMix64(1000 + t).uniform(ops[k].n)
+        reqs.append((t, k, b))
+    return reqs
+
+
+def serve(ops, reqs, **kw):
+    S = pamg.Server(**kw)
+    xs = {}
+    torch.cuda.synchronize()
+    for tag, k, b in reqs:
+        x = torch.zeros(ops[k].n, dtype=torch.float64, device="cuda:0")
+        bd = dev(b)
+        torch.cuda.synchronize()
+        xs[tag] = x
+        S.submit(k, ops[k], bd, x, tol=1e-6, tag=tag)
+    done = wait_all(S, len(reqs))
+    stats = S.stats()
+    S.close()
+    return {t: xs[t].cpu().numpy() for t in xs}, done, stats
+
+
+def test_served_results_correct_and_independent_of_the_mix(ops):
+    reqs = make_requests(ops, 40)
+    xs, done, stats = serve(ops, reqs)
+    assert stats.completed == 40 and stats.rejected == 0 and stats.setups == len(ops)
+    hier = {k: oracle.Hierarchy(A) for k, A in ops.items()}
+    for tag, k, b in reqs:
+        c = done[tag]
+        assert c.status == pamg.OK, (tag, c.status)
+        A = ops[k].to_scipy()
+        rel = np.linalg.norm(b - A @ xs[tag]) / np.linalg.norm(b)
+        assert rel <= 1e-6 and abs(rel - c.relres_true) <= 1e-9
+        x_or, _, _, _ = hier[k].solve(b, 1e-6)
+        assert np.linalg.norm(xs[tag] - x_or) <= 1e-4 * np.linalg.norm(x_or)
+    # alone: the same request through a fresh server, and as a one-column batch
+    for tag, k, b in reqs[:4]:
+        xa, da, _ = serve(ops, [(tag, k, b)])
+        assert da[tag].iterations == done[tag].iterations
+        assert np.array_equal(xa[tag].view(np.uint64), xs[tag].view(np.uint64)), f"request {tag} differs alone"
+        H = pamg.Hierarchy(ops[k], build_f32=1)
+        X = torch.zeros((1, ops[k].n), dtype=torch.float64, device="cuda:0")
+        inf = H.solve_batch(dev(b[None, :]), X, tol=1e-6, precision=pamg.PREC_F32)
+        assert inf[0].iterations == done[tag].iterations
+        assert np.array_equal(X[0].cpu().numpy().view(np.uint64), xs[tag].view(np.uint64))
+
+
+def test_fp64_vcycle_server(ops):
+    reqs = make_requests(ops, 12, seed=3)
+    xs, done, stats = serve(ops, reqs, precision=pamg.PREC_F64)
+    for tag, k, b in reqs:
+        O = oracle.Hierarchy(ops[k])
+        x_or, it_or, _, _ = O.solve(b, 1e-6)
+        assert done[tag].status == pamg.OK and abs(done[tag].iterations - it_or) <= 1
+        if done[tag].iterations == it_or:
+            assert np.linalg.norm(xs[tag] - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+def test_tiny_budget_queues_and_evicts(ops):
+    # room for about one operator at a time: requests for the others wait,
+    # idle operators are evicted, everything still completes
+    est = max(pamg.server_estimate_bytes(A) for A in ops.values())
+    reqs = make_requests(ops, 24, seed=11)
+    xs, done, stats = serve(ops, reqs, hbm_budget_bytes=int(est * 1.02))
+    assert stats.completed == 24 and stats.rejected == 0
+    # one operator fits at a time: each later operator evicts an idle one
+    assert stats.evictions >= len(ops) - 1 and stats.setups >= len(ops)
+    assert stats.bytes_in_use <= stats.hbm_budget_bytes
+    for tag, k, b in reqs:
+        assert done[tag].status == pamg.OK
+        rel = np.linalg.norm(b - ops[k].to_scipy() @ xs[tag]) / np.linalg.norm(b)
+        assert rel <= 1e-6
+
+
+def test_oversized_operator_refused_and_zero_rhs(ops):
+    S = pamg.Server(hbm_budget_bytes=1 << 20)
+    x = torch.zeros(ops[1].n, dtype=torch.float64, device="cuda:0")
+    S.submit(1, ops[1], dev(np.ones(ops[1].n)), x, tag=1)
+    d = wait_all(S, 1)
+    assert d[1].status == pamg.E_BUSY
+    S.close()
+    S = pamg.Server()
+    x = torch.ones(ops[0].n, dtype=torch.float64, device="cuda:0")
+    S.submit(0, ops[0], dev(np.zeros(ops[0].n)), x, tag=2)
+    d = wait_all(S, 1)
+    assert d[2].status == pamg.OK and d[2].iterations == 0 and not x.cpu().numpy().any()
+    S.close()
