@@ -348,12 +348,27 @@ def bench_serve(args, torch, np, pamg, log) -> int:
         torch.cuda.synchronize()
         comps = []
         stop = threading.Event()
+        failed = threading.Event()
 
         def poller():
+            last_report = time.perf_counter()
+            last_progress = (time.perf_counter(), 0)
             while not stop.is_set() or len(comps) < count:
                 comps.extend(S.poll())
                 if len(comps) >= count:
                     break
+                now = time.perf_counter()
+                if len(comps) != last_progress[1]:
+                    last_progress = (now, len(comps))
+                elif now - last_progress[0] > 300:
+                    log("serving made no progress for 300 s; giving up")
+                    failed.set()
+                    break
+                if now - last_report > 10:
+                    st = S.stats()
+                    log(f"  {len(comps)}/{count} done, {st.active_columns} running, {st.pending} waiting, "
+                        f"{st.cached_operators} cached, {st.setups} setups, {st.evictions} evictions")
+                    last_report = now
                 time.sleep(0.0005)
 
         th = threading.Thread(target=poller)
@@ -370,11 +385,13 @@ def bench_serve(args, torch, np, pamg, log) -> int:
         th.join()
         wall = time.perf_counter() - t_start
         st = S.stats()
+        if failed.is_set():
+            raise RuntimeError("serving stalled")
         S.close()
         return comps, wall, st
 
     # closed loop: everything queued at once -> capacity
-    ncl = min(args.requests, 500)
+    ncl = min(args.requests, 300)
     comps, wall, st = run(ncl, None)
     capacity = ncl / wall
     log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s "
