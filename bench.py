@@ -85,7 +85,7 @@ def main() -> int:
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "mixed"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -110,6 +110,8 @@ def main() -> int:
 
     if args.mode == "serve":
         return bench_serve(args, torch, np, pamg, log)
+    if args.mode == "mixed":
+        return bench_mixed(args, torch, np, pamg, log)
     t0 = time.perf_counter()
     A = q1_stretched(args.n, args.ratio)
     b = q1_rhs(args.n, args.ratio, 2)
@@ -427,6 +429,92 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     }
     print(json.dumps(out), flush=True)
     return 0 if ok == len(comps) else 1
+
+
+def bench_mixed(args, torch, np, pamg, log) -> int:
+    """FP64 hierarchy versus FP32 hierarchy (both under the FP64 FCG) on the
+    same stretched Q1 system (256^3 elements unless --n says otherwise,
+    divergence right-hand side seed 3), each to a true FP64 relative residual
+    of 1e-6; the solutions are compared with each other and with the oracle's
+    stored FP64 solution samples when they exist for this workload."""
+    from workloads import q1_rhs, q1_stretched
+    n = args.n if args.n != 128 else 256
+    t0 = time.perf_counter()
+    A = q1_stretched(n, args.ratio, progress=log)
+    b = q1_rhs(n, args.ratio, 3, progress=log)
+    log(f"generated Q1 {n}^3: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"q1_{n}_fcg.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            g = json.load(f)
+        if g["workload"]["rhs_seed"] == 3 and g["workload"]["n"] == A.n and g["workload"]["ratio"] == args.ratio:
+            golden = g
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    H = pamg.Hierarchy(A, build_f32=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = H.info()
+    log(f"setup {setup_s:.2f}s, {info.levels} levels")
+    b_d = torch.from_numpy(b).to(dev)
+    S = A.to_scipy()
+    bn = float(np.linalg.norm(b))
+    res = {}
+    xs = {}
+    for name, prec in (("f64", pamg.PREC_F64), ("f32", pamg.PREC_F32)):
+        x_d = torch.zeros(A.n, dtype=torch.float64, device=dev)
+        opts = dict(tol=args.tol, krylov="fcg", precision=prec, true_residual=1)
+        for _ in range(args.warmup):
+            x_d.zero_()
+            H.solve(b_d, x_d, **opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            x_d.zero_()
+            inf = H.solve(b_d, x_d, **opts)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1) / args.steps
+        x = x_d.cpu().numpy()
+        xs[name] = x
+        rel = float(np.linalg.norm(b - S @ x) / bn)
+        r_d = b_d.clone()
+        v_ms, _ = H.time_kernels(r_d, reps=10, precision=prec)
+        vbytes = info.vcycle_bytes_f32 if prec == pamg.PREC_F32 else info.vcycle_bytes_f64
+        entry = {"ms_per_solve": round(ms, 3), "iterations": inf.iterations, "status": inf.status,
+                 "relres_true": rel, "vcycle_ms": round(v_ms, 4),
+                 "vcycle_GBps": round(vbytes / (v_ms * 1e-3) / 1e9, 1)}
+        if golden is not None:
+            idx = np.array(golden["sample_index"])
+            xo = np.array(golden["x_sample"])
+            entry["err_vs_oracle_sample"] = float(np.linalg.norm(x[idx] - xo) / np.linalg.norm(xo))
+        res[name] = entry
+        log(f"{name}: {ms:.1f} ms/solve, {inf.iterations} iterations, true relres {rel:.3e}")
+        if inf.status != pamg.OK or rel > args.tol:
+            print(json.dumps({"error": f"{name} solve did not reach the tolerance", **entry}), flush=True)
+            return 1
+    err32 = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
+    out = {
+        "metric": "FP32-hierarchy speedup over FP64 at a true FP64 relative residual of 1e-6",
+        "value": round(res["f64"]["ms_per_solve"] / res["f32"]["ms_per_solve"], 3),
+        "unit": "x",
+        "higher_is_better": True,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "dtype": "f64 | f32-vcycle/f64-fcg",
+        "data": "synthetic",
+        "config": {"workload": f"Q1 hexahedral FE Laplacian, {n}^3 elements, vertical stretching {args.ratio}, "
+                               f"divergence RHS seed 3; FCG + AMG V-cycle to a true residual of {args.tol:g}",
+                   "n": A.n, "nnz": A.nnz, "levels": info.levels},
+        "setup_s": round(setup_s, 2),
+        "f64": res["f64"],
+        "f32": res["f32"],
+        "f32_vs_f64_solution_relerr": err32,
+        "oracle_reference": "stored oracle FP64 solution samples (512 entries)" if golden is not None else None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

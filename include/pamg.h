@@ -60,13 +60,19 @@ typedef struct {
 typedef struct {
     int32_t max_coarse;       /* coarsen while n_l > max_coarse (default 200, Sec. 3.1 coarsest size) */
     int32_t max_levels;       /* default 50 */
-    int32_t max_dense;        /* largest coarsest level accepted for the dense solve (default 4096) */
+    int32_t max_dense;        /* largest coarsest level accepted for the dense solve (default 8192,
+                                 at most 8192; the factorization runs on the device) */
     int32_t match_all_edges;  /* 0: only edges with weight > 1 may be matched (default) */
     int32_t build_f32;        /* 1: also keep an FP32 copy of the hierarchy (mixed-precision V-cycle) */
     int32_t num_threads;      /* host threads for setup (0 = hardware concurrency) */
     int32_t check_symmetry;   /* 1: reject A unless bitwise symmetric */
-    int32_t host_only;        /* 1: build the hierarchy on the host only (no device upload; info,
-                                 aggregates and level queries work, solves return PAMG_E_INVALID) */
+    int32_t host_only;        /* 1: build the hierarchy on the host only (no device upload and no
+                                 coarse factorization; info, aggregates and level queries work,
+                                 solves return PAMG_E_INVALID) */
+    double min_ratio;         /* a level with n_l <= max_dense whose matching would give
+                                 n_l < min_ratio * n_{l+1} is the coarsest (default 1.5; <= 1: off).
+                                 The paper does not say when coarsening stops if matching stalls
+                                 (weakly coupled vertices that stay singletons on every level). */
     int32_t reserved[8];
 } pamg_params;
 

@@ -45,6 +45,12 @@
  *   R9 levels: coarsen while n_l > max_coarse (200); a level whose matching
  *      has no pair is the coarsest (error STALLED if it exceeds max_dense);
  *      at most max_levels levels.  Levels are 0..L; smoothing on 0..L-1.
+ *   R11 stalled coarsening: a level with n_l <= max_dense whose matching
+ *      would give n_{l+1} with n_l < min_ratio * n_{l+1} (default 1.5) is
+ *      the coarsest; its matching is discarded.  (Weakly coupled vertices
+ *      can stay singletons on every level while everything else merges, so
+ *      that later levels shed one pair each.)  min_ratio <= 1 turns the
+ *      rule off; above max_dense coarsening always continues.
  *   R10 Krylov: PCG, or FCG(1) with beta = -(z.q_old)/delta_old and
  *      alpha = (p.r)/delta; dot products summed in index order.
  */
@@ -318,7 +324,7 @@ static int validate(int n, const int *rp, const int *ci, const double *v) {
 }
 
 int oracle_setup(int n, const int *rp, const int *ci, const double *v,
-                 int max_coarse, int max_levels, int max_dense, int match_all,
+                 int max_coarse, int max_levels, int max_dense, double min_ratio, int match_all,
                  or_hier **out) {
     *out = NULL;
     int st = validate(n, rp, ci, v);
@@ -352,6 +358,10 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
         long pairs = greedy_matching(A, h->w[l], match_all, mate);
         if (pairs < 0) { free(mate); oracle_free(h); return OR_E_OOM; }
         if (pairs == 0) { free(mate); break; }               /* stall: this level is coarsest */
+        if (A->n <= max_dense && (double)A->n < min_ratio * (double)(A->n - pairs)) {
+            free(mate);                                       /* R11: too little reduction */
+            break;
+        }
         h->n_pairs[l] = (int)pairs;
         h->agg[l] = (int *)malloc(sizeof(int) * (size_t)A->n);
         h->p[l] = (double *)malloc(sizeof(double) * (size_t)A->n);

@@ -31,7 +31,8 @@ class pamg_csr(C.Structure):
 class pamg_params(C.Structure):
     _fields_ = [("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("max_dense", C.c_int32),
                 ("match_all_edges", C.c_int32), ("build_f32", C.c_int32), ("num_threads", C.c_int32),
-                ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("min_ratio", C.c_double),
+                ("reserved", C.c_int32 * 8)]
 
 
 class pamg_solve_opts(C.Structure):
@@ -158,7 +159,7 @@ def params(**kw) -> pamg_params:
     p = pamg_params()
     _check(lib().pamg_params_default(C.byref(p)), "pamg_params_default")
     for k, v in kw.items():
-        setattr(p, k, int(v))
+        setattr(p, k, float(v) if k == "min_ratio" else int(v))
     return p
 
 

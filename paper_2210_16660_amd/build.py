@@ -3,8 +3,11 @@
 * csrc/setup.cpp (host hierarchy construction) is compiled with g++ and
   -ffp-contract=off so that every weight, prolongator entry and Galerkin sum
   is one IEEE operation per written operation.
-* csrc/device.hip (kernels, driver, C ABI) is compiled with hipcc for gfx950.
-  Packed-FP32 instructions are disabled for all device code.
+* csrc/device.hip (single right-hand side kernels, driver, C ABI),
+  csrc/batch.hip (16 right-hand sides), csrc/serve.hip (server) and
+  csrc/dense.hip (coarsest-level factorization) are compiled with hipcc for
+  gfx950 (in parallel).  Packed-FP32 instructions are disabled for all device
+  code.
 """
 from __future__ import annotations
 
@@ -32,19 +35,22 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     setup_o = os.path.join(BUILD, "setup.o")
-    device_o = os.path.join(BUILD, "device.o")
-    batch_o = os.path.join(BUILD, "batch.o")
-    serve_o = os.path.join(BUILD, "serve.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-pthread",
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
-    _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
-          "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "device.hip"), "-o", device_o])
-    _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
-          "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "batch.hip"), "-o", batch_o])
-    _run([HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
-          "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "serve.hip"), "-o", serve_o])
+    objs = []
+    procs = []
+    for name in ("device", "batch", "serve", "dense"):
+        o = os.path.join(BUILD, f"{name}.o")
+        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
+               "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o]
+        print(" ".join(cmd), flush=True)
+        procs.append((name, subprocess.Popen(cmd)))
+        objs.append(o)
+    failed = [name for name, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed for {', '.join(failed)}")
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", device_o, batch_o, serve_o, setup_o, "-o", tmp, "-pthread"])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, setup_o, "-o", tmp, "-pthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -133,7 +133,17 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
         return 1;
     }
     const DevLevelIdx& F = h->idx[L - 1];
-    if (L - 1 == 0)
+    if (nL > kCoarseRowsMin) {
+        const dim3 g(coarse_rows_grid_b(nL));
+        if (L - 1 == 0)
+            hipLaunchKernelGGL((kb_coarse_rows<T, T, double>), g, dim3(kBlock), 0, s, nL, (const T*)V.ainv,
+                               (const T*)E->r[L], (const int*)F.aggptr, (const double*)E->R, (const T*)V.dinv[0],
+                               (const T*)V.p[0], (T*)E->zp[0], done);
+        else
+            hipLaunchKernelGGL((kb_coarse_rows<T, T, T>), g, dim3(kBlock), 0, s, nL, (const T*)V.ainv,
+                               (const T*)E->r[L], (const int*)F.aggptr, (const T*)E->r[L - 1],
+                               (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], (T*)E->zp[L - 1], done);
+    } else if (L - 1 == 0)
         hipLaunchKernelGGL((kb_coarse<T, T, double, false>), dim3(1), dim3(kCoarseThreads), 0, s, nL,
                            (const T*)V.ainv, (const T*)E->r[L], (T*)E->zc, (const int*)F.aggptr, (const double*)E->R,
                            (const T*)V.dinv[0], (const T*)V.p[0], (T*)E->zp[0], (double*)nullptr,

@@ -38,8 +38,6 @@ struct HostLevel {
 
 struct HostHierarchy {
     std::vector<HostLevel> lev;         // 0..L
-    std::vector<double> coarse_inv;    // A_L^{-1}, n_L x n_L (symmetric, row-major)
-    std::vector<double> coarse_chol;   // lower factor of A_L, row-major
 };
 
 // Device-ready layout of one level in hierarchical (aggregate-contiguous) order.

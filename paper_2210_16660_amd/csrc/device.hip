@@ -46,7 +46,17 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size());
         maxn = std::max(maxn, lay[l].dinv.size());
     }
-    V.ainv = upload<T>(h, h->host.coarse_inv, s);
+    // A_L^{-1}: factorized on the device in FP64; the FP32 copy is its rounding
+    const DevLevelIdx& C = h->idx[nl - 1];
+    V.ainv = dalloc<T>(h, (size_t)C.n * C.n);
+    if constexpr (std::is_same<T, double>::value) {
+        coarse_inverse_device(C.n, C.rp, C.ci, V.v[nl - 1], V.ainv, s);
+    } else {
+        const long long nn = (long long)C.n * C.n;
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(nn)), dim3(kBlock), 0, s, nn,
+                           (const double*)h->f64.ainv, V.ainv);
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
     V.dbg_in = dalloc<T>(h, maxn);
     V.dbg_in2 = dalloc<T>(h, maxn);
     V.built = true;
@@ -208,11 +218,19 @@ template <typename T, typename RT, typename RTF, bool OUT>
 static void launch_coarse(int nL, const T* ainv, const RT* r, const int* aggptr_f, const RTF* r_f, const T* dinv_f,
                           const T* p_f, T* zp_f, double* z_out, const double* dv, double* partial, const int* done,
                           hipStream_t s) {
+    if (nL > kCoarseRowsMin) {
+        hipLaunchKernelGGL((k_coarse_rows<T, RT, RTF, OUT>), dim3(coarse_rows_grid(nL)), dim3(kBlock), 0, s, nL, ainv,
+                           r, aggptr_f, r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        return;
+    }
     const int G = coarse_groups(nL);
     const size_t lds = (size_t)(1 + G) * nL * sizeof(T);
     hipLaunchKernelGGL((k_coarse<T, RT, RTF, OUT>), dim3(1), dim3(kCoarseThreads), lds, s, nL, G, ainv, r, aggptr_f,
                        r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
 }
+
+// number of partials the coarsest level leaves when it writes z (single level)
+static int coarse_partials(int nL) { return nL > kCoarseRowsMin ? coarse_rows_grid(nL) : 1; }
 
 // ---------------------------------------------------------------- schedule
 
@@ -233,7 +251,7 @@ static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, do
     if (L == 0) {
         launch_coarse<T, double, double, true>(nL, V.ainv, r0, nullptr, (const double*)nullptr, nullptr, nullptr,
                                                nullptr, z_out, dv, h->partial, done, s);
-        return 1;
+        return coarse_partials(nL);
     }
     const DevLevelIdx& F = h->idx[L - 1];
     if (L - 1 == 0)
@@ -651,7 +669,8 @@ int pamg_params_default(pamg_params* p) {
     std::memset(p, 0, sizeof(*p));
     p->max_coarse = 200;
     p->max_levels = 50;
-    p->max_dense = 4096;
+    p->max_dense = pamg::kMaxDense;
+    p->min_ratio = 1.5;
     p->match_all_edges = 0;
     p->build_f32 = 0;
     p->num_threads = 0;
@@ -678,8 +697,9 @@ int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_
         pamg_params prm;
         if (params) prm = *params; else pamg_params_default(&prm);
         if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
-            prm.max_dense > 4096)
-            throw pamg::Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, 1 <= max_dense <= 4096)");
+            prm.max_dense > pamg::kMaxDense || !(prm.min_ratio == prm.min_ratio))
+            throw pamg::Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
+                                              "1 <= max_dense <= 8192, min_ratio not NaN)");
         pamg::set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
         auto t0 = std::chrono::steady_clock::now();
         pamg::validate_csr(*A, prm.check_symmetry != 0);

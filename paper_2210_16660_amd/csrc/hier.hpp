@@ -87,6 +87,13 @@ inline int vec_grid(long long n) {
     return g < 1 ? 1 : (int)g;
 }
 void require_device(const pamg_hierarchy* h);
+
+// Dense limit of the coarsest level (its FP64 inverse is n_L^2 doubles).
+constexpr int kMaxDense = 8192;
+// A_L^{-1} (FP64, n x n row-major, symmetric) of the coarsest level from its
+// device CSR: Cholesky and inverse on the matrix cores (dense.hip).  Throws
+// PAMG_E_NOT_SPD on a non-positive pivot.  Synchronizes the stream.
+void coarse_inverse_device(int n, const int* rp, const int* ci, const double* v, double* ainv, hipStream_t s);
 }  // namespace pamg
 
 namespace pamg {

@@ -333,6 +333,56 @@ static __global__ __launch_bounds__(kCoarseThreads) void k_coarse(
 }
 
 // ----------------------------------------------------------------------------
+// Coarsest level when it is large (a stalled coarsening can leave thousands of
+// rows): the same product and prolongation as k_coarse, spread over
+// ceil(nL / 64) workgroups.  A workgroup owns 64 rows; its four waves split
+// the columns j in four fixed ranges and meet in LDS (fixed order).  Reads of
+// the (symmetric) inverse are coalesced along the rows.
+constexpr int kCoarseRowsMin = 512;          // above this size the coarsest runs on many workgroups
+constexpr int kCoarseRowsPerBlock = 64;
+inline int coarse_rows_grid(int nL) { return (nL + kCoarseRowsPerBlock - 1) / kCoarseRowsPerBlock; }
+
+template <typename T, typename RT, typename RTF, bool TO_OUT>
+static __global__ __launch_bounds__(kBlock) void k_coarse_rows(
+    int nL, const T* __restrict__ ainv, const RT* __restrict__ r,
+    const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
+    const T* __restrict__ p_f, T* __restrict__ zp_f,
+    double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
+    const int* __restrict__ done) {
+    if (*done) return;
+    __shared__ T s_part[kBlock / kCoarseRowsPerBlock][kCoarseRowsPerBlock];
+    constexpr int G = kBlock / kCoarseRowsPerBlock;
+    const int tid = threadIdx.x, g = tid / kCoarseRowsPerBlock, lt = tid % kCoarseRowsPerBlock;
+    const int I = blockIdx.x * kCoarseRowsPerBlock + lt;
+    const int j0 = (int)((long long)nL * g / G), j1 = (int)((long long)nL * (g + 1) / G);
+    T s = 0;
+    if (I < nL) {
+#pragma unroll 8
+        for (int j = j0; j < j1; ++j) s += ainv[(size_t)j * nL + I] * (T)r[j];
+    }
+    s_part[g][lt] = s;
+    __syncthreads();
+    if (tid < kCoarseRowsPerBlock) {          // one full wave
+        double dot = 0.0;
+        if (I < nL) {
+            T z = s_part[0][lt];
+            for (int q = 1; q < G; ++q) z += s_part[q][lt];
+            if constexpr (TO_OUT) {
+                z_out[I] = (double)z;
+                dot = (double)z * dv[I];
+            } else {
+                for (int m = aggptr_f[I]; m < aggptr_f[I + 1]; ++m)
+                    zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
+            }
+        }
+        if constexpr (TO_OUT) {
+            dot = wave_sum(dot);
+            if (tid == 0) partial[blockIdx.x] = dot;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // Prolongation alone (parity checks): zp_f[m] = dinv_f[m] r_f[m] + p_f[m] e[I]
 // for the members m of every coarse row I.
 template <typename T>

@@ -296,6 +296,74 @@ static __global__ __launch_bounds__(kCoarseThreads) void kb_coarse(
     }
 }
 
+// Large coarsest level (L >= 1): the product and the prolongation into level
+// L-1 spread over many workgroups of 256 threads.  FP64: one wave per 16-row
+// block on the matrix cores, prolongated straight from the result registers.
+// FP32: a workgroup owns 64 rows, its four waves split the columns j in four
+// fixed ranges (one row and all 16 right-hand sides per thread) and meet in
+// LDS in a fixed order.
+constexpr int kCoarseRowsBlockRows = 64;
+inline int coarse_rows_grid_b(int nL) { return (nL + kCoarseRowsBlockRows - 1) / kCoarseRowsBlockRows; }
+
+template <typename T, typename RT, typename RTF>
+static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
+    int nL, const T* __restrict__ ainv, const RT* __restrict__ r,
+    const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
+    const T* __restrict__ p_f, T* __restrict__ zp_f, const int* __restrict__ done) {
+    if (*done) return;
+    const int tid = threadIdx.x, wave = tid / 64, l = tid % 64;
+    if constexpr (std::is_same<T, double>::value) {
+        using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+        const int rb = blockIdx.x * (kBlock / 64) + wave;        // 16-row block of this wave
+        if (rb * 16 >= nL) return;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int m = rb * 16 + (l % 16);
+        for (int k0 = 0; k0 < nL; k0 += 4) {
+            const int k = k0 + l / 16;
+            const double a = (m < nL && k < nL) ? ainv[(size_t)m * nL + k] : 0.0;
+            const double b = (k < nL) ? (double)r[(size_t)k * kW + (l % 16)] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        const int c = l % 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int I = rb * 16 + 4 * i + (l / 16);
+            if (I >= nL) continue;
+            const T z = acc[i];
+            for (int mm = aggptr_f[I]; mm < aggptr_f[I + 1]; ++mm)
+                zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
+        }
+    } else {
+        constexpr int G = kBlock / kCoarseRowsBlockRows;
+        __shared__ T s_part[G][kCoarseRowsBlockRows][kW + 1];
+        const int g = tid / kCoarseRowsBlockRows, lt = tid % kCoarseRowsBlockRows;
+        const int I = blockIdx.x * kCoarseRowsBlockRows + lt;
+        const int j0 = (int)((long long)nL * g / G), j1 = (int)((long long)nL * (g + 1) / G);
+        T acc[kW];
+#pragma unroll
+        for (int c = 0; c < kW; ++c) acc[c] = 0;
+        if (I < nL) {
+            for (int j = j0; j < j1; ++j) {
+                const T a = ainv[(size_t)j * nL + I];
+#pragma unroll
+                for (int c = 0; c < kW; ++c) acc[c] += a * (T)r[(size_t)j * kW + c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kW; ++c) s_part[g][lt][c] = acc[c];
+        __syncthreads();
+        for (int e = tid; e < kCoarseRowsBlockRows * kW; e += kBlock) {
+            const int row = e / kW, c = e % kW;
+            const int II = blockIdx.x * kCoarseRowsBlockRows + row;
+            if (II >= nL) continue;
+            T z = s_part[0][row][c];
+            for (int q = 1; q < G; ++q) z += s_part[q][row][c];
+            for (int mm = aggptr_f[II]; mm < aggptr_f[II + 1]; ++mm)
+                zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- Krylov
 
 // p = z + beta_c p_old (p = z on a column's first iteration), q = A p, and

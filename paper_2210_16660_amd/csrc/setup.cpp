@@ -19,9 +19,11 @@
 //   * Galerkin A_{l+1} = P^T A P: entry (I, J) is the sum of a_ij (p_i p_j)
 //     over stored (i, j) with agg(i) = I, agg(j) = J, added left to right in
 //     ascending (min(i,j), max(i,j), i); structural zeros are kept.
-//   * coarsen while n_l > max_coarse; a level without pairs is the coarsest.
-//   * coarsest: dense Cholesky A_L = L L^T and the explicit inverse
-//     A_L^{-1} = L^{-T} L^{-1} used by the device coarse solve.
+//   * coarsen while n_l > max_coarse; a level without pairs is the coarsest,
+//     and so is a level within the dense limit whose matching would shrink it
+//     by less than min_ratio (stalled coarsening).
+//   * the coarsest matrix is factorized on the device (Cholesky and explicit
+//     inverse, dense.hip).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -273,49 +275,6 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
     });
 }
 
-// ---------------------------------------------------------------- coarsest
-
-static void dense_factor_and_inverse(const HostCSR& A, std::vector<double>& L, std::vector<double>& Ainv) {
-    const int32_t n = A.n;
-    L.assign((size_t)n * n, 0.0);
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) L[(size_t)i * n + A.ci[k]] = A.v[k];
-    // right-looking Cholesky on the lower triangle
-    for (int32_t j = 0; j < n; ++j) {
-        double d = L[(size_t)j * n + j];
-        if (!(d > 0.0)) throw Error(PAMG_E_NOT_SPD, "coarsest matrix is not positive definite (pivot " +
-                                                   std::to_string(j) + ")");
-        d = std::sqrt(d);
-        L[(size_t)j * n + j] = d;
-        for (int32_t i = j + 1; i < n; ++i) L[(size_t)i * n + j] /= d;
-        for (int32_t k = j + 1; k < n; ++k) {
-            double lkj = L[(size_t)k * n + j];
-            for (int32_t i = k; i < n; ++i) L[(size_t)i * n + k] -= L[(size_t)i * n + j] * lkj;
-        }
-    }
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t j = i + 1; j < n; ++j) L[(size_t)i * n + j] = 0.0;
-    // X = L^{-1} by forward substitution on the identity
-    std::vector<double> X((size_t)n * n, 0.0);
-    for (int32_t c = 0; c < n; ++c) {
-        for (int32_t i = c; i < n; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int32_t k = c; k < i; ++k) s -= L[(size_t)i * n + k] * X[(size_t)k * n + c];
-            X[(size_t)i * n + c] = s / L[(size_t)i * n + i];
-        }
-    }
-    // A^{-1} = X^T X (symmetric by construction)
-    Ainv.assign((size_t)n * n, 0.0);
-    parallel_for(n, [&](int64_t i) {
-        for (int32_t j = 0; j < n; ++j) {
-            double s = 0.0;
-            int32_t k0 = std::max((int32_t)i, j);
-            for (int32_t k = k0; k < n; ++k) s += X[(size_t)k * n + i] * X[(size_t)k * n + j];
-            Ainv[(size_t)i * n + j] = s;
-        }
-    }, 16);
-}
-
 // ---------------------------------------------------------------- driver
 
 HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
@@ -348,6 +307,8 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
         std::vector<int32_t> mate(n, -1);
         int64_t pairs = suitor_matching(g, n, mate);
         if (pairs == 0) break;
+        // too little reduction on a level the dense solve can take: coarsest
+        if (n <= prm.max_dense && (double)n < prm.min_ratio * (double)(n - pairs)) break;
         cur.pairs = (int32_t)pairs;
         // aggregates numbered by smallest member
         cur.agg.assign(n, -1);
@@ -387,7 +348,6 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
     if (AL.n > prm.max_dense)
         throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
                                         " unknowns, above the dense-solve limit");
-    dense_factor_and_inverse(AL, H.coarse_chol, H.coarse_inv);
     return H;
 }
 

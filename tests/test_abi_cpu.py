@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_defaults():
     p = pamg.params()
-    assert (p.max_coarse, p.max_levels, p.max_dense, p.match_all_edges) == (200, 50, 4096, 0)
+    assert (p.max_coarse, p.max_levels, p.max_dense, p.match_all_edges) == (200, 50, 8192, 0)
+    assert p.min_ratio == 1.5
     o = pamg.solve_opts()
     assert o.tol == 1e-6 and o.maxit == 1000 and o.krylov == pamg.KRYLOV_FCG and o.check_every == 4
 
@@ -70,13 +71,25 @@ def test_symmetry_check_option():
     assert e.value.code == pamg.E_INVALID
 
 
-def test_not_spd_reported():
+def test_host_only_skips_the_coarse_factorization():
+    # the coarsest factorization runs on the device: an indefinite coarsest
+    # matrix still gives a host-only hierarchy (the device setup reports it)
     import scipy.sparse as sp
     M = sp.csr_matrix(np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 1.0]]))
     A = CSR(3, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
-    with pytest.raises(pamg.PamgError) as e:
-        pamg.Hierarchy(A, host_only=1)
-    assert e.value.code == pamg.E_NOT_SPD
+    H = pamg.Hierarchy(A, host_only=1)
+    assert H.levels == 1
+
+
+def test_stalled_coarsening_stops_like_the_oracle():
+    from test_oracle_pins import pairs_and_isolated, star_graph
+    for A, kw in [(star_graph(299), {}), (star_graph(299), {"min_ratio": 0.0}),
+                  (pairs_and_isolated(100, 100), {}), (pairs_and_isolated(99, 102), {}),
+                  (pairs_and_isolated(99, 102), {"max_dense": 250})]:
+        O = oracle.Hierarchy(A, **kw)
+        H = pamg.Hierarchy(A, host_only=1, **kw)
+        assert H.levels == O.nlevels
+        assert [H.info().n[l] for l in range(H.levels)] == [O.n(l) for l in range(O.nlevels)]
 
 
 def test_stall_reported():
@@ -94,7 +107,9 @@ def test_bad_params_rejected():
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, max_levels=0)
     with pytest.raises(pamg.PamgError):
-        pamg.Hierarchy(lap7(3), host_only=1, max_dense=5000)
+        pamg.Hierarchy(lap7(3), host_only=1, max_dense=8193)
+    with pytest.raises(pamg.PamgError):
+        pamg.Hierarchy(lap7(3), host_only=1, min_ratio=float("nan"))
 
 
 def test_host_only_hierarchy_refuses_device_calls():
@@ -112,6 +127,7 @@ CASES = {
     "q1_12_uniform": (lambda: q1_stretched(12, 1.0), {}),
     "q1_16_match_all": (lambda: q1_stretched(16, 1.05), {"match_all": True}),
     "lap7_16_small_coarse": (lambda: lap7(16), {"max_coarse": 20}),
+    "varcoef_36_stalled": (lambda: varcoef7(36, seed=5000), {}),
 }
 
 

@@ -24,6 +24,7 @@ CASES = {
     "q1_20": (lambda: q1_stretched(20, 1.05), 20),
     "varcoef_22": (lambda: varcoef7(22, seed=6), None),
     "single_level_lap7_5": (lambda: lap7(5), None),
+    "stalled_varcoef_48": (lambda: varcoef7(48, seed=5000), None),
 }
 KW = {"single_level_lap7_5": {"max_coarse": 1000}}
 

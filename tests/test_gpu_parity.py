@@ -58,8 +58,14 @@ CASES = {
     "varcoef_30": lambda: varcoef7(30, seed=5),
     "arrow_16": lambda: arrow_matrix(16),
     "single_level_lap7_5": lambda: lap7(5),
+    # lognormal coefficients: coarsening stalls and stops at 522 rows (the
+    # coarsest then runs on many workgroups)
+    "stalled_varcoef_48": lambda: varcoef7(48, seed=5000),
+    # one level of 2197 rows: the dense factorization over 35 tiles and the
+    # multi-workgroup coarse product that writes z
+    "single_level_lap7_13": lambda: lap7(13),
 }
-KW = {"single_level_lap7_5": {"max_coarse": 1000}}
+KW = {"single_level_lap7_5": {"max_coarse": 1000}, "single_level_lap7_13": {"max_coarse": 4000}}
 
 
 @pytest.fixture(scope="module")
@@ -265,3 +271,35 @@ def test_mixed_precision_solve(built, case):
     assert abs(info.iterations - it_or) <= max(2, it_or // 5)
     err = np.linalg.norm(xs - x_or) / np.linalg.norm(x_or)
     assert err <= 1e-4, f"FP32-preconditioned solution vs FP64 oracle: {err:.3e}"
+
+
+def test_device_factorization_reports_not_spd():
+    M = sp.csr_matrix(np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 1.0]]))
+    A = CSR(3, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
+    with pytest.raises(pamg.PamgError) as e:
+        pamg.Hierarchy(A)
+    assert e.value.code == pamg.E_NOT_SPD
+
+
+def test_dense_inverse_at_the_size_limit():
+    # 8000 unknowns on one level (125 x 125 tiles): the coarse solve against a
+    # sparse direct solve; cond of the 7-point Laplacian in closed form
+    import scipy.sparse.linalg as spla
+    n3 = 20
+    A = lap7(n3)
+    H = pamg.Hierarchy(A, build_f32=1, max_coarse=8192)
+    assert H.levels == 1
+    S = A.to_scipy().tocsc()
+    th = np.pi / (n3 + 1)
+    cond = (1 - np.cos(n3 * th)) / (1 - np.cos(th))
+    r = rand(A.n, 77)
+    ref = spla.spsolve(S, r)
+    for prec, tol in ((pamg.PREC_F64, max(1e-13, 16 * cond * EPS)), (pamg.PREC_F32, max(2e-6, 16 * cond * 6e-8))):
+        out = torch.empty(A.n, dtype=torch.float64, device="cuda:0")
+        H.debug_apply(pamg.OP_COARSE, 0, dev(r), out, precision=prec)
+        err = np.linalg.norm(host(out) - ref) / np.linalg.norm(ref)
+        assert err <= tol, f"precision {prec}: {err:.3e} (cond {cond:.3g})"
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    info = H.solve(dev(r), x, tol=1e-10)
+    assert info.status == pamg.OK and info.iterations <= 2
+    assert np.linalg.norm(host(x) - ref) <= 1e-10 * np.linalg.norm(ref) * cond

@@ -33,6 +33,10 @@ MUTANTS = {
     "l1_not_absolute": ("for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) d += fabs(a->v[k]);",
                         "for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) d += a->v[k];"),
     "pair_norm_wrong": ("double nu = sqrt(w[i] * w[i] + w[m] * w[m]);", "double nu = sqrt(w[i] * w[i] + w[i] * w[m]);"),
+    "stop_rule_not_strict": ("(double)A->n < min_ratio * (double)(A->n - pairs)",
+                             "(double)A->n <= min_ratio * (double)(A->n - pairs)"),
+    "stop_rule_ignores_dense_limit": ("if (A->n <= max_dense && (double)A->n < min_ratio",
+                                      "if ((double)A->n < min_ratio"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

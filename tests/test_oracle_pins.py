@@ -414,6 +414,73 @@ def test_diag_level_count_doubling_claim_of_plain_cg():
     assert its[-1] <= 2 * its[0] + 4
 
 
+# --------------------------------------------------------------------------- stalled coarsening
+
+def star_graph(k, hub=None):
+    """Hub 0 joined to spokes 1..k (a_0i = -1), diagonally dominant."""
+    n = k + 1
+    M = sp.lil_matrix((n, n))
+    M[0, 0] = float(k + 1) if hub is None else hub
+    for i in range(1, n):
+        M[0, i] = M[i, 0] = -1.0
+        M[i, i] = 2.0
+    return csr_from_scipy(M.tocsr())
+
+
+def pairs_and_isolated(n_pairs, n_iso):
+    """n_pairs disjoint edges plus n_iso isolated vertices."""
+    n = 2 * n_pairs + n_iso
+    M = sp.lil_matrix((n, n))
+    for q in range(n_pairs):
+        i, j = 2 * q, 2 * q + 1
+        M[i, i] = M[j, j] = 2.0
+        M[i, j] = M[j, i] = -1.0
+    for i in range(2 * n_pairs, n):
+        M[i, i] = 1.0
+    return csr_from_scipy(M.tocsr())
+
+
+def test_star_graph_stops_instead_of_shedding_one_pair_per_level():
+    # every edge meets the hub: each matching has exactly one pair, so without
+    # the stop rule level l has 300 - l rows until max_levels
+    A = star_graph(299)
+    off = oracle.Hierarchy(A, min_ratio=0.0)
+    assert off.nlevels == 50
+    assert [off.n(l) for l in range(50)] == [300 - l for l in range(50)]
+    assert all(off.pairs(l) == 1 for l in range(49))
+    on = oracle.Hierarchy(A)
+    assert on.nlevels == 1 and on.n(0) == 300
+
+
+def test_stop_rule_threshold_is_strict():
+    # 100 pairs of 300 rows: 300 == 1.5 * 200, coarsening goes on (to 200 <= max_coarse)
+    H = oracle.Hierarchy(pairs_and_isolated(100, 100))
+    assert H.nlevels == 2 and H.n(1) == 200 and H.pairs(0) == 100
+    # 99 pairs: 300 < 1.5 * 201, level 0 is the coarsest
+    H = oracle.Hierarchy(pairs_and_isolated(99, 102))
+    assert H.nlevels == 1
+    # above the dense limit the rule does not apply: level 1 (201 rows, no
+    # edges left) is the coarsest by the no-pair rule
+    H = oracle.Hierarchy(pairs_and_isolated(99, 102), max_dense=250)
+    assert H.nlevels == 2 and H.n(1) == 201
+
+
+def test_stop_rule_on_lognormal_coefficients():
+    # lognormal cell coefficients leave weakly coupled vertices unmatched on
+    # every level; the hierarchy stops where a matching would shrink a level
+    # by less than 1.5, and every earlier level shrank by at least that
+    A = varcoef7(36, seed=5000)
+    on = oracle.Hierarchy(A)
+    off = oracle.Hierarchy(A, min_ratio=0.0)
+    L = on.nlevels - 1
+    assert off.nlevels > on.nlevels
+    for l in range(on.nlevels):
+        assert on.n(l) == off.n(l)
+    for l in range(L):
+        assert on.n(l) >= 1.5 * on.n(l + 1)
+    assert on.n(L) > 200 and on.n(L) < 1.5 * off.n(L + 1)
+
+
 # --------------------------------------------------------------------------- failures
 
 def test_invalid_inputs_rejected():

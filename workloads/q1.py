@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .csr import CSR, from_dense_rows
+from .csr import CSR
 from .rng import SplitMix64
 
 _K1 = np.array([[1.0, -1.0], [-1.0, 1.0]])
@@ -70,56 +70,81 @@ def _dof_numbering(N: int) -> np.ndarray:
     return num.reshape(N + 1, N + 1, N + 1).transpose(2, 1, 0)
 
 
-def q1_stretched(N: int, ratio: float = 1.05) -> CSR:
-    """Assemble the Q1 stiffness matrix described in the module docstring."""
+def q1_stretched(N: int, ratio: float = 1.05, progress=None) -> CSR:
+    """Assemble the Q1 stiffness matrix described in the module docstring.
+
+    An entry depends on the x and y position of its row node only through
+    whether that node is on the first, an interior or the last plane (which
+    element corners exist), so the coefficients are summed once per such
+    class and gathered; the per-element sums keep the corner order.
+    ``progress(msg)`` is called after each stencil offset."""
     P = N + 1
     h = 1.0 / N
     z = node_z(N, ratio)
     hz = z[1:] - z[:-1]                       # (N,)
-    # coefficient arrays per node u = (i,j,k) for offsets d >= 0 in column order;
+    rep = np.array([0, min(1, N), N])         # a node of each class: first, interior, last
+    cls = np.ones(P, dtype=np.intp)
+    cls[0], cls[N] = 0, 2
+    kk = np.arange(P)
+    # coef[d][cx, cy, k]: entry (u, u + d) for offsets d >= 0 in column order;
     # the lower half is mirrored from the upper half for bitwise symmetry.
     upper = [d for d in _OFFS27 if (d[2], d[1], d[0]) >= (0, 0, 0)]
     coef = {}
-    ii = np.arange(P)
     for d in upper:
-        acc = np.zeros((P, P, P))
+        acc = np.zeros((3, 3, P))
         for a in _CORNERS:
             b = (a[0] + d[0], a[1] + d[1], a[2] + d[2])
             if min(b) < 0 or max(b) > 1:
                 continue
             # element e = u - a must exist: 0 <= u_c - a_c < N
-            vx = (ii - a[0] >= 0) & (ii - a[0] < N)
-            vy = (ii - a[1] >= 0) & (ii - a[1] < N)
-            ez = np.clip(ii - a[2], 0, N - 1)
-            vz = (ii - a[2] >= 0) & (ii - a[2] < N)
+            vx = (rep - a[0] >= 0) & (rep - a[0] < N)
+            vy = (rep - a[1] >= 0) & (rep - a[1] < N)
+            ez = np.clip(kk - a[2], 0, N - 1)
+            vz = (kk - a[2] >= 0) & (kk - a[2] < N)
             ent_z = np.where(vz, _elem_entry(a, b, hz[ez], h), 0.0)       # (P,)
             m = (vx[:, None, None] & vy[None, :, None] & vz[None, None, :])
             acc += np.where(m, ent_z[None, None, :], 0.0)
         coef[d] = acc
-    num = _dof_numbering(N)
-    n = int((num >= 0).sum())
-    cols = np.full((P, P, P, 27), -1, dtype=np.int32)
-    vals = np.zeros((P, P, P, 27))
-    I, J, K = np.meshgrid(ii, ii, ii, indexing="ij")
-    for s, d in enumerate(_OFFS27):
-        dx, dy, dz = d
-        inb = ((I + dx >= 0) & (I + dx <= N) & (J + dy >= 0) & (J + dy <= N)
-               & (K + dz >= 0) & (K + dz <= N))
-        Ix = np.clip(I + dx, 0, N)
-        Jy = np.clip(J + dy, 0, N)
-        Kz = np.clip(K + dz, 0, N)
-        c = np.where(inb, num[Ix, Jy, Kz], -1)
-        if d in coef:
-            v = coef[d]
-        else:  # mirror: a(u, u+d) = a(u+d, u) = coef[-d] at node u+d
-            v = coef[(-dx, -dy, -dz)][Ix, Jy, Kz]
-        cols[..., s] = c
-        vals[..., s] = np.where(inb, v, 0.0)
-    keep = (num >= 0).transpose(2, 1, 0)          # x-fastest order = dof order
-    cols = cols.transpose(2, 1, 0, 3)[keep]
-    vals = vals.transpose(2, 1, 0, 3)[keep]
-    mask = cols >= 0
-    return from_dense_rows(n, cols, vals, mask)
+    # kept nodes in dof order: lexicographic index lex = i + P j + P^2 k (x
+    # fastest) with the top layer k = N and the pinned node lex = 0 removed,
+    # so dof = lex - 1.  Rows are assembled in cache-sized chunks.
+    n = P * P * N - 1
+    chunk = 1 << 16
+    rp_parts, col_parts, val_parts = [], [], []
+    cols = np.empty((chunk, 27), dtype=np.int32)
+    vals = np.empty((chunk, 27))
+    next_report = 0.1
+    for r0 in range(0, n, chunk):
+        lex = np.arange(r0 + 1, min(n, r0 + chunk) + 1, dtype=np.int64)
+        m = lex.size
+        i = lex % P
+        j = (lex // P) % P
+        k = lex // (P * P)
+        ci, cj = cls[i], cls[j]
+        for s, d in enumerate(_OFFS27):
+            dx, dy, dz = d
+            i2, j2, k2 = i + dx, j + dy, k + dz
+            keep2 = ((i2 >= 0) & (i2 <= N) & (j2 >= 0) & (j2 <= N) & (k2 >= 0) & (k2 < N)
+                     & ~((i2 == 0) & (j2 == 0) & (k2 == 0)))
+            cols[:m, s] = np.where(keep2, lex + (dx + P * dy + P * P * dz) - 1, -1)
+            if d in coef:
+                vals[:m, s] = coef[d][ci, cj, k]
+            else:  # mirror: a(u, u+d) = a(u+d, u) = coef[-d] at node u+d
+                vals[:m, s] = coef[(-dx, -dy, -dz)][cls[np.clip(i2, 0, N)], cls[np.clip(j2, 0, N)],
+                                                    np.clip(k2, 0, N)]
+        mask = cols[:m] >= 0
+        rp_parts.append(mask.sum(axis=1))
+        col_parts.append(cols[:m][mask])
+        val_parts.append(vals[:m][mask])
+        if progress is not None and (r0 + m) / n >= next_report:
+            progress(f"Q1 {N}^3 assembly: {100 * (r0 + m) // n}% of rows")
+            next_report += 0.1
+    counts = np.concatenate(rp_parts)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 indices")
+    return CSR(n, row_ptr.astype(np.int32), np.concatenate(col_parts), np.concatenate(val_parts))
 
 
 def random_modes(seed: int, n_modes: int = 64, kmax: int = 8):
@@ -138,7 +163,7 @@ def random_modes(seed: int, n_modes: int = 64, kmax: int = 8):
     return k, amp, phase
 
 
-def velocity_field(N: int, ratio: float, seed: int) -> np.ndarray:
+def velocity_field(N: int, ratio: float, seed: int, progress=None) -> np.ndarray:
     """Nodal velocity u[c, i, j, k] (c = component) of the random smooth field."""
     k, amp, phase = random_modes(seed)
     x = np.arange(N + 1) / N
@@ -151,6 +176,8 @@ def velocity_field(N: int, ratio: float, seed: int) -> np.ndarray:
         s = np.imag(ex[:, None, None] * ey[None, :, None] * ez[None, None, :])
         for c in range(3):
             u[c] += amp[m, c] * s
+        if progress is not None and (m + 1) % 16 == 0:
+            progress(f"velocity field {N}^3: {m + 1}/{k.shape[0]} modes")
     return u
 
 
@@ -179,8 +206,8 @@ def divergence_rhs(N: int, ratio: float, u: np.ndarray) -> np.ndarray:
     return out
 
 
-def q1_rhs(N: int, ratio: float, seed: int) -> np.ndarray:
-    return divergence_rhs(N, ratio, velocity_field(N, ratio, seed))
+def q1_rhs(N: int, ratio: float, seed: int, progress=None) -> np.ndarray:
+    return divergence_rhs(N, ratio, velocity_field(N, ratio, seed, progress))
 
 
 def q1_rhs_sequence(N: int, ratio: float, seed: int, count: int = 16, amp: float = 0.05):
