@@ -412,8 +412,8 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     comps, wall = run(0, ncl, None)
     capacity = ncl / wall
     log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s")
-    # open loop: Poisson arrivals at 0.7 x capacity over the remaining requests
-    lam = 0.7 * capacity
+    # open loop: Poisson arrivals at half the capacity over the remaining requests
+    lam = 0.5 * capacity
     nol = args.requests - ncl
     arrivals = np.cumsum(SplitMix64(55).exponential(nol, lam))
     st1 = S.stats()
@@ -430,7 +430,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
         "unit": "solves/s",
         "higher_is_better": True,
         "config": {"workload": f"{args.requests} requests ({ncl} queued at once for the capacity, then {nol} "
-                               f"with Poisson arrivals at lambda = 0.7 x capacity) after a warm-up that caches every "
+                               f"with Poisson arrivals at lambda = 0.5 x capacity) after a warm-up that caches every "
                                f"operator's hierarchy; "
                                f"variable-coefficient 7-point operators (pool of {args.pool}, n^3 with n log-uniform "
                                f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "

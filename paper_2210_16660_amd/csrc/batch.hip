@@ -345,6 +345,10 @@ void batch_read_state(BatchEngine* E, hipStream_t s) {
     HIP_CHECK(hipStreamSynchronize(s));
 }
 
+void batch_read_state_async(BatchEngine* E, hipStream_t s) {
+    HIP_CHECK(hipMemcpyAsync(E->st_host, E->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+}
+
 void batch_write_state(BatchEngine* E, hipStream_t s) {
     HIP_CHECK(hipMemcpyAsync(E->st, E->st_host, sizeof(BatchState), hipMemcpyHostToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));

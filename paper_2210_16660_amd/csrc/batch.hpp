@@ -12,6 +12,9 @@ const BatchState& batch_state(const BatchEngine* E);
 BatchState& batch_state_host(BatchEngine* E);
 uint64_t batch_bytes(const BatchEngine* E);
 void batch_read_state(BatchEngine* E, hipStream_t s);
+// Enqueue the state copy to the host without waiting (the host copy is valid
+// once the stream has passed it, e.g. after an event recorded behind it).
+void batch_read_state_async(BatchEngine* E, hipStream_t s);
 void batch_write_state(BatchEngine* E, hipStream_t s);
 void batch_load(BatchEngine* E, const double* const* src, const double* tol, const int* maxit, const int* fixed,
                 int krylov, hipStream_t s);

@@ -13,8 +13,10 @@
 //     columns; a waiting request takes a free column between iteration blocks
 //     and its recurrence starts there (columns are independent, so a result
 //     is the same whatever else is in the group);
-//   * overlap: each tick launches one iteration block for every group with
-//     running columns before waiting on any, so the groups' work overlaps;
+//   * overlap: every group with running columns has one iteration block in
+//     flight on its own stream; a group whose block has finished (its event)
+//     is served at once, without waiting for the others, so small operators
+//     are not held back by large ones and the groups' work overlaps;
 //   * retirement: a column whose stopping test holds (or hit maxit) is copied
 //     out and freed at once; with the FP32 V-cycle its true residual is
 //     checked first and the recurrence restarted from it if needed.
@@ -64,7 +66,9 @@ struct ServeGroup {
     uint64_t last_used = 0;
     uint64_t bytes = 0;
     uint64_t iter_bytes = 0;     // algorithmic bytes of one batched iteration
-    bool launched = false;
+    hipEvent_t ev = nullptr;     // recorded behind the state copy of the block in flight
+    bool in_flight = false;
+    int iter_before[kW] = {};    // column iteration counts when the block was launched
 };
 
 }  // namespace pamg
@@ -91,6 +95,7 @@ struct pamg_server {
     std::map<uint64_t, pamg::SetupJob*> setups;      // keys queued, in progress or waiting for room
     uint64_t tick = 0;
     std::string fatal;
+    bool progressed = false;                         // scheduler-owned: the last tick did something
 };
 
 namespace pamg {
@@ -158,6 +163,7 @@ static void complete(pamg_server* S, ServeRequest* q, int status, int iters, dou
 static void evict(pamg_server* S, ServeGroup* g) {
     HIP_CHECK(hipStreamSynchronize(g->stream));
     pamg_hierarchy_destroy(g->h);
+    (void)hipEventDestroy(g->ev);
     (void)hipStreamDestroy(g->stream);
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -238,7 +244,9 @@ static void admit_ready(pamg_server* S) {
         while (in_use() + need > budget) {
             ServeGroup* lru = nullptr;
             for (auto& kv : S->groups)
-                if (kv.second->active == 0 && (!lru || kv.second->last_used < lru->last_used)) lru = kv.second;
+                if (kv.second->active == 0 && !kv.second->in_flight &&
+                    (!lru || kv.second->last_used < lru->last_used))
+                    lru = kv.second;
             if (!lru) { room = false; break; }       // everything busy: try again next tick
             evict(S, lru);
         }
@@ -246,11 +254,13 @@ static void admit_ready(pamg_server* S) {
         std::unique_ptr<ServeGroup> g(new ServeGroup());
         g->key = j->key;
         HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
         const double host_ms = j->built->host_ms;
         const auto t0 = Clock::now();
         try {
             g->h = finish_build(std::move(j->built), g->stream);
         } catch (const Error& e) {
+            (void)hipEventDestroy(g->ev);
             (void)hipStreamDestroy(g->stream);
             it = S->setups.erase(it);
             fail_key(S, j->key, e.code);
@@ -354,7 +364,23 @@ static void retire(pamg_server* S, ServeGroup* g) {
 
 static void scheduler_tick(pamg_server* S) {
     ++S->tick;
-    // 1. finished host phases become cached operators as the budget allows;
+    // 1. groups whose block has finished: account, retire finished columns
+    //    (before admission, so that waiting requests join between blocks)
+    uint64_t moved = 0;
+    for (auto& kv : S->groups) {
+        ServeGroup* g = kv.second;
+        if (!g->in_flight) continue;
+        const hipError_t q = hipEventQuery(g->ev);
+        if (q == hipErrorNotReady) continue;
+        HIP_CHECK(q);
+        g->in_flight = false;
+        int ran = 0;
+        for (int c = 0; c < kW; ++c) ran = std::max(ran, batch_state_host(g->E).col[c].iter - g->iter_before[c]);
+        moved += (uint64_t)ran * g->iter_bytes;
+        retire(S, g);
+        S->progressed = true;
+    }
+    // 2. finished host phases become cached operators as the budget allows;
     //    waiting requests take free columns of cached operators
     admit_ready(S);
     std::map<ServeGroup*, int> loads;
@@ -372,7 +398,7 @@ static void scheduler_tick(pamg_server* S) {
             continue;
         }
         ServeGroup* g = gi->second;
-        if (g->active >= kW) {
+        if (g->active >= kW || g->in_flight) {   // joins happen between blocks
             ++it;
             continue;
         }
@@ -402,32 +428,23 @@ static void scheduler_tick(pamg_server* S) {
         batch_read_state(g->E, g->stream);
         batch_load(g->E, src, tol, maxit, fixed, PAMG_KRYLOV_FCG, g->stream);
         retire(S, g);                    // zero right-hand sides finish at once
+        S->progressed = true;
     }
-    // 2. one iteration block for every group with running columns, all
-    //    launched before any is waited on
+    // 3. every idle group with running columns gets its next block, followed
+    //    by an asynchronous copy of its state and an event
     const int k = S->opts.block_iters;
     uint64_t blocks = 0;
     for (auto& kv : S->groups) {
         ServeGroup* g = kv.second;
-        g->launched = false;
-        if (g->active == 0 || batch_state_host(g->E).all_done) continue;
+        if (g->in_flight || g->active == 0 || batch_state_host(g->E).all_done) continue;
+        for (int c = 0; c < kW; ++c) g->iter_before[c] = batch_state_host(g->E).col[c].iter;
         batch_run_block(g->E, PAMG_KRYLOV_FCG, k, true, g->stream);
-        g->launched = true;
+        batch_read_state_async(g->E, g->stream);
+        HIP_CHECK(hipEventRecord(g->ev, g->stream));
+        g->in_flight = true;
         g->last_used = S->tick;
         ++blocks;
-    }
-    // 3. collect: read each group's state, retire finished columns
-    uint64_t moved = 0;
-    for (auto it = S->groups.begin(); it != S->groups.end();) {
-        ServeGroup* g = (it++)->second;
-        if (!g->launched) continue;
-        int before[kW];
-        for (int c = 0; c < kW; ++c) before[c] = batch_state_host(g->E).col[c].iter;
-        batch_read_state(g->E, g->stream);
-        int ran = 0;
-        for (int c = 0; c < kW; ++c) ran = std::max(ran, batch_state_host(g->E).col[c].iter - before[c]);
-        moved += (uint64_t)ran * g->iter_bytes;
-        retire(S, g);
+        S->progressed = true;
     }
     std::lock_guard<std::mutex> lk(S->mu);
     S->stats.blocks += blocks;
@@ -461,7 +478,13 @@ static void scheduler_main(pamg_server* S) {
                 }
             }
             auto t0 = Clock::now();
+            S->progressed = false;
             scheduler_tick(S);
+            if (!S->progressed) {
+                // blocks in flight, nothing finished yet: poll again shortly
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                continue;
+            }
             const double dt = ms_between(t0, Clock::now());
             std::lock_guard<std::mutex> lk(S->mu);
             S->stats.busy_ms += dt;
@@ -574,6 +597,7 @@ int pamg_server_destroy(pamg_server* S) {
         for (auto& kv : S->groups) {
             (void)hipStreamSynchronize(kv.second->stream);
             pamg_hierarchy_destroy(kv.second->h);
+            (void)hipEventDestroy(kv.second->ev);
             (void)hipStreamDestroy(kv.second->stream);
             for (auto* q : kv.second->col) delete q;
             delete kv.second;
