@@ -41,6 +41,13 @@ struct HostHierarchy {
 };
 
 // Device-ready layout of one level in hierarchical (aggregate-contiguous) order.
+struct TileDict {
+    std::vector<int32_t> span;      // 2 ints per tile: first dictionary entry, dictionary length
+    std::vector<int32_t> col;       // the dictionaries, tile after tile
+    std::vector<uint16_t> local;    // per matrix entry: position of its column in the tile's dictionary
+    int32_t max_len = 0;            // longest dictionary of the level
+};
+
 struct LayoutLevel {
     std::vector<int32_t> perm;      // canonical -> hierarchical index
     std::vector<int32_t> iperm;     // hierarchical -> canonical
@@ -52,10 +59,17 @@ struct LayoutLevel {
     int items = 8;                  // tile capacity of this level: items * kBlock entries
     std::vector<int32_t> down_tiles;  // 4 ints per restriction tile: k0, k1, c0, c1 (l < L)
     std::vector<int32_t> up_tiles;    // 4 ints per row tile: k0, k1, r0, r1
+    // Column dictionaries of the tiles: the distinct columns of a tile's
+    // entries, ascending, gathered once per tile into LDS; every entry stores
+    // the 16-bit position of its column in its tile's dictionary.  A tile
+    // holding one row / aggregate longer than a tile has no dictionary.
+    TileDict up_dict, down_dict;
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
-constexpr int kMaxItems = 8;         // matrix entries per thread per tile (largest tiles)
+constexpr int kMaxItems = 16;        // matrix entries per thread per tile (largest tiles)
+constexpr int kDictItems = 8;        // tiles of at least this many items per thread use column dictionaries
+constexpr int kDictMaxLarge = 3072;  // longest dictionary accepted for the largest tiles (LDS)
 constexpr int kTileRows = kBlock;    // at most one row (or aggregate) per thread in a tile
 constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep >= this many
 

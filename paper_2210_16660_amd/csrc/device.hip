@@ -62,13 +62,22 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
     V.built = true;
 }
 
+// Matrix bytes of one pass over a level in the tile format: values, 16-bit
+// dictionary positions, the tiles' dictionaries, descriptors (16 B) and spans
+// (8 B), and the row pointer.
+static uint64_t matrix_bytes(const DevLevelIdx& I, bool down, uint64_t s) {
+    const uint64_t dict = (uint64_t)(down ? I.down_dlen : I.up_dlen);
+    const uint64_t nt = (uint64_t)(down ? I.n_down : I.n_up);
+    return (uint64_t)I.nnz * (2 + s) + 4 * dict + 24 * nt + 4 * ((uint64_t)I.n + 1);
+}
+
 static uint64_t vcycle_bytes(const pamg_hierarchy* h, int s) {
-    // sum over l < L of 2 M_l + (10 n_l + 2 n_{l+1}) s, plus the coarse solve
+    // sum over l < L of the two matrix passes + (10 n_l + 2 n_{l+1}) s, plus the coarse solve
     uint64_t B = 0;
     for (int l = 0; l < h->L; ++l) {
-        const uint64_t n = h->idx[l].n, nc = h->idx[l + 1].n, nnz = h->idx[l].nnz;
-        const uint64_t M = nnz * (4 + s) + 4 * (n + 1);
-        B += 2 * M + (10 * n + 2 * nc) * s;
+        const DevLevelIdx& I = h->idx[l];
+        const uint64_t n = I.n, nc = h->idx[l + 1].n;
+        B += matrix_bytes(I, true, s) + matrix_bytes(I, false, s) + (10 * n + 2 * nc) * s;
     }
     const uint64_t nL = h->idx[h->L].n;
     B += (nL * nL + 2 * nL) * s;
@@ -92,10 +101,20 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
         I.iperm = upload<int>(h, Ly.iperm, s);
         I.up_tiles = reinterpret_cast<const int4*>(upload<int>(h, Ly.up_tiles, s));
         I.n_up = (int)Ly.up_tiles.size() / 4;
+        I.up_span = reinterpret_cast<const int2*>(upload<int>(h, Ly.up_dict.span, s));
+        I.up_col = upload<int>(h, Ly.up_dict.col, s);
+        I.up_loc = upload<uint16_t>(h, Ly.up_dict.local, s);
+        I.up_dmax = std::max(1, (int)Ly.up_dict.max_len);
+        I.up_dlen = (long long)Ly.up_dict.col.size();
         if (l + 1 < nl) {
             I.aggptr = upload<int>(h, Ly.aggptr, s);
             I.down_tiles = reinterpret_cast<const int4*>(upload<int>(h, Ly.down_tiles, s));
             I.n_down = (int)Ly.down_tiles.size() / 4;
+            I.down_span = reinterpret_cast<const int2*>(upload<int>(h, Ly.down_dict.span, s));
+            I.down_col = upload<int>(h, Ly.down_dict.col, s);
+            I.down_loc = upload<uint16_t>(h, Ly.down_dict.local, s);
+            I.down_dmax = std::max(1, (int)Ly.down_dict.max_len);
+            I.down_dlen = (long long)Ly.down_dict.col.size();
         }
     }
     upload_values<double>(h, h->f64, lay, s);
@@ -135,7 +154,7 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     h->info.operator_complexity = tot / (double)h->idx[0].nnz;
     h->info.vcycle_bytes_f64 = vcycle_bytes(h, 8);
     h->info.vcycle_bytes_f32 = build_f32 ? vcycle_bytes(h, 4) : 0;
-    h->info.spmv_bytes = (uint64_t)h->idx[0].nnz * 12 + 4 * ((uint64_t)n0 + 1) + 2 * 8 * (uint64_t)n0;
+    h->info.spmv_bytes = matrix_bytes(h->idx[0], false, 8) + 2 * 8 * (uint64_t)n0;
 }
 
 void destroy_hierarchy(pamg_hierarchy* h) {
@@ -169,7 +188,8 @@ static void with_items(int items, F&& f) {
         case 1: f(std::integral_constant<int, 1>{}); break;
         case 2: f(std::integral_constant<int, 2>{}); break;
         case 4: f(std::integral_constant<int, 4>{}); break;
-        default: f(std::integral_constant<int, 8>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default: f(std::integral_constant<int, 16>{}); break;
     }
 }
 
@@ -178,8 +198,9 @@ static void launch_down(const DevLevelIdx& I, const T* vd, const RT* r, const T*
                         hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_down<IT, T, RT>), tile_grid(I.n_down), 0, s, (const int*)I.rp, (const int*)I.ci, vd, r, p,
-               (const int*)I.aggptr, I.down_tiles, I.n_down, rc, done);
+        LAUNCH((k_down<IT, T, RT>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, vd, r, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
+               I.down_loc, rc, done);
     });
 }
 
@@ -189,8 +210,9 @@ static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r
                       double* partial, const int* done, hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_up<IT, T, RT, RTF, OUT>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, zp, r,
-               dinv, I.up_tiles, I.n_up, aggptr_f, r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        LAUNCH((k_up<IT, T, RT, RTF, OUT>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f, r_f,
+               dinv_f, p_f, zp_f, z_out, dv, partial, done);
     });
 }
 
@@ -199,8 +221,8 @@ static void launch_spmv(const DevLevelIdx& I, const T* v, const XT* x, const dou
                         hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, x, b, y,
-               I.up_tiles, I.n_up, partial);
+        LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, partial);
     });
 }
 
@@ -209,8 +231,9 @@ static void launch_krylov(const DevLevelIdx& I, const double* v, const double* z
                           hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), 0, s, (const int*)I.rp, (const int*)I.ci, v, z, p_old, p_new,
-               q, r, I.up_tiles, I.n_up, st, partial, done);
+        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), I.up_dmax * sizeof(double), s, (const int*)I.rp,
+               (const int*)I.ci, v, z, p_old, p_new, q, r, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, st,
+               partial, done);
     });
 }
 
@@ -561,7 +584,8 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
     const DevLevelIdx& I = h->idx[l];
     const int* nodone = h->zero_flag;
     const uint64_t n = I.n, nnz = I.nnz, sz = sizeof(T);
-    const uint64_t M = nnz * (4 + sz) + 4 * (n + 1);
+    const uint64_t M = matrix_bytes(I, op == PAMG_OP_DOWN, sz);
+    (void)nnz;
     std::function<void()> launch;
     if (op == PAMG_OP_DOWN) {
         if (l >= h->L) throw Error(PAMG_E_INVALID, "DOWN needs level < L");
@@ -604,7 +628,7 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
         launch = [=]() { launch_spmv<T, T>(I, V.v[l], V.dbg_in, nullptr, h->dbg1, nullptr, s); };
     } else if (op == PAMG_OP_KRYLOV) {
         if (l != 0) throw Error(PAMG_E_INVALID, "KRYLOV runs on level 0");
-        const uint64_t M8 = nnz * 12 + 4 * (n + 1);
+        const uint64_t M8 = matrix_bytes(I, false, 8);
         // matrix (FP64), z, p_old, r reads; p_new, q writes
         *bytes = M8 + 5 * n * 8;
         launch = [=]() {

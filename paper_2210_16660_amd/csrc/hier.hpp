@@ -42,6 +42,13 @@ struct DevLevelIdx {
     int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *perm = nullptr, *iperm = nullptr;
     const int4 *down_tiles = nullptr, *up_tiles = nullptr;
     int n_down = 0, n_up = 0;
+    // tile column dictionaries (per tile: first entry, length; the columns;
+    // per matrix entry: its 16-bit position in its tile's dictionary)
+    const int2 *up_span = nullptr, *down_span = nullptr;
+    const int *up_col = nullptr, *down_col = nullptr;
+    const uint16_t *up_loc = nullptr, *down_loc = nullptr;
+    int up_dmax = 1, down_dmax = 1;     // longest dictionary (dynamic LDS of the tile kernels)
+    long long up_dlen = 0, down_dlen = 0;  // total dictionary entries
 };
 
 }  // namespace pamg

@@ -108,12 +108,69 @@ __device__ __forceinline__ void tile_slots(int k0, int k1, int (&kk)[ITEMS]) {
     }
 }
 
+// Column dictionary of a tile (span = first entry in ucol, length): the
+// distinct columns of its entries, ascending.  The vector values at those
+// columns are gathered once per tile into LDS (s_x), so each distinct column
+// is fetched once and neighbouring lanes read neighbouring addresses; every
+// entry then reads its value from LDS through its 16-bit dictionary position.
+template <int ITEMS, typename T, class G>
+__device__ __forceinline__ void tile_dict_fill(int2 span, const int* __restrict__ ucol, T* s_x, G gather) {
+    int c[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int j = it * kBlock + (int)threadIdx.x;
+        if (it * kBlock < span.y) c[it] = ucol[span.x + (j < span.y ? j : span.y - 1)];
+    }
+    T x[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it)
+        if (it * kBlock < span.y) x[it] = gather(c[it]);
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int j = it * kBlock + (int)threadIdx.x;
+        if (it * kBlock < span.y && j < span.y) s_x[j] = x[it];
+    }
+}
+
+// Tiles of at least 2048 entries (the large levels) use the dictionary; the
+// small tiles of the small levels, where one more dependent load per tile
+// costs more than it saves, gather per entry.
+template <int ITEMS>
+constexpr bool tile_uses_dict() { return ITEMS >= kDictItems; }
+
+template <int ITEMS, typename T, class G>
+__device__ __forceinline__ void tile_direct(const int* __restrict__ ci, const int (&kk)[ITEMS], T (&x)[ITEMS],
+                                            G gather) {
+    int c[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) x[it] = gather(c[it]);
+}
+
 template <int ITEMS, typename T>
 __device__ __forceinline__ void tile_store(int k0, int k1, const T (&a)[ITEMS], const T (&x)[ITEMS], T* s_prod) {
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const int k = k0 + it * kBlock + (int)threadIdx.x;
         if (k < k1) s_prod[k - k0] = a[it] * x[it];
+    }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void tile_local(const uint16_t* __restrict__ loc, const int (&kk)[ITEMS],
+                                           uint16_t (&li)[ITEMS]) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) li[it] = ld_stream(&loc[kk[it]]);
+}
+
+template <int ITEMS, typename T>
+__device__ __forceinline__ void tile_store_dict(int k0, int k1, const T (&a)[ITEMS], const uint16_t (&li)[ITEMS],
+                                                const T* s_x, T* s_prod) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int k = k0 + it * kBlock + (int)threadIdx.x;
+        if (k < k1) s_prod[k - k0] = a[it] * s_x[li[it]];
     }
 }
 
@@ -125,34 +182,47 @@ template <int ITEMS, typename T, typename RT>
 static __global__ __launch_bounds__(kBlock) void k_down(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ ad,
     const RT* __restrict__ r, const T* __restrict__ p, const int* __restrict__ aggptr,
-    const int4* __restrict__ tiles, int ntiles, T* __restrict__ rc, const int* __restrict__ done) {
+    const int4* __restrict__ tiles, int ntiles,
+    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, T* __restrict__ rc, const int* __restrict__ done) {
     if (*done) return;
     __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     for (int t = w.first; t < w.end; t += w.stride) {
         const int4 d = tiles[t];
         const int k0 = d.x, k1 = d.y, c0 = d.z, c1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
-            int kk[ITEMS], c[ITEMS];
-            T a[ITEMS], x[ITEMS];
+            int kk[ITEMS];
+            T a[ITEMS];
+            uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
+            const auto gather = [&](int c) { return (T)r[c]; };
+            T x[ITEMS];
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_local<ITEMS>(loc, kk, li);
+            } else {
+                tile_direct<ITEMS, T>(ci, kk, x, gather);
+            }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&ad[kk[it]]);
             const int I = c0 + tid;
             const bool own = I < c1;
             const int Ic = own ? I : c1 - 1;
             const int m0 = aggptr[Ic], m1 = aggptr[Ic + 1];
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) x[it] = (T)r[c[it]];
             const int e0 = rp[m0], e1 = rp[m0 + 1], e2 = rp[m1];
             const T r0 = (T)r[m0], p0 = p[m0];
             const bool two = m1 - m0 >= 2;
             const T r1 = two ? (T)r[m0 + 1] : T(0), p1 = two ? p[m0 + 1] : T(0);
-            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                __syncthreads();                // dictionary values in LDS
+                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+            } else {
+                tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            }
             __syncthreads();
             if (own) {
                 T s = 0;
@@ -198,6 +268,7 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
     const int4* __restrict__ tiles, int ntiles,
+    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
     const T* __restrict__ p_f, T* __restrict__ zp_f,
     double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
@@ -206,6 +277,8 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double dot = 0.0;
@@ -213,11 +286,18 @@ static __global__ __launch_bounds__(kBlock) void k_up(
         const int4 d = tiles[t];
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
-            int kk[ITEMS], c[ITEMS];
-            T a[ITEMS], x[ITEMS];
+            int kk[ITEMS];
+            T a[ITEMS];
+            uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
+            const auto gather = [&](int c) { return zp[c]; };
+            T x[ITEMS];
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_local<ITEMS>(loc, kk, li);
+            } else {
+                tile_direct<ITEMS, T>(ci, kk, x, gather);
+            }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
@@ -228,8 +308,6 @@ static __global__ __launch_bounds__(kBlock) void k_up(
             const T ri = (T)r[ic];
             int a0 = 0, a1 = 0;
             if constexpr (!TO_OUT) { a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1]; }
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) x[it] = zp[c[it]];
             double dvi = 0.0;
             T rf0 = 0, df0 = 0, pf0 = 0, rf1 = 0, df1 = 0, pf1 = 0;
             if constexpr (TO_OUT) {
@@ -238,7 +316,12 @@ static __global__ __launch_bounds__(kBlock) void k_up(
                 rf0 = (T)r_f[a0]; df0 = dinv_f[a0]; pf0 = p_f[a0];
                 if (a1 - a0 >= 2) { rf1 = (T)r_f[a0 + 1]; df1 = dinv_f[a0 + 1]; pf1 = p_f[a0 + 1]; }
             }
-            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                __syncthreads();                // dictionary values in LDS
+                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+            } else {
+                tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            }
             __syncthreads();
             if (own) {
                 T s = 0;
@@ -403,10 +486,13 @@ template <int ITEMS, typename T, typename XT, typename YT>
 static __global__ __launch_bounds__(kBlock) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const XT* __restrict__ xv, const double* __restrict__ b, YT* __restrict__ y,
-    const int4* __restrict__ tiles, int ntiles, double* __restrict__ partial) {
+    const int4* __restrict__ tiles, int ntiles,
+    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, double* __restrict__ partial) {
     __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double nrm = 0.0;
@@ -414,11 +500,18 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
         const int4 d = tiles[t];
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
-            int kk[ITEMS], c[ITEMS];
-            T a[ITEMS], x[ITEMS];
+            int kk[ITEMS];
+            T a[ITEMS];
+            uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
+            const auto gather = [&](int c) { return (T)xv[c]; };
+            T x[ITEMS];
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_local<ITEMS>(loc, kk, li);
+            } else {
+                tile_direct<ITEMS, T>(ci, kk, x, gather);
+            }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
@@ -426,9 +519,12 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
             const double bi = b ? b[ic] : 0.0;
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) x[it] = (T)xv[c[it]];
-            tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                __syncthreads();                // dictionary values in LDS
+                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+            } else {
+                tile_store<ITEMS>(k0, k1, a, x, s_prod);
+            }
             __syncthreads();
             if (own) {
                 T s = 0;
@@ -458,18 +554,22 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
 
 // ----------------------------------------------------------------------------
 // Krylov step, part 1: p = z + beta p_old (p = z on the first iteration),
-// q = A p, partials of p.q and p.r.  p_j is formed at the gather from z and
-// p_old (ping-pong buffers), with the same expression as for the owned rows.
+// q = A p, partials of p.q and p.r.  p_j is formed in the tile's dictionary
+// from z and p_old (ping-pong buffers), with the same expression as for the
+// owned rows.
 template <int ITEMS>
 static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
     const double* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
     double* __restrict__ q, const double* __restrict__ r,
-    const int4* __restrict__ tiles, int ntiles, const SolveState* __restrict__ st,
-    double* __restrict__ partial, const int* __restrict__ done) {
+    const int4* __restrict__ tiles, int ntiles,
+    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc,
+    const SolveState* __restrict__ st, double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
     __shared__ double s_prod[ITEMS * kBlock];
     __shared__ double s_red[kBlock / 64];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    double* s_x = reinterpret_cast<double*>(s_dyn);
     const int tid = threadIdx.x;
     const bool first = st->first != 0;
     const double beta = st->beta;
@@ -479,11 +579,18 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
         const int4 d = tiles[t];
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
-            int kk[ITEMS], c[ITEMS];
-            double a[ITEMS], x[ITEMS];
+            int kk[ITEMS];
+            double a[ITEMS];
+            uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) c[it] = ld_stream(&ci[kk[it]]);
+            const auto gather = [&](int c) { return first ? z[c] : z[c] + beta * p_old[c]; };
+            double x[ITEMS];
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                tile_dict_fill<ITEMS, double>(span[t], ucol, s_x, gather);
+                tile_local<ITEMS>(loc, kk, li);
+            } else {
+                tile_direct<ITEMS, double>(ci, kk, x, gather);
+            }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
             const int i = i0 + tid;
@@ -491,19 +598,12 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
             const double zi = z[ic], poi = p_old[ic], ri = r[ic];
-            if (first) {
-#pragma unroll
-                for (int it = 0; it < ITEMS; ++it) x[it] = z[c[it]];
+            if constexpr (tile_uses_dict<ITEMS>()) {
+                __syncthreads();                // dictionary values in LDS
+                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
             } else {
-                double zc[ITEMS], pc[ITEMS];
-#pragma unroll
-                for (int it = 0; it < ITEMS; ++it) zc[it] = z[c[it]];
-#pragma unroll
-                for (int it = 0; it < ITEMS; ++it) pc[it] = p_old[c[it]];
-#pragma unroll
-                for (int it = 0; it < ITEMS; ++it) x[it] = zc[it] + beta * pc[it];
+                tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
-            tile_store<ITEMS>(k0, k1, a, x, s_prod);
             __syncthreads();
             if (own) {
                 double s = 0.0;

@@ -353,6 +353,49 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
 
 // ---------------------------------------------------------------- layout
 
+// Column dictionary of every tile (tiles given as 4 ints k0, k1, *, *).
+// Per tile: the distinct columns are collected with a per-worker position
+// array (n entries, reset after each tile), sorted, and every entry's column
+// is then looked up directly.
+static TileDict build_dicts(const std::vector<int32_t>& tiles, const std::vector<int32_t>& ci, int32_t n,
+                            int32_t cap) {
+    TileDict D;
+    const int64_t nt = (int64_t)tiles.size() / 4;
+    D.span.assign(2 * nt, 0);
+    D.local.assign(ci.size(), 0);
+    std::vector<std::vector<int32_t>> dict(nt);
+    parallel_ranges(nt, [&](int, int64_t b, int64_t e) {
+        std::vector<int32_t> pos(n, -1);
+        for (int64_t t = b; t < e; ++t) {
+            const int32_t k0 = tiles[4 * t], k1 = tiles[4 * t + 1];
+            if (k1 - k0 > cap) continue;
+            std::vector<int32_t>& u = dict[t];
+            for (int32_t k = k0; k < k1; ++k)
+                if (pos[ci[k]] < 0) {
+                    pos[ci[k]] = 0;
+                    u.push_back(ci[k]);
+                }
+            std::sort(u.begin(), u.end());
+            for (size_t j = 0; j < u.size(); ++j) pos[u[j]] = (int32_t)j;
+            for (int32_t k = k0; k < k1; ++k) D.local[k] = (uint16_t)pos[ci[k]];
+            for (int32_t c : u) pos[c] = -1;
+        }
+    });
+    int64_t total = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        D.span[2 * t] = (int32_t)total;
+        D.span[2 * t + 1] = (int32_t)dict[t].size();
+        D.max_len = std::max<int32_t>(D.max_len, (int32_t)dict[t].size());
+        total += (int64_t)dict[t].size();
+    }
+    if (total >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "tile dictionaries exceed 2^31 entries");
+    D.col.resize(total);
+    parallel_ranges(nt, [&](int, int64_t b, int64_t e) {
+        for (int64_t t = b; t < e; ++t) std::copy(dict[t].begin(), dict[t].end(), D.col.begin() + D.span[2 * t]);
+    });
+    return D;
+}
+
 // Hierarchical numbering: the coarsest level keeps its numbering; on every
 // finer level the members of each aggregate are placed next to each other,
 // in the order of their aggregate's (already permuted) coarse index, members
@@ -422,16 +465,14 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
         });
         // tile capacity: the largest power of two <= kMaxItems with at least
         // kTargetTiles tiles' worth of entries (small levels get small tiles)
-        {
-            const int64_t nnz = L.rp[n];
-            int items = kMaxItems;
-            while (items > 1 && (int64_t)items * kBlock * kTargetTiles > nnz) items /= 2;
+        int items = kMaxItems;
+        while (items > 1 && (int64_t)items * kBlock * kTargetTiles > (int64_t)L.rp[n]) items /= 2;
+        const int32_t nc = l + 1 < nl ? H.lev[l + 1].A.n : 0;
+        for (;;) {
             L.items = items;
-        }
-        const int32_t cap = L.items * kBlock;
-        // row tiles: <= kTileRows rows and <= cap entries, or a single long row
-        L.up_tiles.clear();
-        {
+            const int32_t cap = items * kBlock;
+            // row tiles: <= kTileRows rows and <= cap entries, or a single long row
+            L.up_tiles.clear();
             int32_t start = 0;
             while (start < n) {
                 int32_t end = start + 1;
@@ -439,13 +480,10 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
                 L.up_tiles.insert(L.up_tiles.end(), {L.rp[start], L.rp[end], start, end});
                 start = end;
             }
-        }
-        // restriction tiles over coarse rows: the fine rows of <= kTileRows
-        // aggregates holding <= cap entries, or a single aggregate
-        if (l + 1 < nl) {
-            const int32_t nc = H.lev[l + 1].A.n;
+            // restriction tiles over coarse rows: the fine rows of <= kTileRows
+            // aggregates holding <= cap entries, or a single aggregate
             L.down_tiles.clear();
-            int32_t start = 0;
+            start = 0;
             while (start < nc) {
                 int32_t end = start + 1;
                 while (end < nc && end - start < kTileRows &&
@@ -454,6 +492,16 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
                 L.down_tiles.insert(L.down_tiles.end(), {L.rp[L.aggptr[start]], L.rp[L.aggptr[end]], start, end});
                 start = end;
             }
+            if (items < kDictItems) break;            // small tiles gather per entry
+            L.up_dict = build_dicts(L.up_tiles, L.ci, n, cap);
+            if (nc > 0) L.down_dict = build_dicts(L.down_tiles, L.ci, n, cap);
+            // the largest tiles keep their dictionary within LDS, else halve them
+            if (items == kDictItems || std::max(L.up_dict.max_len, L.down_dict.max_len) <= kDictMaxLarge) break;
+            items /= 2;
+            L.up_dict = TileDict();
+            L.down_dict = TileDict();
+        }
+        if (l + 1 < nl) {
             // column-scaled values for the restriction pass: a_ij / d_j
             L.vd.resize(L.v.size());
             parallel_for(n, [&](int64_t ip) {
