@@ -289,6 +289,22 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
         torch.cuda.synchronize()
         return time.perf_counter() - t, its
 
+    info = H.info()
+    L = info.levels - 1
+
+    def batch_iter_bytes(s):
+        """Algorithmic bytes of one 16-column iteration: per level l < L two
+        passes over the matrix (int32 columns) and the n x 16 vectors, the
+        coarse GEMM, and the FP64 Krylov step at level 0."""
+        B = 0
+        for l in range(L):
+            n, nc, nnz = info.n[l], info.n[l + 1], info.nnz[l]
+            B += 2 * (nnz * (4 + s) + 4 * (n + 1)) + (10 * n + 2 * nc) * 16 * s
+        nL = info.n[L]
+        B += nL * nL * s + 2 * nL * 16 * s
+        B += info.nnz[0] * 12 + 4 * (info.n[0] + 1) + 12 * info.n[0] * 16 * 8
+        return B
+
     res = {}
     for name, prec in (("f64", pamg.PREC_F64), ("f32", pamg.PREC_F32)):
         run_batch(prec)                      # first call builds the engine and runs the autotuner
@@ -301,7 +317,9 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
         res[name] = {"batch_ms": round(1e3 * tb, 3), "single16_ms": round(1e3 * ts, 3),
                      "batch_solves_per_s": round(16 / tb, 2), "single_solves_per_s": round(16 / ts, 2),
                      "batch_iterations": [i.iterations for i in infos], "single_iterations": its,
-                     "max_true_relres": rel}
+                     "max_true_relres": rel,
+                     "batch_GBps": round(batch_iter_bytes(8 if name == "f64" else 4)
+                                         * max(i.iterations for i in infos) / tb / 1e9, 1)}
         log(f"{name}: batch {1e3 * tb:.1f} ms, 16 singles {1e3 * ts:.1f} ms, max true relres {rel:.2e}")
     cfg = H.batch_config(pamg.PREC_F32)
     out = {

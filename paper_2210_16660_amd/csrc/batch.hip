@@ -15,10 +15,11 @@
 
 namespace pamg {
 
-// kernel variants tried by the autotuner: unroll depth x columns per lane
-constexpr int kNumVariants = 6;
-static inline int variant_unroll(int v) { return v % 3 == 0 ? 1 : (v % 3 == 1 ? 2 : 4); }
-static inline int variant_cpl(int v) { return v < 3 ? 1 : 2; }
+// kernel variants tried by the autotuner: unroll depth (entries of a row
+// whose loads are in flight together) x columns per lane
+constexpr int kNumVariants = 10;
+static inline int variant_unroll(int v) { return 1 << (v % 5); }
+static inline int variant_cpl(int v) { return v < 5 ? 1 : 2; }
 
 template <typename F>
 static void with_variant(int v, F&& f) {
@@ -27,9 +28,13 @@ static void with_variant(int v, F&& f) {
         case 0: f(integral_constant<int, 1>{}, integral_constant<int, 1>{}); break;
         case 1: f(integral_constant<int, 2>{}, integral_constant<int, 1>{}); break;
         case 2: f(integral_constant<int, 4>{}, integral_constant<int, 1>{}); break;
-        case 3: f(integral_constant<int, 1>{}, integral_constant<int, 2>{}); break;
-        case 4: f(integral_constant<int, 2>{}, integral_constant<int, 2>{}); break;
-        default: f(integral_constant<int, 4>{}, integral_constant<int, 2>{}); break;
+        case 3: f(integral_constant<int, 8>{}, integral_constant<int, 1>{}); break;
+        case 4: f(integral_constant<int, 16>{}, integral_constant<int, 1>{}); break;
+        case 5: f(integral_constant<int, 1>{}, integral_constant<int, 2>{}); break;
+        case 6: f(integral_constant<int, 2>{}, integral_constant<int, 2>{}); break;
+        case 7: f(integral_constant<int, 4>{}, integral_constant<int, 2>{}); break;
+        case 8: f(integral_constant<int, 8>{}, integral_constant<int, 2>{}); break;
+        default: f(integral_constant<int, 16>{}, integral_constant<int, 2>{}); break;
     }
 }
 
@@ -221,7 +226,7 @@ static void autotune(BatchEngine* E, DevVals<T>& V, hipStream_t s) {
     pamg_hierarchy* h = E->h;
     const int L = h->L;
     const int* nodone = h->zero_flag;
-    E->cfg_down.assign(L + 1, 2);
+    E->cfg_down.assign(L + 1, 2);              // unroll 4, one column per lane until tuned
     E->cfg_up.assign(L + 1, 2);
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
@@ -582,7 +587,7 @@ void batch_config(pamg_hierarchy* h, int prec, int32_t* cfg) {
     for (int l = 0; l < L; ++l) {
         cfg[4 * l + 0] = variant_unroll(E->cfg_down[l]);
         cfg[4 * l + 1] = variant_cpl(E->cfg_down[l]);
-        cfg[4 * l + 2] = l > 0 ? variant_unroll(E->cfg_up[l]) : 4;
+        cfg[4 * l + 2] = l > 0 ? variant_unroll(E->cfg_up[l]) : 8;
         cfg[4 * l + 3] = l > 0 ? variant_cpl(E->cfg_up[l]) : 1;
     }
 }

@@ -197,7 +197,7 @@ static __global__ __launch_bounds__(kBlock) void kb_up(int n, const int* __restr
 }
 
 // Level-0 up-sweep: z = zp + D^-1 (r - A zp) written in FP64, with per-column
-// partials of z . dv.  Fixed shape (one lane per column, unroll 4): its
+// partials of z . dv.  Fixed shape (one lane per column, unroll 8): its
 // partial sums must not depend on tuning.
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -213,7 +213,7 @@ static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __rest
     double dot = 0.0;
     for (int i = w.first; i < w.end; i += w.stride) {
         T s[1] = {0};
-        row_accumulate<4, 1, T, T>(rp[i], rp[i + 1], ci, av, zp, lane, s);
+        row_accumulate<8, 1, T, T>(rp[i], rp[i + 1], ci, av, zp, lane, s);
         const size_t e = (size_t)i * kW + lane;
         const T z = zp[e] + dinv[i] * ((T)r[e] - s[0]);
         z_out[e] = (double)z;
@@ -386,21 +386,22 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
         double s = 0.0;
         const int kb = rp[i], ke = rp[i + 1];
         int k = kb;
-        for (; k + 4 <= ke; k += 4) {
-            int c[4];
-            double a[4], zc[4], pc[4];
+        constexpr int U = 8;
+        for (; k + U <= ke; k += U) {
+            int c[U];
+            double a[U], zc[U], pc[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] = ci[k + u];
+            for (int u = 0; u < U; ++u) c[u] = ci[k + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = av[k + u];
+            for (int u = 0; u < U; ++u) a[u] = av[k + u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) zc[u] = z[(size_t)c[u] * kW + lane];
+            for (int u = 0; u < U; ++u) zc[u] = z[(size_t)c[u] * kW + lane];
             if (!first) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) pc[u] = p_old[(size_t)c[u] * kW + lane];
+                for (int u = 0; u < U; ++u) pc[u] = p_old[(size_t)c[u] * kW + lane];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s += a[u] * (first ? zc[u] : zc[u] + beta * pc[u]);
+            for (int u = 0; u < U; ++u) s += a[u] * (first ? zc[u] : zc[u] + beta * pc[u]);
         }
         for (; k < ke; ++k) {
             const size_t e = (size_t)ci[k] * kW + lane;
