@@ -44,8 +44,11 @@ def kernels_hash() -> str:
     return hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
 
 
-def traffic_for(kernel: str):
-    """Counter-measured HBM bytes per launch of `kernel`, if measured on this source."""
+def traffic_for(kernel: str, measured_config: bool = True):
+    """Counter-measured HBM bytes per launch of `kernel`, if measured on this
+    source and this configuration (FP64 V-cycle, pairwise levels)."""
+    if not measured_config:
+        return None
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -90,6 +93,8 @@ def main() -> int:
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=200.0)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--agg-steps", type=int, default=1,
+                    help="aggregate-size composition: keep every n-th pairwise level (aggregates up to 2^n)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,7 +128,7 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
-    H = pamg.Hierarchy(A, build_f32=1 if prec == pamg.PREC_F32 else 0)
+    H = pamg.Hierarchy(A, build_f32=1 if prec == pamg.PREC_F32 else 0, agg_steps=args.agg_steps)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = H.info()
@@ -188,7 +193,7 @@ def main() -> int:
     dom = max(kern, key=lambda k: kern[k]["ms"])
     dk = kern[dom]
     copy_gbs, _ = copy_bandwidth(torch)
-    traffic = traffic_for(dom)
+    traffic = traffic_for(dom, prec == pamg.PREC_F64 and args.agg_steps == 1)
     log(f"V-cycle {v_ms:.3f} ms ({v_gbs:.0f} GB/s), SpMV {s_ms:.3f} ms ({s_gbs:.0f} GB/s); "
         + ", ".join(f"{k} {v['ms']:.4f} ms {v['GBps']:.0f} GB/s" for k, v in kern.items()))
 
@@ -211,6 +216,7 @@ def main() -> int:
                         f"l1-Jacobi 1+1, dense coarse solve) to {args.tol:g}",
             "n": A.n, "nnz": A.nnz, "levels": info.levels,
             "operator_complexity": round(info.operator_complexity, 4),
+            "aggregate_steps": args.agg_steps,
         },
         "iterations": iters[0],
         "relres_true": relres_true,
@@ -238,7 +244,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
-        O = oracle.Hierarchy(A)
+        O = oracle.Hierarchy(A, agg_steps=args.agg_steps)
         t_or_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         _, it_or, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=args.cpu_iters)

@@ -73,7 +73,10 @@ typedef struct {
                                  n_l < min_ratio * n_{l+1} is the coarsest (default 1.5; <= 1: off).
                                  The paper does not say when coarsening stops if matching stalls
                                  (weakly coupled vertices that stay singletons on every level). */
-    int32_t reserved[8];
+    int32_t agg_steps;        /* aggregate-size composition (Sec. 3.1): keep every agg_steps-th level of
+                                 the pairwise hierarchy, prolongators multiplied in between, so that
+                                 aggregates hold up to 2^agg_steps unknowns (default 1: pairs; 1..4) */
+    int32_t reserved[7];
 } pamg_params;
 
 typedef struct {

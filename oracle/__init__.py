@@ -48,7 +48,7 @@ def lib():
             L = C.CDLL(_LIB)
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.oracle_setup.argtypes = [C.c_int, ip, ip, dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
-                                   C.POINTER(vp)]
+                                   C.c_int, C.POINTER(vp)]
         L.oracle_setup.restype = C.c_int
         L.oracle_round_f32.argtypes = [vp, C.POINTER(vp)]
         L.oracle_round_f32.restype = C.c_int
@@ -106,7 +106,7 @@ class Hierarchy:
     """The oracle's AMG hierarchy in canonical (setup) numbering."""
 
     def __init__(self, A, max_coarse=200, max_levels=50, max_dense=8192, min_ratio=1.5, match_all=False,
-                 _handle=None):
+                 agg_steps=1, _handle=None):
         L = lib()
         if _handle is not None:
             self._h = _handle
@@ -116,7 +116,7 @@ class Hierarchy:
         h = C.c_void_p()
         rc = L.oracle_setup(int(A.n), _p(self._keep[0], C.c_int), _p(self._keep[1], C.c_int),
                             _p(self._keep[2], C.c_double), max_coarse, max_levels, max_dense,
-                            float(min_ratio), 1 if match_all else 0, C.byref(h))
+                            float(min_ratio), 1 if match_all else 0, int(agg_steps), C.byref(h))
         if rc != 0:
             raise OracleError(rc, "oracle_setup")
         self._h = h

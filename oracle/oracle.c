@@ -51,6 +51,14 @@
  *      can stay singletons on every level while everything else merges, so
  *      that later levels shed one pair each.)  min_ratio <= 1 turns the
  *      rule off; above max_dense coarsening always continues.
+ *   R12 aggregate-size composition (Sec. 3.1: aggregates larger than pairs
+ *      by multiplying successive pairwise prolongators): with agg_steps = s,
+ *      the pairwise hierarchy is built as above and only levels 0, s, 2s, ...
+ *      and the coarsest are kept; the prolongator from a kept level to the
+ *      next is the product of the pairwise ones in between, itself piecewise
+ *      constant: agg(i) follows the chain of aggregates and p(i) is the
+ *      product of the chain's p values, multiplied finest first.  The kept
+ *      coarse matrices are the pairwise Galerkin matrices (the same sums).
  *   R10 Krylov: PCG, or FCG(1) with beta = -(z.q_old)/delta_old and
  *      alpha = (p.r)/delta; dot products summed in index order.
  */
@@ -307,6 +315,61 @@ static int dense_cholesky(const or_csr *a, double **out) {
 
 /* ------------------------------------------------------------ setup */
 
+/* ------------------------------------------ aggregate-size composition (R12) */
+
+/* Keep levels 0, s, 2s, ... and the coarsest; compose the prolongators in
+ * between (agg along the chain, p multiplied finest first). */
+static int compose_levels(or_hier *h, int s) {
+    const int L = h->nlev - 1;
+    int kept[OR_MAX_LEVELS], nk = 0;
+    for (int l = 0; l < L; l += s) kept[nk++] = l;
+    kept[nk++] = L;
+    or_hier tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    for (int j = 0; j < nk; ++j) {
+        const int a = kept[j];
+        tmp.A[j] = h->A[a];
+        tmp.w[j] = h->w[a];
+        tmp.dinv[j] = h->dinv[a];
+        h->A[a].rp = NULL; h->A[a].ci = NULL; h->A[a].v = NULL;
+        h->w[a] = NULL; h->dinv[a] = NULL;
+        if (j + 1 == nk) break;
+        const int b = kept[j + 1], n = tmp.A[j].n;
+        int *agg = (int *)malloc(sizeof(int) * (size_t)n);
+        double *p = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!agg || !p) { free(agg); free(p); return OR_E_OOM; }
+        for (int i = 0; i < n; ++i) {
+            int I = h->agg[a][i];
+            double pc = h->p[a][i];
+            for (int m = a + 1; m < b; ++m) {
+                pc = pc * h->p[m][I];
+                I = h->agg[m][I];
+            }
+            agg[i] = I;
+            p[i] = pc;
+        }
+        tmp.agg[j] = agg;
+        tmp.p[j] = p;
+        tmp.n_pairs[j] = h->n_pairs[a];
+    }
+    /* free what was not moved, then install the kept levels */
+    for (int l = 0; l < OR_MAX_LEVELS; ++l) {
+        csr_free(&h->A[l]);
+        free(h->w[l]); free(h->dinv[l]); free(h->agg[l]); free(h->p[l]);
+        h->w[l] = NULL; h->dinv[l] = NULL; h->agg[l] = NULL; h->p[l] = NULL; h->n_pairs[l] = 0;
+    }
+    for (int j = 0; j < nk; ++j) {
+        h->A[j] = tmp.A[j];
+        h->w[j] = tmp.w[j];
+        h->dinv[j] = tmp.dinv[j];
+        h->agg[j] = tmp.agg[j];
+        h->p[j] = tmp.p[j];
+        h->n_pairs[j] = tmp.n_pairs[j];
+    }
+    h->nlev = nk;
+    return OR_OK;
+}
+
 static int validate(int n, const int *rp, const int *ci, const double *v) {
     if (n <= 0 || !rp || !ci || !v) return OR_E_INVALID;
     if (rp[0] != 0) return OR_E_INVALID;
@@ -325,11 +388,11 @@ static int validate(int n, const int *rp, const int *ci, const double *v) {
 
 int oracle_setup(int n, const int *rp, const int *ci, const double *v,
                  int max_coarse, int max_levels, int max_dense, double min_ratio, int match_all,
-                 or_hier **out) {
+                 int agg_steps, or_hier **out) {
     *out = NULL;
     int st = validate(n, rp, ci, v);
     if (st) return st;
-    if (max_levels < 1 || max_levels > OR_MAX_LEVELS) return OR_E_INVALID;
+    if (max_levels < 1 || max_levels > OR_MAX_LEVELS || agg_steps < 1) return OR_E_INVALID;
     or_hier *h = (or_hier *)calloc(1, sizeof(or_hier));
     if (!h) return OR_E_OOM;
     or_csr *A0 = &h->A[0];
@@ -375,6 +438,11 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
     }
     h->nlev = l + 1;
     if (h->A[l].n > max_dense) { oracle_free(h); return OR_E_STALLED; }
+    if (agg_steps > 1) {
+        st = compose_levels(h, agg_steps);
+        if (st) { oracle_free(h); return st; }
+        l = h->nlev - 1;
+    }
     st = dense_cholesky(&h->A[l], &h->chol);
     if (st) { oracle_free(h); return st; }
     *out = h;

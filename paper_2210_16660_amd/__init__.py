@@ -32,7 +32,7 @@ class pamg_params(C.Structure):
     _fields_ = [("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("max_dense", C.c_int32),
                 ("match_all_edges", C.c_int32), ("build_f32", C.c_int32), ("num_threads", C.c_int32),
                 ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("min_ratio", C.c_double),
-                ("reserved", C.c_int32 * 8)]
+                ("agg_steps", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class pamg_solve_opts(C.Structure):

@@ -275,6 +275,43 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
     });
 }
 
+// ------------------------------------------ aggregate-size composition
+
+// Keep levels 0, s, 2s, ... and the coarsest of the pairwise hierarchy; the
+// prolongator between kept levels is the product of the pairwise ones in
+// between (Sec. 3.1): agg follows the chain, p is multiplied finest first.
+static void compose_levels(HostHierarchy& H, int s) {
+    const int L = (int)H.lev.size() - 1;
+    std::vector<int> kept;
+    for (int l = 0; l < L; l += s) kept.push_back(l);
+    kept.push_back(L);
+    std::vector<HostLevel> out(kept.size());
+    for (size_t j = 0; j < kept.size(); ++j) {
+        const int a = kept[j];
+        HostLevel& o = out[j];
+        o.A = std::move(H.lev[a].A);
+        o.w = std::move(H.lev[a].w);
+        o.dinv = std::move(H.lev[a].dinv);
+        o.pairs = H.lev[a].pairs;
+        if (j + 1 == kept.size()) break;
+        const int b = kept[j + 1];
+        const int32_t n = o.A.n;
+        o.agg.resize(n);
+        o.p.resize(n);
+        parallel_for(n, [&](int64_t i) {
+            int32_t I = H.lev[a].agg[i];
+            double pc = H.lev[a].p[i];
+            for (int m = a + 1; m < b; ++m) {
+                pc = pc * H.lev[m].p[I];
+                I = H.lev[m].agg[I];
+            }
+            o.agg[i] = I;
+            o.p[i] = pc;
+        });
+    }
+    H.lev = std::move(out);
+}
+
 // ---------------------------------------------------------------- driver
 
 HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
@@ -348,6 +385,7 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
     if (AL.n > prm.max_dense)
         throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
                                         " unknowns, above the dense-solve limit");
+    if (prm.agg_steps > 1) compose_levels(H, prm.agg_steps);
     return H;
 }
 
@@ -414,11 +452,14 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
     for (int l = nl - 2; l >= 0; --l) {
         const HostLevel& hl = H.lev[l];
         const int32_t n = hl.A.n, nc = H.lev[l + 1].A.n;
-        // canonical members of each canonical aggregate, ascending
-        std::vector<int32_t> first(nc, -1), second(nc, -1);
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t I = hl.agg[i];
-            if (first[I] < 0) first[I] = i; else second[I] = i;
+        // canonical members of each canonical aggregate, ascending (pairs,
+        // or up to 2^s members with aggregate-size composition)
+        std::vector<int32_t> mptr(nc + 1, 0), mem(n);
+        for (int32_t i = 0; i < n; ++i) ++mptr[hl.agg[i] + 1];
+        for (int32_t I = 0; I < nc; ++I) mptr[I + 1] += mptr[I];
+        {
+            std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1);
+            for (int32_t i = 0; i < n; ++i) mem[fill[hl.agg[i]]++] = i;
         }
         LayoutLevel& L = out[l];
         L.iperm.resize(n);
@@ -429,8 +470,7 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
         for (int32_t Ip = 0; Ip < nc; ++Ip) {
             int32_t I = cip[Ip];
             L.aggptr[Ip] = q;
-            L.iperm[q++] = first[I];
-            if (second[I] >= 0) L.iperm[q++] = second[I];
+            for (int32_t k = mptr[I]; k < mptr[I + 1]; ++k) L.iperm[q++] = mem[k];
         }
         L.aggptr[nc] = q;
         for (int32_t ip = 0; ip < n; ++ip) L.perm[L.iperm[ip]] = ip;

@@ -110,6 +110,8 @@ def test_bad_params_rejected():
         pamg.Hierarchy(lap7(3), host_only=1, max_dense=8193)
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, min_ratio=float("nan"))
+    with pytest.raises(pamg.PamgError):
+        pamg.Hierarchy(lap7(3), host_only=1, agg_steps=5)
 
 
 def test_host_only_hierarchy_refuses_device_calls():
@@ -128,6 +130,8 @@ CASES = {
     "q1_16_match_all": (lambda: q1_stretched(16, 1.05), {"match_all": True}),
     "lap7_16_small_coarse": (lambda: lap7(16), {"max_coarse": 20}),
     "varcoef_36_stalled": (lambda: varcoef7(36, seed=5000), {}),
+    "q1_16_composed3": (lambda: q1_stretched(16, 1.05), {"agg_steps": 3}),
+    "varcoef_20_composed2": (lambda: varcoef7(20, seed=5), {"agg_steps": 2}),
 }
 
 
@@ -135,9 +139,10 @@ CASES = {
 def test_setup_bitexact_with_oracle(case):
     make, kw = CASES[case]
     A = make()
-    O = oracle.Hierarchy(A, max_coarse=kw.get("max_coarse", 200), match_all=kw.get("match_all", False))
+    O = oracle.Hierarchy(A, max_coarse=kw.get("max_coarse", 200), match_all=kw.get("match_all", False),
+                         agg_steps=kw.get("agg_steps", 1))
     H = pamg.Hierarchy(A, host_only=1, max_coarse=kw.get("max_coarse", 200),
-                       match_all_edges=int(kw.get("match_all", False)))
+                       match_all_edges=int(kw.get("match_all", False)), agg_steps=kw.get("agg_steps", 1))
     assert H.levels == O.nlevels
     for l in range(H.levels - 1):
         assert np.array_equal(H.aggregates(l), O.agg(l)), f"level {l} aggregates differ"

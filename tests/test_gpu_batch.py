@@ -25,8 +25,9 @@ CASES = {
     "varcoef_22": (lambda: varcoef7(22, seed=6), None),
     "single_level_lap7_5": (lambda: lap7(5), None),
     "stalled_varcoef_48": (lambda: varcoef7(48, seed=5000), None),
+    "varcoef_22_composed2": (lambda: varcoef7(22, seed=6), None),
 }
-KW = {"single_level_lap7_5": {"max_coarse": 1000}}
+KW = {"single_level_lap7_5": {"max_coarse": 1000}, "varcoef_22_composed2": {"agg_steps": 2}}
 
 
 @pytest.fixture(scope="module")

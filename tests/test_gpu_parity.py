@@ -64,8 +64,12 @@ CASES = {
     # one level of 2197 rows: the dense factorization over 35 tiles and the
     # multi-workgroup coarse product that writes z
     "single_level_lap7_13": lambda: lap7(13),
+    # aggregate-size composition: aggregates of up to 8 unknowns (every third
+    # pairwise level kept, prolongators multiplied)
+    "q1_24_composed3": lambda: q1_stretched(24, 1.05),
 }
-KW = {"single_level_lap7_5": {"max_coarse": 1000}, "single_level_lap7_13": {"max_coarse": 4000}}
+KW = {"single_level_lap7_5": {"max_coarse": 1000}, "single_level_lap7_13": {"max_coarse": 4000},
+      "q1_24_composed3": {"agg_steps": 3}}
 
 
 @pytest.fixture(scope="module")

@@ -37,6 +37,8 @@ MUTANTS = {
                              "(double)A->n <= min_ratio * (double)(A->n - pairs)"),
     "stop_rule_ignores_dense_limit": ("if (A->n <= max_dense && (double)A->n < min_ratio",
                                       "if ((double)A->n < min_ratio"),
+    "compose_drops_p": ("                pc = pc * h->p[m][I];", "                pc = pc * h->p[a][I];"),
+    "compose_wrong_chain": ("                I = h->agg[m][I];", "                I = h->agg[a][I];"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

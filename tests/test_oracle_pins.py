@@ -310,11 +310,11 @@ def _dense_B(H, l):
     return (np.eye(n) - E) @ np.linalg.inv(A)
 
 
-@pytest.mark.parametrize("case", ["lap7_6", "q1_4", "varcoef_6"])
+@pytest.mark.parametrize("case", ["lap7_6", "q1_4", "varcoef_6", "lap7_8_composed"])
 def test_vcycle_matches_multiplicative_composition(case):
     A = {"lap7_6": lambda: lap7(6), "q1_4": lambda: q1_stretched(4, 1.05),
-         "varcoef_6": lambda: varcoef7(6, seed=8)}[case]()
-    H = oracle.Hierarchy(A, max_coarse=12)
+         "varcoef_6": lambda: varcoef7(6, seed=8), "lap7_8_composed": lambda: lap7(8)}[case]()
+    H = oracle.Hierarchy(A, max_coarse=12, agg_steps=2 if case.endswith("composed") else 1)
     assert H.nlevels >= 3
     n = H.n(0)
     Bcols = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
@@ -479,6 +479,58 @@ def test_stop_rule_on_lognormal_coefficients():
     for l in range(L):
         assert on.n(l) >= 1.5 * on.n(l + 1)
     assert on.n(L) > 200 and on.n(L) < 1.5 * off.n(L + 1)
+
+
+# --------------------------------------------------------------------------- aggregate-size composition
+
+@pytest.mark.parametrize("steps", [2, 3])
+@pytest.mark.parametrize("case", ["lap7_16", "varcoef_14", "q1_8"])
+def test_composed_prolongator_is_product_of_pairwise(case, steps):
+    # Sec. 3.1: aggregates larger than pairs come from multiplying successive
+    # pairwise prolongators.  The composed hierarchy keeps every steps-th
+    # pairwise level; its prolongator equals the (scipy) product of the
+    # pairwise ones in between, bitwise, and its coarse matrices are the
+    # pairwise Galerkin matrices
+    A = {"lap7_16": lambda: lap7(16), "varcoef_14": lambda: varcoef7(14, seed=4),
+         "q1_8": lambda: q1_stretched(8, 1.05)}[case]()
+    P1 = oracle.Hierarchy(A)
+    C = oracle.Hierarchy(A, agg_steps=steps)
+    L1 = P1.nlevels - 1
+    kept = list(range(0, L1, steps)) + [L1]
+    assert C.nlevels == len(kept)
+    for j, a in enumerate(kept):
+        rp, ci, v = C.level(j)
+        orp, oci, ov = P1.level(a)
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci) and np.array_equal(v.view(np.uint64), ov.view(np.uint64))
+        if j + 1 == len(kept):
+            break
+        b = kept[j + 1]
+        prod = prolongator(P1, a)
+        for m in range(a + 1, b):
+            prod = (prod @ prolongator(P1, m)).tocsr()
+        prod.sort_indices()
+        Pc = prolongator(C, j).tocsr()
+        Pc.sort_indices()
+        assert prod.shape == Pc.shape and np.array_equal(prod.indices, Pc.indices)
+        assert np.array_equal(prod.data.view(np.uint64), Pc.data.view(np.uint64))
+        # Galerkin identity across the composed step (sums in another order)
+        Ac = (Pc.T @ C.level_scipy(j) @ Pc).toarray()
+        An = C.level_scipy(j + 1).toarray()
+        assert np.abs(Ac - An).max() <= 1e-12 * np.abs(An).max()
+        # aggregates of at most 2**(b - a) members
+        sizes = np.bincount(C.agg(j), minlength=C.n(j + 1))
+        assert sizes.min() >= 1 and sizes.max() <= 2 ** (b - a)
+
+
+def test_composed_hierarchy_solves():
+    A = varcoef7(16, seed=3)
+    b = uniform_rhs(A.n, 2)
+    for steps in (1, 2, 3):
+        H = oracle.Hierarchy(A, agg_steps=steps)
+        x, it, rr, st = H.solve(b, 1e-8)
+        assert st == 0
+        r = b - A.to_scipy() @ x
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
 
 
 # --------------------------------------------------------------------------- failures
