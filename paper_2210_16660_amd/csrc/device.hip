@@ -688,7 +688,7 @@ namespace pamg {
 
 std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm) {
     if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
-        prm.max_dense > kMaxDense || !(prm.min_ratio == prm.min_ratio) || prm.agg_steps < 1 || prm.agg_steps > 4)
+        prm.max_dense > kMaxDense || !(prm.min_ratio == prm.min_ratio) || prm.agg_steps < 1 || prm.agg_steps > kMaxAggSteps)
         throw Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
                                     "1 <= max_dense <= 8192, min_ratio not NaN, 1 <= agg_steps <= 4)");
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);

@@ -186,6 +186,7 @@ static __global__ __launch_bounds__(kBlock) void k_down(
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, T* __restrict__ rc, const int* __restrict__ done) {
     if (*done) return;
     __shared__ T s_prod[ITEMS * kBlock];
+    __shared__ T s_u[kBlock];
     __shared__ T s_red[kBlock / 64];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T* s_x = reinterpret_cast<T*>(s_dyn);
@@ -209,14 +210,19 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&ad[kk[it]]);
+            // phase 2: thread j finishes fine row f0 + j (the tile holds at
+            // most kBlock fine rows), u_m = p_m (r_m - s_m) into LDS; then
+            // thread j sums the members of coarse row c0 + j in order.
+            const int f0 = aggptr[c0], f1 = aggptr[c1];
+            const int m = f0 + tid;
+            const bool fown = m < f1;
+            const int mc = fown ? m : f1 - 1;
+            const int e0 = rp[mc], e1 = rp[mc + 1];
+            const T rm = (T)r[mc], pm = p[mc];
             const int I = c0 + tid;
             const bool own = I < c1;
             const int Ic = own ? I : c1 - 1;
-            const int m0 = aggptr[Ic], m1 = aggptr[Ic + 1];
-            const int e0 = rp[m0], e1 = rp[m0 + 1], e2 = rp[m1];
-            const T r0 = (T)r[m0], p0 = p[m0];
-            const bool two = m1 - m0 >= 2;
-            const T r1 = two ? (T)r[m0 + 1] : T(0), p1 = two ? p[m0 + 1] : T(0);
+            const int a0 = aggptr[Ic] - f0, a1 = aggptr[Ic + 1] - f0;
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
                 tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
@@ -224,24 +230,19 @@ static __global__ __launch_bounds__(kBlock) void k_down(
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
             __syncthreads();
-            if (own) {
+            if (fown) {
                 T s = 0;
                 for (int k = e0 - k0; k < e1 - k0; ++k) s += s_prod[k];
-                T acc = p0 * (r0 - s);
-                if (two) {
-                    const int e1b = (m1 - m0 == 2) ? e2 : rp[m0 + 2];
-                    s = 0;
-                    for (int k = e1 - k0; k < e1b - k0; ++k) s += s_prod[k];
-                    acc += p1 * (r1 - s);
-                    for (int m = m0 + 2; m < m1; ++m) {      // aggregates larger than pairs
-                        s = 0;
-                        for (int k = rp[m] - k0; k < rp[m + 1] - k0; ++k) s += s_prod[k];
-                        acc += p[m] * ((T)r[m] - s);
-                    }
-                }
-                rc[I] = acc;
+                s_u[tid] = pm * (rm - s);
             }
             __syncthreads();
+            if (own) {
+                T acc = s_u[a0];
+                for (int j = a0 + 1; j < a1; ++j) acc += s_u[j];
+                rc[I] = acc;
+            }
+            // no barrier here: the next tile writes s_x and s_prod (last read
+            // before the barrier above) and s_u only after two barriers
         } else {
             // one aggregate whose rows exceed a tile
             const int f0 = aggptr[c0], f1 = aggptr[c1];

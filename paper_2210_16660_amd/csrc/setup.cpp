@@ -520,13 +520,14 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
                 L.up_tiles.insert(L.up_tiles.end(), {L.rp[start], L.rp[end], start, end});
                 start = end;
             }
-            // restriction tiles over coarse rows: the fine rows of <= kTileRows
-            // aggregates holding <= cap entries, or a single aggregate
+            // restriction tiles over coarse rows: the <= kTileRows fine rows of
+            // <= kTileRows aggregates holding <= cap entries, or a single
+            // aggregate (at most 2^kMaxAggSteps members)
             L.down_tiles.clear();
             start = 0;
             while (start < nc) {
                 int32_t end = start + 1;
-                while (end < nc && end - start < kTileRows &&
+                while (end < nc && end - start < kTileRows && L.aggptr[end + 1] - L.aggptr[start] <= kTileRows &&
                        L.rp[L.aggptr[end + 1]] - L.rp[L.aggptr[start]] <= cap)
                     ++end;
                 L.down_tiles.insert(L.down_tiles.end(), {L.rp[L.aggptr[start]], L.rp[L.aggptr[end]], start, end});
