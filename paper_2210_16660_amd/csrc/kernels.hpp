@@ -278,6 +278,8 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
+    __shared__ T s_z[kBlock];                          // l > 0: z of the tile's rows
+    __shared__ uint8_t s_own[kBlock << kMaxAggSteps];  // l > 0: owning row of each fine row
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
@@ -307,15 +309,18 @@ static __global__ __launch_bounds__(kBlock) void k_up(
             const int rb = rp[ic], re = rp[ic + 1];
             const T zpi = zp[ic], di = dinv[ic];
             const T ri = (T)r[ic];
-            int a0 = 0, a1 = 0;
-            if constexpr (!TO_OUT) { a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1]; }
+            // l > 0: the fine rows F0..F1 of the tile's rows are prolongated
+            // one per thread (first chunk's operands loaded here)
+            int a0 = 0, a1 = 0, F0 = 0, F1 = 0;
             double dvi = 0.0;
-            T rf0 = 0, df0 = 0, pf0 = 0, rf1 = 0, df1 = 0, pf1 = 0;
+            T rf = 0, df = 0, pf = 0;
             if constexpr (TO_OUT) {
                 dvi = dv[ic];
             } else {
-                rf0 = (T)r_f[a0]; df0 = dinv_f[a0]; pf0 = p_f[a0];
-                if (a1 - a0 >= 2) { rf1 = (T)r_f[a0 + 1]; df1 = dinv_f[a0 + 1]; pf1 = p_f[a0 + 1]; }
+                a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1];
+                F0 = aggptr_f[i0]; F1 = aggptr_f[i1];
+                const int m = F0 + tid < F1 ? F0 + tid : F1 - 1;
+                rf = (T)r_f[m]; df = dinv_f[m]; pf = p_f[m];
             }
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
@@ -324,20 +329,33 @@ static __global__ __launch_bounds__(kBlock) void k_up(
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
             __syncthreads();
+            T z = 0;
             if (own) {
                 T s = 0;
                 for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
-                const T z = zpi + di * (ri - s);
-                if constexpr (TO_OUT) {
+                z = zpi + di * (ri - s);
+            }
+            if constexpr (TO_OUT) {
+                if (own) {
                     z_out[i] = (double)z;
                     dot += (double)z * dvi;
-                } else {
-                    zp_f[a0] = prolong_value(df0, rf0, pf0, z);
-                    if (a1 - a0 >= 2) zp_f[a0 + 1] = prolong_value(df1, rf1, pf1, z);
-                    for (int m = a0 + 2; m < a1; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
                 }
+                __syncthreads();
+            } else {
+                if (own) {
+                    s_z[tid] = z;
+                    for (int m = a0; m < a1; ++m) s_own[m - F0] = (uint8_t)tid;
+                }
+                __syncthreads();
+                if (F0 + tid < F1) zp_f[F0 + tid] = prolong_value(df, rf, pf, s_z[s_own[tid]]);
+                for (int j = tid + kBlock; j < F1 - F0; j += kBlock) {
+                    const int m = F0 + j;
+                    zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], s_z[s_own[j]]);
+                }
+                // no barrier here: the next tile writes s_x and s_prod (last
+                // read before the barrier above), s_z and s_own only after
+                // its own first barrier
             }
-            __syncthreads();
         } else {
             T s = 0;
             for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * zp[ci[k]];
