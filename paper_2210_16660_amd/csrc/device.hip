@@ -108,6 +108,8 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
         I.up_dlen = (long long)Ly.up_dict.col.size();
         if (l + 1 < nl) {
             I.aggptr = upload<int>(h, Ly.aggptr, s);
+            for (size_t c = 0; c + 1 < Ly.aggptr.size(); ++c)
+                I.max_agg = std::max(I.max_agg, Ly.aggptr[c + 1] - Ly.aggptr[c]);
             I.down_tiles = reinterpret_cast<const int4*>(upload<int>(h, Ly.down_tiles, s));
             I.n_down = (int)Ly.down_tiles.size() / 4;
             I.down_span = reinterpret_cast<const int2*>(upload<int>(h, Ly.down_dict.span, s));
@@ -204,15 +206,27 @@ static void launch_down(const DevLevelIdx& I, const T* vd, const RT* r, const T*
     });
 }
 
+// F: the finer level (l - 1) prolongated into, or nullptr at level 0 (OUT).
 template <typename T, typename RT, typename RTF, bool OUT>
-static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r, const T* dinv, const int* aggptr_f,
+static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r, const T* dinv, const DevLevelIdx* F,
                       const RTF* r_f, const T* dinv_f, const T* p_f, T* zp_f, double* z_out, const double* dv,
                       double* partial, const int* done, hipStream_t s) {
+    const int* aggptr_f = F ? (const int*)F->aggptr : nullptr;
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_up<IT, T, RT, RTF, OUT>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
-               (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f, r_f,
-               dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        if constexpr (OUT) {
+            LAUNCH((k_up<IT, T, RT, RTF, kUpOut>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+                   (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
+                   r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        } else if (F->max_agg <= 2) {
+            LAUNCH((k_up<IT, T, RT, RTF, kUpPair>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+                   (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
+                   r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        } else {
+            LAUNCH((k_up<IT, T, RT, RTF, kUpWide>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+                   (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
+                   r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
+        }
     });
 }
 
@@ -287,10 +301,10 @@ static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, do
         const DevLevelIdx& I = h->idx[l];
         const DevLevelIdx& Fi = h->idx[l - 1];
         if (l - 1 == 0)
-            launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], Fi.aggptr, r0, V.dinv[0], V.p[0],
+            launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &Fi, r0, V.dinv[0], V.p[0],
                                            V.zp[0], nullptr, nullptr, nullptr, done, s);
         else
-            launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], Fi.aggptr, V.r[l - 1], V.dinv[l - 1],
+            launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &Fi, V.r[l - 1], V.dinv[l - 1],
                                       V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr, done, s);
     }
     const DevLevelIdx& I0 = h->idx[0];
@@ -613,12 +627,12 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
             *bytes = M + 3 * n * sz + 4 * (n + 1) + nf * ((l - 1 == 0 ? 8 : sz) + 3 * sz);
             if (l - 1 == 0)
                 launch = [=]() {
-                    launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], F.aggptr, h->r, V.dinv[0],
+                    launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &F, h->r, V.dinv[0],
                                                    V.p[0], V.zp[0], nullptr, nullptr, nullptr, nodone, s);
                 };
             else
                 launch = [=]() {
-                    launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], F.aggptr, V.r[l - 1],
+                    launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &F, V.r[l - 1],
                                               V.dinv[l - 1], V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr,
                                               nodone, s);
                 };

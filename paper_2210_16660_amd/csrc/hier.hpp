@@ -38,6 +38,7 @@ struct BatchDeleter {
 
 struct DevLevelIdx {
     int n = 0, nc = 0, items = 8;
+    int max_agg = 0;                    // most rows in one aggregate of this level (l < L)
     long long nnz = 0;
     int *rp = nullptr, *ci = nullptr, *aggptr = nullptr, *perm = nullptr, *iperm = nullptr;
     const int4 *down_tiles = nullptr, *up_tiles = nullptr;

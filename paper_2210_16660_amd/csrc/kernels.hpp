@@ -264,7 +264,12 @@ static __global__ __launch_bounds__(kBlock) void k_down(
 //   l > 0: prolongate into level l-1:  zp_f[m] = dinv_f[m] r_f[m] + p_f[m] z_I
 //          for the members m of coarse row I (= this level's row);
 //   l = 0: write z (FP64) and accumulate the partial of z . dv.
-template <int ITEMS, typename T, typename RT, typename RTF, bool TO_OUT>
+// MODE: kUpOut (l = 0), kUpPair (aggregates of at most two rows: the row's
+// thread writes its members), kUpWide (larger aggregates: z is staged in LDS
+// and the tile's fine rows are written one per thread, coalesced).
+constexpr int kUpOut = 0, kUpPair = 1, kUpWide = 2;
+
+template <int ITEMS, typename T, typename RT, typename RTF, int MODE>
 static __global__ __launch_bounds__(kBlock) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
@@ -274,12 +279,13 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     const T* __restrict__ p_f, T* __restrict__ zp_f,
     double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
     const int* __restrict__ done) {
+    constexpr bool TO_OUT = MODE == kUpOut;
     if (*done) return;
     __shared__ T s_prod[ITEMS * kBlock];
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
-    __shared__ T s_z[kBlock];                          // l > 0: z of the tile's rows
-    __shared__ uint8_t s_own[kBlock << kMaxAggSteps];  // l > 0: owning row of each fine row
+    __shared__ T s_z[kBlock];                          // kUpWide: z of the tile's rows
+    __shared__ uint8_t s_own[kBlock << kMaxAggSteps];  // kUpWide: owning row of each fine row
     extern __shared__ __align__(16) unsigned char s_dyn[];
     T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
@@ -309,18 +315,22 @@ static __global__ __launch_bounds__(kBlock) void k_up(
             const int rb = rp[ic], re = rp[ic + 1];
             const T zpi = zp[ic], di = dinv[ic];
             const T ri = (T)r[ic];
-            // l > 0: the fine rows F0..F1 of the tile's rows are prolongated
-            // one per thread (first chunk's operands loaded here)
+            // operands of the prolongation, loaded before the barriers
             int a0 = 0, a1 = 0, F0 = 0, F1 = 0;
             double dvi = 0.0;
-            T rf = 0, df = 0, pf = 0;
-            if constexpr (TO_OUT) {
+            T rf0 = 0, df0 = 0, pf0 = 0, rf1 = 0, df1 = 0, pf1 = 0;
+            if constexpr (MODE == kUpOut) {
                 dvi = dv[ic];
+            } else if constexpr (MODE == kUpPair) {
+                a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1];
+                rf0 = (T)r_f[a0]; df0 = dinv_f[a0]; pf0 = p_f[a0];
+                if (a1 - a0 >= 2) { rf1 = (T)r_f[a0 + 1]; df1 = dinv_f[a0 + 1]; pf1 = p_f[a0 + 1]; }
             } else {
+                // the fine rows F0..F1 of the tile's rows, one per thread
                 a0 = aggptr_f[ic]; a1 = aggptr_f[ic + 1];
                 F0 = aggptr_f[i0]; F1 = aggptr_f[i1];
                 const int m = F0 + tid < F1 ? F0 + tid : F1 - 1;
-                rf = (T)r_f[m]; df = dinv_f[m]; pf = p_f[m];
+                rf0 = (T)r_f[m]; df0 = dinv_f[m]; pf0 = p_f[m];
             }
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
@@ -335,10 +345,17 @@ static __global__ __launch_bounds__(kBlock) void k_up(
                 for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
                 z = zpi + di * (ri - s);
             }
-            if constexpr (TO_OUT) {
+            if constexpr (MODE == kUpOut) {
                 if (own) {
                     z_out[i] = (double)z;
                     dot += (double)z * dvi;
+                }
+                __syncthreads();
+            } else if constexpr (MODE == kUpPair) {
+                if (own) {
+                    zp_f[a0] = prolong_value(df0, rf0, pf0, z);
+                    if (a1 - a0 >= 2) zp_f[a0 + 1] = prolong_value(df1, rf1, pf1, z);
+                    for (int m = a0 + 2; m < a1; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
                 }
                 __syncthreads();
             } else {
@@ -347,7 +364,7 @@ static __global__ __launch_bounds__(kBlock) void k_up(
                     for (int m = a0; m < a1; ++m) s_own[m - F0] = (uint8_t)tid;
                 }
                 __syncthreads();
-                if (F0 + tid < F1) zp_f[F0 + tid] = prolong_value(df, rf, pf, s_z[s_own[tid]]);
+                if (F0 + tid < F1) zp_f[F0 + tid] = prolong_value(df0, rf0, pf0, s_z[s_own[tid]]);
                 for (int j = tid + kBlock; j < F1 - F0; j += kBlock) {
                     const int m = F0 + j;
                     zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], s_z[s_own[j]]);
