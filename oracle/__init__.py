@@ -52,6 +52,8 @@ def lib():
         L.oracle_setup.restype = C.c_int
         L.oracle_round_f32.argtypes = [vp, C.POINTER(vp)]
         L.oracle_round_f32.restype = C.c_int
+        L.oracle_update.argtypes = [vp, dp, C.POINTER(vp)]
+        L.oracle_update.restype = C.c_int
         L.oracle_free.argtypes = [vp]
         for name in ("oracle_nlevels",):
             getattr(L, name).argtypes = [vp]
@@ -133,6 +135,18 @@ class Hierarchy:
         rc = lib().oracle_round_f32(self._h, C.byref(h))
         if rc != 0:
             raise OracleError(rc, "oracle_round_f32")
+        return Hierarchy(None, _handle=h)
+
+    def update(self, val) -> "Hierarchy":
+        """The hierarchy rebuilt for new values of A_0 (same pattern), keeping
+        every aggregate and prolongator (coefficient-only reuse)."""
+        v = np.ascontiguousarray(val, np.float64)
+        if v.shape != (self.nnz(0),):
+            raise ValueError("update values must have the pattern's nnz entries")
+        h = C.c_void_p()
+        rc = lib().oracle_update(self._h, _p(v, C.c_double), C.byref(h))
+        if rc != 0:
+            raise OracleError(rc, "oracle_update")
         return Hierarchy(None, _handle=h)
 
     @property

@@ -61,6 +61,15 @@
  *      coarse matrices are the pairwise Galerkin matrices (the same sums).
  *   R10 Krylov: PCG, or FCG(1) with beta = -(z.q_old)/delta_old and
  *      alpha = (p.r)/delta; dot products summed in index order.
+ *   R13 coefficient-only reuse (Sec. 4: when only the coefficients of A
+ *      change, the prolongators are kept and the coarse matrices and
+ *      smoothers rebuilt): new values of A_0 with the same pattern; every
+ *      pairwise step keeps its aggregates and p, its Galerkin matrix is
+ *      recomputed from the new fine values by R8, the l1 diagonals by R1 and
+ *      the coarsest factor anew.  With composition (R12) the whole pairwise
+ *      chain is recomputed and the kept levels are taken from it, so the
+ *      result is the hierarchy a setup would give if its matchings were
+ *      those of the original matrix.
  */
 #include <math.h>
 #include <stdint.h>
@@ -94,6 +103,12 @@ typedef struct {
     double *p[OR_MAX_LEVELS];       /* the single nonzero of row i of P_l (l < L) */
     int n_pairs[OR_MAX_LEVELS];
     double *chol;                   /* lower Cholesky factor of A_L, row-major n_L x n_L */
+    /* the pairwise chain before composition (R12), kept for reuse (R13) */
+    int pw_nlev;                    /* pairwise levels 0 .. pw_nlev-1 */
+    int pw_n[OR_MAX_LEVELS];
+    int *pw_agg[OR_MAX_LEVELS];     /* pairwise step m: level m -> m+1 */
+    double *pw_p[OR_MAX_LEVELS];
+    int kept[OR_MAX_LEVELS];        /* pairwise level of each kept level */
 } or_hier;
 
 /* ------------------------------------------------------------------ utils */
@@ -108,6 +123,7 @@ void oracle_free(or_hier *h) {
     for (int l = 0; l < OR_MAX_LEVELS; ++l) {
         csr_free(&h->A[l]);
         free(h->w[l]); free(h->dinv[l]); free(h->agg[l]); free(h->p[l]);
+        free(h->pw_agg[l]); free(h->pw_p[l]);
     }
     free(h->chol);
     free(h);
@@ -324,6 +340,7 @@ static int compose_levels(or_hier *h, int s) {
     int kept[OR_MAX_LEVELS], nk = 0;
     for (int l = 0; l < L; l += s) kept[nk++] = l;
     kept[nk++] = L;
+    for (int j = 0; j < nk; ++j) h->kept[j] = kept[j];
     or_hier tmp;
     memset(&tmp, 0, sizeof(tmp));
     for (int j = 0; j < nk; ++j) {
@@ -367,6 +384,23 @@ static int compose_levels(or_hier *h, int s) {
         h->n_pairs[j] = tmp.n_pairs[j];
     }
     h->nlev = nk;
+    return OR_OK;
+}
+
+/* Copy the pairwise aggregates and prolongators (before any composition). */
+static int keep_pairwise_chain(or_hier *h) {
+    h->pw_nlev = h->nlev;
+    for (int m = 0; m < h->nlev; ++m) {
+        h->pw_n[m] = h->A[m].n;
+        h->kept[m] = m;
+        if (m + 1 == h->nlev) break;
+        size_t n = (size_t)h->A[m].n;
+        h->pw_agg[m] = (int *)malloc(sizeof(int) * n);
+        h->pw_p[m] = (double *)malloc(sizeof(double) * n);
+        if (!h->pw_agg[m] || !h->pw_p[m]) return OR_E_OOM;
+        memcpy(h->pw_agg[m], h->agg[m], sizeof(int) * n);
+        memcpy(h->pw_p[m], h->p[m], sizeof(double) * n);
+    }
     return OR_OK;
 }
 
@@ -438,6 +472,8 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
     }
     h->nlev = l + 1;
     if (h->A[l].n > max_dense) { oracle_free(h); return OR_E_STALLED; }
+    st = keep_pairwise_chain(h);
+    if (st) { oracle_free(h); return st; }
     if (agg_steps > 1) {
         st = compose_levels(h, agg_steps);
         if (st) { oracle_free(h); return st; }
@@ -446,6 +482,72 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
     st = dense_cholesky(&h->A[l], &h->chol);
     if (st) { oracle_free(h); return st; }
     *out = h;
+    return OR_OK;
+}
+
+/* R13: the hierarchy of h rebuilt for new values v of A_0 (the pattern of
+ * h's A_0).  The pairwise chain is re-run with its stored aggregates and
+ * prolongators; the kept levels take their matrices from it. */
+static double *dup_doubles(const double *a, size_t n) {
+    double *b = (double *)malloc(sizeof(double) * (n ? n : 1));
+    if (b && n) memcpy(b, a, sizeof(double) * n);
+    return b;
+}
+
+static int *dup_ints(const int *a, size_t n) {
+    int *b = (int *)malloc(sizeof(int) * (n ? n : 1));
+    if (b && n) memcpy(b, a, sizeof(int) * n);
+    return b;
+}
+
+int oracle_update(const or_hier *h, const double *v, or_hier **out) {
+    *out = NULL;
+    const or_csr *A0 = &h->A[0];
+    if (!v || h->pw_nlev < 1) return OR_E_INVALID;
+    int st = validate(A0->n, A0->rp, A0->ci, v);
+    if (st) return st;
+    or_hier *g = (or_hier *)calloc(1, sizeof(or_hier));
+    if (!g) return OR_E_OOM;
+    or_csr chain[OR_MAX_LEVELS];
+    memset(chain, 0, sizeof(chain));
+    chain[0].n = A0->n;
+    chain[0].nnz = A0->nnz;
+    chain[0].rp = dup_ints(A0->rp, (size_t)A0->n + 1);
+    chain[0].ci = dup_ints(A0->ci, (size_t)A0->nnz);
+    chain[0].v = dup_doubles(v, (size_t)A0->nnz);
+    if (!chain[0].rp || !chain[0].ci || !chain[0].v) st = OR_E_OOM;
+    for (int m = 0; !st && m + 1 < h->pw_nlev; ++m)
+        st = galerkin(&chain[m], h->pw_agg[m], h->pw_p[m], h->pw_n[m + 1], &chain[m + 1]);
+    g->nlev = h->nlev;
+    for (int j = 0; !st && j < h->nlev; ++j) {
+        const int m = h->kept[j], n = chain[m].n;
+        g->A[j] = chain[m];
+        memset(&chain[m], 0, sizeof(or_csr));
+        g->dinv[j] = (double *)malloc(sizeof(double) * (size_t)n);
+        g->w[j] = dup_doubles(h->w[j], (size_t)n);
+        if (!g->dinv[j] || !g->w[j]) { st = OR_E_OOM; break; }
+        st = l1_inverse(&g->A[j], g->dinv[j]);
+        if (st) break;
+        if (j + 1 < h->nlev) {
+            g->agg[j] = dup_ints(h->agg[j], (size_t)n);
+            g->p[j] = dup_doubles(h->p[j], (size_t)n);
+            if (!g->agg[j] || !g->p[j]) { st = OR_E_OOM; break; }
+            g->n_pairs[j] = h->n_pairs[j];
+        }
+    }
+    g->pw_nlev = h->pw_nlev;
+    for (int m = 0; !st && m < h->pw_nlev; ++m) {
+        g->pw_n[m] = h->pw_n[m];
+        g->kept[m] = h->kept[m];
+        if (m + 1 == h->pw_nlev) break;
+        g->pw_agg[m] = dup_ints(h->pw_agg[m], (size_t)h->pw_n[m]);
+        g->pw_p[m] = dup_doubles(h->pw_p[m], (size_t)h->pw_n[m]);
+        if (!g->pw_agg[m] || !g->pw_p[m]) st = OR_E_OOM;
+    }
+    for (int m = 0; m < OR_MAX_LEVELS; ++m) csr_free(&chain[m]);
+    if (!st) st = dense_cholesky(&g->A[g->nlev - 1], &g->chol);
+    if (st) { oracle_free(g); return st; }
+    *out = g;
     return OR_OK;
 }
 

@@ -39,6 +39,13 @@ MUTANTS = {
                                       "if ((double)A->n < min_ratio"),
     "compose_drops_p": ("                pc = pc * h->p[m][I];", "                pc = pc * h->p[a][I];"),
     "compose_wrong_chain": ("                I = h->agg[m][I];", "                I = h->agg[a][I];"),
+    "update_stale_smoother": ("        st = l1_inverse(&g->A[j], g->dinv[j]);\n        if (st) break;",
+                              "        memcpy(g->dinv[j], h->dinv[j], sizeof(double) * (size_t)n);"),
+    "update_wrong_step_p": ("st = galerkin(&chain[m], h->pw_agg[m], h->pw_p[m], h->pw_n[m + 1], &chain[m + 1]);",
+                            "st = galerkin(&chain[m], h->pw_agg[m], h->pw_p[0], h->pw_n[m + 1], &chain[m + 1]);"),
+    "update_ignores_kept_map": ("        const int m = h->kept[j], n = chain[m].n;", "        const int m = j, n = chain[m].n;"),
+    "update_old_coarse_factor": ("if (!st) st = dense_cholesky(&g->A[g->nlev - 1], &g->chol);",
+                                 "if (!st) st = dense_cholesky(&h->A[h->nlev - 1], &g->chol);"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

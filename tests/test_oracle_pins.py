@@ -533,6 +533,83 @@ def test_composed_hierarchy_solves():
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
 
 
+# --------------------------------------------------------------------------- coefficient-only reuse
+
+def _same_level(G, H, l):
+    for x, y in zip(G.level(l), H.level(l)):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8)), l
+    assert np.array_equal(G.dinv(l).view(np.uint64), H.dinv(l).view(np.uint64)), l
+
+
+@pytest.mark.parametrize("steps", [1, 2])
+def test_update_with_power_of_two_scaling_equals_fresh_setup(steps):
+    # Sec. 4 reuse: the prolongators are kept and the coarse matrices and
+    # smoothers rebuilt.  Scaling A by 4 leaves every edge weight of
+    # eq. (weights) bitwise unchanged (numerator and denominator scale
+    # exactly), so a fresh setup of 4A matches exactly as A did, and reuse
+    # must then give that fresh hierarchy bit for bit: every level, its l1
+    # diagonal and the coarsest Cholesky factor.
+    A = varcoef7(12, seed=5)
+    H = oracle.Hierarchy(A, agg_steps=steps)
+    F = oracle.Hierarchy(CSR(A.n, A.row_ptr, A.col, 4.0 * A.val), agg_steps=steps)
+    U = H.update(4.0 * A.val)
+    assert U.nlevels == F.nlevels == H.nlevels
+    for l in range(U.nlevels):
+        _same_level(U, F, l)
+        if l + 1 < U.nlevels:
+            assert np.array_equal(U.agg(l), H.agg(l)) and np.array_equal(U.p(l), H.p(l))
+    assert np.array_equal(U.chol().view(np.uint64), F.chol().view(np.uint64))
+    # and the same values give back the original hierarchy
+    S = U.update(A.val)
+    for l in range(S.nlevels):
+        _same_level(S, H, l)
+    assert np.array_equal(S.chol().view(np.uint64), H.chol().view(np.uint64))
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_update_recomputes_galerkin_and_smoother_from_new_values(steps):
+    # new lognormal coefficients on the same pattern: every coarse matrix is
+    # P^T A P of the new finer matrix with the ORIGINAL prolongators (scipy
+    # products, another summation order), the l1 diagonal is that of the new
+    # matrices, and the factor reproduces the new coarsest matrix
+    A, B = varcoef7(14, seed=6), varcoef7(14, seed=7)
+    assert np.array_equal(A.row_ptr, B.row_ptr) and np.array_equal(A.col, B.col)
+    H = oracle.Hierarchy(A, agg_steps=steps)
+    U = H.update(B.val)
+    M = B.to_scipy()
+    for l in range(U.nlevels):
+        An = U.level_scipy(l)
+        assert np.abs((An - M).toarray()).max() <= 1e-12 * np.abs(M).max(), l
+        rs = np.asarray(abs(An).sum(axis=1)).ravel()
+        assert np.allclose(U.dinv(l), 1.0 / rs, rtol=4 * ULP * 27, atol=0)
+        if l + 1 == U.nlevels:
+            break
+        P = prolongator(H, l)
+        assert np.array_equal(U.agg(l), H.agg(l))
+        M = (P.T @ An @ P).tocsr()
+    Lc = U.chol()
+    AL = U.level_scipy(U.nlevels - 1).toarray()
+    assert np.abs(Lc @ Lc.T - AL).max() <= 1e-12 * np.abs(AL).max()
+    # the old hierarchy's matrices are not the new ones (the update did work)
+    assert np.abs(U.level_scipy(1) - H.level_scipy(1)).max() > 1e-3 * np.abs(H.level_scipy(1)).max()
+    # and the rebuilt hierarchy preconditions the new matrix
+    b = uniform_rhs(B.n, 3)
+    x, it, rr, st = U.solve(b, 1e-8)
+    assert st == 0 and np.linalg.norm(b - B.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+
+
+def test_update_rejects_bad_values():
+    A = varcoef7(6, seed=1)
+    H = oracle.Hierarchy(A)
+    bad = A.val.copy()
+    bad[A.row_ptr[3]:A.row_ptr[4]] *= -1.0          # row 3: negative diagonal
+    with pytest.raises(oracle.OracleError) as e:
+        H.update(bad)
+    assert e.value.code == oracle.E_INVALID
+    with pytest.raises(ValueError):
+        H.update(A.val[:-1])
+
+
 # --------------------------------------------------------------------------- failures
 
 def test_invalid_inputs_rejected():
