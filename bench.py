@@ -13,6 +13,9 @@ hierarchy setup is timed separately.  Prints one JSON line.
     python bench.py --mode batch [--steps K]    (16 right-hand sides from
                     consecutive time steps: one batched solve vs 16 single
                     solves, FP64 and FP32 V-cycles; prints its own JSON line)
+    python bench.py --mode reuse [--steps K]    (coefficient-only update of the
+                    hierarchy for a second stretching ratio on the same mesh,
+                    against a fresh setup; prints its own JSON line)
     python bench.py --mode serve [--requests R] (serving stream: variable-
                     coefficient 7-point operators from a pool of 64, Poisson
                     arrivals at 0.7 x the closed-loop capacity; p50/p99
@@ -88,7 +91,7 @@ def main() -> int:
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "mixed"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "mixed", "reuse"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=200.0)
@@ -124,6 +127,8 @@ def main() -> int:
     prec = pamg.PREC_F32 if args.precision == "f32" else pamg.PREC_F64
     if args.mode == "batch":
         return bench_batch(args, A, torch, np, pamg, log)
+    if args.mode == "reuse":
+        return bench_reuse(args, A, b, torch, np, pamg, log)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
@@ -341,6 +346,94 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
         "speedup_batch_f32_vs_16_single_f32": round(res["f32"]["single16_ms"] / res["f32"]["batch_ms"], 3),
         "speedup_batch_f64_vs_16_single_f64": round(res["f64"]["single16_ms"] / res["f64"]["batch_ms"], 3),
         "autotuned_f32": cfg,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_reuse(args, A, b, torch, np, pamg, log) -> int:
+    """Coefficient-only reuse: the hierarchy of the 1.05-stretched mesh is
+    updated to the values of the 1.06-stretched mesh (same pattern) on the
+    device, versus a fresh setup of that matrix."""
+    from workloads import q1_rhs, q1_stretched
+    r2 = args.ratio + 0.01
+    A2 = q1_stretched(args.n, r2)
+    assert np.array_equal(A2.row_ptr, A.row_ptr) and np.array_equal(A2.col, A.col)
+    b2 = torch.from_numpy(q1_rhs(args.n, r2, 2)).cuda()
+    dev = torch.device("cuda:0")
+    v1 = torch.from_numpy(A.val).to(dev)
+    v2 = torch.from_numpy(A2.val).to(dev)
+    t0 = time.perf_counter()
+    H = pamg.Hierarchy(A, agg_steps=args.agg_steps)
+    torch.cuda.synchronize()
+    setup1_s = time.perf_counter() - t0
+    info = H.info()
+    t0 = time.perf_counter()
+    H.update_values(v2)                       # first update also builds the summation plans
+    first_ms = 1e3 * (time.perf_counter() - t0)
+    log(f"setup {setup1_s:.2f}s; first update (plans) {first_ms:.1f} ms")
+    times = []
+    for k in range(max(2, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.update_values(v1 if k % 2 == 0 else v2)
+        times.append(1e3 * (time.perf_counter() - t0))
+    if max(2, args.steps) % 2 == 1:
+        H.update_values(v2)
+    t0 = time.perf_counter()
+    H.update_values(A2.val)                   # host values: includes the PCIe copy
+    host_ms = 1e3 * (time.perf_counter() - t0)
+    upd_ms = sorted(times)[len(times) // 2]
+    x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    H.solve(b2, x, tol=args.tol)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inf_u = H.solve(b2, x, tol=args.tol)
+    torch.cuda.synchronize()
+    solve_u_ms = 1e3 * (time.perf_counter() - t0)
+    xs = x.cpu().numpy()
+    bh = b2.cpu().numpy()
+    rel_u = float(np.linalg.norm(bh - A2.to_scipy() @ xs) / np.linalg.norm(bh))
+    t0 = time.perf_counter()
+    F = pamg.Hierarchy(A2, agg_steps=args.agg_steps)
+    torch.cuda.synchronize()
+    setup2_s = time.perf_counter() - t0
+    x.zero_()
+    F.solve(b2, x, tol=args.tol)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inf_f = F.solve(b2, x, tol=args.tol)
+    torch.cuda.synchronize()
+    solve_f_ms = 1e3 * (time.perf_counter() - t0)
+    # algorithmic bytes of one update from device values (pairwise levels)
+    L = info.levels - 1
+    n = [info.n[l] for l in range(L + 1)]
+    z = [info.nnz[l] for l in range(L + 1)]
+    by = 16 * z[0] + 8 * z[0] + 12 * n[0]                           # copy in, validity check
+    for m in range(L):
+        by += 4 * (z[m + 1] + 1) + 20 * z[m] + 8 * z[m + 1]          # plan, fine values, coarse values
+    for l in range(L + 1):
+        by += 4 * (n[l] + 1) + 8 * z[l] + 8 * n[l]                   # l1 diagonal
+        by += 20 * z[l] + 20 * n[l]                                  # device-order values and diagonal
+        if l < L:
+            by += 20 * z[l] + 8 * n[l]                               # column-scaled values
+    log(f"update {upd_ms:.2f} ms (device values), {host_ms:.1f} ms (host values); fresh setup {setup2_s:.2f}s; "
+        f"iterations {inf_u.iterations} (updated) vs {inf_f.iterations} (fresh)")
+    out = {
+        "metric": "coefficient-only hierarchy update time (values already in HBM)",
+        "value": round(upd_ms, 3), "unit": "ms", "higher_is_better": False,
+        "config": {"workload": f"Q1 {args.n}^3 stretched: hierarchy of ratio {args.ratio} updated to the "
+                               f"values of ratio {r2} (same mesh pattern); FCG + AMG to {args.tol}",
+                   "n": A.n, "nnz": A.nnz, "levels": info.levels, "aggregate_steps": args.agg_steps},
+        "update_ms_median": round(upd_ms, 3), "update_ms_all": [round(t, 3) for t in times],
+        "first_update_ms_with_plans": round(first_ms, 1), "update_host_values_ms": round(host_ms, 1),
+        "fresh_setup_s": round(setup2_s, 3), "speedup_vs_fresh_setup": round(1e3 * setup2_s / upd_ms, 1),
+        "update_algorithmic_bytes": by, "update_GBps": round(by / (upd_ms * 1e-3) / 1e9, 1),
+        "iterations_updated": inf_u.iterations, "iterations_fresh": inf_f.iterations,
+        "solve_ms_updated": round(solve_u_ms, 2), "solve_ms_fresh": round(solve_f_ms, 2),
+        "true_relres_updated": rel_u,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -135,9 +135,28 @@ int pamg_hierarchy_info(const pamg_hierarchy *h, pamg_hier_info *out);
 int pamg_hierarchy_aggregates(const pamg_hierarchy *h, int32_t level, int32_t *agg_host);
 
 /* Level-l Galerkin matrix in canonical numbering (host buffers of n_l+1 and
- * nnz_l entries). */
+ * nnz_l entries).  After pamg_hierarchy_update_values the values are the
+ * updated ones (read back from the device). */
 int pamg_hierarchy_level_csr(const pamg_hierarchy *h, int32_t level, int32_t *row_ptr,
                              int32_t *col_idx, double *val);
+
+/* Coefficient-only reuse (Sec. 4: when only the matrix coefficients change,
+ * the prolongators are kept and the coarse matrices and smoothers rebuilt).
+ * val: nnz new values of the setup matrix A_0 in its CSR order (same row_ptr
+ * and col_idx as given to pamg_setup); host memory, or device memory if
+ * on_device != 0; read only, the caller keeps ownership.  The aggregates and
+ * prolongators of every level are kept; the Galerkin matrices (with
+ * aggregate-size composition: of the whole pairwise chain), l1 diagonals,
+ * FP32 copies and the coarsest factorization are recomputed on the device,
+ * bitwise equal to what a setup with the same aggregates gives.  The first
+ * call also builds the summation plans (host work, kept on the device, about
+ * 24 bytes per matrix entry of every pairwise level).  Runs on `stream`
+ * (HIP stream, NULL = default) and returns when the hierarchy holds the new
+ * values; batched engines of the hierarchy see them too.  Errors: INVALID
+ * (null, host_only hierarchy, a non-finite value or non-positive diagonal:
+ * checked before anything is changed), NOT_SPD (coarsest factorization: the
+ * hierarchy must be updated again before use), OOM, DEVICE. */
+int pamg_hierarchy_update_values(pamg_hierarchy *h, const double *val, int32_t on_device, void *stream);
 
 /* Solve A x = b.  b_dev, x_dev: n doubles in the caller's numbering.  On
  * return x_dev holds the last iterate (also for NOT_CONVERGED). */

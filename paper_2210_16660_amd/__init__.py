@@ -88,6 +88,7 @@ SIGNATURES = {
     "pamg_hierarchy_aggregates": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
     "pamg_hierarchy_level_csr": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                            C.POINTER(C.c_double)]),
+    "pamg_hierarchy_update_values": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
     "pamg_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pamg_solve_opts), _VP, C.POINTER(pamg_solve_info)]),
     "pamg_solve_batch": (C.c_int, [_VP, C.c_int32, _VP, C.c_int64, _VP, C.c_int64, C.POINTER(pamg_solve_opts), _VP,
                                    C.POINTER(pamg_solve_info)]),
@@ -230,6 +231,23 @@ class Hierarchy:
                                               ci.ctypes.data_as(C.POINTER(C.c_int32)),
                                               v.ctypes.data_as(C.POINTER(C.c_double))), "pamg_hierarchy_level_csr")
         return rp, ci, v
+
+    def update_values(self, val, stream=None):
+        """Coefficient-only reuse: new values of the setup matrix (same pattern,
+        its CSR order), a numpy array or a float64 device tensor of nnz entries.
+        Aggregates and prolongators are kept; everything else is recomputed."""
+        nnz = self.info().nnz[0]
+        if isinstance(val, np.ndarray):
+            v = np.ascontiguousarray(val, dtype=np.float64)
+            if v.shape != (nnz,):
+                raise ValueError(f"expected {nnz} values")
+            _check(lib().pamg_hierarchy_update_values(self._h, v.ctypes.data, 0, _stream(stream)),
+                   "pamg_hierarchy_update_values")
+        else:
+            if tuple(val.shape) != (nnz,) or not val.is_contiguous() or str(val.dtype) != "torch.float64":
+                raise ValueError(f"expected a contiguous float64 tensor of {nnz} values")
+            _check(lib().pamg_hierarchy_update_values(self._h, _ptr(val), 1, _stream(stream)),
+                   "pamg_hierarchy_update_values")
 
     def solve(self, b, x, stream=None, **kw) -> pamg_solve_info:
         """Solve A x = b for device tensors b, x (float64, n).  x is the initial

@@ -4,8 +4,9 @@
   -ffp-contract=off so that every weight, prolongator entry and Galerkin sum
   is one IEEE operation per written operation.
 * csrc/device.hip (single right-hand side kernels, driver, C ABI),
-  csrc/batch.hip (16 right-hand sides), csrc/serve.hip (server) and
-  csrc/dense.hip (coarsest-level factorization) are compiled with hipcc for
+  csrc/batch.hip (16 right-hand sides), csrc/serve.hip (server),
+  csrc/dense.hip (coarsest-level factorization) and csrc/reuse.hip
+  (coefficient-only updates) are compiled with hipcc for
   gfx950 (in parallel).  Packed-FP32 instructions are disabled for all device
   code.
 """
@@ -39,7 +40,7 @@ def build(verbose: bool = True) -> str:
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     objs = []
     procs = []
-    for name in ("device", "batch", "serve", "dense"):
+    for name in ("device", "batch", "serve", "dense", "reuse"):
         o = os.path.join(BUILD, f"{name}.o")
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
                "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o]

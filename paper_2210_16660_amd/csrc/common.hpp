@@ -36,8 +36,19 @@ struct HostLevel {
     int32_t pairs = 0;
 };
 
+// One level of the pairwise chain that aggregate-size composition condenses:
+// its pairwise aggregates and prolongator (levels < last) and, for a level
+// that composition dropped, its pattern.  Kept for coefficient-only reuse.
+struct PairLevel {
+    int32_t kept = -1;                  // its index among the kept levels, or -1 (dropped)
+    HostCSR S;                          // pattern (rp, ci) of a dropped level; values unused
+    std::vector<int32_t> agg;
+    std::vector<double> p;
+};
+
 struct HostHierarchy {
     std::vector<HostLevel> lev;         // 0..L
+    std::vector<PairLevel> chain;       // the pairwise levels behind lev (empty: lev itself)
 };
 
 // Device-ready layout of one level in hierarchical (aggregate-contiguous) order.
@@ -78,6 +89,21 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 void validate_csr(const pamg_csr& A, bool check_symmetry);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
 std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
+
+// Coefficient-only reuse.  The Galerkin sum of one pairwise step as a plan:
+// for every coarse entry (canonical CSR order of Ac) the fine entries of A
+// that sum into it, in the setup's order, each with its factor p_i p_j (the
+// setup's term is a_ij (p_i p_j)).  A and Ac are used for their patterns.
+struct GalerkinPlan {
+    std::vector<int32_t> ptr;   // nnz(Ac) + 1: terms of coarse entry e are [ptr[e], ptr[e+1])
+    std::vector<int32_t> k;     // nnz(A): fine entry of each term
+    std::vector<double> pp;     // nnz(A): p_i p_j of each term
+};
+GalerkinPlan galerkin_plan(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,
+                           const HostCSR& Ac);
+// For every entry of a level's hierarchical CSR, its canonical entry index.
+std::vector<int32_t> entry_order(const HostCSR& A, const std::vector<int32_t>& perm,
+                                 const std::vector<int32_t>& iperm);
 
 // parallel helpers
 int num_threads();

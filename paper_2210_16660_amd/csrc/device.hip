@@ -822,7 +822,10 @@ int pamg_hierarchy_level_csr(const pamg_hierarchy* h, int32_t level, int32_t* rp
         const auto& A = h->host.lev[level].A;
         std::memcpy(rp, A.rp.data(), A.rp.size() * sizeof(int32_t));
         std::memcpy(ci, A.ci.data(), A.ci.size() * sizeof(int32_t));
-        std::memcpy(v, A.v.data(), A.v.size() * sizeof(double));
+        if (h->values_updated)
+            pamg::updated_level_values(h, level, v);
+        else
+            std::memcpy(v, A.v.data(), A.v.size() * sizeof(double));
         return PAMG_OK;
     });
 }

@@ -52,6 +52,23 @@ struct DevLevelIdx {
     long long up_dlen = 0, down_dlen = 0;  // total dictionary entries
 };
 
+// Coefficient-only reuse: built on the first value update and kept.  Its
+// device arrays belong to the hierarchy's allocation list.
+struct ReusePlan {
+    int npw = 0;                          // pairwise levels (composition condenses them)
+    std::vector<long long> nnz;           // entries of each pairwise level
+    std::vector<double*> vcan;            // each pairwise level's values, canonical CSR order
+    std::vector<int*> gptr, gk;           // Galerkin plan of each pairwise step m -> m+1
+    std::vector<double*> gpp;
+    std::vector<int> kept_pw;             // pairwise level of each kept level
+    std::vector<int*> crp;                // canonical row pointer of each kept level
+    std::vector<int*> hperm;              // device CSR entry -> canonical entry, each kept level
+    std::vector<double*> dcan;            // canonical l1 inverse diagonal, each kept level
+    int* dpos0 = nullptr;                 // canonical position of each diagonal entry of A_0
+    int* flag = nullptr;
+    double plan_ms = 0.0;
+};
+
 }  // namespace pamg
 
 struct pamg_hierarchy {
@@ -75,6 +92,8 @@ struct pamg_hierarchy {
     pamg_hier_info info{};
     std::mutex mu;
     std::unique_ptr<pamg::BatchEngine, pamg::BatchDeleter> batch[2];   // multi-RHS workspaces (FP64 / FP32 V-cycle)
+    std::unique_ptr<pamg::ReusePlan> reuse;   // coefficient-only updates
+    bool values_updated = false;              // host copies of the values are stale
 };
 
 namespace pamg {
@@ -115,6 +134,8 @@ constexpr int kMaxDense = 8192;
 // device CSR: Cholesky and inverse on the matrix cores (dense.hip).  Throws
 // PAMG_E_NOT_SPD on a non-positive pivot.  Synchronizes the stream.
 void coarse_inverse_device(int n, const int* rp, const int* ci, const double* v, double* ainv, hipStream_t s);
+// Canonical values of a kept level after a coefficient-only update (reuse.hip).
+void updated_level_values(const pamg_hierarchy* h, int level, double* v);
 }  // namespace pamg
 
 namespace pamg {

@@ -309,6 +309,19 @@ static void compose_levels(HostHierarchy& H, int s) {
             o.p[i] = pc;
         });
     }
+    // the pairwise chain stays behind the kept levels (coefficient-only reuse)
+    H.chain.assign(L + 1, PairLevel());
+    for (size_t j = 0; j < kept.size(); ++j) H.chain[kept[j]].kept = (int32_t)j;
+    for (int m = 0; m <= L; ++m) {
+        PairLevel& c = H.chain[m];
+        if (c.kept < 0) {
+            c.S.n = H.lev[m].A.n;
+            c.S.rp = std::move(H.lev[m].A.rp);
+            c.S.ci = std::move(H.lev[m].A.ci);
+        }
+        c.agg = std::move(H.lev[m].agg);
+        c.p = std::move(H.lev[m].p);
+    }
     H.lev = std::move(out);
 }
 
@@ -387,6 +400,89 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
                                         " unknowns, above the dense-solve limit");
     if (prm.agg_steps > 1) compose_levels(H, prm.agg_steps);
     return H;
+}
+
+// ------------------------------------------------ coefficient-only reuse
+
+GalerkinPlan galerkin_plan(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,
+                           const HostCSR& Ac) {
+    const int32_t n = A.n, nc = Ac.n;
+    std::vector<int32_t> mptr(nc + 1, 0), mem(n);
+    for (int32_t i = 0; i < n; ++i) ++mptr[agg[i] + 1];
+    for (int32_t I = 0; I < nc; ++I) mptr[I + 1] += mptr[I];
+    {
+        std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i) mem[fill[agg[i]]++] = i;
+    }
+    // first term of each coarse row: the terms of a row are its members' entries
+    std::vector<int64_t> toff(nc + 1, 0);
+    for (int32_t I = 0; I < nc; ++I) {
+        int64_t c = 0;
+        for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) c += A.rp[mem[q] + 1] - A.rp[mem[q]];
+        toff[I + 1] = toff[I] + c;
+    }
+    GalerkinPlan g;
+    g.ptr.assign(Ac.nnz() + 1, 0);
+    g.k.resize(A.nnz());
+    g.pp.resize(A.nnz());
+    std::atomic<int> bad{0};
+    parallel_ranges(nc, [&](int, int64_t b, int64_t e) {
+        struct Key {
+            int32_t J, k1, k2, k3, k;
+        };
+        std::vector<Key> t;
+        for (int64_t I = b; I < e; ++I) {
+            t.clear();
+            for (int32_t q = mptr[I]; q < mptr[I + 1]; ++q) {
+                const int32_t i = mem[q];
+                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                    const int32_t j = A.ci[k];
+                    t.push_back({agg[j], std::min(i, j), std::max(i, j), i, k});
+                }
+            }
+            // the order of the setup's Galerkin sum (a strict total order)
+            std::sort(t.begin(), t.end(), [](const Key& x, const Key& y) {
+                if (x.J != y.J) return x.J < y.J;
+                if (x.k1 != y.k1) return x.k1 < y.k1;
+                if (x.k2 != y.k2) return x.k2 < y.k2;
+                return x.k3 < y.k3;
+            });
+            int64_t q = toff[I];
+            int32_t c = Ac.rp[I] - 1;
+            for (size_t u = 0; u < t.size(); ++u, ++q) {
+                if (u == 0 || t[u].J != t[u - 1].J) {
+                    ++c;
+                    if (c >= Ac.rp[I + 1] || Ac.ci[c] != t[u].J) bad.store(1);
+                    else g.ptr[c] = (int32_t)q;
+                }
+                g.k[q] = t[u].k;
+                g.pp[q] = p[t[u].k3] * p[A.ci[t[u].k]];
+            }
+            if (c != Ac.rp[I + 1] - 1) bad.store(1);
+        }
+    });
+    if (bad.load()) throw Error(PAMG_E_DEVICE, "Galerkin plan does not match the coarse pattern");
+    g.ptr[Ac.nnz()] = (int32_t)A.nnz();
+    return g;
+}
+
+std::vector<int32_t> entry_order(const HostCSR& A, const std::vector<int32_t>& perm,
+                                 const std::vector<int32_t>& iperm) {
+    const int32_t n = A.n;
+    std::vector<int32_t> rp(n + 1, 0);
+    for (int32_t ip = 0; ip < n; ++ip) rp[ip + 1] = rp[ip] + (A.rp[iperm[ip] + 1] - A.rp[iperm[ip]]);
+    std::vector<int32_t> out(A.nnz());
+    parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+        std::vector<std::pair<int32_t, int32_t>> row;
+        for (int64_t ip = b; ip < e; ++ip) {
+            const int32_t i = iperm[ip];
+            row.clear();
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) row.emplace_back(perm[A.ci[k]], k);
+            std::sort(row.begin(), row.end());
+            for (size_t u = 0; u < row.size(); ++u) out[rp[ip] + u] = row[u].second;
+        }
+    });
+    return out;
 }
 
 // ---------------------------------------------------------------- layout

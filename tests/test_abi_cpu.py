@@ -119,6 +119,11 @@ def test_host_only_hierarchy_refuses_device_calls():
     with pytest.raises(pamg.PamgError) as e:
         H.solve(8, 16, stream=0)
     assert e.value.code in (pamg.E_INVALID,)
+    # a coefficient update needs the device hierarchy too (refused before any
+    # device call)
+    with pytest.raises(pamg.PamgError) as e:
+        H.update_values(lap7(4).val, stream=0)
+    assert e.value.code == pamg.E_INVALID
 
 
 CASES = {
