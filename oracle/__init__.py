@@ -54,6 +54,10 @@ def lib():
         L.oracle_round_f32.restype = C.c_int
         L.oracle_update.argtypes = [vp, dp, C.POINTER(vp)]
         L.oracle_update.restype = C.c_int
+        L.oracle_set_smoother.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.oracle_set_smoother.restype = C.c_int
+        L.oracle_nested_order.argtypes = [vp, C.c_int, ip]
+        L.oracle_hgs_smooth.argtypes = [vp, C.c_int, C.c_int, C.c_int, dp, dp]
         L.oracle_free.argtypes = [vp]
         for name in ("oracle_nlevels",):
             getattr(L, name).argtypes = [vp]
@@ -148,6 +152,32 @@ class Hierarchy:
         if rc != 0:
             raise OracleError(rc, "oracle_update")
         return Hierarchy(None, _handle=h)
+
+    def set_smoother(self, kind: str = "l1", nu: int = 4, nb: int = 256, omega: float = 1.0):
+        """'l1' (l1-Jacobi, one pre- and one post-sweep) or 'hgs' (hybrid
+        forward/backward Gauss-Seidel: nu sweeps over nested-order blocks of nb)."""
+        k = {"l1": 0, "hgs": 1}[kind]
+        rc = lib().oracle_set_smoother(self._h, k, int(nu), int(nb), float(omega))
+        if rc != 0:
+            raise OracleError(rc, "oracle_set_smoother")
+        return self
+
+    def nested_order(self, l: int) -> np.ndarray:
+        o = np.empty(self.n(l), np.int32)
+        lib().oracle_nested_order(self._h, l, _p(o, C.c_int))
+        return o
+
+    def hgs_smooth(self, l, r, x=None, backward=False):
+        """nu hybrid Gauss-Seidel sweeps on A_l x = r: forward from zero
+        (x None), or backward from x."""
+        r = np.ascontiguousarray(r, np.float64)
+        if x is None:
+            out = np.zeros(self.n(l))
+            lib().oracle_hgs_smooth(self._h, l, 1 if backward else 0, 1, _p(r, C.c_double), _p(out, C.c_double))
+        else:
+            out = np.array(x, np.float64, copy=True)
+            lib().oracle_hgs_smooth(self._h, l, 1 if backward else 0, 0, _p(r, C.c_double), _p(out, C.c_double))
+        return out
 
     @property
     def nlevels(self) -> int:

@@ -70,6 +70,19 @@
  *      chain is recomputed and the kept levels are taken from it, so the
  *      result is the hierarchy a setup would give if its matchings were
  *      those of the original matrix.
+ *   R14 hybrid forward/backward Gauss-Seidel smoother (Sec. 3.1, the
+ *      smoother the paper uses; optional here, R1 is the default): the
+ *      unknowns of a level are taken in nested-aggregate order (the coarsest
+ *      level in its own order; a finer level lists the members of each
+ *      coarse unknown, coarse unknowns in their nested order, members in
+ *      ascending index) and cut into consecutive blocks of nb unknowns, the
+ *      row blocks of the paper's row-block distribution.  One sweep is
+ *      x <- x + M^-1 (r - A x) with M = blockdiag(omega (L_pp + D_pp)):
+ *      within a block, in nested order,
+ *      d_i = ((r_i - sum_j a_ij x_j) - sum_{j earlier in the block} a_ij d_j) / a_ii
+ *      (both sums in ascending column order), then x_i += d_i / omega.  A
+ *      backward sweep runs each block in reverse (M^T).  Pre-smoothing: nu forward sweeps from zero;
+ *      post-smoothing: nu backward sweeps, so the V-cycle stays symmetric.
  */
 #include <math.h>
 #include <stdint.h>
@@ -109,6 +122,10 @@ typedef struct {
     int *pw_agg[OR_MAX_LEVELS];     /* pairwise step m: level m -> m+1 */
     double *pw_p[OR_MAX_LEVELS];
     int kept[OR_MAX_LEVELS];        /* pairwise level of each kept level */
+    /* smoother (R1 l1-Jacobi unless set by oracle_set_smoother, R14) */
+    int smoother;                   /* 0: l1-Jacobi, 1: hybrid forward/backward Gauss-Seidel */
+    int gs_nu, gs_nb;
+    double gs_omega;
 } or_hier;
 
 /* ------------------------------------------------------------------ utils */
@@ -535,6 +552,7 @@ int oracle_update(const or_hier *h, const double *v, or_hier **out) {
             g->n_pairs[j] = h->n_pairs[j];
         }
     }
+    g->smoother = h->smoother; g->gs_nu = h->gs_nu; g->gs_nb = h->gs_nb; g->gs_omega = h->gs_omega;
     g->pw_nlev = h->pw_nlev;
     for (int m = 0; !st && m < h->pw_nlev; ++m) {
         g->pw_n[m] = h->pw_n[m];
@@ -558,6 +576,7 @@ int oracle_round_f32(const or_hier *h, or_hier **out) {
     or_hier *g = (or_hier *)calloc(1, sizeof(or_hier));
     if (!g) return OR_E_OOM;
     g->nlev = h->nlev;
+    g->smoother = h->smoother; g->gs_nu = h->gs_nu; g->gs_nb = h->gs_nb; g->gs_omega = h->gs_omega;
     for (int l = 0; l < h->nlev; ++l) {
         const or_csr *a = &h->A[l];
         or_csr *b = &g->A[l];
@@ -646,10 +665,101 @@ void oracle_coarse_solve(const or_hier *h, const double *r, double *z) {
     }
 }
 
-/* z = V(l, r): eq. (multiplicative_composition) with nu = 1, M = diag(l1) */
+/* ------------------------------------- hybrid Gauss-Seidel smoother (R14) */
+
+int oracle_set_smoother(or_hier *h, int kind, int nu, int nb, double omega) {
+    if (kind == 0) { h->smoother = 0; return OR_OK; }
+    if (kind != 1 || nu < 1 || nb < 1 || !(omega > 0.0)) return OR_E_INVALID;
+    h->smoother = 1; h->gs_nu = nu; h->gs_nb = nb; h->gs_omega = omega;
+    return OR_OK;
+}
+
+/* order[q] = the level-l unknown at nested position q (R14) */
+void oracle_nested_order(const or_hier *h, int l, int *order) {
+    int L = h->nlev - 1;
+    for (int q = 0; q < h->A[L].n; ++q) order[q] = q;
+    for (int m = L - 1; m >= l; --m) {
+        int nf = h->A[m].n, nc = h->A[m + 1].n;
+        int *size = (int *)calloc((size_t)nc, sizeof(int));
+        int *first = (int *)malloc(sizeof(int) * (size_t)nc);
+        int *finer = (int *)malloc(sizeof(int) * (size_t)nf);
+        for (int i = 0; i < nf; ++i) size[h->agg[m][i]]++;
+        /* coarse unknowns in their nested order, each followed by its members */
+        int acc = 0;
+        for (int q = 0; q < nc; ++q) { first[order[q]] = acc; acc += size[order[q]]; }
+        for (int i = 0; i < nf; ++i) finer[first[h->agg[m][i]]++] = i;   /* ascending i */
+        memcpy(order, finer, sizeof(int) * (size_t)nf);
+        free(size); free(first); free(finer);
+    }
+}
+
+/* one sweep x_new = x_old + M^-1 (r - A x_old), M = blockdiag(omega (L+D))
+   (forward) or its transpose (backward) over nested-order blocks: within a
+   block the correction d solves (L_pp + D_pp) d = (r - A x_old)_p by
+   substitution in nested order, and x_new = x_old + d / omega */
+static void hgs_sweep(const or_hier *h, int l, const int *order, const int *pos, int backward,
+                      const double *r, const double *x_old, double *x_new, double *d) {
+    const or_csr *a = &h->A[l];
+    int n = a->n, nb = h->gs_nb;
+    for (int b0 = 0; b0 < n; b0 += nb) {
+        int b1 = b0 + nb < n ? b0 + nb : n;
+        for (int s = 0; s < b1 - b0; ++s) {
+            int q = backward ? b1 - 1 - s : b0 + s;
+            int i = order[q];
+            double old = 0.0, fresh = 0.0, aii = 0.0;
+            for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+                int j = a->ci[k], qj = pos[j];
+                old += a->v[k] * x_old[j];
+                if (qj >= b0 && qj < b1 && (backward ? qj > q : qj < q)) fresh += a->v[k] * d[j];
+                if (j == i) aii = a->v[k];
+            }
+            d[i] = ((r[i] - old) - fresh) / aii;
+        }
+        for (int q = b0; q < b1; ++q) {
+            int i = order[q];
+            x_new[i] = x_old[i] + d[i] / h->gs_omega;
+        }
+    }
+}
+
+/* x <- nu sweeps (forward from x = 0 if zero_start, else backward from x) */
+void oracle_hgs_smooth(const or_hier *h, int l, int backward, int zero_start, const double *r, double *x) {
+    int n = h->A[l].n;
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    int *pos = (int *)malloc(sizeof(int) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d = (double *)malloc(sizeof(double) * (size_t)n);
+    oracle_nested_order(h, l, order);
+    for (int q = 0; q < n; ++q) pos[order[q]] = q;
+    if (zero_start)
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+    for (int s = 0; s < h->gs_nu; ++s) {
+        hgs_sweep(h, l, order, pos, backward, r, x, y, d);
+        memcpy(x, y, sizeof(double) * (size_t)n);
+    }
+    free(order); free(pos); free(y); free(d);
+}
+
+/* z = V(l, r): eq. (multiplicative_composition); smoother R1 (nu = 1,
+   M = diag(l1)) or R14 (nu hybrid Gauss-Seidel sweeps) */
 void oracle_vcycle(const or_hier *h, int l, const double *r, double *z) {
     int L = h->nlev - 1;
     if (l == L) { oracle_coarse_solve(h, r, z); return; }
+    if (h->smoother == 1) {
+        int n = h->A[l].n, nc = h->A[l + 1].n;
+        double *t = (double *)malloc(sizeof(double) * (size_t)n);
+        double *rc = (double *)malloc(sizeof(double) * (size_t)nc);
+        double *e = (double *)malloc(sizeof(double) * (size_t)nc);
+        oracle_hgs_smooth(h, l, 0, 1, r, z);                    /* pre-smooth: forward from zero */
+        csr_mv(&h->A[l], z, t);
+        for (int i = 0; i < n; ++i) t[i] = r[i] - t[i];         /* residual */
+        oracle_restrict(h, l, t, rc);
+        oracle_vcycle(h, l + 1, rc, e);
+        oracle_prolong_add(h, l, e, z);
+        oracle_hgs_smooth(h, l, 1, 0, r, z);                    /* post-smooth: backward */
+        free(t); free(rc); free(e);
+        return;
+    }
     int n = h->A[l].n, nc = h->A[l + 1].n;
     const double *dinv = h->dinv[l];
     double *t = (double *)malloc(sizeof(double) * (size_t)n);

@@ -46,6 +46,15 @@ MUTANTS = {
     "update_ignores_kept_map": ("        const int m = h->kept[j], n = chain[m].n;", "        const int m = j, n = chain[m].n;"),
     "update_old_coarse_factor": ("if (!st) st = dense_cholesky(&g->A[g->nlev - 1], &g->chol);",
                                  "if (!st) st = dense_cholesky(&h->A[h->nlev - 1], &g->chol);"),
+    "hgs_fresh_wrong_side": ("if (qj >= b0 && qj < b1 && (backward ? qj > q : qj < q)) fresh",
+                             "if (qj >= b0 && qj < b1 && (backward ? qj < q : qj > q)) fresh"),
+    "hgs_ignores_blocks": ("if (qj >= b0 && qj < b1 && (backward ? qj > q : qj < q)) fresh",
+                           "if ((backward ? qj > q : qj < q)) fresh"),
+    "hgs_post_forward": ("oracle_hgs_smooth(h, l, 1, 0, r, z);", "oracle_hgs_smooth(h, l, 0, 0, r, z);"),
+    "hgs_omega_dropped": ("x_new[i] = x_old[i] + d[i] / h->gs_omega;", "x_new[i] = x_old[i] + d[i];"),
+    "hgs_omega_inside": ("d[i] = ((r[i] - old) - fresh) / aii;", "d[i] = ((r[i] - old) - fresh) / (h->gs_omega * aii);"),
+    "nested_members_descending": ("for (int i = 0; i < nf; ++i) finer[first[h->agg[m][i]]++] = i;",
+                                  "for (int i = nf - 1; i >= 0; --i) finer[first[h->agg[m][i]]++] = i;"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

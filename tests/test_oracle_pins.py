@@ -533,6 +533,132 @@ def test_composed_hierarchy_solves():
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
 
 
+# --------------------------------------------------------------------------- hybrid Gauss-Seidel smoother
+
+def _nested_order_py(H, l):
+    """Nested-aggregate order written out: the coarsest level in its own
+    order, then per finer level the members of each coarse unknown (coarse
+    unknowns in their nested order), members ascending."""
+    L = H.nlevels - 1
+    order = list(range(H.n(L)))
+    for m in range(L - 1, l - 1, -1):
+        agg = H.agg(m)
+        members = {}
+        for i in range(H.n(m)):
+            members.setdefault(int(agg[i]), []).append(i)
+        order = [i for I in order for i in members[I]]
+    return np.array(order)
+
+
+def _hgs_M(H, l, nb, omega, backward=False):
+    """M = blockdiag(omega (L_pp + D_pp)) (its transpose for backward) in the
+    level's own numbering, blocks of nb consecutive nested positions."""
+    A = H.level_scipy(l).toarray()
+    o = _nested_order_py(H, l)
+    Ap = A[np.ix_(o, o)]
+    n = A.shape[0]
+    Mp = np.zeros_like(Ap)
+    for b0 in range(0, n, nb):
+        b1 = min(b0 + nb, n)
+        blk = Ap[b0:b1, b0:b1]
+        Mp[b0:b1, b0:b1] = omega * (np.triu(blk) if backward else np.tril(blk))
+    M = np.zeros_like(A)
+    M[np.ix_(o, o)] = Mp
+    return M
+
+
+@pytest.mark.parametrize("case", ["varcoef_10", "q1_6_composed2"])
+def test_nested_order_definition(case):
+    A = varcoef7(10, seed=2) if case == "varcoef_10" else q1_stretched(6, 1.05)
+    H = oracle.Hierarchy(A, agg_steps=2 if "composed" in case else 1)
+    for l in range(H.nlevels):
+        o = H.nested_order(l)
+        assert np.array_equal(o, _nested_order_py(H, l)), l
+        assert np.array_equal(np.sort(o), np.arange(H.n(l)))
+
+
+@pytest.mark.parametrize("nb,omega,nu", [(1, 0.8, 2), (10 ** 6, 1.0, 1), (37, 0.9, 1), (64, 1.0, 3)])
+def test_hgs_sweeps_are_block_triangular_solves(nb, omega, nu):
+    # Sec. 3.1: M = blockdiag(omega (L_pp + D_pp)) over the row blocks; one
+    # unknown per block is damped Jacobi with the true diagonal, one block is
+    # plain (damped) Gauss-Seidel.  nu forward sweeps from zero, then nu
+    # backward sweeps (M^T) from the result, against dense solves with M.
+    A = varcoef7(9, seed=3)
+    H = oracle.Hierarchy(A).set_smoother("hgs", nu=nu, nb=nb, omega=omega)
+    for l in range(H.nlevels - 1):
+        Al = H.level_scipy(l).toarray()
+        r = uniform_rhs(H.n(l), 10 + l)
+        Mf, Mb = _hgs_M(H, l, nb, omega), _hgs_M(H, l, nb, omega, backward=True)
+        x = np.zeros(H.n(l))
+        for _ in range(nu):
+            x = x + np.linalg.solve(Mf, r - Al @ x)
+        xo = H.hgs_smooth(l, r)
+        assert np.allclose(xo, x, rtol=1e-11, atol=1e-11 * abs(x).max()), l
+        y = x.copy()
+        for _ in range(nu):
+            y = y + np.linalg.solve(Mb, r - Al @ y)
+        yo = H.hgs_smooth(l, r, x=xo, backward=True)
+        assert np.allclose(yo, y, rtol=1e-10, atol=1e-10 * abs(y).max()), l
+    if nb == 1:
+        # damped Jacobi: one sweep from zero is r / (omega a_ii)
+        d = A.to_scipy().diagonal()
+        r = uniform_rhs(A.n, 3)
+        H1 = oracle.Hierarchy(A).set_smoother("hgs", nu=1, nb=1, omega=omega)
+        assert np.allclose(H1.hgs_smooth(0, r), r / (omega * d), rtol=1e-15, atol=0)
+
+
+def _dense_B_hgs(H, l, nu, nb, omega):
+    """B_l of eq. (multiplicative_composition) with nu forward sweeps of M
+    before and nu backward sweeps of M^T after the coarse correction."""
+    A = H.level_scipy(l).toarray()
+    if l == H.nlevels - 1:
+        return np.linalg.inv(A)
+    n = A.shape[0]
+    P = prolongator(H, l).toarray()
+    Mf, Mb = _hgs_M(H, l, nb, omega), _hgs_M(H, l, nb, omega, backward=True)
+    Sf = np.linalg.matrix_power(np.eye(n) - np.linalg.solve(Mf, A), nu)
+    Sb = np.linalg.matrix_power(np.eye(n) - np.linalg.solve(Mb, A), nu)
+    C = np.eye(n) - P @ _dense_B_hgs(H, l + 1, nu, nb, omega) @ P.T @ A
+    return (np.eye(n) - Sb @ C @ Sf) @ np.linalg.inv(A)
+
+
+@pytest.mark.parametrize("case", ["varcoef_6", "q1_4_composed2"])
+def test_hgs_vcycle_matches_multiplicative_composition(case):
+    A = varcoef7(6, seed=8) if case == "varcoef_6" else q1_stretched(4, 1.05)
+    H = oracle.Hierarchy(A, max_coarse=12, agg_steps=2 if "composed" in case else 1)
+    H.set_smoother("hgs", nu=2, nb=23, omega=1.0)
+    assert H.nlevels >= 3
+    n = H.n(0)
+    Bcols = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    Bf = _dense_B_hgs(H, 0, 2, 23, 1.0)
+    assert np.allclose(Bcols, Bf, rtol=1e-9, atol=1e-9 * abs(Bf).max())
+    # forward before, backward after: a symmetric positive definite preconditioner
+    assert np.allclose(Bcols, Bcols.T, rtol=1e-10, atol=1e-10 * abs(Bcols).max())
+    assert np.linalg.eigvalsh(0.5 * (Bcols + Bcols.T)).min() > 0
+
+
+def test_hgs_smooths_better_than_l1_jacobi():
+    # the paper's reason for Gauss-Seidel: fewer outer iterations
+    A = q1_stretched(10, 1.05)
+    b = q1_rhs(10, 1.05, 2)
+    its = {}
+    for kind in ("l1", "hgs"):
+        H = oracle.Hierarchy(A).set_smoother(kind, nu=4, nb=256)
+        x, it, rr, st = H.solve(b, 1e-8)
+        assert st == 0 and np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+        its[kind] = it
+    assert its["hgs"] < its["l1"]
+
+
+def test_hgs_parameters_validated():
+    H = oracle.Hierarchy(lap7(4))
+    for bad in [dict(nu=0), dict(nb=0), dict(omega=0.0), dict(omega=float("nan"))]:
+        kw = dict(nu=4, nb=8, omega=1.0)
+        kw.update(bad)
+        with pytest.raises(oracle.OracleError):
+            H.set_smoother("hgs", **kw)
+
+
 # --------------------------------------------------------------------------- coefficient-only reuse
 
 def _same_level(G, H, l):
