@@ -16,7 +16,8 @@ SRC = os.path.join(ROOT, "oracle", "oracle.c")
 
 MUTANTS = {
     "post_smooth_sign": ("z[i] += dinv[i] * (r[i] - t[i]);", "z[i] += dinv[i] * (t[i] - r[i]);"),
-    "residual_sign": ("t[i] = r[i] - t[i];", "t[i] = r[i] + t[i];"),
+    "residual_sign": ("t[i] = r[i] - t[i];             /* residual */", "t[i] = r[i] + t[i];             /* residual */"),
+    "hgs_residual_sign": ("t[i] = r[i] - t[i];         /* residual */", "t[i] = r[i] + t[i];         /* residual */"),
     "prolong_drops_p": ("z[i] += h->p[l][i] * e[h->agg[l][i]];", "z[i] += e[h->agg[l][i]];"),
     "restrict_drops_p": ("rc[h->agg[l][i]] += h->p[l][i] * t[i];", "rc[h->agg[l][i]] += t[i];"),
     "weight_wrong_index": ("double num = ((2.0 * a_lohi) * w_lo) * w_hi;",
