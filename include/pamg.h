@@ -13,7 +13,8 @@
  *   solve A x = b with A symmetric positive definite, by preconditioned CG or
  *   flexible CG, where the preconditioner B is the V-cycle of
  *   eq. (multiplicative_composition) with nu = 1 pre-/post-sweep of the
- *   l1-Jacobi smoother, tentative piecewise-constant prolongators of
+ *   l1-Jacobi smoother (or, optionally, nu sweeps of the paper's hybrid
+ *   forward/backward Gauss-Seidel), tentative piecewise-constant prolongators of
  *   eq. (prolongator) built from a maximum-product matching of the weights
  *   of eq. (weights), Galerkin coarse matrices A_{l+1} = P_l^T A_l P_l, and a
  *   dense direct solve on the coarsest level.  Stopping test: ||r||_2 no
@@ -43,6 +44,7 @@ typedef enum {
 
 enum { PAMG_PREC_F64 = 0, PAMG_PREC_F32 = 1 };   /* storage/arithmetic of the V-cycle */
 enum { PAMG_KRYLOV_CG = 0, PAMG_KRYLOV_FCG = 1 };
+enum { PAMG_SMOOTHER_L1_JACOBI = 0, PAMG_SMOOTHER_HYBRID_GS = 1 };
 
 typedef struct pamg_hierarchy pamg_hierarchy;
 
@@ -76,7 +78,17 @@ typedef struct {
     int32_t agg_steps;        /* aggregate-size composition (Sec. 3.1): keep every agg_steps-th level of
                                  the pairwise hierarchy, prolongators multiplied in between, so that
                                  aggregates hold up to 2^agg_steps unknowns (default 1: pairs; 1..4) */
-    int32_t reserved[7];
+    int32_t smoother;         /* PAMG_SMOOTHER_L1_JACOBI (default: one pre- and one post-sweep) or
+                                 PAMG_SMOOTHER_HYBRID_GS (Sec. 3.1: hybrid forward/backward
+                                 Gauss-Seidel, M = blockdiag(omega (L_pp + D_pp)) over row blocks of
+                                 gs_block unknowns in nested-aggregate order; `sweeps` forward sweeps
+                                 before and as many backward sweeps after the coarse correction) */
+    int32_t sweeps;           /* hybrid GS sweeps per side, 1..16 (0: 4, the paper's nu); l1-Jacobi: 0 or 1 */
+    int32_t gs_block;         /* hybrid GS block size, 1..256 (0: 256) */
+    double omega;             /* hybrid GS damping of M = omega (L + D), > 0 (0: 1.5; omega = 1, the
+                                 plain method, lets the Jacobi coupling between the small blocks
+                                 diverge on large 3D meshes) */
+    int32_t reserved[2];
 } pamg_params;
 
 typedef struct {
@@ -170,7 +182,8 @@ int pamg_solve(pamg_hierarchy *h, const double *b_dev, double *x_dev, const pamg
  * recurrence with its own step lengths and stopping test; every pass over a
  * level's matrix serves all columns.  x0 = 0 (use_x0 must be 0).  A column's
  * result does not depend on the other columns.  infos: nrhs entries.  The
- * return value is the worst column status. */
+ * return value is the worst column status.  l1-Jacobi hierarchies only
+ * (INVALID for the hybrid Gauss-Seidel smoother). */
 int pamg_solve_batch(pamg_hierarchy *h, int32_t nrhs, const double *B_dev, int64_t ldb, double *X_dev,
                      int64_t ldx, const pamg_solve_opts *opts, void *stream, pamg_solve_info *infos);
 
@@ -194,10 +207,14 @@ int pamg_batch_config(pamg_hierarchy *h, int32_t precision, int32_t *cfg);
  *   PAMG_OP_UP       out = in1 + D_l^-1 (in0 - A_l in1)         (post-smooth of in1 given r = in0)
  *   PAMG_OP_PROLONG  out = D_l^-1 in0 + P_l in1                 (in1 has n_{l+1} entries)
  *   PAMG_OP_COARSE   out = A_L^-1 in0                           (level = L)
- *   PAMG_OP_VCYCLE   out = B in0                                (level 0)
+ *   PAMG_OP_VCYCLE   out = B in0                                (level 0; the hierarchy's smoother)
+ *   PAMG_OP_SMOOTH   hybrid GS hierarchies (level < L): in1 == NULL: out = `sweeps` forward
+ *                    sweeps on A_l x = in0 from x = 0 (pre-smoothing); else out = `sweeps`
+ *                    backward sweeps from x = in1 (post-smoothing)
+ * DOWN, UP and PROLONG are the l1-Jacobi kernels whatever the smoother.
  */
 enum { PAMG_OP_SPMV = 0, PAMG_OP_DOWN = 1, PAMG_OP_UP = 2, PAMG_OP_PROLONG = 3, PAMG_OP_COARSE = 4,
-       PAMG_OP_VCYCLE = 5 };
+       PAMG_OP_VCYCLE = 5, PAMG_OP_SMOOTH = 7 };
 int pamg_debug_apply(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision, const double *in0_dev,
                      const double *in1_dev, double *out_dev, void *stream);
 

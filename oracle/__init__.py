@@ -153,7 +153,7 @@ class Hierarchy:
             raise OracleError(rc, "oracle_update")
         return Hierarchy(None, _handle=h)
 
-    def set_smoother(self, kind: str = "l1", nu: int = 4, nb: int = 256, omega: float = 1.0):
+    def set_smoother(self, kind: str = "l1", nu: int = 4, nb: int = 256, omega: float = 1.5):
         """'l1' (l1-Jacobi, one pre- and one post-sweep) or 'hgs' (hybrid
         forward/backward Gauss-Seidel: nu sweeps over nested-order blocks of nb)."""
         k = {"l1": 0, "hgs": 1}[kind]

@@ -19,7 +19,8 @@ OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NOT_SPD, E_NUMERIC, E_OOM, E_DEVICE, E_STALLED, E_BUSY = -1, -2, -3, -4, -5, -6, -7
 PREC_F64, PREC_F32 = 0, 1
 KRYLOV_CG, KRYLOV_FCG = 0, 1
-OP_SPMV, OP_DOWN, OP_UP, OP_PROLONG, OP_COARSE, OP_VCYCLE, OP_KRYLOV = 0, 1, 2, 3, 4, 5, 6
+OP_SPMV, OP_DOWN, OP_UP, OP_PROLONG, OP_COARSE, OP_VCYCLE, OP_KRYLOV, OP_SMOOTH = 0, 1, 2, 3, 4, 5, 6, 7
+SMOOTHER_L1_JACOBI, SMOOTHER_HYBRID_GS = 0, 1
 MAX_LEVELS = 64
 
 
@@ -32,7 +33,8 @@ class pamg_params(C.Structure):
     _fields_ = [("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("max_dense", C.c_int32),
                 ("match_all_edges", C.c_int32), ("build_f32", C.c_int32), ("num_threads", C.c_int32),
                 ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("min_ratio", C.c_double),
-                ("agg_steps", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("agg_steps", C.c_int32), ("smoother", C.c_int32), ("sweeps", C.c_int32),
+                ("gs_block", C.c_int32), ("omega", C.c_double), ("reserved", C.c_int32 * 2)]
 
 
 class pamg_solve_opts(C.Structure):
@@ -161,7 +163,9 @@ def params(**kw) -> pamg_params:
     p = pamg_params()
     _check(lib().pamg_params_default(C.byref(p)), "pamg_params_default")
     for k, v in kw.items():
-        setattr(p, k, float(v) if k == "min_ratio" else int(v))
+        if k == "smoother" and isinstance(v, str):
+            v = {"l1": SMOOTHER_L1_JACOBI, "l1_jacobi": SMOOTHER_L1_JACOBI, "hgs": SMOOTHER_HYBRID_GS}[v]
+        setattr(p, k, float(v) if k in ("min_ratio", "omega") else int(v))
     return p
 
 

@@ -15,6 +15,12 @@
 
 namespace pamg {
 
+// The 16-column engine runs the l1-Jacobi V-cycle only.
+static void require_l1_smoother(const pamg_hierarchy* h) {
+    if (h->smoother != PAMG_SMOOTHER_L1_JACOBI)
+        throw Error(PAMG_E_INVALID, "batched solves support the l1-Jacobi smoother only");
+}
+
 // kernel variants tried by the autotuner: unroll depth (entries of a row
 // whose loads are in flight together) x columns per lane
 constexpr int kNumVariants = 10;
@@ -435,6 +441,7 @@ void batch_true_residual(BatchEngine* E, int restart_mask, double* relres, hipSt
 int solve_batch(pamg_hierarchy* h, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
                 const pamg_solve_opts& o, hipStream_t s, pamg_solve_info* infos) {
     require_device(h);
+    require_l1_smoother(h);
     std::lock_guard<std::mutex> lk(h->mu);
     HIP_CHECK(hipSetDevice(h->device));
     auto t0 = std::chrono::steady_clock::now();
@@ -553,6 +560,7 @@ static void debug_batch_impl(BatchEngine* E, DevVals<T>& V, int op, const double
 
 void debug_batch(pamg_hierarchy* h, int op, int prec, const double* in, double* out, hipStream_t s) {
     require_device(h);
+    require_l1_smoother(h);
     std::lock_guard<std::mutex> lk(h->mu);
     HIP_CHECK(hipSetDevice(h->device));
     BatchEngine* E = get_engine(h, prec, s);
@@ -580,6 +588,7 @@ void batch_retire(BatchEngine* E, int mask) {
 
 void batch_config(pamg_hierarchy* h, int prec, int32_t* cfg) {
     require_device(h);
+    require_l1_smoother(h);
     std::lock_guard<std::mutex> lk(h->mu);
     HIP_CHECK(hipSetDevice(h->device));
     BatchEngine* E = get_engine(h, prec, nullptr);

@@ -59,6 +59,17 @@ struct TileDict {
     int32_t max_len = 0;            // longest dictionary of the level
 };
 
+// Hybrid Gauss-Seidel schedule of one level in hierarchical (nested-aggregate)
+// order, blocks of nb consecutive rows: every row's depth in its block's
+// forward (earlier rows) and backward (later rows) dependency graph (rows of
+// one depth are independent, so a sweep runs depth by depth), each block's
+// largest depth per direction, and 1 / a_ii.
+struct GsLevel {
+    std::vector<uint8_t> depth_f, depth_b;
+    std::vector<int32_t> maxd;      // 2 per block: forward, backward
+    std::vector<double> ainv;       // 1 / a_ii
+};
+
 struct LayoutLevel {
     std::vector<int32_t> perm;      // canonical -> hierarchical index
     std::vector<int32_t> iperm;     // hierarchical -> canonical
@@ -75,6 +86,7 @@ struct LayoutLevel {
     // the 16-bit position of its column in its tile's dictionary.  A tile
     // holding one row / aggregate longer than a tile has no dictionary.
     TileDict up_dict, down_dict;
+    GsLevel gs;                     // hybrid Gauss-Seidel smoother only (l < L)
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
@@ -89,6 +101,9 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 void validate_csr(const pamg_csr& A, bool check_symmetry);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
 std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
+
+// Hybrid Gauss-Seidel schedule of a laid-out level (blocks of nb <= 256 rows).
+GsLevel gs_schedule(const LayoutLevel& L, int nb);
 
 // Coefficient-only reuse.  The Galerkin sum of one pairwise step as a plan:
 // for every coarse entry (canonical CSR order of Ac) the fine entries of A

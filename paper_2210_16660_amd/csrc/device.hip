@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "hier.hpp"
+#include "kernels_gs.hpp"
 
 namespace pamg {
 
@@ -45,6 +46,15 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         }
         if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size());
         maxn = std::max(maxn, lay[l].dinv.size());
+    }
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+        V.gsa.assign(nl, nullptr);
+        V.zt.assign(nl, nullptr);
+        for (int l = 0; l + 1 < nl; ++l) {
+            V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
+            V.zt[l] = dalloc<T>(h, lay[l].dinv.size());
+        }
+        V.zc = dalloc<T>(h, lay[nl - 1].dinv.size());
     }
     // A_L^{-1}: factorized on the device in FP64; the FP32 copy is its rounding
     const DevLevelIdx& C = h->idx[nl - 1];
@@ -117,6 +127,12 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
             I.down_loc = upload<uint16_t>(h, Ly.down_dict.local, s);
             I.down_dmax = std::max(1, (int)Ly.down_dict.max_len);
             I.down_dlen = (long long)Ly.down_dict.col.size();
+            if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+                I.gs_df = upload<uint8_t>(h, Ly.gs.depth_f, s);
+                I.gs_db = upload<uint8_t>(h, Ly.gs.depth_b, s);
+                I.gs_maxd = upload<int>(h, Ly.gs.maxd, s);
+                I.gs_nblk = (int)Ly.gs.maxd.size() / 2;
+            }
         }
     }
     upload_values<double>(h, h->f64, lay, s);
@@ -200,8 +216,20 @@ static void launch_down(const DevLevelIdx& I, const T* vd, const RT* r, const T*
                         hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_down<IT, T, RT>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
-               (const int*)I.ci, vd, r, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
+        LAUNCH((k_down<IT, T, RT, RT>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, vd, r, r, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
+               I.down_loc, rc, done);
+    });
+}
+
+// Residual of a smoothed z and its restriction: rc = P^T (r - A z).
+template <typename T, typename RT>
+static void launch_resid_restrict(const DevLevelIdx& I, const T* v, const RT* r, const T* z, const T* p, T* rc,
+                                  const int* done, hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_down<IT, T, RT, T>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, v, r, z, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
                I.down_loc, rc, done);
     });
 }
@@ -271,12 +299,79 @@ static int coarse_partials(int nL) { return nL > kCoarseRowsMin ? coarse_rows_gr
 
 // ---------------------------------------------------------------- schedule
 
+// `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from
+// x = 0 (pre-smoothing) or backward from x (post-smoothing).  Ping-pongs
+// between x and the level's second buffer; returns where the result is.
+template <typename T, typename RT>
+static T* enqueue_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, T* x, bool backward, const int* done,
+                      hipStream_t s) {
+    const DevLevelIdx& I = h->idx[l];
+    T* a = x;
+    T* b = (x == V.zt[l]) ? V.zp[l] : V.zt[l];
+    const T winv = (T)(1.0 / h->omega);
+    const dim3 g(I.gs_nblk), blk(kBlock);
+    for (int k = 0; k < h->sweeps; ++k) {
+        if (backward)
+            hipLaunchKernelGGL((k_hgs<T, RT, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_db, I.gs_maxd, r,
+                               (const T*)a, b, winv, done);
+        else if (k == 0)
+            hipLaunchKernelGGL((k_hgs<T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
+                               (const T*)nullptr, b, winv, done);
+        else
+            hipLaunchKernelGGL((k_hgs<T, RT, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
+                               (const T*)a, b, winv, done);
+        std::swap(a, b);
+    }
+    return a;
+}
+
+// V-cycle with the hybrid Gauss-Seidel smoother (L >= 1): per level `sweeps`
+// forward sweeps from zero, the residual and its restriction (tile kernel),
+// then after the coarse solve the prolongated correction and `sweeps`
+// backward sweeps.  Returns the number of z . dv partials.
+template <typename T>
+static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
+                             const int* done, hipStream_t s) {
+    const int L = h->L;
+    std::vector<T*> z(L + 1, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const DevLevelIdx& I = h->idx[l];
+        if (l == 0) {
+            z[0] = enqueue_hgs<T, double>(h, V, 0, r0, V.zp[0], false, done, s);
+            launch_resid_restrict<T, double>(I, V.v[0], r0, z[0], V.p[0], V.r[1], done, s);
+        } else {
+            z[l] = enqueue_hgs<T, T>(h, V, l, (const T*)V.r[l], V.zp[l], false, done, s);
+            launch_resid_restrict<T, T>(I, V.v[l], V.r[l], z[l], V.p[l], V.r[l + 1], done, s);
+        }
+    }
+    const int nL = h->idx[L].n;
+    LAUNCH((k_gs_coarse<T, T>), vec_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
+    z[L] = V.zc;
+    for (int l = L - 1; l >= 0; --l) {
+        const DevLevelIdx& I = h->idx[l];
+        const int nc = h->idx[l + 1].n;
+        LAUNCH((k_gs_prolong<T>), vec_grid(nc), 0, s, nc, (const int*)I.aggptr, (const T*)V.p[l],
+               (const T*)z[l + 1], z[l], done);
+        if (l == 0)
+            z[0] = enqueue_hgs<T, double>(h, V, 0, r0, z[0], true, done, s);
+        else
+            z[l] = enqueue_hgs<T, T>(h, V, l, (const T*)V.r[l], z[l], true, done, s);
+    }
+    const int n0 = h->idx[0].n, g = vec_grid(n0);
+    LAUNCH((k_gs_out<T>), g, 0, s, n0, (const T*)z[0], z_out, dv, h->partial, done);
+    return g;
+}
+
 // z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
 // up-sweep also writes the partials of z . dv.  Returns the number of partials.
 template <typename T>
 static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
                           const int* done, hipStream_t s) {
     const int L = h->L;
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS && L > 0) return enqueue_vcycle_gs<T>(h, V, r0, z_out, dv, done, s);
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         if (l == 0)
@@ -519,6 +614,23 @@ static void debug_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, const do
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.perm, (const double*)h->dbg1, out);
             break;
         }
+        case PAMG_OP_SMOOTH: {
+            // hybrid GS sweeps: forward from zero on r = in0, or backward from x = in1
+            if (h->smoother != PAMG_SMOOTHER_HYBRID_GS || l >= h->L)
+                throw Error(PAMG_E_INVALID, "SMOOTH needs a hybrid Gauss-Seidel hierarchy and level < L");
+            const bool back = in1 != nullptr;
+            if (back) LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in1, V.zp[l]);
+            T* res;
+            if (l == 0) {
+                LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
+                res = enqueue_hgs<T, double>(h, V, 0, (const double*)h->dbg0, V.zp[0], back, nodone, s);
+            } else {
+                LAUNCH((k_gather<double, T>), gv, 0, s, I.n, (const int*)I.iperm, in0, V.dbg_in);
+                res = enqueue_hgs<T, T>(h, V, l, (const T*)V.dbg_in, V.zp[l], back, nodone, s);
+            }
+            LAUNCH((k_gather<T, double>), gv, 0, s, I.n, (const int*)I.perm, (const T*)res, out);
+            break;
+        }
         case PAMG_OP_VCYCLE: {
             if (l != 0) throw Error(PAMG_E_INVALID, "VCYCLE is applied at level 0");
             LAUNCH((k_gather<double, double>), gv, 0, s, I.n, (const int*)I.iperm, in0, h->dbg0);
@@ -648,8 +760,29 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
         launch = [=]() {
             launch_krylov(I, h->f64.v[0], h->z, h->p[0], h->p[1], h->q, h->r, h->st, h->partial, nodone, s);
         };
+    } else if (op == PAMG_OP_SMOOTH) {
+        // one backward hybrid Gauss-Seidel sweep: CSR (int32 columns), own r,
+        // x_old, 1/a_ii, depth, x_new; per block its largest depths
+        if (h->smoother != PAMG_SMOOTHER_HYBRID_GS || l >= h->L)
+            throw Error(PAMG_E_INVALID, "SMOOTH needs a hybrid Gauss-Seidel hierarchy and level < L");
+        *bytes = I.nnz * (4 + sz) + 4 * (n + 1) + n * ((l == 0 ? 8 : sz) + 3 * sz + 1) + 8 * (uint64_t)I.gs_nblk;
+        const T winv = (T)(1.0 / h->omega);
+        if (l == 0)
+            launch = [=]() {
+                hipLaunchKernelGGL((k_hgs<T, double, true, false>), dim3(I.gs_nblk), dim3(kBlock), 0, s, I.n,
+                                   h->gs_block, (const int*)I.rp, (const int*)I.ci, (const T*)V.v[0],
+                                   (const T*)V.gsa[0], I.gs_db, I.gs_maxd, (const double*)h->r, (const T*)V.zp[0],
+                                   V.zt[0], winv, nodone);
+            };
+        else
+            launch = [=]() {
+                hipLaunchKernelGGL((k_hgs<T, T, true, false>), dim3(I.gs_nblk), dim3(kBlock), 0, s, I.n,
+                                   h->gs_block, (const int*)I.rp, (const int*)I.ci, (const T*)V.v[l],
+                                   (const T*)V.gsa[l], I.gs_db, I.gs_maxd, (const T*)V.r[l], (const T*)V.zp[l],
+                                   V.zt[l], winv, nodone);
+            };
     } else {
-        throw Error(PAMG_E_INVALID, "op must be DOWN, UP, SPMV or KRYLOV");
+        throw Error(PAMG_E_INVALID, "op must be DOWN, UP, SPMV, KRYLOV or SMOOTH");
     }
     *ms = time_launches(launch, reps, s);
 }
@@ -705,6 +838,17 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
         prm.max_dense > kMaxDense || !(prm.min_ratio == prm.min_ratio) || prm.agg_steps < 1 || prm.agg_steps > kMaxAggSteps)
         throw Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
                                     "1 <= max_dense <= 8192, min_ratio not NaN, 1 <= agg_steps <= 4)");
+    if (prm.smoother == PAMG_SMOOTHER_L1_JACOBI) {
+        if (prm.sweeps != 0 && prm.sweeps != 1)
+            throw Error(PAMG_E_INVALID, "the l1-Jacobi smoother runs one sweep per side (sweeps 0 or 1)");
+    } else if (prm.smoother == PAMG_SMOOTHER_HYBRID_GS) {
+        if (prm.sweeps < 0 || prm.sweeps > 16 || prm.gs_block < 0 || prm.gs_block > 256 ||
+            !(prm.omega >= 0.0) || std::isinf(prm.omega))
+            throw Error(PAMG_E_INVALID, "bad hybrid Gauss-Seidel params (need 0 <= sweeps <= 16, "
+                                        "0 <= gs_block <= 256, finite omega >= 0; 0 = default)");
+    } else {
+        throw Error(PAMG_E_INVALID, "unknown smoother");
+    }
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<HostBuild> b(new HostBuild());
@@ -712,6 +856,10 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
     validate_csr(A, prm.check_symmetry != 0);
     b->H = build_hierarchy(A, prm);
     b->lay = build_layout(b->H);
+    if (prm.smoother == PAMG_SMOOTHER_HYBRID_GS) {
+        const int nb = prm.gs_block > 0 ? prm.gs_block : 256;
+        for (size_t l = 0; l + 1 < b->lay.size(); ++l) b->lay[l].gs = gs_schedule(b->lay[l], nb);
+    }
     b->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return b;
 }
@@ -721,6 +869,12 @@ int coarsest_n(const HostBuild& b) { return b.H.lev.back().A.n; }
 pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream) {
     auto t0 = std::chrono::steady_clock::now();
     pamg_hierarchy* h = new_hierarchy(b->prm.host_only != 0);
+    h->smoother = b->prm.smoother;
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+        h->sweeps = b->prm.sweeps > 0 ? b->prm.sweeps : 4;
+        h->gs_block = b->prm.gs_block > 0 ? b->prm.gs_block : 256;
+        h->omega = b->prm.omega > 0.0 ? b->prm.omega : 1.5;
+    }
     try {
         h->host = std::move(b->H);
         if (b->prm.host_only) {

@@ -25,6 +25,8 @@ struct DevVals {
     bool built = false;
     std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
     std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
+    std::vector<T*> gsa, zt;          // hybrid GS: 1 / a_ii and a second iterate buffer (l < L)
+    T* zc = nullptr;                  // hybrid GS: coarsest-level solution
     T* ainv = nullptr;                // dense A_L^{-1}
     T* dbg_in = nullptr;              // scratch in this precision (max n)
     T* dbg_in2 = nullptr;
@@ -50,6 +52,10 @@ struct DevLevelIdx {
     const uint16_t *up_loc = nullptr, *down_loc = nullptr;
     int up_dmax = 1, down_dmax = 1;     // longest dictionary (dynamic LDS of the tile kernels)
     long long up_dlen = 0, down_dlen = 0;  // total dictionary entries
+    // hybrid Gauss-Seidel schedule (l < L): per-row depths, per-block largest depths
+    const uint8_t *gs_df = nullptr, *gs_db = nullptr;
+    const int* gs_maxd = nullptr;
+    int gs_nblk = 0;
 };
 
 // Coefficient-only reuse: built on the first value update and kept.  Its
@@ -75,6 +81,9 @@ struct pamg_hierarchy {
     int device = 0;
     int L = 0;
     bool host_only = false;
+    int smoother = PAMG_SMOOTHER_L1_JACOBI;   // hybrid GS: sweeps per side, block size, damping
+    int sweeps = 1, gs_block = 256;
+    double omega = 1.0;
     std::vector<pamg::DevLevelIdx> idx;
     pamg::DevVals<double> f64;
     pamg::DevVals<float> f32;

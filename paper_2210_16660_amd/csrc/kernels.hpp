@@ -177,11 +177,13 @@ __device__ __forceinline__ void tile_store_dict(int k0, int k1, const T (&a)[ITE
 // ----------------------------------------------------------------------------
 // Down-sweep at level l (pre-smooth from zero, residual, restriction):
 //   z = D^-1 r;  t = r - A z = r - (A D^-1) r;  rc[I] = sum_{i in G_I} p_i t_i
-// `ad` holds the column-scaled values a_ij / d_j, so one gather of r suffices.
-template <int ITEMS, typename T, typename RT>
+// `ad` holds the column-scaled values a_ij / d_j, so one gather of r suffices
+// (g = r).  With another smoother the same pass takes the smoothed z as g and
+// the plain values as `ad`: rc[I] = sum_{i in G_I} p_i (r_i - (A z)_i).
+template <int ITEMS, typename T, typename RT, typename GT>
 static __global__ __launch_bounds__(kBlock) void k_down(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ ad,
-    const RT* __restrict__ r, const T* __restrict__ p, const int* __restrict__ aggptr,
+    const RT* __restrict__ r, const GT* __restrict__ g, const T* __restrict__ p, const int* __restrict__ aggptr,
     const int4* __restrict__ tiles, int ntiles,
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, T* __restrict__ rc, const int* __restrict__ done) {
     if (*done) return;
@@ -200,7 +202,7 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             T a[ITEMS];
             uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-            const auto gather = [&](int c) { return (T)r[c]; };
+            const auto gather = [&](int c) { return (T)g[c]; };
             T x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
@@ -249,7 +251,7 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             T acc = 0;
             for (int m = f0; m < f1; ++m) {
                 T s = 0;
-                for (int k = rp[m] + tid; k < rp[m + 1]; k += kBlock) s += ad[k] * (T)r[ci[k]];
+                for (int k = rp[m] + tid; k < rp[m + 1]; k += kBlock) s += ad[k] * (T)g[ci[k]];
                 s = block_sum(s, s_red);
                 if (tid == 0) acc += p[m] * ((T)r[m] - s);
             }

@@ -11,7 +11,8 @@
 //     with aggregate-size composition the whole pairwise chain is re-run and
 //     the kept levels are taken from it;
 //   * the l1 diagonals (canonical row order), the device-order values, the
-//     column-scaled values a_ij / d_j, the FP32 copies;
+//     column-scaled values a_ij / d_j, 1 / a_ii for the hybrid Gauss-Seidel
+//     smoother, the FP32 copies;
 //   * the coarsest level's Cholesky factor and inverse (dense.hip).
 // Every product and sum is one IEEE operation (no contraction).
 #include <hip/hip_runtime.h>
@@ -70,6 +71,16 @@ static __global__ __launch_bounds__(kBlock) void k_scale_columns(long long nnz, 
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < nnz; k += stride)
         vd[k] = v[k] * dinv[ci[k]];
+}
+
+// Hybrid Gauss-Seidel: 1 / a_ii of every row (device order).
+static __global__ __launch_bounds__(kBlock) void k_diag_inverse(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const double* __restrict__ v,
+                                                         double* __restrict__ ainv) {
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) ainv[i] = 1.0 / v[k];
 }
 
 template <typename T>
@@ -176,6 +187,10 @@ static void update_values(pamg_hierarchy* h, const double* val, bool on_device, 
         if (j < h->L)
             hipLaunchKernelGGL(k_scale_columns, dim3(vec_grid(I.nnz)), dim3(kBlock), 0, s, I.nnz, (const int*)I.ci,
                                (const double*)V.v[j], (const double*)V.dinv[j], V.vd[j]);
+        const bool gs = h->smoother == PAMG_SMOOTHER_HYBRID_GS && j < h->L;
+        if (gs)
+            hipLaunchKernelGGL(k_diag_inverse, dim3(vec_grid(I.n)), dim3(kBlock), 0, s, I.n, (const int*)I.rp,
+                               (const int*)I.ci, (const double*)V.v[j], V.gsa[j]);
         if (h->f32.built) {
             hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(I.nnz)), dim3(kBlock), 0, s, I.nnz,
                                (const double*)V.v[j], h->f32.v[j]);
@@ -184,6 +199,9 @@ static void update_values(pamg_hierarchy* h, const double* val, bool on_device, 
             if (j < h->L)
                 hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(I.nnz)), dim3(kBlock), 0, s, I.nnz,
                                    (const double*)V.vd[j], h->f32.vd[j]);
+            if (gs)
+                hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(I.n)), dim3(kBlock), 0, s,
+                                   (long long)I.n, (const double*)V.gsa[j], h->f32.gsa[j]);
         }
     }
     HIP_CHECK(hipGetLastError());

@@ -402,6 +402,49 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
     return H;
 }
 
+// ------------------------------------------- hybrid Gauss-Seidel schedule
+
+GsLevel gs_schedule(const LayoutLevel& L, int nb) {
+    const int32_t n = (int32_t)L.dinv.size();
+    const int32_t nblk = (n + nb - 1) / nb;
+    GsLevel g;
+    g.depth_f.assign(n, 0);
+    g.depth_b.assign(n, 0);
+    g.maxd.assign(2 * (size_t)nblk, 0);
+    g.ainv.assign(n, 0.0);
+    std::atomic<int> bad{0};
+    parallel_for(nblk, [&](int64_t p) {
+        const int32_t b0 = (int32_t)p * nb, b1 = std::min(n, b0 + nb);
+        int32_t mf = 0, mb = 0;
+        for (int32_t i = b0; i < b1; ++i) {
+            int32_t d = 0;
+            for (int32_t k = L.rp[i]; k < L.rp[i + 1]; ++k) {
+                const int32_t j = L.ci[k];
+                if (j >= b0 && j < i) d = std::max(d, g.depth_f[j] + 1);
+                if (j == i) {
+                    if (!(L.v[k] > 0.0)) bad.store(1);
+                    g.ainv[i] = 1.0 / L.v[k];
+                }
+            }
+            g.depth_f[i] = (uint8_t)d;
+            mf = std::max(mf, d);
+        }
+        for (int32_t i = b1 - 1; i >= b0; --i) {
+            int32_t d = 0;
+            for (int32_t k = L.rp[i]; k < L.rp[i + 1]; ++k) {
+                const int32_t j = L.ci[k];
+                if (j > i && j < b1) d = std::max(d, g.depth_b[j] + 1);
+            }
+            g.depth_b[i] = (uint8_t)d;
+            mb = std::max(mb, d);
+        }
+        g.maxd[2 * p] = mf;
+        g.maxd[2 * p + 1] = mb;
+    });
+    if (bad.load()) throw Error(PAMG_E_NOT_SPD, "non-positive diagonal on a coarse level (Gauss-Seidel smoother)");
+    return g;
+}
+
 // ------------------------------------------------ coefficient-only reuse
 
 GalerkinPlan galerkin_plan(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,

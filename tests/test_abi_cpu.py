@@ -112,6 +112,18 @@ def test_bad_params_rejected():
         pamg.Hierarchy(lap7(3), host_only=1, min_ratio=float("nan"))
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, agg_steps=5)
+    # smoother parameters
+    for kw in [dict(smoother=2), dict(sweeps=2), dict(smoother="hgs", sweeps=17),
+               dict(smoother="hgs", gs_block=257), dict(smoother="hgs", omega=-1.0),
+               dict(smoother="hgs", omega=float("inf")), dict(smoother="hgs", gs_block=-1)]:
+        with pytest.raises(pamg.PamgError) as e:
+            pamg.Hierarchy(lap7(3), host_only=1, **kw)
+        assert e.value.code == pamg.E_INVALID, kw
+    # defaults and the paper's nu = 4 are accepted; the Gauss-Seidel schedule
+    # is built on the host
+    H = pamg.Hierarchy(lap7(8), host_only=1, smoother="hgs")
+    assert H.info().levels >= 2
+    pamg.Hierarchy(lap7(8), host_only=1, smoother="hgs", sweeps=4, gs_block=1, omega=0.7)
 
 
 def test_host_only_hierarchy_refuses_device_calls():
