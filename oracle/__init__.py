@@ -48,7 +48,12 @@ def lib():
             L = C.CDLL(_LIB)
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.oracle_setup.argtypes = [C.c_int, ip, ip, dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
-                                   C.c_int, C.POINTER(vp)]
+                                   C.c_int, C.c_int, C.POINTER(vp)]
+        L.oracle_prolongator_nnz.argtypes = [vp, C.c_int]
+        L.oracle_prolongator_nnz.restype = C.c_long
+        L.oracle_prolongator_omega.argtypes = [vp, C.c_int]
+        L.oracle_prolongator_omega.restype = C.c_double
+        L.oracle_get_prolongator.argtypes = [vp, C.c_int, ip, ip, dp]
         L.oracle_setup.restype = C.c_int
         L.oracle_round_f32.argtypes = [vp, C.POINTER(vp)]
         L.oracle_round_f32.restype = C.c_int
@@ -112,7 +117,7 @@ class Hierarchy:
     """The oracle's AMG hierarchy in canonical (setup) numbering."""
 
     def __init__(self, A, max_coarse=200, max_levels=50, max_dense=8192, min_ratio=1.5, match_all=False,
-                 agg_steps=1, _handle=None):
+                 agg_steps=1, smooth_prolongator=False, _handle=None):
         L = lib()
         if _handle is not None:
             self._h = _handle
@@ -122,7 +127,8 @@ class Hierarchy:
         h = C.c_void_p()
         rc = L.oracle_setup(int(A.n), _p(self._keep[0], C.c_int), _p(self._keep[1], C.c_int),
                             _p(self._keep[2], C.c_double), max_coarse, max_levels, max_dense,
-                            float(min_ratio), 1 if match_all else 0, int(agg_steps), C.byref(h))
+                            float(min_ratio), 1 if match_all else 0, int(agg_steps),
+                            1 if smooth_prolongator else 0, C.byref(h))
         if rc != 0:
             raise OracleError(rc, "oracle_setup")
         self._h = h
@@ -161,6 +167,23 @@ class Hierarchy:
         if rc != 0:
             raise OracleError(rc, "oracle_set_smoother")
         return self
+
+    def prolongator(self, l: int):
+        """P_l as scipy CSR: the smoothed prolongator (R15), or the tentative
+        one built from agg and p."""
+        import scipy.sparse as sp
+        n, nc = self.n(l), self.n(l + 1)
+        nnz = lib().oracle_prolongator_nnz(self._h, l)
+        if nnz == 0:
+            return sp.csr_matrix((self.p(l), (np.arange(n), self.agg(l))), shape=(n, nc))
+        rp = np.empty(n + 1, np.int32)
+        ci = np.empty(nnz, np.int32)
+        v = np.empty(nnz, np.float64)
+        lib().oracle_get_prolongator(self._h, l, _p(rp, C.c_int), _p(ci, C.c_int), _p(v, C.c_double))
+        return sp.csr_matrix((v, ci, rp), shape=(n, nc))
+
+    def prolongator_omega(self, l: int) -> float:
+        return lib().oracle_prolongator_omega(self._h, l)
 
     def nested_order(self, l: int) -> np.ndarray:
         o = np.empty(self.n(l), np.int32)

@@ -81,8 +81,20 @@
  *      within a block, in nested order,
  *      d_i = ((r_i - sum_j a_ij x_j) - sum_{j earlier in the block} a_ij d_j) / a_ii
  *      (both sums in ascending column order), then x_i += d_i / omega.  A
- *      backward sweep runs each block in reverse (M^T).  Pre-smoothing: nu forward sweeps from zero;
- *      post-smoothing: nu backward sweeps, so the V-cycle stays symmetric.
+ *      backward sweep runs each block in reverse (M^T).  Pre-smoothing: nu
+ *      forward sweeps from zero; post-smoothing: nu backward sweeps, so the
+ *      V-cycle stays symmetric.
+ *   R15 smoothed prolongator (Sec. 3.1, optional, pairwise levels only):
+ *      P = (I - omega D^-1 A) P^ with D = diag(A) and
+ *      omega = 1 / ||D^-1 A||_inf = 1 / max_i ((sum_j |a_ij|) / a_ii).
+ *      Row i: P_iJ = [J = agg(i)] p_i - sum_{j: agg(j) = J} (omega (a_ij / a_ii)) p_j,
+ *      starting from p_i (or 0.0) and subtracting in ascending j; its pattern
+ *      is {agg(j) : a_ij stored}.  Galerkin: B = A P with
+ *      B_kJ = 0.0 + sum over j ascending of a_kj P_jJ, then for I <= J
+ *      A_{l+1}[I,J] = 0.0 + sum over i ascending of P_iI B_iJ, and
+ *      A_{l+1}[J,I] = A_{l+1}[I,J] (bitwise symmetric).  The matching of the
+ *      next level runs on this matrix with the tentative coarse w.
+ *      Restriction is P^T (sums over ascending i), prolongation P.
  */
 #include <math.h>
 #include <stdint.h>
@@ -122,6 +134,10 @@ typedef struct {
     int *pw_agg[OR_MAX_LEVELS];     /* pairwise step m: level m -> m+1 */
     double *pw_p[OR_MAX_LEVELS];
     int kept[OR_MAX_LEVELS];        /* pairwise level of each kept level */
+    /* smoothed prolongators (R15): P[l] is n_l x n_{l+1} (l < L) */
+    int smoothed;
+    or_csr P[OR_MAX_LEVELS];
+    double omega_p[OR_MAX_LEVELS];
     /* smoother (R1 l1-Jacobi unless set by oracle_set_smoother, R14) */
     int smoother;                   /* 0: l1-Jacobi, 1: hybrid forward/backward Gauss-Seidel */
     int gs_nu, gs_nb;
@@ -141,6 +157,7 @@ void oracle_free(or_hier *h) {
         csr_free(&h->A[l]);
         free(h->w[l]); free(h->dinv[l]); free(h->agg[l]); free(h->p[l]);
         free(h->pw_agg[l]); free(h->pw_p[l]);
+        csr_free(&h->P[l]);
     }
     free(h->chol);
     free(h);
@@ -307,6 +324,186 @@ static int galerkin(const or_csr *a, const int *agg, const double *p, int nc, or
     return OR_OK;
 }
 
+/* ------------------------------------------- smoothed prolongator (R15) */
+
+static int smoothed_prolongator(const or_csr *a, const int *agg, const double *p, or_csr *P, double *omega_out) {
+    int n = a->n;
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0, aii = 0.0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            s += fabs(a->v[k]);
+            if (a->ci[k] == i) aii = a->v[k];
+        }
+        double r = s / aii;
+        if (r > mx) mx = r;
+    }
+    double omega = 1.0 / mx;
+    *omega_out = omega;
+    /* pattern: the distinct agg(j) of each row, ascending */
+    P->n = n;
+    P->rp = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *cols = (int *)malloc(sizeof(int) * (size_t)(a->nnz > 0 ? a->nnz : 1));
+    if (!P->rp || !cols) { free(cols); return OR_E_OOM; }
+    long q = 0;
+    for (int i = 0; i < n; ++i) {
+        long r0 = q;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            int J = agg[a->ci[k]], dup = 0;
+            for (long u = r0; u < q; ++u)
+                if (cols[u] == J) { dup = 1; break; }
+            if (!dup) cols[q++] = J;
+        }
+        for (long u = r0 + 1; u < q; ++u) {        /* insertion sort of the row */
+            int c = cols[u];
+            long w = u;
+            while (w > r0 && cols[w - 1] > c) { cols[w] = cols[w - 1]; --w; }
+            cols[w] = c;
+        }
+        P->rp[i + 1] = (int)q;
+    }
+    P->nnz = q;
+    P->ci = (int *)malloc(sizeof(int) * (size_t)(q > 0 ? q : 1));
+    P->v = (double *)malloc(sizeof(double) * (size_t)(q > 0 ? q : 1));
+    if (!P->ci || !P->v) { free(cols); return OR_E_OOM; }
+    memcpy(P->ci, cols, sizeof(int) * (size_t)q);
+    free(cols);
+    for (int i = 0; i < n; ++i) {
+        double aii = diag_entry(a, i);
+        for (int u = P->rp[i]; u < P->rp[i + 1]; ++u) P->v[u] = P->ci[u] == agg[i] ? p[i] : 0.0;
+        for (int k = a->rp[i]; k < a->rp[i + 1]; ++k) {
+            int j = a->ci[k], J = agg[j];
+            int u = P->rp[i];
+            while (P->ci[u] != J) ++u;
+            P->v[u] = P->v[u] - (omega * (a->v[k] / aii)) * p[j];
+        }
+    }
+    return OR_OK;
+}
+
+static void sort_ints(int *x, int m) {
+    for (int u = 1; u < m; ++u) {
+        int c = x[u], w = u;
+        while (w > 0 && x[w - 1] > c) { x[w] = x[w - 1]; --w; }
+        x[w] = c;
+    }
+}
+
+/* A_c = P^T A P through B = A P; the upper triangle is summed and mirrored (R15) */
+static int galerkin_smoothed(const or_csr *a, const or_csr *P, int nc, or_csr *out) {
+    int n = a->n, st = OR_OK;
+    double *acc = (double *)calloc((size_t)nc, sizeof(double));
+    int *mark = (int *)malloc(sizeof(int) * (size_t)nc);
+    int *list = (int *)malloc(sizeof(int) * (size_t)nc);
+    or_csr B, U;
+    memset(&B, 0, sizeof(B));
+    memset(&U, 0, sizeof(U));
+    B.rp = (int *)calloc((size_t)n + 1, sizeof(int));
+    U.rp = (int *)calloc((size_t)nc + 1, sizeof(int));
+    int *tp = (int *)calloc((size_t)nc + 1, sizeof(int));
+    int *ti = (int *)malloc(sizeof(int) * (size_t)(P->nnz > 0 ? P->nnz : 1));
+    double *tv = (double *)malloc(sizeof(double) * (size_t)(P->nnz > 0 ? P->nnz : 1));
+    int *fill = (int *)malloc(sizeof(int) * ((size_t)nc + 1));
+    long cap = 1024;
+    B.ci = (int *)malloc(sizeof(int) * (size_t)cap);
+    B.v = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!acc || !mark || !list || !B.rp || !U.rp || !tp || !ti || !tv || !fill || !B.ci || !B.v) {
+        st = OR_E_OOM;
+        goto done;
+    }
+    /* B = A P, row k: B_kJ = 0.0 + sum over j ascending of a_kj P_jJ */
+    for (int J = 0; J < nc; ++J) mark[J] = -1;
+    long used = 0;
+    for (int k = 0; k < n; ++k) {
+        int m = 0;
+        for (int e = a->rp[k]; e < a->rp[k + 1]; ++e) {
+            int j = a->ci[e];
+            for (int u = P->rp[j]; u < P->rp[j + 1]; ++u) {
+                int J = P->ci[u];
+                if (mark[J] != k) { mark[J] = k; acc[J] = 0.0; list[m++] = J; }
+                acc[J] = acc[J] + a->v[e] * P->v[u];
+            }
+        }
+        sort_ints(list, m);
+        if (used + m > cap) {
+            while (used + m > cap) cap *= 2;
+            B.ci = (int *)realloc(B.ci, sizeof(int) * (size_t)cap);
+            B.v = (double *)realloc(B.v, sizeof(double) * (size_t)cap);
+            if (!B.ci || !B.v) { st = OR_E_OOM; goto done; }
+        }
+        for (int x = 0; x < m; ++x) { B.ci[used + x] = list[x]; B.v[used + x] = acc[list[x]]; }
+        used += m;
+        B.rp[k + 1] = (int)used;
+    }
+    /* P^T: for each coarse I the rows i with P_iI stored, ascending i */
+    for (long u = 0; u < P->nnz; ++u) tp[P->ci[u] + 1]++;
+    for (int I = 0; I < nc; ++I) tp[I + 1] += tp[I];
+    memcpy(fill, tp, sizeof(int) * (size_t)nc);
+    for (int i = 0; i < n; ++i)
+        for (int u = P->rp[i]; u < P->rp[i + 1]; ++u) {
+            int I = P->ci[u];
+            ti[fill[I]] = i;
+            tv[fill[I]] = P->v[u];
+            fill[I]++;
+        }
+    /* upper triangle: for J >= I, 0.0 + sum over i ascending of P_iI B_iJ */
+    cap = 1024;
+    U.ci = (int *)malloc(sizeof(int) * (size_t)cap);
+    U.v = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!U.ci || !U.v) { st = OR_E_OOM; goto done; }
+    for (int J = 0; J < nc; ++J) mark[J] = -1;
+    used = 0;
+    for (int I = 0; I < nc; ++I) {
+        int m = 0;
+        for (int x = tp[I]; x < tp[I + 1]; ++x) {
+            int i = ti[x];
+            for (int u = B.rp[i]; u < B.rp[i + 1]; ++u) {
+                int J = B.ci[u];
+                if (J < I) continue;
+                if (mark[J] != I) { mark[J] = I; acc[J] = 0.0; list[m++] = J; }
+                acc[J] = acc[J] + tv[x] * B.v[u];
+            }
+        }
+        sort_ints(list, m);
+        if (used + m > cap) {
+            while (used + m > cap) cap *= 2;
+            U.ci = (int *)realloc(U.ci, sizeof(int) * (size_t)cap);
+            U.v = (double *)realloc(U.v, sizeof(double) * (size_t)cap);
+            if (!U.ci || !U.v) { st = OR_E_OOM; goto done; }
+        }
+        for (int x = 0; x < m; ++x) { U.ci[used + x] = list[x]; U.v[used + x] = acc[list[x]]; }
+        used += m;
+        U.rp[I + 1] = (int)used;
+    }
+    /* full rows: the mirrored entries (J < I) in ascending J, then the upper row */
+    for (int I = 0; I <= nc; ++I) fill[I] = 0;
+    for (int I = 0; I < nc; ++I)
+        for (int u = U.rp[I]; u < U.rp[I + 1]; ++u) {
+            fill[I + 1]++;
+            if (U.ci[u] != I) fill[U.ci[u] + 1]++;
+        }
+    for (int I = 0; I < nc; ++I) fill[I + 1] += fill[I];
+    out->n = nc;
+    out->nnz = fill[nc];
+    out->rp = (int *)malloc(sizeof(int) * ((size_t)nc + 1));
+    out->ci = (int *)malloc(sizeof(int) * (size_t)(out->nnz > 0 ? out->nnz : 1));
+    out->v = (double *)malloc(sizeof(double) * (size_t)(out->nnz > 0 ? out->nnz : 1));
+    if (!out->rp || !out->ci || !out->v) { st = OR_E_OOM; goto done; }
+    memcpy(out->rp, fill, sizeof(int) * ((size_t)nc + 1));
+    for (int I = 0; I < nc; ++I) mark[I] = out->rp[I];
+    for (int I = 0; I < nc; ++I)
+        for (int u = U.rp[I]; u < U.rp[I + 1]; ++u) {
+            int J = U.ci[u];
+            if (J != I) { out->ci[mark[J]] = I; out->v[mark[J]] = U.v[u]; mark[J]++; }
+        }
+    for (int I = 0; I < nc; ++I)
+        for (int u = U.rp[I]; u < U.rp[I + 1]; ++u) { out->ci[mark[I]] = U.ci[u]; out->v[mark[I]] = U.v[u]; mark[I]++; }
+done:
+    free(acc); free(mark); free(list); free(tp); free(ti); free(tv); free(fill);
+    csr_free(&B); csr_free(&U);
+    return st;
+}
+
 /* ------------------------------------------------- l1 diagonal (R1) */
 
 static int l1_inverse(const or_csr *a, double *dinv) {
@@ -439,11 +636,12 @@ static int validate(int n, const int *rp, const int *ci, const double *v) {
 
 int oracle_setup(int n, const int *rp, const int *ci, const double *v,
                  int max_coarse, int max_levels, int max_dense, double min_ratio, int match_all,
-                 int agg_steps, or_hier **out) {
+                 int agg_steps, int smooth_p, or_hier **out) {
     *out = NULL;
     int st = validate(n, rp, ci, v);
     if (st) return st;
     if (max_levels < 1 || max_levels > OR_MAX_LEVELS || agg_steps < 1) return OR_E_INVALID;
+    if (smooth_p && agg_steps != 1) return OR_E_INVALID;      /* R15: pairwise levels only */
     or_hier *h = (or_hier *)calloc(1, sizeof(or_hier));
     if (!h) return OR_E_OOM;
     or_csr *A0 = &h->A[0];
@@ -483,11 +681,17 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
         if (!h->agg[l] || !h->p[l] || !h->w[l + 1]) { free(mate); oracle_free(h); return OR_E_OOM; }
         int nc = build_aggregates(A->n, mate, h->w[l], h->agg[l], h->p[l], h->w[l + 1]);
         free(mate);
-        st = galerkin(A, h->agg[l], h->p[l], nc, &h->A[l + 1]);
+        if (smooth_p) {                                          /* R15 */
+            st = smoothed_prolongator(A, h->agg[l], h->p[l], &h->P[l], &h->omega_p[l]);
+            if (!st) st = galerkin_smoothed(A, &h->P[l], nc, &h->A[l + 1]);
+        } else {
+            st = galerkin(A, h->agg[l], h->p[l], nc, &h->A[l + 1]);
+        }
         if (st) { oracle_free(h); return st; }
         ++l;
     }
     h->nlev = l + 1;
+    h->smoothed = smooth_p ? 1 : 0;
     if (h->A[l].n > max_dense) { oracle_free(h); return OR_E_STALLED; }
     st = keep_pairwise_chain(h);
     if (st) { oracle_free(h); return st; }
@@ -520,7 +724,7 @@ static int *dup_ints(const int *a, size_t n) {
 int oracle_update(const or_hier *h, const double *v, or_hier **out) {
     *out = NULL;
     const or_csr *A0 = &h->A[0];
-    if (!v || h->pw_nlev < 1) return OR_E_INVALID;
+    if (!v || h->pw_nlev < 1 || h->smoothed) return OR_E_INVALID;   /* R15: P depends on A */
     int st = validate(A0->n, A0->rp, A0->ci, v);
     if (st) return st;
     or_hier *g = (or_hier *)calloc(1, sizeof(or_hier));
@@ -601,8 +805,21 @@ int oracle_round_f32(const or_hier *h, or_hier **out) {
             memcpy(g->agg[l], h->agg[l], sizeof(int) * (size_t)a->n);
             for (int i = 0; i < a->n; ++i) g->p[l][i] = (double)(float)h->p[l][i];
             g->n_pairs[l] = h->n_pairs[l];
+            if (h->smoothed) {
+                const or_csr *P = &h->P[l];
+                or_csr *Q = &g->P[l];
+                Q->n = P->n; Q->nnz = P->nnz;
+                Q->rp = (int *)malloc(sizeof(int) * ((size_t)P->n + 1));
+                Q->ci = (int *)malloc(sizeof(int) * (size_t)(P->nnz > 0 ? P->nnz : 1));
+                Q->v = (double *)malloc(sizeof(double) * (size_t)(P->nnz > 0 ? P->nnz : 1));
+                if (!Q->rp || !Q->ci || !Q->v) { oracle_free(g); return OR_E_OOM; }
+                memcpy(Q->rp, P->rp, sizeof(int) * ((size_t)P->n + 1));
+                memcpy(Q->ci, P->ci, sizeof(int) * (size_t)P->nnz);
+                for (long k = 0; k < P->nnz; ++k) Q->v[k] = (double)(float)P->v[k];
+            }
         }
     }
+    g->smoothed = h->smoothed;
     int nL = h->A[h->nlev - 1].n;
     g->chol = (double *)malloc(sizeof(double) * (size_t)nL * (size_t)nL);
     if (!g->chol) { oracle_free(g); return OR_E_OOM; }
@@ -627,6 +844,14 @@ void oracle_get_level(const or_hier *h, int l, int *rp, int *ci, double *v) {
 void oracle_get_agg(const or_hier *h, int l, int *agg) { memcpy(agg, h->agg[l], sizeof(int) * (size_t)h->A[l].n); }
 void oracle_get_p(const or_hier *h, int l, double *p) { memcpy(p, h->p[l], sizeof(double) * (size_t)h->A[l].n); }
 void oracle_get_w(const or_hier *h, int l, double *w) { memcpy(w, h->w[l], sizeof(double) * (size_t)h->A[l].n); }
+long oracle_prolongator_nnz(const or_hier *h, int l) { return h->smoothed ? h->P[l].nnz : 0; }
+double oracle_prolongator_omega(const or_hier *h, int l) { return h->omega_p[l]; }
+void oracle_get_prolongator(const or_hier *h, int l, int *rp, int *ci, double *v) {
+    const or_csr *P = &h->P[l];
+    memcpy(rp, P->rp, sizeof(int) * ((size_t)P->n + 1));
+    memcpy(ci, P->ci, sizeof(int) * (size_t)P->nnz);
+    memcpy(v, P->v, sizeof(double) * (size_t)P->nnz);
+}
 void oracle_get_dinv(const or_hier *h, int l, double *d) { memcpy(d, h->dinv[l], sizeof(double) * (size_t)h->A[l].n); }
 void oracle_get_chol(const or_hier *h, double *L) {
     int n = h->A[h->nlev - 1].n;
@@ -641,11 +866,26 @@ void oracle_spmv(const or_hier *h, int l, const double *x, double *y) { csr_mv(&
 void oracle_restrict(const or_hier *h, int l, const double *t, double *rc) {
     int nc = h->A[l + 1].n;
     for (int I = 0; I < nc; ++I) rc[I] = 0.0;
+    if (h->smoothed) {                                           /* P^T t, ascending i (R15) */
+        const or_csr *P = &h->P[l];
+        for (int i = 0; i < P->n; ++i)
+            for (int u = P->rp[i]; u < P->rp[i + 1]; ++u) rc[P->ci[u]] += P->v[u] * t[i];
+        return;
+    }
     for (int i = 0; i < h->A[l].n; ++i) rc[h->agg[l][i]] += h->p[l][i] * t[i];
 }
 
 /* z += P_l e */
 void oracle_prolong_add(const or_hier *h, int l, const double *e, double *z) {
+    if (h->smoothed) {                                           /* z += P e (R15) */
+        const or_csr *P = &h->P[l];
+        for (int i = 0; i < P->n; ++i) {
+            double s = 0.0;
+            for (int u = P->rp[i]; u < P->rp[i + 1]; ++u) s += P->v[u] * e[P->ci[u]];
+            z[i] += s;
+        }
+        return;
+    }
     for (int i = 0; i < h->A[l].n; ++i) z[i] += h->p[l][i] * e[h->agg[l][i]];
 }
 

@@ -56,6 +56,15 @@ MUTANTS = {
     "hgs_omega_inside": ("d[i] = ((r[i] - old) - fresh) / aii;", "d[i] = ((r[i] - old) - fresh) / (h->gs_omega * aii);"),
     "nested_members_descending": ("for (int i = 0; i < nf; ++i) finer[first[h->agg[m][i]]++] = i;",
                                   "for (int i = nf - 1; i >= 0; --i) finer[first[h->agg[m][i]]++] = i;"),
+    "sa_omega_l1_diagonal": ("        double r = s / aii;\n        if (r > mx) mx = r;", "        double r = s / s;\n        if (r > mx) mx = r;"),
+    "sa_smoothing_sign": ("P->v[u] = P->v[u] - (omega * (a->v[k] / aii)) * p[j];",
+                          "P->v[u] = P->v[u] + (omega * (a->v[k] / aii)) * p[j];"),
+    "sa_wrong_column_weight": ("P->v[u] = P->v[u] - (omega * (a->v[k] / aii)) * p[j];",
+                               "P->v[u] = P->v[u] - (omega * (a->v[k] / aii)) * p[i];"),
+    "sa_restrict_uses_tentative": ("for (int u = P->rp[i]; u < P->rp[i + 1]; ++u) rc[P->ci[u]] += P->v[u] * t[i];",
+                                   "rc[h->agg[l][i]] += h->p[l][i] * t[i];"),
+    "sa_galerkin_drops_lower_mirror": ("if (J != I) { out->ci[mark[J]] = I; out->v[mark[J]] = U.v[u]; mark[J]++; }",
+                                       "if (J != I) { out->ci[mark[J]] = I; out->v[mark[J]] = 0.0; mark[J]++; }"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

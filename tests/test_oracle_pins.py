@@ -533,6 +533,76 @@ def test_composed_hierarchy_solves():
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
 
 
+# --------------------------------------------------------------------------- smoothed prolongator
+
+@pytest.mark.parametrize("case", ["varcoef_9", "q1_8", "lap7_10"])
+def test_smoothed_prolongator_definition(case):
+    # Sec. 3.1: P = (I - omega D^-1 A) P^, D = diag(A), omega = 1/||D^-1 A||_inf,
+    # against dense numpy on every level; the coarse matrix is P^T A P and is
+    # stored bitwise symmetric; P keeps w in range: P w_c = w - omega D^-1 A w
+    A = {"varcoef_9": lambda: varcoef7(9, seed=30), "q1_8": lambda: q1_stretched(8, 1.05),
+         "lap7_10": lambda: lap7(10)}[case]()
+    H = oracle.Hierarchy(A, smooth_prolongator=True)
+    assert H.nlevels >= 3
+    for l in range(H.nlevels - 1):
+        Al = H.level_scipy(l).toarray()
+        d = np.diag(Al)
+        om = 1.0 / np.max(np.abs(Al).sum(axis=1) / d)
+        assert abs(H.prolongator_omega(l) - om) <= 4 * ULP * om
+        Ph = sp.csr_matrix((H.p(l), (np.arange(H.n(l)), H.agg(l))), shape=(H.n(l), H.n(l + 1))).toarray()
+        Pd = (np.eye(H.n(l)) - om * (Al / d[:, None])) @ Ph
+        P = H.prolongator(l).toarray()
+        assert np.abs(P - Pd).max() <= 1e-14 * np.abs(Pd).max(), l
+        # pattern: exactly the aggregates of each row's neighbours
+        Ps = H.prolongator(l)
+        for i in range(0, H.n(l), max(1, H.n(l) // 50)):
+            nb = sorted(set(H.agg(l)[H.level_scipy(l).indices[H.level_scipy(l).indptr[i]:H.level_scipy(l).indptr[i + 1]]]))
+            assert list(Ps.indices[Ps.indptr[i]:Ps.indptr[i + 1]]) == nb
+        w, wc = H.w(l), H.w(l + 1)
+        assert np.allclose(P @ wc, w - om * (Al @ w) / d, rtol=1e-13, atol=1e-13 * np.abs(w).max())
+        Ac = H.level_scipy(l + 1).toarray()
+        assert np.abs(Ac - P.T @ Al @ P).max() <= 1e-12 * np.abs(Ac).max(), l
+        assert np.array_equal(Ac.view(np.uint64), Ac.T.view(np.uint64))
+
+
+def test_smoothed_vcycle_matches_multiplicative_composition():
+    A = varcoef7(6, seed=31)
+    H = oracle.Hierarchy(A, max_coarse=12, smooth_prolongator=True)
+    assert H.nlevels >= 3
+
+    def dense_B(l):
+        Al = H.level_scipy(l).toarray()
+        if l == H.nlevels - 1:
+            return np.linalg.inv(Al)
+        n = Al.shape[0]
+        P = H.prolongator(l).toarray()
+        S = np.eye(n) - np.diag(H.dinv(l)) @ Al
+        C = np.eye(n) - P @ dense_B(l + 1) @ P.T @ Al
+        return (np.eye(n) - S @ C @ S) @ np.linalg.inv(Al)
+
+    n = H.n(0)
+    Bcols = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    Bf = dense_B(0)
+    assert np.allclose(Bcols, Bf, rtol=1e-10, atol=1e-10 * abs(Bf).max())
+    assert np.allclose(Bcols, Bcols.T, rtol=1e-11, atol=1e-11 * abs(Bcols).max())
+
+
+def test_smoothed_prolongator_solves_and_options():
+    A = q1_stretched(10, 1.05)
+    b = q1_rhs(10, 1.05, 2)
+    its = {}
+    for smooth in (False, True):
+        H = oracle.Hierarchy(A, smooth_prolongator=smooth)
+        x, it, rr, st = H.solve(b, 1e-8)
+        assert st == 0 and np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+        its[smooth] = it
+    assert its[True] <= its[False]
+    with pytest.raises(oracle.OracleError):                 # pairwise levels only
+        oracle.Hierarchy(A, smooth_prolongator=True, agg_steps=2)
+    with pytest.raises(oracle.OracleError):                 # P depends on A: no reuse
+        oracle.Hierarchy(A, smooth_prolongator=True).update(A.val)
+
+
 # --------------------------------------------------------------------------- hybrid Gauss-Seidel smoother
 
 def _nested_order_py(H, l):
