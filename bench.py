@@ -103,6 +103,8 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=0, help="hybrid GS sweeps per side (0: 4)")
     ap.add_argument("--gs-block", type=int, default=0, help="hybrid GS block size (0: 256)")
     ap.add_argument("--omega", type=float, default=0.0, help="hybrid GS damping (0: 1.5)")
+    ap.add_argument("--smooth-prolongator", action="store_true",
+                    help="smoothed prolongators P = (I - w D^-1 A) P^ (moderate sizes: coarse levels fill in)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,6 +142,8 @@ def main() -> int:
     t0 = time.perf_counter()
     smooth_kw = {} if args.smoother == "l1" else dict(smoother="hgs", sweeps=args.sweeps, gs_block=args.gs_block,
                                                       omega=args.omega)
+    if args.smooth_prolongator:
+        smooth_kw["smooth_prolongator"] = 1
     H = pamg.Hierarchy(A, build_f32=1 if prec == pamg.PREC_F32 else 0, agg_steps=args.agg_steps, **smooth_kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
@@ -194,13 +198,16 @@ def main() -> int:
     v_ms, s_ms = H.time_kernels(r_d, reps=20, precision=prec)
     vbytes = info.vcycle_bytes_f32 if prec == pamg.PREC_F32 else info.vcycle_bytes_f64
     # (the algorithmic V-cycle bytes are those of the l1-Jacobi cycle)
-    v_gbs = vbytes / (v_ms * 1e-3) / 1e9 if args.smoother == "l1" else float("nan")
+    v_gbs = vbytes / (v_ms * 1e-3) / 1e9 if args.smoother == "l1" and not args.smooth_prolongator else float("nan")
     s_gbs = info.spmv_bytes / (s_ms * 1e-3) / 1e9
 
     # the kernels that stream the level-0 matrix, each timed live with HIP events
     kern = {}
-    level0_ops = ((("vcycle_down_l0", pamg.OP_DOWN), ("vcycle_up_l0", pamg.OP_UP)) if args.smoother == "l1"
-                  else (("hgs_sweep_l0", pamg.OP_SMOOTH),)) + (("krylov_spmv_l0", pamg.OP_KRYLOV),)
+    if args.smooth_prolongator:
+        level0_ops = (("krylov_spmv_l0", pamg.OP_KRYLOV),)
+    else:
+        level0_ops = ((("vcycle_down_l0", pamg.OP_DOWN), ("vcycle_up_l0", pamg.OP_UP)) if args.smoother == "l1"
+                      else (("hgs_sweep_l0", pamg.OP_SMOOTH),)) + (("krylov_spmv_l0", pamg.OP_KRYLOV),)
     for name, op in level0_ops:
         if op == pamg.OP_KRYLOV and prec == pamg.PREC_F32:
             ms, nb = H.time_op(op, 0, reps=20, precision=pamg.PREC_F64)
@@ -210,7 +217,8 @@ def main() -> int:
     dom = max(kern, key=lambda k: kern[k]["ms"])
     dk = kern[dom]
     copy_gbs, _ = copy_bandwidth(torch)
-    traffic = traffic_for(dom, prec == pamg.PREC_F64 and args.agg_steps == 1 and args.smoother == "l1")
+    traffic = traffic_for(dom, prec == pamg.PREC_F64 and args.agg_steps == 1 and args.smoother == "l1"
+                          and not args.smooth_prolongator)
     log(f"V-cycle {v_ms:.3f} ms ({v_gbs:.0f} GB/s), SpMV {s_ms:.3f} ms ({s_gbs:.0f} GB/s); "
         + ", ".join(f"{k} {v['ms']:.4f} ms {v['GBps']:.0f} GB/s" for k, v in kern.items()))
 
@@ -229,7 +237,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"Q1 hexahedral FE Laplacian, {args.n}^3 elements, vertical stretching {args.ratio}, "
-                        f"divergence RHS seed 2; FCG + AMG V-cycle (pairwise matching aggregation, "
+                        f"divergence RHS seed 2; FCG + AMG V-cycle (pairwise matching aggregation"
+                        + (", smoothed prolongators, " if args.smooth_prolongator else ", ")
                         + ("l1-Jacobi 1+1" if args.smoother == "l1" else
                            f"hybrid forward/backward Gauss-Seidel {H.params.sweeps or 4}+{H.params.sweeps or 4} "
                            f"(blocks of {H.params.gs_block or 256}, omega {H.params.omega or 1.5:g})")
@@ -238,6 +247,7 @@ def main() -> int:
             "operator_complexity": round(info.operator_complexity, 4),
             "aggregate_steps": args.agg_steps,
             "smoother": args.smoother,
+            "smoothed_prolongator": bool(args.smooth_prolongator),
         },
         "iterations": iters[0],
         "relres_true": relres_true,
@@ -473,10 +483,10 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     # right-hand sides, generated up front and kept on the device
     t0 = time.perf_counter()
     rhs = [torch.from_numpy(SplitMix64(50000 + t).uniform(ops[int(picks[t])].n)).to(dev) for t in range(args.requests)]
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
     log(f"{args.requests} right-hand sides in {time.perf_counter() - t0:.1f}s")
     budget = int(args.budget_gib * (1 << 30))
-    S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32)
+    S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32, use_graph=1)
 
     def wait_for(count, what):
         comps = []
@@ -504,7 +514,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     for k in range(args.pool):
         zeros[k] = (torch.zeros(ops[k].n, dtype=torch.float64, device=dev),
                     torch.zeros(ops[k].n, dtype=torch.float64, device=dev))
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
     for k in range(args.pool):
         S.submit(k, ops[k], zeros[k][0], zeros[k][1], tol=1e-6, tag=1 << 40 | k)
     wait_for(args.pool, "warm-up")
@@ -518,7 +528,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     def run(first, count, arrivals):
         """Requests first .. first+count-1 (arrivals: offsets in s, or None = all at once)."""
         xs = [torch.zeros(ops[int(picks[t])].n, dtype=torch.float64, device=dev) for t in range(first, first + count)]
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         res = {}
 
         def poller():

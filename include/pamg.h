@@ -88,7 +88,11 @@ typedef struct {
     double omega;             /* hybrid GS damping of M = omega (L + D), > 0 (0: 1.5; omega = 1, the
                                  plain method, lets the Jacobi coupling between the small blocks
                                  diverge on large 3D meshes) */
-    int32_t reserved[2];
+    int32_t smooth_prolongator; /* 1: P = (I - w D^-1 A) P^ with w = 1/||D^-1 A||_inf, D = diag(A)
+                                 (Sec. 3.1 smoothed aggregation) and A_{l+1} = P^T A P; needs
+                                 agg_steps = 1 and the l1-Jacobi smoother.  Coarse matrices fill in
+                                 quickly with pairwise aggregates (moderate sizes only).  Default 0. */
+    int32_t reserved[1];
 } pamg_params;
 
 typedef struct {
@@ -257,7 +261,12 @@ typedef struct {
     int32_t block_iters;         /* iterations per block between join/retire points (default 4, made even) */
     int32_t precision;           /* V-cycle precision, default PAMG_PREC_F32 (FP64 recurrences; a
                                     column is accepted on its true FP64 residual) */
-    int32_t reserved[8];
+    int32_t use_graph;           /* 1: replay each operator's block as a HIP graph, captured on the
+                                    scheduler thread.  While a capture runs, device-wide calls from
+                                    the application's threads (hipDeviceSynchronize) fail with
+                                    hipErrorStreamCaptureUnsupported, so such programs must
+                                    synchronize streams instead.  Default 0: direct launches. */
+    int32_t reserved[7];
 } pamg_server_opts;
 
 typedef struct {

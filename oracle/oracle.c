@@ -84,7 +84,7 @@
  *      backward sweep runs each block in reverse (M^T).  Pre-smoothing: nu
  *      forward sweeps from zero; post-smoothing: nu backward sweeps, so the
  *      V-cycle stays symmetric.
- *   R15 smoothed prolongator (Sec. 3.1, optional, pairwise levels only):
+ *   R15 smoothed prolongator (Sec. 3.1, optional):
  *      P = (I - omega D^-1 A) P^ with D = diag(A) and
  *      omega = 1 / ||D^-1 A||_inf = 1 / max_i ((sum_j |a_ij|) / a_ii).
  *      Row i: P_iJ = [J = agg(i)] p_i - sum_{j: agg(j) = J} (omega (a_ij / a_ii)) p_j,
@@ -94,7 +94,13 @@
  *      A_{l+1}[I,J] = 0.0 + sum over i ascending of P_iI B_iJ, and
  *      A_{l+1}[J,I] = A_{l+1}[I,J] (bitwise symmetric).  The matching of the
  *      next level runs on this matrix with the tentative coarse w.
- *      Restriction is P^T (sums over ascending i), prolongation P.
+ *      Restriction is P^T (sums over ascending i), prolongation P.  With
+ *      composition (R12, agg_steps = s > 1) the levels are built one kept
+ *      level at a time: from kept level K, up to s pairwise steps (matching,
+ *      aggregates, tentative Galerkin between steps, every stop rule applied
+ *      to every step) give the composed aggregates and p; K's prolongator is
+ *      that composed tentative prolongator smoothed with K, and the next kept
+ *      level is P^T K P.
  */
 #include <math.h>
 #include <stdint.h>
@@ -601,6 +607,90 @@ static int compose_levels(or_hier *h, int s) {
     return OR_OK;
 }
 
+/* R15 with aggregate-size composition (R12): from each kept level K, up to
+ * s pairwise steps -- matching, aggregates and the tentative Galerkin product
+ * between steps, every stop rule applied to every step -- give the composed
+ * aggregates and p of K; K's prolongator is that composed tentative one
+ * smoothed with K, and the next kept level is P^T K P. */
+static int build_smoothed_composed(or_hier *h, int s, int max_coarse, int max_levels, int max_dense,
+                                   double min_ratio, int match_all) {
+    int j = 0, st = OR_OK;
+    for (;;) {
+        or_csr *K = &h->A[j];
+        h->dinv[j] = (double *)malloc(sizeof(double) * (size_t)K->n);
+        if (!h->dinv[j]) return OR_E_OOM;
+        st = l1_inverse(K, h->dinv[j]);
+        if (st) return st;
+        if (K->n <= max_coarse || j + 1 >= max_levels) break;
+        int n = K->n, steps = 0, nc = 0;
+        long first_pairs = 0;
+        int *cagg = (int *)malloc(sizeof(int) * (size_t)n);
+        double *cp = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!cagg || !cp) { free(cagg); free(cp); return OR_E_OOM; }
+        or_csr own;                       /* the chain's current matrix once it is not K */
+        memset(&own, 0, sizeof(own));
+        const or_csr *C = K;
+        double *wc = h->w[j], *w_own = NULL;
+        for (int m = 0; m < s; ++m) {
+            if (m > 0 && C->n <= max_coarse) break;
+            int *mate = (int *)malloc(sizeof(int) * (size_t)C->n);
+            if (!mate) { st = OR_E_OOM; break; }
+            long pairs = greedy_matching(C, wc, match_all, mate);
+            if (pairs < 0) { free(mate); st = OR_E_OOM; break; }
+            if (pairs == 0 || (C->n <= max_dense && (double)C->n < min_ratio * (double)(C->n - pairs))) {
+                free(mate);
+                break;
+            }
+            if (m == 0) first_pairs = pairs;
+            int *agg = (int *)malloc(sizeof(int) * (size_t)C->n);
+            double *p = (double *)malloc(sizeof(double) * (size_t)C->n);
+            double *wn = (double *)malloc(sizeof(double) * (size_t)C->n);
+            if (!agg || !p || !wn) { free(mate); free(agg); free(p); free(wn); st = OR_E_OOM; break; }
+            nc = build_aggregates(C->n, mate, wc, agg, p, wn);
+            free(mate);
+            if (m == 0) {
+                memcpy(cagg, agg, sizeof(int) * (size_t)n);
+                memcpy(cp, p, sizeof(double) * (size_t)n);
+            } else {
+                for (int i = 0; i < n; ++i) {          /* finest first, as R12 */
+                    int I = cagg[i];
+                    cp[i] = cp[i] * p[I];
+                    cagg[i] = agg[I];
+                }
+            }
+            or_csr next;
+            memset(&next, 0, sizeof(next));
+            if (m + 1 < s) st = galerkin(C, agg, p, nc, &next);   /* tentative, for the next step */
+            else next.n = nc;
+            free(agg); free(p);
+            csr_free(&own);
+            own = next;
+            C = &own;
+            free(w_own);
+            w_own = wn;
+            wc = wn;
+            ++steps;
+            if (st) break;
+        }
+        csr_free(&own);
+        if (st || steps == 0) {
+            free(cagg); free(cp); free(w_own);
+            if (st) return st;
+            break;                                    /* K is the coarsest level */
+        }
+        h->n_pairs[j] = (int)first_pairs;
+        h->agg[j] = cagg;
+        h->p[j] = cp;
+        h->w[j + 1] = w_own;
+        st = smoothed_prolongator(K, cagg, cp, &h->P[j], &h->omega_p[j]);
+        if (!st) st = galerkin_smoothed(K, &h->P[j], nc, &h->A[j + 1]);
+        if (st) return st;
+        ++j;
+    }
+    h->nlev = j + 1;
+    return OR_OK;
+}
+
 /* Copy the pairwise aggregates and prolongators (before any composition). */
 static int keep_pairwise_chain(or_hier *h) {
     h->pw_nlev = h->nlev;
@@ -641,7 +731,6 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
     int st = validate(n, rp, ci, v);
     if (st) return st;
     if (max_levels < 1 || max_levels > OR_MAX_LEVELS || agg_steps < 1) return OR_E_INVALID;
-    if (smooth_p && agg_steps != 1) return OR_E_INVALID;      /* R15: pairwise levels only */
     or_hier *h = (or_hier *)calloc(1, sizeof(or_hier));
     if (!h) return OR_E_OOM;
     or_csr *A0 = &h->A[0];
@@ -656,6 +745,18 @@ int oracle_setup(int n, const int *rp, const int *ci, const double *v,
     memcpy(A0->ci, ci, sizeof(int) * (size_t)nnz);
     memcpy(A0->v, v, sizeof(double) * (size_t)nnz);
     for (int i = 0; i < n; ++i) h->w[0][i] = 1.0;         /* R2 */
+
+    if (smooth_p && agg_steps > 1) {                         /* R15 with R12 */
+        st = build_smoothed_composed(h, agg_steps, max_coarse, max_levels, max_dense, min_ratio, match_all);
+        if (st) { oracle_free(h); return st; }
+        h->smoothed = 1;
+        int L = h->nlev - 1;
+        if (h->A[L].n > max_dense) { oracle_free(h); return OR_E_STALLED; }
+        st = dense_cholesky(&h->A[L], &h->chol);
+        if (st) { oracle_free(h); return st; }
+        *out = h;
+        return OR_OK;
+    }
 
     int l = 0;
     for (;;) {

@@ -34,7 +34,8 @@ class pamg_params(C.Structure):
                 ("match_all_edges", C.c_int32), ("build_f32", C.c_int32), ("num_threads", C.c_int32),
                 ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("min_ratio", C.c_double),
                 ("agg_steps", C.c_int32), ("smoother", C.c_int32), ("sweeps", C.c_int32),
-                ("gs_block", C.c_int32), ("omega", C.c_double), ("reserved", C.c_int32 * 2)]
+                ("gs_block", C.c_int32), ("omega", C.c_double), ("smooth_prolongator", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class pamg_solve_opts(C.Structure):
@@ -57,7 +58,7 @@ class pamg_hier_info(C.Structure):
 
 class pamg_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("block_iters", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32 * 8)]
+                ("use_graph", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class pamg_request(C.Structure):
@@ -335,12 +336,14 @@ class Server:
     CSRs and the device vectors of outstanding requests alive until their
     completions are polled."""
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32):
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32,
+                 use_graph: int = 0):
         o = pamg_server_opts()
         _check(lib().pamg_server_opts_default(C.byref(o)), "pamg_server_opts_default")
         o.hbm_budget_bytes = int(hbm_budget_bytes)
         o.block_iters = int(block_iters)
         o.precision = int(precision)
+        o.use_graph = int(use_graph)
         h = C.c_void_p()
         _check(lib().pamg_server_create(C.byref(o), C.byref(h)), "pamg_server_create")
         self._h = h

@@ -15,10 +15,11 @@
 
 namespace pamg {
 
-// The 16-column engine runs the l1-Jacobi V-cycle only.
+// The 16-column engine runs the l1-Jacobi V-cycle with tentative prolongators only.
 static void require_l1_smoother(const pamg_hierarchy* h) {
     if (h->smoother != PAMG_SMOOTHER_L1_JACOBI)
         throw Error(PAMG_E_INVALID, "batched solves support the l1-Jacobi smoother only");
+    if (h->smoothed_p) throw Error(PAMG_E_INVALID, "batched solves support tentative prolongators only");
 }
 
 // kernel variants tried by the autotuner: unroll depth (entries of a row

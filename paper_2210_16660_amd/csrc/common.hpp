@@ -34,6 +34,8 @@ struct HostLevel {
     std::vector<int32_t> agg;   // aggregate of each unknown (levels < L)
     std::vector<double> p;      // prolongator entry of each unknown (levels < L)
     int32_t pairs = 0;
+    HostCSR P;                  // smoothed prolongator n_l x n_{l+1} (smooth_prolongator only)
+    double omega_p = 0.0;
 };
 
 // One level of the pairwise chain that aggregate-size composition condenses:
@@ -87,6 +89,10 @@ struct LayoutLevel {
     // holding one row / aggregate longer than a tile has no dictionary.
     TileDict up_dict, down_dict;
     GsLevel gs;                     // hybrid Gauss-Seidel smoother only (l < L)
+    // smoothed prolongator only (l < L): P (rows of this level, columns of the
+    // next, both hierarchical, columns ascending) and P^T
+    std::vector<int32_t> sa_prp, sa_pci, sa_trp, sa_tci;
+    std::vector<double> sa_pv, sa_tv;
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
@@ -101,6 +107,9 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 void validate_csr(const pamg_csr& A, bool check_symmetry);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
 std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
+
+// Smoothed prolongator of level l in hierarchical numbering (P and P^T).
+void sa_layout(const HostCSR& P, const LayoutLevel& fine, const LayoutLevel& coarse, LayoutLevel& out);
 
 // Hybrid Gauss-Seidel schedule of a laid-out level (blocks of nb <= 256 rows).
 GsLevel gs_schedule(const LayoutLevel& L, int nb);

@@ -12,6 +12,7 @@
 
 #include "hier.hpp"
 #include "kernels_gs.hpp"
+#include "kernels_sa.hpp"
 
 namespace pamg {
 
@@ -47,11 +48,17 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size());
         maxn = std::max(maxn, lay[l].dinv.size());
     }
-    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {
         V.gsa.assign(nl, nullptr);
         V.zt.assign(nl, nullptr);
+        V.sa_pv.assign(nl, nullptr);
+        V.sa_tv.assign(nl, nullptr);
         for (int l = 0; l + 1 < nl; ++l) {
-            V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
+            if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
+            if (h->smoothed_p) {
+                V.sa_pv[l] = upload<T>(h, lay[l].sa_pv, s);
+                V.sa_tv[l] = upload<T>(h, lay[l].sa_tv, s);
+            }
             V.zt[l] = dalloc<T>(h, lay[l].dinv.size());
         }
         V.zc = dalloc<T>(h, lay[nl - 1].dinv.size());
@@ -127,6 +134,13 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
             I.down_loc = upload<uint16_t>(h, Ly.down_dict.local, s);
             I.down_dmax = std::max(1, (int)Ly.down_dict.max_len);
             I.down_dlen = (long long)Ly.down_dict.col.size();
+            if (h->smoothed_p) {
+                I.sa_prp = upload<int>(h, Ly.sa_prp, s);
+                I.sa_pci = upload<int>(h, Ly.sa_pci, s);
+                I.sa_trp = upload<int>(h, Ly.sa_trp, s);
+                I.sa_tci = upload<int>(h, Ly.sa_tci, s);
+                I.sa_nnz = (long long)Ly.sa_pci.size();
+            }
             if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
                 I.gs_df = upload<uint8_t>(h, Ly.gs.depth_f, s);
                 I.gs_db = upload<uint8_t>(h, Ly.gs.depth_b, s);
@@ -365,6 +379,49 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     return g;
 }
 
+// V-cycle with smoothed prolongators (L >= 1): per level the residual of the
+// l1-Jacobi pre-smoothing from zero and its restriction P^T t; after the
+// coarse solve the prolongation D^-1 r + P e and the post-smoothing.
+template <typename T>
+static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
+                             const int* done, hipStream_t s) {
+    const int L = h->L;
+    for (int l = 0; l < L; ++l) {
+        const DevLevelIdx& I = h->idx[l];
+        const int nc = h->idx[l + 1].n;
+        if (l == 0)
+            LAUNCH((k_sa_resid<T, double>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
+                   (const T*)V.vd[0], r0, V.zt[0], done);
+        else
+            LAUNCH((k_sa_resid<T, T>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
+                   (const T*)V.vd[l], (const T*)V.r[l], V.zt[l], done);
+        LAUNCH((k_sa_restrict<T>), vec_grid(nc), 0, s, nc, I.sa_trp, I.sa_tci, (const T*)V.sa_tv[l],
+               (const T*)V.zt[l], V.r[l + 1], done);
+    }
+    const int nL = h->idx[L].n;
+    LAUNCH((k_gs_coarse<T, T>), vec_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
+    const T* e = V.zc;
+    for (int l = L - 1; l >= 0; --l) {
+        const DevLevelIdx& I = h->idx[l];
+        // z_l goes to zt[l] (the residual there is no longer needed)
+        if (l == 0) {
+            LAUNCH((k_sa_prolong<T, double>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[0], e,
+                   r0, (const T*)V.dinv[0], V.zp[0], done);
+            LAUNCH((k_sa_post<T, double>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
+                   (const T*)V.v[0], r0, (const T*)V.dinv[0], (const T*)V.zp[0], V.zt[0], done);
+        } else {
+            LAUNCH((k_sa_prolong<T, T>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l], e,
+                   (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
+            LAUNCH((k_sa_post<T, T>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
+                   (const T*)V.v[l], (const T*)V.r[l], (const T*)V.dinv[l], (const T*)V.zp[l], V.zt[l], done);
+        }
+        e = V.zt[l];
+    }
+    const int n0 = h->idx[0].n, g = vec_grid(n0);
+    LAUNCH((k_gs_out<T>), g, 0, s, n0, (const T*)V.zt[0], z_out, dv, h->partial, done);
+    return g;
+}
+
 // z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
 // up-sweep also writes the partials of z . dv.  Returns the number of partials.
 template <typename T>
@@ -372,6 +429,7 @@ static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, do
                           const int* done, hipStream_t s) {
     const int L = h->L;
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS && L > 0) return enqueue_vcycle_gs<T>(h, V, r0, z_out, dv, done, s);
+    if (h->smoothed_p && L > 0) return enqueue_vcycle_sa<T>(h, V, r0, z_out, dv, done, s);
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         if (l == 0)
@@ -849,6 +907,9 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
     } else {
         throw Error(PAMG_E_INVALID, "unknown smoother");
     }
+    if (prm.smooth_prolongator != 0 &&
+        (prm.smooth_prolongator != 1 || prm.agg_steps != 1 || prm.smoother != PAMG_SMOOTHER_L1_JACOBI))
+        throw Error(PAMG_E_INVALID, "smooth_prolongator = 1 needs agg_steps = 1 and the l1-Jacobi smoother");
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<HostBuild> b(new HostBuild());
@@ -860,6 +921,8 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
         const int nb = prm.gs_block > 0 ? prm.gs_block : 256;
         for (size_t l = 0; l + 1 < b->lay.size(); ++l) b->lay[l].gs = gs_schedule(b->lay[l], nb);
     }
+    if (prm.smooth_prolongator)
+        for (size_t l = 0; l + 1 < b->lay.size(); ++l) sa_layout(b->H.lev[l].P, b->lay[l], b->lay[l + 1], b->lay[l]);
     b->host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return b;
 }
@@ -870,6 +933,7 @@ pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream) {
     auto t0 = std::chrono::steady_clock::now();
     pamg_hierarchy* h = new_hierarchy(b->prm.host_only != 0);
     h->smoother = b->prm.smoother;
+    h->smoothed_p = b->prm.smooth_prolongator != 0;
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
         h->sweeps = b->prm.sweeps > 0 ? b->prm.sweeps : 4;
         h->gs_block = b->prm.gs_block > 0 ? b->prm.gs_block : 256;

@@ -26,6 +26,7 @@ struct DevVals {
     std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
     std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
     std::vector<T*> gsa, zt;          // hybrid GS: 1 / a_ii and a second iterate buffer (l < L)
+    std::vector<T*> sa_pv, sa_tv;     // smoothed prolongator: values of P and P^T (l < L)
     T* zc = nullptr;                  // hybrid GS: coarsest-level solution
     T* ainv = nullptr;                // dense A_L^{-1}
     T* dbg_in = nullptr;              // scratch in this precision (max n)
@@ -56,6 +57,9 @@ struct DevLevelIdx {
     const uint8_t *gs_df = nullptr, *gs_db = nullptr;
     const int* gs_maxd = nullptr;
     int gs_nblk = 0;
+    // smoothed prolongator (l < L): P and P^T patterns, hierarchical numbering
+    const int *sa_prp = nullptr, *sa_pci = nullptr, *sa_trp = nullptr, *sa_tci = nullptr;
+    long long sa_nnz = 0;
 };
 
 // Coefficient-only reuse: built on the first value update and kept.  Its
@@ -84,6 +88,7 @@ struct pamg_hierarchy {
     int smoother = PAMG_SMOOTHER_L1_JACOBI;   // hybrid GS: sweeps per side, block size, damping
     int sweeps = 1, gs_block = 256;
     double omega = 1.0;
+    bool smoothed_p = false;                  // smoothed prolongators (general sparse P)
     std::vector<pamg::DevLevelIdx> idx;
     pamg::DevVals<double> f64;
     pamg::DevVals<float> f32;

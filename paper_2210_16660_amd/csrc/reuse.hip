@@ -230,6 +230,8 @@ extern "C" int pamg_hierarchy_update_values(pamg_hierarchy* h, const double* val
     return pamg::guarded([&]() -> int {
         if (!h || !val) throw pamg::Error(PAMG_E_INVALID, "null argument");
         pamg::require_device(h);
+        if (h->smoothed_p)
+            throw pamg::Error(PAMG_E_INVALID, "smoothed prolongators depend on the values: set up again");
         std::lock_guard<std::mutex> lk(h->mu);
         HIP_CHECK(hipSetDevice(h->device));
         pamg::update_values(h, val, on_device != 0, (hipStream_t)stream);

@@ -438,7 +438,7 @@ static void scheduler_tick(pamg_server* S) {
         ServeGroup* g = kv.second;
         if (g->in_flight || g->active == 0 || batch_state_host(g->E).all_done) continue;
         for (int c = 0; c < kW; ++c) g->iter_before[c] = batch_state_host(g->E).col[c].iter;
-        batch_run_block(g->E, PAMG_KRYLOV_FCG, k, true, g->stream);
+        batch_run_block(g->E, PAMG_KRYLOV_FCG, k, S->opts.use_graph != 0, g->stream);
         batch_read_state_async(g->E, g->stream);
         HIP_CHECK(hipEventRecord(g->ev, g->stream));
         g->in_flight = true;

@@ -275,6 +275,168 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
     });
 }
 
+// ------------------------------------------------ smoothed prolongator
+
+// P = (I - omega D^-1 A) P^ (Sec. 3.1), D = diag(A), omega = 1/||D^-1 A||_inf.
+// Row i: P_iJ = [J = agg(i)] p_i - sum_{j: agg(j) = J} (omega (a_ij / a_ii)) p_j,
+// subtracted in ascending j; pattern {agg(j) : a_ij stored}, ascending.
+static void smoothed_prolongator(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,
+                                 HostCSR& P, double& omega) {
+    const int32_t n = A.n;
+    std::vector<double> ratio(n);
+    parallel_for(n, [&](int64_t i) {
+        double s = 0.0, aii = 0.0;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            s += std::fabs(A.v[k]);
+            if (A.ci[k] == i) aii = A.v[k];
+        }
+        ratio[i] = s / aii;
+    });
+    double mx = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        if (ratio[i] > mx) mx = ratio[i];
+    omega = 1.0 / mx;
+    const double om = omega;
+    std::vector<std::vector<int32_t>> cols(n);
+    std::vector<std::vector<double>> vals(n);
+    parallel_for(n, [&](int64_t i) {
+        std::vector<int32_t>& c = cols[i];
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) c.push_back(agg[A.ci[k]]);
+        std::sort(c.begin(), c.end());
+        c.erase(std::unique(c.begin(), c.end()), c.end());
+        std::vector<double>& v = vals[i];
+        v.assign(c.size(), 0.0);
+        double aii = 0.0;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] == i) aii = A.v[k];
+        for (size_t u = 0; u < c.size(); ++u) v[u] = c[u] == agg[i] ? p[i] : 0.0;
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t j = A.ci[k];
+            const size_t u = std::lower_bound(c.begin(), c.end(), agg[j]) - c.begin();
+            v[u] = v[u] - (om * (A.v[k] / aii)) * p[j];
+        }
+    });
+    P.n = n;
+    P.rp.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + (int32_t)cols[i].size();
+    P.ci.resize(P.rp[n]);
+    P.v.resize(P.rp[n]);
+    parallel_for(n, [&](int64_t i) {
+        std::copy(cols[i].begin(), cols[i].end(), P.ci.begin() + P.rp[i]);
+        std::copy(vals[i].begin(), vals[i].end(), P.v.begin() + P.rp[i]);
+    });
+}
+
+// Rows of a sparse product accumulated in a fixed order: out row r =
+// sum over the listed (coefficient, source row) pairs, in list order, of
+// coefficient * source row; keep(J) filters the columns; 0.0 starts each sum.
+// Rows are built by `emit(r, visit)` where visit(coef, row_ptr, row_col, row_val).
+template <class Emit>
+static void accumulate_rows(int32_t nrows, int32_t ncols, Emit emit, HostCSR& out) {
+    std::vector<std::vector<int32_t>> cols(nrows);
+    std::vector<std::vector<double>> vals(nrows);
+    parallel_ranges(nrows, [&](int, int64_t b, int64_t e) {
+        std::vector<double> acc(ncols, 0.0);
+        std::vector<int32_t> mark(ncols, -1), list;
+        for (int64_t r = b; r < e; ++r) {
+            list.clear();
+            emit((int32_t)r, [&](int32_t J, double term) {
+                if (mark[J] != r) {
+                    mark[J] = (int32_t)r;
+                    acc[J] = 0.0;
+                    list.push_back(J);
+                }
+                acc[J] = acc[J] + term;
+            });
+            std::sort(list.begin(), list.end());
+            cols[r] = list;
+            vals[r].resize(list.size());
+            for (size_t u = 0; u < list.size(); ++u) vals[r][u] = acc[list[u]];
+        }
+    });
+    out.n = nrows;
+    out.rp.assign(nrows + 1, 0);
+    for (int32_t r = 0; r < nrows; ++r) {
+        const int64_t nx = (int64_t)out.rp[r] + (int64_t)cols[r].size();
+        if (nx >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "smoothed Galerkin product exceeds 2^31 entries");
+        out.rp[r + 1] = (int32_t)nx;
+    }
+    out.ci.resize(out.rp[nrows]);
+    out.v.resize(out.rp[nrows]);
+    parallel_for(nrows, [&](int64_t r) {
+        std::copy(cols[r].begin(), cols[r].end(), out.ci.begin() + out.rp[r]);
+        std::copy(vals[r].begin(), vals[r].end(), out.v.begin() + out.rp[r]);
+    });
+}
+
+// A_c = P^T A P: B = A P (B_kJ = 0.0 + sum over j ascending of a_kj P_jJ), then
+// for I <= J: A_c[I,J] = 0.0 + sum over i ascending of P_iI B_iJ; mirrored.
+static void galerkin_smoothed(const HostCSR& A, const HostCSR& P, int32_t nc, HostCSR& Ac) {
+    const int32_t n = A.n;
+    HostCSR B;
+    accumulate_rows(n, nc, [&](int32_t k, auto&& add) {
+        for (int32_t e = A.rp[k]; e < A.rp[k + 1]; ++e) {
+            const int32_t j = A.ci[e];
+            for (int32_t u = P.rp[j]; u < P.rp[j + 1]; ++u) add(P.ci[u], A.v[e] * P.v[u]);
+        }
+    }, B);
+    // P^T: rows I, entries (i, P_iI) with i ascending
+    std::vector<int32_t> tp(nc + 1, 0), ti(P.rp[n]);
+    std::vector<double> tv(P.rp[n]);
+    for (int32_t u = 0; u < P.rp[n]; ++u) ++tp[P.ci[u] + 1];
+    for (int32_t I = 0; I < nc; ++I) tp[I + 1] += tp[I];
+    {
+        std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t u = P.rp[i]; u < P.rp[i + 1]; ++u) {
+                const int32_t I = P.ci[u];
+                ti[fill[I]] = i;
+                tv[fill[I]] = P.v[u];
+                ++fill[I];
+            }
+    }
+    HostCSR U;
+    accumulate_rows(nc, nc, [&](int32_t I, auto&& add) {
+        for (int32_t x = tp[I]; x < tp[I + 1]; ++x) {
+            const int32_t i = ti[x];
+            for (int32_t u = B.rp[i]; u < B.rp[i + 1]; ++u)
+                if (B.ci[u] >= I) add(B.ci[u], tv[x] * B.v[u]);
+        }
+    }, U);
+    // full rows: mirrored entries (ascending source row), then the upper row
+    std::vector<int32_t> cnt(nc + 1, 0);
+    for (int32_t I = 0; I < nc; ++I)
+        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
+            ++cnt[I + 1];
+            if (U.ci[u] != I) ++cnt[U.ci[u] + 1];
+        }
+    for (int32_t I = 0; I < nc; ++I) {
+        const int64_t nx = (int64_t)cnt[I + 1] + cnt[I];
+        if (nx >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "coarse matrix exceeds 2^31 entries");
+        cnt[I + 1] = (int32_t)nx;
+    }
+    Ac.n = nc;
+    Ac.rp = cnt;
+    Ac.ci.resize(cnt[nc]);
+    Ac.v.resize(cnt[nc]);
+    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int32_t I = 0; I < nc; ++I)
+        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
+            const int32_t J = U.ci[u];
+            if (J != I) {
+                Ac.ci[pos[J]] = I;
+                Ac.v[pos[J]] = U.v[u];
+                ++pos[J];
+            }
+        }
+    for (int32_t I = 0; I < nc; ++I)
+        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
+            Ac.ci[pos[I]] = U.ci[u];
+            Ac.v[pos[I]] = U.v[u];
+            ++pos[I];
+        }
+}
+
 // ------------------------------------------ aggregate-size composition
 
 // Keep levels 0, s, 2s, ... and the coarsest of the pairwise hierarchy; the
@@ -390,7 +552,12 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
         }
         mem_ptr[nc] = q;
         HostLevel next;
-        galerkin(A, cur.agg, cur.p, mem_ptr, mem, next.A);
+        if (prm.smooth_prolongator) {
+            smoothed_prolongator(A, cur.agg, cur.p, cur.P, cur.omega_p);
+            galerkin_smoothed(A, cur.P, nc, next.A);
+        } else {
+            galerkin(A, cur.agg, cur.p, mem_ptr, mem, next.A);
+        }
         next.w = std::move(wc);
         H.lev.push_back(std::move(next));
     }
@@ -400,6 +567,47 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
                                         " unknowns, above the dense-solve limit");
     if (prm.agg_steps > 1) compose_levels(H, prm.agg_steps);
     return H;
+}
+
+// ------------------------------------------- smoothed prolongator layout
+
+void sa_layout(const HostCSR& P, const LayoutLevel& fine, const LayoutLevel& coarse, LayoutLevel& out) {
+    const int32_t n = P.n, nc = (int32_t)coarse.perm.size();
+    out.sa_prp.assign(n + 1, 0);
+    for (int32_t ip = 0; ip < n; ++ip) {
+        const int32_t i = fine.iperm[ip];
+        out.sa_prp[ip + 1] = out.sa_prp[ip] + (P.rp[i + 1] - P.rp[i]);
+    }
+    out.sa_pci.resize(out.sa_prp[n]);
+    out.sa_pv.resize(out.sa_prp[n]);
+    parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t ip = b; ip < e; ++ip) {
+            const int32_t i = fine.iperm[ip];
+            row.clear();
+            for (int32_t u = P.rp[i]; u < P.rp[i + 1]; ++u) row.emplace_back(coarse.perm[P.ci[u]], P.v[u]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) { return x.first < y.first; });
+            for (size_t u = 0; u < row.size(); ++u) {
+                out.sa_pci[out.sa_prp[ip] + u] = row[u].first;
+                out.sa_pv[out.sa_prp[ip] + u] = row[u].second;
+            }
+        }
+    });
+    // P^T: rows = coarse (hierarchical), entries = fine rows ascending
+    out.sa_trp.assign(nc + 1, 0);
+    for (int32_t u = 0; u < out.sa_prp[n]; ++u) ++out.sa_trp[out.sa_pci[u] + 1];
+    for (int32_t I = 0; I < nc; ++I) out.sa_trp[I + 1] += out.sa_trp[I];
+    out.sa_tci.resize(out.sa_prp[n]);
+    out.sa_tv.resize(out.sa_prp[n]);
+    std::vector<int32_t> fill(out.sa_trp.begin(), out.sa_trp.end() - 1);
+    for (int32_t ip = 0; ip < n; ++ip)
+        for (int32_t u = out.sa_prp[ip]; u < out.sa_prp[ip + 1]; ++u) {
+            const int32_t I = out.sa_pci[u];
+            out.sa_tci[fill[I]] = ip;
+            out.sa_tv[fill[I]] = out.sa_pv[u];
+            ++fill[I];
+        }
 }
 
 // ------------------------------------------- hybrid Gauss-Seidel schedule

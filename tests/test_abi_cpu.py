@@ -113,7 +113,9 @@ def test_bad_params_rejected():
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, agg_steps=5)
     # smoother parameters
-    for kw in [dict(smoother=2), dict(sweeps=2), dict(smoother="hgs", sweeps=17),
+    for kw in [dict(smooth_prolongator=1, agg_steps=2), dict(smooth_prolongator=1, smoother="hgs"),
+               dict(smooth_prolongator=2),
+               dict(smoother=2), dict(sweeps=2), dict(smoother="hgs", sweeps=17),
                dict(smoother="hgs", gs_block=257), dict(smoother="hgs", omega=-1.0),
                dict(smoother="hgs", omega=float("inf")), dict(smoother="hgs", gs_block=-1)]:
         with pytest.raises(pamg.PamgError) as e:
@@ -149,6 +151,8 @@ CASES = {
     "varcoef_36_stalled": (lambda: varcoef7(36, seed=5000), {}),
     "q1_16_composed3": (lambda: q1_stretched(16, 1.05), {"agg_steps": 3}),
     "varcoef_20_composed2": (lambda: varcoef7(20, seed=5), {"agg_steps": 2}),
+    "varcoef_18_smoothed": (lambda: varcoef7(18, seed=6), {"smooth_prolongator": True}),
+    "q1_12_smoothed": (lambda: q1_stretched(12, 1.05), {"smooth_prolongator": True}),
 }
 
 
@@ -156,10 +160,12 @@ CASES = {
 def test_setup_bitexact_with_oracle(case):
     make, kw = CASES[case]
     A = make()
+    sm = bool(kw.get("smooth_prolongator", False))
     O = oracle.Hierarchy(A, max_coarse=kw.get("max_coarse", 200), match_all=kw.get("match_all", False),
-                         agg_steps=kw.get("agg_steps", 1))
+                         agg_steps=kw.get("agg_steps", 1), smooth_prolongator=sm)
     H = pamg.Hierarchy(A, host_only=1, max_coarse=kw.get("max_coarse", 200),
-                       match_all_edges=int(kw.get("match_all", False)), agg_steps=kw.get("agg_steps", 1))
+                       match_all_edges=int(kw.get("match_all", False)), agg_steps=kw.get("agg_steps", 1),
+                       smooth_prolongator=int(sm))
     assert H.levels == O.nlevels
     for l in range(H.levels - 1):
         assert np.array_equal(H.aggregates(l), O.agg(l)), f"level {l} aggregates differ"

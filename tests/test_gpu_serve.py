@@ -8,6 +8,7 @@
 * a tiny HBM budget forces queueing and LRU eviction, and every request
   still completes correctly; an operator larger than the budget is refused;
 * a zero right-hand side completes with x = 0;
+* graph-replayed blocks give bitwise the results of direct launches;
 * the host phase of a new operator's setup runs beside the solving of
   cached operators (their requests finish first).
 """
@@ -61,11 +62,11 @@ def make_requests(ops, count, seed=7):
 def serve(ops, reqs, **kw):
     S = pamg.Server(**kw)
     xs = {}
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
     for tag, k, b in reqs:
         x = torch.zeros(ops[k].n, dtype=torch.float64, device="cuda:0")
         bd = dev(b)
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         xs[tag] = x
         S.submit(k, ops[k], bd, x, tol=1e-6, tag=tag)
     done = wait_all(S, len(reqs))
@@ -97,6 +98,18 @@ def test_served_results_correct_and_independent_of_the_mix(ops):
         inf = H.solve_batch(dev(b[None, :]), X, tol=1e-6, precision=pamg.PREC_F32)
         assert inf[0].iterations == done[tag].iterations
         assert np.array_equal(X[0].cpu().numpy().view(np.uint64), xs[tag].view(np.uint64))
+
+
+def test_graph_replay_server_matches_direct_launches(ops):
+    # blocks replayed as HIP graphs give bitwise the results of direct launches
+    # (the application synchronizes its own stream while the server captures)
+    reqs = make_requests(ops, 16, seed=5)
+    xd, dd, _ = serve(ops, reqs)
+    xg, dg, st = serve(ops, reqs, use_graph=1)
+    assert st.completed == 16
+    for tag, k, b in reqs:
+        assert dg[tag].status == pamg.OK and dg[tag].iterations == dd[tag].iterations
+        assert np.array_equal(xg[tag].view(np.uint64), xd[tag].view(np.uint64))
 
 
 def test_fp64_vcycle_server(ops):
@@ -152,7 +165,7 @@ def test_setup_runs_beside_solves(ops):
     bb = dev(SplitMix64(78).uniform(big.n))
     xs = [torch.zeros(ops[0].n, dtype=torch.float64, device="cuda:0") for _ in range(8)]
     bs = [dev(SplitMix64(2000 + t).uniform(ops[0].n)) for t in range(8)]
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
     S.submit(99, big, bb, xb, tag=99)
     for t in range(8):
         S.submit(0, None, bs[t], xs[t], tag=t)

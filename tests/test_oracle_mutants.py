@@ -65,6 +65,9 @@ MUTANTS = {
                                    "rc[h->agg[l][i]] += h->p[l][i] * t[i];"),
     "sa_galerkin_drops_lower_mirror": ("if (J != I) { out->ci[mark[J]] = I; out->v[mark[J]] = U.v[u]; mark[J]++; }",
                                        "if (J != I) { out->ci[mark[J]] = I; out->v[mark[J]] = 0.0; mark[J]++; }"),
+    "sa_composed_p_not_multiplied": ("                    cp[i] = cp[i] * p[I];", "                    cp[i] = p[I];"),
+    "sa_composed_smooths_wrong_matrix": ("st = smoothed_prolongator(K, cagg, cp, &h->P[j], &h->omega_p[j]);",
+                                         "st = smoothed_prolongator(&h->A[0], cagg, cp, &h->P[j], &h->omega_p[j]);"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
 }

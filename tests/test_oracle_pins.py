@@ -535,15 +535,25 @@ def test_composed_hierarchy_solves():
 
 # --------------------------------------------------------------------------- smoothed prolongator
 
-@pytest.mark.parametrize("case", ["varcoef_9", "q1_8", "lap7_10"])
+@pytest.mark.parametrize("case", ["varcoef_9", "q1_8", "lap7_10", "q1_12_composed3", "varcoef_12_composed2"])
 def test_smoothed_prolongator_definition(case):
     # Sec. 3.1: P = (I - omega D^-1 A) P^, D = diag(A), omega = 1/||D^-1 A||_inf,
     # against dense numpy on every level; the coarse matrix is P^T A P and is
     # stored bitwise symmetric; P keeps w in range: P w_c = w - omega D^-1 A w
     A = {"varcoef_9": lambda: varcoef7(9, seed=30), "q1_8": lambda: q1_stretched(8, 1.05),
-         "lap7_10": lambda: lap7(10)}[case]()
-    H = oracle.Hierarchy(A, smooth_prolongator=True)
+         "lap7_10": lambda: lap7(10), "q1_12_composed3": lambda: q1_stretched(12, 1.05),
+         "varcoef_12_composed2": lambda: varcoef7(12, seed=32)}[case]()
+    steps = 3 if case.endswith("composed3") else (2 if case.endswith("composed2") else 1)
+    H = oracle.Hierarchy(A, smooth_prolongator=True, agg_steps=steps, max_coarse=40)
     assert H.nlevels >= 3
+    if steps > 1:
+        # the first kept level's composed aggregates come from the pairwise
+        # chain of A_0, exactly as without smoothing
+        T = oracle.Hierarchy(A, agg_steps=steps, max_coarse=40)
+        assert np.array_equal(H.agg(0), T.agg(0)) and np.array_equal(H.p(0).view(np.uint64), T.p(0).view(np.uint64))
+        for l in range(H.nlevels - 1):
+            sizes = np.bincount(H.agg(l), minlength=H.n(l + 1))
+            assert sizes.min() >= 1 and sizes.max() <= 2 ** steps
     for l in range(H.nlevels - 1):
         Al = H.level_scipy(l).toarray()
         d = np.diag(Al)
@@ -597,8 +607,11 @@ def test_smoothed_prolongator_solves_and_options():
         assert st == 0 and np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
         its[smooth] = it
     assert its[True] <= its[False]
-    with pytest.raises(oracle.OracleError):                 # pairwise levels only
-        oracle.Hierarchy(A, smooth_prolongator=True, agg_steps=2)
+    # with aggregates of up to 8 (the paper's configuration) smoothing still
+    # pays, at a fraction of the pairwise fill-in
+    S3, T3 = oracle.Hierarchy(A, smooth_prolongator=True, agg_steps=3), oracle.Hierarchy(A, agg_steps=3)
+    assert S3.solve(b, 1e-8)[1] < T3.solve(b, 1e-8)[1]
+    assert sum(S3.nnz(l) for l in range(S3.nlevels)) < 3 * A.nnz
     with pytest.raises(oracle.OracleError):                 # P depends on A: no reuse
         oracle.Hierarchy(A, smooth_prolongator=True).update(A.val)
 
