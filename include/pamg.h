@@ -89,9 +89,11 @@ typedef struct {
                                  plain method, lets the Jacobi coupling between the small blocks
                                  diverge on large 3D meshes) */
     int32_t smooth_prolongator; /* 1: P = (I - w D^-1 A) P^ with w = 1/||D^-1 A||_inf, D = diag(A)
-                                 (Sec. 3.1 smoothed aggregation) and A_{l+1} = P^T A P; needs
-                                 agg_steps = 1 and the l1-Jacobi smoother.  Coarse matrices fill in
-                                 quickly with pairwise aggregates (moderate sizes only).  Default 0. */
+                                 (Sec. 3.1 smoothed aggregation) and A_{l+1} = P^T A P, l1-Jacobi
+                                 smoother only.  With agg_steps = s > 1 each kept level's composed
+                                 tentative prolongator is smoothed (the paper's configuration);
+                                 with pairwise aggregates the coarse matrices fill in quickly.
+                                 Default 0. */
     int32_t reserved[1];
 } pamg_params;
 

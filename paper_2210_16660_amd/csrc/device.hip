@@ -907,9 +907,8 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
     } else {
         throw Error(PAMG_E_INVALID, "unknown smoother");
     }
-    if (prm.smooth_prolongator != 0 &&
-        (prm.smooth_prolongator != 1 || prm.agg_steps != 1 || prm.smoother != PAMG_SMOOTHER_L1_JACOBI))
-        throw Error(PAMG_E_INVALID, "smooth_prolongator = 1 needs agg_steps = 1 and the l1-Jacobi smoother");
+    if (prm.smooth_prolongator != 0 && (prm.smooth_prolongator != 1 || prm.smoother != PAMG_SMOOTHER_L1_JACOBI))
+        throw Error(PAMG_E_INVALID, "smooth_prolongator = 1 needs the l1-Jacobi smoother");
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<HostBuild> b(new HostBuild());

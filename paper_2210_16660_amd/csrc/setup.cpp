@@ -487,6 +487,134 @@ static void compose_levels(HostHierarchy& H, int s) {
     H.lev = std::move(out);
 }
 
+// ------------------------------- smoothed prolongators with composition
+
+// One pairwise step on A with near-null vector w: matching, stop rules and
+// aggregates, as in the pairwise loop of build_hierarchy.  False when A is
+// the coarsest level.
+struct PairStepOut {
+    std::vector<int32_t> agg, mem_ptr, mem;
+    std::vector<double> p, wc;
+    int32_t nc = 0;
+    int64_t pairs = 0;
+};
+
+static bool pairwise_step(const HostCSR& A, const std::vector<double>& w, const pamg_params& prm, PairStepOut& o) {
+    const int32_t n = A.n;
+    std::vector<double> diag(n, 0.0);
+    parallel_for(n, [&](int64_t i) {
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] == i) diag[i] = A.v[k];
+    });
+    Adj g = eligible_adjacency(A, diag, w, prm.match_all_edges != 0);
+    std::vector<int32_t> mate(n, -1);
+    const int64_t pairs = suitor_matching(g, n, mate);
+    if (pairs == 0) return false;
+    if (n <= prm.max_dense && (double)n < prm.min_ratio * (double)(n - pairs)) return false;
+    o.pairs = pairs;
+    o.agg.assign(n, -1);
+    o.p.assign(n, 0.0);
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (mate[i] < 0 || mate[i] > i) ++nc;
+    o.nc = nc;
+    o.wc.resize(nc);
+    o.mem_ptr.resize(nc + 1);
+    o.mem.resize(n);
+    int32_t I = 0, q = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t m = mate[i];
+        if (m >= 0 && m < i) continue;
+        o.mem_ptr[I] = q;
+        if (m < 0) {
+            o.agg[i] = I;
+            o.p[i] = w[i] / std::fabs(w[i]);
+            o.wc[I] = std::fabs(w[i]);
+            o.mem[q++] = i;
+        } else {
+            const double nu = std::sqrt(w[i] * w[i] + w[m] * w[m]);
+            o.agg[i] = I;
+            o.agg[m] = I;
+            o.p[i] = w[i] / nu;
+            o.p[m] = w[m] / nu;
+            o.wc[I] = nu;
+            o.mem[q++] = i;
+            o.mem[q++] = m;
+        }
+        ++I;
+    }
+    o.mem_ptr[nc] = q;
+    return true;
+}
+
+// Kept levels one at a time: from kept level K, up to s pairwise steps
+// (tentative Galerkin products between them) give K's composed aggregates and
+// p (finest first); K's prolongator is the composed tentative one smoothed
+// with K, and the next kept level is P^T K P.
+static void build_smoothed_composed(HostHierarchy& H, const pamg_params& prm) {
+    const int s = prm.agg_steps;
+    for (int j = 0;; ++j) {
+        {
+            HostLevel& K = H.lev[j];
+            const HostCSR& A = K.A;
+            K.dinv.resize(A.n);
+            parallel_for(A.n, [&](int64_t i) {
+                double d = 0.0;
+                for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) d += std::fabs(A.v[k]);
+                K.dinv[i] = 1.0 / d;
+            });
+            if (A.n <= prm.max_coarse || j + 1 >= prm.max_levels) break;
+        }
+        const HostCSR& KA = H.lev[j].A;
+        const int32_t n = KA.n;
+        std::vector<int32_t> cagg;
+        std::vector<double> cp, wcur = H.lev[j].w;
+        const HostCSR* C = &KA;
+        HostCSR own;
+        int steps = 0;
+        int32_t nc = 0;
+        int64_t first_pairs = 0;
+        for (int m = 0; m < s; ++m) {
+            if (m > 0 && C->n <= prm.max_coarse) break;
+            PairStepOut o;
+            if (!pairwise_step(*C, wcur, prm, o)) break;
+            if (m == 0) {
+                first_pairs = o.pairs;
+                cagg = o.agg;
+                cp = o.p;
+            } else {
+                parallel_for(n, [&](int64_t i) {
+                    const int32_t I = cagg[i];
+                    cp[i] = cp[i] * o.p[I];
+                    cagg[i] = o.agg[I];
+                });
+            }
+            nc = o.nc;
+            HostCSR next;
+            if (m + 1 < s)
+                galerkin(*C, o.agg, o.p, o.mem_ptr, o.mem, next);
+            else
+                next.n = nc;
+            own = std::move(next);
+            C = &own;
+            wcur = std::move(o.wc);
+            ++steps;
+        }
+        if (steps == 0) break;
+        HostLevel next;
+        {
+            HostLevel& K = H.lev[j];
+            K.pairs = (int32_t)first_pairs;
+            K.agg = std::move(cagg);
+            K.p = std::move(cp);
+            smoothed_prolongator(K.A, K.agg, K.p, K.P, K.omega_p);
+            galerkin_smoothed(K.A, K.P, nc, next.A);
+        }
+        next.w = std::move(wcur);
+        H.lev.push_back(std::move(next));
+    }
+}
+
 // ---------------------------------------------------------------- driver
 
 HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
@@ -499,6 +627,13 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
         L0.A.ci.assign(Ain.col_idx, Ain.col_idx + Ain.nnz);
         L0.A.v.assign(Ain.val, Ain.val + Ain.nnz);
         L0.w.assign(Ain.n, 1.0);
+    }
+    if (prm.smooth_prolongator && prm.agg_steps > 1) {
+        build_smoothed_composed(H, prm);
+        if (H.lev.back().A.n > prm.max_dense)
+            throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(H.lev.back().A.n) +
+                                            " unknowns, above the dense-solve limit");
+        return H;
     }
     for (int l = 0;; ++l) {
         HostLevel& cur = H.lev[l];

@@ -113,7 +113,7 @@ def test_bad_params_rejected():
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, agg_steps=5)
     # smoother parameters
-    for kw in [dict(smooth_prolongator=1, agg_steps=2), dict(smooth_prolongator=1, smoother="hgs"),
+    for kw in [dict(smooth_prolongator=1, smoother="hgs"),
                dict(smooth_prolongator=2),
                dict(smoother=2), dict(sweeps=2), dict(smoother="hgs", sweeps=17),
                dict(smoother="hgs", gs_block=257), dict(smoother="hgs", omega=-1.0),
@@ -153,6 +153,8 @@ CASES = {
     "varcoef_20_composed2": (lambda: varcoef7(20, seed=5), {"agg_steps": 2}),
     "varcoef_18_smoothed": (lambda: varcoef7(18, seed=6), {"smooth_prolongator": True}),
     "q1_12_smoothed": (lambda: q1_stretched(12, 1.05), {"smooth_prolongator": True}),
+    "q1_20_smoothed_composed3": (lambda: q1_stretched(20, 1.05), {"smooth_prolongator": True, "agg_steps": 3}),
+    "varcoef_24_smoothed_composed2": (lambda: varcoef7(24, seed=7), {"smooth_prolongator": True, "agg_steps": 2}),
 }
 
 

@@ -29,9 +29,13 @@ def host(t):
 
 
 CASES = {
-    "varcoef_16": lambda: varcoef7(16, seed=40),
-    "q1_12": lambda: q1_stretched(12, 1.05),
-    "varcoef_22_stalled_small_coarse": lambda: varcoef7(22, seed=41),
+    # name: (matrix, agg_steps)
+    "varcoef_16": (lambda: varcoef7(16, seed=40), 1),
+    "q1_12": (lambda: q1_stretched(12, 1.05), 1),
+    "varcoef_22": (lambda: varcoef7(22, seed=41), 1),
+    # the paper's configuration: aggregates of up to 8 (4), smoothed
+    "q1_28_composed3": (lambda: q1_stretched(28, 1.05), 3),
+    "varcoef_30_composed2": (lambda: varcoef7(30, seed=42), 2),
 }
 
 
@@ -41,9 +45,10 @@ def built():
 
     def get(case):
         if case not in cache:
-            A = CASES[case]()
-            H = pamg.Hierarchy(A, smooth_prolongator=1, build_f32=1)
-            O = oracle.Hierarchy(A, smooth_prolongator=True)
+            mk, steps = CASES[case]
+            A = mk()
+            H = pamg.Hierarchy(A, smooth_prolongator=1, agg_steps=steps, build_f32=1)
+            O = oracle.Hierarchy(A, smooth_prolongator=True, agg_steps=steps)
             cache[case] = (A, H, O)
         return cache[case]
 
