@@ -282,6 +282,16 @@ static void launch_spmv(const DevLevelIdx& I, const T* v, const XT* x, const dou
     });
 }
 
+// y = b - A x through the row tiles, any vector types; no partials.
+template <typename T, typename XT, typename YT, typename BT>
+static void launch_resid(const DevLevelIdx& I, const T* v, const XT* x, const BT* b, YT* y, hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_spmv<IT, T, XT, YT, BT>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+               (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, (double*)nullptr);
+    });
+}
+
 static void launch_krylov(const DevLevelIdx& I, const double* v, const double* z, const double* p_old, double* p_new,
                           double* q, const double* r, const SolveState* st, double* partial, const int* done,
                           hipStream_t s) {
@@ -389,12 +399,11 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         const int nc = h->idx[l + 1].n;
+        // t = r - (A D^-1) r through the row tiles (column-scaled values)
         if (l == 0)
-            LAUNCH((k_sa_resid<T, double>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
-                   (const T*)V.vd[0], r0, V.zt[0], done);
+            launch_resid<T, double, T, double>(I, V.vd[0], r0, r0, V.zt[0], s);
         else
-            LAUNCH((k_sa_resid<T, T>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
-                   (const T*)V.vd[l], (const T*)V.r[l], V.zt[l], done);
+            launch_resid<T, T, T, T>(I, V.vd[l], (const T*)V.r[l], (const T*)V.r[l], V.zt[l], s);
         LAUNCH((k_sa_restrict<T>), vec_grid(nc), 0, s, nc, I.sa_trp, I.sa_tci, (const T*)V.sa_tv[l],
                (const T*)V.zt[l], V.r[l + 1], done);
     }
@@ -404,17 +413,18 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     for (int l = L - 1; l >= 0; --l) {
         const DevLevelIdx& I = h->idx[l];
         // z_l goes to zt[l] (the residual there is no longer needed)
+        // zp = D^-1 r + P e; t = r - A zp (row tiles); z = zp + D^-1 t
         if (l == 0) {
             LAUNCH((k_sa_prolong<T, double>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[0], e,
                    r0, (const T*)V.dinv[0], V.zp[0], done);
-            LAUNCH((k_sa_post<T, double>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
-                   (const T*)V.v[0], r0, (const T*)V.dinv[0], (const T*)V.zp[0], V.zt[0], done);
+            launch_resid<T, T, T, double>(I, V.v[0], (const T*)V.zp[0], r0, V.zt[0], s);
         } else {
             LAUNCH((k_sa_prolong<T, T>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l], e,
                    (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
-            LAUNCH((k_sa_post<T, T>), vec_grid(I.n), 0, s, I.n, (const int*)I.rp, (const int*)I.ci,
-                   (const T*)V.v[l], (const T*)V.r[l], (const T*)V.dinv[l], (const T*)V.zp[l], V.zt[l], done);
+            launch_resid<T, T, T, T>(I, V.v[l], (const T*)V.zp[l], (const T*)V.r[l], V.zt[l], s);
         }
+        LAUNCH((k_sa_update<T>), vec_grid(I.n), 0, s, I.n, (const T*)V.zp[l], (const T*)V.dinv[l],
+               (const T*)V.zt[l], V.zt[l], done);
         e = V.zt[l];
     }
     const int n0 = h->idx[0].n, g = vec_grid(n0);

@@ -520,10 +520,10 @@ static __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __re
 // ----------------------------------------------------------------------------
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
 // y . y.
-template <int ITEMS, typename T, typename XT, typename YT>
+template <int ITEMS, typename T, typename XT, typename YT, typename BT = double>
 static __global__ __launch_bounds__(kBlock) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const XT* __restrict__ xv, const double* __restrict__ b, YT* __restrict__ y,
+    const XT* __restrict__ xv, const BT* __restrict__ b, YT* __restrict__ y,
     const int4* __restrict__ tiles, int ntiles,
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, double* __restrict__ partial) {
     __shared__ T s_prod[ITEMS * kBlock];
@@ -556,7 +556,7 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
-            const double bi = b ? b[ic] : 0.0;
+            const double bi = b ? (double)b[ic] : 0.0;
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
                 tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
@@ -577,7 +577,7 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (T)xv[ci[k]];
             s = block_sum(s, s_red);
             if (tid == 0) {
-                const double v = b ? b[i0] - (double)s : (double)s;
+                const double v = b ? (double)b[i0] - (double)s : (double)s;
                 y[i0] = (YT)v;
                 nrm += v * v;
             }

@@ -1,8 +1,9 @@
 // V-cycle kernels for the smoothed prolongator (arXiv 2210.16660, Sec. 3.1:
 // P = (I - omega D^-1 A) P^): with P no longer piecewise constant, the
 // restriction and the prolongation are sparse products with P^T and P
-// (hierarchical CSR), next to the l1-Jacobi pre- and post-smoothing.  One
-// thread per row, the row's entries loaded in batches of kSaBatch.
+// (hierarchical CSR), one thread per row with the row's entries loaded in
+// batches of kSaBatch; the passes over A (residuals of the l1-Jacobi pre-
+// and post-smoothing) run through the row-tile SpMV.
 #pragma once
 
 #include "kernels.hpp"
@@ -34,18 +35,6 @@ __device__ __forceinline__ T sa_row_dot(int k0, int k1, const int* __restrict__ 
     return s;
 }
 
-// Pre-smoothing from zero and the residual: t = r - A D^-1 r (vd = a_ij / d_j).
-template <typename T, typename RT>
-static __global__ __launch_bounds__(kBlock) void k_sa_resid(int n, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const T* __restrict__ vd,
-                                                     const RT* __restrict__ r, T* __restrict__ t,
-                                                     const int* __restrict__ done) {
-    if (*done) return;
-    const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        t[i] = (T)r[i] - sa_row_dot<T, RT>(rp[i], rp[i + 1], ci, vd, r);
-}
-
 // Restriction rc = P^T t (rows of P^T: coarse unknowns).
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void k_sa_restrict(int nc, const int* __restrict__ trp,
@@ -71,17 +60,14 @@ static __global__ __launch_bounds__(kBlock) void k_sa_prolong(int n, const int* 
         zp[i] = dinv[i] * (T)r[i] + sa_row_dot<T, T>(prp[i], prp[i + 1], pci, pv, e);
 }
 
-// Post-smoothing: z = zp + D^-1 (r - A zp).
-template <typename T, typename RT>
-static __global__ __launch_bounds__(kBlock) void k_sa_post(int n, const int* __restrict__ rp,
-                                                    const int* __restrict__ ci, const T* __restrict__ av,
-                                                    const RT* __restrict__ r, const T* __restrict__ dinv,
-                                                    const T* __restrict__ zp, T* __restrict__ z,
-                                                    const int* __restrict__ done) {
+// Post-smoothing update from the residual t = r - A zp: z = zp + D^-1 t
+// (in place when z aliases t).
+template <typename T>
+static __global__ __launch_bounds__(kBlock) void k_sa_update(int n, const T* __restrict__ zp, const T* __restrict__ dinv,
+                                                      const T* t, T* z, const int* __restrict__ done) {
     if (*done) return;
     const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        z[i] = zp[i] + dinv[i] * ((T)r[i] - sa_row_dot<T, T>(rp[i], rp[i + 1], ci, av, zp));
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) z[i] = zp[i] + dinv[i] * t[i];
 }
 
 }  // namespace pamg
