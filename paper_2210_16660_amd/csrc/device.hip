@@ -389,6 +389,9 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     return g;
 }
 
+// Workgroups for `rows` rows handled by groups of `lanes` lanes.
+static int sa_grid(long long rows, int lanes) { return vec_grid(rows * lanes); }
+
 // V-cycle with smoothed prolongators (L >= 1): per level the residual of the
 // l1-Jacobi pre-smoothing from zero and its restriction P^T t; after the
 // coarse solve the prolongation D^-1 r + P e and the post-smoothing.
@@ -404,8 +407,8 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
             launch_resid<T, double, T, double>(I, V.vd[0], r0, r0, V.zt[0], s);
         else
             launch_resid<T, T, T, T>(I, V.vd[l], (const T*)V.r[l], (const T*)V.r[l], V.zt[l], s);
-        LAUNCH((k_sa_restrict<T>), vec_grid(nc), 0, s, nc, I.sa_trp, I.sa_tci, (const T*)V.sa_tv[l],
-               (const T*)V.zt[l], V.r[l + 1], done);
+        LAUNCH((k_sa_restrict<T>), sa_grid(nc, kSaRestrictLanes), 0, s, nc, I.sa_trp, I.sa_tci,
+               (const T*)V.sa_tv[l], (const T*)V.zt[l], V.r[l + 1], done);
     }
     const int nL = h->idx[L].n;
     LAUNCH((k_gs_coarse<T, T>), vec_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
@@ -415,11 +418,11 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
         // z_l goes to zt[l] (the residual there is no longer needed)
         // zp = D^-1 r + P e; t = r - A zp (row tiles); z = zp + D^-1 t
         if (l == 0) {
-            LAUNCH((k_sa_prolong<T, double>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[0], e,
+            LAUNCH((k_sa_prolong<T, double>), sa_grid(I.n, kSaProlongLanes), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[0], e,
                    r0, (const T*)V.dinv[0], V.zp[0], done);
             launch_resid<T, T, T, double>(I, V.v[0], (const T*)V.zp[0], r0, V.zt[0], s);
         } else {
-            LAUNCH((k_sa_prolong<T, T>), vec_grid(I.n), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l], e,
+            LAUNCH((k_sa_prolong<T, T>), sa_grid(I.n, kSaProlongLanes), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l], e,
                    (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
             launch_resid<T, T, T, T>(I, V.v[l], (const T*)V.zp[l], (const T*)V.r[l], V.zt[l], s);
         }

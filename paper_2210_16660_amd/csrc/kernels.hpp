@@ -552,7 +552,12 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
-            const int i = i0 + tid;
+            // phase 2: G lanes per row (G = 1 unless the tile has few, long
+            // rows), each summing a strided part, then a fixed-order butterfly
+            int G = 1;
+            while (G < 64 && 2 * G * (i1 - i0) <= kBlock) G *= 2;
+            const int lane = tid & (G - 1);
+            const int i = i0 + tid / G;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
@@ -564,9 +569,11 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
             __syncthreads();
-            if (own) {
-                T s = 0;
-                for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
+            T s = 0;
+            if (own)
+                for (int k = rb - k0 + lane; k < re - k0; k += G) s += s_prod[k];
+            for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+            if (own && lane == 0) {
                 const double v = b ? bi - (double)s : (double)s;
                 y[i] = (YT)v;
                 nrm += v * v;

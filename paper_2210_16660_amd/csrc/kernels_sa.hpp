@@ -1,53 +1,48 @@
 // V-cycle kernels for the smoothed prolongator (arXiv 2210.16660, Sec. 3.1:
 // P = (I - omega D^-1 A) P^): with P no longer piecewise constant, the
 // restriction and the prolongation are sparse products with P^T and P
-// (hierarchical CSR), one thread per row with the row's entries loaded in
-// batches of kSaBatch; the passes over A (residuals of the l1-Jacobi pre-
-// and post-smoothing) run through the row-tile SpMV.
+// (hierarchical CSR), a group of lanes per row; the passes over A
+// (residuals of the l1-Jacobi pre- and post-smoothing) run through the
+// row-tile SpMV.
 #pragma once
 
 #include "kernels.hpp"
 
 namespace pamg {
 
-constexpr int kSaBatch = 8;
-
-// s = sum_k val[k] * x[col[k]] over [k0, k1), in order; batched loads.
-template <typename T, typename XT>
-__device__ __forceinline__ T sa_row_dot(int k0, int k1, const int* __restrict__ col, const T* __restrict__ val,
-                                        const XT* __restrict__ x) {
+// Sum over one CSR row by a group of LPR lanes (entries strided over the
+// group, then a butterfly in fixed order): every lane gets the sum.
+template <int LPR, typename T, typename XT>
+__device__ __forceinline__ T sa_group_dot(int k0, int k1, int lane, const int* __restrict__ col,
+                                          const T* __restrict__ val, const XT* __restrict__ x) {
     T s = 0;
-    for (int kb = k0; kb < k1; kb += kSaBatch) {
-        int c[kSaBatch];
-        T a[kSaBatch], xv[kSaBatch];
+    for (int k = k0 + lane; k < k1; k += LPR) s += val[k] * (T)x[col[k]];
 #pragma unroll
-        for (int u = 0; u < kSaBatch; ++u) {
-            const int k = min(kb + u, k1 - 1);
-            c[u] = col[k];
-            a[u] = val[k];
-        }
-#pragma unroll
-        for (int u = 0; u < kSaBatch; ++u) xv[u] = (T)x[c[u]];
-#pragma unroll
-        for (int u = 0; u < kSaBatch; ++u)
-            if (kb + u < k1) s += a[u] * xv[u];
-    }
+    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
     return s;
 }
 
-// Restriction rc = P^T t (rows of P^T: coarse unknowns).
+// Restriction rc = P^T t (rows of P^T: coarse unknowns, long rows: a group
+// of kSaRestrictLanes lanes per row).
+constexpr int kSaRestrictLanes = 16, kSaProlongLanes = 8;
+
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void k_sa_restrict(int nc, const int* __restrict__ trp,
                                                         const int* __restrict__ tci, const T* __restrict__ tv,
                                                         const T* __restrict__ t, T* __restrict__ rc,
                                                         const int* __restrict__ done) {
     if (*done) return;
-    const int stride = gridDim.x * kBlock;
-    for (int I = blockIdx.x * kBlock + threadIdx.x; I < nc; I += stride)
-        rc[I] = sa_row_dot<T, T>(trp[I], trp[I + 1], tci, tv, t);
+    constexpr int G = kSaRestrictLanes;
+    const int lane = threadIdx.x % G;
+    const int stride = gridDim.x * (kBlock / G);
+    for (int I = blockIdx.x * (kBlock / G) + threadIdx.x / G; I < nc; I += stride) {
+        const T v = sa_group_dot<G, T, T>(trp[I], trp[I + 1], lane, tci, tv, t);
+        if (lane == 0) rc[I] = v;
+    }
 }
 
-// Prolongation onto the pre-smoothed iterate: zp = D^-1 r + P e.
+// Prolongation onto the pre-smoothed iterate: zp = D^-1 r + P e (a group of
+// kSaProlongLanes lanes per row).
 template <typename T, typename RT>
 static __global__ __launch_bounds__(kBlock) void k_sa_prolong(int n, const int* __restrict__ prp,
                                                        const int* __restrict__ pci, const T* __restrict__ pv,
@@ -55,9 +50,13 @@ static __global__ __launch_bounds__(kBlock) void k_sa_prolong(int n, const int* 
                                                        const T* __restrict__ dinv, T* __restrict__ zp,
                                                        const int* __restrict__ done) {
     if (*done) return;
-    const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-        zp[i] = dinv[i] * (T)r[i] + sa_row_dot<T, T>(prp[i], prp[i + 1], pci, pv, e);
+    constexpr int G = kSaProlongLanes;
+    const int lane = threadIdx.x % G;
+    const int stride = gridDim.x * (kBlock / G);
+    for (int i = blockIdx.x * (kBlock / G) + threadIdx.x / G; i < n; i += stride) {
+        const T v = sa_group_dot<G, T, T>(prp[i], prp[i + 1], lane, pci, pv, e);
+        if (lane == 0) zp[i] = dinv[i] * (T)r[i] + v;
+    }
 }
 
 // Post-smoothing update from the residual t = r - A zp: z = zp + D^-1 t
