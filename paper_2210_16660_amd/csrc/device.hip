@@ -326,27 +326,41 @@ static int coarse_partials(int nL) { return nL > kCoarseRowsMin ? coarse_rows_gr
 // `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from
 // x = 0 (pre-smoothing) or backward from x (post-smoothing).  Ping-pongs
 // between x and the level's second buffer; returns where the result is.
+template <int MAXB, typename T, typename RT>
+static void launch_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, const T* x_old, T* x_new, bool backward,
+                       bool zero, const int* done, hipStream_t s) {
+    const DevLevelIdx& I = h->idx[l];
+    const T winv = (T)(1.0 / h->omega);
+    const dim3 g(I.gs_nblk), blk(MAXB);
+    if (backward)
+        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_db, I.gs_maxd, r, x_old, x_new,
+                           winv, done);
+    else if (zero)
+        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
+                           (const T*)nullptr, x_new, winv, done);
+    else
+        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
+                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r, x_old, x_new,
+                           winv, done);
+}
+
+// `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from
+// x = 0 (pre-smoothing) or backward from x (post-smoothing).  Ping-pongs
+// between x and the level's second buffer; returns where the result is.
+// Blocks of at most 64 rows run one wave per workgroup.
 template <typename T, typename RT>
 static T* enqueue_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, T* x, bool backward, const int* done,
                       hipStream_t s) {
-    const DevLevelIdx& I = h->idx[l];
     T* a = x;
     T* b = (x == V.zt[l]) ? V.zp[l] : V.zt[l];
-    const T winv = (T)(1.0 / h->omega);
-    const dim3 g(I.gs_nblk), blk(kBlock);
     for (int k = 0; k < h->sweeps; ++k) {
-        if (backward)
-            hipLaunchKernelGGL((k_hgs<T, RT, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_db, I.gs_maxd, r,
-                               (const T*)a, b, winv, done);
-        else if (k == 0)
-            hipLaunchKernelGGL((k_hgs<T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
-                               (const T*)nullptr, b, winv, done);
+        const bool zero = !backward && k == 0;
+        if (h->gs_block <= kGsSmallBlock)
+            launch_hgs<kGsSmallBlock, T, RT>(h, V, l, r, a, b, backward, zero, done, s);
         else
-            hipLaunchKernelGGL((k_hgs<T, RT, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                               (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
-                               (const T*)a, b, winv, done);
+            launch_hgs<kGsMaxBlock, T, RT>(h, V, l, r, a, b, backward, zero, done, s);
         std::swap(a, b);
     }
     return a;
@@ -838,19 +852,26 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
             throw Error(PAMG_E_INVALID, "SMOOTH needs a hybrid Gauss-Seidel hierarchy and level < L");
         *bytes = I.nnz * (4 + sz) + 4 * (n + 1) + n * ((l == 0 ? 8 : sz) + 3 * sz + 1) + 8 * (uint64_t)I.gs_nblk;
         const T winv = (T)(1.0 / h->omega);
+        (void)winv;
+        DevVals<T>* Vp = &V;
+        const bool small = h->gs_block <= kGsSmallBlock;
         if (l == 0)
             launch = [=]() {
-                hipLaunchKernelGGL((k_hgs<T, double, true, false>), dim3(I.gs_nblk), dim3(kBlock), 0, s, I.n,
-                                   h->gs_block, (const int*)I.rp, (const int*)I.ci, (const T*)V.v[0],
-                                   (const T*)V.gsa[0], I.gs_db, I.gs_maxd, (const double*)h->r, (const T*)V.zp[0],
-                                   V.zt[0], winv, nodone);
+                if (small)
+                    launch_hgs<kGsSmallBlock, T, double>(h, *Vp, 0, (const double*)h->r, Vp->zp[0], Vp->zt[0], true,
+                                                         false, nodone, s);
+                else
+                    launch_hgs<kGsMaxBlock, T, double>(h, *Vp, 0, (const double*)h->r, Vp->zp[0], Vp->zt[0], true,
+                                                       false, nodone, s);
             };
         else
             launch = [=]() {
-                hipLaunchKernelGGL((k_hgs<T, T, true, false>), dim3(I.gs_nblk), dim3(kBlock), 0, s, I.n,
-                                   h->gs_block, (const int*)I.rp, (const int*)I.ci, (const T*)V.v[l],
-                                   (const T*)V.gsa[l], I.gs_db, I.gs_maxd, (const T*)V.r[l], (const T*)V.zp[l],
-                                   V.zt[l], winv, nodone);
+                if (small)
+                    launch_hgs<kGsSmallBlock, T, T>(h, *Vp, l, (const T*)Vp->r[l], Vp->zp[l], Vp->zt[l], true, false,
+                                                    nodone, s);
+                else
+                    launch_hgs<kGsMaxBlock, T, T>(h, *Vp, l, (const T*)Vp->r[l], Vp->zp[l], Vp->zt[l], true, false,
+                                                  nodone, s);
             };
     } else {
         throw Error(PAMG_E_INVALID, "op must be DOWN, UP, SPMV, KRYLOV or SMOOTH");

@@ -17,7 +17,8 @@
 
 namespace pamg {
 
-constexpr int kGsMaxBlock = kBlock;
+constexpr int kGsMaxBlock = kBlock;   // largest block (one workgroup of kBlock threads)
+constexpr int kGsSmallBlock = 64;     // blocks of <= 64 rows run one wave per workgroup
 constexpr int kGsFresh = 16;     // in-block entries of a row kept in LDS for the substitution
 constexpr int kGsBatch = 8;      // row entries loaded together in the first pass
 
@@ -28,16 +29,16 @@ constexpr int kGsBatch = 8;      // row entries loaded together in the first pas
 // entries (value, position in the block) into LDS; the substitution then
 // runs depth by depth from LDS (a row with more fresh entries reads its row
 // again).
-template <typename T, typename RT, bool BACKWARD, bool ZERO>
-static __global__ __launch_bounds__(kBlock) void k_hgs(
+template <int MAXB, typename T, typename RT, bool BACKWARD, bool ZERO>
+static __global__ __launch_bounds__(MAXB) void k_hgs(
     int n, int nb, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ ainv, const uint8_t* __restrict__ depth, const int* __restrict__ maxd,
     const RT* __restrict__ r, const T* __restrict__ x_old, T* __restrict__ x_new, T omega_inv,
     const int* __restrict__ done) {
     if (*done) return;
-    __shared__ T s_d[kGsMaxBlock];
-    __shared__ T s_fa[kGsFresh * kGsMaxBlock];
-    __shared__ uint8_t s_fq[kGsFresh * kGsMaxBlock];
+    __shared__ T s_d[MAXB];
+    __shared__ T s_fa[kGsFresh * MAXB];
+    __shared__ uint8_t s_fq[kGsFresh * MAXB];
     const int p = blockIdx.x, t = threadIdx.x;
     const int b0 = p * nb, b1 = min(n, b0 + nb);
     const int i = b0 + t;
@@ -72,8 +73,8 @@ static __global__ __launch_bounds__(kBlock) void k_hgs(
                 const bool f = BACKWARD ? (j > i && j < b1) : (j >= b0 && j < i);
                 if (f) {
                     if (nf < kGsFresh) {
-                        s_fa[nf * kGsMaxBlock + t] = aa[u];
-                        s_fq[nf * kGsMaxBlock + t] = (uint8_t)(j - b0);
+                        s_fa[nf * MAXB + t] = aa[u];
+                        s_fq[nf * MAXB + t] = (uint8_t)(j - b0);
                     }
                     ++nf;
                 }
@@ -85,8 +86,8 @@ static __global__ __launch_bounds__(kBlock) void k_hgs(
     int fq[kGsFresh];
 #pragma unroll
     for (int u = 0; u < kGsFresh; ++u) {
-        fa[u] = u < nf ? s_fa[u * kGsMaxBlock + t] : T(0);
-        fq[u] = u < nf ? (int)s_fq[u * kGsMaxBlock + t] : 0;
+        fa[u] = u < nf ? s_fa[u * MAXB + t] : T(0);
+        fq[u] = u < nf ? (int)s_fq[u * MAXB + t] : 0;
     }
     const int md = maxd[2 * p + (BACKWARD ? 1 : 0)];
     for (int d = 0; d <= md; ++d) {
