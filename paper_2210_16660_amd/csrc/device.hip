@@ -851,8 +851,6 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
         if (h->smoother != PAMG_SMOOTHER_HYBRID_GS || l >= h->L)
             throw Error(PAMG_E_INVALID, "SMOOTH needs a hybrid Gauss-Seidel hierarchy and level < L");
         *bytes = I.nnz * (4 + sz) + 4 * (n + 1) + n * ((l == 0 ? 8 : sz) + 3 * sz + 1) + 8 * (uint64_t)I.gs_nblk;
-        const T winv = (T)(1.0 / h->omega);
-        (void)winv;
         DevVals<T>* Vp = &V;
         const bool small = h->gs_block <= kGsSmallBlock;
         if (l == 0)
