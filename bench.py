@@ -95,6 +95,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=200.0)
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="serving: open-loop arrival rate as a fraction of the closed-loop capacity")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--agg-steps", type=int, default=1,
                     help="aggregate-size composition: keep every n-th pairwise level (aggregates up to 2^n)")
@@ -556,7 +558,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     capacity = ncl / wall
     log(f"closed loop: {ncl} requests in {wall:.2f}s -> {capacity:.1f} solves/s")
     # open loop: Poisson arrivals at half the capacity over the remaining requests
-    lam = 0.5 * capacity
+    lam = args.serve_load * capacity
     nol = args.requests - ncl
     arrivals = np.cumsum(SplitMix64(55).exponential(nol, lam))
     st1 = S.stats()
@@ -573,7 +575,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
         "unit": "solves/s",
         "higher_is_better": True,
         "config": {"workload": f"{args.requests} requests ({ncl} queued at once for the capacity, then {nol} "
-                               f"with Poisson arrivals at lambda = 0.5 x capacity) after a warm-up that caches every "
+                               f"with Poisson arrivals at lambda = {args.serve_load:g} x capacity) after a warm-up that caches every "
                                f"operator's hierarchy; "
                                f"variable-coefficient 7-point operators (pool of {args.pool}, n^3 with n log-uniform "
                                f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "
