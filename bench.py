@@ -97,6 +97,10 @@ def main() -> int:
     ap.add_argument("--budget-gib", type=float, default=200.0)
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="serving: open-loop arrival rate as a fraction of the closed-loop capacity")
+    ap.add_argument("--single-path", type=int, default=1, choices=[0, 1],
+                    help="serving: a request alone on its operator runs on the single-right-hand-side solver")
+    ap.add_argument("--batch-from", type=int, default=4,
+                    help="serving: waiting requests of one operator from which they are batched")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--agg-steps", type=int, default=1,
                     help="aggregate-size composition: keep every n-th pairwise level (aggregates up to 2^n)")
@@ -488,7 +492,8 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     torch.cuda.current_stream().synchronize()
     log(f"{args.requests} right-hand sides in {time.perf_counter() - t0:.1f}s")
     budget = int(args.budget_gib * (1 << 30))
-    S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32, use_graph=1)
+    S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32, use_graph=1,
+                    single_path=args.single_path, batch_from=args.batch_from)
 
     def wait_for(count, what):
         comps = []
@@ -580,7 +585,8 @@ def bench_serve(args, torch, np, pamg, log) -> int:
                                f"variable-coefficient 7-point operators (pool of {args.pool}, n^3 with n log-uniform "
                                f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "
                                f"FP32 V-cycle / FP64 FCG, accepted on the true residual",
-                   "hbm_budget_gib": args.budget_gib, "block_iters": 4},
+                   "hbm_budget_gib": args.budget_gib, "block_iters": 4, "single_path": args.single_path,
+                   "batch_from": args.batch_from},
         "lambda_per_s": round(lam, 2),
         "closed_loop_capacity_per_s": round(capacity, 2),
         "open_loop_rate_per_s": round(len(comps) / wall, 2),

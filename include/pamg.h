@@ -255,7 +255,9 @@ int pamg_time_op(pamg_hierarchy *h, int32_t op, int32_t level, int32_t precision
  * requests join between iteration blocks and finished ones retire at once.
  * Blocks of all operators are launched before any is waited on, so their
  * work overlaps.  A request's result does not depend on what it was batched
- * with.  Calls that overlap on one server from several threads are safe. */
+ * with (with single_path, a request alone on its operator runs on the
+ * single-right-hand-side solver instead).  Calls that overlap on one server
+ * from several threads are safe. */
 typedef struct pamg_server pamg_server;
 
 typedef struct {
@@ -268,7 +270,18 @@ typedef struct {
                                     the application's threads (hipDeviceSynchronize) fail with
                                     hipErrorStreamCaptureUnsupported, so such programs must
                                     synchronize streams instead.  Default 0: direct launches. */
-    int32_t reserved[7];
+    int32_t single_path;         /* 1: while fewer than batch_from requests for an operator are
+                                    waiting and its batch has no running column, its requests run
+                                    one at a time on the single-right-hand-side solver (n-long
+                                    vectors instead of n x 16; later ones wait for it), and such a
+                                    result is bitwise that of pamg_solve with the same tolerance,
+                                    maxit and precision; otherwise they join the batch engine.
+                                    Which solver serves a request then depends on the mix.
+                                    Default 0: every request is a column of the batch engine,
+                                    bitwise independent of the mix. */
+    int32_t batch_from;          /* with single_path: waiting requests of one operator from which
+                                    they go to the batch engine (<= 0: 4) */
+    int32_t reserved[5];
 } pamg_server_opts;
 
 typedef struct {

@@ -341,6 +341,8 @@ static hipGraphExec_t block_graph(BatchEngine* E, int krylov, int k) {
     return ex;
 }
 
+void batch_prepare_graph(BatchEngine* E, int krylov, int k) { (void)block_graph(E, krylov, k); }
+
 // One block of k iterations (graph replay or direct launches).
 void batch_run_block(BatchEngine* E, int krylov, int k, bool use_graph, hipStream_t s) {
     if (use_graph) {

@@ -21,6 +21,8 @@ void batch_load(BatchEngine* E, const double* const* src, const double* tol, con
 void batch_store(BatchEngine* E, double* const* dst, hipStream_t s);
 void batch_true_residual(BatchEngine* E, int restart_mask, double* relres, hipStream_t s);
 void batch_run_block(BatchEngine* E, int krylov, int k, bool use_graph, hipStream_t s);
+// Capture and instantiate the block graph batch_run_block replays (no launch).
+void batch_prepare_graph(BatchEngine* E, int krylov, int k);
 // Mark the columns in `mask` inactive in the host copy of the state (written
 // back by the next batch_write_state / batch_load).
 void batch_retire(BatchEngine* E, int mask);

@@ -531,8 +531,12 @@ static hipGraphExec_t get_graph(pamg_hierarchy* h, DevVals<T>& V, int prec, int 
     return ex;
 }
 
-static void read_state(pamg_hierarchy* h, hipStream_t s) {
+static void read_state_async(pamg_hierarchy* h, hipStream_t s) {
     HIP_CHECK(hipMemcpyAsync(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+}
+
+static void read_state(pamg_hierarchy* h, hipStream_t s) {
+    read_state_async(h, s);
     HIP_CHECK(hipStreamSynchronize(s));
 }
 
@@ -549,27 +553,25 @@ static double true_relres(pamg_hierarchy* h, hipStream_t s) {
     return std::sqrt(rr) / h->st_host->bnorm;
 }
 
-template <typename T>
-static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double* b_user, double* x_user,
-                       const pamg_solve_opts& o, hipStream_t s, pamg_solve_info* info) {
-    auto t0 = std::chrono::steady_clock::now();
+// Start of a solve: the recurrence state, b in hierarchical order, x (x0 or
+// zero) and r = b - A x.  The host copy of the state is the staging buffer,
+// so the stream must have passed any earlier copy through it.
+static void begin_solve(pamg_hierarchy* h, const double* b_user, const double* x0_user, double tol, int maxit,
+                        int fixed_iters, int krylov, hipStream_t s) {
     const DevLevelIdx& I0 = h->idx[0];
     const int n = I0.n;
     const int gv = vec_grid(n);
-    const int krylov = o.krylov == PAMG_KRYLOV_CG ? PAMG_KRYLOV_CG : PAMG_KRYLOV_FCG;
     SolveState init{};
-    init.tol = o.tol;
-    init.maxit = o.maxit;
-    init.fixed_iters = o.fixed_iters;
+    init.tol = tol;
+    init.maxit = maxit;
+    init.fixed_iters = fixed_iters;
     init.krylov = krylov;
-    // wait for any earlier use of the pinned staging buffer
-    HIP_CHECK(hipStreamSynchronize(s));
     *h->st_host = init;
     HIP_CHECK(hipMemcpyAsync(h->st, h->st_host, sizeof(SolveState), hipMemcpyHostToDevice, s));
     LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, b_user, h->b);
     LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, (double*)nullptr, h->partial_b);
-    if (o.use_x0) {
-        LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, (const double*)x_user, h->x);
+    if (x0_user) {
+        LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.iperm, x0_user, h->x);
         launch_spmv<double, double>(I0, h->f64.v[0], h->x, h->b, h->r, h->partial, s);
         LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial,
                tile_grid(I0.n_up));
@@ -578,6 +580,46 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
         LAUNCH(k_norm2, gv, 0, s, n, (const double*)h->b, h->r, h->partial);
         LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, gv, (const double*)h->partial, gv);
     }
+}
+
+// k iterations (a replay of `ex` when given), then the state copy to the host.
+template <typename T>
+static void run_block(pamg_hierarchy* h, DevVals<T>& V, int krylov, int k, hipGraphExec_t ex, hipStream_t s) {
+    if (ex)
+        HIP_CHECK(hipGraphLaunch(ex, s));
+    else
+        enqueue_block<T>(h, V, krylov, k, s);
+    read_state_async(h, s);
+}
+
+// The recurrence restarted from the true residual r = b - A x (the FP32
+// preconditioner's recurrence residual can drift from it); then the state copy.
+static void restart_solve(pamg_hierarchy* h, hipStream_t s) {
+    const DevLevelIdx& I0 = h->idx[0];
+    launch_spmv<double, double>(I0, h->f64.v[0], h->x, h->b, h->r, h->partial, s);
+    LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, 0, (const double*)h->partial,
+           tile_grid(I0.n_up));
+    read_state_async(h, s);
+}
+
+// x in the caller's numbering (zero for a zero right-hand side); the host
+// copy of the state must be current.
+static void end_solve(pamg_hierarchy* h, double* x_user, hipStream_t s) {
+    const DevLevelIdx& I0 = h->idx[0];
+    const int n = I0.n;
+    const int gv = vec_grid(n);
+    if (h->st_host->done == 2) LAUNCH(k_fill, gv, 0, s, (long long)n, h->x, 0.0);
+    LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.perm, (const double*)h->x, x_user);
+}
+
+template <typename T>
+static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double* b_user, double* x_user,
+                       const pamg_solve_opts& o, hipStream_t s, pamg_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int krylov = o.krylov == PAMG_KRYLOV_CG ? PAMG_KRYLOV_CG : PAMG_KRYLOV_FCG;
+    // wait for any earlier use of the pinned staging buffer
+    HIP_CHECK(hipStreamSynchronize(s));
+    begin_solve(h, b_user, o.use_x0 ? x_user : nullptr, o.tol, o.maxit, o.fixed_iters, krylov, s);
     int k = o.check_every > 0 ? o.check_every : 4;
     if (k & 1) ++k;
     hipGraphExec_t ex = o.use_graph ? get_graph<T>(h, V, prec, krylov, k) : nullptr;
@@ -586,29 +628,20 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
     read_state(h, s);
     for (;;) {
         while (!h->st_host->done) {
-            if (ex)
-                HIP_CHECK(hipGraphLaunch(ex, s));
-            else
-                enqueue_block<T>(h, V, krylov, k, s);
-            read_state(h, s);
+            run_block<T>(h, V, krylov, k, ex, s);
+            HIP_CHECK(hipStreamSynchronize(s));
         }
-        if (h->st_host->done == 2) {   // zero right-hand side
-            LAUNCH(k_fill, gv, 0, s, (long long)n, h->x, 0.0);
-            break;
-        }
+        if (h->st_host->done == 2) break;   // zero right-hand side
         const bool want_true = o.true_residual || prec == PAMG_PREC_F32;
         if (!want_true || h->st_host->status != PAMG_OK || o.fixed_iters > 0) break;
         relres_true = true_relres(h, s);
         if (relres_true <= o.tol || prec != PAMG_PREC_F32 || restarts >= 10 || h->st_host->iter >= o.maxit) break;
-        // FP32 preconditioner: restart the recurrence from the true residual
         ++restarts;
-        launch_spmv<double, double>(I0, h->f64.v[0], h->x, h->b, h->r, h->partial, s);
-        LAUNCH(k_fin_init, 1, 0, s, h->st, (const double*)h->partial_b, 0, (const double*)h->partial,
-               tile_grid(I0.n_up));
-        read_state(h, s);
+        restart_solve(h, s);
+        HIP_CHECK(hipStreamSynchronize(s));
         relres_true = -1.0;
     }
-    LAUNCH((k_gather<double, double>), gv, 0, s, n, (const int*)I0.perm, (const double*)h->x, x_user);
+    end_solve(h, x_user, s);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
@@ -640,6 +673,53 @@ int solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts& 
         solve_impl<double>(h, h->f64, 0, b, x, o, s, info);
     }
     return info->status;
+}
+
+// ---------------------------------------------------------------- stepped solve
+// The serving loop drives a single-right-hand-side FCG solve step by step on
+// its own stream, with the arithmetic of solve() (x0 = 0): the caller orders
+// the steps and waits for the stream before reading single_state.
+
+void single_begin(pamg_hierarchy* h, const double* b, double tol, int maxit, hipStream_t s) {
+    require_device(h);
+    begin_solve(h, b, nullptr, tol, maxit, 0, PAMG_KRYLOV_FCG, s);
+}
+
+void single_block(pamg_hierarchy* h, int prec, int k, bool use_graph, hipStream_t s) {
+    if (k & 1) ++k;
+    if (prec == PAMG_PREC_F32) {
+        if (!h->f32.built) throw Error(PAMG_E_INVALID, "FP32 hierarchy not built (set params.build_f32)");
+        run_block<float>(h, h->f32, PAMG_KRYLOV_FCG, k,
+                         use_graph ? get_graph<float>(h, h->f32, 1, PAMG_KRYLOV_FCG, k) : nullptr, s);
+    } else {
+        run_block<double>(h, h->f64, PAMG_KRYLOV_FCG, k,
+                          use_graph ? get_graph<double>(h, h->f64, 0, PAMG_KRYLOV_FCG, k) : nullptr, s);
+    }
+}
+
+void single_prepare_graph(pamg_hierarchy* h, int prec, int k) {
+    if (k & 1) ++k;
+    if (prec == PAMG_PREC_F32)
+        (void)get_graph<float>(h, h->f32, 1, PAMG_KRYLOV_FCG, k);
+    else
+        (void)get_graph<double>(h, h->f64, 0, PAMG_KRYLOV_FCG, k);
+}
+
+const SolveState& single_state(const pamg_hierarchy* h) { return *h->st_host; }
+double single_true_relres(pamg_hierarchy* h, hipStream_t s) { return true_relres(h, s); }
+void single_restart(pamg_hierarchy* h, hipStream_t s) { restart_solve(h, s); }
+
+void single_end(pamg_hierarchy* h, double* x, hipStream_t s) {
+    end_solve(h, x, s);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(s));
+}
+
+// Algorithmic bytes of one iteration: the V-cycle, the FP64 Krylov product
+// and twelve level-0 vector passes.
+uint64_t single_iteration_bytes(const pamg_hierarchy* h, int prec) {
+    const uint64_t n0 = (uint64_t)h->idx[0].n;
+    return vcycle_bytes(h, prec == PAMG_PREC_F32 ? 4 : 8) + matrix_bytes(h->idx[0], false, 8) + 12 * n0 * 8;
 }
 
 // ---------------------------------------------------------------- debug ops

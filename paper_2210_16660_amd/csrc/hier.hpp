@@ -148,6 +148,18 @@ constexpr int kMaxDense = 8192;
 // device CSR: Cholesky and inverse on the matrix cores (dense.hip).  Throws
 // PAMG_E_NOT_SPD on a non-positive pivot.  Synchronizes the stream.
 void coarse_inverse_device(int n, const int* rp, const int* ci, const double* v, double* ainv, hipStream_t s);
+// Single-right-hand-side FCG (x0 = 0) in steps on a caller's stream, with the
+// arithmetic of pamg_solve: begin, blocks of k iterations each followed by an
+// asynchronous copy of the state to its host copy, the true residual and a
+// restart from it, and the result in the caller's numbering (synchronizes).
+void single_begin(pamg_hierarchy* h, const double* b, double tol, int maxit, hipStream_t s);
+void single_block(pamg_hierarchy* h, int prec, int k, bool use_graph, hipStream_t s);
+void single_prepare_graph(pamg_hierarchy* h, int prec, int k);   // capture only, no launch
+const SolveState& single_state(const pamg_hierarchy* h);
+double single_true_relres(pamg_hierarchy* h, hipStream_t s);
+void single_restart(pamg_hierarchy* h, hipStream_t s);
+void single_end(pamg_hierarchy* h, double* x, hipStream_t s);
+uint64_t single_iteration_bytes(const pamg_hierarchy* h, int prec);
 // Canonical values of a kept level after a coefficient-only update (reuse.hip).
 void updated_level_values(const pamg_hierarchy* h, int level, double* v);
 }  // namespace pamg

@@ -69,6 +69,16 @@ struct ServeGroup {
     hipEvent_t ev = nullptr;     // recorded behind the state copy of the block in flight
     bool in_flight = false;
     int iter_before[kW] = {};    // column iteration counts when the block was launched
+    // single-right-hand-side path: one request on the hierarchy's own solver
+    // (its vectors are n, not n x 16), on the same stream (a second stream
+    // per operator would also take a share of the hardware queues, which
+    // streams get round-robin)
+    ServeRequest* single = nullptr;
+    hipEvent_t single_ev = nullptr;
+    bool single_in_flight = false;
+    int single_iter_before = 0;  // its iteration count at the last state copy read
+    uint64_t single_iter_bytes = 0;
+    bool idle() const { return active == 0 && !in_flight && !single && !single_in_flight; }
 };
 
 }  // namespace pamg
@@ -160,11 +170,16 @@ static void complete(pamg_server* S, ServeRequest* q, int status, int iters, dou
     delete q;
 }
 
+static void release_streams(ServeGroup* g) {
+    (void)hipEventDestroy(g->ev);
+    if (g->single_ev) (void)hipEventDestroy(g->single_ev);
+    (void)hipStreamDestroy(g->stream);
+}
+
 static void evict(pamg_server* S, ServeGroup* g) {
     HIP_CHECK(hipStreamSynchronize(g->stream));
     pamg_hierarchy_destroy(g->h);
-    (void)hipEventDestroy(g->ev);
-    (void)hipStreamDestroy(g->stream);
+    release_streams(g);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stats.bytes_in_use -= g->bytes;
@@ -244,8 +259,7 @@ static void admit_ready(pamg_server* S) {
         while (in_use() + need > budget) {
             ServeGroup* lru = nullptr;
             for (auto& kv : S->groups)
-                if (kv.second->active == 0 && !kv.second->in_flight &&
-                    (!lru || kv.second->last_used < lru->last_used))
+                if (kv.second->idle() && (!lru || kv.second->last_used < lru->last_used))
                     lru = kv.second;
             if (!lru) { room = false; break; }       // everything busy: try again next tick
             evict(S, lru);
@@ -255,21 +269,26 @@ static void admit_ready(pamg_server* S) {
         g->key = j->key;
         HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
+        if (S->opts.single_path) HIP_CHECK(hipEventCreateWithFlags(&g->single_ev, hipEventDisableTiming));
         const double host_ms = j->built->host_ms;
         const auto t0 = Clock::now();
         try {
             g->h = finish_build(std::move(j->built), g->stream);
         } catch (const Error& e) {
-            (void)hipEventDestroy(g->ev);
-            (void)hipStreamDestroy(g->stream);
+            release_streams(g.get());
             it = S->setups.erase(it);
             fail_key(S, j->key, e.code);
             delete j;
             continue;
         }
         g->E = get_engine(g->h, prec, g->stream);
+        if (S->opts.use_graph) {     // capture the block graphs now, not on the first request
+            batch_prepare_graph(g->E, PAMG_KRYLOV_FCG, S->opts.block_iters);
+            if (S->opts.single_path) single_prepare_graph(g->h, prec, S->opts.block_iters);
+        }
         g->bytes = g->h->info.device_bytes + batch_bytes(g->E);
         g->iter_bytes = batch_iteration_bytes(g->h, prec);
+        g->single_iter_bytes = single_iteration_bytes(g->h, prec);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->stats.bytes_in_use += g->bytes;
@@ -362,6 +381,27 @@ static void retire(pamg_server* S, ServeGroup* g) {
     batch_write_state(g->E, g->stream);
 }
 
+// The single-path request of a group after a block (state host copy current):
+// finished -> (FP32 V-cycle: accepted on its true residual, else restarted
+// from it, as in pamg_solve) result written and completed.
+static void retire_single(pamg_server* S, ServeGroup* g) {
+    const SolveState& st = single_state(g->h);
+    if (!st.done) return;
+    ServeRequest* q = g->single;
+    double rel = -1.0;
+    if (st.done == 1 && S->opts.precision == PAMG_PREC_F32 && st.status == PAMG_OK) {
+        rel = single_true_relres(g->h, g->stream);
+        if (rel > st.tol && q->restarts < 10 && st.iter < st.maxit) {
+            q->restarts += 1;
+            single_restart(g->h, g->stream);   // the next block continues from it
+            return;
+        }
+    }
+    single_end(g->h, q->r.x_dev, g->stream);
+    complete(S, q, st.status, st.iter, st.bnorm > 0 ? st.rnorm / st.bnorm : 0.0, rel);
+    g->single = nullptr;
+}
+
 static void scheduler_tick(pamg_server* S) {
     ++S->tick;
     // 1. groups whose block has finished: account, retire finished columns
@@ -380,10 +420,26 @@ static void scheduler_tick(pamg_server* S) {
         retire(S, g);
         S->progressed = true;
     }
+    for (auto& kv : S->groups) {
+        ServeGroup* g = kv.second;
+        if (!g->single_in_flight) continue;
+        const hipError_t q = hipEventQuery(g->single_ev);
+        if (q == hipErrorNotReady) continue;
+        HIP_CHECK(q);
+        g->single_in_flight = false;
+        const int it_now = single_state(g->h).iter;
+        moved += (uint64_t)std::max(0, it_now - g->single_iter_before) * g->single_iter_bytes;
+        g->single_iter_before = it_now;
+        retire_single(S, g);
+        S->progressed = true;
+    }
     // 2. finished host phases become cached operators as the budget allows;
     //    waiting requests take free columns of cached operators
     admit_ready(S);
     std::map<ServeGroup*, int> loads;
+    std::map<uint64_t, int> waiting;     // pending requests per operator not yet placed
+    if (S->opts.single_path)
+        for (ServeRequest* q : S->pending) waiting[q->r.op_key] += 1;
     for (auto it = S->pending.begin(); it != S->pending.end();) {
         ServeRequest* q = *it;
         auto gi = S->groups.find(q->r.op_key);
@@ -398,6 +454,23 @@ static void scheduler_tick(pamg_server* S) {
             continue;
         }
         ServeGroup* g = gi->second;
+        if (S->opts.single_path && g->active == 0 && waiting[g->key] < S->opts.batch_from) {
+            // few requests for this operator and no batch running: one at a
+            // time on the single-right-hand-side solver (its iterations move
+            // about a sixth of the bytes of a 16-column batched iteration)
+            if (g->single || g->single_in_flight) {
+                ++it;
+                continue;
+            }
+            single_begin(g->h, q->r.b_dev, q->r.tol, q->r.maxit > 0 ? q->r.maxit : 1000, g->stream);
+            g->single = q;
+            g->single_iter_before = 0;
+            waiting[g->key] -= 1;
+            q->t_admit = Clock::now();
+            it = S->pending.erase(it);
+            S->progressed = true;
+            continue;
+        }
         if (g->active >= kW || g->in_flight) {   // joins happen between blocks
             ++it;
             continue;
@@ -407,6 +480,7 @@ static void scheduler_tick(pamg_server* S) {
         g->col[c] = q;
         g->active += 1;
         loads[g] |= 1 << c;
+        if (S->opts.single_path) waiting[g->key] -= 1;
         q->t_admit = Clock::now();
         it = S->pending.erase(it);
     }
@@ -436,6 +510,16 @@ static void scheduler_tick(pamg_server* S) {
     uint64_t blocks = 0;
     for (auto& kv : S->groups) {
         ServeGroup* g = kv.second;
+        if (!g->single || g->single_in_flight) continue;
+        single_block(g->h, S->opts.precision, k, S->opts.use_graph != 0, g->stream);
+        HIP_CHECK(hipEventRecord(g->single_ev, g->stream));
+        g->single_in_flight = true;
+        g->last_used = S->tick;
+        ++blocks;
+        S->progressed = true;
+    }
+    for (auto& kv : S->groups) {
+        ServeGroup* g = kv.second;
         if (g->in_flight || g->active == 0 || batch_state_host(g->E).all_done) continue;
         for (int c = 0; c < kW; ++c) g->iter_before[c] = batch_state_host(g->E).col[c].iter;
         batch_run_block(g->E, PAMG_KRYLOV_FCG, k, S->opts.use_graph != 0, g->stream);
@@ -450,7 +534,7 @@ static void scheduler_tick(pamg_server* S) {
     S->stats.blocks += blocks;
     S->stats.algorithmic_bytes += moved;
     int active = 0;
-    for (auto& kv : S->groups) active += kv.second->active;
+    for (auto& kv : S->groups) active += kv.second->active + (kv.second->single ? 1 : 0);
     S->stats.active_columns = active;
     S->stats.pending = (int32_t)S->pending.size();
 }
@@ -465,7 +549,7 @@ static void scheduler_main(pamg_server* S) {
                 // a finished host phase (requests waiting on a setup cannot run)
                 bool busy = false;
                 for (auto& kv : S->groups)
-                    if (kv.second->active) busy = true;
+                    if (!kv.second->idle()) busy = true;
                 bool waiting_only = true;
                 for (ServeRequest* q : S->pending)
                     if (!S->setups.count(q->r.op_key)) waiting_only = false;
@@ -525,6 +609,7 @@ int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
         if (S->opts.block_iters < 2) S->opts.block_iters = 2;
         if (S->opts.block_iters & 1) S->opts.block_iters += 1;
         if (S->opts.precision != PAMG_PREC_F32) S->opts.precision = PAMG_PREC_F64;
+        if (S->opts.batch_from <= 0) S->opts.batch_from = 4;
         if (S->opts.hbm_budget_bytes == 0) throw pamg::Error(PAMG_E_INVALID, "zero HBM budget");
         HIP_CHECK(hipGetDevice(&S->device));
         S->stats.hbm_budget_bytes = S->opts.hbm_budget_bytes;
@@ -597,9 +682,9 @@ int pamg_server_destroy(pamg_server* S) {
         for (auto& kv : S->groups) {
             (void)hipStreamSynchronize(kv.second->stream);
             pamg_hierarchy_destroy(kv.second->h);
-            (void)hipEventDestroy(kv.second->ev);
-            (void)hipStreamDestroy(kv.second->stream);
+            release_streams(kv.second);
             for (auto* q : kv.second->col) delete q;
+            delete kv.second->single;
             delete kv.second;
         }
         delete S;

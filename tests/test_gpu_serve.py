@@ -9,6 +9,9 @@
   still completes correctly; an operator larger than the budget is refused;
 * a zero right-hand side completes with x = 0;
 * graph-replayed blocks give bitwise the results of direct launches;
+* with the single-right-hand-side path on, every result is bitwise that of
+  pamg_solve or of a one-column batched solve (the path depends on the mix),
+  and a request alone takes the single path;
 * the host phase of a new operator's setup runs beside the solving of
   cached operators (their requests finish first).
 """
@@ -121,6 +124,49 @@ def test_fp64_vcycle_server(ops):
         assert done[tag].status == pamg.OK and abs(done[tag].iterations - it_or) <= 1
         if done[tag].iterations == it_or:
             assert np.linalg.norm(xs[tag] - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+@pytest.mark.parametrize("prec,graph,batch_from", [(pamg.PREC_F32, 0, 100), (pamg.PREC_F64, 0, 4),
+                                                   (pamg.PREC_F32, 1, 4), (pamg.PREC_F64, 1, 100)])
+def test_single_path_results(ops, prec, graph, batch_from):
+    # with single_path, an operator's requests run one at a time on the
+    # single-right-hand-side solver while fewer than batch_from are waiting:
+    # every result is bitwise either that of pamg_solve (same tolerance, maxit
+    # and precision) or that of a one-column batched solve, whichever path the
+    # mix gave it; with a threshold above the request count nothing is batched
+    reqs = make_requests(ops, 24, seed=13)
+    reqs.append((24, 2, np.zeros(ops[2].n)))
+    xs, done, stats = serve(ops, reqs, single_path=1, batch_from=batch_from, precision=prec, use_graph=graph)
+    assert stats.completed == 25 and stats.rejected == 0
+    H = {k: pamg.Hierarchy(A, build_f32=1) for k, A in ops.items()}
+    paths = {"single": 0, "batch": 0}
+    for tag, k, b in reqs:
+        c = done[tag]
+        assert c.status == pamg.OK, (tag, c.status)
+        if tag == 24:
+            assert c.iterations == 0 and not xs[tag].any()
+            continue
+        rel = np.linalg.norm(b - ops[k].to_scipy() @ xs[tag]) / np.linalg.norm(b)
+        assert rel <= (1e-6 if prec == pamg.PREC_F32 else 2e-6), (tag, rel)
+        x1 = torch.zeros(ops[k].n, dtype=torch.float64, device="cuda:0")
+        inf1 = H[k].solve(dev(b), x1, tol=1e-6, maxit=1000, precision=prec)
+        X = torch.zeros((1, ops[k].n), dtype=torch.float64, device="cuda:0")
+        infb = H[k].solve_batch(dev(b[None, :]), X, tol=1e-6, precision=prec)
+        if np.array_equal(x1.cpu().numpy().view(np.uint64), xs[tag].view(np.uint64)):
+            assert c.iterations == inf1.iterations
+            paths["single"] += 1
+        else:
+            assert np.array_equal(X[0].cpu().numpy().view(np.uint64), xs[tag].view(np.uint64)), tag
+            assert c.iterations == infb[0].iterations
+            paths["batch"] += 1
+    if batch_from > len(reqs):
+        assert paths["batch"] == 0, paths
+    # a request alone on the server always takes the single path
+    tag, k, b = reqs[0]
+    xa, da, _ = serve(ops, [(tag, k, b)], single_path=1, batch_from=batch_from, precision=prec, use_graph=graph)
+    x1 = torch.zeros(ops[k].n, dtype=torch.float64, device="cuda:0")
+    H[k].solve(dev(b), x1, tol=1e-6, maxit=1000, precision=prec)
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), xa[tag].view(np.uint64))
 
 
 def test_tiny_budget_queues_and_evicts(ops):
