@@ -389,9 +389,9 @@ static void retire_single(pamg_server* S, ServeGroup* g) {
     if (!st.done) return;
     ServeRequest* q = g->single;
     double rel = -1.0;
-    if (st.done == 1 && S->opts.precision == PAMG_PREC_F32 && st.status == PAMG_OK) {
+    if (st.done == 1 && S->opts.precision == PAMG_PREC_F32) {
         rel = single_true_relres(g->h, g->stream);
-        if (rel > st.tol && q->restarts < 10 && st.iter < st.maxit) {
+        if (st.status == PAMG_OK && rel > st.tol && q->restarts < 10 && st.iter < st.maxit) {
             q->restarts += 1;
             single_restart(g->h, g->stream);   // the next block continues from it
             return;

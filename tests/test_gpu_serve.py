@@ -152,11 +152,15 @@ def test_single_path_results(ops, prec, graph, batch_from):
         inf1 = H[k].solve(dev(b), x1, tol=1e-6, maxit=1000, precision=prec)
         X = torch.zeros((1, ops[k].n), dtype=torch.float64, device="cuda:0")
         infb = H[k].solve_batch(dev(b[None, :]), X, tol=1e-6, precision=prec)
+        xb = X[0].cpu().numpy()
+        if inf1.iterations == infb[0].iterations:
+            # the two solvers agree to rounding when their iteration counts do
+            assert np.linalg.norm(x1.cpu().numpy() - xb) <= 1e-8 * np.linalg.norm(xb), tag
         if np.array_equal(x1.cpu().numpy().view(np.uint64), xs[tag].view(np.uint64)):
             assert c.iterations == inf1.iterations
             paths["single"] += 1
         else:
-            assert np.array_equal(X[0].cpu().numpy().view(np.uint64), xs[tag].view(np.uint64)), tag
+            assert np.array_equal(xb.view(np.uint64), xs[tag].view(np.uint64)), tag
             assert c.iterations == infb[0].iterations
             paths["batch"] += 1
     if batch_from > len(reqs):
