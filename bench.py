@@ -101,6 +101,8 @@ def main() -> int:
                     help="serving: a request alone on its operator runs on the single-right-hand-side solver")
     ap.add_argument("--batch-from", type=int, default=4,
                     help="serving: waiting requests of one operator from which they are batched")
+    ap.add_argument("--setup-workers", type=int, default=4,
+                    help="serving: host phases of new operators built at once")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--agg-steps", type=int, default=1,
                     help="aggregate-size composition: keep every n-th pairwise level (aggregates up to 2^n)")
@@ -493,7 +495,8 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     log(f"{args.requests} right-hand sides in {time.perf_counter() - t0:.1f}s")
     budget = int(args.budget_gib * (1 << 30))
     S = pamg.Server(hbm_budget_bytes=budget, block_iters=4, precision=pamg.PREC_F32, use_graph=1,
-                    single_path=args.single_path, batch_from=args.batch_from)
+                    single_path=args.single_path, batch_from=args.batch_from,
+                    setup_workers=args.setup_workers)
 
     def wait_for(count, what):
         comps = []
@@ -586,7 +589,7 @@ def bench_serve(args, torch, np, pamg, log) -> int:
                                f"in [24, 160], lognormal sigma=1 cell coefficients); U[-1,1] right-hand sides; "
                                f"FP32 V-cycle / FP64 FCG, accepted on the true residual",
                    "hbm_budget_gib": args.budget_gib, "block_iters": 4, "single_path": args.single_path,
-                   "batch_from": args.batch_from},
+                   "batch_from": args.batch_from, "setup_workers": args.setup_workers},
         "lambda_per_s": round(lam, 2),
         "closed_loop_capacity_per_s": round(capacity, 2),
         "open_loop_rate_per_s": round(len(comps) / wall, 2),

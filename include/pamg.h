@@ -281,7 +281,9 @@ typedef struct {
                                     bitwise independent of the mix. */
     int32_t batch_from;          /* with single_path: waiting requests of one operator from which
                                     they go to the batch engine (<= 0: 4) */
-    int32_t reserved[5];
+    int32_t setup_workers;       /* threads running host phases of new operators at once, each with
+                                    an equal share of the host cores (<= 0: 1; at most 16) */
+    int32_t reserved[4];
 } pamg_server_opts;
 
 typedef struct {

@@ -59,7 +59,7 @@ class pamg_hier_info(C.Structure):
 class pamg_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("block_iters", C.c_int32), ("precision", C.c_int32),
                 ("use_graph", C.c_int32), ("single_path", C.c_int32), ("batch_from", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("setup_workers", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class pamg_request(C.Structure):
@@ -338,7 +338,7 @@ class Server:
     completions are polled."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32,
-                 use_graph: int = 0, single_path: int = 0, batch_from: int = 4):
+                 use_graph: int = 0, single_path: int = 0, batch_from: int = 4, setup_workers: int = 1):
         o = pamg_server_opts()
         _check(lib().pamg_server_opts_default(C.byref(o)), "pamg_server_opts_default")
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -347,6 +347,7 @@ class Server:
         o.use_graph = int(use_graph)
         o.single_path = int(single_path)
         o.batch_from = int(batch_from)
+        o.setup_workers = int(setup_workers)
         h = C.c_void_p()
         _check(lib().pamg_server_create(C.byref(o), C.byref(h)), "pamg_server_create")
         self._h = h

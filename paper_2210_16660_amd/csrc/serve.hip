@@ -94,7 +94,7 @@ struct pamg_server {
     std::vector<pamg_completion> done;               // guarded by mu
     pamg_server_stats stats{};                       // guarded by mu (copied out)
     // setup worker
-    std::thread setup_th;
+    std::vector<std::thread> setup_th;               // setup workers
     std::condition_variable setup_cv;
     std::deque<pamg::SetupJob*> setup_queue;         // guarded by mu
     bool sched_done = false;                         // guarded by mu: scheduler thread has ended
@@ -304,7 +304,8 @@ static void admit_ready(pamg_server* S) {
     }
 }
 
-static void setup_main(pamg_server* S) {
+static void setup_main(pamg_server* S, int threads) {
+    set_num_threads(threads);        // this worker's share of the host cores
     for (;;) {
         SetupJob* j = nullptr;
         {
@@ -610,12 +611,17 @@ int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
         if (S->opts.block_iters & 1) S->opts.block_iters += 1;
         if (S->opts.precision != PAMG_PREC_F32) S->opts.precision = PAMG_PREC_F64;
         if (S->opts.batch_from <= 0) S->opts.batch_from = 4;
+        if (S->opts.setup_workers <= 0) S->opts.setup_workers = 1;
+        if (S->opts.setup_workers > 16) S->opts.setup_workers = 16;
         if (S->opts.hbm_budget_bytes == 0) throw pamg::Error(PAMG_E_INVALID, "zero HBM budget");
         HIP_CHECK(hipGetDevice(&S->device));
         S->stats.hbm_budget_bytes = S->opts.hbm_budget_bytes;
         pamg_server* raw = S.release();
         raw->th = std::thread(pamg::scheduler_main, raw);
-        raw->setup_th = std::thread(pamg::setup_main, raw);
+        const int workers = raw->opts.setup_workers;
+        const int cores = pamg::num_threads();
+        for (int w = 0; w < workers; ++w)
+            raw->setup_th.emplace_back(pamg::setup_main, raw, std::max(1, cores / workers));
         *out = raw;
         return PAMG_OK;
     });
@@ -674,7 +680,8 @@ int pamg_server_destroy(pamg_server* S) {
             S->sched_done = true;
             S->setup_cv.notify_all();
         }
-        if (S->setup_th.joinable()) S->setup_th.join();
+        for (auto& t : S->setup_th)
+            if (t.joinable()) t.join();
         for (auto& kv : S->setups) delete kv.second;     // every job not yet admitted or failed
         // outstanding requests (only after a fatal error) are dropped
         for (auto* q : S->pending) delete q;

@@ -13,7 +13,8 @@
   pamg_solve or of a one-column batched solve (the path depends on the mix),
   and a request alone takes the single path;
 * the host phase of a new operator's setup runs beside the solving of
-  cached operators (their requests finish first).
+  cached operators (their requests finish first), and several setup workers
+  give bitwise the results of one.
 """
 import time
 
@@ -113,6 +114,18 @@ def test_graph_replay_server_matches_direct_launches(ops):
     for tag, k, b in reqs:
         assert dg[tag].status == pamg.OK and dg[tag].iterations == dd[tag].iterations
         assert np.array_equal(xg[tag].view(np.uint64), xd[tag].view(np.uint64))
+
+
+def test_setup_workers_give_the_same_results(ops):
+    # host phases built by several workers at once (each with a share of the
+    # cores) give the same hierarchies: results bitwise those of one worker
+    reqs = make_requests(ops, 12, seed=17)
+    x1, d1, _ = serve(ops, reqs)
+    x4, d4, st = serve(ops, reqs, setup_workers=4)
+    assert st.setups == len(ops) and st.completed == 12
+    for tag, k, b in reqs:
+        assert d4[tag].status == pamg.OK and d4[tag].iterations == d1[tag].iterations
+        assert np.array_equal(x4[tag].view(np.uint64), x1[tag].view(np.uint64))
 
 
 def test_fp64_vcycle_server(ops):
