@@ -366,8 +366,13 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
 
 // ---------------------------------------------------------------- Krylov
 
-// p = z + beta_c p_old (p = z on a column's first iteration), q = A p, and
-// per-column partials of p.q and p.r.  Fixed shape (one lane per column).
+// p = z + beta_c p_old (p = z on a column's first iteration), q = A p as
+// A z + beta_c q_old (the same vector in exact arithmetic: only z is
+// gathered, one line per entry instead of two), and per-column partials of
+// p.q and p.r.  A column on its first iteration, or finished, takes q = A z
+// (an idle column's q stays bounded).  q holds q_old on entry; each element
+// is read before it is overwritten, by the same lane.  Fixed shape (one lane
+// per column).
 static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                        const double* __restrict__ av, const double* __restrict__ z,
                                                        const double* __restrict__ p_old, double* __restrict__ p_new,
@@ -379,6 +384,7 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
     __shared__ double s_pq[GPB][kW], s_pr[GPB][kW];
     const int g = threadIdx.x / kW, lane = threadIdx.x % kW;
     const bool first = st->col[lane].first != 0;
+    const bool fresh = first || st->col[lane].done != 0;
     const double beta = st->col[lane].beta;
     const TileWalk w = unit_walk(n, GPB, g);
     double pq = 0.0, pr = 0.0;
@@ -389,29 +395,23 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
         constexpr int U = 8;
         for (; k + U <= ke; k += U) {
             int c[U];
-            double a[U], zc[U], pc[U];
+            double a[U], zc[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) c[u] = ci[k + u];
 #pragma unroll
             for (int u = 0; u < U; ++u) a[u] = av[k + u];
 #pragma unroll
             for (int u = 0; u < U; ++u) zc[u] = z[(size_t)c[u] * kW + lane];
-            if (!first) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) pc[u] = p_old[(size_t)c[u] * kW + lane];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) s += a[u] * (first ? zc[u] : zc[u] + beta * pc[u]);
+            for (int u = 0; u < U; ++u) s += a[u] * zc[u];
         }
-        for (; k < ke; ++k) {
-            const size_t e = (size_t)ci[k] * kW + lane;
-            s += av[k] * (first ? z[e] : z[e] + beta * p_old[e]);
-        }
+        for (; k < ke; ++k) s += av[k] * z[(size_t)ci[k] * kW + lane];
         const size_t e = (size_t)i * kW + lane;
         const double pi = first ? z[e] : z[e] + beta * p_old[e];
+        const double qi = fresh ? s : s + beta * q[e];
         p_new[e] = pi;
-        q[e] = s;
-        pq += pi * s;
+        q[e] = qi;
+        pq += pi * qi;
         pr += pi * r[e];
     }
     s_pq[g][lane] = pq;
