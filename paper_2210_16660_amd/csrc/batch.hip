@@ -176,7 +176,7 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
                            E->r[l - 1], false, V.dinv[l - 1], V.p[l - 1], (T*)E->zp[l - 1], done, s);
     }
     const DevLevelIdx& I0 = h->idx[0];
-    const int g = unit_grid(I0.n, kBlock / kW);
+    const int g = unit_grid(I0.n, up0_rows_per_block<T>());
     hipLaunchKernelGGL((kb_up0<T>), dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
                        (const T*)V.v[0], (const T*)E->zp[0], (const double*)E->R, (const T*)V.dinv[0], E->Z, dv,
                        E->partial, done);
@@ -191,11 +191,12 @@ static void enqueue_iteration_b(BatchEngine* E, DevVals<T>& V, int krylov, int p
     const int cnt = enqueue_vcycle_b<T>(E, V, dv, done, s);
     hipLaunchKernelGGL(kb_fin_beta, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, cnt);
     const DevLevelIdx& I0 = h->idx[0];
-    const int g = unit_grid(I0.n, kBlock / kW);
-    hipLaunchKernelGGL(kb_krylov_pq, dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
+    const int gk = unit_grid(I0.n, kKrylovRowsPerBlock);
+    hipLaunchKernelGGL(kb_krylov_pq, dim3(gk), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
                        (const double*)h->f64.v[0], (const double*)E->Z, (const double*)E->P[parity], E->P[1 - parity],
                        E->Q, (const double*)E->R, (const BatchState*)E->st, E->partial, done);
-    hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, g);
+    hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, gk);
+    const int g = unit_grid(I0.n, kBlock / kW);
     hipLaunchKernelGGL(kb_update, dim3(g), dim3(kBlock), 0, s, I0.n, E->X, E->R, (const double*)E->P[1 - parity],
                        (const double*)E->Q, (const BatchState*)E->st, E->partial, done);
     hipLaunchKernelGGL(kb_fin_norm, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, g);

@@ -197,8 +197,14 @@ static __global__ __launch_bounds__(kBlock) void kb_up(int n, const int* __restr
 }
 
 // Level-0 up-sweep: z = zp + D^-1 (r - A zp) written in FP64, with per-column
-// partials of z . dv.  Fixed shape (one lane per column, unroll 8): its
-// partial sums must not depend on tuning.
+// partials of z . dv.  Fixed shape, whatever the tuning (its partial sums
+// must not depend on it): unroll 8 and 16-byte loads, i.e. kUp0Cols columns
+// per lane.
+template <typename T>
+constexpr int up0_cols() { return std::is_same<T, double>::value ? 2 : 4; }
+template <typename T>
+constexpr int up0_rows_per_block() { return kBlock / (kW / up0_cols<T>()); }
+
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const T* __restrict__ av, const T* __restrict__ zp,
@@ -206,20 +212,30 @@ static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __rest
                                                  double* __restrict__ z_out, const double* __restrict__ dv,
                                                  double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
-    constexpr int GPB = kBlock / kW;
+    constexpr int CPL = up0_cols<T>(), LPR = kW / CPL, GPB = kBlock / LPR;
     __shared__ double s_dot[GPB][kW];
-    const int g = threadIdx.x / kW, lane = threadIdx.x % kW;
+    const int g = threadIdx.x / LPR, col0 = (threadIdx.x % LPR) * CPL;
     const TileWalk w = unit_walk(n, GPB, g);
-    double dot = 0.0;
+    double dot[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) dot[q] = 0.0;
     for (int i = w.first; i < w.end; i += w.stride) {
-        T s[1] = {0};
-        row_accumulate<8, 1, T, T>(rp[i], rp[i + 1], ci, av, zp, lane, s);
-        const size_t e = (size_t)i * kW + lane;
-        const T z = zp[e] + dinv[i] * ((T)r[e] - s[0]);
-        z_out[e] = (double)z;
-        dot += (double)z * dv[e];
+        T s[CPL];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) s[q] = 0;
+        row_accumulate<8, CPL, T, T>(rp[i], rp[i + 1], ci, av, zp, col0, s);
+        const size_t e = (size_t)i * kW + col0;
+        const Vec<T, CPL> zv = vload<T, CPL>(zp + e);
+        const T di = dinv[i];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const T z = zv.v[q] + di * ((T)r[e + q] - s[q]);
+            z_out[e + q] = (double)z;
+            dot[q] += (double)z * dv[e + q];
+        }
     }
-    s_dot[g][lane] = dot;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) s_dot[g][col0 + q] = dot[q];
     __syncthreads();
     if (threadIdx.x < kW) {
         double t = 0.0;
@@ -371,8 +387,11 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
 // gathered, one line per entry instead of two), and per-column partials of
 // p.q and p.r.  A column on its first iteration, or finished, takes q = A z
 // (an idle column's q stays bounded).  q holds q_old on entry; each element
-// is read before it is overwritten, by the same lane.  Fixed shape (one lane
-// per column).
+// is read before it is overwritten, by the same lane.  Fixed shape: unroll 8,
+// two columns per lane.
+constexpr int kKrylovCols = 2;                                   // columns per lane (16-byte loads)
+constexpr int kKrylovRowsPerBlock = kBlock / (kW / kKrylovCols);
+
 static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                        const double* __restrict__ av, const double* __restrict__ z,
                                                        const double* __restrict__ p_old, double* __restrict__ p_new,
@@ -380,42 +399,45 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
                                                        const BatchState* __restrict__ st, double* __restrict__ partial,
                                                        const int* __restrict__ done) {
     if (*done) return;
-    constexpr int GPB = kBlock / kW;
+    constexpr int CPL = kKrylovCols, LPR = kW / CPL, GPB = kBlock / LPR;
     __shared__ double s_pq[GPB][kW], s_pr[GPB][kW];
-    const int g = threadIdx.x / kW, lane = threadIdx.x % kW;
-    const bool first = st->col[lane].first != 0;
-    const bool fresh = first || st->col[lane].done != 0;
-    const double beta = st->col[lane].beta;
-    const TileWalk w = unit_walk(n, GPB, g);
-    double pq = 0.0, pr = 0.0;
-    for (int i = w.first; i < w.end; i += w.stride) {
-        double s = 0.0;
-        const int kb = rp[i], ke = rp[i + 1];
-        int k = kb;
-        constexpr int U = 8;
-        for (; k + U <= ke; k += U) {
-            int c[U];
-            double a[U], zc[U];
+    const int g = threadIdx.x / LPR, col0 = (threadIdx.x % LPR) * CPL;
+    bool first[CPL], fresh[CPL];
+    double beta[CPL], pq[CPL], pr[CPL];
 #pragma unroll
-            for (int u = 0; u < U; ++u) c[u] = ci[k + u];
-#pragma unroll
-            for (int u = 0; u < U; ++u) a[u] = av[k + u];
-#pragma unroll
-            for (int u = 0; u < U; ++u) zc[u] = z[(size_t)c[u] * kW + lane];
-#pragma unroll
-            for (int u = 0; u < U; ++u) s += a[u] * zc[u];
-        }
-        for (; k < ke; ++k) s += av[k] * z[(size_t)ci[k] * kW + lane];
-        const size_t e = (size_t)i * kW + lane;
-        const double pi = first ? z[e] : z[e] + beta * p_old[e];
-        const double qi = fresh ? s : s + beta * q[e];
-        p_new[e] = pi;
-        q[e] = qi;
-        pq += pi * qi;
-        pr += pi * r[e];
+    for (int c = 0; c < CPL; ++c) {
+        const BatchCol& C = st->col[col0 + c];
+        first[c] = C.first != 0;
+        fresh[c] = first[c] || C.done != 0;
+        beta[c] = C.beta;
+        pq[c] = 0.0;
+        pr[c] = 0.0;
     }
-    s_pq[g][lane] = pq;
-    s_pr[g][lane] = pr;
+    const TileWalk w = unit_walk(n, GPB, g);
+    for (int i = w.first; i < w.end; i += w.stride) {
+        double s[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) s[c] = 0.0;
+        row_accumulate<8, CPL, double, double>(rp[i], rp[i + 1], ci, av, z, col0, s);
+        const size_t e = (size_t)i * kW + col0;
+        const Vec<double, CPL> zi = vload<double, CPL>(z + e), po = vload<double, CPL>(p_old + e);
+        const Vec<double, CPL> qo = vload<double, CPL>(q + e), ri = vload<double, CPL>(r + e);
+        Vec<double, CPL> pn, qn;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            pn.v[c] = first[c] ? zi.v[c] : zi.v[c] + beta[c] * po.v[c];
+            qn.v[c] = fresh[c] ? s[c] : s[c] + beta[c] * qo.v[c];
+            pq[c] += pn.v[c] * qn.v[c];
+            pr[c] += pn.v[c] * ri.v[c];
+        }
+        vstore<double, CPL>(p_new + e, pn);
+        vstore<double, CPL>(q + e, qn);
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        s_pq[g][col0 + c] = pq[c];
+        s_pr[g][col0 + c] = pr[c];
+    }
     __syncthreads();
     if (threadIdx.x < kW) {
         double a = 0.0, b = 0.0;
