@@ -23,10 +23,10 @@ static void require_l1_smoother(const pamg_hierarchy* h) {
 }
 
 // kernel variants tried by the autotuner: unroll depth (entries of a row
-// whose loads are in flight together) x columns per lane
-constexpr int kNumVariants = 10;
+// whose loads are in flight together) x columns per lane (1, 2 or 4)
+constexpr int kNumVariants = 15;
 static inline int variant_unroll(int v) { return 1 << (v % 5); }
-static inline int variant_cpl(int v) { return v < 5 ? 1 : 2; }
+static inline int variant_cpl(int v) { return v < 5 ? 1 : v < 10 ? 2 : 4; }
 
 template <typename F>
 static void with_variant(int v, F&& f) {
@@ -41,7 +41,12 @@ static void with_variant(int v, F&& f) {
         case 6: f(integral_constant<int, 2>{}, integral_constant<int, 2>{}); break;
         case 7: f(integral_constant<int, 4>{}, integral_constant<int, 2>{}); break;
         case 8: f(integral_constant<int, 8>{}, integral_constant<int, 2>{}); break;
-        default: f(integral_constant<int, 16>{}, integral_constant<int, 2>{}); break;
+        case 9: f(integral_constant<int, 16>{}, integral_constant<int, 2>{}); break;
+        case 10: f(integral_constant<int, 1>{}, integral_constant<int, 4>{}); break;
+        case 11: f(integral_constant<int, 2>{}, integral_constant<int, 4>{}); break;
+        case 12: f(integral_constant<int, 4>{}, integral_constant<int, 4>{}); break;
+        case 13: f(integral_constant<int, 8>{}, integral_constant<int, 4>{}); break;
+        default: f(integral_constant<int, 16>{}, integral_constant<int, 4>{}); break;
     }
 }
 
@@ -600,8 +605,8 @@ void batch_config(pamg_hierarchy* h, int prec, int32_t* cfg) {
     for (int l = 0; l < L; ++l) {
         cfg[4 * l + 0] = variant_unroll(E->cfg_down[l]);
         cfg[4 * l + 1] = variant_cpl(E->cfg_down[l]);
-        cfg[4 * l + 2] = l > 0 ? variant_unroll(E->cfg_up[l]) : 8;
-        cfg[4 * l + 3] = l > 0 ? variant_cpl(E->cfg_up[l]) : 1;
+        cfg[4 * l + 2] = l > 0 ? variant_unroll(E->cfg_up[l]) : 8;     // level 0: the fixed-shape kb_up0
+        cfg[4 * l + 3] = l > 0 ? variant_cpl(E->cfg_up[l]) : (prec == PAMG_PREC_F32 ? up0_cols<float>() : up0_cols<double>());
     }
 }
 

@@ -49,10 +49,15 @@ __device__ __forceinline__ Vec<T, C> vload(const T* p) {
         const V2 t = *reinterpret_cast<const V2*>(p);
         r.v[0] = t.x;
         r.v[1] = t.y;
-    } else {
-        static_assert(C == 4 && std::is_same<T, float>::value, "4 columns per lane only for float");
+    } else if constexpr (std::is_same<T, float>::value) {
+        static_assert(C == 4, "1, 2 or 4 columns per lane");
         const float4 t = *reinterpret_cast<const float4*>(p);
         r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    } else {
+        static_assert(C == 4, "1, 2 or 4 columns per lane");
+        const double2 t0 = *reinterpret_cast<const double2*>(p);
+        const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+        r.v[0] = t0.x; r.v[1] = t0.y; r.v[2] = t1.x; r.v[3] = t1.y;
     }
     return r;
 }
@@ -67,10 +72,16 @@ __device__ __forceinline__ void vstore(T* p, const Vec<T, C>& a) {
         t.x = a.v[0];
         t.y = a.v[1];
         *reinterpret_cast<V2*>(p) = t;
-    } else {
+    } else if constexpr (std::is_same<T, float>::value) {
         float4 t;
         t.x = a.v[0]; t.y = a.v[1]; t.z = a.v[2]; t.w = a.v[3];
         *reinterpret_cast<float4*>(p) = t;
+    } else {
+        double2 t0, t1;
+        t0.x = a.v[0]; t0.y = a.v[1];
+        t1.x = a.v[2]; t1.y = a.v[3];
+        *reinterpret_cast<double2*>(p) = t0;
+        *reinterpret_cast<double2*>(p + 2) = t1;
     }
 }
 

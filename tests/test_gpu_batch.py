@@ -187,4 +187,4 @@ def test_batch_autotuner_choices(built):
     cfg = H.batch_config(pamg.PREC_F64)
     assert len(cfg) == H.levels - 1
     for du, dc, uu, uc in cfg:
-        assert du in (1, 2, 4, 8, 16) and uu in (1, 2, 4, 8, 16) and dc in (1, 2) and uc in (1, 2)
+        assert du in (1, 2, 4, 8, 16) and uu in (1, 2, 4, 8, 16) and dc in (1, 2, 4) and uc in (1, 2, 4)
