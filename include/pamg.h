@@ -205,7 +205,7 @@ int pamg_debug_apply_batch(pamg_hierarchy *h, int32_t op, int32_t precision, con
  * = down-sweep unroll (1..16), down-sweep columns per lane (1, 2 or 4),
  * up-sweep unroll, up-sweep columns per lane, for l = 0 .. levels-2 (cfg holds
  * 4*(levels-1) entries; level 0's up-sweep is a fixed shape, reported as
- * unroll 8 with 2 (FP64) or 4 (FP32) columns per lane). */
+ * unroll 8 with 4 columns per lane). */
 int pamg_batch_config(pamg_hierarchy *h, int32_t precision, int32_t *cfg);
 
 /* Single operators of the V-cycle, for parity checks.  Vectors are FP64 in

@@ -209,10 +209,10 @@ static __global__ __launch_bounds__(kBlock) void kb_up(int n, const int* __restr
 
 // Level-0 up-sweep: z = zp + D^-1 (r - A zp) written in FP64, with per-column
 // partials of z . dv.  Fixed shape, whatever the tuning (its partial sums
-// must not depend on it): unroll 8 and 16-byte loads, i.e. kUp0Cols columns
-// per lane.
+// must not depend on it): unroll 8 and four columns per lane (one 16-byte
+// load in FP32, two in FP64).
 template <typename T>
-constexpr int up0_cols() { return std::is_same<T, double>::value ? 2 : 4; }
+constexpr int up0_cols() { return 4; }
 template <typename T>
 constexpr int up0_rows_per_block() { return kBlock / (kW / up0_cols<T>()); }
 
@@ -399,8 +399,8 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
 // p.q and p.r.  A column on its first iteration, or finished, takes q = A z
 // (an idle column's q stays bounded).  q holds q_old on entry; each element
 // is read before it is overwritten, by the same lane.  Fixed shape: unroll 8,
-// two columns per lane.
-constexpr int kKrylovCols = 2;                                   // columns per lane (16-byte loads)
+// four columns per lane (two 16-byte loads).
+constexpr int kKrylovCols = 4;
 constexpr int kKrylovRowsPerBlock = kBlock / (kW / kKrylovCols);
 
 static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* __restrict__ rp, const int* __restrict__ ci,
