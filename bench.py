@@ -16,10 +16,12 @@ hierarchy setup is timed separately.  Prints one JSON line.
     python bench.py --mode reuse [--steps K]    (coefficient-only update of the
                     hierarchy for a second stretching ratio on the same mesh,
                     against a fresh setup; prints its own JSON line)
-    python bench.py --mode serve [--requests R] (serving stream: variable-
-                    coefficient 7-point operators from a pool of 64, Poisson
-                    arrivals at 0.7 x the closed-loop capacity; p50/p99
-                    latency and solves/s; prints its own JSON line)
+    python bench.py --mode serve [--requests R] [--serve-load F]
+                    [--single-path 0|1] [--batch-from B] [--setup-workers W]
+                    (serving stream: variable-coefficient 7-point operators
+                    from a pool of 64, a closed loop for the capacity, then
+                    Poisson arrivals at F (default 0.5) x that capacity;
+                    p50/p99 latency and solves/s; prints its own JSON line)
 
 The roofline "traffic" figure comes from profiles/traffic_q1_128.json (HBM
 bytes per launch from FETCH_SIZE/WRITE_SIZE counter runs, calibrated on a
