@@ -57,6 +57,7 @@ struct BatchEngine {
     void* zc = nullptr;                       // coarse result scratch (n_L x 16)
     double *X = nullptr, *R = nullptr, *Z = nullptr, *P[2] = {nullptr, nullptr}, *Q = nullptr, *B = nullptr,
            *Y = nullptr;
+    float* R32 = nullptr;                     // FP32 V-cycle: R rounded once per cycle for level 0
     double *partial = nullptr, *partial_b = nullptr;
     BatchState* st = nullptr;
     BatchState* st_host = nullptr;            // pinned
@@ -130,14 +131,33 @@ static void launch_up_b(const DevLevelIdx& I, const DevLevelIdx& F, int v, const
 }
 
 // z (E->Z) = B r (E->R), per column; partials of z . dv.  Returns their count.
+// The level-0 right-hand side as the V-cycle reads it: with the FP32 cycle,
+// R rounded to FP32 once (the kernels would round each load the same way),
+// so that its gathers move 64-byte lines instead of 128-byte ones.
+template <typename T>
+static const void* level0_rhs(BatchEngine* E, const int* done, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        const long long cnt = (long long)E->h->idx[0].n * kW;
+        hipLaunchKernelGGL(kb_narrow, dim3(vec_grid(cnt)), dim3(kBlock), 0, s, cnt, (const double*)E->R, E->R32,
+                           done);
+        return E->R32;
+    } else {
+        (void)done;
+        (void)s;
+        return E->R;
+    }
+}
+
 template <typename T>
 static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, const int* done, hipStream_t s) {
     pamg_hierarchy* h = E->h;
     const int L = h->L;
+    constexpr bool r0_f64 = std::is_same<T, double>::value;
+    const void* r0 = L > 0 ? level0_rhs<T>(E, done, s) : E->R;
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         if (l == 0)
-            launch_down_b<T>(I, E->cfg_down[0], V.vd[0], E->R, true, V.p[0], (T*)E->r[1], done, s);
+            launch_down_b<T>(I, E->cfg_down[0], V.vd[0], r0, r0_f64, V.p[0], (T*)E->r[1], done, s);
         else
             launch_down_b<T>(I, E->cfg_down[l], V.vd[l], E->r[l], false, V.p[l], (T*)E->r[l + 1], done, s);
     }
@@ -174,7 +194,7 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
         const DevLevelIdx& I = h->idx[l];
         const DevLevelIdx& Fi = h->idx[l - 1];
         if (l - 1 == 0)
-            launch_up_b<T>(I, Fi, E->cfg_up[l], V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l], E->R, true,
+            launch_up_b<T>(I, Fi, E->cfg_up[l], V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l], r0, r0_f64,
                            V.dinv[0], V.p[0], (T*)E->zp[0], done, s);
         else
             launch_up_b<T>(I, Fi, E->cfg_up[l], V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l],
@@ -183,7 +203,7 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
     const DevLevelIdx& I0 = h->idx[0];
     const int g = unit_grid(I0.n, up0_rows_per_block<T>());
     hipLaunchKernelGGL((kb_up0<T>), dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
-                       (const T*)V.v[0], (const T*)E->zp[0], (const double*)E->R, (const T*)V.dinv[0], E->Z, dv,
+                       (const T*)V.v[0], (const T*)E->zp[0], (const T*)r0, (const T*)V.dinv[0], E->Z, dv,
                        E->partial, done);
     return g;
 }
@@ -241,13 +261,15 @@ static void autotune(BatchEngine* E, DevVals<T>& V, hipStream_t s) {
     const int* nodone = h->zero_flag;
     E->cfg_down.assign(L + 1, 2);              // unroll 4, one column per lane until tuned
     E->cfg_up.assign(L + 1, 2);
+    constexpr bool r0_f64 = std::is_same<T, double>::value;
+    const void* r0 = L > 0 ? level0_rhs<T>(E, nodone, s) : E->R;
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         float best = 1e30f;
         for (int v = 0; v < kNumVariants; ++v) {
             const float t = time_variant([&]() {
                 if (l == 0)
-                    launch_down_b<T>(I, v, V.vd[0], E->R, true, V.p[0], (T*)E->r[1], nodone, s);
+                    launch_down_b<T>(I, v, V.vd[0], r0, r0_f64, V.p[0], (T*)E->r[1], nodone, s);
                 else
                     launch_down_b<T>(I, v, V.vd[l], E->r[l], false, V.p[l], (T*)E->r[l + 1], nodone, s);
             }, s);
@@ -259,7 +281,7 @@ static void autotune(BatchEngine* E, DevVals<T>& V, hipStream_t s) {
         for (int v = 0; v < kNumVariants; ++v) {
             const float t = time_variant([&]() {
                 if (l - 1 == 0)
-                    launch_up_b<T>(I, Fi, v, V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l], E->R, true,
+                    launch_up_b<T>(I, Fi, v, V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l], r0, r0_f64,
                                    V.dinv[0], V.p[0], (T*)E->zp[0], nodone, s);
                 else
                     launch_up_b<T>(I, Fi, v, V.v[l], (const T*)E->zp[l], (const T*)E->r[l], V.dinv[l], E->r[l - 1],
@@ -289,6 +311,7 @@ static BatchEngine* create_engine(pamg_hierarchy* h, DevVals<T>& V, int prec, hi
     const size_t n0 = (size_t)h->idx[0].n * kW;
     E->X = balloc<double>(E.get(), n0, s);
     E->R = balloc<double>(E.get(), n0, s);
+    if (std::is_same<T, float>::value) E->R32 = balloc<float>(E.get(), n0, s);
     E->Z = balloc<double>(E.get(), n0, s);
     E->P[0] = balloc<double>(E.get(), n0, s);
     E->P[1] = balloc<double>(E.get(), n0, s);

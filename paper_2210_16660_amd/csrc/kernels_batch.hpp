@@ -219,7 +219,7 @@ constexpr int up0_rows_per_block() { return kBlock / (kW / up0_cols<T>()); }
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const T* __restrict__ av, const T* __restrict__ zp,
-                                                 const double* __restrict__ r, const T* __restrict__ dinv,
+                                                 const T* __restrict__ r, const T* __restrict__ dinv,
                                                  double* __restrict__ z_out, const double* __restrict__ dv,
                                                  double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
@@ -240,7 +240,7 @@ static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __rest
         const T di = dinv[i];
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
-            const T z = zv.v[q] + di * ((T)r[e + q] - s[q]);
+            const T z = zv.v[q] + di * (r[e + q] - s[q]);
             z_out[e + q] = (double)z;
             dot[q] += (double)z * dv[e + q];
         }
@@ -389,6 +389,14 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
                 zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
         }
     }
+}
+
+// FP64 -> FP32 copy of n x 16 values (the FP32 cycle's level-0 right-hand side).
+static __global__ __launch_bounds__(kBlock) void kb_narrow(long long cnt, const double* __restrict__ src,
+                                                    float* __restrict__ dst, const int* __restrict__ done) {
+    if (*done) return;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += stride) dst[i] = (float)src[i];
 }
 
 // ---------------------------------------------------------------- Krylov

@@ -119,7 +119,8 @@ static double ms_between(Clock::time_point a, Clock::time_point b) {
 // Hierarchy: per level index arrays, values and the restriction values (plus
 // their FP32 copies), vectors; coarse levels add at most 1.3x the finest
 // (pairwise coarsening), fixed buffers ~0.2 MB.  Engine: eight n x 16 FP64
-// vectors at level 0, two n_l x 16 vectors per level, 1.1 MB of partials.
+// vectors at level 0 (plus an FP32 copy of one with the FP32 cycle), two
+// n_l x 16 vectors per level, 1.1 MB of partials.
 static uint64_t dense_bytes(uint64_t nL, int prec) { return nL * nL * (prec == PAMG_PREC_F32 ? 12 : 8); }
 
 static uint64_t estimate_core(const pamg_csr& A, int prec) {
@@ -128,7 +129,8 @@ static uint64_t estimate_core(const pamg_csr& A, int prec) {
     const double s = prec == PAMG_PREC_F32 ? 4.0 : 8.0;
     double hier = cx * (nnz * (4 + 8 + 8) + n * 80) + 96.0 * n + (1 << 18);
     if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32);
-    const double engine = n * kW * 8 * 8 + 2.0 * cx * n * kW * s + 1.2 * (1 << 20);
+    const double engine = n * kW * 8 * 8 + (prec == PAMG_PREC_F32 ? n * kW * 4 : 0.0) + 2.0 * cx * n * kW * s +
+                          1.2 * (1 << 20);
     return (uint64_t)(hier + engine);
 }
 
