@@ -186,6 +186,26 @@ def test_single_path_results(ops, prec, graph, batch_from):
     assert np.array_equal(x1.cpu().numpy().view(np.uint64), xa[tag].view(np.uint64))
 
 
+@pytest.mark.parametrize("prec", [pamg.PREC_F32, pamg.PREC_F64])
+def test_admission_estimate_bounds_the_cached_bytes(ops, prec):
+    # the admission charge of an operator (hierarchy + 16-column engine, the
+    # FP32 engine with its FP32 copy of the level-0 right-hand side) is an
+    # upper bound of the bytes it holds once cached, and not a loose one
+    from workloads import q1_stretched
+    cases = [ops[0], ops[2], varcoef7(40, seed=91), q1_stretched(16, 1.05)]
+    for A in cases:
+        S = pamg.Server(precision=prec, single_path=1)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+        S.submit(1, A, dev(np.zeros(A.n)), x, tag=1)
+        d = wait_all(S, 1)
+        st = S.stats()
+        S.close()
+        assert d[1].status == pamg.OK and st.setups == 1
+        est = pamg.server_estimate_bytes(A, prec)
+        assert st.bytes_in_use <= est, (A.n, st.bytes_in_use, est)
+        assert st.bytes_in_use >= est // 16, (A.n, st.bytes_in_use, est)
+
+
 def test_tiny_budget_queues_and_evicts(ops):
     # room for about one operator at a time: requests for the others wait,
     # idle operators are evicted, everything still completes
