@@ -455,12 +455,13 @@ static __global__ __launch_bounds__(kCoarseThreads) void k_coarse(
 
 // ----------------------------------------------------------------------------
 // Coarsest level when it is large (a stalled coarsening can leave thousands of
-// rows): the same product and prolongation as k_coarse, spread over
-// ceil(nL / 64) workgroups.  A workgroup owns 64 rows; its four waves split
-// the columns j in four fixed ranges and meet in LDS (fixed order).  Reads of
-// the (symmetric) inverse are coalesced along the rows.
+// rows): the same product and prolongation as k_coarse, one wave per row.  The
+// inverse is symmetric, so row I is read along its length (coalesced, 64
+// consecutive columns per load) and the lanes' partial sums meet in a wave
+// butterfly (fixed order); ceil(nL / 4) workgroups of four waves, so even a
+// coarsest level of a few thousand rows spreads over the whole chip.
 constexpr int kCoarseRowsMin = 512;          // above this size the coarsest runs on many workgroups
-constexpr int kCoarseRowsPerBlock = 64;
+constexpr int kCoarseRowsPerBlock = kBlock / 64;
 inline int coarse_rows_grid(int nL) { return (nL + kCoarseRowsPerBlock - 1) / kCoarseRowsPerBlock; }
 
 template <typename T, typename RT, typename RTF, bool TO_OUT>
@@ -471,34 +472,35 @@ static __global__ __launch_bounds__(kBlock) void k_coarse_rows(
     double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
     const int* __restrict__ done) {
     if (*done) return;
-    __shared__ T s_part[kBlock / kCoarseRowsPerBlock][kCoarseRowsPerBlock];
-    constexpr int G = kBlock / kCoarseRowsPerBlock;
-    const int tid = threadIdx.x, g = tid / kCoarseRowsPerBlock, lt = tid % kCoarseRowsPerBlock;
-    const int I = blockIdx.x * kCoarseRowsPerBlock + lt;
-    const int j0 = (int)((long long)nL * g / G), j1 = (int)((long long)nL * (g + 1) / G);
+    __shared__ double s_dot[kCoarseRowsPerBlock];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int I = blockIdx.x * kCoarseRowsPerBlock + wave;
     T s = 0;
     if (I < nL) {
-#pragma unroll 8
-        for (int j = j0; j < j1; ++j) s += ainv[(size_t)j * nL + I] * (T)r[j];
+        const T* __restrict__ row = ainv + (size_t)I * nL;
+#pragma unroll 4
+        for (int j = lane; j < nL; j += 64) s += row[j] * (T)r[j];
     }
-    s_part[g][lt] = s;
-    __syncthreads();
-    if (tid < kCoarseRowsPerBlock) {          // one full wave
-        double dot = 0.0;
-        if (I < nL) {
-            T z = s_part[0][lt];
-            for (int q = 1; q < G; ++q) z += s_part[q][lt];
-            if constexpr (TO_OUT) {
+    const T z = wave_sum(s);
+    double dot = 0.0;
+    if (I < nL) {
+        if constexpr (TO_OUT) {
+            if (lane == 0) {
                 z_out[I] = (double)z;
                 dot = (double)z * dv[I];
-            } else {
-                for (int m = aggptr_f[I]; m < aggptr_f[I + 1]; ++m)
-                    zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
             }
+        } else {
+            for (int m = aggptr_f[I] + lane; m < aggptr_f[I + 1]; m += 64)
+                zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
         }
-        if constexpr (TO_OUT) {
-            dot = wave_sum(dot);
-            if (tid == 0) partial[blockIdx.x] = dot;
+    }
+    if constexpr (TO_OUT) {
+        if (lane == 0) s_dot[wave] = dot;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int q = 0; q < kCoarseRowsPerBlock; ++q) t += s_dot[q];
+            partial[blockIdx.x] = t;
         }
     }
 }
