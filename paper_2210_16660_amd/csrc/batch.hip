@@ -170,8 +170,8 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
         return 1;
     }
     const DevLevelIdx& F = h->idx[L - 1];
-    if (nL > kCoarseRowsMin) {
-        const dim3 g(coarse_rows_grid_b(nL));
+    if (nL > coarse_rows_min_b<T>()) {
+        const dim3 g(coarse_rows_grid_b<T>(nL));
         if (L - 1 == 0)
             hipLaunchKernelGGL((kb_coarse_rows<T, T, double>), g, dim3(kBlock), 0, s, nL, (const T*)V.ainv,
                                (const T*)E->r[L], (const int*)F.aggptr, (const double*)E->R, (const T*)V.dinv[0],

@@ -325,12 +325,24 @@ static __global__ __launch_bounds__(kCoarseThreads) void kb_coarse(
 
 // Large coarsest level (L >= 1): the product and the prolongation into level
 // L-1 spread over many workgroups of 256 threads.  FP64: one wave per 16-row
-// block on the matrix cores, prolongated straight from the result registers.
-// FP32: a workgroup owns 64 rows, its four waves split the columns j in four
-// fixed ranges (one row and all 16 right-hand sides per thread) and meet in
-// LDS in a fixed order.
-constexpr int kCoarseRowsBlockRows = 64;
-inline int coarse_rows_grid_b(int nL) { return (nL + kCoarseRowsBlockRows - 1) / kCoarseRowsBlockRows; }
+// block on the matrix cores (four waves, 64 rows per workgroup), prolongated
+// straight from the result registers.  FP32: a workgroup owns 16 rows and its
+// threads split the columns j in 16 fixed ranges (one row and all 16
+// right-hand sides per thread), meeting in LDS in a fixed order; small row
+// blocks give ceil(n_L / 16) workgroups, enough to spread a coarsest level of
+// a few thousand rows over the chip.
+template <typename T>
+constexpr int coarse_rows_block_rows_b() { return std::is_same<T, double>::value ? 64 : 16; }
+// Coarsest sizes from which the many-workgroup kernel replaces the single
+// workgroup: FP64 keeps the single-workgroup matrix-core product up to the
+// single-right-hand-side threshold; FP32, whose single workgroup computes
+// each (row, column) entry as a serial loop over n_L, switches early.
+template <typename T>
+constexpr int coarse_rows_min_b() { return std::is_same<T, double>::value ? kCoarseRowsMin : 32; }
+template <typename T>
+inline int coarse_rows_grid_b(int nL) {
+    return (nL + coarse_rows_block_rows_b<T>() - 1) / coarse_rows_block_rows_b<T>();
+}
 
 template <typename T, typename RT, typename RTF>
 static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
@@ -361,10 +373,10 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
                 zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
         }
     } else {
-        constexpr int G = kBlock / kCoarseRowsBlockRows;
-        __shared__ T s_part[G][kCoarseRowsBlockRows][kW + 1];
-        const int g = tid / kCoarseRowsBlockRows, lt = tid % kCoarseRowsBlockRows;
-        const int I = blockIdx.x * kCoarseRowsBlockRows + lt;
+        constexpr int R = coarse_rows_block_rows_b<T>(), G = kBlock / R;
+        __shared__ T s_part[G][R][kW + 1];
+        const int g = tid / R, lt = tid % R;
+        const int I = blockIdx.x * R + lt;
         const int j0 = (int)((long long)nL * g / G), j1 = (int)((long long)nL * (g + 1) / G);
         T acc[kW];
 #pragma unroll
@@ -379,9 +391,9 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
 #pragma unroll
         for (int c = 0; c < kW; ++c) s_part[g][lt][c] = acc[c];
         __syncthreads();
-        for (int e = tid; e < kCoarseRowsBlockRows * kW; e += kBlock) {
+        for (int e = tid; e < R * kW; e += kBlock) {
             const int row = e / kW, c = e % kW;
-            const int II = blockIdx.x * kCoarseRowsBlockRows + row;
+            const int II = blockIdx.x * R + row;
             if (II >= nL) continue;
             T z = s_part[0][row][c];
             for (int q = 1; q < G; ++q) z += s_part[q][row][c];
