@@ -70,6 +70,14 @@ MUTANTS = {
                                          "st = smoothed_prolongator(&h->A[0], cagg, cp, &h->P[j], &h->omega_p[j]);"),
     "backsolve_transposed": ("for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * z[k];",
                              "for (int k = i + 1; k < n; ++k) s -= L[(size_t)i * n + k] * z[k];"),
+    "round_f32_dinv_unrounded": ("g->dinv[l][i] = (double)(float)h->dinv[l][i];", "g->dinv[l][i] = h->dinv[l][i];"),
+    "round_f32_rounds_w": ("g->w[l][i] = h->w[l][i];", "g->w[l][i] = (double)(float)h->w[l][i];"),
+    "round_f32_p_unrounded": ("for (int i = 0; i < a->n; ++i) g->p[l][i] = (double)(float)h->p[l][i];",
+                              "for (int i = 0; i < a->n; ++i) g->p[l][i] = h->p[l][i];"),
+    "round_f32_chol_unrounded": ("g->chol[k] = (double)(float)h->chol[k];", "g->chol[k] = h->chol[k];"),
+    "restart_from_recurrence_residual": (
+        "restart:\n    csr_mv(A, x, q);\n    for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];",
+        "    csr_mv(A, x, q);\n    for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];\nrestart:"),
 }
 
 

@@ -839,3 +839,95 @@ def test_indefinite_matrix_reports_not_spd():
     with pytest.raises(oracle.OracleError) as e:
         oracle.Hierarchy(csr_from_scipy(M))
     assert e.value.code == oracle.E_NOT_SPD
+
+
+# --------------------------------------------------------------------------- FP32 hierarchy (ext. a)
+
+@pytest.mark.parametrize("case", ["q1_6", "varcoef_8", "lap7_8_composed", "q1_6_smoothed"])
+def test_round_f32_is_binary32_rounding_of_the_fp64_hierarchy(case):
+    """The FP32 hierarchy is the FP64 setup with A_l, the l1 inverse diagonal,
+    the prolongator weights and the coarsest Cholesky factor rounded to
+    binary32 (numpy's float32 cast is the reference rounding); aggregates and
+    the near-null vector w stay as built.  Its V-cycle is the multiplicative
+    composition (Sec. 3.1) of those rounded operators with the coarsest solve
+    through the rounded factor, B_L = (L32 L32^T)^-1."""
+    kw = {"lap7_8_composed": dict(agg_steps=2), "q1_6_smoothed": dict(smooth_prolongator=True, agg_steps=2)}
+    A = {"q1_6": lambda: q1_stretched(6, 1.05), "varcoef_8": lambda: varcoef7(8, seed=8),
+         "lap7_8_composed": lambda: lap7(8), "q1_6_smoothed": lambda: q1_stretched(6, 1.05)}[case]()
+    H = oracle.Hierarchy(A, max_coarse=12, **kw.get(case, {}))
+    G = H.round_f32()
+    f32 = lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+    assert G.nlevels == H.nlevels >= 3
+    rounded_any = False
+    for l in range(H.nlevels):
+        rp, ci, v = H.level(l)
+        rq, cq, u = G.level(l)
+        assert np.array_equal(rp, rq) and np.array_equal(ci, cq)
+        assert np.array_equal(u, f32(v))
+        assert np.array_equal(G.dinv(l), f32(H.dinv(l)))
+        assert np.array_equal(G.w(l), H.w(l))               # w is not rounded
+        rounded_any |= not np.array_equal(u, v) or not np.array_equal(G.dinv(l), H.dinv(l))
+        if l + 1 < H.nlevels:
+            assert np.array_equal(G.agg(l), H.agg(l))
+            assert np.array_equal(G.p(l), f32(H.p(l)))
+            PH, PG = H.prolongator(l), G.prolongator(l)
+            assert np.array_equal(PH.indptr, PG.indptr) and np.array_equal(PH.indices, PG.indices)
+            assert np.array_equal(PG.data, f32(PH.data))
+    assert rounded_any
+    L64, L32 = H.chol(), G.chol()
+    assert np.array_equal(L32, f32(L64))
+    assert not np.array_equal(L32, L64)
+
+    def dense_B(l):
+        Al = G.level_scipy(l).toarray()
+        if l == G.nlevels - 1:
+            return np.linalg.inv(L32 @ L32.T)
+        n = Al.shape[0]
+        P = G.prolongator(l).toarray()
+        S = np.eye(n) - np.diag(G.dinv(l)) @ Al
+        C = np.eye(n) - P @ dense_B(l + 1) @ P.T @ Al
+        return (np.eye(n) - S @ C @ S) @ np.linalg.inv(Al)
+
+    n = G.n(0)
+    Bcols = np.stack([G.vcycle(e) for e in np.eye(n)], axis=1)
+    Bf = dense_B(0)
+    assert np.allclose(Bcols, Bf, rtol=1e-10, atol=1e-10 * abs(Bf).max())
+    # and it differs from the FP64 cycle by the binary32 rounding, not less
+    B64 = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    d = np.abs(Bcols - B64).max() / np.abs(B64).max()
+    assert 1e-10 < d < 1e-4
+
+
+# --------------------------------------------------------------------------- true-residual restart
+
+def test_true_residual_restart_is_a_warm_restart_from_b_minus_ax():
+    """With the true-residual check (ext. a, the stopping test of Sec. 5 taken
+    on b - A x), a solve whose recurrence residual meets tol while the true
+    residual does not restarts the recurrence from r = b - A x: the result is
+    the chain 'solve, then solve again warm-started from x' (each warm start
+    recomputes r = b - A x0), and it ends with a true residual within tol."""
+    A = lap7(10)
+    H = oracle.Hierarchy(A, max_coarse=30)
+    b = uniform_rhs(A.n, 9)
+    S = A.to_scipy()
+    nb = np.linalg.norm(b)
+    tol = 5e-16                       # below the recurrence's attainable agreement with b - A x
+    x1, it1, rr1, st1 = H.solve(b, tol)
+    assert st1 == 0 and rr1 <= tol
+    assert np.linalg.norm(b - S @ x1) > tol * nb          # the branch is taken
+    x2, it2, rr2, st2 = H.solve(b, tol, true_res=True)
+    assert st2 == 0 and it2 > it1
+    # the warm-started chain, restarts bounded as in the oracle (10)
+    x, total = x1, it1
+    for _ in range(10):
+        if np.linalg.norm(b - S @ x) <= tol * nb:
+            break
+        x, itw, _, stw = H.solve(b, tol, maxit=1000 - total, x0=x)
+        assert stw == 0
+        total += itw
+    assert total == it2
+    assert np.array_equal(x, x2)
+    assert np.linalg.norm(b - S @ x2) <= tol * nb
+    # without the request the branch is never taken
+    x3, it3, _, _ = H.solve(b, tol, true_res=False)
+    assert it3 == it1 and np.array_equal(x3, x1)
