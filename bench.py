@@ -1,32 +1,49 @@
-"""Benchmark: FCG + AMG V-cycle solve of the 128^3 stretched-mesh Q1 pressure
-system to a 1e-6 relative residual on one MI355X.
+"""Benchmark: FCG + AMG V-cycle solve of the stretched-mesh Q1 pressure system
+(256^3 elements, 16.9M dofs, 453M nonzeros, by default) to a true relative
+residual of 1e-6 on one MI355X.
 
 A step is one complete solve from x0 = 0 (every outer iteration: V-cycle
 down-sweeps, coarse solve, up-sweeps, Krylov SpMV, dot products, axpys,
-convergence test), with the hierarchy and all vectors resident in HBM.  The
-hierarchy setup is timed separately.  Prints one JSON line.
+convergence test, and the final true-residual check), with the hierarchy and
+all vectors resident in HBM.  The value is the plain FP64 form; the same line
+carries the FP32-hierarchy form (its time, iterations, true residual and
+error against the oracle's stored FP64 solution), the V-cycle's and the
+level-0 kernels' HBM rates, and the CPU oracle's time per iteration on the
+same system.  The hierarchy setup is timed separately.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 128]
-                    [--precision f64|f32] [--no-cpu-baseline]
-    python bench.py --mode kernels [--reps R]   (level-0 kernels and a plain
-                    copy only, for hardware-counter runs under rocprofv3)
-    python bench.py --mode batch [--steps K]    (16 right-hand sides from
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
+                    [--no-cpu-baseline] [--cpu-iters I] [--cpu-deadline S]
+    python bench.py --mode kernels [--reps R] [--n N] [--precision f64|f32]
+                    (level-0 kernels and a plain copy only, for hardware-counter
+                    runs under rocprofv3)
+    python bench.py --mode batch --n 128 [--steps K]  (16 right-hand sides from
                     consecutive time steps: one batched solve vs 16 single
                     solves, FP64 and FP32 V-cycles; prints its own JSON line)
-    python bench.py --mode reuse [--steps K]    (coefficient-only update of the
-                    hierarchy for a second stretching ratio on the same mesh,
-                    against a fresh setup; prints its own JSON line)
+    python bench.py --mode reuse --n 128 [--steps K]  (coefficient-only update of
+                    the hierarchy for a second stretching ratio on the same
+                    mesh, against a fresh setup; prints its own JSON line)
     python bench.py --mode serve [--requests R] [--serve-load F]
-                    [--single-path 0|1] [--batch-from B] [--setup-workers W]
+                    [--budget-gib G] [--single-path 0|1] [--batch-from B]
+                    [--setup-workers W]
                     (serving stream: variable-coefficient 7-point operators
                     from a pool of 64, a closed loop for the capacity, then
-                    Poisson arrivals at F (default 0.5) x that capacity;
-                    p50/p99 latency and solves/s; prints its own JSON line)
+                    Poisson arrivals at F (default 0.7) x that capacity under
+                    an HBM budget of G GiB (default 64); p50/p99 latency and
+                    solves/s; prints its own JSON line)
 
-The roofline "traffic" figure comes from profiles/traffic_q1_128.json (HBM
-bytes per launch from FETCH_SIZE/WRITE_SIZE counter runs, calibrated on a
-plain copy); it is reported only while the kernel source it was measured on
-is unchanged (SHA-256 of csrc/kernels.hpp), else null.
+Byte model of the roofline figures: plain CSR (int32 column indices and row
+pointers, 8-byte values) with each owned vector entry counted once, as the
+algorithmic bytes of the method; the library's own tile format moves fewer
+matrix bytes (16-bit dictionary positions), reported beside it.  The
+roofline "traffic" figure comes from profiles/traffic_q1_<n>.json (HBM bytes
+per launch from FETCH_SIZE/WRITE_SIZE counter runs, calibrated on a plain
+copy); it is reported only for the workload, precision and kernel source it
+was measured on (SHA-256 of csrc/kernels.hpp), else null.
+
+The CPU baseline runs the oracle in a child process started at once: its
+hierarchy setup (minutes at 256^3) overlaps the GPU work, and its solve
+phase is timed after the GPU timing, single-threaded on one pinned core and
+on all cores.
 """
 from __future__ import annotations
 
@@ -42,23 +59,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNELS_SRC = os.path.join(ROOT, "paper_2210_16660_amd", "csrc", "kernels.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_q1_128.json")
 
 
 def kernels_hash() -> str:
     return hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
 
 
-def traffic_for(kernel: str, measured_config: bool = True):
+def traffic_for(kernel: str, n: int, precision: str, agg_steps: int):
     """Counter-measured HBM bytes per launch of `kernel`, if measured on this
-    source and this configuration (FP64 V-cycle, pairwise levels)."""
-    if not measured_config:
-        return None
+    kernel source, for this workload size, precision and aggregate size."""
+    path = os.path.join(ROOT, "profiles", f"traffic_q1_{n}.json")
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_hpp_sha256") != kernels_hash():
+    cfg = rec.get("config", {})
+    if (rec.get("kernels_hpp_sha256") != kernels_hash() or cfg.get("n_elements") != n
+            or cfg.get("precision") != precision or cfg.get("agg_steps") != agg_steps):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("traffic_bytes")
@@ -82,22 +99,217 @@ def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
+def csr_bytes(nnz, n, s):
+    """Bytes of one pass over a CSR matrix: int32 columns, s-byte values,
+    int32 row pointers (the survey's M_l)."""
+    return nnz * (4 + s) + 4 * (n + 1)
+
+
+def level0_csr_bytes(info, name, s=8):
+    """Algorithmic bytes of one launch of a level-0 kernel, plain-CSR model:
+    Krylov pass M_0 + 5 n_0 8 (z, p_old, r in; p, q out); down-sweep
+    M_0 + (4 n_0 + n_1) s; up-sweep M_0 + (6 n_0 + n_1) s; SpMV M_0 + 2 n_0 8."""
+    n0, n1, nnz0 = info.n[0], info.n[1] if info.levels > 1 else 0, info.nnz[0]
+    if name == "krylov_spmv_l0":
+        return csr_bytes(nnz0, n0, 8) + 5 * n0 * 8
+    if name == "vcycle_down_l0":
+        return csr_bytes(nnz0, n0, s) + (4 * n0 + n1) * s
+    if name == "vcycle_up_l0":
+        return csr_bytes(nnz0, n0, s) + (6 * n0 + n1) * s
+    if name == "spmv_l0":
+        return csr_bytes(nnz0, n0, 8) + 2 * n0 * 8
+    raise KeyError(name)
+
+
+def rhs_seed(n):
+    """Right-hand-side seeds of the stored oracle values: 128^3 seed 2, 256^3 seed 3."""
+    return {256: 3}.get(n, 2)
+
+
+def load_golden(n, ratio, seed, A):
+    path = os.path.join(ROOT, "tests", "golden", f"q1_{n}_fcg.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    w = g["workload"]
+    if w["rhs_seed"] != seed or w["n"] != A.n or w["ratio"] != ratio:
+        return None
+    return g
+
+
+def load_workload(args, seed, write=True):
+    """The Q1 operator and its divergence right-hand side; with --cache DIR the
+    generated arrays are kept there (.npy) for later runs on the same machine
+    (several profiler passes in one session)."""
+    import numpy as np
+    from workloads import CSR, q1_rhs, q1_stretched
+    if args.cache:
+        stem = os.path.join(args.cache, f"q1_{args.n}_{args.ratio!r}_seed{seed}")
+        names = [stem + s for s in ("_rp.npy", "_ci.npy", "_v.npy", "_b.npy")]
+        if all(os.path.exists(f) for f in names):
+            rp, ci, v, b = (np.load(f) for f in names)
+            return CSR(len(rp) - 1, rp, ci, v), b
+    A = q1_stretched(args.n, args.ratio)
+    b = q1_rhs(args.n, args.ratio, seed)
+    if args.cache and write:
+        os.makedirs(args.cache, exist_ok=True)
+        for f, arr in zip(names, (A.row_ptr, A.col, A.val, b)):
+            np.save(f + ".tmp.npy", arr)
+            os.replace(f + ".tmp.npy", f)
+    return A, b
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline_worker(args) -> int:
+    """The CPU baseline leg (a child process of the benchmark): the oracle's
+    hierarchy for the same workload is built first (its setup is reported, not
+    counted), then, when the parent says so on stdin (after its GPU timing),
+    `cpu_iters` FCG iterations of the oracle's solve are timed three times
+    single-threaded on one pinned core and three times on all cores of this
+    process's affinity mask (the oracle's OpenMP timing build, bitwise the
+    plain build); medians reported per iteration."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    oracle.use_openmp_build()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    t0 = time.perf_counter()
+    A, b = load_workload(args, rhs_seed(args.n), write=False)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O = oracle.Hierarchy(A, agg_steps=args.agg_steps)
+    t_setup = time.perf_counter() - t0
+    del A
+    print(json.dumps({"ready": True, "gen_s": round(t_gen, 1), "setup_s": round(t_setup, 1)}), flush=True)
+    if sys.stdin.readline().strip() != "go":
+        return 0
+    cpus = sorted(os.sched_getaffinity(0))
+
+    def timed(threads):
+        gomp.omp_set_num_threads(threads)
+        runs = []
+        for _ in range(3):
+            t = time.perf_counter()
+            _, it, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=args.cpu_iters)
+            runs.append(1e3 * (time.perf_counter() - t) / it)
+        return sorted(runs)[1], runs
+
+    os.sched_setaffinity(0, {cpus[0]})
+    one, one_runs = timed(1)
+    os.sched_setaffinity(0, set(cpus))
+    # the host share of one GPU can be smaller than the mask: OMP_NUM_THREADS caps it
+    threads = max(1, min(len(cpus), int(os.environ.get("OMP_NUM_THREADS", len(cpus)))))
+    allc, all_runs = timed(threads)
+    print(json.dumps({"single_ms_per_iter": one, "single_runs": one_runs, "all_ms_per_iter": allc,
+                      "iters": args.cpu_iters,
+                      "all_runs": all_runs, "threads": threads, "setup_s": round(t_setup, 1),
+                      "gen_s": round(t_gen, 1), **cpu_info()}), flush=True)
+    return 0
+
+
+class CpuBaseline:
+    """Starts the CPU baseline worker at once (its oracle setup overlaps the
+    GPU work) and collects it after the GPU timing."""
+
+    def __init__(self, args, log):
+        import subprocess
+        self.log = log
+        self.t0 = time.perf_counter()
+        cmd = [sys.executable, "-u", os.path.abspath(__file__), "--cpu-baseline-worker", "--n", str(args.n),
+               "--ratio", repr(args.ratio), "--agg-steps", str(args.agg_steps), "--cpu-iters", str(args.cpu_iters)]
+        if args.cache:
+            cmd += ["--cache", args.cache]
+        self.p = subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+        self.deadline = args.cpu_deadline
+
+    def _readline(self, until):
+        import select
+        while True:
+            left = until - time.perf_counter()
+            if left <= 0:
+                return None
+            r, _, _ = select.select([self.p.stdout], [], [], min(left, 30.0))
+            if r:
+                return self.p.stdout.readline()
+            self.log(f"waiting for the CPU baseline worker ({time.perf_counter() - self.t0:.0f} s)")
+
+    def collect(self, gpu_iters, gpu_ms_per_iter):
+        until = self.t0 + self.deadline
+        line = self._readline(until)
+        if not line:
+            self.p.kill()
+            self.p.wait()
+            self.log("CPU baseline worker did not finish its setup within the time budget")
+            return None
+        ready = json.loads(line)
+        self.log(f"oracle setup {ready['setup_s']} s; timing the oracle's solve")
+        self.p.stdin.write("go\n")
+        self.p.stdin.flush()
+        line = self._readline(time.perf_counter() + 600)
+        self.p.wait()
+        if not line:
+            return None
+        r = json.loads(line)
+        return {
+            "value": round(r["single_ms_per_iter"], 1),
+            "unit": "ms per FCG iteration",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"3 timed runs of the oracle's FCG solve phase, {r['iters']} iterations each, on the "
+                      f"same operator and right-hand side (median per "
+                      f"iteration; its hierarchy setup of {r['setup_s']} s is not counted), single-threaded and "
+                      f"pinned to one core",
+            "all_cores": {"value": round(r["all_ms_per_iter"], 1), "unit": "ms per FCG iteration",
+                          "threads": r["threads"], "build": "the oracle's OpenMP timing build (row and element loops "
+                                                            "over threads, reductions serial; bitwise the plain build)"},
+            "runs_ms_per_iter": {"single": [round(v, 1) for v in r["single_runs"]],
+                                 "all_cores": [round(v, 1) for v in r["all_runs"]]},
+            "gpu_ms_per_iter": round(gpu_ms_per_iter, 3),
+            "single_vs_gpu": round(r["single_ms_per_iter"] / gpu_ms_per_iter, 1),
+            "oracle_setup_s": r["setup_s"],
+            "per_solve_ms_scaled": round(r["single_ms_per_iter"] * gpu_iters, 1),
+            "per_solve_note": f"per-iteration median x the {gpu_iters} iterations of the GPU solve (an estimate, "
+                              f"not a timed full solve)",
+            "nproc": r["nproc"], "affinity_cpus": r["affinity_cpus"], "cpu_model": r["cpu_model"],
+        }
+
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=128, help="Q1 mesh elements per direction")
+    ap.add_argument("--n", type=int, default=256, help="Q1 mesh elements per direction")
     ap.add_argument("--ratio", type=float, default=1.05)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
+                    help="batch/reuse modes: V-cycle precision (the solve mode times both)")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations per timed CPU baseline run")
+    ap.add_argument("--cpu-deadline", type=float, default=420.0,
+                    help="seconds from the start by which the CPU baseline's oracle setup must be done")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "mixed", "reuse"])
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "reuse"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--budget-gib", type=float, default=200.0)
-    ap.add_argument("--serve-load", type=float, default=0.5,
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-load", type=float, default=0.7,
                     help="serving: open-loop arrival rate as a fraction of the closed-loop capacity")
     ap.add_argument("--single-path", type=int, default=1, choices=[0, 1],
                     help="serving: a request alone on its operator runs on the single-right-hand-side solver")
@@ -106,6 +318,7 @@ def main() -> int:
     ap.add_argument("--setup-workers", type=int, default=4,
                     help="serving: host phases of new operators built at once")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--cache", default="", help="directory that keeps the generated workload between runs")
     ap.add_argument("--agg-steps", type=int, default=1,
                     help="aggregate-size composition: keep every n-th pairwise level (aggregates up to 2^n)")
     ap.add_argument("--smoother", default="l1", choices=["l1", "hgs"],
@@ -116,6 +329,8 @@ def main() -> int:
     ap.add_argument("--smooth-prolongator", action="store_true",
                     help="smoothed prolongators P = (I - w D^-1 A) P^ (moderate sizes: coarse levels fill in)")
     args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        return cpu_baseline_worker(args)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -124,37 +339,37 @@ def main() -> int:
                           "n_gpus": args.gpus}))
         return 2
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.mode == "solve" and not args.no_cpu_baseline:
+        cpu = CpuBaseline(args, log)
+
     import numpy as np
     import torch
 
     import paper_2210_16660_amd as pamg
-    from workloads import q1_rhs, q1_rhs_sequence, q1_stretched
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     if args.mode == "serve":
         return bench_serve(args, torch, np, pamg, log)
-    if args.mode == "mixed":
-        return bench_mixed(args, torch, np, pamg, log)
     t0 = time.perf_counter()
-    A = q1_stretched(args.n, args.ratio)
-    b = q1_rhs(args.n, args.ratio, 2)
-    log(f"generated Q1 {args.n}^3: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
-    prec = pamg.PREC_F32 if args.precision == "f32" else pamg.PREC_F64
+    seed = rhs_seed(args.n)
+    A, b = load_workload(args, seed)
+    log(f"generated Q1 {args.n}^3: n={A.n} nnz={A.nnz}, right-hand side seed {seed}, "
+        f"in {time.perf_counter() - t0:.1f}s")
     if args.mode == "batch":
         return bench_batch(args, A, torch, np, pamg, log)
     if args.mode == "reuse":
         return bench_reuse(args, A, b, torch, np, pamg, log)
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
     smooth_kw = {} if args.smoother == "l1" else dict(smoother="hgs", sweeps=args.sweeps, gs_block=args.gs_block,
                                                       omega=args.omega)
     if args.smooth_prolongator:
         smooth_kw["smooth_prolongator"] = 1
-    H = pamg.Hierarchy(A, build_f32=1 if prec == pamg.PREC_F32 else 0, agg_steps=args.agg_steps, **smooth_kw)
+    H = pamg.Hierarchy(A, build_f32=1, agg_steps=args.agg_steps, **smooth_kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = H.info()
@@ -162,12 +377,12 @@ def main() -> int:
 
     b_d = torch.from_numpy(b).to(dev)
     x_d = torch.zeros(A.n, dtype=torch.float64, device=dev)
-    opts = dict(tol=args.tol, krylov="fcg", precision=prec)
 
     if args.mode == "kernels":
         # one warm solve fills every work vector with real data, then each
         # level-0 kernel and a plain copy are launched back to back
-        H.solve(b_d, x_d, **opts)
+        prec = pamg.PREC_F32 if args.precision == "f32" else pamg.PREC_F64
+        H.solve(b_d, x_d, tol=args.tol, precision=prec)
         out = {}
         for name, op in (("vcycle_down_l0", pamg.OP_DOWN), ("vcycle_up_l0", pamg.OP_UP),
                          ("krylov_spmv_l0", pamg.OP_KRYLOV)):
@@ -178,38 +393,61 @@ def main() -> int:
         print(json.dumps(out), flush=True)
         return 0
 
-    for k in range(args.warmup):
-        x_d.zero_()
-        t1 = time.perf_counter()
-        inf = H.solve(b_d, x_d, **opts)
-        log(f"warm-up solve {k}: {1e3 * (time.perf_counter() - t1):.1f} ms, {inf.iterations} iterations")
-    torch.cuda.synchronize()
-    times, iters = [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        x_d.zero_()
-        t1 = time.perf_counter()
-        inf = H.solve(b_d, x_d, **opts)
+    golden = load_golden(args.n, args.ratio, seed, A) if args.agg_steps == 1 and args.smoother == "l1" \
+        and not args.smooth_prolongator else None
+    S = A.to_scipy()
+    bn = float(np.linalg.norm(b))
+    res = {}
+    for name, prec, steps, warm in (("f64", pamg.PREC_F64, args.steps, args.warmup),
+                                    ("f32", pamg.PREC_F32, max(1, args.steps // 2), max(1, args.warmup // 2))):
+        opts = dict(tol=args.tol, krylov="fcg", precision=prec, true_residual=1)
+        for k in range(warm):
+            x_d.zero_()
+            t1 = time.perf_counter()
+            inf = H.solve(b_d, x_d, **opts)
+            log(f"{name} warm-up solve {k}: {1e3 * (time.perf_counter() - t1):.1f} ms, {inf.iterations} iterations")
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        iters.append(inf.iterations)
-        if inf.status != pamg.OK:
-            log(f"solve status {inf.status}")
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            x_d.zero_()
+            inf = H.solve(b_d, x_d, **opts)
+            if inf.status != pamg.OK:
+                log(f"{name} solve status {inf.status}")
+                return 1
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t_start) / steps
+        x = x_d.cpu().numpy()
+        rel = float(np.linalg.norm(b - S @ x) / bn)
+        entry = {"ms_per_solve": round(ms, 4), "steps": steps, "iterations": inf.iterations,
+                 "restarts": inf.restarts, "relres_true": rel}
+        if golden is not None:
+            idx = np.array(golden["sample_index"])
+            xo = np.array(golden["x_sample"])
+            entry["err_vs_oracle_sample"] = float(np.linalg.norm(x[idx] - xo) / np.linalg.norm(xo))
+            entry["oracle_iterations"] = golden["fcg_iterations"]
+        res[name] = entry
+        res[name + "_x"] = x
+        log(f"{name}: {ms:.2f} ms/solve, {inf.iterations} iterations, true relres {rel:.3e}"
+            + (f", sampled error vs oracle {entry['err_vs_oracle_sample']:.2e}" if golden is not None else ""))
+        if rel > args.tol:
+            print(json.dumps({"error": f"{name} solve did not reach the tolerance", **entry}), flush=True)
             return 1
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ms_per_step = 1e3 * total / args.steps
-    x = x_d.cpu().numpy()
-    relres_true = float(np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b))
-    log(f"solve {ms_per_step:.2f} ms/step, iterations {iters[0]}, true relres {relres_true:.3e}")
+    err32 = float(np.linalg.norm(res["f32_x"] - res["f64_x"]) / np.linalg.norm(res["f64_x"]))
+    ms_per_step = res["f64"]["ms_per_solve"]
+    iters = res["f64"]["iterations"]
 
     # V-cycle and SpMV throughput (back-to-back, HIP events on this stream)
     r_d = b_d.clone()
-    v_ms, s_ms = H.time_kernels(r_d, reps=20, precision=prec)
-    vbytes = info.vcycle_bytes_f32 if prec == pamg.PREC_F32 else info.vcycle_bytes_f64
-    # (the algorithmic V-cycle bytes are those of the l1-Jacobi cycle)
-    v_gbs = vbytes / (v_ms * 1e-3) / 1e9 if args.smoother == "l1" and not args.smooth_prolongator else float("nan")
-    s_gbs = info.spmv_bytes / (s_ms * 1e-3) / 1e9
+    plain = args.smoother == "l1" and not args.smooth_prolongator
+    vc = {}
+    for name, prec in (("f64", pamg.PREC_F64), ("f32", pamg.PREC_F32)):
+        v_ms, s_ms = H.time_kernels(r_d, reps=20, precision=prec)
+        csr_b = info.csr_vcycle_bytes_f64 if prec == pamg.PREC_F64 else info.csr_vcycle_bytes_f32
+        tile_b = info.vcycle_bytes_f64 if prec == pamg.PREC_F64 else info.vcycle_bytes_f32
+        vc[name] = {"ms": v_ms, "GBps": csr_b / (v_ms * 1e-3) / 1e9 if plain else float("nan"),
+                    "GBps_tile_format": tile_b / (v_ms * 1e-3) / 1e9 if plain else float("nan"), "spmv_ms": s_ms}
+    s_ms = vc["f64"]["spmv_ms"]
+    s_gbs = level0_csr_bytes(info, "spmv_l0") / (s_ms * 1e-3) / 1e9
 
     # the kernels that stream the level-0 matrix, each timed live with HIP events
     kern = {}
@@ -219,18 +457,23 @@ def main() -> int:
         level0_ops = ((("vcycle_down_l0", pamg.OP_DOWN), ("vcycle_up_l0", pamg.OP_UP)) if args.smoother == "l1"
                       else (("hgs_sweep_l0", pamg.OP_SMOOTH),)) + (("krylov_spmv_l0", pamg.OP_KRYLOV),)
     for name, op in level0_ops:
-        if op == pamg.OP_KRYLOV and prec == pamg.PREC_F32:
-            ms, nb = H.time_op(op, 0, reps=20, precision=pamg.PREC_F64)
-        else:
-            ms, nb = H.time_op(op, 0, reps=20, precision=prec)
-        kern[name] = {"ms": ms, "bytes": nb, "GBps": nb / (ms * 1e-3) / 1e9}
+        ms, nb = H.time_op(op, 0, reps=20, precision=pamg.PREC_F64)
+        k = {"ms": ms, "bytes_tile_format": nb, "GBps_tile_format": nb / (ms * 1e-3) / 1e9}
+        if name != "hgs_sweep_l0":
+            k["bytes"] = level0_csr_bytes(info, name)
+            k["GBps"] = k["bytes"] / (ms * 1e-3) / 1e9
+        kern[name] = k
     dom = max(kern, key=lambda k: kern[k]["ms"])
     dk = kern[dom]
     copy_gbs, _ = copy_bandwidth(torch)
-    traffic = traffic_for(dom, prec == pamg.PREC_F64 and args.agg_steps == 1 and args.smoother == "l1"
-                          and not args.smooth_prolongator)
-    log(f"V-cycle {v_ms:.3f} ms ({v_gbs:.0f} GB/s), SpMV {s_ms:.3f} ms ({s_gbs:.0f} GB/s); "
-        + ", ".join(f"{k} {v['ms']:.4f} ms {v['GBps']:.0f} GB/s" for k, v in kern.items()))
+    traffic = traffic_for(dom, args.n, "f64", args.agg_steps) if plain else None
+    log(f"V-cycle {vc['f64']['ms']:.3f} ms ({vc['f64']['GBps']:.0f} GB/s), FP32 V-cycle {vc['f32']['ms']:.3f} ms; "
+        f"SpMV {s_ms:.3f} ms ({s_gbs:.0f} GB/s); "
+        + ", ".join(f"{k} {v['ms']:.4f} ms {v.get('GBps', float('nan')):.0f} GB/s" for k, v in kern.items()))
+    achieved = dk.get("GBps", dk["GBps_tile_format"])
+
+    def r1(v):
+        return round(v, 1) if v == v else None
 
     result = {
         "metric": "PCG-AMG solve time to 1e-6 rel. residual + V-cycle HBM GB/s (% of peak)",
@@ -243,63 +486,59 @@ def main() -> int:
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == pamg.PREC_F64 else "f32-vcycle/f64-fcg",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"Q1 hexahedral FE Laplacian, {args.n}^3 elements, vertical stretching {args.ratio}, "
-                        f"divergence RHS seed 2; FCG + AMG V-cycle (pairwise matching aggregation"
+                        f"divergence right-hand side seed {seed}; FCG + AMG V-cycle (pairwise matching aggregation"
+                        + (f", aggregates of up to {2 ** args.agg_steps}" if args.agg_steps > 1 else "")
                         + (", smoothed prolongators, " if args.smooth_prolongator else ", ")
                         + ("l1-Jacobi 1+1" if args.smoother == "l1" else
                            f"hybrid forward/backward Gauss-Seidel {H.params.sweeps or 4}+{H.params.sweeps or 4} "
                            f"(blocks of {H.params.gs_block or 256}, omega {H.params.omega or 1.5:g})")
-                        + f", dense coarse solve) to {args.tol:g}",
+                        + f", dense coarse solve) to a true relative residual of {args.tol:g}; value: the plain "
+                          f"FP64 form; the FP32-hierarchy form in 'mixed_precision'",
             "n": A.n, "nnz": A.nnz, "levels": info.levels,
             "operator_complexity": round(info.operator_complexity, 4),
             "aggregate_steps": args.agg_steps,
             "smoother": args.smoother,
             "smoothed_prolongator": bool(args.smooth_prolongator),
         },
-        "iterations": iters[0],
-        "relres_true": relres_true,
+        "iterations": iters,
+        "relres_true": res["f64"]["relres_true"],
+        "err_vs_oracle_sample": res["f64"].get("err_vs_oracle_sample"),
+        "oracle_iterations": res["f64"].get("oracle_iterations"),
+        "mixed_precision": {**res["f32"], "speedup_vs_f64": round(ms_per_step / res["f32"]["ms_per_solve"], 3),
+                            "solution_relerr_vs_f64": err32, "vcycle_ms": round(vc["f32"]["ms"], 4),
+                            "vcycle_GBps": r1(vc["f32"]["GBps"])},
         "setup_s": round(setup_s, 3),
-        "vcycle_ms": round(v_ms, 4),
-        "vcycle_GBps": round(v_gbs, 1) if v_gbs == v_gbs else None,
-        "vcycle_pct_peak": round(100 * v_gbs / HBM_PEAK_GBS, 2) if v_gbs == v_gbs else None,
+        "vcycle_ms": round(vc["f64"]["ms"], 4),
+        "vcycle_GBps": r1(vc["f64"]["GBps"]),
+        "vcycle_pct_peak": round(100 * vc["f64"]["GBps"] / HBM_PEAK_GBS, 2) if plain else None,
+        "vcycle_GBps_tile_format": r1(vc["f64"]["GBps_tile_format"]),
         "spmv_ms": round(s_ms, 4),
         "spmv_GBps": round(s_gbs, 1),
         "spmv_pct_peak": round(100 * s_gbs / HBM_PEAK_GBS, 2),
-        "kernels": {k: {"ms": round(v["ms"], 5), "bytes": v["bytes"], "GBps": round(v["GBps"], 1)}
+        "byte_model": "plain CSR (int32 columns and row pointers, 8-byte values) with each owned vector entry "
+                      "counted once; *_tile_format: the library's tile format (16-bit dictionary positions)",
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "copy_GBps": round(copy_gbs, 1),
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
-            "achieved": round(dk["GBps"], 1),
+            "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
         },
     }
-
-    if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.perf_counter()
-        O = oracle.Hierarchy(A, agg_steps=args.agg_steps)
-        t_or_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, it_or, _, _ = O.solve(b, 0.0, krylov="fcg", fixed_iters=args.cpu_iters)
-        t_or = time.perf_counter() - t0
-        per_iter_ms = 1e3 * t_or / it_or
-        result["cpu_baseline"] = {
-            "value": round(per_iter_ms * iters[0], 2),
-            "unit": "ms",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"{it_or} FCG iterations of the same solve (single-threaded C oracle, its setup "
-                      f"of {t_or_setup:.1f}s excluded), scaled to the {iters[0]} iterations of a full solve",
-        }
-        log(f"oracle {per_iter_ms:.1f} ms/iteration")
+    if cpu is not None:
+        cb = cpu.collect(iters, ms_per_step / iters)
+        result["cpu_baseline"] = cb if cb is not None else {
+            "value": None, "unit": "ms per FCG iteration", "cores": 1, "kind": "oracle",
+            "sample": f"not measured: the oracle's setup did not finish within {args.cpu_deadline:g} s"}
     print(json.dumps(result), flush=True)
     return 0
 
@@ -611,92 +850,6 @@ def bench_serve(args, torch, np, pamg, log) -> int:
     }
     print(json.dumps(out), flush=True)
     return 0 if ok == len(comps) else 1
-
-
-def bench_mixed(args, torch, np, pamg, log) -> int:
-    """FP64 hierarchy versus FP32 hierarchy (both under the FP64 FCG) on the
-    same stretched Q1 system (256^3 elements unless --n says otherwise,
-    divergence right-hand side seed 3), each to a true FP64 relative residual
-    of 1e-6; the solutions are compared with each other and with the oracle's
-    stored FP64 solution samples when they exist for this workload."""
-    from workloads import q1_rhs, q1_stretched
-    n = args.n if args.n != 128 else 256
-    t0 = time.perf_counter()
-    A = q1_stretched(n, args.ratio, progress=log)
-    b = q1_rhs(n, args.ratio, 3, progress=log)
-    log(f"generated Q1 {n}^3: n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
-    golden = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"q1_{n}_fcg.json")
-    if os.path.exists(gpath):
-        with open(gpath) as f:
-            g = json.load(f)
-        if g["workload"]["rhs_seed"] == 3 and g["workload"]["n"] == A.n and g["workload"]["ratio"] == args.ratio:
-            golden = g
-    dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    H = pamg.Hierarchy(A, build_f32=1)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    info = H.info()
-    log(f"setup {setup_s:.2f}s, {info.levels} levels")
-    b_d = torch.from_numpy(b).to(dev)
-    S = A.to_scipy()
-    bn = float(np.linalg.norm(b))
-    res = {}
-    xs = {}
-    for name, prec in (("f64", pamg.PREC_F64), ("f32", pamg.PREC_F32)):
-        x_d = torch.zeros(A.n, dtype=torch.float64, device=dev)
-        opts = dict(tol=args.tol, krylov="fcg", precision=prec, true_residual=1)
-        for _ in range(args.warmup):
-            x_d.zero_()
-            H.solve(b_d, x_d, **opts)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            x_d.zero_()
-            inf = H.solve(b_d, x_d, **opts)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t1) / args.steps
-        x = x_d.cpu().numpy()
-        xs[name] = x
-        rel = float(np.linalg.norm(b - S @ x) / bn)
-        r_d = b_d.clone()
-        v_ms, _ = H.time_kernels(r_d, reps=10, precision=prec)
-        vbytes = info.vcycle_bytes_f32 if prec == pamg.PREC_F32 else info.vcycle_bytes_f64
-        entry = {"ms_per_solve": round(ms, 3), "iterations": inf.iterations, "status": inf.status,
-                 "relres_true": rel, "vcycle_ms": round(v_ms, 4),
-                 "vcycle_GBps": round(vbytes / (v_ms * 1e-3) / 1e9, 1)}
-        if golden is not None:
-            idx = np.array(golden["sample_index"])
-            xo = np.array(golden["x_sample"])
-            entry["err_vs_oracle_sample"] = float(np.linalg.norm(x[idx] - xo) / np.linalg.norm(xo))
-        res[name] = entry
-        log(f"{name}: {ms:.1f} ms/solve, {inf.iterations} iterations, true relres {rel:.3e}")
-        if inf.status != pamg.OK or rel > args.tol:
-            print(json.dumps({"error": f"{name} solve did not reach the tolerance", **entry}), flush=True)
-            return 1
-    err32 = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
-    out = {
-        "metric": "FP32-hierarchy speedup over FP64 at a true FP64 relative residual of 1e-6",
-        "value": round(res["f64"]["ms_per_solve"] / res["f32"]["ms_per_solve"], 3),
-        "unit": "x",
-        "higher_is_better": True,
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "dtype": "f64 | f32-vcycle/f64-fcg",
-        "data": "synthetic",
-        "config": {"workload": f"Q1 hexahedral FE Laplacian, {n}^3 elements, vertical stretching {args.ratio}, "
-                               f"divergence RHS seed 3; FCG + AMG V-cycle to a true residual of {args.tol:g}",
-                   "n": A.n, "nnz": A.nnz, "levels": info.levels},
-        "setup_s": round(setup_s, 2),
-        "f64": res["f64"],
-        "f32": res["f32"],
-        "f32_vs_f64_solution_relerr": err32,
-        "oracle_reference": "stored oracle FP64 solution samples (512 entries)" if golden is not None else None,
-    }
-    print(json.dumps(out), flush=True)
-    return 0
 
 
 if __name__ == "__main__":

@@ -48,6 +48,46 @@ enum { PAMG_SMOOTHER_L1_JACOBI = 0, PAMG_SMOOTHER_HYBRID_GS = 1 };
 
 typedef struct pamg_hierarchy pamg_hierarchy;
 
+/* ------------------------------------------------------------- context
+ *
+ * Sec. 4: the preconditioner module declares, allocates and initialises the
+ * library's data.  A context fixes the device and the allocator through
+ * which every device buffer of the hierarchies, multi-RHS engines and
+ * servers made with it is allocated and freed (a framework's caching
+ * allocator, or hipMalloc/hipFree).
+ *   alloc(bytes, stream, user): a device pointer, aligned to at least 16
+ *       bytes (256 recommended), usable on
+ *       `stream` (the stream of the call that allocates; NULL = the default
+ *       stream); NULL on failure, which the calling entry point reports as
+ *       PAMG_E_OOM after freeing whatever it had allocated in that call.
+ *   free(ptr, stream, user): releases a pointer returned by alloc.  The
+ *       library has synchronized the device before it frees, so no work on
+ *       any stream still uses the memory.
+ * The callbacks may be called from the library's own threads (a server's
+ * scheduler and setup workers), and from several threads at once. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} pamg_allocator;
+
+typedef struct pamg_context pamg_context;
+
+typedef struct {
+    uint64_t allocs, frees;       /* successful alloc calls, free calls */
+    uint64_t failed;              /* alloc calls that returned NULL */
+    uint64_t live_bytes, peak_bytes;
+    int32_t device, users;        /* users: hierarchies and servers made with the context */
+} pamg_context_stats;
+
+/* device: HIP device ordinal; allocator NULL: hipMalloc/hipFree (the
+ * allocator struct is copied).  Errors: INVALID (device out of range),
+ * OOM (host). */
+int pamg_context_create(int32_t device, const pamg_allocator *allocator, pamg_context **out);
+/* Errors: BUSY while hierarchies or servers made with it still exist. */
+int pamg_context_destroy(pamg_context *ctx);
+int pamg_context_stats_get(const pamg_context *ctx, pamg_context_stats *out);
+
 /* A in CSR, host memory, 0-based, full symmetric storage, columns strictly
  * ascending in every row, a positive diagonal entry present in every row.
  * (Sec. 4: the application hands the matrix over in CSR.) */
@@ -131,6 +171,13 @@ typedef struct {
     uint64_t vcycle_bytes_f64;   /* algorithmic HBM bytes of one FP64 V-cycle */
     uint64_t vcycle_bytes_f32;   /* same for the FP32 V-cycle (0 if not built) */
     uint64_t spmv_bytes;         /* algorithmic bytes of one level-0 FP64 SpMV */
+    int32_t tile_items[PAMG_MAX_LEVELS];  /* matrix entries per thread of the level's tiles (tiles of
+                                             256 x items entries; items >= 8: column dictionaries) */
+    uint64_t csr_vcycle_bytes_f64;  /* one FP64 V-cycle counted with plain CSR matrices (int32 columns,
+                                       s-byte values, int32 row pointers): sum over l < L of
+                                       2 (nnz_l (4 + s) + 4 (n_l + 1)) + (10 n_l + 2 n_{l+1}) s,
+                                       plus (n_L^2 + 2 n_L) s */
+    uint64_t csr_vcycle_bytes_f32;  /* same with s = 4 (0 if not built) */
 } pamg_hier_info;
 
 /* Fill defaults. */
@@ -138,11 +185,15 @@ int pamg_params_default(pamg_params *p);
 int pamg_solve_opts_default(pamg_solve_opts *o);
 
 /* Build the hierarchy from A (copied; the caller may free A on return), then
- * upload it to the current device.  Deterministic: aggregates and coarse
- * matrices are bitwise reproducible (Sec. 3.1 construction, readings listed
- * in the design notes).  Errors: INVALID (bad CSR), NOT_SPD (coarsest
- * factorisation), STALLED, OOM, DEVICE. */
-int pamg_setup(const pamg_csr *A, const pamg_params *params, void *stream, pamg_hierarchy **out);
+ * upload it to the context's device; every device buffer of the hierarchy
+ * comes from the context's allocator (ctx NULL: hipMalloc on the current
+ * device).  The context must outlive the hierarchy.  Deterministic:
+ * aggregates and coarse matrices are bitwise reproducible (Sec. 3.1
+ * construction, readings listed in the design notes).  Errors: INVALID (bad
+ * CSR), NOT_SPD (coarsest factorisation), STALLED, OOM (everything allocated
+ * by the call is freed again), DEVICE. */
+int pamg_setup(pamg_context *ctx, const pamg_csr *A, const pamg_params *params, void *stream,
+               pamg_hierarchy **out);
 
 int pamg_hierarchy_destroy(pamg_hierarchy *h);
 int pamg_hierarchy_info(const pamg_hierarchy *h, pamg_hier_info *out);
@@ -207,6 +258,16 @@ int pamg_debug_apply_batch(pamg_hierarchy *h, int32_t op, int32_t precision, con
  * 4*(levels-1) entries; level 0's up-sweep is a fixed shape, reported as
  * unroll 8 with 4 columns per lane). */
 int pamg_batch_config(pamg_hierarchy *h, int32_t precision, int32_t *cfg);
+
+/* Pin the kernel variants of the multi-RHS engine instead of the autotuner's
+ * choice (same layout as pamg_batch_config; level 0's up-sweep entries are
+ * ignored, its shape is fixed).  Every variant computes each column with the
+ * same operations in the same order, so the results do not depend on this
+ * choice; it exists to check that claim and to time variants.  Builds the
+ * engine (and runs the autotuner once) if needed; the pinned variants stay
+ * until the next call.  Errors: INVALID (null, unknown variant, a hybrid
+ * Gauss-Seidel or smoothed-prolongator hierarchy), OOM, DEVICE. */
+int pamg_batch_set_config(pamg_hierarchy *h, int32_t precision, const int32_t *cfg);
 
 /* Single operators of the V-cycle, for parity checks.  Vectors are FP64 in
  * canonical level numbering.
@@ -326,7 +387,9 @@ int pamg_server_opts_default(pamg_server_opts *o);
  * exists: an upper estimate of hierarchy + 16-column engine for A (host CSR)
  * at the given V-cycle precision.  Once built, the exact figure is used. */
 int pamg_server_estimate_bytes(const pamg_csr *A, int32_t precision, uint64_t *out);
-int pamg_server_create(const pamg_server_opts *opts, pamg_server **out);
+/* ctx: allocator and device of every hierarchy the server builds (NULL:
+ * hipMalloc on the current device); it must outlive the server. */
+int pamg_server_create(pamg_context *ctx, const pamg_server_opts *opts, pamg_server **out);
 /* Queue a request (copied).  Errors: INVALID (null pointers, bad tol). */
 int pamg_server_submit(pamg_server *s, const pamg_request *req);
 /* Move up to `max` completions into out (non-blocking); *n_out = count. */

@@ -24,6 +24,19 @@ SMOOTHER_L1_JACOBI, SMOOTHER_HYBRID_GS = 0, 1
 MAX_LEVELS = 64
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class pamg_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class pamg_context_stats(C.Structure):
+    _fields_ = [("allocs", C.c_uint64), ("frees", C.c_uint64), ("failed", C.c_uint64), ("live_bytes", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("device", C.c_int32), ("users", C.c_int32)]
+
+
 class pamg_csr(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.POINTER(C.c_int32)),
                 ("col_idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
@@ -53,7 +66,8 @@ class pamg_hier_info(C.Structure):
     _fields_ = [("levels", C.c_int32), ("n", C.c_int32 * MAX_LEVELS), ("nnz", C.c_int64 * MAX_LEVELS),
                 ("pairs", C.c_int32 * MAX_LEVELS), ("setup_ms", C.c_double), ("operator_complexity", C.c_double),
                 ("device_bytes", C.c_uint64), ("vcycle_bytes_f64", C.c_uint64), ("vcycle_bytes_f32", C.c_uint64),
-                ("spmv_bytes", C.c_uint64)]
+                ("spmv_bytes", C.c_uint64), ("tile_items", C.c_int32 * MAX_LEVELS),
+                ("csr_vcycle_bytes_f64", C.c_uint64), ("csr_vcycle_bytes_f32", C.c_uint64)]
 
 
 class pamg_server_opts(C.Structure):
@@ -86,7 +100,10 @@ _VP = C.c_void_p
 SIGNATURES = {
     "pamg_params_default": (C.c_int, [C.POINTER(pamg_params)]),
     "pamg_solve_opts_default": (C.c_int, [C.POINTER(pamg_solve_opts)]),
-    "pamg_setup": (C.c_int, [C.POINTER(pamg_csr), C.POINTER(pamg_params), _VP, C.POINTER(_VP)]),
+    "pamg_context_create": (C.c_int, [C.c_int32, C.POINTER(pamg_allocator), C.POINTER(_VP)]),
+    "pamg_context_destroy": (C.c_int, [_VP]),
+    "pamg_context_stats_get": (C.c_int, [_VP, C.POINTER(pamg_context_stats)]),
+    "pamg_setup": (C.c_int, [_VP, C.POINTER(pamg_csr), C.POINTER(pamg_params), _VP, C.POINTER(_VP)]),
     "pamg_hierarchy_destroy": (C.c_int, [_VP]),
     "pamg_hierarchy_info": (C.c_int, [_VP, C.POINTER(pamg_hier_info)]),
     "pamg_hierarchy_aggregates": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
@@ -97,6 +114,7 @@ SIGNATURES = {
     "pamg_solve_batch": (C.c_int, [_VP, C.c_int32, _VP, C.c_int64, _VP, C.c_int64, C.POINTER(pamg_solve_opts), _VP,
                                    C.POINTER(pamg_solve_info)]),
     "pamg_batch_config": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
+    "pamg_batch_set_config": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
     "pamg_debug_apply_batch": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP]),
     "pamg_debug_apply": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP]),
     "pamg_time_kernels": (C.c_int, [_VP, C.c_int32, _VP, C.c_int32, _VP, C.POINTER(C.c_double),
@@ -105,7 +123,7 @@ SIGNATURES = {
                                C.POINTER(C.c_uint64)]),
     "pamg_server_opts_default": (C.c_int, [C.POINTER(pamg_server_opts)]),
     "pamg_server_estimate_bytes": (C.c_int, [C.POINTER(pamg_csr), C.c_int32, C.POINTER(C.c_uint64)]),
-    "pamg_server_create": (C.c_int, [C.POINTER(pamg_server_opts), C.POINTER(_VP)]),
+    "pamg_server_create": (C.c_int, [_VP, C.POINTER(pamg_server_opts), C.POINTER(_VP)]),
     "pamg_server_submit": (C.c_int, [_VP, C.POINTER(pamg_request)]),
     "pamg_server_poll": (C.c_int, [_VP, C.POINTER(pamg_completion), C.c_int32, C.POINTER(C.c_int32)]),
     "pamg_server_stats_get": (C.c_int, [_VP, C.POINTER(pamg_server_stats)]),
@@ -183,10 +201,97 @@ def solve_opts(**kw) -> pamg_solve_opts:
     return o
 
 
-class Hierarchy:
-    """An AMG hierarchy built by pamg_setup (owned by the library)."""
+class Context:
+    """A pamg_context: the device and the allocator of every device buffer of
+    the hierarchies and servers made with it.
 
-    def __init__(self, A, stream=None, **kw):
+    allocator="torch" (default): PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc/delete on the stream the library
+    names); "hip": hipMalloc/hipFree; or a pair of Python callables
+    (alloc(nbytes, stream) -> device pointer or 0, free(ptr, stream)).  Keep
+    the context alive while its hierarchies and servers exist (they hold a
+    reference)."""
+
+    def __init__(self, device=None, allocator="torch"):
+        if device is None:
+            import torch
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self._cb = None
+        if allocator == "hip":
+            a = None
+        else:
+            if allocator == "torch":
+                alloc_py, free_py = _torch_allocator(self.device)
+            else:
+                alloc_py, free_py = allocator
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return int(alloc_py(int(nbytes), int(stream or 0))) or None
+                except Exception:          # an allocator failure is reported as PAMG_E_OOM
+                    return None
+
+            def _free(ptr, stream, user):
+                try:
+                    free_py(int(ptr), int(stream or 0))
+                except Exception:
+                    pass
+
+            self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+            a = pamg_allocator(self._cb[0], self._cb[1], None)
+        h = C.c_void_p()
+        _check(lib().pamg_context_create(self.device, C.byref(a) if a is not None else None, C.byref(h)),
+               "pamg_context_create")
+        self._h = h
+
+    def stats(self) -> pamg_context_stats:
+        st = pamg_context_stats()
+        _check(lib().pamg_context_stats_get(self._h, C.byref(st)), "pamg_context_stats_get")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _check(_lib.pamg_context_destroy(self._h), "pamg_context_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except PamgError:
+            pass
+
+
+def _torch_allocator(device):
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, device, stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
+_default_contexts = {}
+
+
+def default_context(device=None) -> Context:
+    """The binding's context per device: PyTorch's caching allocator."""
+    import torch
+    d = torch.cuda.current_device() if device is None else int(device)
+    if d not in _default_contexts:
+        _default_contexts[d] = Context(d, "torch")
+    return _default_contexts[d]
+
+
+class Hierarchy:
+    """An AMG hierarchy built by pamg_setup (owned by the library).  Its device
+    buffers come from `context` (default: the binding's PyTorch-allocator
+    context of the current device)."""
+
+    def __init__(self, A, stream=None, context=None, **kw):
         rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(A.col, dtype=np.int32)
         v = np.ascontiguousarray(A.val, dtype=np.float64)
@@ -194,8 +299,12 @@ class Hierarchy:
                        ci.ctypes.data_as(C.POINTER(C.c_int32)), v.ctypes.data_as(C.POINTER(C.c_double)))
         self.params = params(**kw)
         h = C.c_void_p()
-        s = None if self.params.host_only else _stream(stream)
-        _check(lib().pamg_setup(C.byref(csr), C.byref(self.params), s, C.byref(h)), "pamg_setup")
+        if self.params.host_only:
+            s, self.context = None, context
+        else:
+            s, self.context = _stream(stream), context if context is not None else default_context()
+        _check(lib().pamg_setup(self.context._h if self.context is not None else None, C.byref(csr),
+                                C.byref(self.params), s, C.byref(h)), "pamg_setup")
         self._h = h
         self.n = int(A.n)
 
@@ -288,6 +397,15 @@ class Hierarchy:
         _check(lib().pamg_batch_config(self._h, precision, cfg), "pamg_batch_config")
         return [tuple(cfg[4 * l:4 * l + 4]) for l in range(L)]
 
+    def set_batch_config(self, cfg, precision: int = PREC_F64):
+        """Pin the multi-RHS kernel variants: cfg[l] = (down unroll, down cols/lane,
+        up unroll, up cols/lane) for l = 0 .. levels-2 (level 0's up entries ignored)."""
+        L = self.levels - 1
+        if len(cfg) != L:
+            raise ValueError(f"expected {L} levels of variants")
+        arr = (C.c_int32 * (4 * max(L, 1)))(*[int(v) for t in cfg for v in t])
+        _check(lib().pamg_batch_set_config(self._h, precision, arr), "pamg_batch_set_config")
+
     def debug_apply(self, op: int, level: int, in0, out, in1=None, precision: int = PREC_F64, stream=None):
         _check(lib().pamg_debug_apply(self._h, op, level, precision, _ptr(in0), _ptr(in1), _ptr(out),
                                       _stream(stream)), "pamg_debug_apply")
@@ -338,7 +456,8 @@ class Server:
     completions are polled."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32,
-                 use_graph: int = 0, single_path: int = 0, batch_from: int = 4, setup_workers: int = 1):
+                 use_graph: int = 0, single_path: int = 0, batch_from: int = 4, setup_workers: int = 1,
+                 context=None):
         o = pamg_server_opts()
         _check(lib().pamg_server_opts_default(C.byref(o)), "pamg_server_opts_default")
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -349,7 +468,8 @@ class Server:
         o.batch_from = int(batch_from)
         o.setup_workers = int(setup_workers)
         h = C.c_void_p()
-        _check(lib().pamg_server_create(C.byref(o), C.byref(h)), "pamg_server_create")
+        self.context = context if context is not None else default_context()
+        _check(lib().pamg_server_create(self.context._h, C.byref(o), C.byref(h)), "pamg_server_create")
         self._h = h
         self._ops = {}
         self._live = {}

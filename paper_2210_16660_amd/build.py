@@ -40,7 +40,7 @@ def build(verbose: bool = True) -> str:
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     objs = []
     procs = []
-    for name in ("device", "batch", "serve", "dense", "reuse"):
+    for name in ("device", "batch", "serve", "dense", "reuse", "context"):
         o = os.path.join(BUILD, f"{name}.o")
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
                "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o]

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
 
 #include "batch.hpp"
 
@@ -68,7 +69,7 @@ struct BatchEngine {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_k[2] = {0, 0};
     std::vector<int> cfg_down, cfg_up;        // variant per level
-    std::vector<void*> allocs;
+    std::vector<DevAlloc> allocs;             // from the hierarchy's context
     uint64_t bytes = 0;
 };
 
@@ -78,7 +79,7 @@ void destroy_batch(BatchEngine* E) {
     for (auto& g : E->graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (E->cap_stream) (void)hipStreamDestroy(E->cap_stream);
-    for (void* p : E->allocs) (void)hipFree(p);
+    if (E->h) ctx_free_all(E->h->ctx, E->allocs);
     if (E->st_host) (void)hipHostFree(E->st_host);
     if (E->ptr_host) (void)hipHostFree(E->ptr_host);
     delete E;
@@ -86,12 +87,12 @@ void destroy_batch(BatchEngine* E) {
 
 template <typename T>
 static T* balloc(BatchEngine* E, size_t count, hipStream_t s) {
-    void* p = nullptr;
     if (count == 0) count = 1;
-    HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
-    E->allocs.push_back(p);
-    E->bytes += count * sizeof(T);
-    HIP_CHECK(hipMemsetAsync(p, 0, count * sizeof(T), s));
+    const size_t bytes = count * sizeof(T);
+    void* p = ctx_alloc(E->h->ctx, bytes, s);
+    E->allocs.push_back({p, bytes});
+    E->bytes += bytes;
+    HIP_CHECK(hipMemsetAsync(p, 0, bytes, s));
     return static_cast<T*>(p);
 }
 
@@ -175,11 +176,12 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
         if (L - 1 == 0)
             hipLaunchKernelGGL((kb_coarse_rows<T, T, double>), g, dim3(kBlock), 0, s, nL, (const T*)V.ainv,
                                (const T*)E->r[L], (const int*)F.aggptr, (const double*)E->R, (const T*)V.dinv[0],
-                               (const T*)V.p[0], (T*)E->zp[0], done);
+                               (const T*)V.p[0], (T*)E->zp[0], (double*)nullptr, done);
         else
             hipLaunchKernelGGL((kb_coarse_rows<T, T, T>), g, dim3(kBlock), 0, s, nL, (const T*)V.ainv,
                                (const T*)E->r[L], (const int*)F.aggptr, (const T*)E->r[L - 1],
-                               (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], (T*)E->zp[L - 1], done);
+                               (const T*)V.dinv[L - 1], (const T*)V.p[L - 1], (T*)E->zp[L - 1], (double*)nullptr,
+                               done);
     } else if (L - 1 == 0)
         hipLaunchKernelGGL((kb_coarse<T, T, double, false>), dim3(1), dim3(kCoarseThreads), 0, s, nL,
                            (const T*)V.ainv, (const T*)E->r[L], (T*)E->zc, (const int*)F.aggptr, (const double*)E->R,
@@ -570,10 +572,17 @@ static void debug_batch_impl(BatchEngine* E, DevVals<T>& V, int op, const double
         const int g = std::min(kMaxGrid, std::max(1, (I.n * kW + kBlock - 1) / kBlock));
         T* rin = L >= 1 ? (T*)E->r[L] : (T*)E->zc;
         hipLaunchKernelGGL((kb_cols_in<T>), dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.iperm, in, rin);
-        hipLaunchKernelGGL((kb_coarse<T, T, double, true>), dim3(1), dim3(kCoarseThreads), 0, s, I.n,
-                           (const T*)V.ainv, (const T*)rin, (T*)E->Y, (const int*)nullptr, (const double*)nullptr,
-                           (const T*)nullptr, (const T*)nullptr, (T*)nullptr, E->Z, (const double*)E->Z, E->partial,
-                           nodone);
+        // the kernel the cycle runs at this size (a single-level hierarchy
+        // always takes the single-workgroup product)
+        if (L >= 1 && I.n > coarse_rows_min_b<T>())
+            hipLaunchKernelGGL((kb_coarse_rows<T, T, double, true>), dim3(coarse_rows_grid_b<T>(I.n)), dim3(kBlock), 0,
+                               s, I.n, (const T*)V.ainv, (const T*)rin, (const int*)nullptr, (const double*)nullptr,
+                               (const T*)nullptr, (const T*)nullptr, (T*)nullptr, E->Z, nodone);
+        else
+            hipLaunchKernelGGL((kb_coarse<T, T, double, true>), dim3(1), dim3(kCoarseThreads), 0, s, I.n,
+                               (const T*)V.ainv, (const T*)rin, (T*)E->Y, (const int*)nullptr, (const double*)nullptr,
+                               (const T*)nullptr, (const T*)nullptr, (T*)nullptr, E->Z, (const double*)E->Z,
+                               E->partial, nodone);
         hipLaunchKernelGGL(kb_cols_out, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm, (const double*)E->Z,
                            out);
     } else if (op == PAMG_OP_VCYCLE) {
@@ -618,6 +627,41 @@ void batch_retire(BatchEngine* E, int mask) {
     E->st_host->all_done = all;
 }
 
+// Variant index of (unroll, columns per lane), or -1.
+static int variant_of(int unroll, int cpl) {
+    for (int v = 0; v < kNumVariants; ++v)
+        if (variant_unroll(v) == unroll && variant_cpl(v) == cpl) return v;
+    return -1;
+}
+
+void batch_set_config(pamg_hierarchy* h, int prec, const int32_t* cfg) {
+    require_device(h);
+    require_l1_smoother(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    HIP_CHECK(hipSetDevice(h->device));
+    const int L = h->L;
+    std::vector<int> down(L + 1, 2), up(L + 1, 2);
+    for (int l = 0; l < L; ++l) {
+        down[l] = variant_of(cfg[4 * l + 0], cfg[4 * l + 1]);
+        up[l] = l > 0 ? variant_of(cfg[4 * l + 2], cfg[4 * l + 3]) : 2;
+        if (down[l] < 0 || up[l] < 0)
+            throw Error(PAMG_E_INVALID, "kernel variant must be unroll 1, 2, 4, 8 or 16 with 1, 2 or 4 columns "
+                                        "per lane (level " + std::to_string(l) + ")");
+    }
+    BatchEngine* E = get_engine(h, prec, nullptr);
+    HIP_CHECK(hipDeviceSynchronize());
+    for (int k = 0; k < 2; ++k)
+        if (E->graph[k]) {
+            HIP_CHECK(hipGraphExecDestroy(E->graph[k]));
+            E->graph[k] = nullptr;
+            E->graph_k[k] = 0;
+        }
+    for (int l = 0; l < L; ++l) {
+        E->cfg_down[l] = down[l];
+        if (l > 0) E->cfg_up[l] = up[l];
+    }
+}
+
 void batch_config(pamg_hierarchy* h, int prec, int32_t* cfg) {
     require_device(h);
     require_l1_smoother(h);
@@ -655,6 +699,14 @@ int pamg_debug_apply_batch(pamg_hierarchy* h, int32_t op, int32_t precision, con
         if (!h || !in_dev || !out_dev) throw pamg::Error(PAMG_E_INVALID, "null argument");
         pamg::debug_batch(h, op, precision == PAMG_PREC_F32 ? PAMG_PREC_F32 : PAMG_PREC_F64, in_dev, out_dev,
                           (hipStream_t)stream);
+        return PAMG_OK;
+    });
+}
+
+int pamg_batch_set_config(pamg_hierarchy* h, int32_t precision, const int32_t* cfg) {
+    return pamg::guarded([&]() -> int {
+        if (!h || !cfg) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        pamg::batch_set_config(h, precision == PAMG_PREC_F32 ? PAMG_PREC_F32 : PAMG_PREC_F64, cfg);
         return PAMG_OK;
     });
 }

@@ -252,29 +252,37 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_xtx(const double* __res
         }
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
-
 }  // namespace
 
-// A_L^{-1} (FP64, n x n row-major) of the coarsest level from its device CSR.
-void coarse_inverse_device(int n, const int* rp, const int* ci, const double* v, double* ainv, hipStream_t s) {
+std::unique_ptr<DenseWork> dense_work(pamg_context* ctx, int n, hipStream_t s) {
     const int N = (n + kT - 1) / kT * kT;
     const int nb = N / kT;
     const size_t NN = (size_t)N * N;
-    DevBuf M, X, D, flag;
-    HIP_CHECK(hipMalloc(&M.p, NN * sizeof(double)));
-    HIP_CHECK(hipMalloc(&X.p, NN * sizeof(double)));
-    HIP_CHECK(hipMalloc(&D.p, (size_t)nb * kT * kT * sizeof(double)));
-    HIP_CHECK(hipMalloc(&flag.p, sizeof(int)));
-    double* dM = static_cast<double*>(M.p);
-    double* dX = static_cast<double*>(X.p);
-    double* dD = static_cast<double*>(D.p);
-    int* dflag = static_cast<int*>(flag.p);
+    std::unique_ptr<DenseWork> w(new DenseWork());
+    w->ctx = ctx;
+    auto get = [&](size_t bytes) {
+        void* p = ctx_alloc(ctx, bytes, s);
+        w->bufs.push_back({p, bytes});
+        return p;
+    };
+    w->M = static_cast<double*>(get(NN * sizeof(double)));
+    w->X = static_cast<double*>(get(NN * sizeof(double)));
+    w->D = static_cast<double*>(get((size_t)nb * kT * kT * sizeof(double)));
+    w->flag = static_cast<int*>(get(sizeof(int)));
+    return w;
+}
+
+// A_L^{-1} (FP64, n x n row-major) of the coarsest level from its device CSR,
+// in the workspace w (from dense_work for this n).
+void coarse_inverse_device(DenseWork& w, int n, const int* rp, const int* ci, const double* v, double* ainv,
+                           hipStream_t s) {
+    const int N = (n + kT - 1) / kT * kT;
+    const int nb = N / kT;
+    const size_t NN = (size_t)N * N;
+    double* dM = w.M;
+    double* dX = w.X;
+    double* dD = w.D;
+    int* dflag = w.flag;
     HIP_CHECK(hipMemsetAsync(dM, 0, NN * sizeof(double), s));
     HIP_CHECK(hipMemsetAsync(dX, 0, NN * sizeof(double), s));
     HIP_CHECK(hipMemsetAsync(dflag, 0, sizeof(int), s));

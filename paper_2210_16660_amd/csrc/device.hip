@@ -8,6 +8,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "hier.hpp"
@@ -18,7 +19,7 @@ namespace pamg {
 
 template <typename T, typename S>
 static T* upload(pamg_hierarchy* h, const std::vector<S>& src, hipStream_t s) {
-    T* d = dalloc<T>(h, src.size());
+    T* d = dalloc<T>(h, src.size(), s);
     if (src.empty()) return d;
     if constexpr (std::is_same<T, S>::value) {
         HIP_CHECK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
@@ -43,9 +44,9 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         if (l + 1 < nl) {
             V.vd[l] = upload<T>(h, lay[l].vd, s);
             V.p[l] = upload<T>(h, lay[l].p, s);
-            V.zp[l] = dalloc<T>(h, lay[l].dinv.size());
+            V.zp[l] = dalloc<T>(h, lay[l].dinv.size(), s);
         }
-        if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size());
+        if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size(), s);
         maxn = std::max(maxn, lay[l].dinv.size());
     }
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {
@@ -59,23 +60,24 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
                 V.sa_pv[l] = upload<T>(h, lay[l].sa_pv, s);
                 V.sa_tv[l] = upload<T>(h, lay[l].sa_tv, s);
             }
-            V.zt[l] = dalloc<T>(h, lay[l].dinv.size());
+            V.zt[l] = dalloc<T>(h, lay[l].dinv.size(), s);
         }
-        V.zc = dalloc<T>(h, lay[nl - 1].dinv.size());
+        V.zc = dalloc<T>(h, lay[nl - 1].dinv.size(), s);
     }
     // A_L^{-1}: factorized on the device in FP64; the FP32 copy is its rounding
     const DevLevelIdx& C = h->idx[nl - 1];
-    V.ainv = dalloc<T>(h, (size_t)C.n * C.n);
+    V.ainv = dalloc<T>(h, (size_t)C.n * C.n, s);
     if constexpr (std::is_same<T, double>::value) {
-        coarse_inverse_device(C.n, C.rp, C.ci, V.v[nl - 1], V.ainv, s);
+        std::unique_ptr<DenseWork> w = dense_work(h->ctx, C.n, s);
+        coarse_inverse_device(*w, C.n, C.rp, C.ci, V.v[nl - 1], V.ainv, s);
     } else {
         const long long nn = (long long)C.n * C.n;
         hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(nn)), dim3(kBlock), 0, s, nn,
                            (const double*)h->f64.ainv, V.ainv);
         HIP_CHECK(hipStreamSynchronize(s));
     }
-    V.dbg_in = dalloc<T>(h, maxn);
-    V.dbg_in2 = dalloc<T>(h, maxn);
+    V.dbg_in = dalloc<T>(h, maxn, s);
+    V.dbg_in2 = dalloc<T>(h, maxn, s);
     V.built = true;
 }
 
@@ -95,6 +97,19 @@ static uint64_t vcycle_bytes(const pamg_hierarchy* h, int s) {
         const DevLevelIdx& I = h->idx[l];
         const uint64_t n = I.n, nc = h->idx[l + 1].n;
         B += matrix_bytes(I, true, s) + matrix_bytes(I, false, s) + (10 * n + 2 * nc) * s;
+    }
+    const uint64_t nL = h->idx[h->L].n;
+    B += (nL * nL + 2 * nL) * s;
+    return B;
+}
+
+// The same cycle with plain CSR matrices (int32 columns and row pointers).
+static uint64_t csr_vcycle_bytes(const pamg_hierarchy* h, uint64_t s) {
+    uint64_t B = 0;
+    for (int l = 0; l < h->L; ++l) {
+        const DevLevelIdx& I = h->idx[l];
+        const uint64_t n = I.n, nc = h->idx[l + 1].n;
+        B += 2 * ((uint64_t)I.nnz * (4 + s) + 4 * (n + 1)) + (10 * n + 2 * nc) * s;
     }
     const uint64_t nL = h->idx[h->L].n;
     B += (nL * nL + 2 * nL) * s;
@@ -154,20 +169,20 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     const int n0 = h->idx[0].n;
     int maxn = 0;
     for (auto& I : h->idx) maxn = std::max(maxn, I.n);
-    h->x = dalloc<double>(h, n0);
-    h->r = dalloc<double>(h, n0);
-    h->z = dalloc<double>(h, n0);
-    h->p[0] = dalloc<double>(h, n0);
-    h->p[1] = dalloc<double>(h, n0);
-    h->q = dalloc<double>(h, n0);
-    h->b = dalloc<double>(h, n0);
-    h->dbg0 = dalloc<double>(h, maxn);
-    h->dbg1 = dalloc<double>(h, maxn);
-    h->dbg2 = dalloc<double>(h, maxn);
-    h->partial = dalloc<double>(h, 2 * kMaxGrid);
-    h->partial_b = dalloc<double>(h, 2 * kMaxGrid);
-    h->zero_flag = dalloc<int>(h, 1);
-    h->st = dalloc<SolveState>(h, 1);
+    h->x = dalloc<double>(h, n0, s);
+    h->r = dalloc<double>(h, n0, s);
+    h->z = dalloc<double>(h, n0, s);
+    h->p[0] = dalloc<double>(h, n0, s);
+    h->p[1] = dalloc<double>(h, n0, s);
+    h->q = dalloc<double>(h, n0, s);
+    h->b = dalloc<double>(h, n0, s);
+    h->dbg0 = dalloc<double>(h, maxn, s);
+    h->dbg1 = dalloc<double>(h, maxn, s);
+    h->dbg2 = dalloc<double>(h, maxn, s);
+    h->partial = dalloc<double>(h, 2 * kMaxGrid, s);
+    h->partial_b = dalloc<double>(h, 2 * kMaxGrid, s);
+    h->zero_flag = dalloc<int>(h, 1, s);
+    h->st = dalloc<SolveState>(h, 1, s);
     HIP_CHECK(hipMemsetAsync(h->zero_flag, 0, sizeof(int), s));
     HIP_CHECK(hipMemsetAsync(h->st, 0, sizeof(SolveState), s));
     for (double* v : {h->x, h->r, h->z, h->p[0], h->p[1], h->q, h->b, h->dbg0, h->dbg1, h->dbg2})
@@ -186,11 +201,14 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     h->info.operator_complexity = tot / (double)h->idx[0].nnz;
     h->info.vcycle_bytes_f64 = vcycle_bytes(h, 8);
     h->info.vcycle_bytes_f32 = build_f32 ? vcycle_bytes(h, 4) : 0;
+    h->info.csr_vcycle_bytes_f64 = csr_vcycle_bytes(h, 8);
+    h->info.csr_vcycle_bytes_f32 = build_f32 ? csr_vcycle_bytes(h, 4) : 0;
     h->info.spmv_bytes = matrix_bytes(h->idx[0], false, 8) + 2 * 8 * (uint64_t)n0;
 }
 
 void destroy_hierarchy(pamg_hierarchy* h) {
     if (h->host_only) {
+        if (h->ctx) h->ctx->users.fetch_sub(1);
         delete h;
         return;
     }
@@ -201,8 +219,9 @@ void destroy_hierarchy(pamg_hierarchy* h) {
         for (int b = 0; b < 2; ++b)
             if (h->graph[a][b]) (void)hipGraphExecDestroy(h->graph[a][b]);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    for (void* p : h->allocs) (void)hipFree(p);
+    ctx_free_all(h->ctx, h->allocs);
     if (h->st_host) (void)hipHostFree(h->st_host);
+    h->ctx->users.fetch_sub(1);
     delete h;
 }
 
@@ -230,7 +249,7 @@ static void launch_down(const DevLevelIdx& I, const T* vd, const RT* r, const T*
                         hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_down<IT, T, RT, RT>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
+        LAUNCH((k_down<IT, T, RT, RT>), tile_grid(I.n_down), (tile_lds_bytes<IT, T>(I.down_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, vd, r, r, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
                I.down_loc, rc, done);
     });
@@ -242,7 +261,7 @@ static void launch_resid_restrict(const DevLevelIdx& I, const T* v, const RT* r,
                                   const int* done, hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_down<IT, T, RT, T>), tile_grid(I.n_down), I.down_dmax * sizeof(T), s, (const int*)I.rp,
+        LAUNCH((k_down<IT, T, RT, T>), tile_grid(I.n_down), (tile_lds_bytes<IT, T>(I.down_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, v, r, z, p, (const int*)I.aggptr, I.down_tiles, I.n_down, I.down_span, I.down_col,
                I.down_loc, rc, done);
     });
@@ -257,15 +276,15 @@ static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
         if constexpr (OUT) {
-            LAUNCH((k_up<IT, T, RT, RTF, kUpOut>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+            LAUNCH((k_up<IT, T, RT, RTF, kUpOut>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                    (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
                    r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
         } else if (F->max_agg <= 2) {
-            LAUNCH((k_up<IT, T, RT, RTF, kUpPair>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+            LAUNCH((k_up<IT, T, RT, RTF, kUpPair>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                    (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
                    r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
         } else {
-            LAUNCH((k_up<IT, T, RT, RTF, kUpWide>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+            LAUNCH((k_up<IT, T, RT, RTF, kUpWide>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                    (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
                    r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
         }
@@ -277,7 +296,7 @@ static void launch_spmv(const DevLevelIdx& I, const T* v, const XT* x, const dou
                         hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+        LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, partial);
     });
 }
@@ -287,7 +306,7 @@ template <typename T, typename XT, typename YT, typename BT>
 static void launch_resid(const DevLevelIdx& I, const T* v, const XT* x, const BT* b, YT* y, hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_spmv<IT, T, XT, YT, BT>), tile_grid(I.n_up), I.up_dmax * sizeof(T), s, (const int*)I.rp,
+        LAUNCH((k_spmv<IT, T, XT, YT, BT>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, (double*)nullptr);
     });
 }
@@ -297,7 +316,7 @@ static void launch_krylov(const DevLevelIdx& I, const double* v, const double* z
                           hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), I.up_dmax * sizeof(double), s, (const int*)I.rp,
+        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), (tile_lds_bytes<IT, double>(I.up_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, v, z, p_old, p_new, q, r, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, st,
                partial, done);
     });
@@ -545,11 +564,11 @@ static double true_relres(pamg_hierarchy* h, hipStream_t s) {
     const DevLevelIdx& I = h->idx[0];
     const int g = tile_grid(I.n_up);
     launch_spmv<double, double>(I, h->f64.v[0], h->x, h->b, h->dbg0, h->partial_b, s);
-    std::vector<double> part(g);
-    HIP_CHECK(hipMemcpyAsync(part.data(), h->partial_b, sizeof(double) * g, hipMemcpyDeviceToHost, s));
+    double part[kMaxGrid];        // g <= kMaxGrid; no heap allocation on the solve path
+    HIP_CHECK(hipMemcpyAsync(part, h->partial_b, sizeof(double) * g, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     double rr = 0.0;
-    for (double v : part) rr += v;
+    for (int i = 0; i < g; ++i) rr += part[i];
     return std::sqrt(rr) / h->st_host->bnorm;
 }
 
@@ -973,16 +992,19 @@ int time_op(pamg_hierarchy* h, int op, int level, int prec, int reps, hipStream_
     return PAMG_OK;
 }
 
-pamg_hierarchy* new_hierarchy(bool host_only) {
+pamg_hierarchy* new_hierarchy(bool host_only, pamg_context* ctx) {
+    if (!host_only && !ctx) {
+        int dev = 0;
+        HIP_CHECK(hipGetDevice(&dev));
+        ctx = default_context(dev);
+    }
+    if (!host_only) HIP_CHECK(hipSetDevice(ctx->device));
     pamg_hierarchy* h = new pamg_hierarchy();
     h->host_only = host_only;
-    if (!host_only) {
-        try {
-            HIP_CHECK(hipGetDevice(&h->device));
-        } catch (...) {
-            delete h;
-            throw;
-        }
+    h->ctx = ctx;
+    if (ctx) {
+        h->device = ctx->device;
+        ctx->users.fetch_add(1);
     }
     return h;
 }
@@ -1040,9 +1062,9 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
 
 int coarsest_n(const HostBuild& b) { return b.H.lev.back().A.n; }
 
-pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream) {
+pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, pamg_context* ctx) {
     auto t0 = std::chrono::steady_clock::now();
-    pamg_hierarchy* h = new_hierarchy(b->prm.host_only != 0);
+    pamg_hierarchy* h = new_hierarchy(b->prm.host_only != 0, ctx);
     h->smoother = b->prm.smoother;
     h->smoothed_p = b->prm.smooth_prolongator != 0;
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
@@ -1050,6 +1072,7 @@ pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream) {
         h->gs_block = b->prm.gs_block > 0 ? b->prm.gs_block : 256;
         h->omega = b->prm.omega > 0.0 ? b->prm.omega : 1.5;
     }
+    for (size_t l = 0; l < b->lay.size() && l < (size_t)PAMG_MAX_LEVELS; ++l) h->info.tile_items[l] = b->lay[l].items;
     try {
         h->host = std::move(b->H);
         if (b->prm.host_only) {
@@ -1109,14 +1132,14 @@ int pamg_solve_opts_default(pamg_solve_opts* o) {
     return PAMG_OK;
 }
 
-int pamg_setup(const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out) {
+int pamg_setup(pamg_context* ctx, const pamg_csr* A, const pamg_params* params, void* stream, pamg_hierarchy** out) {
     return pamg::guarded([&]() -> int {
         if (!A || !out) throw pamg::Error(PAMG_E_INVALID, "null argument");
         *out = nullptr;
         pamg_params prm;
         if (params) prm = *params; else pamg_params_default(&prm);
         std::unique_ptr<pamg::HostBuild> hb = pamg::host_build(*A, prm);
-        *out = pamg::finish_build(std::move(hb), (hipStream_t)stream);
+        *out = pamg::finish_build(std::move(hb), (hipStream_t)stream, ctx);
         return PAMG_OK;
     });
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -18,7 +19,31 @@
                                 std::string(#call) + ": " + hipGetErrorString(e_));                  \
     } while (0)
 
+// Device and allocator of a family of hierarchies, engines and servers.
+struct pamg_context {
+    int device = 0;
+    pamg_allocator a{};                     // a.alloc == nullptr: hipMalloc / hipFree
+    std::atomic<uint64_t> allocs{0}, frees{0}, failed{0}, live{0}, peak{0};
+    std::atomic<int> users{0};
+};
+
 namespace pamg {
+
+// A device buffer and its size, as the context handed it out.
+struct DevAlloc {
+    void* p;
+    size_t bytes;
+};
+
+// The per-device context of callers that pass none (hipMalloc / hipFree;
+// created on first use, kept until the process ends).
+pamg_context* default_context(int device);
+// bytes (> 0) from the context's allocator for use on stream s; throws
+// PAMG_E_OOM when the allocator fails.
+void* ctx_alloc(pamg_context* c, size_t bytes, hipStream_t s);
+void ctx_free(pamg_context* c, void* p, size_t bytes, hipStream_t s);
+// Free a list of buffers (the device must be idle) and clear it.
+void ctx_free_all(pamg_context* c, std::vector<DevAlloc>& list);
 
 template <typename T>
 struct DevVals {
@@ -82,6 +107,7 @@ struct ReusePlan {
 }  // namespace pamg
 
 struct pamg_hierarchy {
+    pamg_context* ctx = nullptr;
     int device = 0;
     int L = 0;
     bool host_only = false;
@@ -101,7 +127,7 @@ struct pamg_hierarchy {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int graph_k[2][2] = {{0, 0}, {0, 0}};
-    std::vector<void*> allocs;
+    std::vector<pamg::DevAlloc> allocs;
     pamg::HostHierarchy host;
     pamg_hier_info info{};
     std::mutex mu;
@@ -112,13 +138,14 @@ struct pamg_hierarchy {
 
 namespace pamg {
 
+// A device array of the hierarchy (freed with it), from its context.
 template <typename T>
-inline T* dalloc(pamg_hierarchy* h, size_t count) {
-    void* p = nullptr;
+inline T* dalloc(pamg_hierarchy* h, size_t count, hipStream_t s = nullptr) {
     if (count == 0) count = 1;
-    HIP_CHECK(hipMalloc(&p, count * sizeof(T)));
-    h->allocs.push_back(p);
-    h->info.device_bytes += count * sizeof(T);
+    const size_t bytes = count * sizeof(T);
+    void* p = ctx_alloc(h->ctx, bytes, s);
+    h->allocs.push_back({p, bytes});
+    h->info.device_bytes += bytes;
     return static_cast<T*>(p);
 }
 
@@ -140,14 +167,28 @@ struct HostBuild {
 };
 std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm);
 int coarsest_n(const HostBuild& b);
-pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream);
+// ctx: the context the hierarchy allocates from (null: the current device's default)
+pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, pamg_context* ctx);
 
 // Dense limit of the coarsest level (its FP64 inverse is n_L^2 doubles).
 constexpr int kMaxDense = 8192;
 // A_L^{-1} (FP64, n x n row-major, symmetric) of the coarsest level from its
 // device CSR: Cholesky and inverse on the matrix cores (dense.hip).  Throws
 // PAMG_E_NOT_SPD on a non-positive pivot.  Synchronizes the stream.
-void coarse_inverse_device(int n, const int* rp, const int* ci, const double* v, double* ainv, hipStream_t s);
+// Device workspace of the dense factorization of an n-row coarsest level,
+// from the context (allocated before anything it is used for is changed).
+struct DenseWork {
+    pamg_context* ctx = nullptr;
+    std::vector<DevAlloc> bufs;
+    double *M = nullptr, *X = nullptr, *D = nullptr;
+    int* flag = nullptr;
+    ~DenseWork() {
+        if (ctx) ctx_free_all(ctx, bufs);
+    }
+};
+std::unique_ptr<DenseWork> dense_work(pamg_context* ctx, int n, hipStream_t s);
+void coarse_inverse_device(DenseWork& w, int n, const int* rp, const int* ci, const double* v, double* ainv,
+                           hipStream_t s);
 // Single-right-hand-side FCG (x0 = 0) in steps on a caller's stream, with the
 // arithmetic of pamg_solve: begin, blocks of k iterations each followed by an
 // asynchronous copy of the state to its host copy, the true residual and a

@@ -164,15 +164,41 @@ __device__ __forceinline__ void tile_local(const uint16_t* __restrict__ loc, con
     for (int it = 0; it < ITEMS; ++it) li[it] = ld_stream(&loc[kk[it]]);
 }
 
+// Dictionary tiles: the products a_k x_c(k) are formed in registers (a is
+// overwritten), then, after a barrier that ends every read of the
+// dictionary values, stored over them: the products and the dictionary share
+// one LDS buffer of max(ITEMS * kBlock, dictionary length) values, which
+// keeps four workgroups of the largest tiles resident per CU.
 template <int ITEMS, typename T>
-__device__ __forceinline__ void tile_store_dict(int k0, int k1, const T (&a)[ITEMS], const uint16_t (&li)[ITEMS],
-                                                const T* s_x, T* s_prod) {
+__device__ __forceinline__ void tile_products_dict(T (&a)[ITEMS], const uint16_t (&li)[ITEMS], const T* s_x) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) a[it] = a[it] * s_x[li[it]];
+}
+
+template <int ITEMS, typename T>
+__device__ __forceinline__ void tile_store_prod(int k0, int k1, const T (&prod)[ITEMS], T* s_prod) {
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const int k = k0 + it * kBlock + (int)threadIdx.x;
-        if (k < k1) s_prod[k - k0] = a[it] * s_x[li[it]];
+        if (k < k1) s_prod[k - k0] = prod[it];
     }
 }
+
+// Dynamic LDS bytes of a tile kernel launch: the dictionary values (dmax of
+// the level), which dictionary tiles also use for their products.
+template <int ITEMS, typename T>
+inline size_t tile_lds_bytes(int dmax) {
+    const int n = tile_uses_dict<ITEMS>() ? (dmax > ITEMS * kBlock ? dmax : ITEMS * kBlock) : dmax;
+    return (size_t)n * sizeof(T);
+}
+
+// Products array of a tile kernel: the dynamic buffer for dictionary tiles,
+// a static one (sized ITEMS * kBlock) otherwise.
+#define PAMG_TILE_LDS(T, ITEMS)                                                                  \
+    __shared__ T s_prod_static[tile_uses_dict<ITEMS>() ? 1 : ITEMS * kBlock];                   \
+    extern __shared__ __align__(16) unsigned char s_dyn[];                                       \
+    T* s_x = reinterpret_cast<T*>(s_dyn);                                                        \
+    T* s_prod = tile_uses_dict<ITEMS>() ? s_x : s_prod_static;
 
 // ----------------------------------------------------------------------------
 // Down-sweep at level l (pre-smooth from zero, residual, restriction):
@@ -187,11 +213,9 @@ static __global__ __launch_bounds__(kBlock) void k_down(
     const int4* __restrict__ tiles, int ntiles,
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, T* __restrict__ rc, const int* __restrict__ done) {
     if (*done) return;
-    __shared__ T s_prod[ITEMS * kBlock];
+    PAMG_TILE_LDS(T, ITEMS)
     __shared__ T s_u[kBlock];
     __shared__ T s_red[kBlock / 64];
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     for (int t = w.first; t < w.end; t += w.stride) {
@@ -227,7 +251,9 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             const int a0 = aggptr[Ic] - f0, a1 = aggptr[Ic + 1] - f0;
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
-                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+                tile_products_dict<ITEMS>(a, li, s_x);
+                __syncthreads();                // dictionary reads done: products take its place
+                tile_store_prod<ITEMS>(k0, k1, a, s_prod);
             } else {
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
@@ -283,13 +309,11 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     const int* __restrict__ done) {
     constexpr bool TO_OUT = MODE == kUpOut;
     if (*done) return;
-    __shared__ T s_prod[ITEMS * kBlock];
+    PAMG_TILE_LDS(T, ITEMS)
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
     __shared__ T s_z[kBlock];                          // kUpWide: z of the tile's rows
     __shared__ uint8_t s_own[kBlock << kMaxAggSteps];  // kUpWide: owning row of each fine row
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double dot = 0.0;
@@ -336,7 +360,9 @@ static __global__ __launch_bounds__(kBlock) void k_up(
             }
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
-                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+                tile_products_dict<ITEMS>(a, li, s_x);
+                __syncthreads();                // dictionary reads done: products take its place
+                tile_store_prod<ITEMS>(k0, k1, a, s_prod);
             } else {
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
@@ -528,11 +554,9 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
     const XT* __restrict__ xv, const BT* __restrict__ b, YT* __restrict__ y,
     const int4* __restrict__ tiles, int ntiles,
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, double* __restrict__ partial) {
-    __shared__ T s_prod[ITEMS * kBlock];
+    PAMG_TILE_LDS(T, ITEMS)
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    T* s_x = reinterpret_cast<T*>(s_dyn);
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double nrm = 0.0;
@@ -566,7 +590,9 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             const double bi = b ? (double)b[ic] : 0.0;
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
-                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+                tile_products_dict<ITEMS>(a, li, s_x);
+                __syncthreads();                // dictionary reads done: products take its place
+                tile_store_prod<ITEMS>(k0, k1, a, s_prod);
             } else {
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }
@@ -613,10 +639,8 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc,
     const SolveState* __restrict__ st, double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
-    __shared__ double s_prod[ITEMS * kBlock];
+    PAMG_TILE_LDS(double, ITEMS)
     __shared__ double s_red[kBlock / 64];
-    extern __shared__ __align__(16) unsigned char s_dyn[];
-    double* s_x = reinterpret_cast<double*>(s_dyn);
     const int tid = threadIdx.x;
     const bool first = st->first != 0;
     const double beta = st->beta;
@@ -647,7 +671,9 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             const double zi = z[ic], poi = p_old[ic], ri = r[ic];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
-                tile_store_dict<ITEMS>(k0, k1, a, li, s_x, s_prod);
+                tile_products_dict<ITEMS>(a, li, s_x);
+                __syncthreads();                // dictionary reads done: products take its place
+                tile_store_prod<ITEMS>(k0, k1, a, s_prod);
             } else {
                 tile_store<ITEMS>(k0, k1, a, x, s_prod);
             }

@@ -324,7 +324,8 @@ static __global__ __launch_bounds__(kCoarseThreads) void kb_coarse(
 }
 
 // Large coarsest level (L >= 1): the product and the prolongation into level
-// L-1 spread over many workgroups of 256 threads.  FP64: one wave per 16-row
+// L-1 spread over many workgroups of 256 threads (OUT: the product is written
+// to z_out instead, n_L x 16 in FP64, for the per-operator parity check).  FP64: one wave per 16-row
 // block on the matrix cores (four waves, 64 rows per workgroup), prolongated
 // straight from the result registers.  FP32: a workgroup owns 16 rows and its
 // threads split the columns j in 16 fixed ranges (one row and all 16
@@ -344,11 +345,11 @@ inline int coarse_rows_grid_b(int nL) {
     return (nL + coarse_rows_block_rows_b<T>() - 1) / coarse_rows_block_rows_b<T>();
 }
 
-template <typename T, typename RT, typename RTF>
+template <typename T, typename RT, typename RTF, bool OUT = false>
 static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
     int nL, const T* __restrict__ ainv, const RT* __restrict__ r,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
-    const T* __restrict__ p_f, T* __restrict__ zp_f, const int* __restrict__ done) {
+    const T* __restrict__ p_f, T* __restrict__ zp_f, double* __restrict__ z_out, const int* __restrict__ done) {
     if (*done) return;
     const int tid = threadIdx.x, wave = tid / 64, l = tid % 64;
     if constexpr (std::is_same<T, double>::value) {
@@ -369,6 +370,10 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
             const int I = rb * 16 + 4 * i + (l / 16);
             if (I >= nL) continue;
             const T z = acc[i];
+            if constexpr (OUT) {
+                z_out[(size_t)I * kW + c] = (double)z;
+                continue;
+            }
             for (int mm = aggptr_f[I]; mm < aggptr_f[I + 1]; ++mm)
                 zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
         }
@@ -397,6 +402,10 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
             if (II >= nL) continue;
             T z = s_part[0][row][c];
             for (int q = 1; q < G; ++q) z += s_part[q][row][c];
+            if constexpr (OUT) {
+                z_out[(size_t)II * kW + c] = (double)z;
+                continue;
+            }
             for (int mm = aggptr_f[II]; mm < aggptr_f[II + 1]; ++mm)
                 zp_f[(size_t)mm * kW + c] = prolong_value(dinv_f[mm], (T)r_f[(size_t)mm * kW + c], p_f[mm], z);
         }

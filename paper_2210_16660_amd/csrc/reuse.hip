@@ -83,15 +83,6 @@ static __global__ __launch_bounds__(kBlock) void k_diag_inverse(int n, const int
             if (ci[k] == i) ainv[i] = 1.0 / v[k];
 }
 
-template <typename T>
-static T* to_device(pamg_hierarchy* h, const std::vector<T>& src, hipStream_t s) {
-    T* d = dalloc<T>(h, src.size());
-    if (!src.empty()) {
-        HIP_CHECK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-    }
-    return d;
-}
 
 // The pairwise chain behind the kept levels: pattern, aggregates and p of
 // pairwise level m.
@@ -108,9 +99,32 @@ struct ChainView {
     int kept_level(int m) const { return H.chain.empty() ? m : H.chain[m].kept; }
 };
 
+// The plan's device arrays: kept in a list of their own until the plan is
+// complete, so that a failed allocation leaves the hierarchy as it was.
+struct PlanAllocs {
+    pamg_context* ctx;
+    std::vector<DevAlloc> list;
+    ~PlanAllocs() { ctx_free_all(ctx, list); }
+};
+
 static void build_plan(pamg_hierarchy* h, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<ReusePlan> R(new ReusePlan());
+    PlanAllocs pa{h->ctx, {}};
+    auto dalloc_plan = [&](size_t bytes) {
+        void* p = ctx_alloc(h->ctx, bytes, s);
+        pa.list.push_back({p, bytes});
+        return p;
+    };
+    auto to_device = [&](const auto& src) {
+        using T = typename std::decay<decltype(src)>::type::value_type;
+        T* d = static_cast<T*>(dalloc_plan(std::max<size_t>(1, src.size()) * sizeof(T)));
+        if (!src.empty()) {
+            HIP_CHECK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
+        return d;
+    };
     const ChainView C{h->host};
     const int npw = C.levels(), nk = h->L + 1;
     R->npw = npw;
@@ -123,13 +137,13 @@ static void build_plan(pamg_hierarchy* h, hipStream_t s) {
         if (R->kept_pw[j] < 0) throw Error(PAMG_E_DEVICE, "reuse plan: kept level without a pairwise level");
     for (int m = 0; m < npw; ++m) {
         R->nnz.push_back(C.pattern(m).nnz());
-        R->vcan.push_back(dalloc<double>(h, (size_t)C.pattern(m).nnz()));
+        R->vcan.push_back(static_cast<double*>(dalloc_plan(sizeof(double) * std::max<size_t>(1, C.pattern(m).nnz()))));
     }
     for (int m = 0; m + 1 < npw; ++m) {
         GalerkinPlan g = galerkin_plan(C.pattern(m), C.agg(m), C.p(m), C.pattern(m + 1));
-        R->gptr.push_back(to_device(h, g.ptr, s));
-        R->gk.push_back(to_device(h, g.k, s));
-        R->gpp.push_back(to_device(h, g.pp, s));
+        R->gptr.push_back(to_device(g.ptr));
+        R->gk.push_back(to_device(g.k));
+        R->gpp.push_back(to_device(g.pp));
     }
     for (int j = 0; j < nk; ++j) {
         const HostCSR& A = h->host.lev[j].A;
@@ -137,18 +151,24 @@ static void build_plan(pamg_hierarchy* h, hipStream_t s) {
         std::vector<int32_t> perm(I.n), iperm(I.n);
         HIP_CHECK(hipMemcpy(perm.data(), I.perm, sizeof(int32_t) * I.n, hipMemcpyDeviceToHost));
         HIP_CHECK(hipMemcpy(iperm.data(), I.iperm, sizeof(int32_t) * I.n, hipMemcpyDeviceToHost));
-        R->crp.push_back(to_device(h, A.rp, s));
-        R->hperm.push_back(to_device(h, entry_order(A, perm, iperm), s));
-        R->dcan.push_back(dalloc<double>(h, (size_t)I.n));
+        R->crp.push_back(to_device(A.rp));
+        R->hperm.push_back(to_device(entry_order(A, perm, iperm)));
+        R->dcan.push_back(static_cast<double*>(dalloc_plan(sizeof(double) * std::max<size_t>(1, I.n))));
     }
     const HostCSR& A0 = h->host.lev[0].A;
     std::vector<int32_t> dpos(A0.n, 0);
     for (int32_t i = 0; i < A0.n; ++i)
         for (int32_t k = A0.rp[i]; k < A0.rp[i + 1]; ++k)
             if (A0.ci[k] == i) dpos[i] = k;
-    R->dpos0 = to_device(h, dpos, s);
-    R->flag = dalloc<int>(h, 1);
+    R->dpos0 = to_device(dpos);
+    R->flag = static_cast<int*>(dalloc_plan(sizeof(int)));
     R->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // complete: the arrays now belong to the hierarchy
+    for (const DevAlloc& a : pa.list) {
+        h->allocs.push_back(a);
+        h->info.device_bytes += a.bytes;
+    }
+    pa.list.clear();
     h->reuse = std::move(R);
 }
 
@@ -167,6 +187,9 @@ static void update_values(pamg_hierarchy* h, const double* val, bool on_device, 
     HIP_CHECK(hipMemcpyAsync(&bad, R.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     if (bad) throw Error(PAMG_E_INVALID, "new values: non-finite value or non-positive diagonal");
+    // workspace of the coarsest factorization, before any value is changed
+    const DevLevelIdx& CL = h->idx[h->L];
+    std::unique_ptr<DenseWork> dw = dense_work(h->ctx, CL.n, s);
     // the pairwise Galerkin chain
     for (int m = 0; m + 1 < R.npw; ++m) {
         const int ne = (int)R.nnz[m + 1];
@@ -207,8 +230,7 @@ static void update_values(pamg_hierarchy* h, const double* val, bool on_device, 
     HIP_CHECK(hipGetLastError());
     h->values_updated = true;
     // the coarsest level: factorization and inverse (synchronizes)
-    const DevLevelIdx& CL = h->idx[h->L];
-    coarse_inverse_device(CL.n, CL.rp, CL.ci, V.v[h->L], V.ainv, s);
+    coarse_inverse_device(*dw, CL.n, CL.rp, CL.ci, V.v[h->L], V.ainv, s);
     if (h->f32.built) {
         const long long nn = (long long)CL.n * CL.n;
         hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(nn)), dim3(kBlock), 0, s, nn,

@@ -85,6 +85,7 @@ struct ServeGroup {
 
 struct pamg_server {
     pamg_server_opts opts{};
+    pamg_context* ctx = nullptr;                     // allocator of every hierarchy built here
     int device = 0;
     std::thread th;
     std::mutex mu;
@@ -275,7 +276,7 @@ static void admit_ready(pamg_server* S) {
         const double host_ms = j->built->host_ms;
         const auto t0 = Clock::now();
         try {
-            g->h = finish_build(std::move(j->built), g->stream);
+            g->h = finish_build(std::move(j->built), g->stream, S->ctx);
         } catch (const Error& e) {
             release_streams(g.get());
             it = S->setups.erase(it);
@@ -603,11 +604,18 @@ int pamg_server_estimate_bytes(const pamg_csr* A, int32_t precision, uint64_t* o
     });
 }
 
-int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
+int pamg_server_create(pamg_context* ctx, const pamg_server_opts* opts, pamg_server** out) {
     return pamg::guarded([&]() -> int {
         if (!out) throw pamg::Error(PAMG_E_INVALID, "null argument");
         *out = nullptr;
         std::unique_ptr<pamg_server> S(new pamg_server());
+        if (!ctx) {
+            int dev = 0;
+            HIP_CHECK(hipGetDevice(&dev));
+            ctx = pamg::default_context(dev);
+        }
+        HIP_CHECK(hipSetDevice(ctx->device));
+        S->ctx = ctx;
         if (opts) S->opts = *opts; else pamg_server_opts_default(&S->opts);
         if (S->opts.block_iters < 2) S->opts.block_iters = 2;
         if (S->opts.block_iters & 1) S->opts.block_iters += 1;
@@ -616,8 +624,9 @@ int pamg_server_create(const pamg_server_opts* opts, pamg_server** out) {
         if (S->opts.setup_workers <= 0) S->opts.setup_workers = 1;
         if (S->opts.setup_workers > 16) S->opts.setup_workers = 16;
         if (S->opts.hbm_budget_bytes == 0) throw pamg::Error(PAMG_E_INVALID, "zero HBM budget");
-        HIP_CHECK(hipGetDevice(&S->device));
+        S->device = ctx->device;
         S->stats.hbm_budget_bytes = S->opts.hbm_budget_bytes;
+        ctx->users.fetch_add(1);
         pamg_server* raw = S.release();
         raw->th = std::thread(pamg::scheduler_main, raw);
         const int workers = raw->opts.setup_workers;
@@ -696,6 +705,7 @@ int pamg_server_destroy(pamg_server* S) {
             delete kv.second->single;
             delete kv.second;
         }
+        S->ctx->users.fetch_sub(1);
         delete S;
         return PAMG_OK;
     });

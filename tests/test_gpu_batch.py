@@ -188,3 +188,44 @@ def test_batch_autotuner_choices(built):
     assert len(cfg) == H.levels - 1
     for du, dc, uu, uc in cfg:
         assert du in (1, 2, 4, 8, 16) and uu in (1, 2, 4, 8, 16) and dc in (1, 2, 4) and uc in (1, 2, 4)
+
+
+@pytest.mark.parametrize("case", ["q1_20", "varcoef_22_composed2"])
+@pytest.mark.parametrize("prec", [pamg.PREC_F64, pamg.PREC_F32])
+def test_every_kernel_variant_gives_the_same_columns(built, case, prec):
+    # the autotuner's fifteen (unroll, columns per lane) variants change only
+    # scheduling: pin each one on every level in turn, and a mixed assignment,
+    # and every column must come out bitwise the same
+    A, O, H, Bm = built(case)
+    L = H.levels - 1
+    tuned = H.batch_config(prec)
+    variants = [(u, c) for c in (1, 2, 4) for u in (1, 2, 4, 8, 16)]
+    rng = SplitMix64(77)
+    picks = rng.integers(2 * L, 0, len(variants) - 1)
+    mixed = [variants[int(picks[2 * l])] + variants[int(picks[2 * l + 1])] for l in range(L)]
+    configs = [[v + v] * L for v in variants] + [mixed]
+    ref = None
+    try:
+        for cfg in configs:
+            H.set_batch_config(cfg, precision=prec)
+            assert H.batch_config(prec)[1:] == cfg[1:] and H.batch_config(prec)[0][:2] == cfg[0][:2]
+            X = torch.zeros(Bm.shape, dtype=torch.float64, device="cuda:0")
+            infos = H.solve_batch(dev(Bm), X, tol=1e-8, precision=prec)
+            got = (X.cpu().numpy(), [i.iterations for i in infos])
+            if ref is None:
+                ref = got
+                continue
+            assert got[1] == ref[1], cfg
+            assert np.array_equal(got[0].view(np.uint64), ref[0].view(np.uint64)), f"variant {cfg[0]} differs"
+    finally:
+        H.set_batch_config(tuned, precision=prec)
+    assert H.batch_config(prec) == tuned
+
+
+def test_batch_set_config_rejects_unknown_variants(built):
+    A, O, H, Bm = built("lap7_24")
+    L = H.levels - 1
+    with pytest.raises(pamg.PamgError):
+        H.set_batch_config([(3, 1, 4, 1)] * L)
+    with pytest.raises(pamg.PamgError):
+        H.set_batch_config([(4, 8, 4, 1)] * L)

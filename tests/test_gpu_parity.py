@@ -67,9 +67,20 @@ CASES = {
     # aggregate-size composition: aggregates of up to 8 unknowns (every third
     # pairwise level kept, prolongators multiplied)
     "q1_24_composed3": lambda: q1_stretched(24, 1.05),
+    # the shapes of the large levels: level 0 in 4096-entry tiles with 16-bit
+    # column dictionaries (ITEMS 16) and level 1 in 2048-entry dictionary
+    # tiles (ITEMS 8) ...
+    "q1_64_dict16": lambda: q1_stretched(64, 1.05),
+    # ... level 0 in 2048-entry dictionary tiles ...
+    "q1_48_dict8": lambda: q1_stretched(48, 1.05),
+    # ... and 4096-entry tiles prolongated into by aggregates of up to 8 rows
+    # (the fine-row-parallel up-sweep)
+    "q1_64_dict16_composed3": lambda: q1_stretched(64, 1.05),
 }
 KW = {"single_level_lap7_5": {"max_coarse": 1000}, "single_level_lap7_13": {"max_coarse": 4000},
-      "q1_24_composed3": {"agg_steps": 3}}
+      "q1_24_composed3": {"agg_steps": 3}, "q1_64_dict16_composed3": {"agg_steps": 3}}
+# tile capacity (entries per thread) the large-level cases must exercise at levels 0 and 1
+TILE_ITEMS = {"q1_64_dict16": (16, 8), "q1_48_dict8": (8, 4), "q1_64_dict16_composed3": (16, None)}
 
 
 @pytest.fixture(scope="module")
@@ -109,6 +120,10 @@ def test_operators_every_level(built, case, prec):
     tol = 1e-13 if prec == pamg.PREC_F64 else 2e-6
     L = O.nlevels - 1
     assert H.levels == O.nlevels
+    if case in TILE_ITEMS:
+        info = H.info()
+        for l, items in enumerate(TILE_ITEMS[case]):
+            assert items is None or info.tile_items[l] == items, (l, info.tile_items[l])
     for l in range(L + 1):
         n = O.n(l)
         x = rand(n, 100 + l)
