@@ -232,6 +232,25 @@ int pamg_hierarchy_update_values(pamg_hierarchy *h, const double *val, int32_t o
 int pamg_solve(pamg_hierarchy *h, const double *b_dev, double *x_dev, const pamg_solve_opts *opts,
                void *stream, pamg_solve_info *info);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): pamg_solve that makes no
+ * allocation of any kind (device, pinned or host heap).  The solve state and
+ * the reduction partials live in one static device array of
+ * PAMG_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on
+ * holds until the process ends, instead of the hierarchy's own buffers; the
+ * iterations are launched directly (opts->use_graph is ignored, since
+ * instantiating a graph allocates).  Arguments, ownership and results are
+ * those of pamg_solve, and x is bitwise what pamg_solve returns for the
+ * same options.  Every call on one GPU shares that GPU's array (whatever the
+ * hierarchy or stream), which keeps the last call's contents: calls that
+ * overlap on one GPU race and must be serialized by the caller.  Errors: as
+ * pamg_solve; INVALID also for a hierarchy whose reductions need more
+ * partials than the array holds (2 * 2048 per buffer; hierarchies built by
+ * pamg_setup never do: their launches use at most 2048 workgroups). */
+#define PAMG_NOALLOC_SCRATCH_BYTES 66048
+int pamg_solve_noalloc(pamg_hierarchy *h, const double *b_dev, double *x_dev, const pamg_solve_opts *opts,
+                       void *stream, pamg_solve_info *info);
+
 /* Solve A X = B for 1 <= nrhs <= 16 right-hand sides at once (successive time
  * steps, or independent requests on one operator; Sec. 2: one matrix, many
  * solves).  Column j of B is at B_dev + j*ldb, of X at X_dev + j*ldx (device,

@@ -111,6 +111,7 @@ SIGNATURES = {
                                            C.POINTER(C.c_double)]),
     "pamg_hierarchy_update_values": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
     "pamg_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(pamg_solve_opts), _VP, C.POINTER(pamg_solve_info)]),
+    "pamg_solve_noalloc": (C.c_int, [_VP, _VP, _VP, C.POINTER(pamg_solve_opts), _VP, C.POINTER(pamg_solve_info)]),
     "pamg_solve_batch": (C.c_int, [_VP, C.c_int32, _VP, C.c_int64, _VP, C.c_int64, C.POINTER(pamg_solve_opts), _VP,
                                    C.POINTER(pamg_solve_info)]),
     "pamg_batch_config": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32)]),
@@ -371,6 +372,16 @@ class Hierarchy:
         info = pamg_solve_info()
         _check(lib().pamg_solve(self._h, _ptr(b), _ptr(x), C.byref(o), _stream(stream), C.byref(info)),
                "pamg_solve", allow=(OK, NOT_CONVERGED))
+        return info
+
+    def solve_noalloc(self, b, x, stream=None, **kw):
+        """pamg_solve_noalloc: as solve(), with no allocation of any kind (the
+        solve state and partials in the library's static per-GPU scratch,
+        direct launches).  Calls on one GPU must not overlap."""
+        o = solve_opts(**kw)
+        info = pamg_solve_info()
+        _check(lib().pamg_solve_noalloc(self._h, _ptr(b), _ptr(x), C.byref(o), _stream(stream), C.byref(info)),
+               "pamg_solve_noalloc", allow=(OK, NOT_CONVERGED))
         return info
 
     def solve_batch(self, B, X, stream=None, **kw):

@@ -674,6 +674,102 @@ static void solve_impl(pamg_hierarchy* h, DevVals<T>& V, int prec, const double*
     }
 }
 
+// ---------------------------------------------------------------- no-allocation solve
+// pamg_solve for callers that cannot allocate: the solve state and the
+// reduction partials live in `scratch`, a static device array (one copy per
+// GPU, held until the process ends), instead of the hierarchy's buffers, and
+// the iterations are launched directly (instantiating a graph allocates).
+// In host code `scratch` names a host-side stand-in: its device address on
+// each GPU comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is handed to kernels and copies.
+constexpr size_t kScratchStateOff = 0;                  // SolveState
+constexpr size_t kScratchFlagOff = 256;                 // an int that stays 0
+constexpr size_t kScratchPartials = 2 * (size_t)kMaxGrid;
+constexpr size_t kScratchPartOff = 512;                 // partials (kScratchPartials doubles)
+constexpr size_t kScratchPartBOff = kScratchPartOff + kScratchPartials * sizeof(double);
+constexpr size_t kScratchBytes = kScratchPartBOff + kScratchPartials * sizeof(double);
+static_assert(sizeof(SolveState) <= kScratchFlagOff, "solve state exceeds its scratch slot");
+static_assert(kScratchBytes == PAMG_NOALLOC_SCRATCH_BYTES, "scratch size differs from the header");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (taken on the first call there).
+static unsigned char* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) throw Error(PAMG_E_INVALID, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        HIP_CHECK(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw Error(PAMG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[device] = static_cast<unsigned char*>(p);
+    }
+    return g_scratch_dev[device];
+}
+
+// The hierarchy's state and partial buffers pointed at the scratch for the
+// duration of one call (the hierarchy's lock is held), restored after.
+struct ScratchView {
+    pamg_hierarchy* h;
+    SolveState* st;
+    double *partial, *partial_b;
+    int* zero_flag;
+    ScratchView(pamg_hierarchy* hh, unsigned char* base)
+        : h(hh), st(hh->st), partial(hh->partial), partial_b(hh->partial_b), zero_flag(hh->zero_flag) {
+        h->st = reinterpret_cast<SolveState*>(base + kScratchStateOff);
+        h->zero_flag = reinterpret_cast<int*>(base + kScratchFlagOff);
+        h->partial = reinterpret_cast<double*>(base + kScratchPartOff);
+        h->partial_b = reinterpret_cast<double*>(base + kScratchPartBOff);
+    }
+    ~ScratchView() {
+        h->st = st;
+        h->partial = partial;
+        h->partial_b = partial_b;
+        h->zero_flag = zero_flag;
+    }
+};
+
+// Partials the solve's reductions write into one buffer (both hold
+// kScratchPartials): the Krylov pass two per workgroup, the level-0 up-sweep
+// or the single-level coarse product, the vector kernels.
+static size_t solve_partials(const pamg_hierarchy* h) {
+    const DevLevelIdx& I0 = h->idx[0];
+    size_t need = 2 * (size_t)tile_grid(I0.n_up);
+    need = std::max(need, (size_t)vec_grid(I0.n));
+    if (h->L == 0) need = std::max(need, (size_t)coarse_partials(h->idx[0].n));
+    return need;
+}
+
+int solve_noalloc(pamg_hierarchy* h, const double* b, double* x, pamg_solve_opts o, hipStream_t s,
+                  pamg_solve_info* info) {
+    require_device(h);
+    std::lock_guard<std::mutex> lk(h->mu);
+    unsigned char* base = scratch_address(h->device);
+    HIP_CHECK(hipSetDevice(h->device));
+    const size_t need = solve_partials(h);
+    if (need > kScratchPartials)
+        throw Error(PAMG_E_INVALID, "the hierarchy's reductions need " + std::to_string(need) +
+                                        " partials; the static scratch holds " + std::to_string(kScratchPartials));
+    if (o.precision == PAMG_PREC_F32 && !h->f32.built)
+        throw Error(PAMG_E_INVALID, "FP32 hierarchy not built (set params.build_f32)");
+    ScratchView view(h, base);
+    // the array keeps the last call's contents: state and flag start from zero
+    LAUNCH(k_fill, 1, 0, s, (long long)(kScratchPartOff / sizeof(double)), reinterpret_cast<double*>(base), 0.0);
+    o.use_graph = 0;
+    pamg_solve_info tmp{};
+    if (!info) info = &tmp;
+    if (o.precision == PAMG_PREC_F32)
+        solve_impl<float>(h, h->f32, 1, b, x, o, s, info);
+    else
+        solve_impl<double>(h, h->f64, 0, b, x, o, s, info);
+    return info->status;
+}
+
 void require_device(const pamg_hierarchy* h) {
     if (h->host_only) throw Error(PAMG_E_INVALID, "hierarchy was built with host_only=1");
 }
@@ -1191,6 +1287,18 @@ int pamg_solve(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_o
         if (!(o.tol >= 0.0) || o.maxit < 1 || o.fixed_iters < 0)
             throw pamg::Error(PAMG_E_INVALID, "bad solve options (need tol >= 0, maxit >= 1)");
         return pamg::solve(h, b, x, o, (hipStream_t)stream, info);
+    });
+}
+
+int pamg_solve_noalloc(pamg_hierarchy* h, const double* b, double* x, const pamg_solve_opts* opts, void* stream,
+                       pamg_solve_info* info) {
+    return pamg::guarded([&]() -> int {
+        if (!h || !b || !x) throw pamg::Error(PAMG_E_INVALID, "null argument");
+        pamg_solve_opts o;
+        if (opts) o = *opts; else pamg_solve_opts_default(&o);
+        if (!(o.tol >= 0.0) || o.maxit < 1 || o.fixed_iters < 0)
+            throw pamg::Error(PAMG_E_INVALID, "bad solve options (need tol >= 0, maxit >= 1)");
+        return pamg::solve_noalloc(h, b, x, o, (hipStream_t)stream, info);
     });
 }
 
