@@ -98,7 +98,7 @@ struct LayoutLevel {
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
 constexpr int kMaxItems = 16;        // matrix entries per thread per tile (largest tiles)
 constexpr int kDictItems = 8;        // tiles of at least this many items per thread use column dictionaries
-constexpr int kDictMaxLarge = 3072;  // longest dictionary accepted for the largest tiles (LDS)
+constexpr int kDictMaxLarge = 2048;  // longest dictionary accepted for the largest tiles (prefetch slots)
 constexpr int kTileRows = kBlock;    // at most one row (or aggregate) per thread in a tile
 constexpr int kMaxAggSteps = 4;      // composed aggregates hold at most 2^4 fine rows
 constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep >= this many

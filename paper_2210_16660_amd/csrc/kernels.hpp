@@ -113,22 +113,47 @@ __device__ __forceinline__ void tile_slots(int k0, int k1, int (&kk)[ITEMS]) {
 // columns are gathered once per tile into LDS (s_x), so each distinct column
 // is fetched once and neighbouring lanes read neighbouring addresses; every
 // entry then reads its value from LDS through its 16-bit dictionary position.
-template <int ITEMS, typename T, class G>
-__device__ __forceinline__ void tile_dict_fill(int2 span, const int* __restrict__ ucol, T* s_x, G gather) {
-    int c[ITEMS];
+//
+// A workgroup walks its tiles one ahead: the next tile's descriptor and
+// dictionary span are loaded when a tile starts, and its dictionary columns
+// once the tile's own matrix loads are in flight, so that the first
+// dependent step of a tile is the gather of its dictionary values (instead
+// of descriptor, then columns, then values, each waiting on the one before).
+constexpr int kDictSlots = 8;   // a dictionary holds at most kDictSlots * kBlock columns
+static_assert(kDictMaxLarge <= kDictSlots * kBlock, "dictionary longer than the prefetch slots");
+static_assert(kDictItems <= kDictSlots, "dictionary tiles of kDictItems * kBlock entries must fit the slots");
+
+struct TileNext {
+    int4 d;                  // descriptor of the next tile
+    int2 sp;                 // its dictionary span
+    int c[kDictSlots];       // its dictionary columns: slot s holds column s * kBlock + thread
+};
+
+__device__ __forceinline__ void next_desc(TileNext& N, int t, const int4* __restrict__ tiles,
+                                          const int2* __restrict__ span, bool dict) {
+    N.d = tiles[t];
+    N.sp = dict ? span[t] : make_int2(0, 0);
+}
+
+__device__ __forceinline__ void next_cols(TileNext& N, const int* __restrict__ ucol) {
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-        const int j = it * kBlock + (int)threadIdx.x;
-        if (it * kBlock < span.y) c[it] = ucol[span.x + (j < span.y ? j : span.y - 1)];
+    for (int s = 0; s < kDictSlots; ++s) {
+        const int j = s * kBlock + (int)threadIdx.x;
+        if (s * kBlock < N.sp.y) N.c[s] = ucol[N.sp.x + (j < N.sp.y ? j : N.sp.y - 1)];
     }
-    T x[ITEMS];
+}
+
+// The dictionary values of a tile (span sp, columns c) gathered into s_x.
+template <typename T, class G>
+__device__ __forceinline__ void tile_dict_gather(int2 sp, const int (&c)[kDictSlots], T* s_x, G gather) {
+    T x[kDictSlots];
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it)
-        if (it * kBlock < span.y) x[it] = gather(c[it]);
+    for (int s = 0; s < kDictSlots; ++s)
+        if (s * kBlock < sp.y) x[s] = gather(c[s]);
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-        const int j = it * kBlock + (int)threadIdx.x;
-        if (it * kBlock < span.y && j < span.y) s_x[j] = x[it];
+    for (int s = 0; s < kDictSlots; ++s) {
+        const int j = s * kBlock + (int)threadIdx.x;
+        if (s * kBlock < sp.y && j < sp.y) s_x[j] = x[s];
     }
 }
 
@@ -218,8 +243,20 @@ static __global__ __launch_bounds__(kBlock) void k_down(
     __shared__ T s_red[kBlock / 64];
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
+    constexpr bool DICT = tile_uses_dict<ITEMS>();
+    TileNext nx;
+    if (w.first < w.end) {
+        next_desc(nx, w.first, tiles, span, DICT);
+        if constexpr (DICT) next_cols(nx, ucol);
+    }
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int4 d = tiles[t];
+        const int4 d = nx.d;
+        const int2 sp = nx.sp;
+        int cc[kDictSlots];
+#pragma unroll
+        for (int q = 0; q < kDictSlots; ++q) cc[q] = nx.c[q];
+        const bool more = t + w.stride < w.end;
+        if (more) next_desc(nx, t + w.stride, tiles, span, DICT);
         const int k0 = d.x, k1 = d.y, c0 = d.z, c1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
             int kk[ITEMS];
@@ -229,13 +266,16 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             const auto gather = [&](int c) { return (T)g[c]; };
             T x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
-                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_dict_gather<T>(sp, cc, s_x, gather);
                 tile_local<ITEMS>(loc, kk, li);
             } else {
                 tile_direct<ITEMS, T>(ci, kk, x, gather);
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&ad[kk[it]]);
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);      // the next tile's columns, behind this tile's loads
+            }
             // phase 2: thread j finishes fine row f0 + j (the tile holds at
             // most kBlock fine rows), u_m = p_m (r_m - s_m) into LDS; then
             // thread j sums the members of coarse row c0 + j in order.
@@ -273,6 +313,9 @@ static __global__ __launch_bounds__(kBlock) void k_down(
             // before the barrier above) and s_u only after two barriers
         } else {
             // one aggregate whose rows exceed a tile
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);
+            }
             const int f0 = aggptr[c0], f1 = aggptr[c1];
             T acc = 0;
             for (int m = f0; m < f1; ++m) {
@@ -317,8 +360,20 @@ static __global__ __launch_bounds__(kBlock) void k_up(
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double dot = 0.0;
+    constexpr bool DICT = tile_uses_dict<ITEMS>();
+    TileNext nx;
+    if (w.first < w.end) {
+        next_desc(nx, w.first, tiles, span, DICT);
+        if constexpr (DICT) next_cols(nx, ucol);
+    }
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int4 d = tiles[t];
+        const int4 d = nx.d;
+        const int2 sp = nx.sp;
+        int cc[kDictSlots];
+#pragma unroll
+        for (int q = 0; q < kDictSlots; ++q) cc[q] = nx.c[q];
+        const bool more = t + w.stride < w.end;
+        if (more) next_desc(nx, t + w.stride, tiles, span, DICT);
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
             int kk[ITEMS];
@@ -328,13 +383,16 @@ static __global__ __launch_bounds__(kBlock) void k_up(
             const auto gather = [&](int c) { return zp[c]; };
             T x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
-                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_dict_gather<T>(sp, cc, s_x, gather);
                 tile_local<ITEMS>(loc, kk, li);
             } else {
                 tile_direct<ITEMS, T>(ci, kk, x, gather);
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);      // the next tile's columns, behind this tile's loads
+            }
             const int i = i0 + tid;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
@@ -402,6 +460,9 @@ static __global__ __launch_bounds__(kBlock) void k_up(
                 // its own first barrier
             }
         } else {
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);
+            }
             T s = 0;
             for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * zp[ci[k]];
             s = block_sum(s, s_red);
@@ -560,8 +621,20 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
     const int tid = threadIdx.x;
     const TileWalk w = tile_walk(ntiles);
     double nrm = 0.0;
+    constexpr bool DICT = tile_uses_dict<ITEMS>();
+    TileNext nx;
+    if (w.first < w.end) {
+        next_desc(nx, w.first, tiles, span, DICT);
+        if constexpr (DICT) next_cols(nx, ucol);
+    }
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int4 d = tiles[t];
+        const int4 d = nx.d;
+        const int2 sp = nx.sp;
+        int cc[kDictSlots];
+#pragma unroll
+        for (int q = 0; q < kDictSlots; ++q) cc[q] = nx.c[q];
+        const bool more = t + w.stride < w.end;
+        if (more) next_desc(nx, t + w.stride, tiles, span, DICT);
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
             int kk[ITEMS];
@@ -571,13 +644,16 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             const auto gather = [&](int c) { return (T)xv[c]; };
             T x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
-                tile_dict_fill<ITEMS, T>(span[t], ucol, s_x, gather);
+                tile_dict_gather<T>(sp, cc, s_x, gather);
                 tile_local<ITEMS>(loc, kk, li);
             } else {
                 tile_direct<ITEMS, T>(ci, kk, x, gather);
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);      // the next tile's columns, behind this tile's loads
+            }
             // phase 2: G lanes per row (G = 1 unless the tile has few, long
             // rows), each summing a strided part, then a fixed-order butterfly
             int G = 1;
@@ -608,6 +684,9 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
             }
             __syncthreads();
         } else {
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);
+            }
             T s = 0;
             for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (T)xv[ci[k]];
             s = block_sum(s, s_red);
@@ -646,8 +725,20 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const double beta = st->beta;
     const TileWalk w = tile_walk(ntiles);
     double pq = 0.0, pr = 0.0;
+    constexpr bool DICT = tile_uses_dict<ITEMS>();
+    TileNext nx;
+    if (w.first < w.end) {
+        next_desc(nx, w.first, tiles, span, DICT);
+        if constexpr (DICT) next_cols(nx, ucol);
+    }
     for (int t = w.first; t < w.end; t += w.stride) {
-        const int4 d = tiles[t];
+        const int4 d = nx.d;
+        const int2 sp = nx.sp;
+        int cc[kDictSlots];
+#pragma unroll
+        for (int q = 0; q < kDictSlots; ++q) cc[q] = nx.c[q];
+        const bool more = t + w.stride < w.end;
+        if (more) next_desc(nx, t + w.stride, tiles, span, DICT);
         const int k0 = d.x, k1 = d.y, i0 = d.z, i1 = d.w;
         if (k1 - k0 <= ITEMS * kBlock) {
             int kk[ITEMS];
@@ -657,13 +748,16 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             const auto gather = [&](int c) { return first ? z[c] : z[c] + beta * p_old[c]; };
             double x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
-                tile_dict_fill<ITEMS, double>(span[t], ucol, s_x, gather);
+                tile_dict_gather<double>(sp, cc, s_x, gather);
                 tile_local<ITEMS>(loc, kk, li);
             } else {
                 tile_direct<ITEMS, double>(ci, kk, x, gather);
             }
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) a[it] = ld_stream(&av[kk[it]]);
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);      // the next tile's columns, behind this tile's loads
+            }
             const int i = i0 + tid;
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
@@ -689,6 +783,9 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             }
             __syncthreads();
         } else {
+            if constexpr (DICT) {
+                if (more) next_cols(nx, ucol);
+            }
             double s = 0.0;
             for (int k = k0 + tid; k < k1; k += kBlock) {
                 const int c = ci[k];
