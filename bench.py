@@ -107,11 +107,11 @@ def csr_bytes(nnz, n, s):
 
 def level0_csr_bytes(info, name, s=8):
     """Algorithmic bytes of one launch of a level-0 kernel, plain-CSR model:
-    Krylov pass M_0 + 5 n_0 8 (z, p_old, r in; p, q out); down-sweep
+    Krylov pass M_0 + 6 n_0 8 (z, p_old, q_old, r in; p, q out); down-sweep
     M_0 + (4 n_0 + n_1) s; up-sweep M_0 + (6 n_0 + n_1) s; SpMV M_0 + 2 n_0 8."""
     n0, n1, nnz0 = info.n[0], info.n[1] if info.levels > 1 else 0, info.nnz[0]
     if name == "krylov_spmv_l0":
-        return csr_bytes(nnz0, n0, 8) + 5 * n0 * 8
+        return csr_bytes(nnz0, n0, 8) + 6 * n0 * 8
     if name == "vcycle_down_l0":
         return csr_bytes(nnz0, n0, s) + (4 * n0 + n1) * s
     if name == "vcycle_up_l0":

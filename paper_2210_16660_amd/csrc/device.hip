@@ -1035,8 +1035,8 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
     } else if (op == PAMG_OP_KRYLOV) {
         if (l != 0) throw Error(PAMG_E_INVALID, "KRYLOV runs on level 0");
         const uint64_t M8 = matrix_bytes(I, false, 8);
-        // matrix (FP64), z, p_old, r reads; p_new, q writes
-        *bytes = M8 + 5 * n * 8;
+        // matrix (FP64), z, p_old, q_old, r reads; p_new, q writes
+        *bytes = M8 + 6 * n * 8;
         launch = [=]() {
             launch_krylov(I, h->f64.v[0], h->z, h->p[0], h->p[1], h->q, h->r, h->st, h->partial, nodone, s);
         };

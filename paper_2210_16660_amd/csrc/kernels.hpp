@@ -706,9 +706,11 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
 
 // ----------------------------------------------------------------------------
 // Krylov step, part 1: p = z + beta p_old (p = z on the first iteration),
-// q = A p, partials of p.q and p.r.  p_j is formed in the tile's dictionary
-// from z and p_old (ping-pong buffers), with the same expression as for the
-// owned rows.
+// q = A p computed as A z + beta q_old (the same vector in exact arithmetic,
+// so that only z is gathered: one dictionary gather per tile instead of two;
+// q holds q_old on entry and each row's element is read before its owner
+// overwrites it), partials of p.q and p.r.  On the first iteration (and after
+// a restart) q = A z.
 template <int ITEMS>
 static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
@@ -745,7 +747,7 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             double a[ITEMS];
             uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-            const auto gather = [&](int c) { return first ? z[c] : z[c] + beta * p_old[c]; };
+            const auto gather = [&](int c) { return z[c]; };
             double x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 tile_dict_gather<double>(sp, cc, s_x, gather);
@@ -762,7 +764,7 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
-            const double zi = z[ic], poi = p_old[ic], ri = r[ic];
+            const double zi = z[ic], poi = p_old[ic], ri = r[ic], qoi = q[ic];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
                 tile_products_dict<ITEMS>(a, li, s_x);
@@ -776,9 +778,10 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
                 double s = 0.0;
                 for (int k = rb - k0; k < re - k0; ++k) s += s_prod[k];
                 const double pi = first ? zi : zi + beta * poi;
+                const double qi = first ? s : s + beta * qoi;
                 p_new[i] = pi;
-                q[i] = s;
-                pq += pi * s;
+                q[i] = qi;
+                pq += pi * qi;
                 pr += pi * ri;
             }
             __syncthreads();
@@ -787,14 +790,11 @@ static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
                 if (more) next_cols(nx, ucol);
             }
             double s = 0.0;
-            for (int k = k0 + tid; k < k1; k += kBlock) {
-                const int c = ci[k];
-                const double pj = first ? z[c] : z[c] + beta * p_old[c];
-                s += av[k] * pj;
-            }
+            for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * z[ci[k]];
             s = block_sum(s, s_red);
             if (tid == 0) {
                 const double pi = first ? z[i0] : z[i0] + beta * p_old[i0];
+                s = first ? s : s + beta * q[i0];
                 p_new[i0] = pi;
                 q[i0] = s;
                 pq += pi * s;
