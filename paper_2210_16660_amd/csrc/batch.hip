@@ -216,17 +216,17 @@ static void enqueue_iteration_b(BatchEngine* E, DevVals<T>& V, int krylov, int p
     const int* done = &E->st->all_done;
     const double* dv = (krylov == PAMG_KRYLOV_CG) ? E->R : E->Q;
     const int cnt = enqueue_vcycle_b<T>(E, V, dv, done, s);
-    hipLaunchKernelGGL(kb_fin_beta, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, cnt);
+    hipLaunchKernelGGL(kb_fin_beta, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, cnt);
     const DevLevelIdx& I0 = h->idx[0];
     const int gk = unit_grid(I0.n, kKrylovRowsPerBlock);
     hipLaunchKernelGGL(kb_krylov_pq, dim3(gk), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
                        (const double*)h->f64.v[0], (const double*)E->Z, (const double*)E->P[parity], E->P[1 - parity],
                        E->Q, (const double*)E->R, (const BatchState*)E->st, E->partial, done);
-    hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, gk);
+    hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, gk);
     const int g = unit_grid(I0.n, kBlock / kW);
     hipLaunchKernelGGL(kb_update, dim3(g), dim3(kBlock), 0, s, I0.n, E->X, E->R, (const double*)E->P[1 - parity],
                        (const double*)E->Q, (const BatchState*)E->st, E->partial, done);
-    hipLaunchKernelGGL(kb_fin_norm, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial, g);
+    hipLaunchKernelGGL(kb_fin_norm, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, g);
 }
 
 template <typename T>
@@ -427,7 +427,7 @@ void batch_load(BatchEngine* E, const double* const* src, const double* tol, con
     const int g = std::min(kMaxGrid, std::max(1, (I0.n + 15) / 16));
     hipLaunchKernelGGL(kb_load, dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.iperm,
                        (const double* const*)E->src_dev, E->B, E->R, E->X, E->partial_b);
-    hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial_b, g,
+    hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial_b, g,
                        (const double*)E->partial_b, g, mask);
     HIP_CHECK(hipGetLastError());
     batch_read_state(E, s);
@@ -465,7 +465,7 @@ void batch_true_residual(BatchEngine* E, int restart_mask, double* relres, hipSt
         relres[c] = bn > 0 ? std::sqrt(t) / bn : 0.0;
     }
     if (restart_mask) {
-        hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(kBlock), 0, s, E->st, (const double*)E->partial_b, 0,
+        hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial_b, 0,
                            (const double*)E->partial_b, g, restart_mask);
         HIP_CHECK(hipGetLastError());
         batch_read_state(E, s);

@@ -519,15 +519,34 @@ static __global__ __launch_bounds__(kBlock) void kb_update(int n, double* __rest
     }
 }
 
-// Fixed-order per-column sum of `count` partials (stride `stride`, offset
-// `off`): 16 threads per column; result valid in the thread with part == 0.
+// Fixed-order per-column sums of `count` partials (partial gi of column c at
+// ((gi * kW + c) * stride + off)) by one workgroup of kFinThreads: thread t
+// takes column t % kW and the partials gi = t / kW, + kFinParts, ...
+// (neighbouring threads read neighbouring columns of one partial), four loads
+// in flight; the kFinParts part sums of a column then meet in LDS in part
+// order.  The result is valid in threads 0 .. kW-1 (thread c: column c).
+constexpr int kFinThreads = 1024;
+constexpr int kFinParts = kFinThreads / kW;
+
 __device__ __forceinline__ double col_sum(const double* __restrict__ partial, int count, int stride, int off,
-                                          int c, int part) {
-    double s = 0.0;
-    for (int gi = part; gi < count; gi += 16) s += partial[((size_t)gi * kW + c) * stride + off];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    return s;
+                                          double (*s_part)[kW]) {
+    const int c = threadIdx.x % kW, part = threadIdx.x / kW;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int gi = part;
+    for (; gi + 3 * kFinParts < count; gi += 4 * kFinParts) {
+        s0 += partial[((size_t)gi * kW + c) * stride + off];
+        s1 += partial[((size_t)(gi + kFinParts) * kW + c) * stride + off];
+        s2 += partial[((size_t)(gi + 2 * kFinParts) * kW + c) * stride + off];
+        s3 += partial[((size_t)(gi + 3 * kFinParts) * kW + c) * stride + off];
+    }
+    for (; gi < count; gi += kFinParts) s0 += partial[((size_t)gi * kW + c) * stride + off];
+    s_part[part][c] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < kW)
+        for (int q = 0; q < kFinParts; ++q) t += s_part[q][threadIdx.x];
+    __syncthreads();
+    return t;
 }
 
 // all_done = no active column left running (read after the barrier, which
@@ -543,12 +562,13 @@ __device__ __forceinline__ void update_all_done(BatchState* st) {
 }
 
 // beta (and rho for PCG) from the partials of z.dv.
-static __global__ __launch_bounds__(kBlock) void kb_fin_beta(BatchState* __restrict__ st, const double* __restrict__ partial,
-                                                      int count) {
+static __global__ __launch_bounds__(kFinThreads) void kb_fin_beta(BatchState* __restrict__ st,
+                                                                  const double* __restrict__ partial, int count) {
     if (st->all_done) return;
-    const int c = threadIdx.x / 16, part = threadIdx.x % 16;
-    const double d = col_sum(partial, count, 1, 0, c, part);
-    if (part == 0) {
+    __shared__ double s_part[kFinParts][kW];
+    const int c = threadIdx.x;
+    const double d = col_sum(partial, count, 1, 0, s_part);
+    if (c < kW) {
         BatchCol& C = st->col[c];
         if (C.active && !C.done) {
             if (st->krylov == PAMG_KRYLOV_CG) {
@@ -561,13 +581,14 @@ static __global__ __launch_bounds__(kBlock) void kb_fin_beta(BatchState* __restr
     }
 }
 
-static __global__ __launch_bounds__(kBlock) void kb_fin_alpha(BatchState* __restrict__ st, const double* __restrict__ partial,
-                                                       int count) {
+static __global__ __launch_bounds__(kFinThreads) void kb_fin_alpha(BatchState* __restrict__ st,
+                                                                   const double* __restrict__ partial, int count) {
     if (st->all_done) return;
-    const int c = threadIdx.x / 16, part = threadIdx.x % 16;
-    const double pq = col_sum(partial, count, 2, 0, c, part);
-    const double pr = col_sum(partial, count, 2, 1, c, part);
-    if (part == 0) {
+    __shared__ double s_part[kFinParts][kW];
+    const int c = threadIdx.x;
+    const double pq = col_sum(partial, count, 2, 0, s_part);
+    const double pr = col_sum(partial, count, 2, 1, s_part);
+    if (c < kW) {
         BatchCol& C = st->col[c];
         if (C.active && !C.done) {
             if (!(pq > 0.0)) {
@@ -586,12 +607,13 @@ static __global__ __launch_bounds__(kBlock) void kb_fin_alpha(BatchState* __rest
     update_all_done(st);
 }
 
-static __global__ __launch_bounds__(kBlock) void kb_fin_norm(BatchState* __restrict__ st, const double* __restrict__ partial,
-                                                      int count) {
+static __global__ __launch_bounds__(kFinThreads) void kb_fin_norm(BatchState* __restrict__ st,
+                                                                  const double* __restrict__ partial, int count) {
     if (st->all_done) return;
-    const int c = threadIdx.x / 16, part = threadIdx.x % 16;
-    const double rr = col_sum(partial, count, 1, 0, c, part);
-    if (part == 0) {
+    __shared__ double s_part[kFinParts][kW];
+    const int c = threadIdx.x;
+    const double rr = col_sum(partial, count, 1, 0, s_part);
+    if (c < kW) {
         BatchCol& C = st->col[c];
         if (C.active && !C.done) {
             const double rn = sqrt(rr);
@@ -617,13 +639,15 @@ static __global__ __launch_bounds__(kBlock) void kb_fin_norm(BatchState* __restr
 
 // Start (or restart) the columns in `mask`: ||b|| and ||r|| from partials
 // (bb_count == 0: keep bnorm), first iteration next, stopping state.
-static __global__ __launch_bounds__(kBlock) void kb_fin_init(BatchState* __restrict__ st, const double* __restrict__ bb_part,
-                                                      int bb_count, const double* __restrict__ rr_part, int rr_count,
-                                                      int mask) {
-    const int c = threadIdx.x / 16, part = threadIdx.x % 16;
-    const double bb = bb_count > 0 ? col_sum(bb_part, bb_count, 1, 0, c, part) : 0.0;
-    const double rr = col_sum(rr_part, rr_count, 1, 0, c, part);
-    if (part == 0 && ((mask >> c) & 1)) {
+static __global__ __launch_bounds__(kFinThreads) void kb_fin_init(BatchState* __restrict__ st,
+                                                                  const double* __restrict__ bb_part, int bb_count,
+                                                                  const double* __restrict__ rr_part, int rr_count,
+                                                                  int mask) {
+    __shared__ double s_part[kFinParts][kW];
+    const int c = threadIdx.x;
+    const double bb = bb_count > 0 ? col_sum(bb_part, bb_count, 1, 0, s_part) : 0.0;
+    const double rr = col_sum(rr_part, rr_count, 1, 0, s_part);
+    if (c < kW && ((mask >> c) & 1)) {
         BatchCol& C = st->col[c];
         if (bb_count > 0) C.bnorm = sqrt(bb);
         C.rnorm = sqrt(rr);
