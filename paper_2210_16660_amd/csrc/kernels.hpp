@@ -94,6 +94,10 @@ inline int tile_grid(int ntiles) { return ntiles < kMaxGrid ? (ntiles > 0 ? ntil
 // then the gathers, then writes the products to LDS; the per-row data each
 // thread needs in phase 2 is loaded in the same batch.
 
+// The tile kernels keep four workgroups per CU (the LDS of the largest FP64
+// tiles allows four): __launch_bounds__(kBlock, 4) holds them to 128 VGPRs,
+// i.e. four waves per SIMD.
+
 // Streamed matrix arrays are read exactly once per pass: non-temporal loads
 // keep them from evicting the gathered vectors from L2.
 template <typename T>
@@ -232,7 +236,7 @@ inline size_t tile_lds_bytes(int dmax) {
 // (g = r).  With another smoother the same pass takes the smoothed z as g and
 // the plain values as `ad`: rc[I] = sum_{i in G_I} p_i (r_i - (A z)_i).
 template <int ITEMS, typename T, typename RT, typename GT>
-static __global__ __launch_bounds__(kBlock) void k_down(
+static __global__ __launch_bounds__(kBlock, 4) void k_down(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ ad,
     const RT* __restrict__ r, const GT* __restrict__ g, const T* __restrict__ p, const int* __restrict__ aggptr,
     const int4* __restrict__ tiles, int ntiles,
@@ -341,7 +345,7 @@ static __global__ __launch_bounds__(kBlock) void k_down(
 constexpr int kUpOut = 0, kUpPair = 1, kUpWide = 2;
 
 template <int ITEMS, typename T, typename RT, typename RTF, int MODE>
-static __global__ __launch_bounds__(kBlock) void k_up(
+static __global__ __launch_bounds__(kBlock, 4) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
     const int4* __restrict__ tiles, int ntiles,
@@ -610,7 +614,7 @@ static __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __re
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
 // y . y.
 template <int ITEMS, typename T, typename XT, typename YT, typename BT = double>
-static __global__ __launch_bounds__(kBlock) void k_spmv(
+static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const XT* __restrict__ xv, const BT* __restrict__ b, YT* __restrict__ y,
     const int4* __restrict__ tiles, int ntiles,
@@ -712,7 +716,7 @@ static __global__ __launch_bounds__(kBlock) void k_spmv(
 // overwrites it), partials of p.q and p.r.  On the first iteration (and after
 // a restart) q = A z.
 template <int ITEMS>
-static __global__ __launch_bounds__(kBlock) void k_krylov_pq(
+static __global__ __launch_bounds__(kBlock, 4) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
     const double* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
     double* __restrict__ q, const double* __restrict__ r,

@@ -111,6 +111,9 @@ inline int unit_grid(long long nunits, int gpb) {
 }
 
 // s[q] += sum over row entries [kb, ke) of a_k x[c_k][col0 + q], in entry order.
+// (The lanes of a group load the same index and value; plain loads keep the
+// line in L2 for the group's next entries: non-temporal loads made the
+// 16-column engine 1.6x slower.)
 template <int U, int CPL, typename T, typename XT>
 __device__ __forceinline__ void row_accumulate(int kb, int ke, const int* __restrict__ ci, const T* __restrict__ av,
                                                const XT* __restrict__ x, int col0, T (&s)[CPL]) {
