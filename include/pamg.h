@@ -399,12 +399,20 @@ typedef struct {
     uint64_t algorithmic_bytes;  /* HBM bytes the executed iterations had to move */
     double host_setup_ms;        /* host phases of the setups (worker thread, overlaps solving) */
     double device_setup_ms;      /* uploads and coarsest factorizations (scheduler thread) */
+    uint64_t engines_built;      /* 16-column engines built (operators' first batches) */
+    uint64_t engines_freed;      /* engines of idle operators freed to make room */
 } pamg_server_stats;
 
 int pamg_server_opts_default(pamg_server_opts *o);
-/* The bytes admission charges for an uncached operator before its hierarchy
- * exists: an upper estimate of hierarchy + 16-column engine for A (host CSR)
- * at the given V-cycle precision.  Once built, the exact figure is used. */
+/* An upper estimate of the device bytes an operator can hold in a server
+ * (A: host CSR; precision: the V-cycle's): its hierarchy plus its 16-column
+ * engine.  Admission charges the hierarchy part of it for an uncached
+ * operator, then the exact figure once the hierarchy exists; the engine is
+ * built (and charged, exactly) only when the operator's requests first run
+ * as a batch.  Under budget pressure the engines of idle operators are freed
+ * before idle operators are evicted; an engine that can never fit beside its
+ * hierarchy sends the operator's requests to the single-right-hand-side path
+ * (or, without it, refuses them with BUSY). */
 int pamg_server_estimate_bytes(const pamg_csr *A, int32_t precision, uint64_t *out);
 /* ctx: allocator and device of every hierarchy the server builds (NULL:
  * hipMalloc on the current device); it must outlive the server. */

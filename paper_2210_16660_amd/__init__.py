@@ -92,7 +92,7 @@ class pamg_server_stats(C.Structure):
                 ("active_columns", C.c_int32), ("pending", C.c_int32), ("pad", C.c_int32), ("setups", C.c_uint64),
                 ("evictions", C.c_uint64), ("blocks", C.c_uint64), ("busy_ms", C.c_double),
                 ("algorithmic_bytes", C.c_uint64), ("host_setup_ms", C.c_double),
-                ("device_setup_ms", C.c_double)]
+                ("device_setup_ms", C.c_double), ("engines_built", C.c_uint64), ("engines_freed", C.c_uint64)]
 
 
 # every entry point declared in include/pamg.h: name -> (restype, argtypes)

@@ -334,8 +334,16 @@ static BatchEngine* create_engine(pamg_hierarchy* h, DevVals<T>& V, int prec, hi
     E->st_host->all_done = 1;
     HIP_CHECK(hipMemcpyAsync(E->st, E->st_host, sizeof(BatchState), hipMemcpyHostToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    autotune<T>(E.get(), V, s);
-    HIP_CHECK(hipStreamSynchronize(s));
+    if (!h->batch_cfg_down[prec].empty()) {
+        // variants tuned for an earlier engine of this hierarchy
+        E->cfg_down = h->batch_cfg_down[prec];
+        E->cfg_up = h->batch_cfg_up[prec];
+    } else {
+        autotune<T>(E.get(), V, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        h->batch_cfg_down[prec] = E->cfg_down;
+        h->batch_cfg_up[prec] = E->cfg_up;
+    }
     return E.release();
 }
 
@@ -373,6 +381,24 @@ static hipGraphExec_t block_graph(BatchEngine* E, int krylov, int k) {
 }
 
 void batch_prepare_graph(BatchEngine* E, int krylov, int k) { (void)block_graph(E, krylov, k); }
+
+void release_engine(pamg_hierarchy* h, int prec) { h->batch[prec].reset(); }   // destroy_batch synchronizes
+
+// Device bytes of the 16-column engine of h (the allocations create_engine makes).
+uint64_t engine_bytes(const pamg_hierarchy* h, int prec) {
+    const uint64_t s = prec == PAMG_PREC_F32 ? 4 : 8;
+    const int L = h->L;
+    uint64_t b = 0;
+    for (int l = 0; l <= L; ++l) {
+        const uint64_t n = (uint64_t)h->idx[l].n * kW;
+        if (l >= 1) b += n * s;
+        if (l < L) b += n * s;
+    }
+    const uint64_t n0 = (uint64_t)h->idx[0].n * kW;
+    b += (uint64_t)h->idx[L].n * kW * s + 8 * n0 * 8 + (prec == PAMG_PREC_F32 ? n0 * 4 : 0);
+    b += 2 * (uint64_t)kMaxGrid * kW * 2 * 8 + sizeof(BatchState) + 2 * kW * sizeof(void*);
+    return b;
+}
 
 // One block of k iterations (graph replay or direct launches).
 void batch_run_block(BatchEngine* E, int krylov, int k, bool use_graph, hipStream_t s) {
@@ -660,6 +686,8 @@ void batch_set_config(pamg_hierarchy* h, int prec, const int32_t* cfg) {
         E->cfg_down[l] = down[l];
         if (l > 0) E->cfg_up[l] = up[l];
     }
+    h->batch_cfg_down[prec] = E->cfg_down;
+    h->batch_cfg_up[prec] = E->cfg_up;
 }
 
 void batch_config(pamg_hierarchy* h, int prec, int32_t* cfg) {

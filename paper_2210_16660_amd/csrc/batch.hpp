@@ -26,5 +26,10 @@ void batch_prepare_graph(BatchEngine* E, int krylov, int k);
 // Mark the columns in `mask` inactive in the host copy of the state (written
 // back by the next batch_write_state / batch_load).
 void batch_retire(BatchEngine* E, int mask);
+// Free the engine of this precision (synchronizes the device); the tuned
+// kernel variants stay with the hierarchy for the next engine.
+void release_engine(pamg_hierarchy* h, int prec);
+// Device bytes an engine of this precision takes for h.
+uint64_t engine_bytes(const pamg_hierarchy* h, int prec);
 
 }  // namespace pamg

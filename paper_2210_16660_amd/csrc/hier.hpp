@@ -132,6 +132,7 @@ struct pamg_hierarchy {
     pamg_hier_info info{};
     std::mutex mu;
     std::unique_ptr<pamg::BatchEngine, pamg::BatchDeleter> batch[2];   // multi-RHS workspaces (FP64 / FP32 V-cycle)
+    std::vector<int> batch_cfg_down[2], batch_cfg_up[2];   // their tuned kernel variants, kept across engines
     std::unique_ptr<pamg::ReusePlan> reuse;   // coefficient-only updates
     bool values_updated = false;              // host copies of the values are stale
 };

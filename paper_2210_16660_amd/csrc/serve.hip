@@ -64,7 +64,8 @@ struct ServeGroup {
     ServeRequest* col[kW] = {};
     int active = 0;
     uint64_t last_used = 0;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0;          // device bytes: hierarchy, and the engine while it exists
+    uint64_t engine = 0;         // of which the 16-column engine
     uint64_t iter_bytes = 0;     // algorithmic bytes of one batched iteration
     hipEvent_t ev = nullptr;     // recorded behind the state copy of the block in flight
     bool in_flight = false;
@@ -115,31 +116,45 @@ static double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-// Upper estimate of the device bytes of an operator's hierarchy plus its
-// batch engine, before it is built (replaced by the exact figure after).
-// Hierarchy: per level index arrays, values and the restriction values (plus
-// their FP32 copies), vectors; coarse levels add at most 1.3x the finest
-// (pairwise coarsening), fixed buffers ~0.2 MB.  Engine: eight n x 16 FP64
-// vectors at level 0 (plus an FP32 copy of one with the FP32 cycle), two
-// n_l x 16 vectors per level, 1.1 MB of partials.
+// Upper estimate of the device bytes of an operator's hierarchy before it is
+// built (replaced by the exact figure after): per level index arrays, values
+// and the restriction values (plus their FP32 copies), vectors; coarse levels
+// add at most 1.3x the finest (pairwise coarsening), fixed buffers ~0.2 MB.
+// The 16-column engine (eight n x 16 FP64 vectors at level 0 and two
+// n_l x 16 vectors per level) is built only when the operator's requests run
+// as a batch, and is charged then.
 static uint64_t dense_bytes(uint64_t nL, int prec) { return nL * nL * (prec == PAMG_PREC_F32 ? 12 : 8); }
 
 static uint64_t estimate_core(const pamg_csr& A, int prec) {
     const double cx = 2.3;
     const double n = (double)A.n, nnz = (double)A.nnz;
-    const double s = prec == PAMG_PREC_F32 ? 4.0 : 8.0;
     double hier = cx * (nnz * (4 + 8 + 8) + n * 80) + 96.0 * n + (1 << 18);
     if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32);
-    const double engine = n * kW * 8 * 8 + (prec == PAMG_PREC_F32 ? n * kW * 4 : 0.0) + 2.0 * cx * n * kW * s +
-                          1.2 * (1 << 20);
-    return (uint64_t)(hier + engine);
+    return (uint64_t)hier;
 }
 
 // ... plus the dense inverse of a coarsest level of the usual size (at most
 // the default max_coarse rows); a stalled coarsening can leave a larger one,
 // which admission charges once the host phase has fixed n_L.
-uint64_t estimate_bytes(const pamg_csr& A, int prec) {
+static uint64_t hierarchy_estimate(const pamg_csr& A, int prec) {
     return estimate_core(A, prec) + dense_bytes(std::min<uint64_t>((uint64_t)A.n, 200), prec);
+}
+
+// Upper estimate of the 16-column engine before the hierarchy exists (the
+// exact figure, engine_bytes, needs its level sizes): eight FP64 n x 16
+// vectors at level 0 (plus the FP32 copy of the right-hand side), two
+// n_l x 16 vectors per level with the levels' rows summing to at most 2.3 n,
+// the coarsest right-hand side and the reduction partials.
+static uint64_t engine_estimate(uint64_t n, int prec) {
+    const double s = prec == PAMG_PREC_F32 ? 4 : 8;
+    const double per_row = 8 * 8 + (prec == PAMG_PREC_F32 ? 4 : 0) + 2 * 2.3 * s;
+    return (uint64_t)((double)kW * (per_row * (double)n + 200 * s)) + 2ull * kMaxGrid * kW * 2 * 8 + 4096;
+}
+
+// What an operator can hold in the server: its hierarchy and, once its
+// requests run as a batch, its engine.
+uint64_t estimate_bytes(const pamg_csr& A, int prec) {
+    return hierarchy_estimate(A, prec) + engine_estimate((uint64_t)A.n, prec);
 }
 
 static uint64_t batch_iteration_bytes(const pamg_hierarchy* h, int prec) {
@@ -193,6 +208,71 @@ static void evict(pamg_server* S, ServeGroup* g) {
     delete g;
 }
 
+// Free the 16-column engine of an idle operator (its hierarchy stays cached).
+static void drop_engine(pamg_server* S, ServeGroup* g) {
+    HIP_CHECK(hipStreamSynchronize(g->stream));
+    release_engine(g->h, S->opts.precision);
+    g->E = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.bytes_in_use -= g->engine;
+        S->stats.engines_freed += 1;
+    }
+    g->bytes -= g->engine;
+    g->engine = 0;
+}
+
+static uint64_t bytes_in_use(pamg_server* S) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    return S->stats.bytes_in_use;
+}
+
+// Make `need` more bytes fit the budget: first free the engines of idle
+// operators, then (evict_operators) evict idle operators, least recently used
+// first (never `keep`).  False if what is left is busy.
+static bool make_room(pamg_server* S, uint64_t need, const ServeGroup* keep, bool evict_operators) {
+    const uint64_t budget = S->opts.hbm_budget_bytes;
+    while (bytes_in_use(S) + need > budget) {
+        ServeGroup* lru = nullptr;
+        for (auto& kv : S->groups) {
+            ServeGroup* g = kv.second;
+            if (g != keep && g->E && g->active == 0 && !g->in_flight && (!lru || g->last_used < lru->last_used))
+                lru = g;
+        }
+        if (lru) {
+            drop_engine(S, lru);
+            continue;
+        }
+        if (!evict_operators) return false;
+        for (auto& kv : S->groups)
+            if (kv.second != keep && kv.second->idle() && (!lru || kv.second->last_used < lru->last_used))
+                lru = kv.second;
+        if (!lru) return false;
+        evict(S, lru);
+    }
+    return true;
+}
+
+// The operator's 16-column engine, built when its requests first run as a
+// batch (with the kernel variants tuned for its hierarchy, kept across
+// engines) if its bytes fit the budget, freeing idle operators' engines and,
+// with evict_operators (no single-column path to fall back on), evicting idle
+// operators for it; false: not now.
+static bool ensure_engine(pamg_server* S, ServeGroup* g, bool evict_operators) {
+    if (g->E) return true;
+    const int prec = S->opts.precision;
+    const uint64_t need = engine_bytes(g->h, prec);
+    if (need > S->opts.hbm_budget_bytes || !make_room(S, need, g, evict_operators)) return false;
+    g->E = get_engine(g->h, prec, g->stream);
+    if (S->opts.use_graph) batch_prepare_graph(g->E, PAMG_KRYLOV_FCG, S->opts.block_iters);
+    g->engine = batch_bytes(g->E);
+    g->bytes += g->engine;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.bytes_in_use += g->engine;
+    S->stats.engines_built += 1;
+    return true;
+}
+
 // Upper bound of the device bytes of an operator whose host phase is done:
 // the estimate with the dense coarsest inverse at its actual size.
 static uint64_t bound_bytes(const SetupJob& j, int prec) {
@@ -216,7 +296,7 @@ static void request_setup(pamg_server* S, ServeRequest* q) {
     const uint64_t key = q->r.op_key;
     if (S->groups.count(key) || S->setups.count(key)) return;
     if (!q->r.A) throw Error(PAMG_E_INVALID, "request for an uncached operator carries no matrix");
-    if (estimate_bytes(*q->r.A, S->opts.precision) > S->opts.hbm_budget_bytes) throw Error(PAMG_E_BUSY, "");
+    if (hierarchy_estimate(*q->r.A, S->opts.precision) > S->opts.hbm_budget_bytes) throw Error(PAMG_E_BUSY, "");
     SetupJob* j = new SetupJob();
     j->key = key;
     j->A = *q->r.A;
@@ -254,20 +334,7 @@ static void admit_ready(pamg_server* S) {
             delete j;
             continue;
         }
-        auto in_use = [&]() {
-            std::lock_guard<std::mutex> lk(S->mu);
-            return S->stats.bytes_in_use;
-        };
-        bool room = true;
-        while (in_use() + need > budget) {
-            ServeGroup* lru = nullptr;
-            for (auto& kv : S->groups)
-                if (kv.second->idle() && (!lru || kv.second->last_used < lru->last_used))
-                    lru = kv.second;
-            if (!lru) { room = false; break; }       // everything busy: try again next tick
-            evict(S, lru);
-        }
-        if (!room) { ++it; continue; }
+        if (!make_room(S, need, nullptr, true)) { ++it; continue; }   // everything busy: try again next tick
         std::unique_ptr<ServeGroup> g(new ServeGroup());
         g->key = j->key;
         HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
@@ -284,12 +351,9 @@ static void admit_ready(pamg_server* S) {
             delete j;
             continue;
         }
-        g->E = get_engine(g->h, prec, g->stream);
-        if (S->opts.use_graph) {     // capture the block graphs now, not on the first request
-            batch_prepare_graph(g->E, PAMG_KRYLOV_FCG, S->opts.block_iters);
-            if (S->opts.single_path) single_prepare_graph(g->h, prec, S->opts.block_iters);
-        }
-        g->bytes = g->h->info.device_bytes + batch_bytes(g->E);
+        if (S->opts.use_graph && S->opts.single_path)   // capture now, not on the first request
+            single_prepare_graph(g->h, prec, S->opts.block_iters);
+        g->bytes = g->h->info.device_bytes;
         g->iter_bytes = batch_iteration_bytes(g->h, prec);
         g->single_iter_bytes = single_iteration_bytes(g->h, prec);
         {
@@ -458,7 +522,22 @@ static void scheduler_tick(pamg_server* S) {
             continue;
         }
         ServeGroup* g = gi->second;
-        if (S->opts.single_path && g->active == 0 && waiting[g->key] < S->opts.batch_from) {
+        // an engine that can never fit the budget beside the hierarchy: the
+        // operator's requests run on the single-right-hand-side path (or are
+        // refused without it)
+        const bool no_batch = !g->E && g->bytes + engine_bytes(g->h, S->opts.precision) > S->opts.hbm_budget_bytes;
+        if (no_batch && !S->opts.single_path) {
+            it = S->pending.erase(it);
+            complete(S, q, PAMG_E_BUSY, 0, 0.0, -1.0);
+            continue;
+        }
+        // with the single path: a batch only once batch_from requests wait and
+        // its engine exists or can be built now (not behind a single block in
+        // flight on the operator's stream, which would skew the variant tuning)
+        const bool batch = !S->opts.single_path || g->active > 0 ||
+                           (waiting[g->key] >= S->opts.batch_from && !no_batch && !g->in_flight &&
+                            (g->E || !g->single_in_flight) && ensure_engine(S, g, false));
+        if (S->opts.single_path && g->active == 0 && !batch) {
             // few requests for this operator and no batch running: one at a
             // time on the single-right-hand-side solver (its iterations move
             // about a sixth of the bytes of a 16-column batched iteration)
@@ -475,7 +554,7 @@ static void scheduler_tick(pamg_server* S) {
             S->progressed = true;
             continue;
         }
-        if (g->active >= kW || g->in_flight) {   // joins happen between blocks
+        if (g->active >= kW || g->in_flight || !ensure_engine(S, g, !S->opts.single_path)) {   // joins happen between blocks
             ++it;
             continue;
         }
@@ -524,7 +603,7 @@ static void scheduler_tick(pamg_server* S) {
     }
     for (auto& kv : S->groups) {
         ServeGroup* g = kv.second;
-        if (g->in_flight || g->active == 0 || batch_state_host(g->E).all_done) continue;
+        if (g->in_flight || g->active == 0 || !g->E || batch_state_host(g->E).all_done) continue;
         for (int c = 0; c < kW; ++c) g->iter_before[c] = batch_state_host(g->E).col[c].iter;
         batch_run_block(g->E, PAMG_KRYLOV_FCG, k, S->opts.use_graph != 0, g->stream);
         batch_read_state_async(g->E, g->stream);

@@ -188,9 +188,9 @@ def test_single_path_results(ops, prec, graph, batch_from):
 
 @pytest.mark.parametrize("prec", [pamg.PREC_F32, pamg.PREC_F64])
 def test_admission_estimate_bounds_the_cached_bytes(ops, prec):
-    # the admission charge of an operator (hierarchy + 16-column engine, the
-    # FP32 engine with its FP32 copy of the level-0 right-hand side) is an
-    # upper bound of the bytes it holds once cached, and not a loose one
+    # the admission charge of an operator (its hierarchy; a 16-column engine is
+    # charged when it is built) is an upper bound of the bytes it holds once
+    # cached, and not a loose one
     from workloads import q1_stretched
     cases = [ops[0], ops[2], varcoef7(40, seed=91), q1_stretched(16, 1.05)]
     for A in cases:
@@ -207,15 +207,17 @@ def test_admission_estimate_bounds_the_cached_bytes(ops, prec):
 
 
 def test_tiny_budget_queues_and_evicts(ops):
-    # room for about one operator at a time: requests for the others wait,
-    # idle operators are evicted, everything still completes
+    # room for about one batched operator (hierarchy and 16-column engine) at
+    # a time: requests for the others wait, idle operators give up their
+    # engines or are evicted, everything still completes
     est = max(pamg.server_estimate_bytes(A) for A in ops.values())
     reqs = make_requests(ops, 24, seed=11)
     xs, done, stats = serve(ops, reqs, hbm_budget_bytes=int(est * 1.02))
     assert stats.completed == 24 and stats.rejected == 0
-    # the four operators do not fit together: idle ones were evicted (how many
-    # depends on which operators happen to fit beside each other)
-    assert stats.evictions >= 1 and stats.setups >= len(ops)
+    # the four batched operators do not fit together (which ones fit beside
+    # each other decides how many engines are freed and operators evicted)
+    assert stats.engines_built >= len(ops) and stats.setups >= len(ops)
+    assert stats.engines_freed + stats.evictions >= 1
     assert stats.bytes_in_use <= stats.hbm_budget_bytes
     for tag, k, b in reqs:
         assert done[tag].status == pamg.OK
@@ -260,3 +262,53 @@ def test_setup_runs_beside_solves(ops):
     assert st.host_setup_ms > 0 and st.setups == 2
     rel = np.linalg.norm(bb.cpu().numpy() - big.to_scipy() @ xb.cpu().numpy()) / np.linalg.norm(bb.cpu().numpy())
     assert rel <= 1e-6
+
+
+def test_engines_are_built_on_demand_and_freed_before_evictions(ops):
+    # single-right-hand-side path on: an operator whose requests come alone
+    # holds only its hierarchy; several waiting requests build its 16-column
+    # engine; with room for every hierarchy and the largest engine but not
+    # for every engine, idle operators give up their engines (an operator
+    # waits on the single path while the room is busy) and none is evicted
+    reqs = make_requests(ops, 40, seed=13)
+    big = 1 << 36
+    _, _, st_hier = serve(ops, reqs, hbm_budget_bytes=big, single_path=1, batch_from=1000)
+    assert st_hier.engines_built == 0 and st_hier.setups == len(ops)
+    _, _, st_all = serve(ops, reqs, hbm_budget_bytes=big, single_path=1, batch_from=2)
+    assert st_all.engines_built == len(ops) and st_all.engines_freed == 0
+    hier = st_hier.bytes_in_use
+    engines = st_all.bytes_in_use - hier
+    # admission charges an upper estimate until the hierarchy exists
+    room = max(max(pamg.server_estimate_bytes(A) for A in ops.values()), engines // 2)
+    assert room < engines, (room, engines)
+    budget = hier + room
+
+    S = pamg.Server(hbm_budget_bytes=budget, single_path=1, batch_from=2)
+    xs = {}
+
+    def submit(batch):
+        for tag, k, b in batch:
+            x = torch.zeros(ops[k].n, dtype=torch.float64, device="cuda:0")
+            bd = dev(b)
+            torch.cuda.current_stream().synchronize()
+            xs[tag] = (x, bd)
+            S.submit(k, ops[k], bd, x, tol=1e-6, tag=tag)
+        return wait_all(S, len(batch))
+
+    # one lone request per operator: every hierarchy cached, no engine
+    first = [(100 + k, k, SplitMix64(500 + k).uniform(ops[k].n)) for k in ops]
+    done = submit(first)
+    st = S.stats()
+    assert st.setups == len(ops) and st.engines_built == 0 and st.bytes_in_use == hier
+    done.update(submit(reqs))
+    st = S.stats()
+    S.close()
+    assert st.completed == 40 + len(ops) and st.rejected == 0
+    assert st.evictions == 0 and st.setups == len(ops)
+    assert st.engines_built >= 2 and st.engines_freed >= 1
+    assert st.bytes_in_use <= budget
+    for tag, k, b in first + reqs:
+        assert done[tag].status == pamg.OK
+        x = xs[tag][0].cpu().numpy()
+        rel = np.linalg.norm(b - ops[k].to_scipy() @ x) / np.linalg.norm(b)
+        assert rel <= 1e-6
