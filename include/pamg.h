@@ -134,7 +134,17 @@ typedef struct {
                                  tentative prolongator is smoothed (the paper's configuration);
                                  with pairwise aggregates the coarse matrices fill in quickly.
                                  Default 0. */
-    int32_t reserved[1];
+    int32_t device_setup;     /* 1: build the large levels on the device (pairwise aggregates,
+                                 tentative prolongators, l1-Jacobi, weight-eligible edges; other
+                                 configurations and small inputs are built on the host).  The
+                                 hierarchy is bitwise the host-built one: the matching is the
+                                 greedy matching under the same strict order, computed as
+                                 locally dominant edges in parallel rounds (Sec. 3.1, eq.
+                                 (approximatematch)), and every Galerkin entry sums its terms in
+                                 the same order.  Default 0. */
+    int32_t device_min_rows;  /* device_setup: levels with at most this many rows (or max_dense or
+                                 max_coarse, if larger) are built on the host (0: 65536) */
+    int32_t reserved[2];
 } pamg_params;
 
 typedef struct {
@@ -178,6 +188,8 @@ typedef struct {
                                        2 (nnz_l (4 + s) + 4 (n_l + 1)) + (10 n_l + 2 n_{l+1}) s,
                                        plus (n_L^2 + 2 n_L) s */
     uint64_t csr_vcycle_bytes_f32;  /* same with s = 4 (0 if not built) */
+    int32_t device_levels;    /* levels built on the device (device_setup), the finest ones */
+    int32_t reserved0;
 } pamg_hier_info;
 
 /* Fill defaults. */

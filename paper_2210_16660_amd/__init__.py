@@ -48,7 +48,7 @@ class pamg_params(C.Structure):
                 ("check_symmetry", C.c_int32), ("host_only", C.c_int32), ("min_ratio", C.c_double),
                 ("agg_steps", C.c_int32), ("smoother", C.c_int32), ("sweeps", C.c_int32),
                 ("gs_block", C.c_int32), ("omega", C.c_double), ("smooth_prolongator", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("device_setup", C.c_int32), ("device_min_rows", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class pamg_solve_opts(C.Structure):
@@ -67,7 +67,8 @@ class pamg_hier_info(C.Structure):
                 ("pairs", C.c_int32 * MAX_LEVELS), ("setup_ms", C.c_double), ("operator_complexity", C.c_double),
                 ("device_bytes", C.c_uint64), ("vcycle_bytes_f64", C.c_uint64), ("vcycle_bytes_f32", C.c_uint64),
                 ("spmv_bytes", C.c_uint64), ("tile_items", C.c_int32 * MAX_LEVELS),
-                ("csr_vcycle_bytes_f64", C.c_uint64), ("csr_vcycle_bytes_f32", C.c_uint64)]
+                ("csr_vcycle_bytes_f64", C.c_uint64), ("csr_vcycle_bytes_f32", C.c_uint64),
+                ("device_levels", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class pamg_server_opts(C.Structure):

@@ -5,8 +5,10 @@
   is one IEEE operation per written operation.
 * csrc/device.hip (single right-hand side kernels, driver, C ABI),
   csrc/batch.hip (16 right-hand sides), csrc/serve.hip (server),
-  csrc/dense.hip (coarsest-level factorization) and csrc/reuse.hip
-  (coefficient-only updates) are compiled with hipcc for
+  csrc/dense.hip (coarsest-level factorization), csrc/reuse.hip
+  (coefficient-only updates), csrc/context.hip (allocation) and
+  csrc/dsetup.hip (device construction of the large levels, with
+  -ffp-contract=off like setup.cpp) are compiled with hipcc for
   gfx950 (in parallel).  Packed-FP32 instructions are disabled for all device
   code.
 """
@@ -40,9 +42,11 @@ def build(verbose: bool = True) -> str:
           "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     objs = []
     procs = []
-    for name in ("device", "batch", "serve", "dense", "reuse", "context"):
+    for name in ("device", "batch", "serve", "dense", "reuse", "context", "dsetup"):
         o = os.path.join(BUILD, f"{name}.o")
-        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32,
+        # the device setup reproduces the host's floating-point operations one by one
+        exact = ["-ffp-contract=off"] if name == "dsetup" else []
+        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *NO_PACKED_FP32, *exact,
                "-I", INC, "-I", CSRC, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o]
         print(" ".join(cmd), flush=True)
         procs.append((name, subprocess.Popen(cmd)))

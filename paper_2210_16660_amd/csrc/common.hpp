@@ -106,7 +106,11 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 // setup.cpp
 void validate_csr(const pamg_csr& A, bool check_symmetry);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
+void extend_hierarchy(HostHierarchy& H, const pamg_params& prm);
 std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
+int first_tile_items(int64_t nnz);
+void make_tiles(const std::vector<int32_t>& rp, const std::vector<int32_t>& aggptr, int32_t n, int32_t nc,
+                int32_t cap, std::vector<int32_t>& up, std::vector<int32_t>& down);
 
 // Smoothed prolongator of level l in hierarchical numbering (P and P^T).
 void sa_layout(const HostCSR& P, const LayoutLevel& fine, const LayoutLevel& coarse, LayoutLevel& out);

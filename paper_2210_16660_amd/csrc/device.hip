@@ -14,6 +14,7 @@
 #include "hier.hpp"
 #include "kernels_gs.hpp"
 #include "kernels_sa.hpp"
+#include "dsetup.hpp"
 
 namespace pamg {
 
@@ -32,24 +33,56 @@ static T* upload(pamg_hierarchy* h, const std::vector<S>& src, hipStream_t s) {
     return d;
 }
 
+// A device array converted to another precision (the FP32 copy of a
+// device-built level: each value rounded as on the host).
+template <typename D, typename S>
+static D* convert_copy(pamg_hierarchy* h, const S* src, long long n, hipStream_t s) {
+    D* d = dalloc<D>(h, (size_t)n, s);
+    if (n > 0)
+        hipLaunchKernelGGL((k_convert<S, D>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, src, d);
+    return d;
+}
+
+// Values of every level: levels below db->m from the device build (FP64 as
+// built, FP32 converted on the device), the others uploaded from `lay`
+// (level db->m + j is lay[j]).
 template <typename T>
-static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<LayoutLevel>& lay, hipStream_t s) {
-    const int nl = (int)lay.size();
+static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<LayoutLevel>& lay,
+                          const DeviceBuild* db, hipStream_t s) {
+    const int m = db ? db->m : 0;
+    const int nl = m + (int)lay.size();
     V.v.resize(nl); V.dinv.resize(nl);
     V.vd.assign(nl, nullptr); V.p.assign(nl, nullptr); V.r.assign(nl, nullptr); V.zp.assign(nl, nullptr);
     size_t maxn = 0;
     for (int l = 0; l < nl; ++l) {
-        V.v[l] = upload<T>(h, lay[l].v, s);
-        V.dinv[l] = upload<T>(h, lay[l].dinv, s);
-        if (l + 1 < nl) {
-            V.vd[l] = upload<T>(h, lay[l].vd, s);
-            V.p[l] = upload<T>(h, lay[l].p, s);
-            V.zp[l] = dalloc<T>(h, lay[l].dinv.size(), s);
+        const size_t n = (size_t)h->idx[l].n;
+        if (l < m) {
+            const DevLevelOut& D = db->dev[l];
+            if constexpr (std::is_same<T, double>::value) {
+                V.v[l] = D.v;
+                V.dinv[l] = D.dinv;
+                V.vd[l] = D.vd;
+                V.p[l] = D.p;
+            } else {
+                V.v[l] = convert_copy<T>(h, D.v, D.nnz, s);
+                V.dinv[l] = convert_copy<T>(h, D.dinv, D.n, s);
+                V.vd[l] = convert_copy<T>(h, D.vd, D.nnz, s);
+                V.p[l] = convert_copy<T>(h, D.p, D.n, s);
+            }
+        } else {
+            const LayoutLevel& Ly = lay[l - m];
+            V.v[l] = upload<T>(h, Ly.v, s);
+            V.dinv[l] = upload<T>(h, Ly.dinv, s);
+            if (l + 1 < nl) {
+                V.vd[l] = upload<T>(h, Ly.vd, s);
+                V.p[l] = upload<T>(h, Ly.p, s);
+            }
         }
-        if (l >= 1) V.r[l] = dalloc<T>(h, lay[l].dinv.size(), s);
-        maxn = std::max(maxn, lay[l].dinv.size());
+        if (l + 1 < nl) V.zp[l] = dalloc<T>(h, n, s);
+        if (l >= 1) V.r[l] = dalloc<T>(h, n, s);
+        maxn = std::max(maxn, n);
     }
-    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {   // host-built hierarchies only
         V.gsa.assign(nl, nullptr);
         V.zt.assign(nl, nullptr);
         V.sa_pv.assign(nl, nullptr);
@@ -74,8 +107,8 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         const long long nn = (long long)C.n * C.n;
         hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(nn)), dim3(kBlock), 0, s, nn,
                            (const double*)h->f64.ainv, V.ainv);
-        HIP_CHECK(hipStreamSynchronize(s));
     }
+    HIP_CHECK(hipStreamSynchronize(s));
     V.dbg_in = dalloc<T>(h, maxn, s);
     V.dbg_in2 = dalloc<T>(h, maxn, s);
     V.built = true;
@@ -116,16 +149,49 @@ static uint64_t csr_vcycle_bytes(const pamg_hierarchy* h, uint64_t s) {
     return B;
 }
 
-void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bool build_f32, hipStream_t s) {
-    const int nl = (int)lay.size();
+// The device levels of the hierarchy: levels below db->m (if any) from the
+// device build, the others uploaded from `lay` (level db->m + j is lay[j]);
+// then the solver's vectors and the level summary.
+void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bool build_f32, hipStream_t s,
+                      const DeviceBuild* db) {
+    const int m = db ? db->m : 0;
+    const int nl = m + (int)lay.size();
     h->L = nl - 1;
     h->idx.resize(nl);
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l < m; ++l) {
         DevLevelIdx& I = h->idx[l];
-        const LayoutLevel& Ly = lay[l];
+        const DevLevelOut& D = db->dev[l];
+        I.n = D.n;
+        I.nnz = D.nnz;
+        I.nc = D.nc;
+        I.items = D.items;
+        I.rp = D.rp;
+        I.ci = D.ci;
+        I.perm = D.perm;
+        I.iperm = D.iperm;
+        I.aggptr = D.aggptr;
+        I.max_agg = D.pairs > 0 ? 2 : 1;
+        I.up_tiles = reinterpret_cast<const int4*>(D.up_tiles);
+        I.n_up = D.n_up;
+        I.down_tiles = reinterpret_cast<const int4*>(D.down_tiles);
+        I.n_down = D.n_down;
+        auto dict = [&](const DevDict& d, const int2*& span, const int*& col, const uint16_t*& loc, int& dmax,
+                        long long& dlen) {
+            span = reinterpret_cast<const int2*>(d.span ? d.span : dalloc<int>(h, 2, s));
+            col = d.col ? d.col : dalloc<int>(h, 1, s);
+            loc = d.loc ? d.loc : dalloc<uint16_t>(h, 1, s);
+            dmax = std::max(1, d.max_len);
+            dlen = d.len;
+        };
+        dict(D.up_dict, I.up_span, I.up_col, I.up_loc, I.up_dmax, I.up_dlen);
+        dict(D.down_dict, I.down_span, I.down_col, I.down_loc, I.down_dmax, I.down_dlen);
+    }
+    for (int l = m; l < nl; ++l) {
+        DevLevelIdx& I = h->idx[l];
+        const LayoutLevel& Ly = lay[l - m];
         I.n = (int)Ly.dinv.size();
         I.nnz = (long long)Ly.ci.size();
-        I.nc = (l + 1 < nl) ? (int)lay[l + 1].dinv.size() : 0;
+        I.nc = (l + 1 < nl) ? (int)lay[l + 1 - m].dinv.size() : 0;
         I.items = Ly.items;
         I.rp = upload<int>(h, Ly.rp, s);
         I.ci = upload<int>(h, Ly.ci, s);
@@ -164,8 +230,8 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
             }
         }
     }
-    upload_values<double>(h, h->f64, lay, s);
-    if (build_f32) upload_values<float>(h, h->f32, lay, s);
+    upload_values<double>(h, h->f64, lay, db, s);
+    if (build_f32) upload_values<float>(h, h->f32, lay, db, s);
     const int n0 = h->idx[0].n;
     int maxn = 0;
     for (auto& I : h->idx) maxn = std::max(maxn, I.n);
@@ -1121,7 +1187,7 @@ void set_last_error(const std::string& m) { g_last_error = m; }
 
 namespace pamg {
 
-std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm) {
+void check_params(const pamg_params& prm) {
     if (prm.max_coarse < 1 || prm.max_levels < 1 || prm.max_levels > PAMG_MAX_LEVELS || prm.max_dense < 1 ||
         prm.max_dense > kMaxDense || !(prm.min_ratio == prm.min_ratio) || prm.agg_steps < 1 || prm.agg_steps > kMaxAggSteps)
         throw Error(PAMG_E_INVALID, "bad params (need max_coarse >= 1, 1 <= max_levels <= 64, "
@@ -1139,6 +1205,12 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
     }
     if (prm.smooth_prolongator != 0 && (prm.smooth_prolongator != 1 || prm.smoother != PAMG_SMOOTHER_L1_JACOBI))
         throw Error(PAMG_E_INVALID, "smooth_prolongator = 1 needs the l1-Jacobi smoother");
+    if (prm.device_setup != 0 && prm.device_setup != 1) throw Error(PAMG_E_INVALID, "device_setup must be 0 or 1");
+    if (prm.device_min_rows < 0) throw Error(PAMG_E_INVALID, "device_min_rows must be >= 0");
+}
+
+std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm) {
+    check_params(prm);
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<HostBuild> b(new HostBuild());
@@ -1184,7 +1256,7 @@ pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, p
             }
             h->info.operator_complexity = tot / (double)h->info.nnz[0];
         } else {
-            upload_hierarchy(h, b->lay, b->prm.build_f32 != 0, stream);
+            upload_hierarchy(h, b->lay, b->prm.build_f32 != 0, stream, nullptr);
         }
     } catch (...) {
         destroy_hierarchy(h);
@@ -1193,6 +1265,94 @@ pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, p
     const double dev_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     h->info.setup_ms = b->host_ms + dev_ms;
     return h;
+}
+
+pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hipStream_t stream,
+                                   pamg_context* ctx) {
+    auto t0 = std::chrono::steady_clock::now();
+    set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
+    validate_csr(A, prm.check_symmetry != 0);
+    pamg_hierarchy* h = new_hierarchy(false, ctx);
+    try {
+        std::unique_ptr<DeviceBuild> db = device_build(h, A, prm, stream);
+        if (!db) {
+            destroy_hierarchy(h);
+            return nullptr;
+        }
+        const int m = db->m;
+        h->host.lev.resize(m);
+        for (int l = 0; l < m; ++l) {
+            h->host.lev[l].A.n = db->dev[l].n;
+            h->host.lev[l].pairs = db->dev[l].pairs;
+        }
+        for (HostLevel& hl : db->host.lev) h->host.lev.push_back(std::move(hl));
+        h->lazy_levels = m;
+        const int nl = m + (int)db->host_lay.size();
+        for (int l = 0; l < nl && l < PAMG_MAX_LEVELS; ++l)
+            h->info.tile_items[l] = l < m ? db->dev[l].items : db->host_lay[l - m].items;
+        upload_hierarchy(h, db->host_lay, prm.build_f32 != 0, stream, db.get());
+        h->info.device_levels = m;
+    } catch (...) {
+        destroy_hierarchy(h);
+        throw;
+    }
+    h->info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return h;
+}
+
+void ensure_host_levels(pamg_hierarchy* h) {
+    std::lock_guard<std::mutex> lk(h->host_mu);
+    if (h->lazy_levels == 0) return;
+    HIP_CHECK(hipSetDevice(h->device));
+    HIP_CHECK(hipDeviceSynchronize());
+    auto get = [](auto& out, const auto* d, size_t count) {
+        out.resize(count);
+        if (count) HIP_CHECK(hipMemcpy(out.data(), d, count * sizeof(out[0]), hipMemcpyDeviceToHost));
+    };
+    for (int l = 0; l < h->lazy_levels; ++l) {
+        const DevLevelIdx& I = h->idx[l];
+        const int n = I.n, nc = I.nc;
+        std::vector<int32_t> rp, ci, perm, iperm, aggptr, ciperm;
+        std::vector<double> v, dinv, p;
+        get(rp, I.rp, (size_t)n + 1);
+        get(ci, I.ci, (size_t)I.nnz);
+        get(v, h->f64.v[l], (size_t)I.nnz);
+        get(perm, I.perm, (size_t)n);
+        get(iperm, I.iperm, (size_t)n);
+        get(dinv, h->f64.dinv[l], (size_t)n);
+        get(p, h->f64.p[l], (size_t)n);
+        get(aggptr, I.aggptr, (size_t)nc + 1);
+        get(ciperm, h->idx[l + 1].iperm, (size_t)nc);
+        HostLevel& H = h->host.lev[l];
+        H.A.n = n;
+        H.A.rp.assign(n + 1, 0);
+        for (int32_t i = 0; i < n; ++i) H.A.rp[i + 1] = H.A.rp[i] + (rp[perm[i] + 1] - rp[perm[i]]);
+        H.A.ci.resize(I.nnz);
+        H.A.v.resize(I.nnz);
+        H.dinv.resize(n);
+        H.p.resize(n);
+        H.agg.resize(n);
+        parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+            std::vector<std::pair<int32_t, double>> row;
+            for (int64_t i = b; i < e; ++i) {
+                const int32_t ip = perm[i];
+                row.clear();
+                for (int32_t k = rp[ip]; k < rp[ip + 1]; ++k) row.emplace_back(iperm[ci[k]], v[k]);
+                std::sort(row.begin(), row.end(), [](const std::pair<int32_t, double>& x,
+                                                     const std::pair<int32_t, double>& y) { return x.first < y.first; });
+                const int32_t o = H.A.rp[i];
+                for (size_t u = 0; u < row.size(); ++u) {
+                    H.A.ci[o + u] = row[u].first;
+                    H.A.v[o + u] = row[u].second;
+                }
+                H.dinv[i] = dinv[ip];
+                H.p[i] = p[ip];
+            }
+        });
+        for (int32_t Ip = 0; Ip < nc; ++Ip)
+            for (int32_t ip = aggptr[Ip]; ip < aggptr[Ip + 1]; ++ip) H.agg[iperm[ip]] = ciperm[Ip];
+    }
+    h->lazy_levels = 0;
 }
 
 }  // namespace pamg
@@ -1234,6 +1394,11 @@ int pamg_setup(pamg_context* ctx, const pamg_csr* A, const pamg_params* params, 
         *out = nullptr;
         pamg_params prm;
         if (params) prm = *params; else pamg_params_default(&prm);
+        pamg::check_params(prm);
+        if (pamg::device_setup_applies(prm)) {
+            *out = pamg::device_setup_build(*A, prm, (hipStream_t)stream, ctx);
+            if (*out) return PAMG_OK;
+        }
         std::unique_ptr<pamg::HostBuild> hb = pamg::host_build(*A, prm);
         *out = pamg::finish_build(std::move(hb), (hipStream_t)stream, ctx);
         return PAMG_OK;
@@ -1257,6 +1422,7 @@ int pamg_hierarchy_aggregates(const pamg_hierarchy* h, int32_t level, int32_t* a
     return pamg::guarded([&]() -> int {
         if (!h || !agg) throw pamg::Error(PAMG_E_INVALID, "null argument");
         if (level < 0 || level >= h->L) throw pamg::Error(PAMG_E_INVALID, "level must be in [0, levels-2]");
+        pamg::ensure_host_levels(const_cast<pamg_hierarchy*>(h));
         const auto& a = h->host.lev[level].agg;
         std::memcpy(agg, a.data(), a.size() * sizeof(int32_t));
         return PAMG_OK;
@@ -1267,6 +1433,7 @@ int pamg_hierarchy_level_csr(const pamg_hierarchy* h, int32_t level, int32_t* rp
     return pamg::guarded([&]() -> int {
         if (!h || !rp || !ci || !v) throw pamg::Error(PAMG_E_INVALID, "null argument");
         if (level < 0 || level > h->L) throw pamg::Error(PAMG_E_INVALID, "level out of range");
+        pamg::ensure_host_levels(const_cast<pamg_hierarchy*>(h));
         const auto& A = h->host.lev[level].A;
         std::memcpy(rp, A.rp.data(), A.rp.size() * sizeof(int32_t));
         std::memcpy(ci, A.ci.data(), A.ci.size() * sizeof(int32_t));

@@ -129,6 +129,8 @@ struct pamg_hierarchy {
     int graph_k[2][2] = {{0, 0}, {0, 0}};
     std::vector<pamg::DevAlloc> allocs;
     pamg::HostHierarchy host;
+    int lazy_levels = 0;                      // finest levels built on the device: host copies made on first use
+    std::mutex host_mu;
     pamg_hier_info info{};
     std::mutex mu;
     std::unique_ptr<pamg::BatchEngine, pamg::BatchDeleter> batch[2];   // multi-RHS workspaces (FP64 / FP32 V-cycle)
@@ -170,6 +172,14 @@ std::unique_ptr<HostBuild> host_build(const pamg_csr& A, const pamg_params& prm)
 int coarsest_n(const HostBuild& b);
 // ctx: the context the hierarchy allocates from (null: the current device's default)
 pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, pamg_context* ctx);
+// The hierarchy with its large levels built on the device, or null when the
+// device construction does not apply (prm already checked).
+pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hipStream_t stream, pamg_context* ctx);
+// Host copies (canonical numbering) of the device-built levels, made once
+// from the device arrays: matrix, l1 inverse diagonal, aggregates and
+// prolongator entries (no near-null vector).
+void ensure_host_levels(pamg_hierarchy* h);
+void check_params(const pamg_params& prm);
 
 // Dense limit of the coarsest level (its FP64 inverse is n_L^2 doubles).
 constexpr int kMaxDense = 8192;

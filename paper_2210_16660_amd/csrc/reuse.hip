@@ -125,6 +125,7 @@ static void build_plan(pamg_hierarchy* h, hipStream_t s) {
         }
         return d;
     };
+    ensure_host_levels(h);
     const ChainView C{h->host};
     const int npw = C.levels(), nk = h->L + 1;
     R->npw = npw;

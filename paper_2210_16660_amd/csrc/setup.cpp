@@ -635,7 +635,20 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
                                             " unknowns, above the dense-solve limit");
         return H;
     }
-    for (int l = 0;; ++l) {
+    extend_hierarchy(H, prm);
+    const HostCSR& AL = H.lev.back().A;
+    if (AL.n > prm.max_dense)
+        throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
+                                        " unknowns, above the dense-solve limit");
+    if (prm.agg_steps > 1) compose_levels(H, prm.agg_steps);
+    return H;
+}
+
+// The pairwise loop of build_hierarchy from the last level of H (its A and w
+// set): l1 diagonal, matching, stop rules, aggregates, Galerkin product.  The
+// levels of H count towards max_levels.
+void extend_hierarchy(HostHierarchy& H, const pamg_params& prm) {
+    for (int l = (int)H.lev.size() - 1;; ++l) {
         HostLevel& cur = H.lev[l];
         const HostCSR& A = cur.A;
         const int32_t n = A.n;
@@ -696,12 +709,6 @@ HostHierarchy build_hierarchy(const pamg_csr& Ain, const pamg_params& prm) {
         next.w = std::move(wc);
         H.lev.push_back(std::move(next));
     }
-    const HostCSR& AL = H.lev.back().A;
-    if (AL.n > prm.max_dense)
-        throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
-                                        " unknowns, above the dense-solve limit");
-    if (prm.agg_steps > 1) compose_levels(H, prm.agg_steps);
-    return H;
 }
 
 // ------------------------------------------- smoothed prolongator layout
@@ -916,6 +923,40 @@ static TileDict build_dicts(const std::vector<int32_t>& tiles, const std::vector
     return D;
 }
 
+// Tile capacity of a level: the largest power of two <= kMaxItems with at
+// least kTargetTiles tiles' worth of entries (small levels get small tiles).
+int first_tile_items(int64_t nnz) {
+    int items = kMaxItems;
+    while (items > 1 && (int64_t)items * kBlock * kTargetTiles > nnz) items /= 2;
+    return items;
+}
+
+// Row tiles: <= kTileRows rows and <= cap entries, or a single long row.
+// Restriction tiles over coarse rows: the <= kTileRows fine rows of
+// <= kTileRows aggregates holding <= cap entries, or a single aggregate (at
+// most 2^kMaxAggSteps members).  4 ints per tile: k0, k1, first, end.
+void make_tiles(const std::vector<int32_t>& rp, const std::vector<int32_t>& aggptr, int32_t n, int32_t nc,
+                int32_t cap, std::vector<int32_t>& up, std::vector<int32_t>& down) {
+    up.clear();
+    int32_t start = 0;
+    while (start < n) {
+        int32_t end = start + 1;
+        while (end < n && end - start < kTileRows && rp[end + 1] - rp[start] <= cap) ++end;
+        up.insert(up.end(), {rp[start], rp[end], start, end});
+        start = end;
+    }
+    down.clear();
+    start = 0;
+    while (start < nc) {
+        int32_t end = start + 1;
+        while (end < nc && end - start < kTileRows && aggptr[end + 1] - aggptr[start] <= kTileRows &&
+               rp[aggptr[end + 1]] - rp[aggptr[start]] <= cap)
+            ++end;
+        down.insert(down.end(), {rp[aggptr[start]], rp[aggptr[end]], start, end});
+        start = end;
+    }
+}
+
 // Hierarchical numbering: the coarsest level keeps its numbering; on every
 // finer level the members of each aggregate are placed next to each other,
 // in the order of their aggregate's (already permuted) coarse index, members
@@ -985,36 +1026,12 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
                 if (l + 1 < nl) L.p[ip] = hl.p[i];
             }
         });
-        // tile capacity: the largest power of two <= kMaxItems with at least
-        // kTargetTiles tiles' worth of entries (small levels get small tiles)
-        int items = kMaxItems;
-        while (items > 1 && (int64_t)items * kBlock * kTargetTiles > (int64_t)L.rp[n]) items /= 2;
+        int items = first_tile_items((int64_t)L.rp[n]);
         const int32_t nc = l + 1 < nl ? H.lev[l + 1].A.n : 0;
         for (;;) {
             L.items = items;
             const int32_t cap = items * kBlock;
-            // row tiles: <= kTileRows rows and <= cap entries, or a single long row
-            L.up_tiles.clear();
-            int32_t start = 0;
-            while (start < n) {
-                int32_t end = start + 1;
-                while (end < n && end - start < kTileRows && L.rp[end + 1] - L.rp[start] <= cap) ++end;
-                L.up_tiles.insert(L.up_tiles.end(), {L.rp[start], L.rp[end], start, end});
-                start = end;
-            }
-            // restriction tiles over coarse rows: the <= kTileRows fine rows of
-            // <= kTileRows aggregates holding <= cap entries, or a single
-            // aggregate (at most 2^kMaxAggSteps members)
-            L.down_tiles.clear();
-            start = 0;
-            while (start < nc) {
-                int32_t end = start + 1;
-                while (end < nc && end - start < kTileRows && L.aggptr[end + 1] - L.aggptr[start] <= kTileRows &&
-                       L.rp[L.aggptr[end + 1]] - L.rp[L.aggptr[start]] <= cap)
-                    ++end;
-                L.down_tiles.insert(L.down_tiles.end(), {L.rp[L.aggptr[start]], L.rp[L.aggptr[end]], start, end});
-                start = end;
-            }
+            make_tiles(L.rp, L.aggptr, n, nc, cap, L.up_tiles, L.down_tiles);
             if (items < kDictItems) break;            // small tiles gather per entry
             L.up_dict = build_dicts(L.up_tiles, L.ci, n, cap);
             if (nc > 0) L.down_dict = build_dicts(L.down_tiles, L.ci, n, cap);
