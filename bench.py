@@ -22,6 +22,9 @@ same system.  The hierarchy setup is timed separately.  Prints one JSON line.
     python bench.py --mode reuse --n 128 [--steps K]  (coefficient-only update of
                     the hierarchy for a second stretching ratio on the same
                     mesh, against a fresh setup; prints its own JSON line)
+    python bench.py --mode setup --n 256 [--steps K]  (hierarchy setup: the
+                    device construction of the large levels, K runs, against
+                    the host construction; prints its own JSON line)
     python bench.py --mode serve [--requests R] [--serve-load F]
                     [--budget-gib G] [--single-path 0|1] [--batch-from B]
                     [--setup-workers W]
@@ -305,7 +308,9 @@ def main() -> int:
                     help="seconds from the start by which the CPU baseline's oracle setup must be done")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "reuse"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "serve", "reuse", "setup"])
+    ap.add_argument("--device-setup", type=int, default=1, choices=[0, 1],
+                    help="build the large levels of the hierarchy on the device (bitwise the host build)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -362,6 +367,8 @@ def main() -> int:
         return bench_batch(args, A, torch, np, pamg, log)
     if args.mode == "reuse":
         return bench_reuse(args, A, b, torch, np, pamg, log)
+    if args.mode == "setup":
+        return bench_setup(args, A, torch, pamg, log)
     dev = torch.device("cuda:0")
 
     t0 = time.perf_counter()
@@ -369,11 +376,12 @@ def main() -> int:
                                                       omega=args.omega)
     if args.smooth_prolongator:
         smooth_kw["smooth_prolongator"] = 1
-    H = pamg.Hierarchy(A, build_f32=1, agg_steps=args.agg_steps, **smooth_kw)
+    H = pamg.Hierarchy(A, build_f32=1, agg_steps=args.agg_steps, device_setup=args.device_setup, **smooth_kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = H.info()
-    log(f"setup {setup_s:.2f}s, {info.levels} levels, operator complexity {info.operator_complexity:.3f}")
+    log(f"setup {setup_s:.2f}s ({info.device_levels} levels built on the device), {info.levels} levels, "
+        f"operator complexity {info.operator_complexity:.3f}")
 
     b_d = torch.from_numpy(b).to(dev)
     x_d = torch.zeros(A.n, dtype=torch.float64, device=dev)
@@ -512,6 +520,7 @@ def main() -> int:
                             "solution_relerr_vs_f64": err32, "vcycle_ms": round(vc["f32"]["ms"], 4),
                             "vcycle_GBps": r1(vc["f32"]["GBps"])},
         "setup_s": round(setup_s, 3),
+        "setup_device_levels": info.device_levels,
         "vcycle_ms": round(vc["f64"]["ms"], 4),
         "vcycle_GBps": r1(vc["f64"]["GBps"]),
         "vcycle_pct_peak": round(100 * vc["f64"]["GBps"] / HBM_PEAK_GBS, 2) if plain else None,
@@ -624,6 +633,44 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_setup(args, A, torch, pamg, log) -> int:
+    """Hierarchy setup time (FP64 and FP32 copies, as the solve benchmark
+    builds it): the device construction of the large levels against the host
+    construction, and a check that both give the same hierarchy."""
+    import numpy as np
+
+    def build(dev_setup):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = pamg.Hierarchy(A, build_f32=1, device_setup=dev_setup)
+        torch.cuda.synchronize()
+        return H, time.perf_counter() - t0
+
+    runs = []
+    for r in range(args.steps):
+        H, t = build(1)
+        runs.append(t)
+        log(f"device setup {r}: {t:.2f} s, {H.info().device_levels} device levels of {H.info().levels}")
+        if r + 1 < args.steps:
+            H.close()
+            del H
+    Hh, th = build(0)
+    log(f"host setup: {th:.2f} s")
+    i, ih = H.info(), Hh.info()
+    same = i.levels == ih.levels and all(i.n[l] == ih.n[l] and i.nnz[l] == ih.nnz[l] for l in range(i.levels))
+    probe = [0, min(3, i.levels - 2)]
+    for l in probe:
+        same = same and np.array_equal(H.aggregates(l), Hh.aggregates(l))
+    out = {"metric": "hierarchy setup time (s)", "value": round(min(runs), 3), "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"Q1 {args.n}^3 stretched (ratio {args.ratio}), pairwise aggregation, FP64 + FP32 "
+                                  "hierarchy copies", "n": A.n, "nnz": A.nnz, "levels": i.levels},
+           "device_setup_s": [round(t, 3) for t in runs], "device_levels": i.device_levels,
+           "host_setup_s": round(th, 3), "speedup_vs_host": round(th / min(runs), 2),
+           "same_hierarchy_sampled": bool(same)}
+    print(json.dumps(out), flush=True)
+    return 0 if same else 1
 
 
 def bench_reuse(args, A, b, torch, np, pamg, log) -> int:

@@ -219,52 +219,117 @@ __global__ void k_weights(int n, const int* rp, const int* ci, const double* v, 
     }
 }
 
+// Bitonic sort (ascending) of P (a power of two) keys in LDS by one workgroup.
+template <typename K>
+__device__ inline void lds_bitonic(K* key, int P) {
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+                const int a = 2 * t - (t & (stride - 1));
+                const int b = a + stride;
+                const K x = key[a], y = key[b];
+                const bool up = (a & size) == 0;
+                if ((x > y) == up) {
+                    key[a] = y;
+                    key[b] = x;
+                }
+            }
+            __syncthreads();
+        }
+}
+
 constexpr unsigned char kAlive = 0, kMatched = 1, kSingle = 2;
 
-// One round, first half: every alive vertex picks its heaviest eligible
-// neighbour that is not matched; none left: it stays single.
-__global__ void k_pick(int n, const int* rp, const int* ci, const double* c, const int* mate, unsigned char* state,
-                       int* cand) {
-    GRID_STRIDE(i, n) {
-        if (state[i] != kAlive) continue;
-        int best = -1;
-        double bc = 0.0;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-            const int j = ci[k];
-            const double cc = c[k];
-            if (j == (int)i || !(cc > 1.0) || mate[j] >= 0) continue;
-            if (best < 0 || heavier(cc, min((int)i, j), max((int)i, j), bc, min((int)i, best), max((int)i, best))) {
-                best = j;
-                bc = cc;
+// A neighbour of vertex i in the matching order: heavier first; for equal
+// weights the edge with the smaller (lo, hi) first, which for a fixed i is
+// the smaller neighbour index.  x > y: x comes after y.
+struct Nbr {
+    double c;
+    int j;
+    __device__ bool operator>(const Nbr& y) const { return c < y.c || (c == y.c && j > y.j); }
+};
+
+// Every vertex's eligible neighbours (c > 1) in the matching order, at its
+// row's positions in adj; their number in ecnt.  One wavefront per row.
+__global__ __launch_bounds__(64) void k_sort_adj(int n, const int* rp, const int* ci, const double* c, int* adj,
+                                                 int* ecnt) {
+    __shared__ Nbr key[kRowCap];
+    const int lane = threadIdx.x;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int b = rp[i], len = rp[i + 1] - b;
+        int P = 1;
+        while (P < len) P <<= 1;
+        int cnt = 0;
+        for (int t = lane; t < P; t += 64) {
+            Nbr x{-1.0, INT_MAX};
+            if (t < len) {
+                const int j = ci[b + t];
+                const double cc = c[b + t];
+                if (j != i && cc > 1.0) {
+                    x = Nbr{cc, j};
+                    ++cnt;
+                }
             }
+            key[t] = x;
         }
-        cand[i] = best;
-        if (best < 0) state[i] = kSingle;
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        __syncthreads();
+        lds_bitonic(key, P);
+        for (int t = lane; t < cnt; t += 64) adj[b + t] = key[t].j;
+        if (lane == 0) ecnt[i] = cnt;
+        __syncthreads();
     }
 }
 
-// Second half: mutual picks are matched.  cnt[0]: vertices still alive,
-// cnt[1]: vertices matched in this round.
-__global__ __launch_bounds__(kSB) void k_commit(int n, const int* cand, int* mate, unsigned char* state, int* cnt) {
-    int alive = 0, matched = 0;
+// One round, first half: every alive vertex picks its heaviest eligible
+// neighbour that is not matched (the first unmatched one in its sorted list;
+// matched vertices stay matched, so the cursor only moves forward); none
+// left: it stays single.
+__global__ void k_pick(int n, const int* rp, const int* ecnt, const int* adj, const int* mate, unsigned char* state,
+                       int* cur, int* cand) {
+    GRID_STRIDE(i, n) {
+        if (state[i] != kAlive) continue;
+        int q = cur[i];
+        const int e = rp[i] + ecnt[i];
+        while (q < e && mate[adj[q]] >= 0) ++q;
+        cur[i] = q;
+        if (q < e) {
+            cand[i] = adj[q];
+        } else {
+            cand[i] = -1;
+            state[i] = kSingle;
+        }
+    }
+}
+
+__global__ void k_cursor(int n, const int* rp, int* cur) { GRID_STRIDE(i, n) cur[i] = rp[i]; }
+
+// Second half: mutual picks are matched.  flag[0] = 1 if a vertex is still
+// alive after the round, flag[1] = 1 if a vertex was matched (plain stores of
+// 1, one per workgroup that has one; the caller clears them).
+constexpr int kCommitGrid = 2048;
+__global__ __launch_bounds__(kSB) void k_commit(int n, const int* cand, int* mate, unsigned char* state, int* flag) {
+    __shared__ int any[2];
+    if (threadIdx.x < 2) any[threadIdx.x] = 0;
+    __syncthreads();
+    bool alive = false, matched = false;
     GRID_STRIDE(i, n) {
         if (state[i] != kAlive) continue;
         const int j = cand[i];
         if (cand[j] == (int)i) {
             mate[i] = j;
             state[i] = kMatched;
-            ++matched;
+            matched = true;
         } else {
-            ++alive;
+            alive = true;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        alive += __shfl_down(alive, off);
-        matched += __shfl_down(matched, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (alive) atomicAdd(cnt, alive);
-        if (matched) atomicAdd(cnt + 1, matched);
+    if (alive) any[0] = 1;
+    if (matched) any[1] = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (any[0]) flag[0] = 1;
+        if (any[1]) flag[1] = 1;
     }
 }
 
@@ -306,25 +371,6 @@ __global__ void k_aggregate(int n, const int* mate, const double* w, const long 
     }
 }
 
-// Bitonic sort (ascending) of P (a power of two) keys in LDS by one workgroup.
-template <typename K>
-__device__ inline void lds_bitonic(K* key, int P) {
-    for (int size = 2; size <= P; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
-                const int a = 2 * t - (t & (stride - 1));
-                const int b = a + stride;
-                const K x = key[a], y = key[b];
-                const bool up = (a & size) == 0;
-                if ((x > y) == up) {
-                    key[a] = y;
-                    key[b] = x;
-                }
-            }
-            __syncthreads();
-        }
-}
-
 struct GTerm {
     int k1, k2, k3;
     double t;
@@ -341,6 +387,7 @@ __global__ __launch_bounds__(64) void k_galerkin(int nc, const int* mem_ptr, con
                                                  int* cnt, const long long* crp, int* cci, double* cv, int* bad) {
     __shared__ unsigned long long key[kTermCap];
     const int lane = threadIdx.x;
+    int longest = 0;
     for (int I = blockIdx.x; I < nc; I += gridDim.x) {
         const int q0 = mem_ptr[I], q1 = mem_ptr[I + 1];
         const int i0 = mem[q0], i1 = q1 - q0 > 1 ? mem[q0 + 1] : -1;
@@ -399,12 +446,11 @@ __global__ __launch_bounds__(64) void k_galerkin(int nc, const int* mem_ptr, con
             }
             runs += __popcll(mask);
         }
-        if (!FILL && lane == 0) {
-            cnt[I] = runs;
-            atomicMax(bad + 1, runs);
-        }
+        if (!FILL && lane == 0) cnt[I] = runs;
+        longest = max(longest, runs);
         __syncthreads();
     }
+    if (!FILL && lane == 0) atomicMax(bad + 1, longest);
 }
 
 // ------------------------------------------------------------ layout kernels
@@ -579,25 +625,42 @@ Coarsened coarsen(Temps& T, CanLevel& L, CanLevel& C, hipStream_t s) {
     HIP_CHECK(hipStreamSynchronize(s));
     if (head[0]) return kAsymmetric;
     T.release(diag);
-    // matching rounds
+    // eligible neighbours in the matching order
+    int* adj = T.get<int>(L.nnz);
+    int* ecnt = T.get<int>(n);
+    hipLaunchKernelGGL(k_sort_adj, dim3(grid_rows(n)), dim3(64), 0, s, n, (const int*)L.rp, (const int*)L.ci,
+                       (const double*)c, adj, ecnt);
+    T.release(c);
+    // matching rounds, kRoundsPerCheck between looks at the counters (a
+    // round with nothing alive changes nothing); every round with an alive
+    // vertex matches at least the heaviest picked edge
+    constexpr int kRoundsPerCheck = 8;
     int* mate = T.get<int>(n);
     int* cand = T.get<int>(n);
+    int* cur = T.get<int>(n);
     unsigned char* state = T.get<unsigned char>(n);
     HIP_CHECK(hipMemsetAsync(mate, 0xff, sizeof(int) * n, s));
     HIP_CHECK(hipMemsetAsync(state, 0, n, s));
+    hipLaunchKernelGGL(k_cursor, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)L.rp, cur);
     int* cnt = flag + 2;
-    for (int round = 0;; ++round) {
+    const int gc = std::min(grid_for(n, kSB), kCommitGrid);
+    for (long long round = 0;; round += kRoundsPerCheck) {
         HIP_CHECK(hipMemsetAsync(cnt, 0, 2 * sizeof(int), s));
-        hipLaunchKernelGGL(k_pick, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)L.rp, (const int*)L.ci,
-                           (const double*)c, (const int*)mate, state, cand);
-        hipLaunchKernelGGL(k_commit, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)cand, mate, state, cnt);
+        for (int r = 0; r < kRoundsPerCheck; ++r) {
+            HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int), s));
+            hipLaunchKernelGGL(k_pick, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)L.rp,
+                               (const int*)ecnt, (const int*)adj, (const int*)mate, state, cur, cand);
+            hipLaunchKernelGGL(k_commit, dim3(gc), dim3(kSB), 0, s, n, (const int*)cand, mate, state, cnt);
+        }
         int rc[2];
         HIP_CHECK(hipMemcpyAsync(rc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         if (rc[0] == 0) break;
         if (rc[1] == 0 || round > n) throw Error(PAMG_E_DEVICE, "device matching made no progress");
     }
-    T.release(c);
+    T.release(adj);
+    T.release(ecnt);
+    T.release(cur);
     T.release(cand);
     T.release(state);
     // aggregates
