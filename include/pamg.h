@@ -141,7 +141,7 @@ typedef struct {
                                  greedy matching under the same strict order, computed as
                                  locally dominant edges in parallel rounds (Sec. 3.1, eq.
                                  (approximatematch)), and every Galerkin entry sums its terms in
-                                 the same order.  Default 0. */
+                                 the same order.  Default 1 (0: host only). */
     int32_t device_min_rows;  /* device_setup: levels with at most this many rows (or max_dense or
                                  max_coarse, if larger) are built on the host (0: 65536) */
     int32_t reserved[2];

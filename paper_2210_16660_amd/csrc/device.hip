@@ -1373,6 +1373,8 @@ int pamg_params_default(pamg_params* p) {
     p->build_f32 = 0;
     p->num_threads = 0;
     p->check_symmetry = 0;
+    p->device_setup = 1;
+    p->device_min_rows = 0;
     return PAMG_OK;
 }
 

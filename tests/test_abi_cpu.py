@@ -32,6 +32,7 @@ def test_defaults():
     p = pamg.params()
     assert (p.max_coarse, p.max_levels, p.max_dense, p.match_all_edges) == (200, 50, 8192, 0)
     assert p.min_ratio == 1.5
+    assert (p.device_setup, p.device_min_rows) == (1, 0)
     o = pamg.solve_opts()
     assert o.tol == 1e-6 and o.maxit == 1000 and o.krylov == pamg.KRYLOV_FCG and o.check_every == 4
 

@@ -116,7 +116,7 @@ def test_coefficient_update_on_a_device_built_hierarchy():
     A = varcoef7(40, seed=31)
     B = varcoef7(40, seed=32)          # same pattern, new coefficients
     Hd = pamg.Hierarchy(A, device_setup=1, device_min_rows=1000)
-    Hh = pamg.Hierarchy(A)
+    Hh = pamg.Hierarchy(A, device_setup=0)
     assert Hd.info().device_levels >= 2
     Hd.update_values(B.val)
     Hh.update_values(B.val)
@@ -150,7 +150,7 @@ def test_configurations_left_to_the_host():
     ]
     for A, kw in cases:
         Hd = pamg.Hierarchy(A, device_setup=1, **kw)
-        Hh = pamg.Hierarchy(A, **{k: v for k, v in kw.items() if k != "device_min_rows"})
+        Hh = pamg.Hierarchy(A, device_setup=0, **{k: v for k, v in kw.items() if k != "device_min_rows"})
         assert Hd.info().device_levels == 0
         assert Hd.levels == Hh.levels
         for l in range(Hh.levels - 1):
@@ -167,7 +167,7 @@ def test_value_asymmetry_uses_the_upper_entry_like_the_host():
     v[low] = np.nextafter(v[low], 0.0)
     B = CSR(A.n, A.row_ptr, A.col, v)
     Hd = pamg.Hierarchy(B, device_setup=1, device_min_rows=1000)
-    Hh = pamg.Hierarchy(B)
+    Hh = pamg.Hierarchy(B, device_setup=0)
     assert Hd.info().device_levels >= 2
     for l in range(Hh.levels - 1):
         assert np.array_equal(Hd.aggregates(l), Hh.aggregates(l))
