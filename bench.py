@@ -560,7 +560,7 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
     Bm = q1_rhs_sequence(args.n, args.ratio, 4, 16).T.copy()        # (16, n)
     log(f"16 right-hand sides in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    H = pamg.Hierarchy(A, build_f32=1)
+    H = pamg.Hierarchy(A, build_f32=1, device_setup=args.device_setup)
     B = torch.from_numpy(Bm).to(dev)
     X = torch.zeros_like(B)
     S = A.to_scipy()
@@ -617,6 +617,7 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
                                          * max(i.iterations for i in infos) / tb / 1e9, 1)}
         log(f"{name}: batch {1e3 * tb:.1f} ms, 16 singles {1e3 * ts:.1f} ms, max true relres {rel:.2e}")
     cfg = H.batch_config(pamg.PREC_F32)
+    cfg64 = H.batch_config(pamg.PREC_F64)
     out = {
         "metric": "16-RHS batched FCG+AMG solve time to 1e-6 (solves/s)",
         "value": res["f32"]["batch_solves_per_s"],
@@ -629,7 +630,7 @@ def bench_batch(args, A, torch, np, pamg, log) -> int:
         "speedup_batch_f32_vs_16_single_f64": round(res["f64"]["single16_ms"] / res["f32"]["batch_ms"], 3),
         "speedup_batch_f32_vs_16_single_f32": round(res["f32"]["single16_ms"] / res["f32"]["batch_ms"], 3),
         "speedup_batch_f64_vs_16_single_f64": round(res["f64"]["single16_ms"] / res["f64"]["batch_ms"], 3),
-        "autotuned_f32": cfg,
+        "autotuned_f32": cfg, "autotuned_f64": cfg64,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -59,6 +59,7 @@ struct BatchEngine {
     double *X = nullptr, *R = nullptr, *Z = nullptr, *P[2] = {nullptr, nullptr}, *Q = nullptr, *B = nullptr,
            *Y = nullptr;
     float* R32 = nullptr;                     // FP32 V-cycle: R rounded once per cycle for level 0
+    float* Z32 = nullptr;                     // FP32 V-cycle (L >= 1): its result z, exact in FP32
     double *partial = nullptr, *partial_b = nullptr;
     BatchState* st = nullptr;
     BatchState* st_host = nullptr;            // pinned
@@ -131,7 +132,9 @@ static void launch_up_b(const DevLevelIdx& I, const DevLevelIdx& F, int v, const
     });
 }
 
-// z (E->Z) = B r (E->R), per column; partials of z . dv.  Returns their count.
+// z = B r (E->R), per column; partials of z . dv.  Returns their count.  z is
+// E->Z, or E->Z32 with the FP32 cycle on a hierarchy of several levels (the
+// cycle's last step computes it in FP32).
 // The level-0 right-hand side as the V-cycle reads it: with the FP32 cycle,
 // R rounded to FP32 once (the kernels would round each load the same way),
 // so that its gathers move 64-byte lines instead of 128-byte ones.
@@ -204,8 +207,10 @@ static int enqueue_vcycle_b(BatchEngine* E, DevVals<T>& V, const double* dv, con
     }
     const DevLevelIdx& I0 = h->idx[0];
     const int g = unit_grid(I0.n, up0_rows_per_block<T>());
+    T* zout;
+    if constexpr (std::is_same<T, float>::value) zout = E->Z32; else zout = E->Z;
     hipLaunchKernelGGL((kb_up0<T>), dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
-                       (const T*)V.v[0], (const T*)E->zp[0], (const T*)r0, (const T*)V.dinv[0], E->Z, dv,
+                       (const T*)V.v[0], (const T*)E->zp[0], (const T*)r0, (const T*)V.dinv[0], zout, dv,
                        E->partial, done);
     return g;
 }
@@ -219,9 +224,16 @@ static void enqueue_iteration_b(BatchEngine* E, DevVals<T>& V, int krylov, int p
     hipLaunchKernelGGL(kb_fin_beta, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, cnt);
     const DevLevelIdx& I0 = h->idx[0];
     const int gk = unit_grid(I0.n, kKrylovRowsPerBlock);
-    hipLaunchKernelGGL(kb_krylov_pq, dim3(gk), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
-                       (const double*)h->f64.v[0], (const double*)E->Z, (const double*)E->P[parity], E->P[1 - parity],
-                       E->Q, (const double*)E->R, (const BatchState*)E->st, E->partial, done);
+    if (std::is_same<T, float>::value && h->L > 0)
+        hipLaunchKernelGGL(kb_krylov_pq<float>, dim3(gk), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp,
+                           (const int*)I0.ci, (const double*)h->f64.v[0], (const float*)E->Z32,
+                           (const double*)E->P[parity], E->P[1 - parity], E->Q, (const double*)E->R,
+                           (const BatchState*)E->st, E->partial, done);
+    else
+        hipLaunchKernelGGL(kb_krylov_pq<double>, dim3(gk), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp,
+                           (const int*)I0.ci, (const double*)h->f64.v[0], (const double*)E->Z,
+                           (const double*)E->P[parity], E->P[1 - parity], E->Q, (const double*)E->R,
+                           (const BatchState*)E->st, E->partial, done);
     hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, gk);
     const int g = unit_grid(I0.n, kBlock / kW);
     hipLaunchKernelGGL(kb_update, dim3(g), dim3(kBlock), 0, s, I0.n, E->X, E->R, (const double*)E->P[1 - parity],
@@ -313,7 +325,10 @@ static BatchEngine* create_engine(pamg_hierarchy* h, DevVals<T>& V, int prec, hi
     const size_t n0 = (size_t)h->idx[0].n * kW;
     E->X = balloc<double>(E.get(), n0, s);
     E->R = balloc<double>(E.get(), n0, s);
-    if (std::is_same<T, float>::value) E->R32 = balloc<float>(E.get(), n0, s);
+    if (std::is_same<T, float>::value) {
+        E->R32 = balloc<float>(E.get(), n0, s);
+        E->Z32 = balloc<float>(E.get(), n0, s);
+    }
     E->Z = balloc<double>(E.get(), n0, s);
     E->P[0] = balloc<double>(E.get(), n0, s);
     E->P[1] = balloc<double>(E.get(), n0, s);
@@ -395,7 +410,7 @@ uint64_t engine_bytes(const pamg_hierarchy* h, int prec) {
         if (l < L) b += n * s;
     }
     const uint64_t n0 = (uint64_t)h->idx[0].n * kW;
-    b += (uint64_t)h->idx[L].n * kW * s + 8 * n0 * 8 + (prec == PAMG_PREC_F32 ? n0 * 4 : 0);
+    b += (uint64_t)h->idx[L].n * kW * s + 8 * n0 * 8 + (prec == PAMG_PREC_F32 ? 2 * n0 * 4 : 0);
     b += 2 * (uint64_t)kMaxGrid * kW * 2 * 8 + sizeof(BatchState) + 2 * kW * sizeof(void*);
     return b;
 }
@@ -609,15 +624,19 @@ static void debug_batch_impl(BatchEngine* E, DevVals<T>& V, int op, const double
                                (const T*)V.ainv, (const T*)rin, (T*)E->Y, (const int*)nullptr, (const double*)nullptr,
                                (const T*)nullptr, (const T*)nullptr, (T*)nullptr, E->Z, (const double*)E->Z,
                                E->partial, nodone);
-        hipLaunchKernelGGL(kb_cols_out, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm, (const double*)E->Z,
-                           out);
+        hipLaunchKernelGGL(kb_cols_out<double>, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm,
+                           (const double*)E->Z, out);
     } else if (op == PAMG_OP_VCYCLE) {
         const DevLevelIdx& I = h->idx[0];
         const int g = std::min(kMaxGrid, std::max(1, (I.n * kW + kBlock - 1) / kBlock));
         hipLaunchKernelGGL((kb_cols_in<double>), dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.iperm, in, E->R);
         enqueue_vcycle_b<T>(E, V, E->Q, nodone, s);
-        hipLaunchKernelGGL(kb_cols_out, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm, (const double*)E->Z,
-                           out);
+        if (std::is_same<T, float>::value && L > 0)
+            hipLaunchKernelGGL(kb_cols_out<float>, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm,
+                               (const float*)E->Z32, out);
+        else
+            hipLaunchKernelGGL(kb_cols_out<double>, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm,
+                               (const double*)E->Z, out);
     } else {
         throw Error(PAMG_E_INVALID, "batched debug operators: COARSE or VCYCLE");
     }

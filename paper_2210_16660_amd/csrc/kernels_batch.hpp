@@ -219,11 +219,13 @@ constexpr int up0_cols() { return 4; }
 template <typename T>
 constexpr int up0_rows_per_block() { return kBlock / (kW / up0_cols<T>()); }
 
+// z is written in the cycle's precision T: with the FP32 cycle z is a float
+// (exactly its FP64 widening), so the Krylov pass gathers 64-byte rows.
 template <typename T>
 static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const T* __restrict__ av, const T* __restrict__ zp,
                                                  const T* __restrict__ r, const T* __restrict__ dinv,
-                                                 double* __restrict__ z_out, const double* __restrict__ dv,
+                                                 T* __restrict__ z_out, const double* __restrict__ dv,
                                                  double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
     constexpr int CPL = up0_cols<T>(), LPR = kW / CPL, GPB = kBlock / LPR;
@@ -244,7 +246,7 @@ static __global__ __launch_bounds__(kBlock) void kb_up0(int n, const int* __rest
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const T z = zv.v[q] + di * (r[e + q] - s[q]);
-            z_out[e + q] = (double)z;
+            z_out[e + q] = z;
             dot[q] += (double)z * dv[e + q];
         }
     }
@@ -435,8 +437,9 @@ static __global__ __launch_bounds__(kBlock) void kb_narrow(long long cnt, const 
 constexpr int kKrylovCols = 4;
 constexpr int kKrylovRowsPerBlock = kBlock / (kW / kKrylovCols);
 
+template <typename ZT>
 static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const double* __restrict__ av, const double* __restrict__ z,
+                                                       const double* __restrict__ av, const ZT* __restrict__ z,
                                                        const double* __restrict__ p_old, double* __restrict__ p_new,
                                                        double* __restrict__ q, const double* __restrict__ r,
                                                        const BatchState* __restrict__ st, double* __restrict__ partial,
@@ -461,14 +464,16 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
         double s[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) s[c] = 0.0;
-        row_accumulate<8, CPL, double, double>(rp[i], rp[i + 1], ci, av, z, col0, s);
+        row_accumulate<8, CPL, double, ZT>(rp[i], rp[i + 1], ci, av, z, col0, s);
         const size_t e = (size_t)i * kW + col0;
-        const Vec<double, CPL> zi = vload<double, CPL>(z + e), po = vload<double, CPL>(p_old + e);
+        const Vec<ZT, CPL> zi = vload<ZT, CPL>(z + e);
+        const Vec<double, CPL> po = vload<double, CPL>(p_old + e);
         const Vec<double, CPL> qo = vload<double, CPL>(q + e), ri = vload<double, CPL>(r + e);
         Vec<double, CPL> pn, qn;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            pn.v[c] = first[c] ? zi.v[c] : zi.v[c] + beta[c] * po.v[c];
+            const double zc = (double)zi.v[c];
+            pn.v[c] = first[c] ? zc : zc + beta[c] * po.v[c];
             qn.v[c] = fresh[c] ? s[c] : s[c] + beta[c] * qo.v[c];
             pq[c] += pn.v[c] * qn.v[c];
             pr[c] += pn.v[c] * ri.v[c];
@@ -760,13 +765,14 @@ static __global__ __launch_bounds__(kBlock) void kb_cols_in(int n, const int* __
     }
 }
 
+template <typename S>
 static __global__ __launch_bounds__(kBlock) void kb_cols_out(int n, const int* __restrict__ perm,
-                                                             const double* __restrict__ src, double* __restrict__ dst) {
+                                                             const S* __restrict__ src, double* __restrict__ dst) {
     const long long total = (long long)n * kW;
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += stride) {
         const int c = (int)(e / n), i = (int)(e % n);
-        dst[e] = src[(size_t)perm[i] * kW + c];
+        dst[e] = (double)src[(size_t)perm[i] * kW + c];
     }
 }
 
