@@ -377,7 +377,13 @@ typedef struct {
                                     they go to the batch engine (<= 0: 4) */
     int32_t setup_workers;       /* threads running host phases of new operators at once, each with
                                     an equal share of the host cores (<= 0: 1; at most 16) */
-    int32_t reserved[4];
+    int32_t device_setup;        /* 1 (default): a worker builds a new operator's large levels on
+                                    the device (pamg_params.device_setup), on a stream of its own
+                                    beside the solving, once the scheduler has reserved an upper
+                                    bound of its bytes (hierarchy and build temporaries) in the
+                                    budget; operators the device construction does not cover are
+                                    built on the host as with 0 */
+    int32_t reserved[3];
 } pamg_server_opts;
 
 typedef struct {

@@ -74,7 +74,7 @@ class pamg_hier_info(C.Structure):
 class pamg_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("block_iters", C.c_int32), ("precision", C.c_int32),
                 ("use_graph", C.c_int32), ("single_path", C.c_int32), ("batch_from", C.c_int32),
-                ("setup_workers", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("setup_workers", C.c_int32), ("device_setup", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class pamg_request(C.Structure):
@@ -469,7 +469,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, block_iters: int = 4, precision: int = PREC_F32,
                  use_graph: int = 0, single_path: int = 0, batch_from: int = 4, setup_workers: int = 1,
-                 context=None):
+                 device_setup: int = 1, context=None):
         o = pamg_server_opts()
         _check(lib().pamg_server_opts_default(C.byref(o)), "pamg_server_opts_default")
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -479,6 +479,7 @@ class Server:
         o.single_path = int(single_path)
         o.batch_from = int(batch_from)
         o.setup_workers = int(setup_workers)
+        o.device_setup = int(device_setup)
         h = C.c_void_p()
         self.context = context if context is not None else default_context()
         _check(lib().pamg_server_create(self.context._h, C.byref(o), C.byref(h)), "pamg_server_create")

@@ -3,11 +3,14 @@
 // Requests name an operator (a caller-chosen key plus its CSR, read only the
 // first time the key is seen) and carry a device right-hand side, a device
 // output vector and a tolerance.  A scheduler thread owns all GPU work:
-//   * setup off the critical path: the host phase of an operator's setup
-//     (matching, Galerkin products, layout) runs on a worker thread while the
-//     scheduler keeps iterating the cached operators;
-//   * admission: once its host phase is done, an operator is uploaded (with
-//     its 16-column batch engine) if its bytes fit the HBM budget, evicting
+//   * setup off the critical path: an operator's setup runs on a worker
+//     thread while the scheduler keeps iterating the cached operators: its
+//     large levels on the device, on the worker's own stream, once the
+//     scheduler has reserved room for it in the budget; otherwise (or for
+//     the configurations only the host builds) the host phase (matching,
+//     Galerkin products, layout), uploaded by the scheduler;
+//   * admission: an operator's hierarchy is admitted if its bytes fit the HBM
+//     budget, freeing idle operators' 16-column engines and then evicting
 //     idle cached operators in least-recently-used order; otherwise it waits;
 //   * batching: every cached operator is a group with its own stream and 16
 //     columns; a waiting request takes a free column between iteration blocks
@@ -33,6 +36,7 @@
 #include <thread>
 
 #include "batch.hpp"
+#include "dsetup.hpp"
 
 extern "C" int pamg_hierarchy_destroy(pamg_hierarchy* h);
 
@@ -46,14 +50,26 @@ struct ServeRequest {
     int restarts = 0;
 };
 
-// Host phase of one operator's setup, done by the worker thread.
+// One operator's setup, done by a worker thread: the host phase (built), or
+// the whole hierarchy built on the device (h, on the job's stream) after the
+// scheduler reserved `need` bytes for it.
 struct SetupJob {
     uint64_t key = 0;
     pamg_csr A{};                    // the caller's CSR (valid until its requests complete)
     std::unique_ptr<HostBuild> built;
+    pamg_hierarchy* h = nullptr;     // device-built (owned by the job until admitted)
+    hipStream_t stream = nullptr;    // the device build's stream (becomes the group's)
+    uint64_t need = 0;               // bytes to reserve before the device build
+    uint64_t reserved = 0;           // reserved in bytes_in_use (guarded by mu)
+    int room = 0;                    // guarded by mu: 1 reserved, -1 refused (over the budget)
+    double build_ms = 0.0;
     bool returned = false;           // handed back by the worker (scheduler-owned flag)
     int status = PAMG_OK;
     std::string error;
+    ~SetupJob() {
+        if (h) pamg_hierarchy_destroy(h);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 struct ServeGroup {
@@ -101,6 +117,7 @@ struct pamg_server {
     std::deque<pamg::SetupJob*> setup_queue;         // guarded by mu
     bool sched_done = false;                         // guarded by mu: scheduler thread has ended
     std::vector<pamg::SetupJob*> setup_done;         // guarded by mu
+    std::deque<pamg::SetupJob*> room_wait;           // guarded by mu: device builds waiting for room
     // scheduler-owned
     std::deque<pamg::ServeRequest*> pending;
     std::map<uint64_t, pamg::ServeGroup*> groups;
@@ -308,7 +325,43 @@ static void request_setup(pamg_server* S, ServeRequest* q) {
 
 // Upload operators whose host phase is done, as the budget allows (evicting
 // idle cached operators, least recently used first).
+// Give the device builds waiting for room their reservation, in order
+// (freeing idle engines and evicting idle operators as for an admission);
+// a build whose bound exceeds the whole budget is refused.
+static void grant_room(pamg_server* S) {
+    const uint64_t budget = S->opts.hbm_budget_bytes;
+    for (;;) {
+        SetupJob* j = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->room_wait.empty()) return;
+            j = S->room_wait.front();
+            if (j->need > budget) {
+                j->room = -1;
+                S->room_wait.pop_front();
+                S->setup_cv.notify_all();
+                continue;
+            }
+        }
+        if (!make_room(S, j->need, nullptr, true)) return;   // everything busy: next tick
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.bytes_in_use += j->need;
+        j->reserved = j->need;
+        j->room = 1;
+        S->room_wait.pop_front();
+        S->setup_cv.notify_all();
+        S->progressed = true;
+    }
+}
+
+static void release_reservation(pamg_server* S, SetupJob* j) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.bytes_in_use -= j->reserved;
+    j->reserved = 0;
+}
+
 static void admit_ready(pamg_server* S) {
+    grant_room(S);
     std::vector<SetupJob*> fin;
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -317,6 +370,7 @@ static void admit_ready(pamg_server* S) {
     for (SetupJob* j : fin) {
         j->returned = true;
         if (j->status != PAMG_OK) {
+            release_reservation(S, j);
             S->setups.erase(j->key);
             fail_key(S, j->key, j->status);
             delete j;
@@ -327,6 +381,38 @@ static void admit_ready(pamg_server* S) {
     for (auto it = S->setups.begin(); it != S->setups.end();) {
         SetupJob* j = it->second;
         if (!j->returned) { ++it; continue; }
+        if (j->h) {
+            // built on the device within its reservation: the exact bytes replace it
+            std::unique_ptr<ServeGroup> g(new ServeGroup());
+            g->key = j->key;
+            g->stream = j->stream;
+            j->stream = nullptr;
+            g->h = j->h;
+            j->h = nullptr;
+            HIP_CHECK(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
+            if (S->opts.single_path) HIP_CHECK(hipEventCreateWithFlags(&g->single_ev, hipEventDisableTiming));
+            const auto t0 = Clock::now();
+            if (S->opts.use_graph && S->opts.single_path) single_prepare_graph(g->h, prec, S->opts.block_iters);
+            g->bytes = g->h->info.device_bytes;
+            g->iter_bytes = batch_iteration_bytes(g->h, prec);
+            g->single_iter_bytes = single_iteration_bytes(g->h, prec);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->stats.bytes_in_use += g->bytes;
+                S->stats.bytes_in_use -= j->reserved;
+                S->stats.setups += 1;
+                S->stats.cached_operators += 1;
+                S->stats.device_setup_ms += j->build_ms + ms_between(t0, Clock::now());
+            }
+            j->reserved = 0;
+            ServeGroup* raw = g.release();
+            S->groups[raw->key] = raw;
+            it = S->setups.erase(it);
+            delete j;
+            S->progressed = true;
+            continue;
+        }
+        if (j->reserved) release_reservation(S, j);   // the device construction did not apply
         const uint64_t need = bound_bytes(*j, prec);
         if (need > budget) {
             it = S->setups.erase(it);
@@ -371,8 +457,27 @@ static void admit_ready(pamg_server* S) {
     }
 }
 
+// Bytes a device build of A may hold at once: the hierarchy estimate plus
+// the canonical levels and per-level scratch of the construction (about 40
+// bytes per stored entry and 128 per row of the input, with the coarse
+// levels' share).
+static uint64_t device_build_bound(const pamg_csr& A, int prec) {
+    return hierarchy_estimate(A, prec) + 40ull * (uint64_t)A.nnz + 128ull * (uint64_t)A.n + (1ull << 20);
+}
+
+// Ask the scheduler for `need` bytes of the budget; false if refused (more
+// than the budget) or if the server ended.
+static bool wait_for_room(pamg_server* S, SetupJob* j) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->room_wait.push_back(j);
+    S->cv.notify_one();
+    S->setup_cv.wait(lk, [&] { return j->room != 0 || S->sched_done; });
+    return j->room > 0;
+}
+
 static void setup_main(pamg_server* S, int threads) {
     set_num_threads(threads);        // this worker's share of the host cores
+    (void)hipSetDevice(S->device);
     for (;;) {
         SetupJob* j = nullptr;
         {
@@ -387,8 +492,26 @@ static void setup_main(pamg_server* S, int threads) {
         pamg_params prm;
         pamg_params_default(&prm);
         prm.build_f32 = S->opts.precision == PAMG_PREC_F32 ? 1 : 0;
+        prm.num_threads = threads;
+        prm.device_setup = S->opts.device_setup ? 1 : 0;
         try {
-            j->built = host_build(j->A, prm);
+            if (device_setup_applies(prm) && j->A.n > std::max({kDeviceMinRows, prm.max_dense, prm.max_coarse})) {
+                validate_csr(j->A, false);
+                j->need = device_build_bound(j->A, S->opts.precision);
+                // refused (the build's bound exceeds the whole budget): the
+                // host construction, whose admission needs only the hierarchy
+                if (wait_for_room(S, j)) {
+                    HIP_CHECK(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
+                    const auto t0 = Clock::now();
+                    j->h = device_setup_build(j->A, prm, j->stream, S->ctx, true);
+                    j->build_ms = ms_between(t0, Clock::now());
+                    if (!j->h) {
+                        (void)hipStreamDestroy(j->stream);
+                        j->stream = nullptr;
+                    }
+                }
+            }
+            if (!j->h) j->built = host_build(j->A, prm);
         } catch (const Error& e) {
             j->status = e.code;
             j->error = e.what();
@@ -636,7 +759,8 @@ static void scheduler_main(pamg_server* S) {
                 bool waiting_only = true;
                 for (ServeRequest* q : S->pending)
                     if (!S->setups.count(q->r.op_key)) waiting_only = false;
-                if (!busy && waiting_only && S->incoming.empty() && S->setup_done.empty() && !S->stop)
+                if (!busy && waiting_only && S->incoming.empty() && S->setup_done.empty() && S->room_wait.empty() &&
+                    !S->stop)
                     S->cv.wait_for(lk, std::chrono::milliseconds(2));
                 if (S->stop && S->incoming.empty() && S->pending.empty() && !busy) return;
                 while (!S->incoming.empty()) {
@@ -672,6 +796,7 @@ int pamg_server_opts_default(pamg_server_opts* o) {
     o->hbm_budget_bytes = 64ull << 30;
     o->block_iters = 4;
     o->precision = PAMG_PREC_F32;
+    o->device_setup = 1;
     return PAMG_OK;
 }
 

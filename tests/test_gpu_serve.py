@@ -14,7 +14,10 @@
   and a request alone takes the single path;
 * the host phase of a new operator's setup runs beside the solving of
   cached operators (their requests finish first), and several setup workers
-  give bitwise the results of one.
+  give bitwise the results of one;
+* operators large enough for the device construction are built on the
+  device by the setup workers, within a reservation of the budget, and give
+  bitwise the results of host-built ones.
 """
 import time
 
@@ -311,4 +314,28 @@ def test_engines_are_built_on_demand_and_freed_before_evictions(ops):
         assert done[tag].status == pamg.OK
         x = xs[tag][0].cpu().numpy()
         rel = np.linalg.norm(b - ops[k].to_scipy() @ x) / np.linalg.norm(b)
+        assert rel <= 1e-6
+
+
+def test_device_built_operators_serve_like_host_built_ones(ops):
+    # two operators above the device construction's size floor among the
+    # small ones: workers build them on the device (beside the solving, in
+    # a reserved share of the budget); every result is bitwise the
+    # host-built server's (batch engine only: results independent of the mix)
+    from workloads import q1_stretched
+    big = dict(ops)
+    big[4] = varcoef7(44, seed=51)
+    big[5] = q1_stretched(42, 1.05)
+    reqs = make_requests(big, 30, seed=17)
+    reqs += [(100 + t, k, SplitMix64(700 + t).uniform(big[k].n)) for t, k in enumerate([4, 5, 4, 5])]
+    xd, dd, sd = serve(big, reqs, setup_workers=2, device_setup=1)
+    xh, dh, sh = serve(big, reqs, setup_workers=2, device_setup=0)
+    assert sd.completed == sh.completed == len(reqs) and sd.rejected == 0
+    assert sd.setups == sh.setups == len(big)
+    assert sd.device_setup_ms > 0
+    for tag, k, b in reqs:
+        assert dd[tag].status == dh[tag].status == pamg.OK
+        assert dd[tag].iterations == dh[tag].iterations
+        assert np.array_equal(xd[tag], xh[tag]), tag
+        rel = np.linalg.norm(b - big[k].to_scipy() @ xd[tag]) / np.linalg.norm(b)
         assert rel <= 1e-6
