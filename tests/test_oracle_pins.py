@@ -931,3 +931,79 @@ def test_true_residual_restart_is_a_warm_restart_from_b_minus_ax():
     # without the request the branch is never taken
     x3, it3, _, _ = H.solve(b, tol, true_res=False)
     assert it3 == it1 and np.array_equal(x3, x1)
+
+
+def _rounds_matching(A, w):
+    """Locally dominant rounds, as the device setup runs them: every vertex's
+    eligible neighbours sorted heaviest first (equal weights: smaller index
+    first, which for a fixed vertex is the (lo, hi) order); each round an
+    unmatched vertex with neighbours left points at its first unmatched one
+    (a cursor that only moves forward), mutual pointers are matched, a vertex
+    with none left stays single.  Returns mate[] and the number of rounds."""
+    n = A.shape[0]
+    D = A.diagonal()
+    Au = sp.triu(A, 1).tocsr()
+    nbrs = [[] for _ in range(n)]
+    for i in range(n):
+        for k in range(Au.indptr[i], Au.indptr[i + 1]):
+            j = int(Au.indices[k])
+            c = _weights_eq(Au.data[k], D[i], D[j], w[i], w[j])   # the edge's upper entry, both directions
+            if c > 1.0:
+                nbrs[i].append((-c, j))
+                nbrs[j].append((-c, i))
+    for L in nbrs:
+        L.sort()
+    mate = [-1] * n
+    state = [0] * n                 # 0 alive, 1 matched, 2 single
+    cur = [0] * n
+    rounds = 0
+    while any(s == 0 for s in state):
+        rounds += 1
+        cand = [-1] * n
+        for i in range(n):
+            if state[i] != 0:
+                continue
+            while cur[i] < len(nbrs[i]) and mate[nbrs[i][cur[i]][1]] >= 0:
+                cur[i] += 1
+            if cur[i] < len(nbrs[i]):
+                cand[i] = nbrs[i][cur[i]][1]
+            else:
+                state[i] = 2
+        progress = False
+        for i in range(n):
+            if state[i] == 0 and cand[cand[i]] == i:
+                mate[i], state[i], progress = cand[i], 1, True
+        assert progress or not any(s == 0 for s in state), "a round with alive vertices matched nothing"
+    return np.array(mate), rounds
+
+
+def _pairs_of(agg):
+    order = np.argsort(agg, kind="stable")
+    sa = agg[order]
+    starts = np.flatnonzero(np.r_[True, sa[1:] != sa[:-1]])
+    sizes = np.diff(np.r_[starts, len(sa)])
+    return {(int(order[s]), int(order[s + 1])) for s, z in zip(starts, sizes) if z == 2}
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("discrete", [False, True])
+def test_locally_dominant_rounds_give_the_greedy_matching(seed, discrete):
+    # the device setup's matching (parallel rounds) against the oracle's greedy
+    # matching, with many exact weight ties in the discrete case
+    A = _random_spd(80, 0.1, 100 + seed, discrete=discrete)
+    H = oracle.Hierarchy(csr_from_scipy(A), max_coarse=1, max_levels=2)
+    mate, rounds = _rounds_matching(A, np.ones(A.shape[0]))
+    got = {(i, int(m)) for i, m in enumerate(mate) if m > i}
+    assert got == _pairs_of(H.agg(0))
+    assert rounds >= 2
+
+
+@pytest.mark.parametrize("case", ["varcoef_10", "q1_6"])
+def test_locally_dominant_rounds_on_every_level(case):
+    # coarse levels (non-uniform w): the rounds give the oracle's pairs on each
+    A = {"varcoef_10": lambda: varcoef7(10, seed=8), "q1_6": lambda: q1_stretched(6, 1.05)}[case]()
+    H = oracle.Hierarchy(A, max_coarse=10)
+    for l in range(H.nlevels - 1):
+        mate, _ = _rounds_matching(H.level_scipy(l), H.w(l))
+        got = {(i, int(m)) for i, m in enumerate(mate) if m > i}
+        assert got == _pairs_of(H.agg(l)), f"level {l}"
