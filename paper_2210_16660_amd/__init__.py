@@ -148,6 +148,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run `python paper_2210_16660_amd/build.py`")
+        # PyTorch first: the library then binds to the HIP runtime PyTorch
+        # loaded (one runtime per process, so that device pointers, streams
+        # and the caching allocator are shared)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
