@@ -645,7 +645,7 @@ def bench_setup(args, A, torch, pamg, log) -> int:
     def build(dev_setup):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H = pamg.Hierarchy(A, build_f32=1, device_setup=dev_setup)
+        H = pamg.Hierarchy(A, build_f32=1, device_setup=dev_setup, agg_steps=args.agg_steps)
         torch.cuda.synchronize()
         return H, time.perf_counter() - t0
 
@@ -665,8 +665,10 @@ def bench_setup(args, A, torch, pamg, log) -> int:
     for l in probe:
         same = same and np.array_equal(H.aggregates(l), Hh.aggregates(l))
     out = {"metric": "hierarchy setup time (s)", "value": round(min(runs), 3), "unit": "s", "higher_is_better": False,
-           "config": {"workload": f"Q1 {args.n}^3 stretched (ratio {args.ratio}), pairwise aggregation, FP64 + FP32 "
-                                  "hierarchy copies", "n": A.n, "nnz": A.nnz, "levels": i.levels},
+           "config": {"workload": f"Q1 {args.n}^3 stretched (ratio {args.ratio}), "
+                                  + ("pairwise aggregation" if args.agg_steps == 1 else
+                                     f"aggregates of up to {2 ** args.agg_steps} (composed pairwise)")
+                                  + ", FP64 + FP32 hierarchy copies", "n": A.n, "nnz": A.nnz, "levels": i.levels},
            "device_setup_s": [round(t, 3) for t in runs], "device_levels": i.device_levels,
            "host_setup_s": round(th, 3), "speedup_vs_host": round(th / min(runs), 2),
            "same_hierarchy_sampled": bool(same)}

@@ -107,6 +107,9 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 void validate_csr(const pamg_csr& A, bool check_symmetry);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
 void extend_hierarchy(HostHierarchy& H, const pamg_params& prm);
+// Keep levels 0, s, 2s, ... and the last of a pairwise hierarchy, composing
+// aggregates and prolongators in between (the pairwise chain kept in H.chain).
+void compose_levels(HostHierarchy& H, int s);
 std::vector<LayoutLevel> build_layout(const HostHierarchy& H);
 int first_tile_items(int64_t nnz);
 void make_tiles(const std::vector<int32_t>& rp, const std::vector<int32_t>& aggptr, int32_t n, int32_t nc,

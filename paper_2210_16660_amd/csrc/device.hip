@@ -170,7 +170,7 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
         I.perm = D.perm;
         I.iperm = D.iperm;
         I.aggptr = D.aggptr;
-        I.max_agg = D.pairs > 0 ? 2 : 1;
+        I.max_agg = D.max_agg;
         I.up_tiles = reinterpret_cast<const int4*>(D.up_tiles);
         I.n_up = D.n_up;
         I.down_tiles = reinterpret_cast<const int4*>(D.down_tiles);
@@ -1287,6 +1287,7 @@ pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hi
         }
         for (HostLevel& hl : db->host.lev) h->host.lev.push_back(std::move(hl));
         h->lazy_levels = m;
+        h->prm = prm;
         const int nl = m + (int)db->host_lay.size();
         for (int l = 0; l < nl && l < PAMG_MAX_LEVELS; ++l)
             h->info.tile_items[l] = l < m ? db->dev[l].items : db->host_lay[l - m].items;
@@ -1309,7 +1310,12 @@ void ensure_host_levels(pamg_hierarchy* h) {
         out.resize(count);
         if (count) HIP_CHECK(hipMemcpy(out.data(), d, count * sizeof(out[0]), hipMemcpyDeviceToHost));
     };
-    for (int l = 0; l < h->lazy_levels; ++l) {
+    // with composed aggregates the pairwise chain between kept levels exists
+    // only during the build: rebuild the whole host hierarchy (bitwise the
+    // same) from the canonical level-0 matrix
+    const bool composed = h->prm.agg_steps > 1;
+    const int upto = composed ? 1 : h->lazy_levels;
+    for (int l = 0; l < upto; ++l) {
         const DevLevelIdx& I = h->idx[l];
         const int n = I.n, nc = I.nc;
         std::vector<int32_t> rp, ci, perm, iperm, aggptr, ciperm;
@@ -1351,6 +1357,12 @@ void ensure_host_levels(pamg_hierarchy* h) {
         });
         for (int32_t Ip = 0; Ip < nc; ++Ip)
             for (int32_t ip = aggptr[Ip]; ip < aggptr[Ip + 1]; ++ip) H.agg[iperm[ip]] = ciperm[Ip];
+    }
+    if (composed) {
+        const HostCSR& A0 = h->host.lev[0].A;
+        const pamg_csr c{A0.n, A0.nnz(), A0.rp.data(), A0.ci.data(), A0.v.data()};
+        HostHierarchy full = build_hierarchy(c, h->prm);
+        h->host = std::move(full);
     }
     h->lazy_levels = 0;
 }

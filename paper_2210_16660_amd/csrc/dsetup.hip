@@ -11,6 +11,9 @@
 //     eq. (prolongator);
 //   * the Galerkin product with every coarse entry summed in the canonical
 //     order (ascending (min(i,j), max(i,j), i)), one wavefront per coarse row;
+//   * with aggregate-size composition (agg_steps = s > 1), every s-th
+//     pairwise level kept, its aggregates and prolongator entries composed
+//     over the s pairwise steps (p multiplied finest first);
 //   * the hierarchical numbering, the permuted rows (columns ascending), the
 //     column-scaled values and the tiles' column dictionaries.
 // A level is built here while it is large (more rows than the dense limit,
@@ -591,6 +594,60 @@ __global__ void k_spans(int ntiles, const long long* doff, const int* dlen, int*
     }
 }
 
+// ------------------------------------------------------ aggregate composition
+
+// The pairwise levels composed into one kept level (at most kMaxAggSteps).
+struct Chain {
+    const int* agg[kMaxAggSteps];
+    const double* p[kMaxAggSteps];
+    int steps;
+};
+
+// Composed aggregate and prolongator entry of every row of a kept level: the
+// row's aggregate followed through the chain, p multiplied finest first.
+__global__ void k_compose(int n, Chain c, int* cagg, double* cp) {
+    GRID_STRIDE(i, n) {
+        int I = c.agg[0][i];
+        double pc = c.p[0][i];
+        for (int m = 1; m < c.steps; ++m) {
+            pc = pc * c.p[m][I];
+            I = c.agg[m][I];
+        }
+        cagg[i] = I;
+        cp[i] = pc;
+    }
+}
+
+__global__ void k_count_members(int n, const int* cagg, int* cnt) { GRID_STRIDE(i, n) atomicAdd(&cnt[cagg[i]], 1); }
+
+__global__ void k_fill_members(int n, const int* cagg, const long long* mptr, int* fill, int* mem) {
+    GRID_STRIDE(i, n) {
+        const int I = cagg[i];
+        mem[mptr[I] + atomicAdd(&fill[I], 1)] = (int)i;
+    }
+}
+
+// Members of each composed aggregate ascending (at most 2^kMaxAggSteps).
+__global__ void k_sort_members(int nc, const long long* mptr, int* mem, int* mem_ptr, int* longest) {
+    int mx = 0;
+    GRID_STRIDE(I, nc) {
+        const int b = (int)mptr[I], e = (int)mptr[I + 1];
+        for (int q = b + 1; q < e; ++q) {
+            const int x = mem[q];
+            int u = q;
+            while (u > b && mem[u - 1] > x) {
+                mem[u] = mem[u - 1];
+                --u;
+            }
+            mem[u] = x;
+        }
+        mem_ptr[I] = b;
+        if (I == nc - 1) mem_ptr[nc] = e;
+        mx = max(mx, e - b);
+    }
+    atomicMax(longest, mx);
+}
+
 // ------------------------------------------------------------------ driver
 
 // A level in canonical numbering, as the device loop leaves it.
@@ -599,7 +656,7 @@ struct CanLevel {
     long long nnz = 0;
     int *rp = nullptr, *ci = nullptr;
     double *v = nullptr, *w = nullptr, *dinv = nullptr, *p = nullptr;
-    int *mem_ptr = nullptr, *mem = nullptr;
+    int *agg = nullptr, *mem_ptr = nullptr, *mem = nullptr;
 };
 
 int grid_rows(long long n) { return (int)std::min<long long>(std::max<long long>(n, 1), kGridCap); }
@@ -682,6 +739,7 @@ Coarsened coarsen(Temps& T, CanLevel& L, CanLevel& C, hipStream_t s) {
         return kNoPairs;
     }
     int* agg = T.get<int>(n);
+    L.agg = agg;
     L.p = T.get<double>(n);
     C.w = T.get<double>(nc);
     L.mem_ptr = T.get<int>(nc + 1);
@@ -718,7 +776,6 @@ Coarsened coarsen(Temps& T, CanLevel& L, CanLevel& C, hipStream_t s) {
     C.maxrow = head[1];
     T.release(ccnt);
     T.release(crp);
-    T.release(agg);
     return kCoarsened;
 }
 
@@ -734,7 +791,7 @@ void download_level(const CanLevel& L, HostLevel& out, hipStream_t s) {
 }  // namespace
 
 bool device_setup_applies(const pamg_params& prm) {
-    return prm.device_setup != 0 && prm.host_only == 0 && prm.agg_steps == 1 && prm.smooth_prolongator == 0 &&
+    return prm.device_setup != 0 && prm.host_only == 0 && prm.agg_steps >= 1 && prm.smooth_prolongator == 0 &&
            prm.smoother == PAMG_SMOOTHER_L1_JACOBI && prm.match_all_edges == 0;
 }
 
@@ -766,19 +823,23 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
         L0.maxrow = mx;
     }
     if (!dev_level(lev[0], 0)) return nullptr;
-    // device levels
-    int m = 0;
+    // device (pairwise) levels
+    const int steps = std::max(1, prm.agg_steps);
+    int built = 0;
     for (;;) {
-        CanLevel& L = lev[m];
+        CanLevel& L = lev[built];
         L.dinv = T.get<double>(L.n);
         CanLevel C;
         const Coarsened r = coarsen(T, L, C, s);
         if (r == kAsymmetric) return nullptr;
         if (r == kNoPairs) break;          // the host takes this level
         lev.push_back(C);
-        ++m;
-        if (!dev_level(lev[m], m)) break;
+        ++built;
+        if (!dev_level(lev[built], built)) break;
     }
+    // the host continues from a kept level (a multiple of the composition
+    // step), so that every composed prolongator lies on one side
+    const int m = built / steps * steps;
     if (m == 0) return nullptr;
     // host levels from level m
     {
@@ -792,11 +853,58 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
         if (AL.n > prm.max_dense)
             throw Error(PAMG_E_STALLED, "coarsening stalled at " + std::to_string(AL.n) +
                                             " unknowns, above the dense-solve limit");
+        if (steps > 1) compose_levels(Hs, steps);
         out->host_lay = build_layout(Hs);
     }
-    out->m = m;
-    // device layouts of levels m-1 .. 0 (their arrays belong to the hierarchy)
-    out->dev.resize(m);
+    // kept device levels: every steps-th pairwise level below m, with its
+    // aggregates and prolongator composed over the steps in between
+    const int K = m / steps;
+    out->m = K;
+    std::vector<int> kp(K), knc(K);
+    std::vector<double*> kcp(K);
+    std::vector<int*> kmptr(K), kmem(K);
+    for (int j = 0; j < K; ++j) {
+        const int a = j * steps;
+        const CanLevel& L = lev[a];
+        kp[j] = a;
+        knc[j] = lev[a + steps].n;
+        if (steps == 1) {
+            kcp[j] = L.p;
+            kmptr[j] = L.mem_ptr;
+            kmem[j] = L.mem;
+            continue;
+        }
+        Chain ch{};
+        ch.steps = steps;
+        for (int q = 0; q < steps; ++q) {
+            ch.agg[q] = lev[a + q].agg;
+            ch.p[q] = lev[a + q].p;
+        }
+        const int n = L.n, nc = knc[j];
+        int* cagg = T.get<int>(n);
+        kcp[j] = T.get<double>(n);
+        hipLaunchKernelGGL(k_compose, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, ch, cagg, kcp[j]);
+        int* cnt = T.get<int>(nc);
+        HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int) * nc, s));
+        hipLaunchKernelGGL(k_count_members, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)cagg, cnt);
+        long long* mptr = T.get<long long>((size_t)nc + 1);
+        scan<int>(T, nc, cnt, mptr, s);
+        HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int) * nc, s));
+        kmem[j] = T.get<int>(n);
+        kmptr[j] = T.get<int>((size_t)nc + 1);
+        hipLaunchKernelGGL(k_fill_members, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, (const int*)cagg,
+                           (const long long*)mptr, cnt, kmem[j]);
+        int* longest = T.get<int>(1);
+        HIP_CHECK(hipMemsetAsync(longest, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_sort_members, dim3(grid_for(nc, kSB)), dim3(kSB), 0, s, nc, (const long long*)mptr,
+                           kmem[j], kmptr[j], longest);
+        if (read1(longest, s) > (1 << kMaxAggSteps)) throw Error(PAMG_E_DEVICE, "composed aggregate too large");
+        T.release(cnt);
+        T.release(mptr);
+        T.release(cagg);
+    }
+    // device layouts of the kept levels K-1 .. 0 (their arrays belong to the hierarchy)
+    out->dev.resize(K);
     const int* cip = nullptr;   // hierarchical -> canonical of the coarser level
     std::vector<int> cip_host;
     int* cip_dev = nullptr;
@@ -804,23 +912,25 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
     cip_dev = T.get<int>(cip_host.size());
     to_device(cip_dev, cip_host.data(), cip_host.size(), s);
     cip = cip_dev;
-    for (int l = m - 1; l >= 0; --l) {
-        const CanLevel& L = lev[l];
-        DevLevelOut& D = out->dev[l];
-        const int n = L.n, nc = L.nc;
+    for (int j = K - 1; j >= 0; --j) {
+        const CanLevel& L = lev[kp[j]];
+        DevLevelOut& D = out->dev[j];
+        const int n = L.n, nc = knc[j];
+        const int* mem_ptr = kmptr[j];
+        const int* mem = kmem[j];
         D.n = n;
         D.nc = nc;
         D.nnz = L.nnz;
         D.pairs = L.pairs;
         int* sz = T.get<int>(nc);
         long long* ap = T.get<long long>((size_t)nc + 1);
-        hipLaunchKernelGGL(k_agg_sizes, dim3(grid_for(nc, kSB)), dim3(kSB), 0, s, nc, cip, (const int*)L.mem_ptr, sz);
+        hipLaunchKernelGGL(k_agg_sizes, dim3(grid_for(nc, kSB)), dim3(kSB), 0, s, nc, cip, mem_ptr, sz);
         scan<int>(T, nc, sz, ap, s);
         D.aggptr = dalloc<int>(h, (size_t)nc + 1, s);
         D.iperm = dalloc<int>(h, n, s);
         D.perm = dalloc<int>(h, n, s);
-        hipLaunchKernelGGL(k_place, dim3(grid_for(nc, kSB)), dim3(kSB), 0, s, nc, n, cip, (const int*)L.mem_ptr,
-                           (const int*)L.mem, (const long long*)ap, D.aggptr, D.iperm, D.perm);
+        hipLaunchKernelGGL(k_place, dim3(grid_for(nc, kSB)), dim3(kSB), 0, s, nc, n, cip, mem_ptr, mem,
+                           (const long long*)ap, D.aggptr, D.iperm, D.perm);
         T.release(sz);
         T.release(ap);
         int* len = T.get<int>(n);
@@ -836,7 +946,8 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
         D.p = dalloc<double>(h, n, s);
         hipLaunchKernelGGL(k_reorder, dim3(grid_rows(n)), dim3(64), 0, s, n, (const int*)D.iperm,
                            (const int*)D.perm, (const int*)L.rp, (const int*)L.ci, (const double*)L.v,
-                           (const double*)L.dinv, (const double*)L.p, (const long long*)rp2, D.ci, D.v, D.dinv, D.p);
+                           (const double*)L.dinv, (const double*)kcp[j], (const long long*)rp2, D.ci, D.v, D.dinv,
+                           D.p);
         hipLaunchKernelGGL(k_to_int, dim3(grid_for(n + 1, kSB)), dim3(kSB), 0, s, (long long)n + 1,
                            (const long long*)rp2, D.rp);
         T.release(rp2);
@@ -847,6 +958,7 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
         std::vector<int32_t> rp_h, ap_h;
         to_host(rp_h, D.rp, (size_t)n + 1, s);
         to_host(ap_h, D.aggptr, (size_t)nc + 1, s);
+        for (int32_t c = 0; c < nc; ++c) D.max_agg = std::max(D.max_agg, ap_h[c + 1] - ap_h[c]);
         int items = first_tile_items(L.nnz);
         std::vector<int32_t> up, down;
         int* dl_up = nullptr;

@@ -21,7 +21,7 @@ struct DevDict {
 // One device-built level in hierarchical numbering (LayoutLevel on the
 // device); its arrays belong to the hierarchy's allocation list.
 struct DevLevelOut {
-    int n = 0, nc = 0, pairs = 0, items = 8, n_up = 0, n_down = 0;
+    int n = 0, nc = 0, pairs = 0, items = 8, n_up = 0, n_down = 0, max_agg = 0;
     long long nnz = 0;
     int *rp = nullptr, *ci = nullptr, *perm = nullptr, *iperm = nullptr, *aggptr = nullptr;
     int *up_tiles = nullptr, *down_tiles = nullptr;
@@ -30,14 +30,15 @@ struct DevLevelOut {
 };
 
 struct DeviceBuild {
-    int m = 0;                          // levels 0..m-1 built on the device
+    int m = 0;                          // (kept) levels 0..m-1 built on the device
     std::vector<DevLevelOut> dev;
     HostHierarchy host;                 // levels m..L, built on the host from level m
     std::vector<LayoutLevel> host_lay;  // their layouts
 };
 
-// The configurations the device construction covers: pairwise aggregates,
-// tentative prolongators, the l1-Jacobi smoother, weight-eligible edges.
+// The configurations the device construction covers: pairwise aggregates
+// or their composition, tentative prolongators, the l1-Jacobi smoother,
+// weight-eligible edges.
 bool device_setup_applies(const pamg_params& prm);
 
 // Build the hierarchy of A (validated host CSR) with its large levels on the

@@ -130,6 +130,7 @@ struct pamg_hierarchy {
     std::vector<pamg::DevAlloc> allocs;
     pamg::HostHierarchy host;
     int lazy_levels = 0;                      // finest levels built on the device: host copies made on first use
+    pamg_params prm{};                        // the setup's parameters (device-built hierarchies)
     std::mutex host_mu;
     pamg_hier_info info{};
     std::mutex mu;

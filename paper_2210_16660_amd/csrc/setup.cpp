@@ -442,7 +442,7 @@ static void galerkin_smoothed(const HostCSR& A, const HostCSR& P, int32_t nc, Ho
 // Keep levels 0, s, 2s, ... and the coarsest of the pairwise hierarchy; the
 // prolongator between kept levels is the product of the pairwise ones in
 // between (Sec. 3.1): agg follows the chain, p is multiplied finest first.
-static void compose_levels(HostHierarchy& H, int s) {
+void compose_levels(HostHierarchy& H, int s) {
     const int L = (int)H.lev.size() - 1;
     std::vector<int> kept;
     for (int l = 0; l < L; l += s) kept.push_back(l);

@@ -11,6 +11,8 @@ the C ABI.
   order, tiles, dictionaries) is equivalent;
 * coefficient-only updates work on a device-built hierarchy and give the
   host-built hierarchy's results;
+* with aggregate-size composition (agg_steps 2 and 3) the kept levels'
+  composed aggregates, matrices and solves are the oracle's / host's too;
 * configurations the device construction does not cover (small inputs, an
   unsymmetric pattern, the hybrid Gauss-Seidel smoother) are built on the
   host, with identical results.
@@ -46,6 +48,12 @@ CASES = {
                            {"max_dense": 512}, 2),
     "lap7_30_small_coarse": (lambda: lap7(30), {"device_min_rows": 64, "max_dense": 64, "max_coarse": 20},
                              {"max_dense": 64, "max_coarse": 20}, 6),
+    "q1_40_composed2": (lambda: q1_stretched(40, 1.05), {"device_min_rows": 1000, "agg_steps": 2},
+                        {"agg_steps": 2}, 2),
+    "varcoef_48_composed3": (lambda: varcoef7(48, seed=21), {"device_min_rows": 1000, "agg_steps": 3},
+                             {"agg_steps": 3}, 1),
+    "q1_32_deep_composed2": (lambda: q1_stretched(32, 1.05), {"device_min_rows": 64, "max_dense": 256,
+                                                             "agg_steps": 2}, {"max_dense": 256, "agg_steps": 2}, 3),
 }
 
 
@@ -68,7 +76,8 @@ def test_device_setup_bitexact_with_oracle(case):
     info = H.info()
     print(case, "device levels", info.device_levels, "of", info.levels, flush=True)
     assert info.device_levels >= least
-    O = oracle.Hierarchy(A, max_coarse=okw.get("max_coarse", 200), max_dense=okw.get("max_dense", 8192))
+    O = oracle.Hierarchy(A, max_coarse=okw.get("max_coarse", 200), max_dense=okw.get("max_dense", 8192),
+                         agg_steps=okw.get("agg_steps", 1))
     check_against_oracle(H, O)
 
 
@@ -93,7 +102,7 @@ def test_device_setup_matches_the_oracle_digest_at_128():
             assert digest(H.aggregates(l), np.int32) == r["agg"], f"level {l} aggregates"
 
 
-@pytest.mark.parametrize("case", ["q1_40", "varcoef_48", "q1_32_deep"])
+@pytest.mark.parametrize("case", ["q1_40", "varcoef_48", "q1_32_deep", "q1_40_composed2", "varcoef_48_composed3"])
 def test_device_built_hierarchy_solves_like_the_host_built_one(case):
     make, kw, _, _ = CASES[case]
     A = make()
@@ -112,12 +121,13 @@ def test_device_built_hierarchy_solves_like_the_host_built_one(case):
             assert torch.equal(xd, xh), (prec, kwargs)
 
 
-def test_coefficient_update_on_a_device_built_hierarchy():
+@pytest.mark.parametrize("steps", [1, 2])
+def test_coefficient_update_on_a_device_built_hierarchy(steps):
     A = varcoef7(40, seed=31)
     B = varcoef7(40, seed=32)          # same pattern, new coefficients
-    Hd = pamg.Hierarchy(A, device_setup=1, device_min_rows=1000)
-    Hh = pamg.Hierarchy(A, device_setup=0)
-    assert Hd.info().device_levels >= 2
+    Hd = pamg.Hierarchy(A, device_setup=1, device_min_rows=1000, agg_steps=steps)
+    Hh = pamg.Hierarchy(A, device_setup=0, agg_steps=steps)
+    assert Hd.info().device_levels >= 1
     Hd.update_values(B.val)
     Hh.update_values(B.val)
     for l in range(Hh.levels):
@@ -146,7 +156,7 @@ def test_configurations_left_to_the_host():
         (lap7(20), {}),                                     # below the size floor
         (drop_upper_entry(lap7(40), 1234), {"device_min_rows": 1000}),   # unsymmetric pattern
         (lap7(40), {"device_min_rows": 1000, "smoother": "hgs"}),
-        (lap7(40), {"device_min_rows": 1000, "agg_steps": 2}),
+        (lap7(40), {"device_min_rows": 1000, "agg_steps": 2, "smooth_prolongator": 1}),
     ]
     for A, kw in cases:
         Hd = pamg.Hierarchy(A, device_setup=1, **kw)
