@@ -134,9 +134,11 @@ typedef struct {
                                  tentative prolongator is smoothed (the paper's configuration);
                                  with pairwise aggregates the coarse matrices fill in quickly.
                                  Default 0. */
-    int32_t device_setup;     /* 1: build the large levels on the device (pairwise aggregates,
-                                 tentative prolongators, l1-Jacobi, weight-eligible edges; other
-                                 configurations and small inputs are built on the host).  The
+    int32_t device_setup;     /* 1: build the large levels on the device (pairwise aggregates or
+                                 their composition, tentative prolongators, l1-Jacobi,
+                                 weight-eligible edges; smoothed prolongators, the Gauss-Seidel
+                                 smoother, match_all_edges, inputs whose pattern is not
+                                 symmetric and small inputs are built on the host).  The
                                  hierarchy is bitwise the host-built one: the matching is the
                                  greedy matching under the same strict order, computed as
                                  locally dominant edges in parallel rounds (Sec. 3.1, eq.
