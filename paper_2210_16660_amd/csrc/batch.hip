@@ -136,20 +136,17 @@ static void launch_up_b(const DevLevelIdx& I, const DevLevelIdx& F, int v, const
 // E->Z, or E->Z32 with the FP32 cycle on a hierarchy of several levels (the
 // cycle's last step computes it in FP32).
 // The level-0 right-hand side as the V-cycle reads it: with the FP32 cycle,
-// R rounded to FP32 once (the kernels would round each load the same way),
-// so that its gathers move 64-byte lines instead of 128-byte ones.
+// R rounded to FP32 (the kernels would round each load the same way), so
+// that its gathers move 64-byte lines instead of 128-byte ones; every kernel
+// that writes R (load, update, true-residual restart) writes R32 beside it.
 template <typename T>
 static const void* level0_rhs(BatchEngine* E, const int* done, hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value) {
-        const long long cnt = (long long)E->h->idx[0].n * kW;
-        hipLaunchKernelGGL(kb_narrow, dim3(vec_grid(cnt)), dim3(kBlock), 0, s, cnt, (const double*)E->R, E->R32,
-                           done);
+    (void)done;
+    (void)s;
+    if constexpr (std::is_same<T, float>::value)
         return E->R32;
-    } else {
-        (void)done;
-        (void)s;
+    else
         return E->R;
-    }
 }
 
 template <typename T>
@@ -236,8 +233,9 @@ static void enqueue_iteration_b(BatchEngine* E, DevVals<T>& V, int krylov, int p
                            (const BatchState*)E->st, E->partial, done);
     hipLaunchKernelGGL(kb_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, gk);
     const int g = unit_grid(I0.n, kBlock / kW);
-    hipLaunchKernelGGL(kb_update, dim3(g), dim3(kBlock), 0, s, I0.n, E->X, E->R, (const double*)E->P[1 - parity],
-                       (const double*)E->Q, (const BatchState*)E->st, E->partial, done);
+    hipLaunchKernelGGL(kb_update, dim3(g), dim3(kBlock), 0, s, I0.n, E->X, E->R, E->R32,
+                       (const double*)E->P[1 - parity], (const double*)E->Q, (const BatchState*)E->st, E->partial,
+                       done);
     hipLaunchKernelGGL(kb_fin_norm, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial, g);
 }
 
@@ -467,7 +465,7 @@ void batch_load(BatchEngine* E, const double* const* src, const double* tol, con
     HIP_CHECK(hipMemcpyAsync((void*)E->src_dev, E->ptr_host, kW * sizeof(void*), hipMemcpyHostToDevice, s));
     const int g = std::min(kMaxGrid, std::max(1, (I0.n + 15) / 16));
     hipLaunchKernelGGL(kb_load, dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.iperm,
-                       (const double* const*)E->src_dev, E->B, E->R, E->X, E->partial_b);
+                       (const double* const*)E->src_dev, E->B, E->R, E->R32, E->X, E->partial_b);
     hipLaunchKernelGGL(kb_fin_init, dim3(1), dim3(kFinThreads), 0, s, E->st, (const double*)E->partial_b, g,
                        (const double*)E->partial_b, g, mask);
     HIP_CHECK(hipGetLastError());
@@ -495,7 +493,8 @@ void batch_true_residual(BatchEngine* E, int restart_mask, double* relres, hipSt
     const int g = unit_grid(I0.n, kBlock / kW);
     hipLaunchKernelGGL(kb_resid, dim3(g), dim3(kBlock), 0, s, I0.n, (const int*)I0.rp, (const int*)I0.ci,
                        (const double*)h->f64.v[0], (const double*)E->X, (const double*)E->B, E->Y,
-                       restart_mask ? E->R : (double*)nullptr, restart_mask, E->partial_b);
+                       restart_mask ? E->R : (double*)nullptr, restart_mask ? E->R32 : (float*)nullptr, restart_mask,
+                       E->partial_b);
     std::vector<double> part((size_t)g * kW);
     HIP_CHECK(hipMemcpyAsync(part.data(), E->partial_b, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -630,6 +629,11 @@ static void debug_batch_impl(BatchEngine* E, DevVals<T>& V, int op, const double
         const DevLevelIdx& I = h->idx[0];
         const int g = std::min(kMaxGrid, std::max(1, (I.n * kW + kBlock - 1) / kBlock));
         hipLaunchKernelGGL((kb_cols_in<double>), dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.iperm, in, E->R);
+        if (E->R32) {
+            const long long cnt = (long long)I.n * kW;
+            hipLaunchKernelGGL(kb_narrow, dim3(vec_grid(cnt)), dim3(kBlock), 0, s, cnt, (const double*)E->R, E->R32,
+                               nodone);
+        }
         enqueue_vcycle_b<T>(E, V, E->Q, nodone, s);
         if (std::is_same<T, float>::value && L > 0)
             hipLaunchKernelGGL(kb_cols_out<float>, dim3(g), dim3(kBlock), 0, s, I.n, (const int*)I.perm,

@@ -417,7 +417,9 @@ static __global__ __launch_bounds__(kBlock) void kb_coarse_rows(
     }
 }
 
-// FP64 -> FP32 copy of n x 16 values (the FP32 cycle's level-0 right-hand side).
+// FP64 -> FP32 copy of n x 16 values (the FP32 cycle's level-0 right-hand
+// side, for the debug entry point; in the iteration every writer of R also
+// writes R32).
 static __global__ __launch_bounds__(kBlock) void kb_narrow(long long cnt, const double* __restrict__ src,
                                                     float* __restrict__ dst, const int* __restrict__ done) {
     if (*done) return;
@@ -496,10 +498,12 @@ static __global__ __launch_bounds__(kBlock) void kb_krylov_pq(int n, const int* 
 }
 
 // x += alpha_c p, r -= alpha_c q for the active columns; partials of r.r.
+// r32 (the FP32 cycle): r rounded to FP32 beside it, the cycle's level-0
+// right-hand side.
 static __global__ __launch_bounds__(kBlock) void kb_update(int n, double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
-                                                    const BatchState* __restrict__ st, double* __restrict__ partial,
-                                                    const int* __restrict__ done) {
+                                                    float* __restrict__ r32, const double* __restrict__ p,
+                                                    const double* __restrict__ q, const BatchState* __restrict__ st,
+                                                    double* __restrict__ partial, const int* __restrict__ done) {
     if (*done) return;
     constexpr int GPB = kBlock / kW;
     __shared__ double s_rr[GPB][kW];
@@ -515,6 +519,7 @@ static __global__ __launch_bounds__(kBlock) void kb_update(int n, double* __rest
             x[e] += alpha * p[e];
             ri -= alpha * q[e];
             r[e] = ri;
+            if (r32) r32[e] = (float)ri;
         }
         rr += ri * ri;
     }
@@ -682,8 +687,8 @@ static __global__ __launch_bounds__(kFinThreads) void kb_fin_init(BatchState* __
 // X[:, c] = 0; per-column partials of b.b (also r.r).
 static __global__ __launch_bounds__(kBlock) void kb_load(int n, const int* __restrict__ iperm,
                                                   const double* const* __restrict__ src, double* __restrict__ B,
-                                                  double* __restrict__ R, double* __restrict__ X,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ R, float* __restrict__ R32,
+                                                  double* __restrict__ X, double* __restrict__ partial) {
     constexpr int GPB = kBlock / kW;
     __shared__ double s_bb[GPB][kW];
     const int g = threadIdx.x / kW, lane = threadIdx.x % kW;
@@ -696,6 +701,7 @@ static __global__ __launch_bounds__(kBlock) void kb_load(int n, const int* __res
             const double v = sc[iperm[i]];
             B[e] = v;
             R[e] = v;
+            if (R32) R32[e] = (float)v;
             X[e] = 0.0;
             bb += v * v;
         }
@@ -727,7 +733,8 @@ static __global__ __launch_bounds__(kBlock) void kb_store(int n, const int* __re
 static __global__ __launch_bounds__(kBlock) void kb_resid(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const double* __restrict__ av, const double* __restrict__ X,
                                                    const double* __restrict__ B, double* __restrict__ Y,
-                                                   double* __restrict__ R, int mask, double* __restrict__ partial) {
+                                                   double* __restrict__ R, float* __restrict__ R32, int mask,
+                                                   double* __restrict__ partial) {
     constexpr int GPB = kBlock / kW;
     __shared__ double s_yy[GPB][kW];
     const int g = threadIdx.x / kW, lane = threadIdx.x % kW;
@@ -740,7 +747,10 @@ static __global__ __launch_bounds__(kBlock) void kb_resid(int n, const int* __re
         const size_t e = (size_t)i * kW + lane;
         const double y = B[e] - s[0];
         Y[e] = y;
-        if (commit) R[e] = y;
+        if (commit) {
+            R[e] = y;
+            if (R32) R32[e] = (float)y;
+        }
         yy += y * y;
     }
     s_yy[g][lane] = yy;
