@@ -105,6 +105,9 @@ constexpr int kTargetTiles = 1024;   // small levels shrink their tiles to keep 
 
 // setup.cpp
 void validate_csr(const pamg_csr& A, bool check_symmetry);
+void validate_csr_header(const pamg_csr& A);
+// The message of row check `code` (1..6 as validate_csr numbers them) failing in `row`.
+std::string csr_error(int code, int64_t row);
 HostHierarchy build_hierarchy(const pamg_csr& A, const pamg_params& prm);
 void extend_hierarchy(HostHierarchy& H, const pamg_params& prm);
 // Keep levels 0, s, 2s, ... and the last of a pairwise hierarchy, composing

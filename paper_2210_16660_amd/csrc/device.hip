@@ -1268,10 +1268,10 @@ pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, p
 }
 
 pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hipStream_t stream,
-                                   pamg_context* ctx, bool validated) {
+                                   pamg_context* ctx) {
     auto t0 = std::chrono::steady_clock::now();
     set_num_threads(prm.num_threads > 0 ? prm.num_threads : 0);
-    if (!validated) validate_csr(A, prm.check_symmetry != 0);
+    validate_csr_header(A);   // the rows are checked on the device (or by the host build)
     pamg_hierarchy* h = new_hierarchy(false, ctx);
     try {
         std::unique_ptr<DeviceBuild> db = device_build(h, A, prm, stream);

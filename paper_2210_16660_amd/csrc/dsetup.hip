@@ -176,6 +176,49 @@ __global__ void k_l1diag(int n, const int* rp, const int* ci, const double* v, d
     atomicMax(maxrow, mx);
 }
 
+// validate_csr's row checks, one thread per row, in the same order (no
+// entry of a row whose bounds are out of order is read): the smallest
+// failing row and its check, as (row << 8) | check.
+__global__ void k_validate(int n, long long nnz, const int* rp, const int* ci, const double* v,
+                           unsigned long long* first) {
+    GRID_STRIDE(i, n) {
+        const int b = rp[i], e = rp[i + 1];
+        int err = 0;
+        if (e < b || b < 0 || (long long)e > nnz) err = 1;
+        bool diag = false;
+        for (int k = b; k < e && !err; ++k) {
+            const int c = ci[k];
+            if (c < 0 || c >= n) {
+                err = 2;
+            } else if (k > b && c <= ci[k - 1]) {
+                err = 3;
+            } else if (c == (int)i) {
+                diag = true;
+                if (!(v[k] > 0.0)) err = 4;
+            }
+            if (!isfinite(v[k])) err = 6;
+        }
+        if (!err && !diag) err = 5;
+        if (err) atomicMin(first, ((unsigned long long)i << 8) | (unsigned long long)err);
+    }
+}
+
+// check_symmetry: every entry has a mirror with the same bits.
+__global__ void k_check_symmetry(int n, const int* rp, const int* ci, const double* v, int* asym) {
+    GRID_STRIDE(i, n) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = ci[k];
+            int b = rp[j], e = rp[j + 1];
+            while (b < e) {
+                const int m = (b + e) >> 1;
+                if (ci[m] < (int)i) b = m + 1; else e = m;
+            }
+            if (b >= rp[j + 1] || ci[b] != (int)i || __double_as_longlong(v[b]) != __double_as_longlong(v[k]))
+                atomicOr(asym, 1);
+        }
+    }
+}
+
 __device__ inline double edge_weight(double a_lohi, double a_lolo, double a_hihi, double w_lo, double w_hi) {
     double num = ((2.0 * a_lohi) * w_lo) * w_hi;
     double den = (a_lolo * w_lo) * w_lo + (a_hihi * w_hi) * w_hi;
@@ -804,12 +847,16 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
     auto dev_level = [&](const CanLevel& L, int l) {
         return L.n > limit && l + 1 < prm.max_levels && L.maxrow <= kRowCap;
     };
-    // level 0: the input matrix, w = 1
+    // level 0: the input matrix (its header checked by the caller), w = 1
     std::vector<CanLevel> lev(1);
     {
         CanLevel& L0 = lev[0];
         L0.n = A.n;
         L0.nnz = A.nnz;
+        int mx = 0;
+        for (int i = 0; i < A.n; ++i) mx = std::max(mx, A.row_ptr[i + 1] - A.row_ptr[i]);
+        L0.maxrow = mx;
+        if (!dev_level(L0, 0)) return nullptr;   // the host build validates it
         L0.rp = T.get<int>((size_t)A.n + 1);
         L0.ci = T.get<int>(A.nnz);
         L0.v = T.get<double>(A.nnz);
@@ -817,12 +864,22 @@ std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, 
         to_device(L0.rp, A.row_ptr, (size_t)A.n + 1, s);
         to_device(L0.ci, A.col_idx, (size_t)A.nnz, s);
         to_device(L0.v, A.val, (size_t)A.nnz, s);
+        // validate_csr's row checks before any kernel follows the columns
+        unsigned long long* first = T.get<unsigned long long>(1);
+        HIP_CHECK(hipMemsetAsync(first, 0xff, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(A.n, kSB)), dim3(kSB), 0, s, A.n, (long long)A.nnz,
+                           (const int*)L0.rp, (const int*)L0.ci, (const double*)L0.v, first);
+        const unsigned long long f = read1(first, s);
+        if (f != ~0ull) throw Error(PAMG_E_INVALID, csr_error((int)(f & 0xff), (int64_t)(f >> 8)));
+        if (prm.check_symmetry) {
+            int* asym = T.get<int>(1);
+            HIP_CHECK(hipMemsetAsync(asym, 0, sizeof(int), s));
+            hipLaunchKernelGGL(k_check_symmetry, dim3(grid_for(A.n, kSB)), dim3(kSB), 0, s, A.n,
+                               (const int*)L0.rp, (const int*)L0.ci, (const double*)L0.v, asym);
+            if (read1(asym, s)) throw Error(PAMG_E_INVALID, "matrix is not bitwise symmetric");
+        }
         hipLaunchKernelGGL(k_fill_d, dim3(grid_for(A.n, kSB)), dim3(kSB), 0, s, (long long)A.n, L0.w, 1.0);
-        int mx = 0;
-        for (int i = 0; i < A.n; ++i) mx = std::max(mx, A.row_ptr[i + 1] - A.row_ptr[i]);
-        L0.maxrow = mx;
     }
-    if (!dev_level(lev[0], 0)) return nullptr;
     // device (pairwise) levels
     const int steps = std::max(1, prm.agg_steps);
     int built = 0;

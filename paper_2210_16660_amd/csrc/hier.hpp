@@ -174,10 +174,9 @@ int coarsest_n(const HostBuild& b);
 // ctx: the context the hierarchy allocates from (null: the current device's default)
 pamg_hierarchy* finish_build(std::unique_ptr<HostBuild> b, hipStream_t stream, pamg_context* ctx);
 // The hierarchy with its large levels built on the device, or null when the
-// device construction does not apply (prm already checked; A validated
-// already if `validated`).
-pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hipStream_t stream, pamg_context* ctx,
-                                   bool validated = false);
+// device construction does not apply (prm already checked; A's rows are
+// validated on the device, as validate_csr would).
+pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hipStream_t stream, pamg_context* ctx);
 // Host copies (canonical numbering) of the device-built levels, made once
 // from the device arrays: matrix, l1 inverse diagonal, aggregates and
 // prolongator entries (no near-null vector).

@@ -496,14 +496,14 @@ static void setup_main(pamg_server* S, int threads) {
         prm.device_setup = S->opts.device_setup ? 1 : 0;
         try {
             if (device_setup_applies(prm) && j->A.n > std::max({kDeviceMinRows, prm.max_dense, prm.max_coarse})) {
-                validate_csr(j->A, false);
+                validate_csr_header(j->A);   // the rows are checked by the build
                 j->need = device_build_bound(j->A, S->opts.precision);
                 // refused (the build's bound exceeds the whole budget): the
                 // host construction, whose admission needs only the hierarchy
                 if (wait_for_room(S, j)) {
                     HIP_CHECK(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
                     const auto t0 = Clock::now();
-                    j->h = device_setup_build(j->A, prm, j->stream, S->ctx, true);
+                    j->h = device_setup_build(j->A, prm, j->stream, S->ctx);
                     j->build_ms = ms_between(t0, Clock::now());
                     if (!j->h) {
                         (void)hipStreamDestroy(j->stream);

@@ -43,17 +43,29 @@ int num_threads() {
 }
 void set_num_threads(int t) { g_threads = t; }
 
-void validate_csr(const pamg_csr& A, bool check_symmetry) {
+std::string csr_error(int code, int64_t row) {
+    static const char* msg[] = {"", "row_ptr not monotone", "column index out of range",
+                                "columns not strictly ascending", "non-positive diagonal",
+                                "missing diagonal entry", "non-finite value"};
+    return std::string(msg[code]) + " in row " + std::to_string(row);
+}
+
+// The checks of validate_csr that read no row (pointers, sizes, row_ptr ends).
+void validate_csr_header(const pamg_csr& A) {
     if (A.n <= 0) throw Error(PAMG_E_INVALID, "n must be positive");
     if (!A.row_ptr || !A.col_idx || !A.val) throw Error(PAMG_E_INVALID, "null CSR pointer");
     if (A.nnz < A.n || A.nnz >= (int64_t(1) << 31)) throw Error(PAMG_E_INVALID, "nnz out of range (need n <= nnz < 2^31)");
     if (A.row_ptr[0] != 0 || A.row_ptr[A.n] != A.nnz) throw Error(PAMG_E_INVALID, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
-    std::atomic<int> bad{0};
-    std::atomic<int32_t> bad_row{-1};
+}
+
+void validate_csr(const pamg_csr& A, bool check_symmetry) {
+    validate_csr_header(A);
+    // the smallest failing row and its check, as (row << 8) | check
+    std::atomic<int64_t> first{INT64_MAX};
     parallel_for(A.n, [&](int64_t i) {
         int32_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
         int err = 0;
-        if (e < b) err = 1;
+        if (e < b || b < 0 || e > A.nnz) err = 1;   // no entry of such a row is read
         bool diag = false;
         for (int32_t k = b; k < e && !err; ++k) {
             int32_t c = A.col_idx[k];
@@ -66,12 +78,14 @@ void validate_csr(const pamg_csr& A, bool check_symmetry) {
             if (!std::isfinite(A.val[k])) err = 6;
         }
         if (!err && !diag) err = 5;
-        if (err) { bad.store(err); bad_row.store((int32_t)i); }
+        if (err) {
+            const int64_t key = (i << 8) | err;
+            int64_t cur = first.load();
+            while (key < cur && !first.compare_exchange_weak(cur, key)) {
+            }
+        }
     });
-    static const char* msg[] = {"", "row_ptr not monotone", "column index out of range",
-                                "columns not strictly ascending", "non-positive diagonal",
-                                "missing diagonal entry", "non-finite value"};
-    if (bad.load()) throw Error(PAMG_E_INVALID, std::string(msg[bad.load()]) + " in row " + std::to_string(bad_row.load()));
+    if (first.load() != INT64_MAX) throw Error(PAMG_E_INVALID, csr_error((int)(first.load() & 0xff), first.load() >> 8));
     if (check_symmetry) {
         std::atomic<int> asym{0};
         parallel_for(A.n, [&](int64_t i) {

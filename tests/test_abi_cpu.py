@@ -44,7 +44,7 @@ def _bad(A, **mut):
     return CSR(A.n, rp, ci, v)
 
 
-@pytest.mark.parametrize("what", ["col_range", "unsorted", "neg_diag", "no_diag", "nan", "rowptr"])
+@pytest.mark.parametrize("what", ["col_range", "unsorted", "neg_diag", "no_diag", "nan", "rowptr", "rowptr_past_end"])
 def test_invalid_csr_rejected(what):
     A = lap7(4)
     muts = {
@@ -54,6 +54,9 @@ def test_invalid_csr_rejected(what):
         "no_diag": lambda rp, ci, v: ci.__setitem__(0, 1) if ci[0] == 0 and ci[1] == 1 else None,
         "nan": lambda rp, ci, v: v.__setitem__(5, np.nan),
         "rowptr": lambda rp, ci, v: rp.__setitem__(2, rp[3] + 1),
+        # a row ending past nnz (a later row then runs backwards): rejected
+        # without reading the row
+        "rowptr_past_end": lambda rp, ci, v: rp.__setitem__(1, rp[-1] + 100),
     }
     B = _bad(A, m=muts[what])
     with pytest.raises(pamg.PamgError) as e:

@@ -15,7 +15,10 @@ the C ABI.
   composed aggregates, matrices and solves are the oracle's / host's too;
 * configurations the device construction does not cover (small inputs, an
   unsymmetric pattern, the hybrid Gauss-Seidel smoother) are built on the
-  host, with identical results.
+  host, with identical results;
+* the device checks a large input's rows as the host does: every kind of
+  defect is refused with the host build's code and message, and the
+  optional bitwise symmetry check too.
 """
 import hashlib
 import json
@@ -183,3 +186,51 @@ def test_value_asymmetry_uses_the_upper_entry_like_the_host():
         assert np.array_equal(Hd.aggregates(l), Hh.aggregates(l))
     for l in range(Hh.levels):
         assert all(np.array_equal(u, w) for u, w in zip(Hd.level_csr(l), Hh.level_csr(l)))
+
+
+@pytest.mark.parametrize("what", ["col_range", "unsorted", "neg_diag", "no_diag", "nan", "rowptr",
+                                  "rowptr_past_end"])
+def test_device_validation_refuses_like_the_host(what):
+    # one defect in row 7000 of a matrix the device would build
+    A = lap7(42)
+    rp, ci, v = A.row_ptr.copy(), A.col.copy(), A.val.copy()
+    r = 7000
+    b = rp[r]
+    d = b + int(np.flatnonzero(ci[b:rp[r + 1]] == r)[0])      # the diagonal entry
+    if what == "col_range":
+        ci[b] = 10 ** 7
+    elif what == "unsorted":
+        ci[b], ci[b + 1] = ci[b + 1], ci[b]
+    elif what == "neg_diag":
+        v[d] = -1.0
+    elif what == "no_diag":
+        ci[d] = r + 2                                           # between r + 1 and r + 42 in lap7(42)
+        ci[b:rp[r + 1]] = np.sort(ci[b:rp[r + 1]])
+    elif what == "nan":
+        v[b + 1] = np.nan
+    elif what == "rowptr":
+        rp[r + 1] = rp[r] - 1
+    elif what == "rowptr_past_end":
+        rp[r + 1] = rp[-1] + 100
+    B = CSR(A.n, rp, ci, v)
+    msgs = []
+    for ds in (1, 0):
+        with pytest.raises(pamg.PamgError) as e:
+            pamg.Hierarchy(B, device_setup=ds, device_min_rows=1000)
+        assert e.value.code == pamg.E_INVALID
+        msgs.append(str(e.value))
+    assert msgs[0].split(": ", 1)[1] == msgs[1].split(": ", 1)[1], msgs   # the smallest failing row on both
+    assert msgs[0].endswith(f"in row {r}"), msgs
+
+
+def test_device_symmetry_check():
+    A = varcoef7(42, seed=3)
+    v = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    k = int(np.flatnonzero(A.col > rows)[1234])                  # one upper entry
+    v[k] = v[k] * (1.0 + 2 ** -40)
+    B = CSR(A.n, A.row_ptr, A.col, v)
+    assert pamg.Hierarchy(B, device_setup=1, device_min_rows=1000).info().device_levels >= 1
+    with pytest.raises(pamg.PamgError) as e:
+        pamg.Hierarchy(B, device_setup=1, device_min_rows=1000, check_symmetry=1)
+    assert e.value.code == pamg.E_INVALID and "symmetric" in str(e.value)
