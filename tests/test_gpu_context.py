@@ -66,6 +66,33 @@ def test_setup_oom_at_every_stage_frees_everything():
     ctx.close()
 
 
+@pytest.mark.parametrize("steps", [1, 2])
+def test_device_setup_oom_frees_everything(steps):
+    # the device construction: canonical temporaries, layout arrays, the
+    # host-built levels' uploads; a failure anywhere leaves nothing behind
+    A = q1_stretched(32, 1.05)
+    kw = dict(build_f32=1, device_setup=1, device_min_rows=1000, agg_steps=steps)
+    inj = Injector()
+    ctx = pamg.Context(allocator=(inj.alloc, inj.free))
+    H = pamg.Hierarchy(A, context=ctx, **kw)
+    assert H.info().device_levels >= 1
+    n_setup = inj.calls
+    H.close()
+    st = ctx.stats()
+    assert st.allocs == st.frees == n_setup and st.live_bytes == 0 and not inj.live
+    assert n_setup > 60
+    for k in sorted({0, 1, 5, n_setup // 4, n_setup // 3, n_setup // 2, 2 * n_setup // 3, n_setup - 2,
+                     n_setup - 1}):
+        inj.fail_after(k)
+        with pytest.raises(pamg.PamgError) as e:
+            pamg.Hierarchy(A, context=ctx, **kw)
+        assert e.value.code == pamg.E_OOM, k
+        st = ctx.stats()
+        assert st.allocs == st.frees and st.live_bytes == 0 and st.users == 0, k
+        assert not inj.live, k
+    ctx.close()
+
+
 def test_oom_leaves_an_existing_hierarchy_unchanged():
     N = 12
     A = q1_stretched(N, 1.05)
