@@ -1,6 +1,6 @@
-"""Write the stored digest of the 128^3 hierarchy the oracle builds.
+"""Write the stored digest of the hierarchy the oracle builds at 128^3 (or N^3).
 
-Calls only the CPU oracle (and the seeded input generator): the 128^3
+Calls only the CPU oracle (and the seeded input generator): the N^3
 stretched-mesh Q1 operator (ratio 1.05), pairwise aggregation with the
 default stopping rules (Sec. 3.1).  For every level: its size, number of
 stored entries, and SHA-256 digests of the canonical CSR arrays (row
@@ -8,7 +8,7 @@ pointer, columns, the values' binary64 bit patterns) and of the aggregate
 numbering, so that a hierarchy built elsewhere can be checked bit for bit
 without running the oracle.
 
-    python tests/golden/make_golden_setup.py
+    python tests/golden/make_golden_setup.py [N]     (default 128; writes q1_<N>_setup.json)
 """
 import hashlib
 import json
@@ -29,7 +29,7 @@ def digest(a, dtype):
 
 
 def main():
-    N, ratio = 128, 1.05
+    N, ratio = (int(sys.argv[1]) if len(sys.argv) > 1 else 128), 1.05
     A = q1_stretched(N, ratio)
     O = oracle.Hierarchy(A)
     levels = []
@@ -41,9 +41,9 @@ def main():
             rec["agg"] = digest(O.agg(l), np.int32)
         levels.append(rec)
         print(f"level {l}: n {rec['n']} nnz {rec['nnz']}", flush=True)
-    out = {"source": "oracle.Hierarchy(q1_stretched(128, 1.05)), default parameters",
+    out = {"source": f"oracle.Hierarchy(q1_stretched({N}, 1.05)), default parameters",
            "digest": "sha256 of the little-endian int32 / binary64 arrays", "levels": levels}
-    with open(os.path.join(HERE, "q1_128_setup.json"), "w") as f:
+    with open(os.path.join(HERE, f"q1_{N}_setup.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 

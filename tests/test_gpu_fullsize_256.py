@@ -8,8 +8,12 @@ the 5-iteration iterate and of z = B b).  FP64: level sizes exact, iterations
 within +-1, true residual <= 1e-6, fixed-5 and (equal counts) converged
 samples within 1e-8, V-cycle samples within 1e-12.  FP32 hierarchy under the
 FP64 FCG: true residual <= 1e-6, error against the oracle's FP64 solution
-reported and bounded.
+reported and bounded.  The hierarchy (its large levels built on the device)
+matches, level by level and bit for bit, the digest of the oracle's stored by
+`tests/golden/make_golden_setup.py 256` (aggregates, row pointers, columns,
+values).
 """
+import hashlib
 import json
 import os
 
@@ -103,3 +107,23 @@ def test_mixed_precision_256(c3):
           f"{info.restarts} restarts, true relres {rel:.3e}, sampled error vs the FP64 oracle {err:.2e}", flush=True)
     assert abs(info.iterations - GOLD["fcg_iterations"]) <= max(2, GOLD["fcg_iterations"] // 5)
     assert err <= 1e-4
+
+
+def test_hierarchy_matches_the_oracle_digest_256(c3):
+    path = os.path.join(os.path.dirname(__file__), "golden", "q1_256_setup.json")
+    ref = json.load(open(path))["levels"]
+    A, b, H, idx = c3
+    info = H.info()
+    assert info.device_levels >= 5 and info.levels == len(ref)
+
+    def digest(a, dtype):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+    for l, r in enumerate(ref):
+        rp, ci, v = H.level_csr(l)
+        assert (len(rp) - 1, int(rp[-1])) == (r["n"], r["nnz"]), l
+        assert digest(rp, np.int32) == r["rp"] and digest(ci, np.int32) == r["ci"], f"level {l} pattern"
+        assert digest(v, np.float64) == r["v"], f"level {l} values"
+        if "agg" in r:
+            assert digest(H.aggregates(l), np.int32) == r["agg"], f"level {l} aggregates"
+        del rp, ci, v
