@@ -471,7 +471,7 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
         }
     }
     const int nL = h->idx[L].n;
-    LAUNCH((k_gs_coarse<T, T>), vec_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
+    LAUNCH((k_gs_coarse<T, T>), coarse_rows_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
     z[L] = V.zc;
     for (int l = L - 1; l >= 0; --l) {
         const DevLevelIdx& I = h->idx[l];
@@ -491,6 +491,18 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
 // Workgroups for `rows` rows handled by groups of `lanes` lanes.
 static int sa_grid(long long rows, int lanes) { return vec_grid(rows * lanes); }
 
+// Call f with std::integral_constant<int, lanes> for rows of nnz / rows
+// entries on average (sa_lanes).
+template <typename F>
+static void with_sa_lanes(long long nnz, long long rows, F&& f) {
+    switch (sa_lanes(nnz, rows)) {
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        default: f(std::integral_constant<int, 64>{}); break;
+    }
+}
+
 // V-cycle with smoothed prolongators (L >= 1): per level the residual of the
 // l1-Jacobi pre-smoothing from zero and its restriction P^T t; after the
 // coarse solve the prolongation D^-1 r + P e and the post-smoothing.
@@ -506,25 +518,32 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
             launch_resid<T, double, T, double>(I, V.vd[0], r0, r0, V.zt[0], s);
         else
             launch_resid<T, T, T, T>(I, V.vd[l], (const T*)V.r[l], (const T*)V.r[l], V.zt[l], s);
-        LAUNCH((k_sa_restrict<T>), sa_grid(nc, kSaRestrictLanes), 0, s, nc, I.sa_trp, I.sa_tci,
-               (const T*)V.sa_tv[l], (const T*)V.zt[l], V.r[l + 1], done);
+        with_sa_lanes(I.sa_nnz, nc, [&](auto g) {
+            constexpr int G = decltype(g)::value;
+            LAUNCH((k_sa_restrict<G, T>), sa_grid(nc, G), 0, s, nc, I.sa_trp, I.sa_tci, (const T*)V.sa_tv[l],
+                   (const T*)V.zt[l], V.r[l + 1], done);
+        });
     }
     const int nL = h->idx[L].n;
-    LAUNCH((k_gs_coarse<T, T>), vec_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
+    LAUNCH((k_gs_coarse<T, T>), coarse_rows_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
     const T* e = V.zc;
     for (int l = L - 1; l >= 0; --l) {
         const DevLevelIdx& I = h->idx[l];
         // z_l goes to zt[l] (the residual there is no longer needed)
         // zp = D^-1 r + P e; t = r - A zp (row tiles); z = zp + D^-1 t
-        if (l == 0) {
-            LAUNCH((k_sa_prolong<T, double>), sa_grid(I.n, kSaProlongLanes), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[0], e,
-                   r0, (const T*)V.dinv[0], V.zp[0], done);
+        with_sa_lanes(I.sa_nnz, I.n, [&](auto g) {
+            constexpr int G = decltype(g)::value;
+            if (l == 0)
+                LAUNCH((k_sa_prolong<G, T, double>), sa_grid(I.n, G), 0, s, I.n, I.sa_prp, I.sa_pci,
+                       (const T*)V.sa_pv[0], e, r0, (const T*)V.dinv[0], V.zp[0], done);
+            else
+                LAUNCH((k_sa_prolong<G, T, T>), sa_grid(I.n, G), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l],
+                       e, (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
+        });
+        if (l == 0)
             launch_resid<T, T, T, double>(I, V.v[0], (const T*)V.zp[0], r0, V.zt[0], s);
-        } else {
-            LAUNCH((k_sa_prolong<T, T>), sa_grid(I.n, kSaProlongLanes), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l], e,
-                   (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
+        else
             launch_resid<T, T, T, T>(I, V.v[l], (const T*)V.zp[l], (const T*)V.r[l], V.zt[l], s);
-        }
         LAUNCH((k_sa_update<T>), vec_grid(I.n), 0, s, I.n, (const T*)V.zp[l], (const T*)V.dinv[l],
                (const T*)V.zt[l], V.zt[l], done);
         e = V.zt[l];

@@ -111,18 +111,25 @@ static __global__ __launch_bounds__(MAXB) void k_hgs(
     if (own) x_new[i] = xi + s_d[t] * omega_inv;
 }
 
-// Dense coarsest solve e = A_L^-1 r (A_L^-1 symmetric: column-major reads).
+// Dense coarsest solve e = A_L^-1 r: one wave per row of the symmetric
+// inverse (row I read along its length, 64 consecutive columns per load),
+// the lanes' partial sums met in a wave butterfly (fixed order); grid
+// ceil(nL / 4) workgroups of four waves.
 template <typename T, typename RT>
 static __global__ __launch_bounds__(kBlock) void k_gs_coarse(int nL, const T* __restrict__ ainv,
                                                       const RT* __restrict__ r, T* __restrict__ e,
                                                       const int* __restrict__ done) {
     if (*done) return;
-    const int stride = gridDim.x * kBlock;
-    for (int I = blockIdx.x * kBlock + threadIdx.x; I < nL; I += stride) {
-        T s = 0;
-        for (int J = 0; J < nL; ++J) s += ainv[(size_t)J * nL + I] * (T)r[J];
-        e[I] = s;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int I = blockIdx.x * (kBlock / 64) + wave;
+    T s = 0;
+    if (I < nL) {
+        const T* __restrict__ row = ainv + (size_t)I * nL;
+#pragma unroll 4
+        for (int j = lane; j < nL; j += 64) s += row[j] * (T)r[j];
     }
+    s = wave_sum(s);
+    if (I < nL && lane == 0) e[I] = s;
 }
 
 // z_m += p_m e_I for the members m of every coarse row I.
