@@ -61,6 +61,16 @@ struct TileDict {
     int32_t max_len = 0;            // longest dictionary of the level
 };
 
+// A CSR matrix's row tiles (<= kTileRows rows and <= items * kBlock entries,
+// or one longer row; 4 ints per tile: k0, k1, r0, r1) with their column
+// dictionaries (tiles of >= kDictItems items per thread): the layout of the
+// tile kernels, used for the smoothed prolongator's P and P^T.
+struct TiledRows {
+    int items = 1;
+    std::vector<int32_t> tiles;
+    TileDict dict;
+};
+
 // Hybrid Gauss-Seidel schedule of one level in hierarchical (nested-aggregate)
 // order, blocks of nb consecutive rows: every row's depth in its block's
 // forward (earlier rows) and backward (later rows) dependency graph (rows of
@@ -93,6 +103,7 @@ struct LayoutLevel {
     // next, both hierarchical, columns ascending) and P^T
     std::vector<int32_t> sa_prp, sa_pci, sa_trp, sa_tci;
     std::vector<double> sa_pv, sa_tv;
+    TiledRows sa_ptile, sa_ttile;   // their row tiles and column dictionaries
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of the tile kernels
@@ -120,6 +131,8 @@ void make_tiles(const std::vector<int32_t>& rp, const std::vector<int32_t>& aggp
 
 // Smoothed prolongator of level l in hierarchical numbering (P and P^T).
 void sa_layout(const HostCSR& P, const LayoutLevel& fine, const LayoutLevel& coarse, LayoutLevel& out);
+// Row tiles and dictionaries of an n-row CSR matrix with ncols columns.
+TiledRows tile_rows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, int32_t n, int32_t ncols);
 
 // Hybrid Gauss-Seidel schedule of a laid-out level (blocks of nb <= 256 rows).
 GsLevel gs_schedule(const LayoutLevel& L, int nb);

@@ -13,7 +13,6 @@
 
 #include "hier.hpp"
 #include "kernels_gs.hpp"
-#include "kernels_sa.hpp"
 #include "dsetup.hpp"
 
 namespace pamg {
@@ -216,10 +215,22 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
             I.down_dmax = std::max(1, (int)Ly.down_dict.max_len);
             I.down_dlen = (long long)Ly.down_dict.col.size();
             if (h->smoothed_p) {
-                I.sa_prp = upload<int>(h, Ly.sa_prp, s);
-                I.sa_pci = upload<int>(h, Ly.sa_pci, s);
-                I.sa_trp = upload<int>(h, Ly.sa_trp, s);
-                I.sa_tci = upload<int>(h, Ly.sa_tci, s);
+                const auto tiled = [&](const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                                       const TiledRows& T) {
+                    DevTiled D;
+                    D.rp = upload<int>(h, rp, s);
+                    D.ci = upload<int>(h, ci, s);
+                    D.tiles = reinterpret_cast<const int4*>(upload<int>(h, T.tiles, s));
+                    D.ntiles = (int)T.tiles.size() / 4;
+                    D.items = T.items;
+                    D.span = reinterpret_cast<const int2*>(upload<int>(h, T.dict.span, s));
+                    D.col = upload<int>(h, T.dict.col, s);
+                    D.loc = upload<uint16_t>(h, T.dict.local, s);
+                    D.dmax = std::max(1, (int)T.dict.max_len);
+                    return D;
+                };
+                I.sa_p = tiled(Ly.sa_prp, Ly.sa_pci, Ly.sa_ptile);
+                I.sa_t = tiled(Ly.sa_trp, Ly.sa_tci, Ly.sa_ttile);
                 I.sa_nnz = (long long)Ly.sa_pci.size();
             }
             if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
@@ -363,7 +374,8 @@ static void launch_spmv(const DevLevelIdx& I, const T* v, const XT* x, const dou
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
         LAUNCH((k_spmv<IT, T, XT, double>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
-               (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, partial);
+               (const int*)I.ci, v, x, b, (const T*)nullptr, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc,
+               partial, (const int*)nullptr);
     });
 }
 
@@ -373,7 +385,38 @@ static void launch_resid(const DevLevelIdx& I, const T* v, const XT* x, const BT
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
         LAUNCH((k_spmv<IT, T, XT, YT, BT>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
-               (const int*)I.ci, v, x, b, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, (double*)nullptr);
+               (const int*)I.ci, v, x, b, (const T*)nullptr, y, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc,
+               (double*)nullptr, (const int*)nullptr);
+    });
+}
+
+// The l1-Jacobi step from x on a level: y = x + D^-1 (b - A x), through the
+// level's row tiles (t = b - A x rounded to T first).
+template <typename T, typename BT>
+static void launch_smooth(const DevLevelIdx& I, const T* v, const T* x, const BT* b, const T* dinv, T* y,
+                          const int* done, hipStream_t s) {
+    with_items(I.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_spmv<IT, T, T, T, BT, kSpmvSmooth>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s,
+               (const int*)I.rp, (const int*)I.ci, v, x, b, dinv, y, I.up_tiles, I.n_up, I.up_span, I.up_col,
+               I.up_loc, (double*)nullptr, done);
+    });
+}
+
+// Products with a tiled matrix M (the smoothed prolongator's P or P^T):
+// y = M x, or with d: y_i = d_i b_i + (M x)_i.
+template <typename T, typename BT>
+static void launch_tiled(const DevTiled& M, const T* v, const T* x, const BT* b, const T* d, T* y, const int* done,
+                         hipStream_t s) {
+    with_items(M.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        if (d)
+            LAUNCH((k_spmv<IT, T, T, T, BT, kSpmvProlong>), tile_grid(M.ntiles), (tile_lds_bytes<IT, T>(M.dmax)), s, M.rp,
+                   M.ci, v, x, b, d, y, M.tiles, M.ntiles, M.span, M.col, M.loc, (double*)nullptr, done);
+        else
+            LAUNCH((k_spmv<IT, T, T, T, BT>), tile_grid(M.ntiles), (tile_lds_bytes<IT, T>(M.dmax)), s, M.rp, M.ci,
+                   v, x, (const BT*)nullptr, (const T*)nullptr, y, M.tiles, M.ntiles, M.span, M.col, M.loc,
+                   (double*)nullptr, done);
     });
 }
 
@@ -488,69 +531,49 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     return g;
 }
 
-// Workgroups for `rows` rows handled by groups of `lanes` lanes.
-static int sa_grid(long long rows, int lanes) { return vec_grid(rows * lanes); }
-
-// Call f with std::integral_constant<int, lanes> for rows of nnz / rows
-// entries on average (sa_lanes).
-template <typename F>
-static void with_sa_lanes(long long nnz, long long rows, F&& f) {
-    switch (sa_lanes(nnz, rows)) {
-        case 8: f(std::integral_constant<int, 8>{}); break;
-        case 16: f(std::integral_constant<int, 16>{}); break;
-        case 32: f(std::integral_constant<int, 32>{}); break;
-        default: f(std::integral_constant<int, 64>{}); break;
-    }
-}
-
-// V-cycle with smoothed prolongators (L >= 1): per level the residual of the
-// l1-Jacobi pre-smoothing from zero and its restriction P^T t; after the
-// coarse solve the prolongation D^-1 r + P e and the post-smoothing.
+// V-cycle with smoothed prolongators (L >= 1; Sec. 3.1, P = (I - w D^-1 A) P^):
+// per level the residual of the l1-Jacobi pre-smoothing from zero and its
+// restriction P^T t; after the coarse solve the prolongation D^-1 r + P e
+// and the post-smoothing.  P is no longer piecewise constant, so the
+// restriction and the prolongation are products with P^T and P, each in the
+// row-tile layout of a level's matrix (tiles and column dictionaries built
+// for them at setup).
 template <typename T>
 static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
                              const int* done, hipStream_t s) {
     const int L = h->L;
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
-        const int nc = h->idx[l + 1].n;
-        // t = r - (A D^-1) r through the row tiles (column-scaled values)
+        // t = r - (A D^-1) r through the row tiles (column-scaled values),
+        // then r_{l+1} = P^T t through the tiles of P^T
         if (l == 0)
             launch_resid<T, double, T, double>(I, V.vd[0], r0, r0, V.zt[0], s);
         else
             launch_resid<T, T, T, T>(I, V.vd[l], (const T*)V.r[l], (const T*)V.r[l], V.zt[l], s);
-        with_sa_lanes(I.sa_nnz, nc, [&](auto g) {
-            constexpr int G = decltype(g)::value;
-            LAUNCH((k_sa_restrict<G, T>), sa_grid(nc, G), 0, s, nc, I.sa_trp, I.sa_tci, (const T*)V.sa_tv[l],
-                   (const T*)V.zt[l], V.r[l + 1], done);
-        });
+        launch_tiled<T, T>(I.sa_t, (const T*)V.sa_tv[l], (const T*)V.zt[l], (const T*)nullptr, (const T*)nullptr,
+                           V.r[l + 1], done, s);
     }
     const int nL = h->idx[L].n;
     LAUNCH((k_gs_coarse<T, T>), coarse_rows_grid(nL), 0, s, nL, (const T*)V.ainv, (const T*)V.r[L], V.zc, done);
     const T* e = V.zc;
     for (int l = L - 1; l >= 0; --l) {
         const DevLevelIdx& I = h->idx[l];
-        // z_l goes to zt[l] (the residual there is no longer needed)
-        // zp = D^-1 r + P e; t = r - A zp (row tiles); z = zp + D^-1 t
-        with_sa_lanes(I.sa_nnz, I.n, [&](auto g) {
-            constexpr int G = decltype(g)::value;
-            if (l == 0)
-                LAUNCH((k_sa_prolong<G, T, double>), sa_grid(I.n, G), 0, s, I.n, I.sa_prp, I.sa_pci,
-                       (const T*)V.sa_pv[0], e, r0, (const T*)V.dinv[0], V.zp[0], done);
-            else
-                LAUNCH((k_sa_prolong<G, T, T>), sa_grid(I.n, G), 0, s, I.n, I.sa_prp, I.sa_pci, (const T*)V.sa_pv[l],
-                       e, (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done);
-        });
-        if (l == 0)
-            launch_resid<T, T, T, double>(I, V.v[0], (const T*)V.zp[0], r0, V.zt[0], s);
-        else
-            launch_resid<T, T, T, T>(I, V.v[l], (const T*)V.zp[l], (const T*)V.r[l], V.zt[l], s);
-        LAUNCH((k_sa_update<T>), vec_grid(I.n), 0, s, I.n, (const T*)V.zp[l], (const T*)V.dinv[l],
-               (const T*)V.zt[l], V.zt[l], done);
-        e = V.zt[l];
+        // zp = D^-1 r + P e (tiles of P), then the post-smoothing
+        // z = zp + D^-1 (r - A zp): into zt[l] on the levels below (the
+        // residual there is no longer needed), at level 0 the output z with
+        // the partials of z . dv (the level-0 up-sweep kernel)
+        if (l == 0) {
+            launch_tiled<T, double>(I.sa_p, (const T*)V.sa_pv[0], e, r0, (const T*)V.dinv[0], V.zp[0], done, s);
+        } else {
+            launch_tiled<T, T>(I.sa_p, (const T*)V.sa_pv[l], e, (const T*)V.r[l], (const T*)V.dinv[l], V.zp[l], done, s);
+            launch_smooth<T, T>(I, V.v[l], (const T*)V.zp[l], (const T*)V.r[l], (const T*)V.dinv[l], V.zt[l], done, s);
+            e = V.zt[l];
+        }
     }
-    const int n0 = h->idx[0].n, g = vec_grid(n0);
-    LAUNCH((k_gs_out<T>), g, 0, s, n0, (const T*)V.zt[0], z_out, dv, h->partial, done);
-    return g;
+    const DevLevelIdx& I0 = h->idx[0];
+    launch_up<T, double, double, true>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const double*)nullptr, nullptr,
+                                       nullptr, nullptr, z_out, dv, h->partial, done, s);
+    return tile_grid(I0.n_up);
 }
 
 // z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0

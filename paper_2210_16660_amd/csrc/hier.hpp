@@ -64,6 +64,18 @@ struct BatchDeleter {
     void operator()(BatchEngine* b) const { destroy_batch(b); }
 };
 
+// A matrix in the tile kernels' layout (row tiles, column dictionaries):
+// the smoothed prolongator's P and P^T.
+struct DevTiled {
+    const int *rp = nullptr, *ci = nullptr;
+    const int4* tiles = nullptr;
+    int ntiles = 0, items = 1;
+    const int2* span = nullptr;
+    const int* col = nullptr;
+    const uint16_t* loc = nullptr;
+    int dmax = 1;                       // longest dictionary
+};
+
 struct DevLevelIdx {
     int n = 0, nc = 0, items = 8;
     int max_agg = 0;                    // most rows in one aggregate of this level (l < L)
@@ -83,7 +95,7 @@ struct DevLevelIdx {
     const int* gs_maxd = nullptr;
     int gs_nblk = 0;
     // smoothed prolongator (l < L): P and P^T patterns, hierarchical numbering
-    const int *sa_prp = nullptr, *sa_pci = nullptr, *sa_trp = nullptr, *sa_tci = nullptr;
+    DevTiled sa_p, sa_t;
     long long sa_nnz = 0;
 };
 

@@ -612,13 +612,21 @@ static __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __re
 
 // ----------------------------------------------------------------------------
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
-// y . y.
-template <int ITEMS, typename T, typename XT, typename YT, typename BT = double>
+// y . y.  Other epilogues with d = dscale (no partial): kSpmvProlong
+// y_i = d_i b_i + (A x)_i (the smoothed prolongation D^-1 r + P e);
+// kSpmvSmooth y_i = x_i + d_i t_i with t = b - A x rounded to T (an
+// l1-Jacobi step from x).  done
+// (optional): the solve's converged flag.
+constexpr int kSpmvPlain = 0, kSpmvProlong = 1, kSpmvSmooth = 2;
+
+template <int ITEMS, typename T, typename XT, typename YT, typename BT = double, int EPI = kSpmvPlain>
 static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-    const XT* __restrict__ xv, const BT* __restrict__ b, YT* __restrict__ y,
+    const XT* __restrict__ xv, const BT* __restrict__ b, const T* __restrict__ dscale, YT* __restrict__ y,
     const int4* __restrict__ tiles, int ntiles,
-    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, double* __restrict__ partial) {
+    const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc, double* __restrict__ partial,
+    const int* __restrict__ done) {
+    if (done && *done) return;
     PAMG_TILE_LDS(T, ITEMS)
     __shared__ T s_red[kBlock / 64];
     __shared__ double s_redd[kBlock / 64];
@@ -668,6 +676,8 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
             const double bi = b ? (double)b[ic] : 0.0;
+            const T di = EPI != kSpmvPlain ? dscale[ic] : T(0);
+            const T xi = EPI == kSpmvSmooth ? (T)xv[ic] : T(0);
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
                 tile_products_dict<ITEMS>(a, li, s_x);
@@ -682,9 +692,16 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
                 for (int k = rb - k0 + lane; k < re - k0; k += G) s += s_prod[k];
             for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
             if (own && lane == 0) {
-                const double v = b ? bi - (double)s : (double)s;
-                y[i] = (YT)v;
-                nrm += v * v;
+                if constexpr (EPI == kSpmvProlong) {
+                    y[i] = (YT)(di * (T)bi + s);
+                } else if constexpr (EPI == kSpmvSmooth) {
+                    const T t = (T)(bi - (double)s);
+                    y[i] = (YT)(xi + di * t);
+                } else {
+                    const double v = b ? bi - (double)s : (double)s;
+                    y[i] = (YT)v;
+                    nrm += v * v;
+                }
             }
             __syncthreads();
         } else {
@@ -695,9 +712,16 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
             for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (T)xv[ci[k]];
             s = block_sum(s, s_red);
             if (tid == 0) {
-                const double v = b ? (double)b[i0] - (double)s : (double)s;
-                y[i0] = (YT)v;
-                nrm += v * v;
+                if constexpr (EPI == kSpmvProlong) {
+                    y[i0] = (YT)(dscale[i0] * (T)b[i0] + s);
+                } else if constexpr (EPI == kSpmvSmooth) {
+                    const T t = (T)((double)b[i0] - (double)s);
+                    y[i0] = (YT)((T)xv[i0] + dscale[i0] * t);
+                } else {
+                    const double v = b ? (double)b[i0] - (double)s : (double)s;
+                    y[i0] = (YT)v;
+                    nrm += v * v;
+                }
             }
             __syncthreads();
         }

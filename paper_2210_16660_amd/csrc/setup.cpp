@@ -764,6 +764,8 @@ void sa_layout(const HostCSR& P, const LayoutLevel& fine, const LayoutLevel& coa
             out.sa_tv[fill[I]] = out.sa_pv[u];
             ++fill[I];
         }
+    out.sa_ptile = tile_rows(out.sa_prp, out.sa_pci, n, nc);
+    out.sa_ttile = tile_rows(out.sa_trp, out.sa_tci, nc, n);
 }
 
 // ------------------------------------------- hybrid Gauss-Seidel schedule
@@ -969,6 +971,28 @@ void make_tiles(const std::vector<int32_t>& rp, const std::vector<int32_t>& aggp
         down.insert(down.end(), {rp[aggptr[start]], rp[aggptr[end]], start, end});
         start = end;
     }
+}
+
+// Row tiles of an n-row matrix with ncols columns, capacity chosen as for a
+// level's own matrix: the first capacity whose dictionaries fit the
+// prefetch slots (halving from first_tile_items), dictionaries only for
+// tiles of at least kDictItems items per thread.
+TiledRows tile_rows(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, int32_t n, int32_t ncols) {
+    TiledRows T;
+    const std::vector<int32_t> no_aggregates;
+    std::vector<int32_t> no_down;
+    int items = first_tile_items((int64_t)rp[n]);
+    for (;;) {
+        T.items = items;
+        const int32_t cap = items * kBlock;
+        make_tiles(rp, no_aggregates, n, 0, cap, T.tiles, no_down);
+        if (items < kDictItems) break;
+        T.dict = build_dicts(T.tiles, ci, ncols, cap);
+        if (items == kDictItems || T.dict.max_len <= kDictMaxLarge) break;
+        items /= 2;
+        T.dict = TileDict();
+    }
+    return T;
 }
 
 // Hierarchical numbering: the coarsest level keeps its numbering; on every
