@@ -80,6 +80,12 @@ struct GsLevel {
     std::vector<uint8_t> depth_f, depth_b;
     std::vector<int32_t> maxd;      // 2 per block: forward, backward
     std::vector<double> ainv;       // 1 / a_ii
+    // 2 per row: the first entry whose column is in the row's block, and
+    // nf | nb << 8 | diag << 16 with nf (nb) the entries of columns in the
+    // block before (after) the row and diag 1 if the row stores a_ii: the
+    // in-block entries are consecutive in the sorted row, so a sweep reads
+    // only them
+    std::vector<int32_t> fresh;
 };
 
 struct LayoutLevel {

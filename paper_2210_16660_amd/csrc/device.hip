@@ -83,11 +83,15 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
     }
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {   // host-built hierarchies only
         V.gsa.assign(nl, nullptr);
+        V.gst.assign(nl, nullptr);
         V.zt.assign(nl, nullptr);
         V.sa_pv.assign(nl, nullptr);
         V.sa_tv.assign(nl, nullptr);
         for (int l = 0; l + 1 < nl; ++l) {
-            if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
+            if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+                V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
+                V.gst[l] = dalloc<T>(h, lay[l].dinv.size(), s);
+            }
             if (h->smoothed_p) {
                 V.sa_pv[l] = upload<T>(h, lay[l].sa_pv, s);
                 V.sa_tv[l] = upload<T>(h, lay[l].sa_tv, s);
@@ -237,6 +241,7 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
                 I.gs_df = upload<uint8_t>(h, Ly.gs.depth_f, s);
                 I.gs_db = upload<uint8_t>(h, Ly.gs.depth_b, s);
                 I.gs_maxd = upload<int>(h, Ly.gs.maxd, s);
+                I.gs_fresh = reinterpret_cast<const int2*>(upload<int>(h, Ly.gs.fresh, s));
                 I.gs_nblk = (int)Ly.gs.maxd.size() / 2;
             }
         }
@@ -451,27 +456,30 @@ static int coarse_partials(int nL) { return nL > kCoarseRowsMin ? coarse_rows_gr
 
 // ---------------------------------------------------------------- schedule
 
-// `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from
-// x = 0 (pre-smoothing) or backward from x (post-smoothing).  Ping-pongs
-// between x and the level's second buffer; returns where the result is.
+// One hybrid Gauss-Seidel sweep at level l from x_old into x_new (zero: from
+// x_old = 0, the first pre-smoothing sweep, which needs no residual pass).
 template <int MAXB, typename T, typename RT>
 static void launch_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, const T* x_old, T* x_new, bool backward,
                        bool zero, const int* done, hipStream_t s) {
     const DevLevelIdx& I = h->idx[l];
     const T winv = (T)(1.0 / h->omega);
     const dim3 g(I.gs_nblk), blk(MAXB);
-    if (backward)
-        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_db, I.gs_maxd, r, x_old, x_new,
-                           winv, done);
-    else if (zero)
-        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
+    if (zero) {
+        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+                           (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
                            (const T*)nullptr, x_new, winv, done);
+        return;
+    }
+    // t = r - A x_old through the row tiles
+    launch_resid<T, T, T, RT>(I, V.v[l], x_old, r, V.gst[l], s);
+    if (backward)
+        hipLaunchKernelGGL((k_hgs<MAXB, T, T, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+                           (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_db, I.gs_maxd, (const T*)V.gst[l],
+                           x_old, x_new, winv, done);
     else
-        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.rp,
-                           (const int*)I.ci, (const T*)V.v[l], (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r, x_old, x_new,
-                           winv, done);
+        hipLaunchKernelGGL((k_hgs<MAXB, T, T, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+                           (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_df, I.gs_maxd, (const T*)V.gst[l],
+                           x_old, x_new, winv, done);
 }
 
 // `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from

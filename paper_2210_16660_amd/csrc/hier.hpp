@@ -51,6 +51,7 @@ struct DevVals {
     std::vector<T*> v, vd, dinv, p;   // per level (vd, p for l < L)
     std::vector<T*> r, zp;            // V-cycle workspace: r_l (l >= 1), zp_l (l < L)
     std::vector<T*> gsa, zt;          // hybrid GS: 1 / a_ii and a second iterate buffer (l < L)
+    std::vector<T*> gst;              // hybrid GS: residual of the old iterate (l < L)
     std::vector<T*> sa_pv, sa_tv;     // smoothed prolongator: values of P and P^T (l < L)
     T* zc = nullptr;                  // hybrid GS: coarsest-level solution
     T* ainv = nullptr;                // dense A_L^{-1}
@@ -93,6 +94,7 @@ struct DevLevelIdx {
     // hybrid Gauss-Seidel schedule (l < L): per-row depths, per-block largest depths
     const uint8_t *gs_df = nullptr, *gs_db = nullptr;
     const int* gs_maxd = nullptr;
+    const int2* gs_fresh = nullptr;     // per row: first in-block entry, counts (GsLevel::fresh)
     int gs_nblk = 0;
     // smoothed prolongator (l < L): P and P^T patterns, hierarchical numbering
     DevTiled sa_p, sa_t;

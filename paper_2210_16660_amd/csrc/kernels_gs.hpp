@@ -9,8 +9,11 @@
 // Blocks are independent (block Jacobi between them), one workgroup each.
 // Inside a block the substitution runs by depth: a row's depth is one more
 // than the deepest earlier (later) row of the block it couples to, so rows of
-// one depth only need results of smaller depths (schedule built at setup);
-// every row's sum over the old iterate is taken first, in parallel.
+// one depth only need results of smaller depths (schedule built at setup).
+// The residual of the old iterate, r - A x_old, comes from the row-tile SpMV
+// (coalesced, like every other pass over A); the sweep kernel then reads
+// only each row's in-block entries, which are consecutive in the sorted row
+// (their range is part of the schedule).
 #pragma once
 
 #include "kernels.hpp"
@@ -19,92 +22,52 @@ namespace pamg {
 
 constexpr int kGsMaxBlock = kBlock;   // largest block (one workgroup of kBlock threads)
 constexpr int kGsSmallBlock = 64;     // blocks of <= 64 rows run one wave per workgroup
-constexpr int kGsFresh = 16;     // in-block entries of a row kept in LDS for the substitution
-constexpr int kGsBatch = 8;      // row entries loaded together in the first pass
+constexpr int kGsFresh = 16;          // in-block entries of a row held in registers
 
-// One sweep.  ZERO: x_old = 0 (the first pre-smoothing sweep).  Row i of the
-// block: d_i = ((r_i - sum_j a_ij x_old_j) - sum_{fresh j} a_ij d_j) / a_ii,
-// fresh = in the block and earlier (forward) / later (backward).  The first
-// pass reads each row once: the sum over x_old, and up to kGsFresh fresh
-// entries (value, position in the block) into LDS; the substitution then
-// runs depth by depth from LDS (a row with more fresh entries reads its row
-// again).
-template <int MAXB, typename T, typename RT, bool BACKWARD, bool ZERO>
+// One sweep from t = r - A x_old (ZERO: x_old = 0 and t = r, the first
+// pre-smoothing sweep).  Row i of the block: d_i = (t_i - sum_{fresh j}
+// a_ij d_j) / a_ii with fresh = in the block and earlier (forward) / later
+// (backward), in column order; x_new = x_old + d / omega.
+template <int MAXB, typename T, typename TT, bool BACKWARD, bool ZERO>
 static __global__ __launch_bounds__(MAXB) void k_hgs(
-    int n, int nb, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+    int n, int nb, const int* __restrict__ ci, const T* __restrict__ av, const int2* __restrict__ fr,
     const T* __restrict__ ainv, const uint8_t* __restrict__ depth, const int* __restrict__ maxd,
-    const RT* __restrict__ r, const T* __restrict__ x_old, T* __restrict__ x_new, T omega_inv,
+    const TT* __restrict__ tin, const T* __restrict__ x_old, T* __restrict__ x_new, T omega_inv,
     const int* __restrict__ done) {
     if (*done) return;
     __shared__ T s_d[MAXB];
-    __shared__ T s_fa[kGsFresh * MAXB];
-    __shared__ uint8_t s_fq[kGsFresh * MAXB];
     const int p = blockIdx.x, t = threadIdx.x;
     const int b0 = p * nb, b1 = min(n, b0 + nb);
     const int i = b0 + t;
     const bool own = t < nb && i < b1;
-    int rb = 0, re = 0, dep = -1, nf = 0;
-    T old = 0, ri = 0, xi = 0, ai = 0;
+    int dep = -1, nf = 0, kf = 0;
+    T ti = 0, xi = 0, ai = 0;
     if (own) {
-        rb = rp[i];
-        re = rp[i + 1];
-        ri = (T)r[i];
+        const int2 f = fr[i];
+        const int before = f.y & 0xff, after = (f.y >> 8) & 0xff, diag = (f.y >> 16) & 1;
+        nf = BACKWARD ? after : before;
+        kf = BACKWARD ? f.x + before + diag : f.x;
+        ti = (T)tin[i];
         ai = ainv[i];
         dep = depth[i];
         if constexpr (!ZERO) xi = x_old[i];
-        // the row in batches of kGsBatch entries: all loads of a batch in
-        // flight together (addresses clamped into the row), then in order
-        for (int k0 = rb; k0 < re; k0 += kGsBatch) {
-            int jj[kGsBatch];
-            T aa[kGsBatch], xx[kGsBatch];
-#pragma unroll
-            for (int u = 0; u < kGsBatch; ++u) {
-                const int k = min(k0 + u, re - 1);
-                jj[u] = ci[k];
-                aa[u] = av[k];
-            }
-#pragma unroll
-            for (int u = 0; u < kGsBatch; ++u) xx[u] = ZERO ? T(0) : x_old[jj[u]];
-#pragma unroll
-            for (int u = 0; u < kGsBatch; ++u) {
-                if (k0 + u >= re) break;
-                const int j = jj[u];
-                if constexpr (!ZERO) old += aa[u] * xx[u];
-                const bool f = BACKWARD ? (j > i && j < b1) : (j >= b0 && j < i);
-                if (f) {
-                    if (nf < kGsFresh) {
-                        s_fa[nf * MAXB + t] = aa[u];
-                        s_fq[nf * MAXB + t] = (uint8_t)(j - b0);
-                    }
-                    ++nf;
-                }
-            }
-        }
     }
-    // a thread's own fresh entries into registers (its own LDS slots: no barrier)
     T fa[kGsFresh];
     int fq[kGsFresh];
 #pragma unroll
     for (int u = 0; u < kGsFresh; ++u) {
-        fa[u] = u < nf ? s_fa[u * MAXB + t] : T(0);
-        fq[u] = u < nf ? (int)s_fq[u * MAXB + t] : 0;
+        fa[u] = u < nf ? av[kf + u] : T(0);
+        fq[u] = u < nf ? ci[kf + u] - b0 : 0;
     }
     const int md = maxd[2 * p + (BACKWARD ? 1 : 0)];
     for (int d = 0; d <= md; ++d) {
         if (dep == d) {
             T fresh = 0;
-            if (nf <= kGsFresh) {
 #pragma unroll
-                for (int u = 0; u < kGsFresh; ++u)
-                    if (u < nf) fresh += fa[u] * s_d[fq[u]];
-            } else {
-                for (int k = rb; k < re; ++k) {
-                    const int j = ci[k];
-                    const bool f = BACKWARD ? (j > i && j < b1) : (j >= b0 && j < i);
-                    if (f) fresh += av[k] * s_d[j - b0];
-                }
-            }
-            s_d[t] = ((ri - old) - fresh) * ai;
+            for (int u = 0; u < kGsFresh; ++u)
+                if (u < nf) fresh += fa[u] * s_d[fq[u]];
+            for (int k = kf + kGsFresh; k < kf + nf; ++k) fresh += av[k] * s_d[ci[k] - b0];
+            s_d[t] = (ti - fresh) * ai;
         }
         __syncthreads();
     }

@@ -778,20 +778,29 @@ GsLevel gs_schedule(const LayoutLevel& L, int nb) {
     g.depth_b.assign(n, 0);
     g.maxd.assign(2 * (size_t)nblk, 0);
     g.ainv.assign(n, 0.0);
+    g.fresh.assign(2 * (size_t)n, 0);
     std::atomic<int> bad{0};
     parallel_for(nblk, [&](int64_t p) {
         const int32_t b0 = (int32_t)p * nb, b1 = std::min(n, b0 + nb);
         int32_t mf = 0, mb = 0;
         for (int32_t i = b0; i < b1; ++i) {
-            int32_t d = 0;
+            int32_t d = 0, first = -1, nbefore = 0, nafter = 0, diag = 0;
             for (int32_t k = L.rp[i]; k < L.rp[i + 1]; ++k) {
                 const int32_t j = L.ci[k];
-                if (j >= b0 && j < i) d = std::max(d, g.depth_f[j] + 1);
+                if (j >= b0 && j < b1 && first < 0) first = k;
+                if (j >= b0 && j < i) {
+                    d = std::max(d, g.depth_f[j] + 1);
+                    ++nbefore;
+                }
+                if (j > i && j < b1) ++nafter;
                 if (j == i) {
                     if (!(L.v[k] > 0.0)) bad.store(1);
                     g.ainv[i] = 1.0 / L.v[k];
+                    diag = 1;
                 }
             }
+            g.fresh[2 * (size_t)i] = first < 0 ? L.rp[i] : first;
+            g.fresh[2 * (size_t)i + 1] = nbefore | nafter << 8 | diag << 16;
             g.depth_f[i] = (uint8_t)d;
             mf = std::max(mf, d);
         }
