@@ -129,11 +129,13 @@ typedef struct {
                                  plain method, lets the Jacobi coupling between the small blocks
                                  diverge on large 3D meshes) */
     int32_t smooth_prolongator; /* 1: P = (I - w D^-1 A) P^ with w = 1/||D^-1 A||_inf, D = diag(A)
-                                 (Sec. 3.1 smoothed aggregation) and A_{l+1} = P^T A P, l1-Jacobi
-                                 smoother only.  With agg_steps = s > 1 each kept level's composed
-                                 tentative prolongator is smoothed (the paper's configuration);
-                                 with pairwise aggregates the coarse matrices fill in quickly.
-                                 Default 0. */
+                                 (Sec. 3.1 smoothed aggregation) and A_{l+1} = P^T A P, with
+                                 either smoother.  With agg_steps = s > 1 each kept level's
+                                 composed tentative prolongator is smoothed; with the hybrid
+                                 Gauss-Seidel smoother (4 + 4 sweeps) and agg_steps = 3 this is
+                                 the paper's preconditioner (Sec. 3.1, Table 1) but for the
+                                 coarsest solver.  With pairwise aggregates the coarse matrices
+                                 fill in quickly.  Default 0. */
     int32_t device_setup;     /* 1: build the large levels on the device (pairwise aggregates or
                                  their composition, tentative prolongators, l1-Jacobi,
                                  weight-eligible edges; smoothed prolongators, the Gauss-Seidel

@@ -408,6 +408,17 @@ static void launch_smooth(const DevLevelIdx& I, const T* v, const T* x, const BT
     });
 }
 
+// y = z + M x with a tiled matrix M (the prolongated correction z + P e).
+template <typename T>
+static void launch_tiled_add(const DevTiled& M, const T* v, const T* x, const T* z, T* y, const int* done,
+                             hipStream_t s) {
+    with_items(M.items, [&](auto it) {
+        constexpr int IT = decltype(it)::value;
+        LAUNCH((k_spmv<IT, T, T, T, T, kSpmvAdd>), tile_grid(M.ntiles), (tile_lds_bytes<IT, T>(M.dmax)), s, M.rp, M.ci,
+               v, x, z, (const T*)nullptr, y, M.tiles, M.ntiles, M.span, M.col, M.loc, (double*)nullptr, done);
+    });
+}
+
 // Products with a tiled matrix M (the smoothed prolongator's P or P^T):
 // y = M x, or with d: y_i = d_i b_i + (M x)_i.
 template <typename T, typename BT>
@@ -513,11 +524,21 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     std::vector<T*> z(L + 1, nullptr);
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
-        if (l == 0) {
+        if (l == 0)
             z[0] = enqueue_hgs<T, double>(h, V, 0, r0, V.zp[0], false, done, s);
+        else
+            z[l] = enqueue_hgs<T, T>(h, V, l, (const T*)V.r[l], V.zp[l], false, done, s);
+        if (h->smoothed_p) {
+            // t = r - A z (row tiles), then r_{l+1} = P^T t (tiles of P^T)
+            if (l == 0)
+                launch_resid<T, T, T, double>(I, V.v[0], (const T*)z[0], r0, V.gst[0], s);
+            else
+                launch_resid<T, T, T, T>(I, V.v[l], (const T*)z[l], (const T*)V.r[l], V.gst[l], s);
+            launch_tiled<T, T>(I.sa_t, (const T*)V.sa_tv[l], (const T*)V.gst[l], (const T*)nullptr,
+                               (const T*)nullptr, V.r[l + 1], done, s);
+        } else if (l == 0) {
             launch_resid_restrict<T, double>(I, V.v[0], r0, z[0], V.p[0], V.r[1], done, s);
         } else {
-            z[l] = enqueue_hgs<T, T>(h, V, l, (const T*)V.r[l], V.zp[l], false, done, s);
             launch_resid_restrict<T, T>(I, V.v[l], V.r[l], z[l], V.p[l], V.r[l + 1], done, s);
         }
     }
@@ -527,8 +548,15 @@ static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     for (int l = L - 1; l >= 0; --l) {
         const DevLevelIdx& I = h->idx[l];
         const int nc = h->idx[l + 1].n;
-        LAUNCH((k_gs_prolong<T>), vec_grid(nc), 0, s, nc, (const int*)I.aggptr, (const T*)V.p[l],
-               (const T*)z[l + 1], z[l], done);
+        if (h->smoothed_p) {
+            // z + P e (tiles of P) into the level's other iterate buffer
+            T* zn = z[l] == V.zp[l] ? V.zt[l] : V.zp[l];
+            launch_tiled_add<T>(I.sa_p, (const T*)V.sa_pv[l], (const T*)z[l + 1], (const T*)z[l], zn, done, s);
+            z[l] = zn;
+        } else {
+            LAUNCH((k_gs_prolong<T>), vec_grid(nc), 0, s, nc, (const int*)I.aggptr, (const T*)V.p[l],
+                   (const T*)z[l + 1], z[l], done);
+        }
         if (l == 0)
             z[0] = enqueue_hgs<T, double>(h, V, 0, r0, z[0], true, done, s);
         else
@@ -1253,8 +1281,8 @@ void check_params(const pamg_params& prm) {
     } else {
         throw Error(PAMG_E_INVALID, "unknown smoother");
     }
-    if (prm.smooth_prolongator != 0 && (prm.smooth_prolongator != 1 || prm.smoother != PAMG_SMOOTHER_L1_JACOBI))
-        throw Error(PAMG_E_INVALID, "smooth_prolongator = 1 needs the l1-Jacobi smoother");
+    if (prm.smooth_prolongator != 0 && prm.smooth_prolongator != 1)
+        throw Error(PAMG_E_INVALID, "smooth_prolongator must be 0 or 1");
     if (prm.device_setup != 0 && prm.device_setup != 1) throw Error(PAMG_E_INVALID, "device_setup must be 0 or 1");
     if (prm.device_min_rows < 0) throw Error(PAMG_E_INVALID, "device_min_rows must be >= 0");
 }

@@ -612,12 +612,13 @@ static __global__ __launch_bounds__(kBlock) void k_prolong(int nc, const T* __re
 
 // ----------------------------------------------------------------------------
 // y = A x  (or y = b - A x when b != nullptr), row tiles; optional partial of
-// y . y.  Other epilogues with d = dscale (no partial): kSpmvProlong
+// y . y.  Other epilogues (no partial), d = dscale: kSpmvProlong
 // y_i = d_i b_i + (A x)_i (the smoothed prolongation D^-1 r + P e);
 // kSpmvSmooth y_i = x_i + d_i t_i with t = b - A x rounded to T (an
-// l1-Jacobi step from x).  done
+// l1-Jacobi step from x); kSpmvAdd y_i = b_i + (A x)_i (a correction
+// z + P e added to the smoothed iterate).  done
 // (optional): the solve's converged flag.
-constexpr int kSpmvPlain = 0, kSpmvProlong = 1, kSpmvSmooth = 2;
+constexpr int kSpmvPlain = 0, kSpmvProlong = 1, kSpmvSmooth = 2, kSpmvAdd = 3;
 
 template <int ITEMS, typename T, typename XT, typename YT, typename BT = double, int EPI = kSpmvPlain>
 static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
@@ -676,7 +677,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
             const double bi = b ? (double)b[ic] : 0.0;
-            const T di = EPI != kSpmvPlain ? dscale[ic] : T(0);
+            const T di = (EPI == kSpmvProlong || EPI == kSpmvSmooth) ? dscale[ic] : T(0);
             const T xi = EPI == kSpmvSmooth ? (T)xv[ic] : T(0);
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
@@ -694,6 +695,8 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
             if (own && lane == 0) {
                 if constexpr (EPI == kSpmvProlong) {
                     y[i] = (YT)(di * (T)bi + s);
+                } else if constexpr (EPI == kSpmvAdd) {
+                    y[i] = (YT)((T)bi + s);
                 } else if constexpr (EPI == kSpmvSmooth) {
                     const T t = (T)(bi - (double)s);
                     y[i] = (YT)(xi + di * t);
@@ -714,6 +717,8 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
             if (tid == 0) {
                 if constexpr (EPI == kSpmvProlong) {
                     y[i0] = (YT)(dscale[i0] * (T)b[i0] + s);
+                } else if constexpr (EPI == kSpmvAdd) {
+                    y[i0] = (YT)((T)b[i0] + s);
                 } else if constexpr (EPI == kSpmvSmooth) {
                     const T t = (T)((double)b[i0] - (double)s);
                     y[i0] = (YT)((T)xv[i0] + dscale[i0] * t);

@@ -117,8 +117,7 @@ def test_bad_params_rejected():
     with pytest.raises(pamg.PamgError):
         pamg.Hierarchy(lap7(3), host_only=1, agg_steps=5)
     # smoother parameters
-    for kw in [dict(smooth_prolongator=1, smoother="hgs"),
-               dict(smooth_prolongator=2),
+    for kw in [dict(smooth_prolongator=2),
                dict(smoother=2), dict(sweeps=2), dict(smoother="hgs", sweeps=17),
                dict(smoother="hgs", gs_block=257), dict(smoother="hgs", omega=-1.0),
                dict(smoother="hgs", omega=float("inf")), dict(smoother="hgs", gs_block=-1)]:
@@ -130,6 +129,10 @@ def test_bad_params_rejected():
     H = pamg.Hierarchy(lap7(8), host_only=1, smoother="hgs")
     assert H.info().levels >= 2
     pamg.Hierarchy(lap7(8), host_only=1, smoother="hgs", sweeps=4, gs_block=1, omega=0.7)
+    # the paper's preconditioner: smoothed prolongators over aggregates of up to
+    # 8 with the hybrid Gauss-Seidel smoother
+    H = pamg.Hierarchy(lap7(10), host_only=1, smoother="hgs", smooth_prolongator=1, agg_steps=3)
+    assert H.info().levels >= 2
 
 
 def test_host_only_hierarchy_refuses_device_calls():

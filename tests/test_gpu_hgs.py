@@ -31,12 +31,16 @@ def host(t):
 
 
 CASES = {
-    # name: (matrix, agg_steps, sweeps, block, omega)
-    "varcoef_30_nb256": (lambda: varcoef7(30, seed=21), 1, 4, 256, 1.0),
-    "q1_24_nb64_omega12": (lambda: q1_stretched(24, 1.05), 1, 2, 64, 1.2),
-    "varcoef_26_nb37_ragged": (lambda: varcoef7(26, seed=22), 1, 3, 37, 1.0),
-    "q1_20_composed2_nb128": (lambda: q1_stretched(20, 1.05), 2, 4, 128, 1.0),
-    "varcoef_18_nb1_jacobi": (lambda: varcoef7(18, seed=23), 1, 2, 1, 1.5),
+    # name: (matrix, agg_steps, sweeps, block, omega, smoothed prolongators)
+    "varcoef_30_nb256": (lambda: varcoef7(30, seed=21), 1, 4, 256, 1.0, False),
+    "q1_24_nb64_omega12": (lambda: q1_stretched(24, 1.05), 1, 2, 64, 1.2, False),
+    "varcoef_26_nb37_ragged": (lambda: varcoef7(26, seed=22), 1, 3, 37, 1.0, False),
+    "q1_20_composed2_nb128": (lambda: q1_stretched(20, 1.05), 2, 4, 128, 1.0, False),
+    "varcoef_18_nb1_jacobi": (lambda: varcoef7(18, seed=23), 1, 2, 1, 1.5, False),
+    # the paper's preconditioner (Sec. 3.1, Table 1): smoothed prolongators
+    # over aggregates of up to 8, 4 + 4 hybrid Gauss-Seidel sweeps
+    "q1_24_smoothed_composed3_nu4": (lambda: q1_stretched(24, 1.05), 3, 4, 256, 1.5, True),
+    "varcoef_22_smoothed_nb64": (lambda: varcoef7(22, seed=24), 1, 2, 64, 1.2, True),
 }
 
 
@@ -46,10 +50,11 @@ def built():
 
     def get(case):
         if case not in cache:
-            mk, steps, nu, nb, om = CASES[case]
+            mk, steps, nu, nb, om, sm = CASES[case]
             A = mk()
-            H = pamg.Hierarchy(A, agg_steps=steps, smoother="hgs", sweeps=nu, gs_block=nb, omega=om, build_f32=1)
-            O = oracle.Hierarchy(A, agg_steps=steps).set_smoother("hgs", nu=nu, nb=nb, omega=om)
+            H = pamg.Hierarchy(A, agg_steps=steps, smoother="hgs", sweeps=nu, gs_block=nb, omega=om, build_f32=1,
+                               smooth_prolongator=int(sm))
+            O = oracle.Hierarchy(A, agg_steps=steps, smooth_prolongator=sm).set_smoother("hgs", nu=nu, nb=nb, omega=om)
             cache[case] = (A, H, O)
         return cache[case]
 
@@ -86,7 +91,8 @@ def test_vcycle_matches_oracle(built, case):
     assert np.linalg.norm(z - zo) <= 1e-11 * np.linalg.norm(zo)
 
 
-@pytest.mark.parametrize("case", ["varcoef_30_nb256", "q1_24_nb64_omega12", "q1_20_composed2_nb128"])
+@pytest.mark.parametrize("case", ["varcoef_30_nb256", "q1_24_nb64_omega12", "q1_20_composed2_nb128",
+                                  "q1_24_smoothed_composed3_nu4"])
 def test_solve_matches_oracle(built, case):
     A, H, O = built(case)
     b = uniform_rhs(A.n, 9)
@@ -124,7 +130,7 @@ def test_batched_engine_refuses_gauss_seidel_and_update_keeps_it(built):
         H.solve_batch(B, X, tol=1e-6)
     assert e.value.code == pamg.E_INVALID
     # coefficient update: 4A gives bitwise the solve of a fresh 4A setup
-    mk, steps, nu, nb, om = CASES["varcoef_26_nb37_ragged"]
+    mk, steps, nu, nb, om, _ = CASES["varcoef_26_nb37_ragged"]
     A4 = CSR(A.n, A.row_ptr, A.col, 4.0 * A.val)
     G = pamg.Hierarchy(A, agg_steps=steps, smoother="hgs", sweeps=nu, gs_block=nb, omega=om)
     F = pamg.Hierarchy(A4, agg_steps=steps, smoother="hgs", sweeps=nu, gs_block=nb, omega=om)
