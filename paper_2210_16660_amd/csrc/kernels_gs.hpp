@@ -23,6 +23,7 @@ namespace pamg {
 constexpr int kGsMaxBlock = kBlock;   // largest block (one workgroup of kBlock threads)
 constexpr int kGsSmallBlock = 64;     // blocks of <= 64 rows run one wave per workgroup
 constexpr int kGsFresh = 16;          // in-block entries of a row held in registers
+constexpr int kGsBatch = 8;           // entries past those loaded together in a depth step
 
 // One sweep from t = r - A x_old (ZERO: x_old = 0 and t = r, the first
 // pre-smoothing sweep).  Row i of the block: d_i = (t_i - sum_{fresh j}
@@ -66,7 +67,21 @@ static __global__ __launch_bounds__(MAXB) void k_hgs(
 #pragma unroll
             for (int u = 0; u < kGsFresh; ++u)
                 if (u < nf) fresh += fa[u] * s_d[fq[u]];
-            for (int k = kf + kGsFresh; k < kf + nf; ++k) fresh += av[k] * s_d[ci[k] - b0];
+            // entries past the registers (dense coarse rows): loaded
+            // kGsBatch at a time, added in order
+            for (int k0 = kf + kGsFresh; k0 < kf + nf; k0 += kGsBatch) {
+                T ab[kGsBatch];
+                int cb[kGsBatch];
+#pragma unroll
+                for (int u = 0; u < kGsBatch; ++u) {
+                    const int k = min(k0 + u, kf + nf - 1);
+                    ab[u] = av[k];
+                    cb[u] = ci[k] - b0;
+                }
+#pragma unroll
+                for (int u = 0; u < kGsBatch; ++u)
+                    if (k0 + u < kf + nf) fresh += ab[u] * s_d[cb[u]];
+            }
             s_d[t] = (ti - fresh) * ai;
         }
         __syncthreads();
