@@ -137,15 +137,15 @@ typedef struct {
                                  coarsest solver.  With pairwise aggregates the coarse matrices
                                  fill in quickly.  Default 0. */
     int32_t device_setup;     /* 1: build the large levels on the device (pairwise aggregates or
-                                 their composition, tentative prolongators, l1-Jacobi,
-                                 weight-eligible edges; smoothed prolongators, the Gauss-Seidel
-                                 smoother, match_all_edges, inputs whose pattern is not
-                                 symmetric and small inputs are built on the host).  The
-                                 hierarchy is bitwise the host-built one: the matching is the
-                                 greedy matching under the same strict order, computed as
-                                 locally dominant edges in parallel rounds (Sec. 3.1, eq.
-                                 (approximatematch)), and every Galerkin entry sums its terms in
-                                 the same order.  Default 1 (0: host only). */
+                                 their composition, tentative prolongators, either smoother (the
+                                 Gauss-Seidel schedule of those levels too), weight-eligible
+                                 edges; smoothed prolongators, match_all_edges, inputs whose
+                                 pattern is not symmetric and small inputs are built on the
+                                 host).  The hierarchy is bitwise the host-built one: the
+                                 matching is the greedy matching under the same strict order,
+                                 computed as locally dominant edges in parallel rounds (Sec.
+                                 3.1, eq. (approximatematch)), and every Galerkin entry sums its
+                                 terms in the same order.  Default 1 (0: host only). */
     int32_t device_min_rows;  /* device_setup: levels with at most this many rows (or max_dense or
                                  max_coarse, if larger) are built on the host (0: 65536) */
     int32_t reserved[2];

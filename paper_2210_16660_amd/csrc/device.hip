@@ -81,24 +81,34 @@ static void upload_values(pamg_hierarchy* h, DevVals<T>& V, const std::vector<La
         if (l >= 1) V.r[l] = dalloc<T>(h, n, s);
         maxn = std::max(maxn, n);
     }
-    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {   // host-built hierarchies only
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS || h->smoothed_p) {   // smoothed: host-built hierarchies only
         V.gsa.assign(nl, nullptr);
         V.gst.assign(nl, nullptr);
         V.zt.assign(nl, nullptr);
         V.sa_pv.assign(nl, nullptr);
         V.sa_tv.assign(nl, nullptr);
         for (int l = 0; l + 1 < nl; ++l) {
+            const size_t n = (size_t)h->idx[l].n;
             if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
-                V.gsa[l] = upload<T>(h, lay[l].gs.ainv, s);
-                V.gst[l] = dalloc<T>(h, lay[l].dinv.size(), s);
+                if (l < m) {
+                    // 1 / a_ii from the device schedule (FP32: its rounding)
+                    const DevLevelOut& D = db->dev[l];
+                    if constexpr (std::is_same<T, double>::value)
+                        V.gsa[l] = D.gs_ainv;
+                    else
+                        V.gsa[l] = convert_copy<T>(h, D.gs_ainv, D.n, s);
+                } else {
+                    V.gsa[l] = upload<T>(h, lay[l - m].gs.ainv, s);
+                }
+                V.gst[l] = dalloc<T>(h, n, s);
             }
             if (h->smoothed_p) {
-                V.sa_pv[l] = upload<T>(h, lay[l].sa_pv, s);
-                V.sa_tv[l] = upload<T>(h, lay[l].sa_tv, s);
+                V.sa_pv[l] = upload<T>(h, lay[l - m].sa_pv, s);
+                V.sa_tv[l] = upload<T>(h, lay[l - m].sa_tv, s);
             }
-            V.zt[l] = dalloc<T>(h, lay[l].dinv.size(), s);
+            V.zt[l] = dalloc<T>(h, n, s);
         }
-        V.zc = dalloc<T>(h, lay[nl - 1].dinv.size(), s);
+        V.zc = dalloc<T>(h, (size_t)h->idx[nl - 1].n, s);
     }
     // A_L^{-1}: factorized on the device in FP64; the FP32 copy is its rounding
     const DevLevelIdx& C = h->idx[nl - 1];
@@ -188,6 +198,13 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
         };
         dict(D.up_dict, I.up_span, I.up_col, I.up_loc, I.up_dmax, I.up_dlen);
         dict(D.down_dict, I.down_span, I.down_col, I.down_loc, I.down_dmax, I.down_dlen);
+        if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+            I.gs_df = D.gs_df;
+            I.gs_db = D.gs_db;
+            I.gs_maxd = D.gs_maxd;
+            I.gs_fresh = reinterpret_cast<const int2*>(D.gs_fresh);
+            I.gs_nblk = D.gs_nblk;
+        }
     }
     for (int l = m; l < nl; ++l) {
         DevLevelIdx& I = h->idx[l];
@@ -1367,6 +1384,16 @@ pamg_hierarchy* device_setup_build(const pamg_csr& A, const pamg_params& prm, hi
         h->lazy_levels = m;
         h->prm = prm;
         const int nl = m + (int)db->host_lay.size();
+        h->smoother = prm.smoother;
+        if (h->smoother == PAMG_SMOOTHER_HYBRID_GS) {
+            h->sweeps = prm.sweeps > 0 ? prm.sweeps : 4;
+            h->gs_block = prm.gs_block > 0 ? prm.gs_block : 256;
+            h->omega = prm.omega > 0.0 ? prm.omega : 1.5;
+            // the Gauss-Seidel schedule of every level but the coarsest: on
+            // the device for the device-built levels, on the host for the rest
+            for (int l = 0; l < m && l + 1 < nl; ++l) device_gs_schedule(h, db->dev[l], h->gs_block, stream);
+            for (int l = m; l + 1 < nl; ++l) db->host_lay[l - m].gs = gs_schedule(db->host_lay[l - m], h->gs_block);
+        }
         for (int l = 0; l < nl && l < PAMG_MAX_LEVELS; ++l)
             h->info.tile_items[l] = l < m ? db->dev[l].items : db->host_lay[l - m].items;
         upload_hierarchy(h, db->host_lay, prm.build_f32 != 0, stream, db.get());

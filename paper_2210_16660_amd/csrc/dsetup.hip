@@ -835,7 +835,89 @@ void download_level(const CanLevel& L, HostLevel& out, hipStream_t s) {
 
 bool device_setup_applies(const pamg_params& prm) {
     return prm.device_setup != 0 && prm.host_only == 0 && prm.agg_steps >= 1 && prm.smooth_prolongator == 0 &&
-           prm.smoother == PAMG_SMOOTHER_L1_JACOBI && prm.match_all_edges == 0;
+           (prm.smoother == PAMG_SMOOTHER_L1_JACOBI || prm.smoother == PAMG_SMOOTHER_HYBRID_GS) &&
+           prm.match_all_edges == 0;
+}
+
+namespace {
+
+// Per row of a level with blocks of nb rows: 1 / a_ii and the range of the
+// row's entries whose columns lie in its block (first such entry; the counts
+// before and after the row; whether a_ii is stored), as the host schedule.
+__global__ void k_gs_rows(int n, int nb, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ ainv, int* __restrict__ fresh,
+                          int* __restrict__ bad) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int b0 = i / nb * nb, b1 = min(n, b0 + nb);
+        int first = -1, before = 0, after = 0, diag = 0;
+        double a = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = ci[k];
+            if (j >= b0 && j < b1 && first < 0) first = k;
+            if (j >= b0 && j < i) ++before;
+            if (j > i && j < b1) ++after;
+            if (j == i) {
+                if (!(v[k] > 0.0)) *bad = 1;
+                a = 1.0 / v[k];
+                diag = 1;
+            }
+        }
+        ainv[i] = a;
+        fresh[2 * (size_t)i] = first < 0 ? rp[i] : first;
+        fresh[2 * (size_t)i + 1] = before | after << 8 | diag << 16;
+    }
+}
+
+// Per block: each row's depth in the block's forward (earlier rows) and
+// backward (later rows) dependency graph, and the block's largest depths; one
+// thread walks its block's rows in order, as the host schedule.
+__global__ void k_gs_depths(int n, int nb, int nblk, const int* __restrict__ rp, const int* __restrict__ ci,
+                            uint8_t* __restrict__ df, uint8_t* __restrict__ db, int* __restrict__ maxd) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nblk; p += gridDim.x * blockDim.x) {
+        const int b0 = p * nb, b1 = min(n, b0 + nb);
+        int mf = 0, mb = 0;
+        for (int i = b0; i < b1; ++i) {
+            int d = 0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                const int j = ci[k];
+                if (j >= b0 && j < i) d = max(d, (int)df[j] + 1);
+            }
+            df[i] = (uint8_t)d;
+            mf = max(mf, d);
+        }
+        for (int i = b1 - 1; i >= b0; --i) {
+            int d = 0;
+            for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                const int j = ci[k];
+                if (j > i && j < b1) d = max(d, (int)db[j] + 1);
+            }
+            db[i] = (uint8_t)d;
+            mb = max(mb, d);
+        }
+        maxd[2 * p] = mf;
+        maxd[2 * p + 1] = mb;
+    }
+}
+
+}  // namespace
+
+void device_gs_schedule(pamg_hierarchy* h, DevLevelOut& D, int nb, hipStream_t s) {
+    const int n = D.n, nblk = (n + nb - 1) / nb;
+    D.gs_nblk = nblk;
+    D.gs_ainv = dalloc<double>(h, n, s);
+    D.gs_fresh = dalloc<int>(h, 2 * (size_t)n, s);
+    D.gs_df = dalloc<uint8_t>(h, n, s);
+    D.gs_db = dalloc<uint8_t>(h, n, s);
+    D.gs_maxd = dalloc<int>(h, 2 * (size_t)nblk, s);
+    Temps T{h->ctx, s, {}};
+    int* bad = T.get<int>(1);
+    HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_gs_rows, dim3(grid_for(n, kSB)), dim3(kSB), 0, s, n, nb, (const int*)D.rp, (const int*)D.ci,
+                       (const double*)D.v, D.gs_ainv, D.gs_fresh, bad);
+    hipLaunchKernelGGL(k_gs_depths, dim3(grid_for(nblk, 64)), dim3(64), 0, s, n, nb, nblk, (const int*)D.rp,
+                       (const int*)D.ci, D.gs_df, D.gs_db, D.gs_maxd);
+    HIP_CHECK(hipGetLastError());
+    if (read1(bad, s)) throw Error(PAMG_E_NOT_SPD, "non-positive diagonal on a coarse level (Gauss-Seidel smoother)");
 }
 
 std::unique_ptr<DeviceBuild> device_build(pamg_hierarchy* h, const pamg_csr& A, const pamg_params& prm,

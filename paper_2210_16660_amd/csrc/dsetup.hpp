@@ -27,6 +27,11 @@ struct DevLevelOut {
     int *up_tiles = nullptr, *down_tiles = nullptr;
     double *v = nullptr, *vd = nullptr, *dinv = nullptr, *p = nullptr;
     DevDict up_dict, down_dict;
+    // hybrid Gauss-Seidel schedule (GsLevel on the device; device_gs_schedule)
+    uint8_t *gs_df = nullptr, *gs_db = nullptr;
+    int *gs_maxd = nullptr, *gs_fresh = nullptr;
+    double* gs_ainv = nullptr;
+    int gs_nblk = 0;
 };
 
 struct DeviceBuild {
@@ -36,9 +41,15 @@ struct DeviceBuild {
     std::vector<LayoutLevel> host_lay;  // their layouts
 };
 
+// The hybrid Gauss-Seidel schedule of a device-built level with blocks of nb
+// rows: the host's gs_schedule, row by row and block by block, on the
+// device (depths, in-block entry ranges, 1 / a_ii); arrays allocated on h.
+// A non-positive diagonal gives PAMG_E_NOT_SPD, as on the host.
+void device_gs_schedule(pamg_hierarchy* h, DevLevelOut& D, int nb, hipStream_t s);
+
 // The configurations the device construction covers: pairwise aggregates
-// or their composition, tentative prolongators, the l1-Jacobi smoother,
-// weight-eligible edges.
+// or their composition, tentative prolongators, the l1-Jacobi or the hybrid
+// Gauss-Seidel smoother, weight-eligible edges.
 bool device_setup_applies(const pamg_params& prm);
 
 // Build the hierarchy of A (validated host CSR) with its large levels on the

@@ -124,6 +124,32 @@ def test_device_built_hierarchy_solves_like_the_host_built_one(case):
             assert torch.equal(xd, xh), (prec, kwargs)
 
 
+@pytest.mark.parametrize("case", ["q1_40_nb64", "varcoef_48_nb256_composed2", "q1_32_nb37"])
+def test_gauss_seidel_schedule_on_the_device_solves_like_the_host_one(case):
+    # the hybrid Gauss-Seidel schedule (depths, in-block entry ranges, 1 / a_ii)
+    # built on the device is the host's, so the solves agree bit for bit
+    make, kw = {
+        "q1_40_nb64": (lambda: q1_stretched(40, 1.05), dict(sweeps=2, gs_block=64, omega=2.0)),
+        "varcoef_48_nb256_composed2": (lambda: varcoef7(48, seed=34), dict(agg_steps=2)),
+        "q1_32_nb37": (lambda: q1_stretched(32, 1.05), dict(sweeps=3, gs_block=37, omega=1.2)),
+    }[case]
+    A = make()
+    Hd = pamg.Hierarchy(A, device_setup=1, device_min_rows=1000, build_f32=1, smoother="hgs", **kw)
+    Hh = pamg.Hierarchy(A, device_setup=0, build_f32=1, smoother="hgs", **kw)
+    assert Hd.info().device_levels >= 1 and Hh.info().device_levels == 0
+    for l in range(Hh.levels - 1):
+        assert np.array_equal(Hd.aggregates(l), Hh.aggregates(l))
+    b = dev(SplitMix64(78).uniform(A.n))
+    for prec in (pamg.PREC_F64, pamg.PREC_F32):
+        for kwargs in ({"fixed_iters": 5, "tol": 0.0}, {"tol": 1e-8}):
+            xd = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+            xh = torch.zeros_like(xd)
+            idd = Hd.solve(b, xd, precision=prec, **kwargs)
+            ih = Hh.solve(b, xh, precision=prec, **kwargs)
+            assert idd.iterations == ih.iterations
+            assert torch.equal(xd, xh), (prec, kwargs)
+
+
 @pytest.mark.parametrize("steps", [1, 2])
 def test_coefficient_update_on_a_device_built_hierarchy(steps):
     A = varcoef7(40, seed=31)
@@ -158,7 +184,6 @@ def test_configurations_left_to_the_host():
     cases = [
         (lap7(20), {}),                                     # below the size floor
         (drop_upper_entry(lap7(40), 1234), {"device_min_rows": 1000}),   # unsymmetric pattern
-        (lap7(40), {"device_min_rows": 1000, "smoother": "hgs"}),
         (lap7(40), {"device_min_rows": 1000, "agg_steps": 2, "smooth_prolongator": 1}),
     ]
     for A, kw in cases:
