@@ -148,6 +148,17 @@ def test_gauss_seidel_schedule_on_the_device_solves_like_the_host_one(case):
             ih = Hh.solve(b, xh, precision=prec, **kwargs)
             assert idd.iterations == ih.iterations
             assert torch.equal(xd, xh), (prec, kwargs)
+    if case == "q1_40_nb64":
+        # a coefficient update recomputes 1 / a_ii of every level on the device,
+        # on the device-built levels too: still bitwise the host-built hierarchy
+        A2 = q1_stretched(40, 1.07)
+        assert np.array_equal(A2.col, A.col)
+        Hd.update_values(A2.val)
+        Hh.update_values(A2.val)
+        xd = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+        xh = torch.zeros_like(xd)
+        assert Hd.solve(b, xd, tol=1e-8).iterations == Hh.solve(b, xh, tol=1e-8).iterations
+        assert torch.equal(xd, xh)
 
 
 @pytest.mark.parametrize("steps", [1, 2])
