@@ -531,9 +531,11 @@ static T* enqueue_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, T* x
 }
 
 // V-cycle with the hybrid Gauss-Seidel smoother (L >= 1): per level `sweeps`
-// forward sweeps from zero, the residual and its restriction (tile kernel),
-// then after the coarse solve the prolongated correction and `sweeps`
-// backward sweeps.  Returns the number of z . dv partials.
+// forward sweeps from zero, the residual and its restriction (tile kernel;
+// with smoothed prolongators the residual, then P^T t through P^T's tiles),
+// then after the coarse solve the prolongated correction (z + P e through
+// P's tiles when smoothed) and `sweeps` backward sweeps.  Returns the number
+// of z . dv partials.
 template <typename T>
 static int enqueue_vcycle_gs(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
                              const int* done, hipStream_t s) {
