@@ -278,6 +278,7 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     h->dbg0 = dalloc<double>(h, maxn, s);
     h->dbg1 = dalloc<double>(h, maxn, s);
     h->dbg2 = dalloc<double>(h, maxn, s);
+    if (build_f32) h->r32 = dalloc<float>(h, n0, s);
     h->partial = dalloc<double>(h, 2 * kMaxGrid, s);
     h->partial_b = dalloc<double>(h, 2 * kMaxGrid, s);
     h->zero_flag = dalloc<int>(h, 1, s);
@@ -631,31 +632,30 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
     return tile_grid(I0.n_up);
 }
 
-// z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
-// up-sweep also writes the partials of z . dv.  Returns the number of partials.
-template <typename T>
-static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
-                          const int* done, hipStream_t s) {
+// The l1-Jacobi cycle with tentative prolongators; r0 of type R0 (the FP64
+// residual, or its FP32 rounding for the FP32 cycle, whose kernels round
+// every level-0 residual value they read to FP32 anyway).
+template <typename T, typename R0>
+static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, double* z_out, const double* dv,
+                                const int* done, hipStream_t s) {
     const int L = h->L;
-    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS && L > 0) return enqueue_vcycle_gs<T>(h, V, r0, z_out, dv, done, s);
-    if (h->smoothed_p && L > 0) return enqueue_vcycle_sa<T>(h, V, r0, z_out, dv, done, s);
     for (int l = 0; l < L; ++l) {
         const DevLevelIdx& I = h->idx[l];
         if (l == 0)
-            launch_down<T, double>(I, V.vd[0], r0, V.p[0], V.r[1], done, s);
+            launch_down<T, R0>(I, V.vd[0], r0, V.p[0], V.r[1], done, s);
         else
             launch_down<T, T>(I, V.vd[l], V.r[l], V.p[l], V.r[l + 1], done, s);
     }
     const int nL = h->idx[L].n;
     if (L == 0) {
-        launch_coarse<T, double, double, true>(nL, V.ainv, r0, nullptr, (const double*)nullptr, nullptr, nullptr,
-                                               nullptr, z_out, dv, h->partial, done, s);
+        launch_coarse<T, R0, R0, true>(nL, V.ainv, r0, nullptr, (const R0*)nullptr, nullptr, nullptr, nullptr, z_out,
+                                       dv, h->partial, done, s);
         return coarse_partials(nL);
     }
     const DevLevelIdx& F = h->idx[L - 1];
     if (L - 1 == 0)
-        launch_coarse<T, T, double, false>(nL, V.ainv, V.r[L], F.aggptr, r0, V.dinv[0], V.p[0], V.zp[0], nullptr,
-                                           nullptr, nullptr, done, s);
+        launch_coarse<T, T, R0, false>(nL, V.ainv, V.r[L], F.aggptr, r0, V.dinv[0], V.p[0], V.zp[0], nullptr,
+                                       nullptr, nullptr, done, s);
     else
         launch_coarse<T, T, T, false>(nL, V.ainv, V.r[L], F.aggptr, V.r[L - 1], V.dinv[L - 1], V.p[L - 1],
                                       V.zp[L - 1], nullptr, nullptr, nullptr, done, s);
@@ -663,16 +663,36 @@ static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, do
         const DevLevelIdx& I = h->idx[l];
         const DevLevelIdx& Fi = h->idx[l - 1];
         if (l - 1 == 0)
-            launch_up<T, T, double, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &Fi, r0, V.dinv[0], V.p[0],
-                                           V.zp[0], nullptr, nullptr, nullptr, done, s);
+            launch_up<T, T, R0, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &Fi, r0, V.dinv[0], V.p[0],
+                                       V.zp[0], nullptr, nullptr, nullptr, done, s);
         else
             launch_up<T, T, T, false>(I, V.v[l], V.zp[l], V.r[l], V.dinv[l], &Fi, V.r[l - 1], V.dinv[l - 1],
                                       V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr, done, s);
     }
     const DevLevelIdx& I0 = h->idx[0];
-    launch_up<T, double, double, true>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const double*)nullptr, nullptr,
-                                       nullptr, nullptr, z_out, dv, h->partial, done, s);
+    launch_up<T, R0, R0, true>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const R0*)nullptr, nullptr, nullptr,
+                               nullptr, z_out, dv, h->partial, done, s);
     return tile_grid(I0.n_up);
+}
+
+// z_out = B r0 on level 0 (r0, z_out FP64, hierarchical order); the level-0
+// up-sweep also writes the partials of z . dv.  Returns the number of partials.
+// The FP32 cycle first rounds r0 to FP32 once (r32): its level-0 kernels then
+// gather 4-byte values, with the same results.
+template <typename T>
+static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
+                          const int* done, hipStream_t s) {
+    const int L = h->L;
+    if (h->smoother == PAMG_SMOOTHER_HYBRID_GS && L > 0) return enqueue_vcycle_gs<T>(h, V, r0, z_out, dv, done, s);
+    if (h->smoothed_p && L > 0) return enqueue_vcycle_sa<T>(h, V, r0, z_out, dv, done, s);
+    if constexpr (std::is_same<T, float>::value) {
+        if (h->r32) {
+            const long long n0 = h->idx[0].n;
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(n0)), dim3(kBlock), 0, s, n0, r0, h->r32);
+            return enqueue_vcycle_plain<float, float>(h, V, (const float*)h->r32, z_out, dv, done, s);
+        }
+    }
+    return enqueue_vcycle_plain<T, double>(h, V, r0, z_out, dv, done, s);
 }
 
 template <typename T>

@@ -146,7 +146,7 @@ static uint64_t estimate_core(const pamg_csr& A, int prec) {
     const double cx = 2.3;
     const double n = (double)A.n, nnz = (double)A.nnz;
     double hier = cx * (nnz * (4 + 8 + 8) + n * 80) + 96.0 * n + (1 << 18);
-    if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32);
+    if (prec == PAMG_PREC_F32) hier += cx * (nnz * 8 + n * 32) + 4.0 * n;
     return (uint64_t)hier;
 }
 
