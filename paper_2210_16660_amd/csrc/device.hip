@@ -278,7 +278,10 @@ void upload_hierarchy(pamg_hierarchy* h, const std::vector<LayoutLevel>& lay, bo
     h->dbg0 = dalloc<double>(h, maxn, s);
     h->dbg1 = dalloc<double>(h, maxn, s);
     h->dbg2 = dalloc<double>(h, maxn, s);
-    if (build_f32) h->r32 = dalloc<float>(h, n0, s);
+    if (build_f32) {
+        h->r32 = dalloc<float>(h, n0, s);
+        h->z32 = dalloc<float>(h, n0, s);
+    }
     h->partial = dalloc<double>(h, 2 * kMaxGrid, s);
     h->partial_b = dalloc<double>(h, 2 * kMaxGrid, s);
     h->zero_flag = dalloc<int>(h, 1, s);
@@ -368,15 +371,16 @@ static void launch_resid_restrict(const DevLevelIdx& I, const T* v, const RT* r,
 }
 
 // F: the finer level (l - 1) prolongated into, or nullptr at level 0 (OUT).
-template <typename T, typename RT, typename RTF, bool OUT>
+template <typename T, typename RT, typename RTF, bool OUT, typename ZO = double>
 static void launch_up(const DevLevelIdx& I, const T* v, const T* zp, const RT* r, const T* dinv, const DevLevelIdx* F,
-                      const RTF* r_f, const T* dinv_f, const T* p_f, T* zp_f, double* z_out, const double* dv,
+                      const RTF* r_f, const T* dinv_f, const T* p_f, T* zp_f,
+                      typename std::common_type<ZO>::type* z_out, const double* dv,
                       double* partial, const int* done, hipStream_t s) {
     const int* aggptr_f = F ? (const int*)F->aggptr : nullptr;
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
         if constexpr (OUT) {
-            LAUNCH((k_up<IT, T, RT, RTF, kUpOut>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
+            LAUNCH((k_up<IT, T, RT, RTF, kUpOut, ZO>), tile_grid(I.n_up), (tile_lds_bytes<IT, T>(I.up_dmax)), s, (const int*)I.rp,
                    (const int*)I.ci, v, zp, r, dinv, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, aggptr_f,
                    r_f, dinv_f, p_f, zp_f, z_out, dv, partial, done);
         } else if (F->max_agg <= 2) {
@@ -454,12 +458,13 @@ static void launch_tiled(const DevTiled& M, const T* v, const T* x, const BT* b,
     });
 }
 
-static void launch_krylov(const DevLevelIdx& I, const double* v, const double* z, const double* p_old, double* p_new,
+template <typename ZT>
+static void launch_krylov(const DevLevelIdx& I, const double* v, const ZT* z, const double* p_old, double* p_new,
                           double* q, const double* r, const SolveState* st, double* partial, const int* done,
                           hipStream_t s) {
     with_items(I.items, [&](auto it) {
         constexpr int IT = decltype(it)::value;
-        LAUNCH((k_krylov_pq<IT>), tile_grid(I.n_up), (tile_lds_bytes<IT, double>(I.up_dmax)), s, (const int*)I.rp,
+        LAUNCH((k_krylov_pq<IT, ZT>), tile_grid(I.n_up), (tile_lds_bytes<IT, double>(I.up_dmax)), s, (const int*)I.rp,
                (const int*)I.ci, v, z, p_old, p_new, q, r, I.up_tiles, I.n_up, I.up_span, I.up_col, I.up_loc, st,
                partial, done);
     });
@@ -635,8 +640,8 @@ static int enqueue_vcycle_sa(pamg_hierarchy* h, DevVals<T>& V, const double* r0,
 // The l1-Jacobi cycle with tentative prolongators; r0 of type R0 (the FP64
 // residual, or its FP32 rounding for the FP32 cycle, whose kernels round
 // every level-0 residual value they read to FP32 anyway).
-template <typename T, typename R0>
-static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, double* z_out, const double* dv,
+template <typename T, typename R0, typename ZO = double>
+static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, ZO* z_out, const double* dv,
                                 const int* done, hipStream_t s) {
     const int L = h->L;
     for (int l = 0; l < L; ++l) {
@@ -647,10 +652,12 @@ static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, 
             launch_down<T, T>(I, V.vd[l], V.r[l], V.p[l], V.r[l + 1], done, s);
     }
     const int nL = h->idx[L].n;
-    if (L == 0) {
-        launch_coarse<T, R0, R0, true>(nL, V.ainv, r0, nullptr, (const R0*)nullptr, nullptr, nullptr, nullptr, z_out,
-                                       dv, h->partial, done, s);
-        return coarse_partials(nL);
+    if constexpr (std::is_same<ZO, double>::value) {
+        if (L == 0) {
+            launch_coarse<T, R0, R0, true>(nL, V.ainv, r0, nullptr, (const R0*)nullptr, nullptr, nullptr, nullptr,
+                                           z_out, dv, h->partial, done, s);
+            return coarse_partials(nL);
+        }
     }
     const DevLevelIdx& F = h->idx[L - 1];
     if (L - 1 == 0)
@@ -670,8 +677,8 @@ static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, 
                                       V.p[l - 1], V.zp[l - 1], nullptr, nullptr, nullptr, done, s);
     }
     const DevLevelIdx& I0 = h->idx[0];
-    launch_up<T, R0, R0, true>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const R0*)nullptr, nullptr, nullptr,
-                               nullptr, z_out, dv, h->partial, done, s);
+    launch_up<T, R0, R0, true, ZO>(I0, V.v[0], V.zp[0], r0, V.dinv[0], nullptr, (const R0*)nullptr, nullptr, nullptr,
+                                   nullptr, z_out, dv, h->partial, done, s);
     return tile_grid(I0.n_up);
 }
 
@@ -679,9 +686,11 @@ static int enqueue_vcycle_plain(pamg_hierarchy* h, DevVals<T>& V, const R0* r0, 
 // up-sweep also writes the partials of z . dv.  Returns the number of partials.
 // The FP32 cycle first rounds r0 to FP32 once (r32): its level-0 kernels then
 // gather 4-byte values, with the same results.
+// z32_out (FP32 cycle with tentative prolongators and l1-Jacobi, L >= 1
+// only; else null): z written there in FP32, exactly, instead of z_out.
 template <typename T>
 static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, double* z_out, const double* dv,
-                          const int* done, hipStream_t s) {
+                          const int* done, hipStream_t s, float* z32_out = nullptr) {
     const int L = h->L;
     if (h->smoother == PAMG_SMOOTHER_HYBRID_GS && L > 0) return enqueue_vcycle_gs<T>(h, V, r0, z_out, dv, done, s);
     if (h->smoothed_p && L > 0) return enqueue_vcycle_sa<T>(h, V, r0, z_out, dv, done, s);
@@ -689,20 +698,35 @@ static int enqueue_vcycle(pamg_hierarchy* h, DevVals<T>& V, const double* r0, do
         if (h->r32) {
             const long long n0 = h->idx[0].n;
             hipLaunchKernelGGL((k_convert<double, float>), dim3(vec_grid(n0)), dim3(kBlock), 0, s, n0, r0, h->r32);
+            if (z32_out && L > 0)
+                return enqueue_vcycle_plain<float, float, float>(h, V, (const float*)h->r32, z32_out, dv, done, s);
             return enqueue_vcycle_plain<float, float>(h, V, (const float*)h->r32, z_out, dv, done, s);
         }
     }
     return enqueue_vcycle_plain<T, double>(h, V, r0, z_out, dv, done, s);
 }
 
+// Whether the FP32 cycle hands z to the Krylov pass in FP32 (z32).
+template <typename T>
+static bool cycle_z32(const pamg_hierarchy* h) {
+    return std::is_same<T, float>::value && h->z32 && h->r32 && h->L > 0 &&
+           h->smoother == PAMG_SMOOTHER_L1_JACOBI && !h->smoothed_p;
+}
+
 template <typename T>
 static void enqueue_iteration(pamg_hierarchy* h, DevVals<T>& V, int krylov, int parity, hipStream_t s) {
     const int* done = &h->st->done;
     const double* dv = (krylov == PAMG_KRYLOV_CG) ? h->r : h->q;
-    const int cnt = enqueue_vcycle<T>(h, V, h->r, h->z, dv, done, s);
+    const bool z32 = cycle_z32<T>(h);
+    const int cnt = enqueue_vcycle<T>(h, V, h->r, h->z, dv, done, s, z32 ? h->z32 : nullptr);
     LAUNCH(k_fin_beta, 1, 0, s, h->st, (const double*)h->partial, cnt);
     const DevLevelIdx& I = h->idx[0];
-    launch_krylov(I, h->f64.v[0], h->z, h->p[parity], h->p[1 - parity], h->q, h->r, h->st, h->partial, done, s);
+    if (z32)
+        launch_krylov<float>(I, h->f64.v[0], h->z32, h->p[parity], h->p[1 - parity], h->q, h->r, h->st, h->partial,
+                             done, s);
+    else
+        launch_krylov<double>(I, h->f64.v[0], h->z, h->p[parity], h->p[1 - parity], h->q, h->r, h->st, h->partial,
+                              done, s);
     LAUNCH(k_fin_alpha, 1, 0, s, h->st, (const double*)h->partial, tile_grid(I.n_up));
     const int gv = vec_grid(I.n);
     LAUNCH(k_krylov_update, gv, 0, s, I.n, h->x, h->r, (const double*)h->p[1 - parity], (const double*)h->q,
@@ -1221,7 +1245,7 @@ static void time_op_impl(pamg_hierarchy* h, DevVals<T>& V, int op, int l, int re
         // matrix (FP64), z, p_old, q_old, r reads; p_new, q writes
         *bytes = M8 + 6 * n * 8;
         launch = [=]() {
-            launch_krylov(I, h->f64.v[0], h->z, h->p[0], h->p[1], h->q, h->r, h->st, h->partial, nodone, s);
+            launch_krylov<double>(I, h->f64.v[0], h->z, h->p[0], h->p[1], h->q, h->r, h->st, h->partial, nodone, s);
         };
     } else if (op == PAMG_OP_SMOOTH) {
         // one backward hybrid Gauss-Seidel sweep: CSR (int32 columns), own r,

@@ -135,6 +135,7 @@ struct pamg_hierarchy {
     double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *b = nullptr;
     double *dbg0 = nullptr, *dbg1 = nullptr, *dbg2 = nullptr;
     float* r32 = nullptr;             // FP32 cycle: the level-0 residual rounded to FP32 (n0; build_f32)
+    float* z32 = nullptr;             // FP32 cycle: its output z, exactly, for the Krylov pass (n0; build_f32)
     double *partial = nullptr, *partial_b = nullptr;
     int* zero_flag = nullptr;
     pamg::SolveState* st = nullptr;

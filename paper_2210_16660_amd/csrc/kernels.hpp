@@ -338,13 +338,14 @@ static __global__ __launch_bounds__(kBlock, 4) void k_down(
 // Up-sweep at level l: post-smooth z = zp + D^-1 (r - A zp), then
 //   l > 0: prolongate into level l-1:  zp_f[m] = dinv_f[m] r_f[m] + p_f[m] z_I
 //          for the members m of coarse row I (= this level's row);
-//   l = 0: write z (FP64) and accumulate the partial of z . dv.
+//   l = 0: write z (as ZO: FP64, or FP32 from the FP32 cycle, which is exact)
+//   and accumulate the partial of z . dv.
 // MODE: kUpOut (l = 0), kUpPair (aggregates of at most two rows: the row's
 // thread writes its members), kUpWide (larger aggregates: z is staged in LDS
 // and the tile's fine rows are written one per thread, coalesced).
 constexpr int kUpOut = 0, kUpPair = 1, kUpWide = 2;
 
-template <int ITEMS, typename T, typename RT, typename RTF, int MODE>
+template <int ITEMS, typename T, typename RT, typename RTF, int MODE, typename ZO = double>
 static __global__ __launch_bounds__(kBlock, 4) void k_up(
     const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
     const T* __restrict__ zp, const RT* __restrict__ r, const T* __restrict__ dinv,
@@ -352,7 +353,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_up(
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc,
     const int* __restrict__ aggptr_f, const RTF* __restrict__ r_f, const T* __restrict__ dinv_f,
     const T* __restrict__ p_f, T* __restrict__ zp_f,
-    double* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
+    ZO* __restrict__ z_out, const double* __restrict__ dv, double* __restrict__ partial,
     const int* __restrict__ done) {
     constexpr bool TO_OUT = MODE == kUpOut;
     if (*done) return;
@@ -437,7 +438,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_up(
             }
             if constexpr (MODE == kUpOut) {
                 if (own) {
-                    z_out[i] = (double)z;
+                    z_out[i] = (ZO)z;
                     dot += (double)z * dvi;
                 }
                 __syncthreads();
@@ -473,7 +474,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_up(
             if (tid == 0) {
                 const T z = zp[i0] + dinv[i0] * ((T)r[i0] - s);
                 if constexpr (TO_OUT) {
-                    z_out[i0] = (double)z;
+                    z_out[i0] = (ZO)z;
                     dot += (double)z * dv[i0];
                 } else {
                     for (int m = aggptr_f[i0]; m < aggptr_f[i0 + 1]; ++m) zp_f[m] = prolong_value(dinv_f[m], (T)r_f[m], p_f[m], z);
@@ -743,11 +744,12 @@ static __global__ __launch_bounds__(kBlock, 4) void k_spmv(
 // so that only z is gathered: one dictionary gather per tile instead of two;
 // q holds q_old on entry and each row's element is read before its owner
 // overwrites it), partials of p.q and p.r.  On the first iteration (and after
-// a restart) q = A z.
-template <int ITEMS>
+// a restart) q = A z.  z is FP64, or FP32 when it comes from the FP32 cycle
+// (whose z values are FP32 numbers: the same sums, half the gathered bytes).
+template <int ITEMS, typename ZT = double>
 static __global__ __launch_bounds__(kBlock, 4) void k_krylov_pq(
     const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
-    const double* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
+    const ZT* __restrict__ z, const double* __restrict__ p_old, double* __restrict__ p_new,
     double* __restrict__ q, const double* __restrict__ r,
     const int4* __restrict__ tiles, int ntiles,
     const int2* __restrict__ span, const int* __restrict__ ucol, const uint16_t* __restrict__ loc,
@@ -780,7 +782,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_krylov_pq(
             double a[ITEMS];
             uint16_t li[ITEMS];
             tile_slots<ITEMS>(k0, k1, kk);
-            const auto gather = [&](int c) { return z[c]; };
+            const auto gather = [&](int c) { return (double)z[c]; };
             double x[ITEMS];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 tile_dict_gather<double>(sp, cc, s_x, gather);
@@ -797,7 +799,7 @@ static __global__ __launch_bounds__(kBlock, 4) void k_krylov_pq(
             const bool own = i < i1;
             const int ic = own ? i : i1 - 1;
             const int rb = rp[ic], re = rp[ic + 1];
-            const double zi = z[ic], poi = p_old[ic], ri = r[ic], qoi = q[ic];
+            const double zi = (double)z[ic], poi = p_old[ic], ri = r[ic], qoi = q[ic];
             if constexpr (tile_uses_dict<ITEMS>()) {
                 __syncthreads();                // dictionary values in LDS
                 tile_products_dict<ITEMS>(a, li, s_x);
@@ -823,10 +825,10 @@ static __global__ __launch_bounds__(kBlock, 4) void k_krylov_pq(
                 if (more) next_cols(nx, ucol);
             }
             double s = 0.0;
-            for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * z[ci[k]];
+            for (int k = k0 + tid; k < k1; k += kBlock) s += av[k] * (double)z[ci[k]];
             s = block_sum(s, s_red);
             if (tid == 0) {
-                const double pi = first ? z[i0] : z[i0] + beta * p_old[i0];
+                const double pi = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
                 s = first ? s : s + beta * q[i0];
                 p_new[i0] = pi;
                 q[i0] = s;
