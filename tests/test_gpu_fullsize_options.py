@@ -1,6 +1,7 @@
 """Parity of the optional configurations at the benchmark's full size (128^3
 stretched Q1, 2,130,047 dofs): aggregate-size composition, coefficient-only
-reuse, the hybrid Gauss-Seidel smoother and smoothed prolongators.
+reuse, the hybrid Gauss-Seidel smoother, smoothed prolongators, and both
+together (the paper's preconditioner).
 
 Expected values are the oracle's, stored by tests/golden/make_golden_options.py
 (level sizes, FCG iterations to 1e-6, sampled entries of z = B b).  Bars as
@@ -29,6 +30,10 @@ CONFIGS = {
     "reuse_updated_to_1.06": (dict(), "reuse", 1e-12),
     "hybrid_gs_nu4_nb256_omega1.5": (dict(smoother="hgs", sweeps=4, gs_block=256, omega=1.5), None, 1e-11),
     "smoothed_agg_steps_3": (dict(agg_steps=3, smooth_prolongator=1), None, 1e-11),
+    # the paper's preconditioner: smoothed prolongators over aggregates of up
+    # to 8 with the hybrid Gauss-Seidel smoother
+    "smoothed_agg_steps_3_hgs_nu2_nb64_omega2": (dict(agg_steps=3, smooth_prolongator=1, smoother="hgs", sweeps=2,
+                                                      gs_block=64, omega=2.0), None, 1e-11),
 }
 
 
