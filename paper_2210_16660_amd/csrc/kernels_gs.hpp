@@ -53,20 +53,33 @@ static __global__ __launch_bounds__(MAXB) void k_hgs(
         dep = depth[i];
         if constexpr (!ZERO) xi = x_old[i];
     }
+    // the row's first kGsFresh in-block entries: every load issued at once
+    // (indices clamped into the row's range; entry 0 for a row with none),
+    // the conditions applied afterwards, so no load waits for another
     T fa[kGsFresh];
     int fq[kGsFresh];
+    const int kb = nf > 0 ? kf : 0, kl = nf > 0 ? nf - 1 : 0;
 #pragma unroll
     for (int u = 0; u < kGsFresh; ++u) {
-        fa[u] = u < nf ? av[kf + u] : T(0);
-        fq[u] = u < nf ? ci[kf + u] - b0 : 0;
+        const int k = kb + min(u, kl);
+        fa[u] = av[k];
+        fq[u] = ci[k];
+    }
+#pragma unroll
+    for (int u = 0; u < kGsFresh; ++u) {
+        fa[u] = u < nf ? fa[u] : T(0);
+        fq[u] = u < nf ? fq[u] - b0 : 0;
     }
     const int md = maxd[2 * p + (BACKWARD ? 1 : 0)];
     for (int d = 0; d <= md; ++d) {
         if (dep == d) {
+            // the row's LDS reads issued together; terms past nf are not added
             T fresh = 0;
 #pragma unroll
-            for (int u = 0; u < kGsFresh; ++u)
-                if (u < nf) fresh += fa[u] * s_d[fq[u]];
+            for (int u = 0; u < kGsFresh; ++u) {
+                const T dj = s_d[fq[u]];
+                fresh = u < nf ? fresh + fa[u] * dj : fresh;
+            }
             // entries past the registers (dense coarse rows): loaded
             // kGsBatch at a time, added in order
             for (int k0 = kf + kGsFresh; k0 < kf + nf; k0 += kGsBatch) {
