@@ -23,6 +23,7 @@ namespace pamg {
 constexpr int kGsMaxBlock = kBlock;   // largest block (one workgroup of kBlock threads)
 constexpr int kGsSmallBlock = 64;     // blocks of <= 64 rows run one wave per workgroup
 constexpr int kGsFresh = 16;          // in-block entries of a row held in registers
+static_assert(kGsFresh % 4 == 0, "the substitution reads its slots in groups of four");
 constexpr int kGsBatch = 8;           // entries past those loaded together in a depth step
 
 // One sweep from t = r - A x_old (ZERO: x_old = 0 and t = r, the first
@@ -70,15 +71,25 @@ static __global__ __launch_bounds__(MAXB) void k_hgs(
         fa[u] = u < nf ? fa[u] : T(0);
         fq[u] = u < nf ? fq[u] - b0 : 0;
     }
+    // every value a slot can read is finite from the start, so a slot past
+    // the row's count (coefficient 0 at column 0) adds exactly +0
+    s_d[t] = T(0);
+    __syncthreads();
     const int md = maxd[2 * p + (BACKWARD ? 1 : 0)];
     for (int d = 0; d <= md; ++d) {
         if (dep == d) {
-            // the row's LDS reads issued together; terms past nf are not added
+            // slots in groups of four: a group's LDS reads are issued
+            // together, and a group no row at this depth reaches is skipped
             T fresh = 0;
 #pragma unroll
-            for (int u = 0; u < kGsFresh; ++u) {
-                const T dj = s_d[fq[u]];
-                fresh = u < nf ? fresh + fa[u] * dj : fresh;
+            for (int g = 0; g < kGsFresh; g += 4) {
+                if (g == 0 || nf > g) {
+                    T dj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) dj[u] = s_d[fq[g + u]];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) fresh += fa[g + u] * dj[u];
+                }
             }
             // entries past the registers (dense coarse rows): loaded
             // kGsBatch at a time, added in order
