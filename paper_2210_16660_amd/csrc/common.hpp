@@ -1,6 +1,8 @@
 // Internal declarations shared by the host setup and the device driver.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -180,6 +182,38 @@ void parallel_for(int64_t n, F&& f, int64_t grain = 4096) {
         });
     }
     for (auto& x : th) x.join();
+}
+
+// Run f(t) on nt threads, t = 0 .. nt-1 (the calling thread runs t = 0).
+template <class F>
+void parallel_workers(int nt, F&& f) {
+    if (nt <= 1) {
+        f(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back([&f, t]() { f(t); });
+    f(0);
+    for (auto& x : th) x.join();
+}
+
+// Run f(t, begin, end) over chunks of consecutive indices of [0, n) that up
+// to num_threads() threads take from a shared counter (t: the thread,
+// 0-based), for loops whose iterations differ widely in cost.  A chunk holds
+// about n / (64 threads) indices, at least min_grab.
+template <class F>
+void parallel_chunks(int64_t n, int64_t min_grab, F&& f) {
+    const int64_t grab = std::max<int64_t>(min_grab, n / (64 * (int64_t)num_threads()));
+    std::atomic<int64_t> next{0};
+    const int nt = (int)std::min<int64_t>(num_threads(), (n + grab - 1) / grab);
+    parallel_workers(nt, [&](int t) {
+        for (;;) {
+            const int64_t b = next.fetch_add(grab);
+            if (b >= n) break;
+            f(t, b, std::min(n, b + grab));
+        }
+    });
 }
 
 // Run f(t, begin, end) over nt contiguous ranges.

@@ -251,9 +251,16 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
             return a.k3 < b.k3;
         });
     };
-    std::vector<int32_t> cnt(nc, 0);
-    parallel_ranges(nc, [&](int, int64_t b, int64_t e) {
+    // coarse rows in chunks from a shared counter: near the coarsest level the
+    // rows are few and long
+    constexpr int64_t kGrab = 16;
+    struct alignas(64) Scratch {  // one cache line (or more) per thread
         std::vector<Term> t;
+    };
+    std::vector<Scratch> scratch(num_threads());
+    std::vector<int32_t> cnt(nc, 0);
+    parallel_chunks(nc, kGrab, [&](int th, int64_t b, int64_t e) {
+        std::vector<Term>& t = scratch[th].t;
         for (int64_t I = b; I < e; ++I) {
             row_terms((int32_t)I, t);
             int32_t d = 0;
@@ -271,8 +278,8 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
     }
     Ac.ci.resize(Ac.rp[nc]);
     Ac.v.resize(Ac.rp[nc]);
-    parallel_ranges(nc, [&](int, int64_t b, int64_t e) {
-        std::vector<Term> t;
+    parallel_chunks(nc, kGrab, [&](int th, int64_t b, int64_t e) {
+        std::vector<Term>& t = scratch[th].t;
         for (int64_t I = b; I < e; ++I) {
             row_terms((int32_t)I, t);
             int32_t q = Ac.rp[I] - 1;
@@ -297,6 +304,8 @@ static void galerkin(const HostCSR& A, const std::vector<int32_t>& agg, const st
 static void smoothed_prolongator(const HostCSR& A, const std::vector<int32_t>& agg, const std::vector<double>& p,
                                  HostCSR& P, double& omega) {
     const int32_t n = A.n;
+    // the rows of a coarse level are long: small levels are split too
+    constexpr int64_t kSmoothGrain = 64;
     std::vector<double> ratio(n);
     parallel_for(n, [&](int64_t i) {
         double s = 0.0, aii = 0.0;
@@ -305,7 +314,7 @@ static void smoothed_prolongator(const HostCSR& A, const std::vector<int32_t>& a
             if (A.ci[k] == i) aii = A.v[k];
         }
         ratio[i] = s / aii;
-    });
+    }, kSmoothGrain);
     double mx = 0.0;
     for (int32_t i = 0; i < n; ++i)
         if (ratio[i] > mx) mx = ratio[i];
@@ -329,7 +338,7 @@ static void smoothed_prolongator(const HostCSR& A, const std::vector<int32_t>& a
             const size_t u = std::lower_bound(c.begin(), c.end(), agg[j]) - c.begin();
             v[u] = v[u] - (om * (A.v[k] / aii)) * p[j];
         }
-    });
+    }, kSmoothGrain);
     P.n = n;
     P.rp.assign(n + 1, 0);
     for (int32_t i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + (int32_t)cols[i].size();
@@ -349,9 +358,25 @@ template <class Emit>
 static void accumulate_rows(int32_t nrows, int32_t ncols, Emit emit, HostCSR& out) {
     std::vector<std::vector<int32_t>> cols(nrows);
     std::vector<std::vector<double>> vals(nrows);
-    parallel_ranges(nrows, [&](int, int64_t b, int64_t e) {
-        std::vector<double> acc(ncols, 0.0);
-        std::vector<int32_t> mark(ncols, -1), list;
+    // rows taken kGrab at a time from a shared counter: the rows of a coarse
+    // smoothed level are long and few, so equal row ranges (or one thread
+    // for a small level) leave most threads idle; each row is still summed by
+    // one thread in list order
+    constexpr int64_t kGrab = 16;
+    struct alignas(64) Scratch {  // one cache line (or more) per thread
+        std::vector<double> acc;
+        std::vector<int32_t> mark, list;
+    };
+    std::vector<Scratch> scratch(num_threads());
+    parallel_chunks(nrows, kGrab, [&](int th, int64_t b, int64_t e) {
+        Scratch& S = scratch[th];
+        if (S.mark.empty()) {
+            S.acc.assign(ncols, 0.0);
+            S.mark.assign(ncols, -1);
+        }
+        std::vector<double>& acc = S.acc;
+        std::vector<int32_t>& mark = S.mark;
+        std::vector<int32_t>& list = S.list;
         for (int64_t r = b; r < e; ++r) {
             list.clear();
             emit((int32_t)r, [&](int32_t J, double term) {
