@@ -408,6 +408,56 @@ static void accumulate_rows(int32_t nrows, int32_t ncols, Emit emit, HostCSR& ou
     });
 }
 
+// Out row J lists (i, v_iJ) over the stored entries (i, J) of rows 0..n-1
+// that keep(i, J) accepts, i ascending: a stable counting sort by column over
+// contiguous row ranges, one per thread, each thread filling its own slots
+// (column J holds thread 0's rows first, then thread 1's, ...).
+template <class Keep>
+static void transpose_rows(int32_t n, int32_t m, const int32_t* rp, const int32_t* ci, const double* v, Keep keep,
+                           std::vector<int32_t>& orp, std::vector<int32_t>& oci, std::vector<double>& ov) {
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(num_threads(), n / 1024));
+    std::vector<std::vector<int32_t>> slot(nt);
+    auto rows_of = [&](int t, int64_t& b, int64_t& e) {
+        b = (int64_t)n * t / nt;
+        e = (int64_t)n * (t + 1) / nt;
+    };
+    parallel_workers(nt, [&](int t) {
+        int64_t b, e;
+        rows_of(t, b, e);
+        std::vector<int32_t>& c = slot[t];
+        c.assign(m, 0);
+        for (int64_t i = b; i < e; ++i)
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (keep((int32_t)i, ci[k])) ++c[ci[k]];
+    });
+    orp.assign(m + 1, 0);
+    for (int32_t J = 0; J < m; ++J) {
+        int64_t at = orp[J];
+        for (int t = 0; t < nt; ++t) {
+            const int32_t c = slot[t][J];
+            slot[t][J] = (int32_t)at;
+            at += c;
+        }
+        if (at >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "transposed matrix exceeds 2^31 entries");
+        orp[J + 1] = (int32_t)at;
+    }
+    oci.resize(orp[m]);
+    ov.resize(orp[m]);
+    parallel_workers(nt, [&](int t) {
+        int64_t b, e;
+        rows_of(t, b, e);
+        std::vector<int32_t>& pos = slot[t];
+        for (int64_t i = b; i < e; ++i)
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t J = ci[k];
+                if (!keep((int32_t)i, J)) continue;
+                oci[pos[J]] = (int32_t)i;
+                ov[pos[J]] = v[k];
+                ++pos[J];
+            }
+    });
+}
+
 // A_c = P^T A P: B = A P (B_kJ = 0.0 + sum over j ascending of a_kj P_jJ), then
 // for I <= J: A_c[I,J] = 0.0 + sum over i ascending of P_iI B_iJ; mirrored.
 static void galerkin_smoothed(const HostCSR& A, const HostCSR& P, int32_t nc, HostCSR& Ac) {
@@ -420,20 +470,9 @@ static void galerkin_smoothed(const HostCSR& A, const HostCSR& P, int32_t nc, Ho
         }
     }, B);
     // P^T: rows I, entries (i, P_iI) with i ascending
-    std::vector<int32_t> tp(nc + 1, 0), ti(P.rp[n]);
-    std::vector<double> tv(P.rp[n]);
-    for (int32_t u = 0; u < P.rp[n]; ++u) ++tp[P.ci[u] + 1];
-    for (int32_t I = 0; I < nc; ++I) tp[I + 1] += tp[I];
-    {
-        std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
-        for (int32_t i = 0; i < n; ++i)
-            for (int32_t u = P.rp[i]; u < P.rp[i + 1]; ++u) {
-                const int32_t I = P.ci[u];
-                ti[fill[I]] = i;
-                tv[fill[I]] = P.v[u];
-                ++fill[I];
-            }
-    }
+    std::vector<int32_t> tp, ti;
+    std::vector<double> tv;
+    transpose_rows(n, nc, P.rp.data(), P.ci.data(), P.v.data(), [](int32_t, int32_t) { return true; }, tp, ti, tv);
     HostCSR U;
     accumulate_rows(nc, nc, [&](int32_t I, auto&& add) {
         for (int32_t x = tp[I]; x < tp[I + 1]; ++x) {
@@ -443,37 +482,30 @@ static void galerkin_smoothed(const HostCSR& A, const HostCSR& P, int32_t nc, Ho
         }
     }, U);
     // full rows: mirrored entries (ascending source row), then the upper row
-    std::vector<int32_t> cnt(nc + 1, 0);
-    for (int32_t I = 0; I < nc; ++I)
-        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
-            ++cnt[I + 1];
-            if (U.ci[u] != I) ++cnt[U.ci[u] + 1];
-        }
-    for (int32_t I = 0; I < nc; ++I) {
-        const int64_t nx = (int64_t)cnt[I + 1] + cnt[I];
-        if (nx >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "coarse matrix exceeds 2^31 entries");
-        cnt[I + 1] = (int32_t)nx;
-    }
+    std::vector<int32_t> mp, mi;
+    std::vector<double> mv;
+    transpose_rows(nc, nc, U.rp.data(), U.ci.data(), U.v.data(), [](int32_t I, int32_t J) { return J != I; }, mp, mi,
+                   mv);
     Ac.n = nc;
-    Ac.rp = cnt;
-    Ac.ci.resize(cnt[nc]);
-    Ac.v.resize(cnt[nc]);
-    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int32_t I = 0; I < nc; ++I)
-        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
-            const int32_t J = U.ci[u];
-            if (J != I) {
-                Ac.ci[pos[J]] = I;
-                Ac.v[pos[J]] = U.v[u];
-                ++pos[J];
-            }
+    Ac.rp.assign(nc + 1, 0);
+    for (int32_t I = 0; I < nc; ++I) {
+        const int64_t nx = (int64_t)Ac.rp[I] + (mp[I + 1] - mp[I]) + (U.rp[I + 1] - U.rp[I]);
+        if (nx >= (int64_t(1) << 31)) throw Error(PAMG_E_OOM, "coarse matrix exceeds 2^31 entries");
+        Ac.rp[I + 1] = (int32_t)nx;
+    }
+    Ac.ci.resize(Ac.rp[nc]);
+    Ac.v.resize(Ac.rp[nc]);
+    parallel_for(nc, [&](int64_t I) {
+        int32_t q = Ac.rp[I];
+        for (int32_t u = mp[I]; u < mp[I + 1]; ++u, ++q) {
+            Ac.ci[q] = mi[u];
+            Ac.v[q] = mv[u];
         }
-    for (int32_t I = 0; I < nc; ++I)
-        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u) {
-            Ac.ci[pos[I]] = U.ci[u];
-            Ac.v[pos[I]] = U.v[u];
-            ++pos[I];
+        for (int32_t u = U.rp[I]; u < U.rp[I + 1]; ++u, ++q) {
+            Ac.ci[q] = U.ci[u];
+            Ac.v[q] = U.v[u];
         }
+    }, 256);
 }
 
 // ------------------------------------------ aggregate-size composition
