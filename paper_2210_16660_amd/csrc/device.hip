@@ -492,14 +492,14 @@ static int coarse_partials(int nL) { return nL > kCoarseRowsMin ? coarse_rows_gr
 
 // One hybrid Gauss-Seidel sweep at level l from x_old into x_new (zero: from
 // x_old = 0, the first pre-smoothing sweep, which needs no residual pass).
-template <int MAXB, typename T, typename RT>
-static void launch_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, const T* x_old, T* x_new, bool backward,
-                       bool zero, const int* done, hipStream_t s) {
+template <int MAXB, typename T, typename RT, int RB>
+static void launch_hgs_rb(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, const T* x_old, T* x_new,
+                          bool backward, bool zero, const int* done, hipStream_t s) {
     const DevLevelIdx& I = h->idx[l];
     const T winv = (T)(1.0 / h->omega);
     const dim3 g(I.gs_nblk), blk(MAXB);
     if (zero) {
-        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, true>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+        hipLaunchKernelGGL((k_hgs<MAXB, T, RT, false, true, RB>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
                            (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_df, I.gs_maxd, r,
                            (const T*)nullptr, x_new, winv, done);
         return;
@@ -507,13 +507,30 @@ static void launch_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, con
     // t = r - A x_old through the row tiles
     launch_resid<T, T, T, RT>(I, V.v[l], x_old, r, V.gst[l], s);
     if (backward)
-        hipLaunchKernelGGL((k_hgs<MAXB, T, T, true, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+        hipLaunchKernelGGL((k_hgs<MAXB, T, T, true, false, RB>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
                            (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_db, I.gs_maxd, (const T*)V.gst[l],
                            x_old, x_new, winv, done);
     else
-        hipLaunchKernelGGL((k_hgs<MAXB, T, T, false, false>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
+        hipLaunchKernelGGL((k_hgs<MAXB, T, T, false, false, RB>), g, blk, 0, s, I.n, h->gs_block, (const int*)I.ci,
                            (const T*)V.v[l], I.gs_fresh, (const T*)V.gsa[l], I.gs_df, I.gs_maxd, (const T*)V.gst[l],
                            x_old, x_new, winv, done);
+}
+
+// One sweep.  A level whose rows average kGsWideRow entries or more
+// (smoothed coarse levels) loads the in-block entries past the registers
+// kGsWideBatch at a time instead of kGsBatch, at the price of registers (two
+// waves per SIMD): with blocks of 256 rows (many in-block entries per row),
+// or with one-wave blocks when the level's waves fit the chip in one round.
+template <int MAXB, typename T, typename RT>
+static void launch_hgs(pamg_hierarchy* h, DevVals<T>& V, int l, const RT* r, const T* x_old, T* x_new, bool backward,
+                       bool zero, const int* done, hipStream_t s) {
+    const DevLevelIdx& I = h->idx[l];
+    constexpr long long kWideWaves = 256LL * 4 * 2;  // CUs x SIMDs x waves per SIMD of the wide form
+    const bool long_rows = I.nnz >= (long long)kGsWideRow * I.n;
+    if (long_rows && (MAXB > kGsSmallBlock || (long long)I.gs_nblk * (MAXB / 64) <= kWideWaves))
+        launch_hgs_rb<MAXB, T, RT, kGsWideBatch>(h, V, l, r, x_old, x_new, backward, zero, done, s);
+    else
+        launch_hgs_rb<MAXB, T, RT, kGsBatch>(h, V, l, r, x_old, x_new, backward, zero, done, s);
 }
 
 // `sweeps` hybrid Gauss-Seidel sweeps at level l on A_l x = r: forward from

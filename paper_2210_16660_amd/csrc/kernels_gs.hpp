@@ -25,12 +25,14 @@ constexpr int kGsSmallBlock = 64;     // blocks of <= 64 rows run one wave per w
 constexpr int kGsFresh = 16;          // in-block entries of a row held in registers
 static_assert(kGsFresh % 4 == 0, "the substitution reads its slots in groups of four");
 constexpr int kGsBatch = 8;           // entries past those loaded together in a depth step
+constexpr int kGsWideBatch = 32;      // the same on levels with long rows (few blocks, registers to spare)
+constexpr int kGsWideRow = 64;        // mean row length from which a level takes the wide batch
 
 // One sweep from t = r - A x_old (ZERO: x_old = 0 and t = r, the first
 // pre-smoothing sweep).  Row i of the block: d_i = (t_i - sum_{fresh j}
 // a_ij d_j) / a_ii with fresh = in the block and earlier (forward) / later
 // (backward), in column order; x_new = x_old + d / omega.
-template <int MAXB, typename T, typename TT, bool BACKWARD, bool ZERO>
+template <int MAXB, typename T, typename TT, bool BACKWARD, bool ZERO, int RB = kGsBatch>
 static __global__ __launch_bounds__(MAXB) void k_hgs(
     int n, int nb, const int* __restrict__ ci, const T* __restrict__ av, const int2* __restrict__ fr,
     const T* __restrict__ ainv, const uint8_t* __restrict__ depth, const int* __restrict__ maxd,
@@ -91,20 +93,37 @@ static __global__ __launch_bounds__(MAXB) void k_hgs(
                     for (int u = 0; u < 4; ++u) fresh += fa[g + u] * dj[u];
                 }
             }
-            // entries past the registers (dense coarse rows): loaded
-            // kGsBatch at a time, added in order
-            for (int k0 = kf + kGsFresh; k0 < kf + nf; k0 += kGsBatch) {
-                T ab[kGsBatch];
-                int cb[kGsBatch];
+            // entries past the registers: RB at a time, loaded together at
+            // clamped indices, added in order.  The wide form (long coarse
+            // rows, registers to spare) also issues the batch's LDS reads
+            // together (a slot past the row adds exactly +0); the narrow one
+            // keeps a branch per entry, which holds the level-0 kernels'
+            // registers down
+            for (int k0 = kf + kGsFresh; k0 < kf + nf; k0 += RB) {
+                T ab[RB];
+                int cb[RB];
 #pragma unroll
-                for (int u = 0; u < kGsBatch; ++u) {
+                for (int u = 0; u < RB; ++u) {
                     const int k = min(k0 + u, kf + nf - 1);
                     ab[u] = av[k];
                     cb[u] = ci[k] - b0;
                 }
+                if constexpr (RB > kGsBatch) {
 #pragma unroll
-                for (int u = 0; u < kGsBatch; ++u)
-                    if (k0 + u < kf + nf) fresh += ab[u] * s_d[cb[u]];
+                    for (int u = 0; u < RB; ++u) {
+                        ab[u] = k0 + u < kf + nf ? ab[u] : T(0);
+                        cb[u] = k0 + u < kf + nf ? cb[u] : 0;
+                    }
+                    T db[RB];
+#pragma unroll
+                    for (int u = 0; u < RB; ++u) db[u] = s_d[cb[u]];
+#pragma unroll
+                    for (int u = 0; u < RB; ++u) fresh += ab[u] * db[u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RB; ++u)
+                        if (k0 + u < kf + nf) fresh += ab[u] * s_d[cb[u]];
+                }
             }
             s_d[t] = (ti - fresh) * ai;
         }
