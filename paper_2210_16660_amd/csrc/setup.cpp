@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 
 #include "common.hpp"
@@ -129,47 +130,71 @@ static Adj eligible_adjacency(const HostCSR& A, const std::vector<double>& diag,
     const int32_t n = A.n;
     Adj g;
     std::vector<int32_t> deg(n, 0);
-    // upper entries: eligible flag per stored entry
-    std::vector<double> cval(A.nnz());
-    std::vector<uint8_t> elig(A.nnz(), 0);
+    // upper entries: eligible flag per stored entry (both arrays written
+    // here for every entry, first touched by the threads; a weight is read
+    // only where its flag is set)
+    std::unique_ptr<double[]> cval(new double[A.nnz()]);
+    std::unique_ptr<uint8_t[]> elig(new uint8_t[A.nnz()]);
     parallel_for(n, [&](int64_t i) {
         for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
             int32_t j = A.ci[k];
-            if (j <= i) continue;
+            if (j <= i) {
+                cval[k] = 0.0;
+                elig[k] = 0;
+                continue;
+            }
             double c = edge_weight(A.v[k], diag[i], diag[j], w[i], w[j]);
             cval[k] = c;
             elig[k] = (match_all || c > 1.0) ? 1 : 0;
         }
     });
-    // degree count (both endpoints); sequential over rows to keep it simple and exact
-    for (int32_t i = 0; i < n; ++i)
+    // degree count (both endpoints) and fill, rows over threads with atomic
+    // counters: the order in which a vertex's list is filled does not
+    // matter, since the list is then sorted under a strict total order
+    // (weight, then the lower and the higher endpoint)
+    parallel_for(n, [&](int64_t i) {
         for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-            if (elig[k]) { ++deg[i]; ++deg[A.ci[k]]; }
+            if (elig[k]) {
+                __atomic_fetch_add(&deg[i], 1, __ATOMIC_RELAXED);
+                __atomic_fetch_add(&deg[A.ci[k]], 1, __ATOMIC_RELAXED);
+            }
+    });
     g.ptr.assign(n + 1, 0);
     for (int32_t i = 0; i < n; ++i) g.ptr[i + 1] = g.ptr[i] + deg[i];
     g.nbr.resize(g.ptr[n]);
     g.c.resize(g.ptr[n]);
     std::vector<int64_t> pos(g.ptr.begin(), g.ptr.end() - 1);
-    for (int32_t i = 0; i < n; ++i)
+    parallel_for(n, [&](int64_t i) {
         for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
             if (elig[k]) {
-                int32_t j = A.ci[k];
-                g.nbr[pos[i]] = j; g.c[pos[i]++] = cval[k];
-                g.nbr[pos[j]] = i; g.c[pos[j]++] = cval[k];
+                const int32_t j = A.ci[k];
+                const int64_t pi = __atomic_fetch_add(&pos[i], 1, __ATOMIC_RELAXED);
+                const int64_t pj = __atomic_fetch_add(&pos[j], 1, __ATOMIC_RELAXED);
+                g.nbr[pi] = j;
+                g.c[pi] = cval[k];
+                g.nbr[pj] = (int32_t)i;
+                g.c[pj] = cval[k];
             }
-    parallel_for(n, [&](int64_t i) {
-        int64_t b = g.ptr[i], e = g.ptr[i + 1];
-        if (e - b < 2) return;
+    });
+    struct alignas(64) SortBuf {  // one cache line (or more) per thread
         std::vector<std::pair<double, int32_t>> t;
-        t.reserve(e - b);
-        for (int64_t k = b; k < e; ++k) t.emplace_back(g.c[k], g.nbr[k]);
-        int32_t u = (int32_t)i;
-        std::sort(t.begin(), t.end(), [u](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
-            return heavier(x.first, std::min(u, x.second), std::max(u, x.second),
-                           y.first, std::min(u, y.second), std::max(u, y.second));
-        });
-        for (int64_t k = b; k < e; ++k) { g.c[k] = t[k - b].first; g.nbr[k] = t[k - b].second; }
-    }, 1024);
+    };
+    std::vector<SortBuf> buf(num_threads());
+    parallel_chunks(n, 1024, [&](int th, int64_t rb, int64_t re) {
+        std::vector<std::pair<double, int32_t>>& t = buf[th].t;
+        for (int64_t i = rb; i < re; ++i) {
+            int64_t b = g.ptr[i], e = g.ptr[i + 1];
+            if (e - b < 2) continue;
+            t.clear();
+            for (int64_t k = b; k < e; ++k) t.emplace_back(g.c[k], g.nbr[k]);
+            int32_t u = (int32_t)i;
+            std::sort(t.begin(), t.end(), [u](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+                return heavier(x.first, std::min(u, x.second), std::max(u, x.second),
+                               y.first, std::min(u, y.second), std::max(u, y.second));
+            });
+            for (int64_t k = b; k < e; ++k) { g.c[k] = t[k - b].first; g.nbr[k] = t[k - b].second; }
+        }
+    });
     return g;
 }
 
