@@ -998,8 +998,15 @@ static TileDict build_dicts(const std::vector<int32_t>& tiles, const std::vector
     D.span.assign(2 * nt, 0);
     D.local.assign(ci.size(), 0);
     std::vector<std::vector<int32_t>> dict(nt);
-    parallel_ranges(nt, [&](int, int64_t b, int64_t e) {
-        std::vector<int32_t> pos(n, -1);
+    // tiles in chunks from a shared counter (a level has few tiles when its
+    // matrix is small, not when its tiles are cheap)
+    struct alignas(64) PosBuf {  // one cache line (or more) per thread
+        std::vector<int32_t> pos;
+    };
+    std::vector<PosBuf> pbuf(num_threads());
+    parallel_chunks(nt, 4, [&](int th, int64_t b, int64_t e) {
+        std::vector<int32_t>& pos = pbuf[th].pos;
+        if (pos.empty()) pos.assign(n, -1);
         for (int64_t t = b; t < e; ++t) {
             const int32_t k0 = tiles[4 * t], k1 = tiles[4 * t + 1];
             if (k1 - k0 > cap) continue;
@@ -1141,8 +1148,13 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
         L.v.resize(hl.A.nnz());
         L.dinv.resize(n);
         if (l + 1 < nl) L.p.resize(n);
-        parallel_ranges(n, [&](int, int64_t b, int64_t e) {
+        // rows in chunks from a shared counter (small coarse levels have long rows)
+        struct alignas(64) RowBuf {  // one cache line (or more) per thread
             std::vector<std::pair<int32_t, double>> row;
+        };
+        std::vector<RowBuf> rbuf(num_threads());
+        parallel_chunks(n, 16, [&](int th, int64_t b, int64_t e) {
+            std::vector<std::pair<int32_t, double>>& row = rbuf[th].row;
             for (int64_t ip = b; ip < e; ++ip) {
                 int32_t i = L.iperm[ip];
                 row.clear();
@@ -1175,7 +1187,7 @@ std::vector<LayoutLevel> build_layout(const HostHierarchy& H) {
             L.vd.resize(L.v.size());
             parallel_for(n, [&](int64_t ip) {
                 for (int32_t k = L.rp[ip]; k < L.rp[ip + 1]; ++k) L.vd[k] = L.v[k] * L.dinv[L.ci[k]];
-            });
+            }, 64);
         }
     }
     return out;
